@@ -53,6 +53,15 @@ typedef struct {
 static char or_err[256];
 const char *or_last_error(void) { return or_err; }
 
+/* threads an evaluation uses (OpenMP default, e.g. OMP_NUM_THREADS) */
+int or_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* model blob                                                          */
 /* ------------------------------------------------------------------ */

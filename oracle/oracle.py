@@ -48,8 +48,13 @@ def lib():
         L.or_embed_single.argtypes = [P, C.c_int, C.c_int, C.c_double, P]
         L.or_eval.argtypes = [P, i64, P, P, P, P, i64, C.c_int, P, P, P, P, P, P, P, P, P, P, P, P]
         L.or_verlet.argtypes = [P, i64, P, P, P, P, P, C.c_double, i64, i64, C.c_int, P]
+        L.or_num_threads.restype = C.c_int
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
 
 
 def _p(a):

@@ -1,0 +1,151 @@
+// Internal declarations shared by the host runtime (api.cpp) and the HIP
+// kernels of the Deep Potential evaluator.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace dpk {
+
+constexpr int MAXT = 8;        // atom types
+constexpr int MAXL = 4;        // embedding layers
+constexpr int MAXF = 4;        // hidden fitting layers
+constexpr int KEY_CAP = 1024;  // neighbours within rc per atom held by the LDS sort
+constexpr int ROW_TILE = 64;   // fitting-net row tile; each type's rows are padded to it
+
+// Geometry / model dimensions passed by value to every kernel.
+struct Dims {
+  int ntypes, n_emb, n_fit, M1, M2, nnei;
+  double rcut, rcut_smth, inv_nc;
+  int sel[MAXT], off[MAXT + 1];
+  int ew[MAXL + 1];    // embedding widths, ew[0] = 1
+  int ekp[MAXL + 1];   // width rounded up to 4 (as a K dimension)
+  int emp[MAXL + 1];   // width rounded up to 16 (as an M dimension)
+  int fw[MAXF + 2];    // fitting widths, fw[0] = M1*M2, fw[n_fit+1] = 1
+};
+
+// Offsets (in elements) of the padded embedding weights inside one flat
+// array.  Layer 0 (1 -> ew[1]) is stored as W0[ekp[1]], b0[ekp[1]]; layer
+// l >= 1 as W[ekp[l]][emp[l+1]] (row = input feature), b[emp[l+1]], zero
+// padded.  One net per (centre type t, neighbour type u).
+struct EmbOffsets {
+  int64_t w[MAXT][MAXT][MAXL];
+  int64_t b[MAXT][MAXT][MAXL];
+};
+
+// Offsets of the fitting weights: layer l of type t, W[fw[l]][fw[l+1]]
+// row-major (input feature = row), b[fw[l+1]].  Output layer is l = n_fit.
+struct FitOffsets {
+  int64_t w[MAXT][MAXF + 1];
+  int64_t b[MAXT][MAXF + 1];
+};
+
+// Error flags written by kernels, read back by the host.
+enum : uint32_t { FLAG_BAD_TYPE = 1u, FLAG_CAND_CAP = 2u, FLAG_KEY_CAP = 4u, FLAG_NONFINITE = 8u,
+                  FLAG_REBUILD = 16u };
+
+struct NlistBufs {
+  const double *coords;  // caller coords [n][3]
+  const int32_t *types;  // caller types [n]
+  double4 *xw;           // wrapped coords, w = type
+  int32_t *cell_of;      // [n]
+  int32_t *cell_start;   // [ncell + 1]
+  int32_t *cell_fill;    // [ncell]
+  int32_t *cell_atoms;   // [n]
+  int32_t *cand;         // [n][cand_cap]
+  int32_t *cand_n;       // [n]
+  int32_t *nlist;        // [n][nnei]
+  int32_t *nreal;        // [n][ntypes]
+  unsigned long long *overflow;  // [1]
+  int32_t *max_real;     // [MAXT]
+  uint32_t *flags;       // [1]
+};
+
+struct CellGrid {
+  int nc[3];
+  double side[3];
+  double L[3];
+};
+
+// ---- neighbour list (k_nlist.hip) ----
+void launch_wrap(hipStream_t s, int64_t n, const double *coords, const int32_t *types, int ntypes,
+                 const double *L, double4 *xw, uint32_t *flags);
+void launch_type_sort(hipStream_t s, int64_t n, const double4 *xw, int ntypes, int32_t *blk_counts,
+                      int32_t *type_count, int32_t *type_start, int32_t *pos_of_atom, int32_t *atom_of_pos,
+                      int64_t rows_cap);
+// `cond` (may be NULL): when given, the kernels do nothing unless
+// (*cond & FLAG_REBUILD) -- the MD driver decides on the device.
+void launch_cells(hipStream_t s, int64_t n, const double4 *xw, const CellGrid &g, int32_t *cell_of,
+                  int32_t *cell_start, int32_t *cell_fill, int32_t *cell_atoms, int32_t *scan_tmp,
+                  const uint32_t *cond);
+void launch_candidates(hipStream_t s, int64_t n, const double4 *xw, const CellGrid &g, const int32_t *cell_start,
+                       const int32_t *cell_atoms, double rlist, int cand_cap, int32_t *cand, int32_t *cand_n,
+                       uint32_t *flags, const uint32_t *cond);
+void launch_fill_u32(hipStream_t s, uint32_t *p, int64_t n, uint32_t v);
+void launch_format(hipStream_t s, int64_t n, const double4 *xw, const Dims &d, const double *L, const int32_t *cand,
+                   const int32_t *cand_n, int cand_cap, int32_t *nlist, int32_t *nreal,
+                   unsigned long long *overflow, int32_t *max_real, uint32_t *flags);
+void launch_max_disp(hipStream_t s, int64_t n, const double4 *xw, const double4 *xref, const double *L,
+                     double half_skin, uint32_t *flags);
+void launch_copy_ref(hipStream_t s, int64_t n, const double4 *xw, double4 *xref, const uint32_t *cond);
+// clears FLAG_REBUILD and counts the rebuild in *nbuild when it was set
+void launch_end_rebuild(hipStream_t s, uint32_t *flags, unsigned long long *nbuild);
+
+// ---- environment matrix (k_env.hip) ----
+void launch_env(hipStream_t s, int64_t n, const double4 *xw, const Dims &d, const double *L, const int32_t *nlist,
+                const int32_t *nreal, double4 *rt, double4 *dr);
+
+// ---- FP64 embedding + descriptor (k_embed_f64.hip) ----
+struct EmbedArgs {
+  Dims d;
+  EmbOffsets eo;
+  const double *ew;          // padded embedding weights
+  const int32_t *atom_of_pos;
+  const int32_t *pos_of_atom;
+  const int32_t *type_start; // [ntypes+1] padded row starts
+  int64_t rows;              // padded rows in use
+  int64_t natoms;
+  const double4 *xw;
+  const int32_t *nlist, *nreal;
+  const double4 *rt, *dr;
+  double *T;                 // [natoms][M1][4]
+  double *D;                 // [rows][M1*M2]
+  const double *dD;          // [rows][M1*M2]
+  double *force;             // [natoms][3]
+  double *vir_part;          // [grid][9]
+  double *net_deriv;         // optional [natoms][nnei][4]
+};
+void launch_embed_fwd_f64(hipStream_t s, const EmbedArgs &a);
+void launch_embed_bwd_f64(hipStream_t s, const EmbedArgs &a, int grid);
+int embed_bwd_grid(int64_t rows);
+
+// ---- FP64 fitting net (k_fit_f64.hip) ----
+struct FitArgs {
+  Dims d;
+  FitOffsets fo;
+  const double *fwt;          // fitting weights
+  const int32_t *type_start;  // [ntypes+1] padded row starts (device)
+  const int32_t *atom_of_pos; // [rows]
+  int64_t rows;
+  double *X0;                 // D [rows][fw0]
+  double *Y[MAXF + 1];        // Y[l] l=1..n_fit [rows][fw[l]]
+  double *Tt[MAXF + 1];       // tanh outputs per layer [rows][fw[l]]
+  double *G[MAXF + 1];        // gradient wrt Y[l] [rows][fw[l]]; G[0] = dD
+  double *eatom;              // [natoms] (original order)
+};
+void launch_fit_f64(hipStream_t s, const FitArgs &a);
+
+// ---- reductions and MD (k_md.hip) ----
+void launch_sum(hipStream_t s, const double *x, int64_t n, double *partial, double *out, double scale);
+void launch_sum9(hipStream_t s, const double *part, int nparts, double *out);
+void launch_zero(hipStream_t s, double *x, int64_t n);
+void launch_verlet_half(hipStream_t s, int64_t n, double *v, const double *f, const int32_t *types,
+                        const double *inv_m_conv, double half_dt);
+void launch_verlet_drift(hipStream_t s, int64_t n, double *x, const double *v, double dt, const double *L);
+void launch_kinetic(hipStream_t s, int64_t n, const double *v, const int32_t *types, const double *mass,
+                    double *partial, double *out);
+void launch_thermo_row(hipStream_t s, double *row, double step, const double *ke, const double *pe,
+                       const double *vir, double ndof_kb, double inv3v, uint32_t *flags);
+
+}  // namespace dpk

@@ -1,0 +1,487 @@
+// Double-precision embedding net + descriptor, fused per centre atom so the
+// embedding matrix G never reaches HBM (Section V-A, "Increasing
+// computational granularity": the type-sorted, padded list lets every tile
+// of neighbours use one net without branching).
+//
+// Pass 1 (forward):  for each real neighbour j of atom i (net (t_i, t_j)),
+//   G_j = Emb(s_j)  (1 -> w1 on VALU, later layers on MFMA),
+//   T  += G_j R_j^T            (MFMA, K = neighbours)
+//   T  *= 1/Nc,  D = T T_<^T   (MFMA, K = 4)
+// Pass 2 (backward): dT = (dD T_< + [a < M2] dD^T T) / Nc, then per tile the
+//   net is re-run in forward tangent mode (h and dh/ds side by side, the
+//   second MFMA column tile), giving G_j and G'_j = dG_j/ds_j in registers:
+//   dE/dR_j = G_j^T dT,   dE/ds_j += (dT R_j) . G'_j,
+//   g_ij = sum_k dE/dR_jk dR_jk/dr_ij,  F_i += g_ij, F_j -= g_ij (atomics),
+//   Xi -= g_ij (x) r_ij (per-block partial sums, reduced in block order).
+// This fuses the paper's ProdForce and ProdVirial operators into the
+// embedding backward.
+//
+// Matrix layout: each layer is computed transposed, Z^T[out x 16] = W^T H^T,
+// with the 16 neighbours of a tile as the MFMA N dimension.  For
+// v_mfma_f64_16x16x4: A lane l holds A[l%16][l/16], B lane l holds
+// B[l/16][l%16], and D register r of lane l is D[4(l/16)+r][l%16].
+// Weights stream from L2 in their padded [K][M] layout; activations pass
+// between layers through a per-wave LDS tile [feature][neighbour].
+#include "dp_internal.h"
+
+namespace dpk {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int EMB_WAVES = 2;
+constexpr int MAXMT = 8;  // output features per layer <= 128
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline v4d mfma64(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+struct EmbLds {
+  int rows[2];  // rows of the two ping-pong activation buffers
+  int cols;     // 16 (forward) or 32 (tangent pass)
+  int off_buf[2], off_rt, off_t, per_wave;  // offsets in doubles
+};
+
+static EmbLds emb_lds_layout(const Dims &d, int pass) {
+  EmbLds L{};
+  L.cols = pass == 1 ? 16 : 32;
+  for (int l = 0; l < d.n_emb; ++l) {
+    int r = (l == d.n_emb - 1) ? (pass == 1 ? d.emp[d.n_emb] : 0) : d.ekp[l + 1];
+    if (r > L.rows[l & 1]) L.rows[l & 1] = r;
+  }
+  L.off_buf[0] = 0;
+  L.off_buf[1] = L.rows[0] * L.cols;
+  L.off_rt = L.off_buf[1] + L.rows[1] * L.cols;
+  L.off_t = L.off_rt + 64;
+  L.per_wave = L.off_t + d.emp[d.n_emb] * 4;
+  return L;
+}
+
+// One MFMA layer: acc[ct][mt] = (W^T H^T) for column tile ct, output tile mt.
+template <int NCT>
+__device__ inline void mfma_layer(const double *__restrict__ W, int kp, int mp, const double *Hin, int cols, int lane,
+                                  v4d (&acc)[NCT][MAXMT]) {
+  const int nmt = mp >> 4;
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int mt = 0; mt < MAXMT; ++mt) acc[ct][mt] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int kk = 0; kk < kp; kk += 4) {
+    const int krow = kk + (lane >> 4);
+    double bv[NCT];
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) bv[ct] = Hin[krow * cols + ct * 16 + (lane & 15)];
+    const double *wr = W + (size_t)krow * mp + (lane & 15);
+#pragma unroll
+    for (int mt = 0; mt < MAXMT; ++mt) {
+      if (mt < nmt) {
+        double a = wr[mt * 16];
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) acc[ct][mt] = mfma64(a, bv[ct], acc[ct][mt]);
+      }
+    }
+  }
+}
+
+__device__ inline int skip_src(int f, int in, int out) {
+  // feature of the previous layer added by the skip connection, or -1
+  if (out == in) return f;
+  if (out == 2 * in) return f >= in ? f - in : f;
+  return -1;
+}
+
+// ---------------------------------------------------------------------------
+// pass 1
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, EmbLds L) {
+  extern __shared__ double smem[];
+  const Dims &d = a.d;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  double *lds = smem + wv * L.per_wave;
+  double *Rl = lds + L.off_rt;
+  double *Tl = lds + L.off_t;
+  const int64_t nwaves = (int64_t)gridDim.x * EMB_WAVES;
+  const int64_t gw = (int64_t)blockIdx.x * EMB_WAVES + wv;
+  const int64_t chunk = (a.rows + nwaves - 1) / nwaves;
+  const int64_t p_end = (gw + 1) * chunk < a.rows ? (gw + 1) * chunk : a.rows;
+  const int nmtG = d.emp[d.n_emb] >> 4;
+  const int MM = d.M1 * d.M2;
+
+  for (int64_t p = gw * chunk; p < p_end; ++p) {
+    const int i = a.atom_of_pos[p];
+    double *Dp = a.D + p * (int64_t)MM;
+    if (i < 0) {
+      for (int o = lane; o < MM; o += 64) Dp[o] = 0.0;
+      continue;
+    }
+    const int t = (int)a.xw[i].w;
+    v4d Tacc[MAXMT];
+#pragma unroll
+    for (int mt = 0; mt < MAXMT; ++mt) Tacc[mt] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    for (int u = 0; u < d.ntypes; ++u) {
+      const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
+      const int64_t base = (int64_t)i * d.nnei + d.off[u];
+      const double *W0 = a.ew + a.eo.w[t][u][0];
+      const double *b0 = a.ew + a.eo.b[t][u][0];
+      for (int n0 = 0; n0 < cnt; n0 += 16) {
+        if (lane < 16) {
+          double4 r4 = (n0 + lane < cnt) ? a.rt[base + n0 + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
+          Rl[lane * 4 + 0] = r4.x;
+          Rl[lane * 4 + 1] = r4.y;
+          Rl[lane * 4 + 2] = r4.z;
+          Rl[lane * 4 + 3] = r4.w;
+        }
+        wave_sync();
+        // layer 0: 1 -> ew[1] on VALU
+        {
+          const int out1 = d.ew[1];
+          const int rows = (d.n_emb == 1) ? d.emp[1] : d.ekp[1];
+          double *H = lds + L.off_buf[0];
+          for (int idx = lane; idx < rows * 16; idx += 64) {
+            const int f = idx >> 4, n = idx & 15;
+            const double s = Rl[n * 4];
+            double h = 0.0;
+            if (f < out1) {
+              h = tanh(s * W0[f] + b0[f]);
+              if (out1 == 1 || out1 == 2) h += s;
+            }
+            H[f * 16 + n] = h;
+          }
+        }
+        wave_sync();
+        // layers 1 .. n_emb-1 on MFMA
+        for (int l = 1; l < d.n_emb; ++l) {
+          const int in = d.ew[l], out = d.ew[l + 1];
+          const double *Hin = lds + L.off_buf[(l - 1) & 1];
+          double *Hout = lds + L.off_buf[l & 1];
+          const int rows_out = (l == d.n_emb - 1) ? d.emp[l + 1] : d.ekp[l + 1];
+          const double *W = a.ew + a.eo.w[t][u][l];
+          const double *bias = a.ew + a.eo.b[t][u][l];
+          v4d acc[1][MAXMT];
+          mfma_layer<1>(W, d.ekp[l], d.emp[l + 1], Hin, 16, lane, acc);
+          const int nmt = d.emp[l + 1] >> 4;
+#pragma unroll
+          for (int mt = 0; mt < MAXMT; ++mt) {
+            if (mt < nmt) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int f = mt * 16 + (lane >> 4) * 4 + r, n = lane & 15;
+                if (f < rows_out) {
+                  double h = 0.0;
+                  if (f < out) {
+                    h = tanh(acc[0][mt][r] + bias[f]);
+                    const int sf = skip_src(f, in, out);
+                    if (sf >= 0) h += Hin[sf * 16 + n];
+                  }
+                  Hout[f * 16 + n] = h;
+                }
+              }
+            }
+          }
+          wave_sync();
+        }
+        // T += G R (K = the 16 neighbours of the tile)
+        const double *G = lds + L.off_buf[(d.n_emb - 1) & 1];
+#pragma unroll
+        for (int kn = 0; kn < 4; ++kn) {
+          const int nb = kn * 4 + (lane >> 4);
+          const int comp = lane & 15;
+          const double bv = comp < 4 ? Rl[nb * 4 + comp] : 0.0;
+#pragma unroll
+          for (int mt = 0; mt < MAXMT; ++mt)
+            if (mt < nmtG) Tacc[mt] = mfma64(G[(mt * 16 + (lane & 15)) * 16 + nb], bv, Tacc[mt]);
+        }
+        wave_sync();
+      }
+    }
+    // T = Tacc / Nc -> global and LDS; lane holds T[mt*16 + 4(l/16) + r][l%16]
+    {
+      const int comp = lane & 15;
+      double *Tg = a.T + (int64_t)i * d.M1 * 4;
+#pragma unroll
+      for (int mt = 0; mt < MAXMT; ++mt) {
+        if (mt < nmtG) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int f = mt * 16 + (lane >> 4) * 4 + r;
+            const double v = Tacc[mt][r] * d.inv_nc;
+            if (comp < 4) {
+              Tl[f * 4 + comp] = v;
+              if (f < d.M1) Tg[f * 4 + comp] = v;
+            }
+          }
+        }
+      }
+    }
+    wave_sync();
+    // D = T T_<^T : one MFMA step of K = 4 per output tile
+    {
+      const int b = lane & 15;
+      const double bv = b < d.M2 ? Tl[b * 4 + (lane >> 4)] : 0.0;
+#pragma unroll
+      for (int mt = 0; mt < MAXMT; ++mt) {
+        if (mt < nmtG) {
+          v4d z = mfma64(Tl[(mt * 16 + (lane & 15)) * 4 + (lane >> 4)], bv, v4d{0.0, 0.0, 0.0, 0.0});
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int f = mt * 16 + (lane >> 4) * 4 + r;
+            if (f < d.M1 && b < d.M2) Dp[f * d.M2 + b] = z[r];
+          }
+        }
+      }
+    }
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass 2
+// ---------------------------------------------------------------------------
+__device__ inline void switch_fn(double r, double rcs, double rc, double inv_w, double &sw, double &dsw) {
+  if (r < rcs) {
+    sw = 1.0;
+    dsw = 0.0;
+  } else if (r < rc) {
+    const double x = (r - rcs) * inv_w;
+    sw = x * x * x * (-6.0 * x * x + 15.0 * x - 10.0) + 1.0;
+    dsw = x * x * (-30.0 * x * x + 60.0 * x - 30.0) * inv_w;
+  } else {
+    sw = 0.0;
+    dsw = 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_bwd_f64(EmbedArgs a, EmbLds L) {
+  extern __shared__ double smem[];
+  __shared__ double vred[EMB_WAVES][9];
+  const Dims &d = a.d;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  double *lds = smem + wv * L.per_wave;
+  double *Rl = lds + L.off_rt;
+  double *dTl = lds + L.off_t;
+  const int64_t nwaves = (int64_t)gridDim.x * EMB_WAVES;
+  const int64_t gw = (int64_t)blockIdx.x * EMB_WAVES + wv;
+  const int64_t chunk = (a.rows + nwaves - 1) / nwaves;
+  const int64_t p_end = (gw + 1) * chunk < a.rows ? (gw + 1) * chunk : a.rows;
+  const int MM = d.M1 * d.M2;
+  const int M1p = d.emp[d.n_emb];
+  const double rc = d.rcut, rcs = d.rcut_smth, inv_w = 1.0 / (d.rcut - d.rcut_smth);
+  double vir[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) vir[k] = 0.0;
+
+  for (int64_t p = gw * chunk; p < p_end; ++p) {
+    const int i = a.atom_of_pos[p];
+    if (i < 0) continue;
+    const int t = (int)a.xw[i].w;
+    // dT / Nc
+    {
+      const double *Ti = a.T + (int64_t)i * d.M1 * 4;
+      const double *dDp = a.dD + p * (int64_t)MM;
+      for (int o = lane; o < M1p * 4; o += 64) {
+        const int f = o >> 2, k = o & 3;
+        double v = 0.0;
+        if (f < d.M1) {
+          for (int b = 0; b < d.M2; ++b) v += dDp[f * d.M2 + b] * Ti[b * 4 + k];
+          if (f < d.M2)
+            for (int a2 = 0; a2 < d.M1; ++a2) v += dDp[a2 * d.M2 + f] * Ti[a2 * 4 + k];
+        }
+        dTl[o] = v * d.inv_nc;
+      }
+    }
+    wave_sync();
+    double fi0 = 0.0, fi1 = 0.0, fi2 = 0.0;
+    for (int u = 0; u < d.ntypes; ++u) {
+      const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
+      const int64_t base = (int64_t)i * d.nnei + d.off[u];
+      const double *W0 = a.ew + a.eo.w[t][u][0];
+      const double *b0 = a.ew + a.eo.b[t][u][0];
+      for (int n0 = 0; n0 < cnt; n0 += 16) {
+        const bool valid = lane < 16 && n0 + lane < cnt;
+        double4 R4 = make_double4(0.0, 0.0, 0.0, 0.0), D4 = make_double4(0.0, 0.0, 0.0, 1.0);
+        int j = -1;
+        if (valid) {
+          R4 = a.rt[base + n0 + lane];
+          D4 = a.dr[base + n0 + lane];
+          j = a.nlist[base + n0 + lane];
+        }
+        if (lane < 16) {
+          Rl[lane * 4 + 0] = R4.x;
+          Rl[lane * 4 + 1] = R4.y;
+          Rl[lane * 4 + 2] = R4.z;
+          Rl[lane * 4 + 3] = R4.w;
+        }
+        wave_sync();
+        // layer 0 with tangent: h and dh/ds side by side (columns 0..15, 16..31)
+        {
+          const int out1 = d.ew[1];
+          double *H = lds + L.off_buf[0];
+          for (int idx = lane; idx < d.ekp[1] * 16; idx += 64) {
+            const int f = idx >> 4, n = idx & 15;
+            const double s = Rl[n * 4];
+            double h = 0.0, hd = 0.0;
+            if (f < out1) {
+              const double th = tanh(s * W0[f] + b0[f]);
+              h = th;
+              hd = (1.0 - th * th) * W0[f];
+              if (out1 == 1 || out1 == 2) {
+                h += s;
+                hd += 1.0;
+              }
+            }
+            H[f * 32 + n] = h;
+            H[f * 32 + 16 + n] = hd;
+          }
+        }
+        wave_sync();
+        double ga[4] = {0.0, 0.0, 0.0, 0.0}, gb[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int l = 1; l < d.n_emb; ++l) {
+          const int in = d.ew[l], out = d.ew[l + 1];
+          const bool last = (l == d.n_emb - 1);
+          const double *Hin = lds + L.off_buf[(l - 1) & 1];
+          double *Hout = lds + L.off_buf[l & 1];
+          const int rows_out = last ? 0 : d.ekp[l + 1];
+          const double *W = a.ew + a.eo.w[t][u][l];
+          const double *bias = a.ew + a.eo.b[t][u][l];
+          v4d acc[2][MAXMT];
+          mfma_layer<2>(W, d.ekp[l], d.emp[l + 1], Hin, 32, lane, acc);
+          const int nmt = d.emp[l + 1] >> 4;
+#pragma unroll
+          for (int mt = 0; mt < MAXMT; ++mt) {
+            if (mt < nmt) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int f = mt * 16 + (lane >> 4) * 4 + r, n = lane & 15;
+                double h = 0.0, hd = 0.0;
+                if (f < out) {
+                  const double th = tanh(acc[0][mt][r] + bias[f]);
+                  h = th;
+                  hd = (1.0 - th * th) * acc[1][mt][r];
+                  const int sf = skip_src(f, in, out);
+                  if (sf >= 0) {
+                    h += Hin[sf * 32 + n];
+                    hd += Hin[sf * 32 + 16 + n];
+                  }
+                }
+                if (last) {
+                  if (f < out) {
+                    const double *dt = dTl + f * 4;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                      ga[k] += h * dt[k];
+                      gb[k] += hd * dt[k];
+                    }
+                  }
+                } else if (f < rows_out) {
+                  Hout[f * 32 + n] = h;
+                  Hout[f * 32 + 16 + n] = hd;
+                }
+              }
+            }
+          }
+          wave_sync();
+        }
+        // sum the four lane groups: lanes n, n+16, n+32, n+48 share neighbour n
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          ga[k] += __shfl_xor(ga[k], 16);
+          ga[k] += __shfl_xor(ga[k], 32);
+          gb[k] += __shfl_xor(gb[k], 16);
+          gb[k] += __shfl_xor(gb[k], 32);
+        }
+        if (valid) {
+          // dE/dR_j (the 1/Nc is inside dT); the embedding path adds to the s component
+          const double g0 = ga[0] + (R4.x * gb[0] + R4.y * gb[1] + R4.z * gb[2] + R4.w * gb[3]);
+          const double g1 = ga[1], g2 = ga[2], g3 = ga[3];
+          if (a.net_deriv) {
+            double *nd = a.net_deriv + (base + n0 + lane) * 4;
+            nd[0] = g0;
+            nd[1] = g1;
+            nd[2] = g2;
+            nd[3] = g3;
+          }
+          const double dx = D4.x, dy = D4.y, dz = D4.z, r = D4.w;
+          double sw, dsw;
+          switch_fn(r, rcs, rc, inv_w, sw, dsw);
+          const double ir = 1.0 / r;
+          const double s = sw * ir;
+          const double ds = (dsw * r - sw) * ir * ir;
+          const double tt = s * ir;
+          const double dtt = dsw * ir * ir - 2.0 * sw * ir * ir * ir;
+          const double gd = g1 * dx + g2 * dy + g3 * dz;
+          const double c = (g0 * ds + dtt * gd) * ir;
+          const double gx = c * dx + tt * g1, gy = c * dy + tt * g2, gz = c * dz + tt * g3;
+          fi0 += gx;
+          fi1 += gy;
+          fi2 += gz;
+          unsafeAtomicAdd(a.force + 3 * (int64_t)j + 0, -gx);
+          unsafeAtomicAdd(a.force + 3 * (int64_t)j + 1, -gy);
+          unsafeAtomicAdd(a.force + 3 * (int64_t)j + 2, -gz);
+          vir[0] -= gx * dx; vir[1] -= gx * dy; vir[2] -= gx * dz;
+          vir[3] -= gy * dx; vir[4] -= gy * dy; vir[5] -= gy * dz;
+          vir[6] -= gz * dx; vir[7] -= gz * dy; vir[8] -= gz * dz;
+        }
+        wave_sync();
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      fi0 += __shfl_xor(fi0, o);
+      fi1 += __shfl_xor(fi1, o);
+      fi2 += __shfl_xor(fi2, o);
+    }
+    if (lane == 0) {
+      unsafeAtomicAdd(a.force + 3 * (int64_t)i + 0, fi0);
+      unsafeAtomicAdd(a.force + 3 * (int64_t)i + 1, fi1);
+      unsafeAtomicAdd(a.force + 3 * (int64_t)i + 2, fi2);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    double v = vir[k];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
+    if (lane == 0) vred[wv][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 9) {
+    double v = 0.0;
+    for (int w = 0; w < EMB_WAVES; ++w) v += vred[w][threadIdx.x];
+    a.vir_part[(int64_t)blockIdx.x * 9 + threadIdx.x] = v;
+  }
+}
+
+static int emb_grid(int64_t rows) {
+  int64_t g = (rows + EMB_WAVES - 1) / EMB_WAVES;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+int embed_bwd_grid(int64_t rows) { return emb_grid(rows); }
+
+void launch_embed_fwd_f64(hipStream_t s, const EmbedArgs &a) {
+  EmbLds L = emb_lds_layout(a.d, 1);
+  size_t shm = sizeof(double) * (size_t)L.per_wave * EMB_WAVES;
+  hipLaunchKernelGGL(k_embed_fwd_f64, dim3(emb_grid(a.rows)), dim3(64 * EMB_WAVES), shm, s, a, L);
+}
+
+void launch_embed_bwd_f64(hipStream_t s, const EmbedArgs &a, int grid) {
+  EmbLds L = emb_lds_layout(a.d, 2);
+  size_t shm = sizeof(double) * (size_t)L.per_wave * EMB_WAVES;
+  hipLaunchKernelGGL(k_embed_bwd_f64, dim3(grid), dim3(64 * EMB_WAVES), shm, s, a, L);
+}
+
+size_t embed_lds_bytes(const Dims &d, int pass) {
+  EmbLds L = emb_lds_layout(d, pass);
+  return sizeof(double) * (size_t)L.per_wave * EMB_WAVES;
+}
+
+}  // namespace dpk

@@ -1,0 +1,67 @@
+// Environment matrix (the paper's "Environment" operator, Section V-A and
+// Table III): for every real slot of the formatted list,
+//   d = r_j - r_i (minimum image), r = |d|,
+//   R = (s, s dx/r, s dy/r, s dz/r),  s = sw(r)/r,
+//   sw = 1 (r < rcs), u^3 (-6u^2 + 15u - 10) + 1 (rcs <= r < rc), 0 (r >= rc),
+//   u = (r - rcs)/(rc - rcs)  (quintic switch, C2 in the displacements).
+// Output rt[i][slot] = R and dr[i][slot] = (dx, dy, dz, r), double.  Padded
+// slots are not written (every consumer stops at the real count).
+//
+// One wave per centre atom; the lanes stride over the atom's real slots so
+// that the two output streams are written contiguously.  HBM-bound:
+// per real slot 4 B nlist + 32 B neighbour position (L2/MALL) in, 64 B out.
+#include "dp_internal.h"
+
+namespace dpk {
+
+__device__ inline double env_min_image(double v, double L) {
+  if (v > 0.5 * L) v -= L;
+  else if (v < -0.5 * L) v += L;
+  return v;
+}
+
+__global__ void __launch_bounds__(256) k_env(int64_t n, const double4 *__restrict__ xw, Dims d, double L0, double L1,
+                                             double L2, const int32_t *__restrict__ nlist,
+                                             const int32_t *__restrict__ nreal, double4 *__restrict__ rt,
+                                             double4 *__restrict__ dr) {
+  int lane = threadIdx.x & 63;
+  int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  double4 p = xw[i];
+  const double rc = d.rcut, rcs = d.rcut_smth, inv_w = 1.0 / (d.rcut - d.rcut_smth);
+  for (int u = 0; u < d.ntypes; ++u) {
+    int cnt = nreal[i * d.ntypes + u];
+    int64_t base = i * (int64_t)d.nnei + d.off[u];
+    for (int q = lane; q < cnt; q += 64) {
+      int j = nlist[base + q];
+      double4 pj = xw[j];
+      double dx = env_min_image(pj.x - p.x, L0);
+      double dy = env_min_image(pj.y - p.y, L1);
+      double dz = env_min_image(pj.z - p.z, L2);
+      double r = sqrt(dx * dx + dy * dy + dz * dz);
+      double sw;
+      if (r < rcs) {
+        sw = 1.0;
+      } else if (r < rc) {
+        double x = (r - rcs) * inv_w;
+        sw = x * x * x * (-6.0 * x * x + 15.0 * x - 10.0) + 1.0;
+      } else {
+        sw = 0.0;
+      }
+      double inv_r = 1.0 / r;
+      double s = sw * inv_r;
+      double t = s * inv_r;
+      rt[base + q] = make_double4(s, t * dx, t * dy, t * dz);
+      dr[base + q] = make_double4(dx, dy, dz, r);
+    }
+  }
+}
+
+void launch_env(hipStream_t s, int64_t n, const double4 *xw, const Dims &d, const double *L, const int32_t *nlist,
+                const int32_t *nreal, double4 *rt, double4 *dr) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_env, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, xw, d, L[0], L[1], L[2], nlist, nreal,
+                     rt, dr);
+}
+
+}  // namespace dpk

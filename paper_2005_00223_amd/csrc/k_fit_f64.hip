@@ -1,0 +1,201 @@
+// Double-precision fitting net, forward and backward, per centre type
+// (Fig. 1(d,g)).  Rows are atoms in the type-padded row order (each type's
+// rows padded to ROW_TILE, so a 64-row tile never mixes types).
+//
+// Forward hidden layer l (in -> out):  t = tanh(Y_l W + b),
+//   Y_{l+1} = t (+ Y_l if out == in, + (Y_l, Y_l) if out == 2 in).
+// The bias add, tanh, skip add and the store of t (kept for the backward,
+// the paper's fused TANH/TANHGrad idea) all sit in the GEMM epilogue
+// (Section V-B, "Replace MATMUL and SUM" and "Replace CONCAT and SUM").
+// Output layer: E_i = Y_L . w + b (one wave per row).
+// Backward layer l: gZ = gY_{l+1} (1 - t^2) is formed while the A tile is
+// loaded, gY_l = gZ W^T (+ the skip's pass-through), gY_0 = dE/dD.
+//
+// MFMA v_mfma_f64_16x16x4; block tile 64 x 64, four waves of 32 x 32,
+// K staged through LDS in steps of 16.
+#include "dp_internal.h"
+
+namespace dpk {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16, APAD = BK + 1;
+
+enum { FIT_FWD = 0, FIT_BWD = 1 };
+
+struct GemmArgs {
+  int mode, layer, K, N, in, out;  // in/out of the layer (fwd: K=in, N=out; bwd: K=out, N=in)
+  int ntypes;
+  const int32_t *type_start;
+  const double *fwt;
+  FitOffsets fo;
+  const double *X;    // fwd: layer input [rows][in]
+  double *Tt;         // fwd: tanh output [rows][out] (written); bwd: read
+  double *Y;          // fwd: layer output [rows][out]
+  const double *gY;   // bwd: gradient wrt the layer output [rows][out] (NULL = output weights)
+  const double *wout; // bwd: output-layer weights of each type when gY == NULL (offset by type)
+  double *gX;         // bwd: gradient wrt the layer input [rows][in]
+};
+
+__device__ inline int row_type(const int32_t *ts, int ntypes, int64_t r0) {
+  int t = 0;
+  for (int u = 1; u < ntypes; ++u)
+    if (r0 >= ts[u]) t = u;
+  return t;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_fit_gemm(GemmArgs g) {
+  __shared__ double As[BM][APAD];
+  __shared__ double Bs[BK][BN];
+  const int64_t r0 = (int64_t)blockIdx.x * BM;
+  const int c0 = blockIdx.y * BN;
+  if (r0 >= g.type_start[g.ntypes]) return;
+  const int t = row_type(g.type_start, g.ntypes, r0);
+  const double *W = g.fwt + g.fo.w[t][g.layer];
+  const double *bias = g.fwt + g.fo.b[t][g.layer];
+  const double *wo = (MODE == FIT_BWD && g.gY == nullptr) ? g.fwt + g.fo.w[t][g.layer + 1] : nullptr;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  v4d acc[2][2];
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+    // A tile [64 x 16]
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      const int rr = e >> 4, kk = e & 15;
+      const int k = k0 + kk;
+      double v = 0.0;
+      if (k < g.K) {
+        const int64_t row = r0 + rr;
+        if (MODE == FIT_FWD) {
+          v = g.X[row * g.K + k];
+        } else {
+          const double th = g.Tt[row * g.K + k];
+          const double gy = wo ? wo[k] : g.gY[row * g.K + k];
+          v = gy * (1.0 - th * th);
+        }
+      }
+      As[rr][kk] = v;
+    }
+    // B tile [16 x 64]
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      const int kk = e >> 6, cc = e & 63;
+      const int k = k0 + kk, c = c0 + cc;
+      double v = 0.0;
+      if (k < g.K && c < g.N) v = (MODE == FIT_FWD) ? W[(int64_t)k * g.N + c] : W[(int64_t)c * g.K + k];
+      Bs[kk][cc] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      double af[2], bf[2];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) af[mi] = As[wm * 32 + mi * 16 + (lane & 15)][ks + (lane >> 4)];
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) bf[ni] = Bs[ks + (lane >> 4)][wn * 32 + ni * 16 + (lane & 15)];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // epilogue
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = r0 + wm * 32 + mi * 16 + (lane >> 4) * 4 + r;
+        const int col = c0 + wn * 32 + ni * 16 + (lane & 15);
+        if (col >= g.N) continue;
+        const double c = acc[mi][ni][r];
+        if (MODE == FIT_FWD) {
+          const double th = tanh(c + bias[col]);
+          double y = th;
+          if (g.out == g.in) y += g.X[row * g.in + col];
+          else if (g.out == 2 * g.in) y += g.X[row * g.in + (col >= g.in ? col - g.in : col)];
+          g.Tt[row * g.out + col] = th;
+          g.Y[row * g.out + col] = y;
+        } else {
+          double v = c;
+          if (g.out == g.in || g.out == 2 * g.in) {
+            v += wo ? wo[col] : g.gY[row * g.out + col];
+            if (g.out == 2 * g.in) v += wo ? wo[col + g.in] : g.gY[row * g.out + col + g.in];
+          }
+          g.gX[row * g.in + col] = v;
+        }
+      }
+}
+
+// E_i = Y_L . w_out + b_out, one wave per row
+__global__ void __launch_bounds__(256) k_fit_out(const int32_t *type_start, int ntypes, const int32_t *atom_of_pos,
+                                                 const double *fwt, FitOffsets fo, int L, int width, const double *Y,
+                                                 int64_t rows_cap, double *eatom) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows_cap || row >= type_start[ntypes]) return;
+  const int atom = atom_of_pos[row];
+  if (atom < 0) return;
+  const int t = row_type(type_start, ntypes, row);
+  const double *w = fwt + fo.w[t][L];
+  double s = 0.0;
+  for (int o = lane; o < width; o += 64) s += Y[row * width + o] * w[o];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) eatom[atom] = s + fwt[fo.b[t][L]];
+}
+
+void launch_fit_f64(hipStream_t s, const FitArgs &a) {
+  const Dims &d = a.d;
+  const int L = d.n_fit;
+  const unsigned gm = (unsigned)((a.rows + BM - 1) / BM);
+  for (int l = 0; l < L; ++l) {
+    GemmArgs g{};
+    g.mode = FIT_FWD;
+    g.layer = l;
+    g.in = d.fw[l];
+    g.out = d.fw[l + 1];
+    g.K = g.in;
+    g.N = g.out;
+    g.ntypes = d.ntypes;
+    g.type_start = a.type_start;
+    g.fwt = a.fwt;
+    g.fo = a.fo;
+    g.X = (l == 0) ? a.X0 : a.Y[l];
+    g.Tt = a.Tt[l + 1];
+    g.Y = a.Y[l + 1];
+    hipLaunchKernelGGL(k_fit_gemm<FIT_FWD>, dim3(gm, (unsigned)((g.N + BN - 1) / BN)), dim3(256), 0, s, g);
+  }
+  hipLaunchKernelGGL(k_fit_out, dim3((unsigned)((a.rows + 3) / 4)), dim3(256), 0, s, a.type_start, d.ntypes,
+                     a.atom_of_pos, a.fwt, a.fo, L, d.fw[L], a.Y[L], a.rows, a.eatom);
+  for (int l = L - 1; l >= 0; --l) {
+    GemmArgs g{};
+    g.mode = FIT_BWD;
+    g.layer = l;
+    g.in = d.fw[l];
+    g.out = d.fw[l + 1];
+    g.K = g.out;
+    g.N = g.in;
+    g.ntypes = d.ntypes;
+    g.type_start = a.type_start;
+    g.fwt = a.fwt;
+    g.fo = a.fo;
+    g.Tt = a.Tt[l + 1];
+    g.gY = (l == L - 1) ? nullptr : a.G[l + 1];
+    g.gX = a.G[l];
+    hipLaunchKernelGGL(k_fit_gemm<FIT_BWD>, dim3(gm, (unsigned)((g.N + BN - 1) / BN)), dim3(256), 0, s, g);
+  }
+}
+
+}  // namespace dpk

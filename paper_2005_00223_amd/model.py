@@ -1,0 +1,107 @@
+"""torch-facing wrapper of the C ABI: tensors for device memory, the current
+HIP stream for ordering.  All arithmetic happens in libdpmi's kernels."""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _box9(box) -> list:
+    b = np.asarray(box, dtype=np.float64)
+    if b.size == 3:
+        return [b[0], 0, 0, 0, b[1], 0, 0, 0, b[2]]
+    return list(b.reshape(9))
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+class DPModel:
+    """A loaded Deep Potential model on one GPU.
+
+    blob: bytes in the DPMIBLOB v1 layout.  precision: "fp64" (the others
+    come with the mixed-precision kernels)."""
+
+    def __init__(self, blob: bytes, precision: str = "fp64", device: int | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("DPModel needs a ROCm GPU; there is no CPU path")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        stream = torch.cuda.current_stream(self.device)
+        self.ctx = L.dp_create(self.device.index, stream.cuda_stream)
+        self.precision = precision
+        L.dp_set_model(self.ctx, bytes(blob), L.PRECISION[precision])
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            L.dp_destroy(ctx)
+            self.ctx = None
+
+    def set_precision(self, precision: str):
+        L.dp_set_precision(self.ctx, L.PRECISION[precision])
+        self.precision = precision
+
+    def _dev(self, x, dtype):
+        t = torch.as_tensor(x, dtype=dtype)
+        return t.to(self.device).contiguous()
+
+    def compute(self, coords, types, box, keep_intermediates=False):
+        """Energy (eV, 0-d), forces [N,3] (eV/A), virial [3,3] (eV) as
+        double tensors on the GPU."""
+        x = self._dev(coords, torch.float64)
+        t = self._dev(types, torch.int32)
+        n = x.shape[0]
+        e = torch.empty(1, dtype=torch.float64, device=self.device)
+        f = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        v = torch.empty(9, dtype=torch.float64, device=self.device)
+        L.dp_keep_intermediates(self.ctx, keep_intermediates)
+        L.dp_compute(self.ctx, n, _ptr(x), _ptr(t), _box9(box), _ptr(e), _ptr(f), _ptr(v))
+        return e[0], f, v.view(3, 3)
+
+    def nlist(self, natoms, nnei, ntypes, with_list=True):
+        """(nlist [N, nnei], nreal [N, ntypes]) of the last evaluation;
+        with_list=False fetches only the real-neighbour counts."""
+        nl = torch.empty((natoms, nnei), dtype=torch.int32, device=self.device) if with_list else None
+        nr = torch.empty((natoms, ntypes), dtype=torch.int32, device=self.device)
+        L.dp_get_nlist(self.ctx, _ptr(nl), _ptr(nr))
+        return nl, nr
+
+    def intermediates(self, natoms, M1, M2, nnei, which=("atom_e", "T", "D", "net_deriv")):
+        """Per-atom intermediates of the last evaluation (net_deriv needs
+        compute(..., keep_intermediates=True); its padded slots are 0)."""
+        out = {}
+        if "atom_e" in which:
+            out["atom_e"] = torch.empty(natoms, dtype=torch.float64, device=self.device)
+        if "T" in which:
+            out["T"] = torch.empty((natoms, M1, 4), dtype=torch.float64, device=self.device)
+        if "D" in which:
+            out["D"] = torch.empty((natoms, M1 * M2), dtype=torch.float64, device=self.device)
+        if "net_deriv" in which:
+            out["net_deriv"] = torch.empty((natoms, nnei, 4), dtype=torch.float64, device=self.device)
+        L.dp_get_intermediates(self.ctx, *(_ptr(out.get(k)) for k in ("atom_e", "T", "D", "net_deriv")))
+        return out
+
+    def md_run(self, coords, vel, types, box, masses, dt, nsteps, skin=2.0, thermo_every=20, forces=None):
+        """NVE velocity Verlet in place on coords/vel (double CUDA tensors).
+        Returns the thermo tensor [nsteps//thermo_every + 1, 6]."""
+        assert coords.dtype == torch.float64 and vel.dtype == torch.float64 and coords.is_cuda and vel.is_cuda
+        t = self._dev(types, torch.int32)
+        n = coords.shape[0]
+        rows = nsteps // thermo_every + 1 if thermo_every > 0 else 0
+        th = torch.zeros((max(rows, 1), 6), dtype=torch.float64, device=self.device)
+        m = list(np.asarray(masses, dtype=np.float64)) + [1.0] * (8 - len(masses))
+        L.dp_md_run(self.ctx, n, _ptr(coords), _ptr(vel), _ptr(t), _box9(box), m, dt, skin, nsteps,
+                    max(thermo_every, 1), _ptr(th) if rows else None, _ptr(forces))
+        return th[:rows]
+
+    def stats(self):
+        return L.dp_get_stats(self.ctx)
+
+    def enable_timing(self, on=True):
+        L.dp_enable_timing(self.ctx, on)
+
+    def timing(self, name):
+        return L.dp_get_timing(self.ctx, name)
