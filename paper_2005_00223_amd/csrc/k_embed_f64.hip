@@ -19,7 +19,8 @@
 // Matrix layout: each layer is computed transposed, Z^T[out x 16] = W^T H^T,
 // with the 16 neighbours of a tile as the MFMA N dimension.  For
 // v_mfma_f64_16x16x4: A lane l holds A[l%16][l/16], B lane l holds
-// B[l/16][l%16], and D register r of lane l is D[4(l/16)+r][l%16].
+// B[l/16][l%16], and D register r of lane l is D[4r + l/16][l%16] (the f64
+// variant interleaves rows by register, unlike the f32-output variants).
 // Weights stream from L2 in their padded [K][M] layout; activations pass
 // between layers through a per-wave LDS tile [feature][neighbour].
 #include "dp_internal.h"
@@ -171,7 +172,7 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
             if (mt < nmt) {
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
-                const int f = mt * 16 + (lane >> 4) * 4 + r, n = lane & 15;
+                const int f = mt * 16 + 4 * r + (lane >> 4), n = lane & 15;
                 if (f < rows_out) {
                   double h = 0.0;
                   if (f < out) {
@@ -200,7 +201,7 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
         wave_sync();
       }
     }
-    // T = Tacc / Nc -> global and LDS; lane holds T[mt*16 + 4(l/16) + r][l%16]
+    // T = Tacc / Nc -> global and LDS; lane holds T[mt*16 + 4r + l/16][l%16]
     {
       const int comp = lane & 15;
       double *Tg = a.T + (int64_t)i * d.M1 * 4;
@@ -209,7 +210,7 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
         if (mt < nmtG) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int f = mt * 16 + (lane >> 4) * 4 + r;
+            const int f = mt * 16 + 4 * r + (lane >> 4);
             const double v = Tacc[mt][r] * d.inv_nc;
             if (comp < 4) {
               Tl[f * 4 + comp] = v;
@@ -230,7 +231,7 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
           v4d z = mfma64(Tl[(mt * 16 + (lane & 15)) * 4 + (lane >> 4)], bv, v4d{0.0, 0.0, 0.0, 0.0});
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int f = mt * 16 + (lane >> 4) * 4 + r;
+            const int f = mt * 16 + 4 * r + (lane >> 4);
             if (f < d.M1 && b < d.M2) Dp[f * d.M2 + b] = z[r];
           }
         }
@@ -358,7 +359,7 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_bwd_f64(EmbedArgs a, E
             if (mt < nmt) {
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
-                const int f = mt * 16 + (lane >> 4) * 4 + r, n = lane & 15;
+                const int f = mt * 16 + 4 * r + (lane >> 4), n = lane & 15;
                 double h = 0.0, hd = 0.0;
                 if (f < out) {
                   const double th = tanh(acc[0][mt][r] + bias[f]);

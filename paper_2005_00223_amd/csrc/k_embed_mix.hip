@@ -1,0 +1,720 @@
+// Mixed-precision embedding net + descriptor (the paper's MIX-16 scheme,
+// Section V-A "Mixed-precision computation"): the embedding layers after
+// the first are 16-bit matrix-core products (FP16 or BF16, v_mfma_f32_16x16x32)
+// with FP32 accumulation; the rank-1 first layer, tanh, the skip adds and
+// the descriptor contractions stay in FP32; distances, the environment
+// matrix, the force Jacobian and every force/virial sum stay in FP64.
+//
+// Layout.  A wave works on tiles of 16 neighbours; every layer is computed
+// transposed (Z^T = W^T H^T, neighbours as the MFMA N dimension).  The f32
+// output of v_mfma_f32_16x16x32 leaves lane l with rows 4(l/16)+r (r = 0..3)
+// of column l%16, i.e. four consecutive features of one neighbour per
+// 16-row tile.  The next layer's B operand needs eight K values of that same
+// neighbour per lane, so the K dimension is permuted: k-step kk takes, in
+// lane group g = l/16, the features 16(2kk + v/4) + 4g + v%4 (v = 0..7) --
+// exactly the registers of output tiles 2kk and 2kk+1.  The host stores the
+// weight A operands in this permuted order, lane by lane, so activations go
+// from one layer to the next without leaving registers.  Skip partners that
+// live in another lane (the doubling skip) are read back from a per-wave LDS
+// copy of the previous layer.
+//
+// The weights of every (centre type, neighbour type) net are copied into LDS
+// once per block.  Per net: w1[32], b1[32] (f32, by slot), A2 [MT2][KS2][64
+// lanes][8] (16-bit), b2[S2] (f32), A3 [MT3][KS3][64][8], b3[S3] (f32).
+//
+// Pass 1: T += G R^T by an LDS transpose of G and v_mfma_f32_16x16x4f32 (K =
+// the 16 neighbours), T /= Nc, D = T T_<^T (f32 MFMA), D stored 16-bit for
+// the 16-bit fitting layer.  Pass 2: forward tangent mode (h and dh/ds in
+// two MFMA column sets sharing the A operands), then
+//   a = G^T dT, b = G'^T dT as 16-bit MFMAs with G straight from registers,
+//   dE/dR = a + (R . b) e_0, and per 64 neighbours one FP64 pass of
+//   g_ij = dE/dR dR/dr, F_i += g, F_j -= g (atomics), Xi -= g (x) r.
+#include "dp_internal.h"
+#include "dp_mix.h"
+
+namespace dpk {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int P> struct HT;
+template <> struct HT<0> {
+  typedef _Float16 e;
+  typedef _Float16 v8 __attribute__((ext_vector_type(8)));
+};
+template <> struct HT<1> {
+  typedef __bf16 e;
+  typedef __bf16 v8 __attribute__((ext_vector_type(8)));
+};
+
+template <int P>
+__device__ inline v4f mfma16(typename HT<P>::v8 a, typename HT<P>::v8 b, v4f c);
+template <>
+__device__ inline v4f mfma16<0>(HT<0>::v8 a, HT<0>::v8 b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+template <>
+__device__ inline v4f mfma16<1>(HT<1>::v8 a, HT<1>::v8 b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ inline v4f mfma32(float a, float b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+template <int P>
+__device__ inline typename HT<P>::v8 pack8(const float (&x)[4], const float (&y)[4]) {
+  typedef typename HT<P>::e E;
+  typename HT<P>::v8 v;
+  v[0] = (E)x[0]; v[1] = (E)x[1]; v[2] = (E)x[2]; v[3] = (E)x[3];
+  v[4] = (E)y[0]; v[5] = (E)y[1]; v[6] = (E)y[2]; v[7] = (E)y[3];
+  return v;
+}
+
+// tanh(x) = 1 - 2 / (exp(2x) + 1) with the hardware exp2 and reciprocal;
+// absolute error about 2e-7, well below the 16-bit storage of the layers.
+__device__ inline float tanh_f(float x) {
+  const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
+__device__ inline void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// skip kind of a layer (in -> out): 0 none, 1 identity, 2 doubling
+__host__ __device__ constexpr int skip_kind(int in, int out) { return out == in ? 1 : (out == 2 * in ? 2 : 0); }
+
+template <int W1, int W2, int W3>
+struct Shape {
+  static constexpr int S1 = 32;                    // layer-1 slots (= K of layer 2)
+  static constexpr int S2 = (W2 + 31) / 32 * 32;   // layer-2 slots (= K of layer 3)
+  static constexpr int MT2 = S2 / 16;
+  static constexpr int KS3 = S2 / 32;
+  static constexpr int MT3 = (W3 + 15) / 16;
+  static constexpr int S3 = MT3 * 16;
+  static constexpr int KSC = (MT3 + 1) / 2;        // k-steps of the contraction over G's slots
+  static constexpr int SK1 = (W1 <= 2) ? 1 : 0;    // first layer adds s (out = in or 2 in of a scalar)
+  static constexpr int SK2 = skip_kind(W1, W2);
+  static constexpr int SK3 = skip_kind(W2, W3);
+  // per-net byte offsets in the LDS copy
+  static constexpr int O_W1 = 0, O_B1 = 128, O_A2 = 256;
+  static constexpr int O_B2 = O_A2 + MT2 * 1 * 1024;
+  static constexpr int O_A3 = O_B2 + S2 * 4;
+  static constexpr int O_B3 = O_A3 + MT3 * KS3 * 1024;
+  static constexpr int NET_BYTES = O_B3 + S3 * 4;
+  // per-wave LDS scratch (bytes)
+  static constexpr int P1_H1 = 0;                       // float [16][S1]
+  static constexpr int P1_H2 = P1_H1 + 16 * S1 * 4;     // float [16][S2]
+  static constexpr int P1_G = P1_H2 + 16 * S2 * 4;      // float [16][S3]
+  static constexpr int P1_R = P1_G + 16 * S3 * 4;       // float [16][4]
+  static constexpr int P1_T = P1_R + 256;               // float [S3][4]
+  static constexpr int P1_BYTES = P1_T + S3 * 16;
+  static constexpr int P2_H1 = 0;                       // float [2][16][S1] (h, dh)
+  static constexpr int P2_H2 = P2_H1 + 2 * 16 * S1 * 4; // float [2][16][S2]
+  static constexpr int P2_R = P2_H2 + 2 * 16 * S2 * 4;  // float [16][4]
+  static constexpr int P2_GR = P2_R + 256;              // float [64][4]
+  static constexpr int P2_DT = P2_GR + 1024;            // float [S3][4]
+  static constexpr int P2_BYTES = P2_DT + S3 * 16;
+};
+
+constexpr int MIX_WAVES = 4;
+
+// rows handled by wave gw of nwaves: a contiguous chunk
+__device__ inline void wave_rows(int64_t rows, int64_t &p0, int64_t &p1) {
+  const int64_t nwaves = (int64_t)gridDim.x * MIX_WAVES;
+  const int64_t gw = (int64_t)blockIdx.x * MIX_WAVES + (threadIdx.x >> 6);
+  const int64_t chunk = (rows + nwaves - 1) / nwaves;
+  p0 = gw * chunk;
+  p1 = p0 + chunk < rows ? p0 + chunk : rows;
+}
+
+__device__ inline void copy_nets(unsigned char *dst, const unsigned char *src, int bytes) {
+  const uint4 *s = (const uint4 *)src;
+  uint4 *d = (uint4 *)dst;
+  for (int o = threadIdx.x; o < bytes / 16; o += blockDim.x) d[o] = s[o];
+}
+
+// ---------------------------------------------------------------------------
+// layer 1 on VALU: lane (g, n) computes slots 16 mt + 4 g + r (mt < 2)
+// ---------------------------------------------------------------------------
+template <int W1, bool TANGENT>
+__device__ inline void layer1(const float *w1, const float *b1, float s, int g, float (&h)[2][4], float (&hd)[2][4]) {
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    const float4 w = *(const float4 *)(w1 + 16 * mt + 4 * g);
+    const float4 b = *(const float4 *)(b1 + 16 * mt + 4 * g);
+    const float wv[4] = {w.x, w.y, w.z, w.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (16 * mt >= W1) {  // whole tile is padding (compile-time)
+        h[mt][r] = 0.f;
+        hd[mt][r] = 0.f;
+        continue;
+      }
+      const int f = 16 * mt + 4 * g + r;
+      const float t = tanh_f(s * wv[r] + bv[r]);
+      float hv = t, dv = (1.f - t * t) * wv[r];
+      if (W1 <= 2) {
+        hv += s;
+        dv += 1.f;
+      }
+      h[mt][r] = f < W1 ? hv : 0.f;
+      if (TANGENT) hd[mt][r] = f < W1 ? dv : 0.f;
+    }
+  }
+}
+
+// one MFMA layer from 16-bit weights in LDS; acc initialised with the bias
+template <int P, int MT, int KS>
+__device__ inline void layer_mfma(const unsigned char *Aops, const float *bias, const typename HT<P>::v8 (&B)[KS],
+                                  int lane, int g, v4f (&acc)[MT]) {
+  typedef typename HT<P>::v8 V;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const float4 b = *(const float4 *)(bias + 16 * mt + 4 * g);
+    acc[mt] = v4f{b.x, b.y, b.z, b.w};
+  }
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const V a = *(const V *)(Aops + ((mt * KS + kk) * 64 + lane) * 16);
+      acc[mt] = mfma16<P>(a, B[kk], acc[mt]);
+    }
+}
+
+// tangent columns: same A operands, zero initial accumulator
+template <int P, int MT, int KS>
+__device__ inline void layer_mfma_tan(const unsigned char *Aops, const typename HT<P>::v8 (&B)[KS], int lane,
+                                      v4f (&acc)[MT]) {
+  typedef typename HT<P>::v8 V;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) acc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const V a = *(const V *)(Aops + ((mt * KS + kk) * 64 + lane) * 16);
+      acc[mt] = mfma16<P>(a, B[kk], acc[mt]);
+    }
+}
+
+// value of the previous layer added by the skip connection for output
+// feature f of lane (g, n): the same register when f < IN, the LDS copy
+// otherwise (doubling skip); 0 when the layer has no skip.
+template <int IN, int OUT, int SK, int MTI>
+__device__ inline float skip_val(int f, int mt, int r, const float (&prev)[MTI][4], const float *prev_lds, int n,
+                                 int stride) {
+  if (SK == 0 || f >= OUT) return 0.f;
+  if (SK == 1) return (mt < MTI) ? prev[mt < MTI ? mt : 0][r] : 0.f;
+  // doubling
+  float own = (mt < MTI) ? prev[mt < MTI ? mt : 0][r] : 0.f;
+  const int src = f >= IN ? f - IN : 0;
+  const float other = prev_lds[n * stride + src];
+  return f < IN ? own : other;
+}
+
+template <int W1, int W2, int W3, int P>
+__global__ void __launch_bounds__(64 * MIX_WAVES) k_embed_fwd_mix(MixArgs a) {
+  typedef Shape<W1, W2, W3> S;
+  typedef typename HT<P>::v8 V;
+  typedef typename HT<P>::e E;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Dims &d = a.d;
+  const int nnets = d.ntypes * d.ntypes;
+  copy_nets(smem, a.nets, nnets * S::NET_BYTES);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, n = lane & 15;
+  unsigned char *ws = smem + nnets * S::NET_BYTES + wv * S::P1_BYTES;
+  float *h1s = (float *)(ws + S::P1_H1);
+  float *h2s = (float *)(ws + S::P1_H2);
+  float *Gs = (float *)(ws + S::P1_G);
+  float *Rs = (float *)(ws + S::P1_R);
+  float *Ts = (float *)(ws + S::P1_T);
+  const int MM = d.M1 * d.M2;
+  int64_t p0, p1;
+  wave_rows(a.rows, p0, p1);
+  for (int64_t p = p0; p < p1; ++p) {
+    const int i = a.atom_of_pos[p];
+    E *Dp = (E *)a.D16 + p * (int64_t)MM;
+    if (i < 0) {
+      for (int o = lane; o < MM; o += 64) Dp[o] = (E)0.f;
+      continue;
+    }
+    const int t = (int)a.xw[i].w;
+    v4f Tacc[S::MT3];
+#pragma unroll
+    for (int mt = 0; mt < S::MT3; ++mt) Tacc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < d.ntypes; ++u) {
+      const unsigned char *net = smem + (t * d.ntypes + u) * S::NET_BYTES;
+      const float *w1 = (const float *)(net + S::O_W1), *b1 = (const float *)(net + S::O_B1);
+      const float *b2 = (const float *)(net + S::O_B2), *b3 = (const float *)(net + S::O_B3);
+      const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
+      const int64_t base = (int64_t)i * d.nnei + d.off[u];
+      for (int n0 = 0; n0 < cnt; n0 += 16) {
+        const bool valid = n0 + n < cnt;
+        const double4 r4 = valid ? a.rt[base + n0 + n] : make_double4(0.0, 0.0, 0.0, 0.0);
+        const float s = (float)r4.x;
+        if (g == 0) *(float4 *)(Rs + 4 * n) = make_float4((float)r4.x, (float)r4.y, (float)r4.z, (float)r4.w);
+        float h1[2][4], hd_unused[2][4];
+        layer1<W1, false>(w1, b1, s, g, h1, hd_unused);
+        if (S::SK2 == 2)
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt)
+            *(float4 *)(h1s + n * S::S1 + 16 * mt + 4 * g) = make_float4(h1[mt][0], h1[mt][1], h1[mt][2], h1[mt][3]);
+        V B2[1] = {pack8<P>(h1[0], h1[1])};
+        v4f acc2[S::MT2];
+        layer_mfma<P, S::MT2, 1>(net + S::O_A2, b2, B2, lane, g, acc2);
+        wsync();
+        float h2[S::MT2][4];
+#pragma unroll
+        for (int mt = 0; mt < S::MT2; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int f = 16 * mt + 4 * g + r;
+            float v = 0.f;
+            if (16 * mt < W2 && f < W2) v = tanh_f(acc2[mt][r]) + skip_val<W1, W2, S::SK2, 2>(f, mt, r, h1, h1s, n, S::S1);
+            h2[mt][r] = v;
+          }
+        if (S::SK3 == 2)
+#pragma unroll
+          for (int mt = 0; mt < S::MT2; ++mt)
+            *(float4 *)(h2s + n * S::S2 + 16 * mt + 4 * g) = make_float4(h2[mt][0], h2[mt][1], h2[mt][2], h2[mt][3]);
+        V B3[S::KS3];
+#pragma unroll
+        for (int kk = 0; kk < S::KS3; ++kk) B3[kk] = pack8<P>(h2[2 * kk], h2[2 * kk + 1]);
+        v4f acc3[S::MT3];
+        layer_mfma<P, S::MT3, S::KS3>(net + S::O_A3, b3, B3, lane, g, acc3);
+        wsync();
+        // G -> LDS as [neighbour][feature]
+#pragma unroll
+        for (int mt = 0; mt < S::MT3; ++mt) {
+          float gv[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int f = 16 * mt + 4 * g + r;
+            gv[r] = (f < W3) ? tanh_f(acc3[mt][r]) + skip_val<W2, W3, S::SK3, S::MT2>(f, mt, r, h2, h2s, n, S::S2)
+                             : 0.f;
+          }
+          *(float4 *)(Gs + n * S::S3 + 16 * mt + 4 * g) = make_float4(gv[0], gv[1], gv[2], gv[3]);
+        }
+        wsync();
+        // T[f][c] += sum_nb G[nb][f] R[nb][c]: A = G^T (rows f), B = R (K = neighbours)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int nb = 4 * kk + g;
+          const float rb = n < 4 ? Rs[4 * nb + n] : 0.f;
+#pragma unroll
+          for (int mt = 0; mt < S::MT3; ++mt) Tacc[mt] = mfma32(Gs[nb * S::S3 + 16 * mt + n], rb, Tacc[mt]);
+        }
+        wsync();
+      }
+    }
+    // T / Nc: lane (g, n) holds T[16 mt + 4 g + r][n] for n < 4
+    float *Tg = a.T32 + (int64_t)i * d.M1 * 4;
+#pragma unroll
+    for (int mt = 0; mt < S::MT3; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int f = 16 * mt + 4 * g + r;
+        const float v = Tacc[mt][r] * (float)d.inv_nc;
+        if (n < 4) {
+          Ts[4 * f + n] = v;
+          if (f < d.M1) Tg[4 * f + n] = v;
+        }
+      }
+    wsync();
+    // D = T T_<^T, K = 4 components
+    {
+      const float bb = n < d.M2 ? Ts[4 * n + g] : 0.f;
+#pragma unroll
+      for (int mt = 0; mt < S::MT3; ++mt) {
+        const v4f z = mfma32(Ts[4 * (16 * mt + n) + g], bb, v4f{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int f = 16 * mt + 4 * g + r;
+          if (f < d.M1 && n < d.M2) Dp[f * d.M2 + n] = (E)z[r];
+        }
+      }
+    }
+    wsync();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass 2
+// ---------------------------------------------------------------------------
+__device__ inline void switch64(double r, double rcs, double rc, double inv_w, double &sw, double &dsw) {
+  if (r < rcs) {
+    sw = 1.0;
+    dsw = 0.0;
+  } else if (r < rc) {
+    const double x = (r - rcs) * inv_w;
+    sw = x * x * x * (-6.0 * x * x + 15.0 * x - 10.0) + 1.0;
+    dsw = x * x * (-30.0 * x * x + 60.0 * x - 30.0) * inv_w;
+  } else {
+    sw = 0.0;
+    dsw = 0.0;
+  }
+}
+
+template <int W1, int W2, int W3, int P>
+__global__ void __launch_bounds__(64 * MIX_WAVES) k_embed_bwd_mix(MixArgs a) {
+  typedef Shape<W1, W2, W3> S;
+  typedef typename HT<P>::v8 V;
+  typedef typename HT<P>::e E;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double vred[MIX_WAVES][9];
+  const Dims &d = a.d;
+  const int nnets = d.ntypes * d.ntypes;
+  copy_nets(smem, a.nets, nnets * S::NET_BYTES);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, n = lane & 15;
+  unsigned char *ws = smem + nnets * S::NET_BYTES + wv * S::P2_BYTES;
+  float *h1s = (float *)(ws + S::P2_H1), *hd1s = h1s + 16 * S::S1;
+  float *h2s = (float *)(ws + S::P2_H2), *hd2s = h2s + 16 * S::S2;
+  float *Rs = (float *)(ws + S::P2_R);
+  float *gRs = (float *)(ws + S::P2_GR);
+  float *dTs = (float *)(ws + S::P2_DT);
+  const int MM = d.M1 * d.M2;
+  const double rc = d.rcut, rcs = d.rcut_smth, inv_w = 1.0 / (d.rcut - d.rcut_smth);
+  double vir[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) vir[k] = 0.0;
+  int64_t p0, p1;
+  wave_rows(a.rows, p0, p1);
+  for (int64_t p = p0; p < p1; ++p) {
+    const int i = a.atom_of_pos[p];
+    if (i < 0) continue;
+    const int t = (int)a.xw[i].w;
+    // dT / Nc in LDS, rows f >= M1 zero
+    {
+      const float *Ti = a.T32 + (int64_t)i * d.M1 * 4;
+      const float *dDp = a.dD32 + p * (int64_t)MM;
+      for (int o = lane; o < S::S3 * 4; o += 64) {
+        const int f = o >> 2, c = o & 3;
+        float v = 0.f;
+        if (f < d.M1) {
+          for (int b = 0; b < d.M2; ++b) v += dDp[f * d.M2 + b] * Ti[b * 4 + c];
+          if (f < d.M2)
+            for (int a2 = 0; a2 < d.M1; ++a2) v += dDp[a2 * d.M2 + f] * Ti[a2 * 4 + c];
+        }
+        dTs[o] = v * (float)d.inv_nc;
+      }
+    }
+    wsync();
+    // B operand of the contraction: K = G's slots (permuted as the layer chain), N = components
+    V dTB[S::KSC];
+#pragma unroll
+    for (int kk = 0; kk < S::KSC; ++kk) {
+      float x[4], y[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int f0 = 16 * (2 * kk) + 4 * g + v, f1 = 16 * (2 * kk + 1) + 4 * g + v;
+        x[v] = (n < 4 && f0 < S::S3) ? dTs[4 * f0 + n] : 0.f;
+        y[v] = (n < 4 && f1 < S::S3) ? dTs[4 * f1 + n] : 0.f;
+      }
+      dTB[kk] = pack8<P>(x, y);
+    }
+    double fi0 = 0.0, fi1 = 0.0, fi2 = 0.0;
+    for (int u = 0; u < d.ntypes; ++u) {
+      const unsigned char *net = smem + (t * d.ntypes + u) * S::NET_BYTES;
+      const float *w1 = (const float *)(net + S::O_W1), *b1 = (const float *)(net + S::O_B1);
+      const float *b2 = (const float *)(net + S::O_B2), *b3 = (const float *)(net + S::O_B3);
+      const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
+      const int64_t base = (int64_t)i * d.nnei + d.off[u];
+      for (int n0 = 0; n0 < cnt; n0 += 16) {
+        const bool valid = n0 + n < cnt;
+        const double4 r4 = valid ? a.rt[base + n0 + n] : make_double4(0.0, 0.0, 0.0, 0.0);
+        const float s = (float)r4.x;
+        if (g == 0) *(float4 *)(Rs + 4 * n) = make_float4((float)r4.x, (float)r4.y, (float)r4.z, (float)r4.w);
+        float h1[2][4], hd1[2][4];
+        layer1<W1, true>(w1, b1, s, g, h1, hd1);
+        if (S::SK2 == 2)
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt) {
+            *(float4 *)(h1s + n * S::S1 + 16 * mt + 4 * g) = make_float4(h1[mt][0], h1[mt][1], h1[mt][2], h1[mt][3]);
+            *(float4 *)(hd1s + n * S::S1 + 16 * mt + 4 * g) =
+                make_float4(hd1[mt][0], hd1[mt][1], hd1[mt][2], hd1[mt][3]);
+          }
+        V B2h[1] = {pack8<P>(h1[0], h1[1])}, B2d[1] = {pack8<P>(hd1[0], hd1[1])};
+        v4f acc2[S::MT2], acc2d[S::MT2];
+        layer_mfma<P, S::MT2, 1>(net + S::O_A2, b2, B2h, lane, g, acc2);
+        layer_mfma_tan<P, S::MT2, 1>(net + S::O_A2, B2d, lane, acc2d);
+        wsync();
+        float h2[S::MT2][4], hd2[S::MT2][4];
+#pragma unroll
+        for (int mt = 0; mt < S::MT2; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int f = 16 * mt + 4 * g + r;
+            float hv = 0.f, dv = 0.f;
+            if (16 * mt < W2 && f < W2) {
+              const float th = tanh_f(acc2[mt][r]);
+              hv = th + skip_val<W1, W2, S::SK2, 2>(f, mt, r, h1, h1s, n, S::S1);
+              dv = (1.f - th * th) * acc2d[mt][r] + skip_val<W1, W2, S::SK2, 2>(f, mt, r, hd1, hd1s, n, S::S1);
+            }
+            h2[mt][r] = hv;
+            hd2[mt][r] = dv;
+          }
+        if (S::SK3 == 2)
+#pragma unroll
+          for (int mt = 0; mt < S::MT2; ++mt) {
+            *(float4 *)(h2s + n * S::S2 + 16 * mt + 4 * g) = make_float4(h2[mt][0], h2[mt][1], h2[mt][2], h2[mt][3]);
+            *(float4 *)(hd2s + n * S::S2 + 16 * mt + 4 * g) =
+                make_float4(hd2[mt][0], hd2[mt][1], hd2[mt][2], hd2[mt][3]);
+          }
+        V B3h[S::KS3], B3d[S::KS3];
+#pragma unroll
+        for (int kk = 0; kk < S::KS3; ++kk) {
+          B3h[kk] = pack8<P>(h2[2 * kk], h2[2 * kk + 1]);
+          B3d[kk] = pack8<P>(hd2[2 * kk], hd2[2 * kk + 1]);
+        }
+        v4f acc3[S::MT3], acc3d[S::MT3];
+        layer_mfma<P, S::MT3, S::KS3>(net + S::O_A3, b3, B3h, lane, g, acc3);
+        layer_mfma_tan<P, S::MT3, S::KS3>(net + S::O_A3, B3d, lane, acc3d);
+        wsync();
+        float G[S::KSC * 2][4], Gd[S::KSC * 2][4];
+#pragma unroll
+        for (int mt = 0; mt < S::KSC * 2; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int f = 16 * mt + 4 * g + r;
+            float gv = 0.f, dv = 0.f;
+            if (mt < S::MT3 && f < W3) {
+              const float th = tanh_f(acc3[mt < S::MT3 ? mt : 0][r]);
+              gv = th + skip_val<W2, W3, S::SK3, S::MT2>(f, mt, r, h2, h2s, n, S::S2);
+              dv = (1.f - th * th) * acc3d[mt < S::MT3 ? mt : 0][r] +
+                   skip_val<W2, W3, S::SK3, S::MT2>(f, mt, r, hd2, hd2s, n, S::S2);
+            }
+            G[mt][r] = gv;
+            Gd[mt][r] = dv;
+          }
+        // a = G^T dT, b = G'^T dT; lane (g, c) gets rows nb = 4 g + r, column c
+        v4f ca = v4f{0.f, 0.f, 0.f, 0.f}, cb = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < S::KSC; ++kk) {
+          ca = mfma16<P>(pack8<P>(G[2 * kk], G[2 * kk + 1]), dTB[kk], ca);
+          cb = mfma16<P>(pack8<P>(Gd[2 * kk], Gd[2 * kk + 1]), dTB[kk], cb);
+        }
+        const int slot0 = n0 & 63;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int nb = 4 * g + r;
+          float pr = n < 4 ? Rs[4 * nb + n] * cb[r] : 0.f;
+          pr += __shfl_xor(pr, 1);
+          pr += __shfl_xor(pr, 2);
+          const float gr = ca[r] + (n == 0 ? pr : 0.f);
+          if (n < 4) gRs[4 * (slot0 + nb) + n] = gr;
+        }
+        wsync();
+        // every 64 neighbours (or at the end of the type block): FP64 force pass
+        if (((n0 + 16) & 63) == 0 || n0 + 16 >= cnt) {
+          const int c0 = n0 & ~63;
+          const int q = c0 + lane;
+          if (q < cnt) {
+            const float4 gr = *(const float4 *)(gRs + 4 * lane);
+            const double g0 = gr.x, g1 = gr.y, g2 = gr.z, g3 = gr.w;
+            const double4 D4 = a.dr[base + q];
+            const int j = a.nlist[base + q];
+            if (a.net_deriv) {
+              double *nd = a.net_deriv + (base + q) * 4;
+              nd[0] = g0; nd[1] = g1; nd[2] = g2; nd[3] = g3;
+            }
+            const double dx = D4.x, dy = D4.y, dz = D4.z, r = D4.w;
+            double sw, dsw;
+            switch64(r, rcs, rc, inv_w, sw, dsw);
+            const double ir = 1.0 / r;
+            const double sv = sw * ir;
+            const double ds = (dsw * r - sw) * ir * ir;
+            const double tt = sv * ir;
+            const double dtt = dsw * ir * ir - 2.0 * sw * ir * ir * ir;
+            const double gd = g1 * dx + g2 * dy + g3 * dz;
+            const double cc = (g0 * ds + dtt * gd) * ir;
+            const double gx = cc * dx + tt * g1, gy = cc * dy + tt * g2, gz = cc * dz + tt * g3;
+            fi0 += gx;
+            fi1 += gy;
+            fi2 += gz;
+            unsafeAtomicAdd(a.force + 3 * (int64_t)j + 0, -gx);
+            unsafeAtomicAdd(a.force + 3 * (int64_t)j + 1, -gy);
+            unsafeAtomicAdd(a.force + 3 * (int64_t)j + 2, -gz);
+            vir[0] -= gx * dx; vir[1] -= gx * dy; vir[2] -= gx * dz;
+            vir[3] -= gy * dx; vir[4] -= gy * dy; vir[5] -= gy * dz;
+            vir[6] -= gz * dx; vir[7] -= gz * dy; vir[8] -= gz * dz;
+          }
+          wsync();
+        }
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      fi0 += __shfl_xor(fi0, o);
+      fi1 += __shfl_xor(fi1, o);
+      fi2 += __shfl_xor(fi2, o);
+    }
+    if (lane == 0) {
+      unsafeAtomicAdd(a.force + 3 * (int64_t)i + 0, fi0);
+      unsafeAtomicAdd(a.force + 3 * (int64_t)i + 1, fi1);
+      unsafeAtomicAdd(a.force + 3 * (int64_t)i + 2, fi2);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    double v = vir[k];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
+    if (lane == 0) vred[wv][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 9) {
+    double v = 0.0;
+    for (int w = 0; w < MIX_WAVES; ++w) v += vred[w][threadIdx.x];
+    a.vir_part[(int64_t)blockIdx.x * 9 + threadIdx.x] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side: weight packing and dispatch
+// ---------------------------------------------------------------------------
+template <int W1, int W2, int W3>
+static size_t net_bytes_t() {
+  return Shape<W1, W2, W3>::NET_BYTES;
+}
+
+static inline uint16_t to_f16(float x) {
+  _Float16 h = (_Float16)x;
+  uint16_t u;
+  memcpy(&u, &h, 2);
+  return u;
+}
+
+static inline uint16_t to_bf16(float x) {
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;  // round to nearest even (finite inputs)
+  return (uint16_t)(u >> 16);
+}
+
+// Pack one net (t,u) into the LDS image; W[l] are row-major [in][out] doubles.
+template <int W1, int W2, int W3>
+static void pack_net_t(const double *const *W, const double *const *b, int prec, unsigned char *out) {
+  typedef Shape<W1, W2, W3> S;
+  memset(out, 0, S::NET_BYTES);
+  float *w1 = (float *)(out + S::O_W1), *b1 = (float *)(out + S::O_B1);
+  for (int f = 0; f < W1; ++f) {
+    w1[f] = (float)W[0][f];
+    b1[f] = (float)b[0][f];
+  }
+  auto h16 = [&](double v) { return prec == 0 ? to_f16((float)v) : to_bf16((float)v); };
+  // permuted K slot of (kk, lane group g, element v)
+  auto kslot = [](int kk, int g, int v) { return 16 * (2 * kk + v / 4) + 4 * g + (v % 4); };
+  uint16_t *A2 = (uint16_t *)(out + S::O_A2);
+  for (int mt = 0; mt < S::MT2; ++mt)
+    for (int lane = 0; lane < 64; ++lane)
+      for (int v = 0; v < 8; ++v) {
+        const int fo = 16 * mt + (lane & 15), fi = kslot(0, lane >> 4, v);
+        A2[((mt * 1 + 0) * 64 + lane) * 8 + v] = (fo < W2 && fi < W1) ? h16(W[1][fi * W2 + fo]) : 0;
+      }
+  float *b2 = (float *)(out + S::O_B2);
+  for (int f = 0; f < W2; ++f) b2[f] = (float)b[1][f];
+  uint16_t *A3 = (uint16_t *)(out + S::O_A3);
+  for (int mt = 0; mt < S::MT3; ++mt)
+    for (int kk = 0; kk < S::KS3; ++kk)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int v = 0; v < 8; ++v) {
+          const int fo = 16 * mt + (lane & 15), fi = kslot(kk, lane >> 4, v);
+          A3[((mt * S::KS3 + kk) * 64 + lane) * 8 + v] = (fo < W3 && fi < W2) ? h16(W[2][fi * W3 + fo]) : 0;
+        }
+  float *b3 = (float *)(out + S::O_B3);
+  for (int f = 0; f < W3; ++f) b3[f] = (float)b[2][f];
+}
+
+template <int W1, int W2, int W3, int P>
+static void launch_t(hipStream_t s, const MixArgs &a, int pass, int grid) {
+  typedef Shape<W1, W2, W3> S;
+  const int nnets = a.d.ntypes * a.d.ntypes;
+  if (pass == 1) {
+    const size_t shm = (size_t)nnets * S::NET_BYTES + (size_t)MIX_WAVES * S::P1_BYTES;
+    hipLaunchKernelGGL((k_embed_fwd_mix<W1, W2, W3, P>), dim3(grid), dim3(64 * MIX_WAVES), shm, s, a);
+  } else {
+    const size_t shm = (size_t)nnets * S::NET_BYTES + (size_t)MIX_WAVES * S::P2_BYTES;
+    hipLaunchKernelGGL((k_embed_bwd_mix<W1, W2, W3, P>), dim3(grid), dim3(64 * MIX_WAVES), shm, s, a);
+  }
+}
+
+template <int W1, int W2, int W3>
+static size_t lds_t(int ntypes, int pass) {
+  typedef Shape<W1, W2, W3> S;
+  return (size_t)ntypes * ntypes * S::NET_BYTES + (size_t)MIX_WAVES * (pass == 1 ? S::P1_BYTES : S::P2_BYTES);
+}
+
+// supported embedding shapes (widths of the three layers)
+#define DPK_MIX_SHAPES(X) X(25, 50, 100) X(16, 32, 100)
+
+int mix_shape_id(const Dims &d) {
+  if (d.n_emb != 3) return -1;
+  int id = 0;
+#define X(a_, b_, c_)                                         \
+  if (d.ew[1] == a_ && d.ew[2] == b_ && d.ew[3] == c_) return id; \
+  ++id;
+  DPK_MIX_SHAPES(X)
+#undef X
+  return -1;
+}
+
+size_t mix_net_bytes(int shape) {
+  int id = 0;
+#define X(a_, b_, c_)                                  \
+  if (shape == id) return net_bytes_t<a_, b_, c_>(); \
+  ++id;
+  DPK_MIX_SHAPES(X)
+#undef X
+  return 0;
+}
+
+size_t mix_lds_bytes(int shape, int ntypes, int pass) {
+  int id = 0;
+#define X(a_, b_, c_)                                     \
+  if (shape == id) return lds_t<a_, b_, c_>(ntypes, pass); \
+  ++id;
+  DPK_MIX_SHAPES(X)
+#undef X
+  return 0;
+}
+
+void mix_pack_net(int shape, const double *const *W, const double *const *b, int prec, unsigned char *out) {
+  int id = 0;
+#define X(a_, b_, c_)                               \
+  if (shape == id) {                                \
+    pack_net_t<a_, b_, c_>(W, b, prec, out);        \
+    return;                                         \
+  }                                                 \
+  ++id;
+  DPK_MIX_SHAPES(X)
+#undef X
+}
+
+int mix_grid(int64_t rows) {
+  int64_t g = (rows + MIX_WAVES - 1) / MIX_WAVES;
+  if (g > 2048) g = 2048;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+void launch_embed_mix(hipStream_t s, const MixArgs &a, int pass, int grid) {
+  int id = 0;
+#define X(a_, b_, c_)                                     \
+  if (a.shape == id) {                                    \
+    if (a.prec == 0) launch_t<a_, b_, c_, 0>(s, a, pass, grid); \
+    else launch_t<a_, b_, c_, 1>(s, a, pass, grid);       \
+    return;                                               \
+  }                                                       \
+  ++id;
+  DPK_MIX_SHAPES(X)
+#undef X
+}
+
+}  // namespace dpk

@@ -11,8 +11,9 @@
 // Backward layer l: gZ = gY_{l+1} (1 - t^2) is formed while the A tile is
 // loaded, gY_l = gZ W^T (+ the skip's pass-through), gY_0 = dE/dD.
 //
-// MFMA v_mfma_f64_16x16x4; block tile 64 x 64, four waves of 32 x 32,
-// K staged through LDS in steps of 16.
+// MFMA v_mfma_f64_16x16x4 (D register r of lane l is row 4r + l/16,
+// column l%16); block tile 64 x 64, four waves of 32 x 32, K staged through
+// LDS in steps of 16.
 #include "dp_internal.h"
 
 namespace dpk {
@@ -116,7 +117,7 @@ __global__ void __launch_bounds__(256) k_fit_gemm(GemmArgs g) {
     for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + wm * 32 + mi * 16 + (lane >> 4) * 4 + r;
+        const int64_t row = r0 + wm * 32 + mi * 16 + 4 * r + (lane >> 4);
         const int col = c0 + wn * 32 + ni * 16 + (lane & 15);
         if (col >= g.N) continue;
         const double c = acc[mi][ni][r];

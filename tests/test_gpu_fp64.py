@@ -246,7 +246,7 @@ def test_md_matches_oracle_verlet():
     m = gpu_model(w)
     x = torch.tensor(w["coords"], dtype=torch.float64, device="cuda")
     v = torch.tensor(v0, dtype=torch.float64, device="cuda")
-    th = m.md_run(x, v, t, w["box"], w["masses"], 0.5, 20, skin=1.0, thermo_every=5)
+    th = m.md_run(x, v, t, w["box"], w["masses"], 0.5, 20, skin=0.2, thermo_every=5)
     ox, ov, oth = oracle(w).verlet(w["coords"], v0, t, w["box"], w["masses"], 0.5, 20, every=5)
     d = x.cpu().numpy() - ox
     d -= w["box"] * np.round(d / w["box"])
