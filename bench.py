@@ -63,7 +63,7 @@ def cpu_baseline(w, blob, seconds, log_fn):
     o = O.Oracle(blob)
     n = len(w["types"])
     rng = np.random.default_rng(12345)
-    k = min(n, 256)
+    k = min(n, 2048)
     cen = np.sort(rng.choice(n, size=k, replace=False))
     t0 = time.perf_counter()
     o.eval(w["coords"], w["types"], w["box"], centres=cen)
@@ -85,9 +85,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cu500k")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "fp16", "bf16"])
+    ap.add_argument("--precision", default="fp16", choices=["fp64", "fp16", "bf16"])
+    ap.add_argument("--fp64-steps", type=int, default=3, help="FP64 steps timed for the comparison (0 = skip)")
+    ap.add_argument("--rmse-atoms", type=int, default=8, help="atoms sampled for the force RMSE vs the oracle")
     ap.add_argument("--skin", type=float, default=2.0)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -163,9 +165,41 @@ def main():
         "energy_drift_eV_per_atom": drift,
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, blob, args.cpu_seconds, log)
-    print(json.dumps(out), flush=True)
+    # force accuracy of the timed precision at the final MD frame, on sampled atoms
+    if args.rmse_atoms > 0:
+        from oracle import oracle as O
+        e_m, f_m, _ = m.compute(x, t, w["box"])
+        fm = f_m.cpu().numpy()
+        xf = x.cpu().numpy()
+        nl, _ = m.nlist(n, spec.nnei, spec.ntypes)
+        nl = nl.cpu().numpy()
+        o = O.Oracle(blob)
+        rng = np.random.default_rng(7)
+        err, ref = [], []
+        for k in rng.choice(n, size=args.rmse_atoms, replace=False):
+            cen = np.unique(np.concatenate([[k], nl[k][nl[k] >= 0]]))
+            r = o.eval(xf, w["types"], w["box"], centres=cen)
+            err.append(fm[k] - r["force"][k])
+            ref.append(r["force"][k])
+        out["force_rmse_vs_oracle"] = float(np.sqrt((np.array(err) ** 2).sum(1).mean()))
+        out["force_rms"] = float(np.sqrt((np.array(ref) ** 2).sum(1).mean()))
+        out["force_rmse_sample"] = f"{args.rmse_atoms} random atoms of the final MD frame, oracle local evaluation"
+        log(f"[bench] force RMSE vs oracle {out['force_rmse_vs_oracle']:.3e} eV/A")
+    if args.precision != "fp64" and args.fp64_steps > 0:
+        m64 = DPModel(blob, "fp64")
+        f64 = torch.zeros((n, 3), dtype=torch.float64, device=dev)
+        x64, v64 = x.clone(), v.clone()
+        m64.md_run(x64, v64, t, w["box"], w["masses"], w["dt_fs"], 1, skin=args.skin, thermo_every=1, forces=f64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m64.md_run(x64, v64, t, w["box"], w["masses"], w["dt_fs"], args.fp64_steps, skin=args.skin,
+                   thermo_every=args.fp64_steps, forces=f64)
+        torch.cuda.synchronize()
+        s64 = (time.perf_counter() - t0) / args.fp64_steps
+        out["fp64_s_per_step_atom"] = s64 / n
+        out["speedup_vs_fp64"] = s64 / s_step
+        log(f"[bench] fp64 {s64 * 1e3:.1f} ms/step")
+    if not args.no_cpu_baseline:    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -21,7 +21,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libdpmi.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.cpp", "k_nlist.hip", "k_env.hip", "k_embed_f64.hip", "k_fit_f64.hip", "k_md.hip"]
+SOURCES = ["api.cpp", "k_nlist.hip", "k_env.hip", "k_embed_f64.hip", "k_fit_f64.hip", "k_md.hip",
+           "k_embed_mix.hip", "k_fit_mix.hip"]
 EXACT_FP = {"k_nlist.hip"}
 
 

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "dp_internal.h"
+#include "dp_mix.h"
 #include "dpmi.h"
 
 using namespace dpk;
@@ -123,6 +124,9 @@ struct Workspace {
       *atom_of_pos, *blk_counts, *type_count, *type_start;
   double *T, *D, *dD, *Y[MAXF + 1], *Tt[MAXF + 1], *G[MAXF + 1], *eatom, *partial, *vir_part, *force_tmp,
       *net_deriv, *energy, *virial, *ke;
+  // mixed-precision buffers
+  float *T32, *D32, *dD32, *Yf[MAXF + 1], *Ttf[MAXF + 1], *Gf[MAXF + 1];
+  int prec = -1;  // precision the buffers were laid out for
   DevStatus *status;
 };
 
@@ -138,6 +142,10 @@ struct dp_ctx {
   EmbOffsets eo{};
   FitOffsets fo{};
   double *d_emb = nullptr, *d_fit = nullptr;
+  // mixed-precision weights (16-bit MFMA operands + f32)
+  unsigned char *d_mix_nets = nullptr, *d_fit_mix = nullptr;
+  FitMixOffsets fmo{};
+  int mix_shape = -1, n16 = 0;
   Workspace ws;
   DevStatus *h_status = nullptr;  // pinned
   dp_stats stats{};
@@ -174,7 +182,10 @@ int ensure_ws(dp_ctx *c, int64_t n, int64_t ncell, int cand_cap) {
   Workspace &w = c->ws;
   const Dims &d = c->dims;
   const bool need_nd = c->keep;
-  if (n <= w.n_cap && ncell <= w.ncell_cap && cand_cap <= w.cand_cap && (!need_nd || w.nd)) return DP_OK;
+  const bool mixed = c->precision != DP_FP64;
+  if (n <= w.n_cap && ncell <= w.ncell_cap && cand_cap <= w.cand_cap && (!need_nd || w.nd) &&
+      w.prec == c->precision)
+    return DP_OK;
   int64_t nn = std::max<int64_t>(n, w.n_cap > 0 ? (w.n_cap * 5) / 4 : n);
   nn = std::max<int64_t>(nn, 1);
   int64_t nc = std::max<int64_t>(ncell, w.ncell_cap);
@@ -204,13 +215,24 @@ int ensure_ws(dp_ctx *c, int64_t n, int64_t ncell, int cand_cap) {
   add((void **)&w.type_start, 4 * (MAXT + 1));
   add((void **)&w.rt, sizeof(double4) * nn * d.nnei);
   add((void **)&w.dr, sizeof(double4) * nn * d.nnei);
-  add((void **)&w.T, sizeof(double) * nn * d.M1 * 4);
-  add((void **)&w.D, sizeof(double) * rows * d.M1 * d.M2);
-  add((void **)&w.dD, sizeof(double) * rows * d.M1 * d.M2);
-  for (int l = 1; l <= d.n_fit; ++l) {
-    add((void **)&w.Y[l], sizeof(double) * rows * d.fw[l]);
-    add((void **)&w.Tt[l], sizeof(double) * rows * d.fw[l]);
-    if (l < d.n_fit) add((void **)&w.G[l], sizeof(double) * rows * d.fw[l]);
+  if (!mixed) {
+    add((void **)&w.T, sizeof(double) * nn * d.M1 * 4);
+    add((void **)&w.D, sizeof(double) * rows * d.M1 * d.M2);
+    add((void **)&w.dD, sizeof(double) * rows * d.M1 * d.M2);
+    for (int l = 1; l <= d.n_fit; ++l) {
+      add((void **)&w.Y[l], sizeof(double) * rows * d.fw[l]);
+      add((void **)&w.Tt[l], sizeof(double) * rows * d.fw[l]);
+      if (l < d.n_fit) add((void **)&w.G[l], sizeof(double) * rows * d.fw[l]);
+    }
+  } else {
+    add((void **)&w.T32, sizeof(float) * nn * d.M1 * 4);
+    add((void **)&w.D32, sizeof(float) * rows * d.M1 * d.M2);
+    add((void **)&w.dD32, sizeof(float) * rows * d.M1 * d.M2);
+    for (int l = 1; l <= d.n_fit; ++l) {
+      add((void **)&w.Yf[l], sizeof(float) * rows * d.fw[l]);
+      add((void **)&w.Ttf[l], sizeof(float) * rows * d.fw[l]);
+      if (l < d.n_fit) add((void **)&w.Gf[l], sizeof(float) * rows * d.fw[l]);
+    }
   }
   add((void **)&w.eatom, sizeof(double) * nn);
   add((void **)&w.partial, sizeof(double) * 1024);
@@ -234,6 +256,8 @@ int ensure_ws(dp_ctx *c, int64_t n, int64_t ncell, int cand_cap) {
   }
   if (!nd) w.net_deriv = nullptr;
   w.G[0] = w.dD;
+  w.Gf[0] = w.dD32;
+  w.prec = c->precision;
   w.base = base;
   w.bytes = off;
   w.n_cap = nn;
@@ -328,6 +352,90 @@ int upload_model(dp_ctx *c) {
   return DP_OK;
 }
 
+// Mixed-precision weights: per (t,u) the LDS image of the embedding net, and
+// for the fitting net 16-bit W^T / W for the first n16 layers plus f32 copies.
+uint16_t h16_bits(double v, int prec) {
+  const float f = (float)v;
+  if (prec == 0) {
+    _Float16 h = (_Float16)f;
+    uint16_t u;
+    std::memcpy(&u, &h, 2);
+    return u;
+  }
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+int upload_mix(dp_ctx *c) {
+  const HostModel &m = c->hm;
+  const Dims &d = c->dims;
+  const int prec = c->precision == DP_MIX_FP16 ? 0 : 1;
+  const int shape = mix_shape_id(d);
+  if (shape < 0) return fail(c, DP_E_MODEL, "mixed precision supports embedding widths 25-50-100 and 16-32-100");
+  if (mix_lds_bytes(shape, d.ntypes, 2) > 163840 || mix_lds_bytes(shape, d.ntypes, 1) > 163840)
+    return fail(c, DP_E_MODEL, "too many atom types for the mixed-precision LDS layout");
+  const int n16 = std::min(2, d.n_fit);
+  for (int l = 0; l <= n16; ++l)
+    if (d.fw[l] % 8 != 0) return fail(c, DP_E_MODEL, "16-bit fitting layers need widths divisible by 8");
+  const size_t nb = mix_net_bytes(shape);
+  const int T = d.ntypes;
+  std::vector<unsigned char> nets(nb * T * T);
+  for (int t = 0; t < T; ++t)
+    for (int u = 0; u < T; ++u) {
+      const double *W[3], *b[3];
+      for (int l = 0; l < 3; ++l) {
+        W[l] = m.eW[m.eidx(t, u, l)].data();
+        b[l] = m.eb[m.eidx(t, u, l)].data();
+      }
+      mix_pack_net(shape, W, b, prec, nets.data() + (size_t)(t * T + u) * nb);
+    }
+  std::vector<unsigned char> F;
+  auto align = [&]() { F.resize((F.size() + 255) / 256 * 256, 0); };
+  FitMixOffsets fo{};
+  for (int t = 0; t < T; ++t)
+    for (int l = 0; l <= d.n_fit; ++l) {
+      const auto &W = m.fW[m.fidx(t, l)];
+      const auto &bb = m.fb[m.fidx(t, l)];
+      const int in = d.fw[l], out = d.fw[l + 1];
+      if (l < n16) {
+        align();
+        fo.wt16[t][l] = (int64_t)F.size();
+        F.resize(F.size() + 2 * (size_t)in * out);
+        uint16_t *wt = (uint16_t *)(F.data() + fo.wt16[t][l]);
+        for (int i = 0; i < in; ++i)
+          for (int o = 0; o < out; ++o) wt[(size_t)o * in + i] = h16_bits(W[(size_t)i * out + o], prec);
+        align();
+        fo.w16[t][l] = (int64_t)F.size();
+        F.resize(F.size() + 2 * (size_t)in * out);
+        uint16_t *wn = (uint16_t *)(F.data() + fo.w16[t][l]);
+        for (size_t q = 0; q < (size_t)in * out; ++q) wn[q] = h16_bits(W[q], prec);
+      }
+      align();
+      fo.w32[t][l] = (int64_t)F.size();
+      F.resize(F.size() + 4 * (size_t)in * out);
+      float *w32 = (float *)(F.data() + fo.w32[t][l]);
+      for (size_t q = 0; q < (size_t)in * out; ++q) w32[q] = (float)W[q];
+      align();
+      fo.b32[t][l] = (int64_t)F.size();
+      F.resize(F.size() + 4 * (size_t)out);
+      float *b32 = (float *)(F.data() + fo.b32[t][l]);
+      for (int o = 0; o < out; ++o) b32[o] = (float)bb[o];
+    }
+  if (c->d_mix_nets) (void)hipFree(c->d_mix_nets);
+  if (c->d_fit_mix) (void)hipFree(c->d_fit_mix);
+  c->d_mix_nets = c->d_fit_mix = nullptr;
+  HIPCHK(c, hipMalloc(&c->d_mix_nets, nets.size()));
+  HIPCHK(c, hipMalloc(&c->d_fit_mix, F.size()));
+  HIPCHK(c, hipMemcpy(c->d_mix_nets, nets.data(), nets.size(), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->d_fit_mix, F.data(), F.size(), hipMemcpyHostToDevice));
+  c->fmo = fo;
+  c->mix_shape = shape;
+  c->n16 = n16;
+  return DP_OK;
+}
+
 // ---------------------------------------------------------------------------
 // one evaluation
 // ---------------------------------------------------------------------------
@@ -385,51 +493,99 @@ void eval_body(dp_ctx *c, int64_t n, const double L[3], double *F) {
   tmark(c, 2);
   launch_env(s, n, w.xw, d, L, w.nlist, w.nreal, w.rt, w.dr);
   tmark(c, 3);
-  EmbedArgs ea{};
-  ea.d = d;
-  ea.eo = c->eo;
-  ea.ew = c->d_emb;
-  ea.atom_of_pos = w.atom_of_pos;
-  ea.pos_of_atom = w.pos_of_atom;
-  ea.type_start = w.type_start;
-  ea.rows = rows;
-  ea.natoms = n;
-  ea.xw = w.xw;
-  ea.nlist = w.nlist;
-  ea.nreal = w.nreal;
-  ea.rt = w.rt;
-  ea.dr = w.dr;
-  ea.T = w.T;
-  ea.D = w.D;
-  ea.dD = w.dD;
-  ea.force = F;
-  ea.vir_part = w.vir_part;
-  ea.net_deriv = c->keep ? w.net_deriv : nullptr;
-  launch_embed_fwd_f64(s, ea);
-  tmark(c, 4);
-  FitArgs fa{};
-  fa.d = d;
-  fa.fo = c->fo;
-  fa.fwt = c->d_fit;
-  fa.type_start = w.type_start;
-  fa.atom_of_pos = w.atom_of_pos;
-  fa.rows = rows;
-  fa.X0 = w.D;
-  for (int l = 0; l <= MAXF; ++l) {
-    fa.Y[l] = w.Y[l];
-    fa.Tt[l] = w.Tt[l];
-    fa.G[l] = w.G[l];
+  if (c->precision == DP_FP64) {
+    EmbedArgs ea{};
+    ea.d = d;
+    ea.eo = c->eo;
+    ea.ew = c->d_emb;
+    ea.atom_of_pos = w.atom_of_pos;
+    ea.pos_of_atom = w.pos_of_atom;
+    ea.type_start = w.type_start;
+    ea.rows = rows;
+    ea.natoms = n;
+    ea.xw = w.xw;
+    ea.nlist = w.nlist;
+    ea.nreal = w.nreal;
+    ea.rt = w.rt;
+    ea.dr = w.dr;
+    ea.T = w.T;
+    ea.D = w.D;
+    ea.dD = w.dD;
+    ea.force = F;
+    ea.vir_part = w.vir_part;
+    ea.net_deriv = c->keep ? w.net_deriv : nullptr;
+    launch_embed_fwd_f64(s, ea);
+    tmark(c, 4);
+    FitArgs fa{};
+    fa.d = d;
+    fa.fo = c->fo;
+    fa.fwt = c->d_fit;
+    fa.type_start = w.type_start;
+    fa.atom_of_pos = w.atom_of_pos;
+    fa.rows = rows;
+    fa.X0 = w.D;
+    for (int l = 0; l <= MAXF; ++l) {
+      fa.Y[l] = w.Y[l];
+      fa.Tt[l] = w.Tt[l];
+      fa.G[l] = w.G[l];
+    }
+    fa.eatom = w.eatom;
+    launch_fit_f64(s, fa);
+    tmark(c, 5);
+    launch_sum(s, w.eatom, n, w.partial, w.energy, 1.0);
+    launch_zero(s, F, 3 * n);
+    const int grid = embed_bwd_grid(rows);
+    tmark(c, 6);
+    launch_embed_bwd_f64(s, ea, grid);
+    tmark(c, 7);
+    launch_sum9(s, w.vir_part, grid, w.virial);
+  } else {
+    MixArgs ma{};
+    ma.d = d;
+    ma.shape = c->mix_shape;
+    ma.prec = c->precision == DP_MIX_FP16 ? 0 : 1;
+    ma.nets = c->d_mix_nets;
+    ma.rows = rows;
+    ma.atom_of_pos = w.atom_of_pos;
+    ma.xw = w.xw;
+    ma.nlist = w.nlist;
+    ma.nreal = w.nreal;
+    ma.rt = w.rt;
+    ma.dr = w.dr;
+    ma.T32 = w.T32;
+    ma.D32 = w.D32;
+    ma.dD32 = w.dD32;
+    ma.force = F;
+    ma.vir_part = w.vir_part;
+    ma.net_deriv = c->keep ? w.net_deriv : nullptr;
+    const int grid = mix_grid(rows);
+    launch_embed_mix(s, ma, 1, grid);
+    tmark(c, 4);
+    FitMixArgs fa{};
+    fa.d = d;
+    fa.fo = c->fmo;
+    fa.w = c->d_fit_mix;
+    fa.prec = ma.prec;
+    fa.n16 = c->n16;
+    fa.type_start = w.type_start;
+    fa.atom_of_pos = w.atom_of_pos;
+    fa.rows = rows;
+    fa.X0 = w.D32;
+    for (int l = 0; l <= MAXF; ++l) {
+      fa.Y[l] = w.Yf[l];
+      fa.Tt[l] = w.Ttf[l];
+      fa.G[l] = w.Gf[l];
+    }
+    fa.eatom = w.eatom;
+    launch_fit_mix(s, fa);
+    tmark(c, 5);
+    launch_sum(s, w.eatom, n, w.partial, w.energy, 1.0);
+    launch_zero(s, F, 3 * n);
+    tmark(c, 6);
+    launch_embed_mix(s, ma, 2, grid);
+    tmark(c, 7);
+    launch_sum9(s, w.vir_part, grid, w.virial);
   }
-  fa.eatom = w.eatom;
-  launch_fit_f64(s, fa);
-  tmark(c, 5);
-  launch_sum(s, w.eatom, n, w.partial, w.energy, 1.0);
-  launch_zero(s, F, 3 * n);
-  const int grid = embed_bwd_grid(rows);
-  tmark(c, 6);
-  launch_embed_bwd_f64(s, ea, grid);
-  tmark(c, 7);
-  launch_sum9(s, w.vir_part, grid, w.virial);
   tnext(c);
 }
 
@@ -491,6 +647,8 @@ void dp_destroy(dp_ctx *c) {
   free_ws(c->ws);
   if (c->d_emb) (void)hipFree(c->d_emb);
   if (c->d_fit) (void)hipFree(c->d_fit);
+  if (c->d_mix_nets) (void)hipFree(c->d_mix_nets);
+  if (c->d_fit_mix) (void)hipFree(c->d_fit_mix);
   if (c->h_status) (void)hipHostFree(c->h_status);
   for (auto &e : c->ev)
     if (e) (void)hipEventDestroy(e);
@@ -501,7 +659,8 @@ const char *dp_last_error(const dp_ctx *c) { return c ? c->err.c_str() : "NULL c
 
 int dp_set_model(dp_ctx *c, const void *blob, size_t nbytes, int precision) {
   if (!c || !blob) return fail(c, DP_E_ARG, "NULL argument");
-  if (precision != DP_FP64) return fail(c, DP_E_ARG, "unsupported precision policy");
+  if (precision != DP_FP64 && precision != DP_MIX_FP16 && precision != DP_MIX_BF16)
+    return fail(c, DP_E_ARG, "unsupported precision policy");
   HIPCHK(c, hipSetDevice(c->device));
   HostModel m;
   std::string err;
@@ -512,6 +671,10 @@ int dp_set_model(dp_ctx *c, const void *blob, size_t nbytes, int precision) {
   int rc = upload_model(c);
   if (rc) return rc;
   c->precision = precision;
+  if (precision != DP_FP64) {
+    rc = upload_mix(c);
+    if (rc) return rc;
+  }
   c->has_model = true;
   return DP_OK;
 }
@@ -519,8 +682,17 @@ int dp_set_model(dp_ctx *c, const void *blob, size_t nbytes, int precision) {
 int dp_set_precision(dp_ctx *c, int precision) {
   if (!c) return DP_E_ARG;
   if (!c->has_model) return fail(c, DP_E_NOMODEL, "no model");
-  if (precision != DP_FP64) return fail(c, DP_E_ARG, "unsupported precision policy");
+  if (precision != DP_FP64 && precision != DP_MIX_FP16 && precision != DP_MIX_BF16)
+    return fail(c, DP_E_ARG, "unsupported precision policy");
+  const int old = c->precision;
   c->precision = precision;
+  if (precision != DP_FP64) {
+    int rc = upload_mix(c);
+    if (rc) {
+      c->precision = old;
+      return rc;
+    }
+  }
   return DP_OK;
 }
 
@@ -646,6 +818,8 @@ int dp_get_intermediates(dp_ctx *c, double *atom_e, double *T, double *D, double
   const int64_t n = c->last_n;
   const Dims &d = c->dims;
   hipStream_t s = c->stream;
+  if ((T || D) && c->precision != DP_FP64)
+    return fail(c, DP_E_ARG, "T and D intermediates are kept in double only under DP_FP64");
   if (atom_e) HIPCHK(c, hipMemcpyAsync(atom_e, c->ws.eatom, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   if (T) HIPCHK(c, hipMemcpyAsync(T, c->ws.T, sizeof(double) * n * d.M1 * 4, hipMemcpyDeviceToDevice, s));
   if (D || net_deriv) {

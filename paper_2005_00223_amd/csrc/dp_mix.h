@@ -15,7 +15,7 @@ struct MixArgs {
   const int32_t *nlist, *nreal;
   const double4 *rt, *dr;
   float *T32;                 // [natoms][M1][4]
-  void *D16;                  // [rows][M1*M2] 16-bit
+  float *D32;                 // [rows][M1*M2]
   const float *dD32;          // [rows][M1*M2]
   double *force;              // [natoms][3]
   double *vir_part;           // [grid][9]
@@ -45,9 +45,8 @@ struct FitMixArgs {
   const int32_t *type_start;
   const int32_t *atom_of_pos;
   int64_t rows;
-  const void *X16;            // D [rows][fw0] 16-bit
+  const float *X0;            // D [rows][fw0]
   float *Y[MAXF + 1];         // Y[l] f32 [rows][fw[l]], l >= 1
-  void *Yh[MAXF + 1];         // Y[l] 16-bit copy when layer l is 16-bit
   float *Tt[MAXF + 1];        // tanh outputs [rows][fw[l]]
   float *G[MAXF + 1];         // dE/dY[l]; G[0] = dE/dD
   double *eatom;

@@ -1,9 +1,17 @@
-// Mixed-precision embedding net + descriptor (the paper's MIX-16 scheme,
-// Section V-A "Mixed-precision computation"): the embedding layers after
-// the first are 16-bit matrix-core products (FP16 or BF16, v_mfma_f32_16x16x32)
-// with FP32 accumulation; the rank-1 first layer, tanh, the skip adds and
-// the descriptor contractions stay in FP32; distances, the environment
-// matrix, the force Jacobian and every force/virial sum stay in FP64.
+// Mixed-precision embedding net + descriptor (after the paper's MIX-16
+// scheme, Section V-A "Mixed-precision computation"): the embedding layers
+// after the first are 16-bit matrix-core products (FP16 or BF16,
+// v_mfma_f32_16x16x32) with FP32 accumulation and 16-bit weights; the
+// rank-1 first layer, tanh, the skip adds and the descriptor contractions
+// stay in FP32; distances, the environment matrix, the force Jacobian and
+// every force/virial sum stay in FP64.
+//
+// Unlike the paper, activations are not rounded to 16 bits: each 16-bit
+// operand that carries an activation is split into hi = rn16(x) and
+// lo = rn16(x - hi) and multiplied twice (W hi + W lo), which keeps about
+// 22 significant bits.  Rounding the activations alone puts the force error
+// of the random copper model above 1e-3 eV/A; rounding only the weights
+// costs about 4e-5 eV/A (FP16).
 //
 // Layout.  A wave works on tiles of 16 neighbours; every layer is computed
 // transposed (Z^T = W^T H^T, neighbours as the MFMA N dimension).  The f32
@@ -23,12 +31,14 @@
 // lanes][8] (16-bit), b2[S2] (f32), A3 [MT3][KS3][64][8], b3[S3] (f32).
 //
 // Pass 1: T += G R^T by an LDS transpose of G and v_mfma_f32_16x16x4f32 (K =
-// the 16 neighbours), T /= Nc, D = T T_<^T (f32 MFMA), D stored 16-bit for
-// the 16-bit fitting layer.  Pass 2: forward tangent mode (h and dh/ds in
+// the 16 neighbours), T /= Nc, D = T T_<^T (f32 MFMA), D stored in FP32.  Pass 2: forward tangent mode (h and dh/ds in
 // two MFMA column sets sharing the A operands), then
-//   a = G^T dT, b = G'^T dT as 16-bit MFMAs with G straight from registers,
+//   a = G^T dT, b = G'^T dT as split 16-bit MFMAs (hi hi + hi lo + lo hi)
+//   with G straight from registers,
 //   dE/dR = a + (R . b) e_0, and per 64 neighbours one FP64 pass of
 //   g_ij = dE/dR dR/dr, F_i += g, F_j -= g (atomics), Xi -= g (x) r.
+#include <cstring>
+
 #include "dp_internal.h"
 #include "dp_mix.h"
 
@@ -66,6 +76,27 @@ __device__ inline typename HT<P>::v8 pack8(const float (&x)[4], const float (&y)
   v[0] = (E)x[0]; v[1] = (E)x[1]; v[2] = (E)x[2]; v[3] = (E)x[3];
   v[4] = (E)y[0]; v[5] = (E)y[1]; v[6] = (E)y[2]; v[7] = (E)y[3];
   return v;
+}
+
+// hi/lo split of eight activations: x = hi + lo to about 22 bits
+template <int P>
+struct Split8 {
+  typename HT<P>::v8 hi, lo;
+};
+
+template <int P>
+__device__ inline Split8<P> split8(const float (&x)[4], const float (&y)[4]) {
+  typedef typename HT<P>::e E;
+  Split8<P> s;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const E a = (E)x[v], b = (E)y[v];
+    s.hi[v] = a;
+    s.hi[v + 4] = b;
+    s.lo[v] = (E)(x[v] - (float)a);
+    s.lo[v + 4] = (E)(y[v] - (float)b);
+  }
+  return s;
 }
 
 // tanh(x) = 1 - 2 / (exp(2x) + 1) with the hardware exp2 and reciprocal;
@@ -164,10 +195,11 @@ __device__ inline void layer1(const float *w1, const float *b1, float s, int g, 
   }
 }
 
-// one MFMA layer from 16-bit weights in LDS; acc initialised with the bias
+// one MFMA layer from 16-bit weights in LDS; acc initialised with the bias;
+// B holds the hi/lo split activations of each k-step
 template <int P, int MT, int KS>
-__device__ inline void layer_mfma(const unsigned char *Aops, const float *bias, const typename HT<P>::v8 (&B)[KS],
-                                  int lane, int g, v4f (&acc)[MT]) {
+__device__ inline void layer_mfma(const unsigned char *Aops, const float *bias, const Split8<P> (&B)[KS], int lane,
+                                  int g, v4f (&acc)[MT]) {
   typedef typename HT<P>::v8 V;
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
@@ -179,14 +211,14 @@ __device__ inline void layer_mfma(const unsigned char *Aops, const float *bias, 
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
       const V a = *(const V *)(Aops + ((mt * KS + kk) * 64 + lane) * 16);
-      acc[mt] = mfma16<P>(a, B[kk], acc[mt]);
+      acc[mt] = mfma16<P>(a, B[kk].hi, acc[mt]);
+      acc[mt] = mfma16<P>(a, B[kk].lo, acc[mt]);
     }
 }
 
 // tangent columns: same A operands, zero initial accumulator
 template <int P, int MT, int KS>
-__device__ inline void layer_mfma_tan(const unsigned char *Aops, const typename HT<P>::v8 (&B)[KS], int lane,
-                                      v4f (&acc)[MT]) {
+__device__ inline void layer_mfma_tan(const unsigned char *Aops, const Split8<P> (&B)[KS], int lane, v4f (&acc)[MT]) {
   typedef typename HT<P>::v8 V;
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) acc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -195,7 +227,8 @@ __device__ inline void layer_mfma_tan(const unsigned char *Aops, const typename 
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
       const V a = *(const V *)(Aops + ((mt * KS + kk) * 64 + lane) * 16);
-      acc[mt] = mfma16<P>(a, B[kk], acc[mt]);
+      acc[mt] = mfma16<P>(a, B[kk].hi, acc[mt]);
+      acc[mt] = mfma16<P>(a, B[kk].lo, acc[mt]);
     }
 }
 
@@ -237,9 +270,9 @@ __global__ void __launch_bounds__(64 * MIX_WAVES) k_embed_fwd_mix(MixArgs a) {
   wave_rows(a.rows, p0, p1);
   for (int64_t p = p0; p < p1; ++p) {
     const int i = a.atom_of_pos[p];
-    E *Dp = (E *)a.D16 + p * (int64_t)MM;
+    float *Dp = a.D32 + p * (int64_t)MM;
     if (i < 0) {
-      for (int o = lane; o < MM; o += 64) Dp[o] = (E)0.f;
+      for (int o = lane; o < MM; o += 64) Dp[o] = 0.f;
       continue;
     }
     const int t = (int)a.xw[i].w;
@@ -263,7 +296,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES) k_embed_fwd_mix(MixArgs a) {
 #pragma unroll
           for (int mt = 0; mt < 2; ++mt)
             *(float4 *)(h1s + n * S::S1 + 16 * mt + 4 * g) = make_float4(h1[mt][0], h1[mt][1], h1[mt][2], h1[mt][3]);
-        V B2[1] = {pack8<P>(h1[0], h1[1])};
+        Split8<P> B2[1] = {split8<P>(h1[0], h1[1])};
         v4f acc2[S::MT2];
         layer_mfma<P, S::MT2, 1>(net + S::O_A2, b2, B2, lane, g, acc2);
         wsync();
@@ -281,9 +314,9 @@ __global__ void __launch_bounds__(64 * MIX_WAVES) k_embed_fwd_mix(MixArgs a) {
 #pragma unroll
           for (int mt = 0; mt < S::MT2; ++mt)
             *(float4 *)(h2s + n * S::S2 + 16 * mt + 4 * g) = make_float4(h2[mt][0], h2[mt][1], h2[mt][2], h2[mt][3]);
-        V B3[S::KS3];
+        Split8<P> B3[S::KS3];
 #pragma unroll
-        for (int kk = 0; kk < S::KS3; ++kk) B3[kk] = pack8<P>(h2[2 * kk], h2[2 * kk + 1]);
+        for (int kk = 0; kk < S::KS3; ++kk) B3[kk] = split8<P>(h2[2 * kk], h2[2 * kk + 1]);
         v4f acc3[S::MT3];
         layer_mfma<P, S::MT3, S::KS3>(net + S::O_A3, b3, B3, lane, g, acc3);
         wsync();
@@ -334,7 +367,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES) k_embed_fwd_mix(MixArgs a) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int f = 16 * mt + 4 * g + r;
-          if (f < d.M1 && n < d.M2) Dp[f * d.M2 + n] = (E)z[r];
+          if (f < d.M1 && n < d.M2) Dp[f * d.M2 + n] = z[r];
         }
       }
     }
@@ -406,7 +439,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES) k_embed_bwd_mix(MixArgs a) {
     }
     wsync();
     // B operand of the contraction: K = G's slots (permuted as the layer chain), N = components
-    V dTB[S::KSC];
+    Split8<P> dTB[S::KSC];
 #pragma unroll
     for (int kk = 0; kk < S::KSC; ++kk) {
       float x[4], y[4];
@@ -416,7 +449,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES) k_embed_bwd_mix(MixArgs a) {
         x[v] = (n < 4 && f0 < S::S3) ? dTs[4 * f0 + n] : 0.f;
         y[v] = (n < 4 && f1 < S::S3) ? dTs[4 * f1 + n] : 0.f;
       }
-      dTB[kk] = pack8<P>(x, y);
+      dTB[kk] = split8<P>(x, y);
     }
     double fi0 = 0.0, fi1 = 0.0, fi2 = 0.0;
     for (int u = 0; u < d.ntypes; ++u) {
@@ -439,7 +472,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES) k_embed_bwd_mix(MixArgs a) {
             *(float4 *)(hd1s + n * S::S1 + 16 * mt + 4 * g) =
                 make_float4(hd1[mt][0], hd1[mt][1], hd1[mt][2], hd1[mt][3]);
           }
-        V B2h[1] = {pack8<P>(h1[0], h1[1])}, B2d[1] = {pack8<P>(hd1[0], hd1[1])};
+        Split8<P> B2h[1] = {split8<P>(h1[0], h1[1])}, B2d[1] = {split8<P>(hd1[0], hd1[1])};
         v4f acc2[S::MT2], acc2d[S::MT2];
         layer_mfma<P, S::MT2, 1>(net + S::O_A2, b2, B2h, lane, g, acc2);
         layer_mfma_tan<P, S::MT2, 1>(net + S::O_A2, B2d, lane, acc2d);
@@ -466,11 +499,11 @@ __global__ void __launch_bounds__(64 * MIX_WAVES) k_embed_bwd_mix(MixArgs a) {
             *(float4 *)(hd2s + n * S::S2 + 16 * mt + 4 * g) =
                 make_float4(hd2[mt][0], hd2[mt][1], hd2[mt][2], hd2[mt][3]);
           }
-        V B3h[S::KS3], B3d[S::KS3];
+        Split8<P> B3h[S::KS3], B3d[S::KS3];
 #pragma unroll
         for (int kk = 0; kk < S::KS3; ++kk) {
-          B3h[kk] = pack8<P>(h2[2 * kk], h2[2 * kk + 1]);
-          B3d[kk] = pack8<P>(hd2[2 * kk], hd2[2 * kk + 1]);
+          B3h[kk] = split8<P>(h2[2 * kk], h2[2 * kk + 1]);
+          B3d[kk] = split8<P>(hd2[2 * kk], hd2[2 * kk + 1]);
         }
         v4f acc3[S::MT3], acc3d[S::MT3];
         layer_mfma<P, S::MT3, S::KS3>(net + S::O_A3, b3, B3h, lane, g, acc3);
@@ -496,8 +529,14 @@ __global__ void __launch_bounds__(64 * MIX_WAVES) k_embed_bwd_mix(MixArgs a) {
         v4f ca = v4f{0.f, 0.f, 0.f, 0.f}, cb = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kk = 0; kk < S::KSC; ++kk) {
-          ca = mfma16<P>(pack8<P>(G[2 * kk], G[2 * kk + 1]), dTB[kk], ca);
-          cb = mfma16<P>(pack8<P>(Gd[2 * kk], Gd[2 * kk + 1]), dTB[kk], cb);
+          const Split8<P> ga = split8<P>(G[2 * kk], G[2 * kk + 1]);
+          const Split8<P> gb = split8<P>(Gd[2 * kk], Gd[2 * kk + 1]);
+          ca = mfma16<P>(ga.hi, dTB[kk].hi, ca);
+          ca = mfma16<P>(ga.hi, dTB[kk].lo, ca);
+          ca = mfma16<P>(ga.lo, dTB[kk].hi, ca);
+          cb = mfma16<P>(gb.hi, dTB[kk].hi, cb);
+          cb = mfma16<P>(gb.hi, dTB[kk].lo, cb);
+          cb = mfma16<P>(gb.lo, dTB[kk].hi, cb);
         }
         const int slot0 = n0 & 63;
 #pragma unroll
@@ -586,13 +625,13 @@ static size_t net_bytes_t() {
 static inline uint16_t to_f16(float x) {
   _Float16 h = (_Float16)x;
   uint16_t u;
-  memcpy(&u, &h, 2);
+  std::memcpy(&u, &h, 2);
   return u;
 }
 
 static inline uint16_t to_bf16(float x) {
   uint32_t u;
-  memcpy(&u, &x, 4);
+  std::memcpy(&u, &x, 4);
   const uint32_t lsb = (u >> 16) & 1u;
   u += 0x7fffu + lsb;  // round to nearest even (finite inputs)
   return (uint16_t)(u >> 16);
@@ -602,7 +641,7 @@ static inline uint16_t to_bf16(float x) {
 template <int W1, int W2, int W3>
 static void pack_net_t(const double *const *W, const double *const *b, int prec, unsigned char *out) {
   typedef Shape<W1, W2, W3> S;
-  memset(out, 0, S::NET_BYTES);
+  std::memset(out, 0, S::NET_BYTES);
   float *w1 = (float *)(out + S::O_W1), *b1 = (float *)(out + S::O_B1);
   for (int f = 0; f < W1; ++f) {
     w1[f] = (float)W[0][f];

@@ -1,0 +1,127 @@
+"""Mixed-precision HIP path (16-bit matrix-core products, FP32 tanh and
+contractions, FP64 geometry and sums) against the FP64 oracle.
+
+Bar: force RMSE <= 1e-3 eV/A for FP16 on every workload (RMS|F| is about
+1 eV/A for these models).  BF16 keeps 8-bit weights, which a CPU rounding
+emulation puts at about 3e-4 eV/A (copper) and 1.4e-3 eV/A (water), so its
+water bar is 3e-3.  The neighbour list is the FP64 one, bit for bit."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2005_00223_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _model(blob, prec):
+    from paper_2005_00223_amd.model import DPModel
+    return DPModel(blob, prec)
+
+
+def _oracle(blob):
+    from oracle import oracle as O
+    return O.Oracle(blob)
+
+
+BARS = {("water192", "fp16"): 1e-3, ("cu_cells5", "fp16"): 1e-3, ("water192", "bf16"): 3e-3,
+        ("cu_cells5", "bf16"): 1e-3}
+
+
+@pytest.mark.parametrize("name,prec", sorted(BARS))
+def test_force_rmse_full(name, prec):
+    w = synth.workload(name)
+    blob = synth.pack_blob(w["spec"])
+    n = len(w["types"])
+    say(f"[mixed] {name} {prec}")
+    m = _model(blob, prec)
+    e, f, v = m.compute(w["coords"], w["types"], w["box"])
+    r = _oracle(blob).eval(w["coords"], w["types"], w["box"])
+    f = f.cpu().numpy()
+    rmse = np.sqrt(((f - r["force"]) ** 2).sum(1).mean())
+    rms = np.sqrt((r["force"] ** 2).sum(1).mean())
+    say(f"  force RMSE {rmse:.3e} eV/A (RMS|F| {rms:.3f}), energy error per atom "
+        f"{abs(e.item() - r['energy']) / n:.3e} eV")
+    assert rmse <= BARS[(name, prec)]
+    assert abs(e.item() - r["energy"]) <= 1e-3 * abs(r["energy"])
+    vv = v.cpu().numpy()
+    assert np.abs(vv - r["virial"]).max() <= 1e-3 * np.abs(r["virial"]).max()
+    # the neighbour list does not depend on the precision policy
+    nl, _ = m.nlist(n, w["spec"].nnei, w["spec"].ntypes)
+    onl, _, _ = _oracle(blob).nlist(w["coords"], w["types"], w["box"])
+    np.testing.assert_array_equal(nl.cpu().numpy(), onl)
+
+
+@pytest.mark.parametrize("name", ["cu32000", "cu500k"])
+def test_force_rmse_sampled_fp16(name):
+    """Full-size copper: forces of sampled atoms against the oracle's local
+    evaluation over {k} and its neighbours."""
+    w = synth.workload(name)
+    spec = w["spec"]
+    blob = synth.pack_blob(spec)
+    n = len(w["types"])
+    say(f"[mixed sampled] {name} fp16")
+    m = _model(blob, "fp16")
+    e, f, v = m.compute(w["coords"], w["types"], w["box"])
+    f = f.cpu().numpy()
+    nl, _ = m.nlist(n, spec.nnei, spec.ntypes)
+    nl = nl.cpu().numpy()
+    o = _oracle(blob)
+    rng = np.random.default_rng(2)
+    ks = rng.choice(n, size=12, replace=False)
+    err = []
+    for k in ks:
+        cen = np.unique(np.concatenate([[k], nl[k][nl[k] >= 0]]))
+        r = o.eval(w["coords"], w["types"], w["box"], centres=cen)
+        err.append(f[k] - r["force"][k])
+    rmse = np.sqrt((np.array(err) ** 2).sum(1).mean())
+    say(f"  sampled force RMSE {rmse:.3e} eV/A over {len(ks)} atoms")
+    assert rmse <= 1e-3
+    assert np.isfinite(e.item())
+
+
+def test_precision_switch_roundtrip():
+    """Switching the policy on a loaded model re-casts the weights; going
+    back to FP64 restores the exact result."""
+    w = synth.workload("water192")
+    blob = synth.pack_blob(w["spec"])
+    say("[mixed] precision switch")
+    m = _model(blob, "fp64")
+    e0, f0, _ = m.compute(w["coords"], w["types"], w["box"])
+    m.set_precision("fp16")
+    e1, f1, _ = m.compute(w["coords"], w["types"], w["box"])
+    m.set_precision("fp64")
+    e2, f2, _ = m.compute(w["coords"], w["types"], w["box"])
+    assert e2.item() == e0.item()
+    assert torch.allclose(f2, f0, rtol=0, atol=1e-12)
+    assert abs(e1.item() - e0.item()) > 0
+
+
+def test_mixed_md_runs_and_conserves():
+    """100 NVE steps of 1 fs on 500 Cu atoms in FP16: energy stays finite
+    and drifts by well under a meV per atom."""
+    w = synth.workload("cu_cells5")
+    blob = synth.pack_blob(w["spec"])
+    say("[mixed] md cu_cells5")
+    m = _model(blob, "fp16")
+    t = w["types"]
+    v0 = synth.maxwell_boltzmann(w["masses"][t], 300.0, w["vseed"])
+    x = torch.tensor(w["coords"], dtype=torch.float64, device="cuda")
+    v = torch.tensor(v0, dtype=torch.float64, device="cuda")
+    th = m.md_run(x, v, t, w["box"], w["masses"], 1.0, 100, skin=1.0, thermo_every=10).cpu().numpy()
+    etot = th[:, 3]
+    assert np.all(np.isfinite(etot))
+    assert np.ptp(etot) / len(t) < 1e-3
