@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--skin", type=float, default=2.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (traffic-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -101,6 +103,14 @@ def main():
     from paper_2005_00223_amd import synth
     from paper_2005_00223_amd.model import DPModel
 
+    if args.copy_probe_mb > 0:
+        src = torch.empty(args.copy_probe_mb << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: 3 copies of {args.copy_probe_mb} MiB")
+        del src, dst
     w = synth.workload(args.workload)
     spec = w["spec"]
     blob = synth.pack_blob(spec)

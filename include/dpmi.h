@@ -51,16 +51,18 @@ enum {
                           per-atom sort buffer (1024) holds                 */
 };
 
-/* Precision policies (Section V-A "Mixed-precision computation").
+/* Precision policies (after the paper's MIX-16 scheme, Section V-A
+ * "Mixed-precision computation").
  * DP_FP64: everything in double.
- * DP_MIX_FP32: embedding and fitting nets in float (MIX-32).
  * DP_MIX_FP16 / DP_MIX_BF16: embedding layers after the first and the first
- *   two fitting layers as 16-bit matrix-core products with float
- *   accumulation; tanh, the descriptor contraction, the last hidden fitting
- *   layer and the output layer in float (MIX-16).
- * Coordinates, wrapping, distances, the environment matrix, energy and
- * virial reductions, forces and the integrator stay double in every mode. */
-enum { DP_FP64 = 0, DP_MIX_FP32 = 1, DP_MIX_FP16 = 2, DP_MIX_BF16 = 3 };
+ *   two fitting layers as 16-bit matrix-core products with FP32
+ *   accumulation and 16-bit weights; activations enter those products as
+ *   hi + lo 16-bit pairs (about 22 bits); tanh, the descriptor contractions,
+ *   the remaining fitting layers and the output layer in FP32.
+ * Coordinates, wrapping, distances, the environment matrix, the force
+ * Jacobian, energy / force / virial sums and the integrator stay double in
+ * every mode.  (Value 1 is reserved.) */
+enum { DP_FP64 = 0, DP_MIX_FP16 = 2, DP_MIX_BF16 = 3 };
 
 typedef struct {
   int64_t natoms;            /* atoms in the last dp_compute                 */
@@ -104,6 +106,21 @@ int dp_set_precision(dp_ctx *c, int precision);
  * index, nearest sel kept per type, -1 padded). */
 int dp_compute(dp_ctx *c, int64_t natoms, const double *coords, const int32_t *types, const double *box,
                double *energy, double *forces, double *virial);
+
+/* The two halves of dp_compute, for reverse-mode frameworks
+ * (torch.autograd.Function): dp_energy runs the forward half only (list,
+ * environment matrix, embedding + descriptor, fitting net, energy) and keeps
+ * its intermediates; dp_energy_backward then runs the adjoint (fitting-net
+ * backward, embedding backward with the force and virial scatter, the
+ * paper's ProdForce / ProdVirial) for the same configuration and writes
+ *   forces = -grad_energy * dE/dr   (device [natoms][3], may be NULL)
+ *   virial = grad_energy * Xi       (device [9], may be NULL).
+ * dp_energy_backward may be called again with another grad_energy; any
+ * other evaluation on the context invalidates the forward state
+ * (DP_E_ARG).  Arguments as for dp_compute. */
+int dp_energy(dp_ctx *c, int64_t natoms, const double *coords, const int32_t *types, const double *box,
+              double *energy);
+int dp_energy_backward(dp_ctx *c, double grad_energy, double *forces, double *virial);
 
 /* Copy the formatted neighbour list of the last evaluation to `nlist`
  * (device, int32 [natoms][sum sel]) and the per-type real counts to `nreal`

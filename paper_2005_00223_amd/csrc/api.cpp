@@ -155,6 +155,7 @@ struct dp_ctx {
   int64_t nev = 0;      // evaluations recorded since timing was enabled
   int64_t ev_cap = 0;   // evaluations the event ring holds
   int64_t last_n = 0;
+  bool fwd_ready = false;  // dp_energy ran; dp_energy_backward may follow
   std::string err;
 };
 
@@ -481,12 +482,107 @@ inline void tnext(dp_ctx *c) {
   if (c->timing && c->nev < c->ev_cap) ++c->nev;
 }
 
-// nlist format .. forces/virial; F must be a device [n][3] buffer
-void eval_body(dp_ctx *c, int64_t n, const double L[3], double *F) {
+// Arguments of the embedding / fitting launches for the loaded policy.
+EmbedArgs embed_args(dp_ctx *c, int64_t n, int64_t rows, double *F) {
+  Workspace &w = c->ws;
+  EmbedArgs ea{};
+  ea.d = c->dims;
+  ea.eo = c->eo;
+  ea.ew = c->d_emb;
+  ea.atom_of_pos = w.atom_of_pos;
+  ea.pos_of_atom = w.pos_of_atom;
+  ea.type_start = w.type_start;
+  ea.rows = rows;
+  ea.natoms = n;
+  ea.xw = w.xw;
+  ea.nlist = w.nlist;
+  ea.nreal = w.nreal;
+  ea.rt = w.rt;
+  ea.dr = w.dr;
+  ea.T = w.T;
+  ea.D = w.D;
+  ea.dD = w.dD;
+  ea.force = F;
+  ea.vir_part = w.vir_part;
+  ea.net_deriv = c->keep ? w.net_deriv : nullptr;
+  return ea;
+}
+
+FitArgs fit_args(dp_ctx *c, int64_t rows) {
+  Workspace &w = c->ws;
+  FitArgs fa{};
+  fa.d = c->dims;
+  fa.fo = c->fo;
+  fa.fwt = c->d_fit;
+  fa.type_start = w.type_start;
+  fa.atom_of_pos = w.atom_of_pos;
+  fa.rows = rows;
+  fa.X0 = w.D;
+  for (int l = 0; l <= MAXF; ++l) {
+    fa.Y[l] = w.Y[l];
+    fa.Tt[l] = w.Tt[l];
+    fa.G[l] = w.G[l];
+  }
+  fa.eatom = w.eatom;
+  return fa;
+}
+
+MixArgs mix_args(dp_ctx *c, int64_t rows, double *F) {
+  Workspace &w = c->ws;
+  MixArgs ma{};
+  ma.d = c->dims;
+  ma.shape = c->mix_shape;
+  ma.prec = c->precision == DP_MIX_FP16 ? 0 : 1;
+  ma.nets = c->d_mix_nets;
+  ma.rows = rows;
+  ma.atom_of_pos = w.atom_of_pos;
+  ma.xw = w.xw;
+  ma.nlist = w.nlist;
+  ma.nreal = w.nreal;
+  ma.rt = w.rt;
+  ma.dr = w.dr;
+  ma.T32 = w.T32;
+  ma.D32 = w.D32;
+  ma.dD32 = w.dD32;
+  ma.force = F;
+  ma.vir_part = w.vir_part;
+  ma.net_deriv = c->keep ? w.net_deriv : nullptr;
+  return ma;
+}
+
+FitMixArgs fitmix_args(dp_ctx *c, int64_t rows) {
+  Workspace &w = c->ws;
+  FitMixArgs fa{};
+  fa.d = c->dims;
+  fa.fo = c->fmo;
+  fa.w = c->d_fit_mix;
+  fa.prec = c->precision == DP_MIX_FP16 ? 0 : 1;
+  fa.n16 = c->n16;
+  fa.type_start = w.type_start;
+  fa.atom_of_pos = w.atom_of_pos;
+  fa.rows = rows;
+  fa.X0 = w.D32;
+  for (int l = 0; l <= MAXF; ++l) {
+    fa.Y[l] = w.Yf[l];
+    fa.Tt[l] = w.Ttf[l];
+    fa.G[l] = w.Gf[l];
+  }
+  fa.eatom = w.eatom;
+  return fa;
+}
+
+int64_t eval_rows(const dp_ctx *c, int64_t n) {
+  return (n + ROW_TILE - 1) / ROW_TILE * ROW_TILE + (int64_t)ROW_TILE * c->dims.ntypes;
+}
+
+// Forward half of an evaluation: formatted list, environment matrix,
+// embedding + descriptor, fitting net forward, energy.  Leaves everything
+// the backward half needs in the workspace.
+void eval_forward(dp_ctx *c, int64_t n, const double L[3]) {
   Workspace &w = c->ws;
   const Dims &d = c->dims;
   hipStream_t s = c->stream;
-  const int64_t rows = (n + ROW_TILE - 1) / ROW_TILE * ROW_TILE + (int64_t)ROW_TILE * d.ntypes;
+  const int64_t rows = eval_rows(c, n);
   tmark(c, 1);
   launch_format(s, n, w.xw, d, L, w.cand, w.cand_n, w.cand_cap, w.nlist, w.nreal, &w.status->overflow,
                 w.status->max_real, &w.status->flags);
@@ -494,99 +590,48 @@ void eval_body(dp_ctx *c, int64_t n, const double L[3], double *F) {
   launch_env(s, n, w.xw, d, L, w.nlist, w.nreal, w.rt, w.dr);
   tmark(c, 3);
   if (c->precision == DP_FP64) {
-    EmbedArgs ea{};
-    ea.d = d;
-    ea.eo = c->eo;
-    ea.ew = c->d_emb;
-    ea.atom_of_pos = w.atom_of_pos;
-    ea.pos_of_atom = w.pos_of_atom;
-    ea.type_start = w.type_start;
-    ea.rows = rows;
-    ea.natoms = n;
-    ea.xw = w.xw;
-    ea.nlist = w.nlist;
-    ea.nreal = w.nreal;
-    ea.rt = w.rt;
-    ea.dr = w.dr;
-    ea.T = w.T;
-    ea.D = w.D;
-    ea.dD = w.dD;
-    ea.force = F;
-    ea.vir_part = w.vir_part;
-    ea.net_deriv = c->keep ? w.net_deriv : nullptr;
-    launch_embed_fwd_f64(s, ea);
+    launch_embed_fwd_f64(s, embed_args(c, n, rows, nullptr));
     tmark(c, 4);
-    FitArgs fa{};
-    fa.d = d;
-    fa.fo = c->fo;
-    fa.fwt = c->d_fit;
-    fa.type_start = w.type_start;
-    fa.atom_of_pos = w.atom_of_pos;
-    fa.rows = rows;
-    fa.X0 = w.D;
-    for (int l = 0; l <= MAXF; ++l) {
-      fa.Y[l] = w.Y[l];
-      fa.Tt[l] = w.Tt[l];
-      fa.G[l] = w.G[l];
-    }
-    fa.eatom = w.eatom;
-    launch_fit_f64(s, fa);
+    launch_fit_f64(s, fit_args(c, rows), 1);
+  } else {
+    launch_embed_mix(s, mix_args(c, rows, nullptr), 1, mix_grid(rows));
+    tmark(c, 4);
+    launch_fit_mix(s, fitmix_args(c, rows), 1);
+  }
+  launch_sum(s, w.eatom, n, w.partial, w.energy, 1.0);
+}
+
+// Backward half (the adjoint): fitting net backward to dE/dD, then the
+// embedding backward with the force and virial scatter into F.
+void eval_backward(dp_ctx *c, int64_t n, double *F) {
+  Workspace &w = c->ws;
+  hipStream_t s = c->stream;
+  const int64_t rows = eval_rows(c, n);
+  if (c->precision == DP_FP64) {
+    launch_fit_f64(s, fit_args(c, rows), 2);
     tmark(c, 5);
-    launch_sum(s, w.eatom, n, w.partial, w.energy, 1.0);
     launch_zero(s, F, 3 * n);
     const int grid = embed_bwd_grid(rows);
     tmark(c, 6);
-    launch_embed_bwd_f64(s, ea, grid);
+    launch_embed_bwd_f64(s, embed_args(c, n, rows, F), grid);
     tmark(c, 7);
     launch_sum9(s, w.vir_part, grid, w.virial);
   } else {
-    MixArgs ma{};
-    ma.d = d;
-    ma.shape = c->mix_shape;
-    ma.prec = c->precision == DP_MIX_FP16 ? 0 : 1;
-    ma.nets = c->d_mix_nets;
-    ma.rows = rows;
-    ma.atom_of_pos = w.atom_of_pos;
-    ma.xw = w.xw;
-    ma.nlist = w.nlist;
-    ma.nreal = w.nreal;
-    ma.rt = w.rt;
-    ma.dr = w.dr;
-    ma.T32 = w.T32;
-    ma.D32 = w.D32;
-    ma.dD32 = w.dD32;
-    ma.force = F;
-    ma.vir_part = w.vir_part;
-    ma.net_deriv = c->keep ? w.net_deriv : nullptr;
-    const int grid = mix_grid(rows);
-    launch_embed_mix(s, ma, 1, grid);
-    tmark(c, 4);
-    FitMixArgs fa{};
-    fa.d = d;
-    fa.fo = c->fmo;
-    fa.w = c->d_fit_mix;
-    fa.prec = ma.prec;
-    fa.n16 = c->n16;
-    fa.type_start = w.type_start;
-    fa.atom_of_pos = w.atom_of_pos;
-    fa.rows = rows;
-    fa.X0 = w.D32;
-    for (int l = 0; l <= MAXF; ++l) {
-      fa.Y[l] = w.Yf[l];
-      fa.Tt[l] = w.Ttf[l];
-      fa.G[l] = w.Gf[l];
-    }
-    fa.eatom = w.eatom;
-    launch_fit_mix(s, fa);
+    launch_fit_mix(s, fitmix_args(c, rows), 2);
     tmark(c, 5);
-    launch_sum(s, w.eatom, n, w.partial, w.energy, 1.0);
     launch_zero(s, F, 3 * n);
+    const int grid = mix_grid(rows);
     tmark(c, 6);
-    launch_embed_mix(s, ma, 2, grid);
+    launch_embed_mix(s, mix_args(c, rows, F), 2, grid);
     tmark(c, 7);
     launch_sum9(s, w.vir_part, grid, w.virial);
   }
   tnext(c);
+}
+
+void eval_body(dp_ctx *c, int64_t n, const double L[3], double *F) {
+  eval_forward(c, n, L);
+  eval_backward(c, n, F);
 }
 
 void build_lists(dp_ctx *c, int64_t n, const CellGrid &g, double rlist, const uint32_t *cond) {
@@ -741,10 +786,10 @@ int dp_get_timing(dp_ctx *c, const char *name, double *ms) {
   return fail(c, DP_E_ARG, "unknown timer name");
 }
 
-int dp_compute(dp_ctx *c, int64_t n, const double *coords, const int32_t *types, const double *box, double *energy,
-               double *forces, double *virial) {
+static int compute_impl(dp_ctx *c, int64_t n, const double *coords, const int32_t *types, const double *box,
+                        double *energy, double *forces, double *virial, bool backward) {
   if (!c) return DP_E_ARG;
-  if (!c->has_model) return fail(c, DP_E_NOMODEL, "dp_compute before dp_set_model");
+  if (!c->has_model) return fail(c, DP_E_NOMODEL, "evaluation before dp_set_model");
   if (n < 0 || n >= (1 << 26)) return fail(c, DP_E_ARG, "natoms must be in [0, 2^26)");
   if (n > 0 && (!coords || !types)) return fail(c, DP_E_ARG, "NULL coords or types");
   HIPCHK(c, hipSetDevice(c->device));
@@ -757,6 +802,7 @@ int dp_compute(dp_ctx *c, int64_t n, const double *coords, const int32_t *types,
   CellGrid g = make_grid(L, rlist);
   const int64_t ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
   int cap = cand_capacity(n, L, rlist);
+  c->fwd_ready = false;
   for (int attempt = 0; attempt < 4; ++attempt) {
     rc = ensure_ws(c, std::max<int64_t>(n, 1), ncell, cap);
     if (rc) return rc;
@@ -769,7 +815,8 @@ int dp_compute(dp_ctx *c, int64_t n, const double *coords, const int32_t *types,
       launch_type_sort(s, n, w.xw, d.ntypes, w.blk_counts, w.type_count, w.type_start, w.pos_of_atom,
                        w.atom_of_pos, w.rows_cap);
       build_lists(c, n, g, rlist, nullptr);
-      eval_body(c, n, L, F);
+      eval_forward(c, n, L);
+      if (backward) eval_backward(c, n, F);
     } else {
       launch_zero(s, w.energy, 1);
       launch_zero(s, w.virial, 9);
@@ -777,7 +824,8 @@ int dp_compute(dp_ctx *c, int64_t n, const double *coords, const int32_t *types,
       tnext(c);
     }
     if (energy) HIPCHK(c, hipMemcpyAsync(energy, w.energy, sizeof(double), hipMemcpyDeviceToDevice, s));
-    if (virial) HIPCHK(c, hipMemcpyAsync(virial, w.virial, 9 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (virial && backward)
+      HIPCHK(c, hipMemcpyAsync(virial, w.virial, 9 * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(c, hipGetLastError());
     rc = read_status(c);
     if (rc) return rc;
@@ -793,9 +841,51 @@ int dp_compute(dp_ctx *c, int64_t n, const double *coords, const int32_t *types,
     c->stats.evaluations += 1;
     c->stats.cand_cap = c->ws.cand_cap;
     c->last_n = n;
+    c->fwd_ready = !backward;
     return DP_OK;
   }
   return fail(c, DP_E_CAP, "candidate list capacity could not be sized");
+}
+
+__global__ void k_scale(double *x, int64_t n, double a) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= a;
+}
+
+int dp_compute(dp_ctx *c, int64_t n, const double *coords, const int32_t *types, const double *box, double *energy,
+               double *forces, double *virial) {
+  return compute_impl(c, n, coords, types, box, energy, forces, virial, true);
+}
+
+int dp_energy(dp_ctx *c, int64_t n, const double *coords, const int32_t *types, const double *box, double *energy) {
+  return compute_impl(c, n, coords, types, box, energy, nullptr, nullptr, false);
+}
+
+int dp_energy_backward(dp_ctx *c, double grad_energy, double *forces, double *virial) {
+  if (!c) return DP_E_ARG;
+  if (!c->fwd_ready) return fail(c, DP_E_ARG, "dp_energy_backward needs a preceding dp_energy");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int64_t n = c->last_n;
+  Workspace &w = c->ws;
+  hipStream_t s = c->stream;
+  double *F = forces ? forces : w.force_tmp;
+  if (n > 0) {
+    tmark(c, 0);
+    tmark(c, 1);
+    tmark(c, 2);
+    tmark(c, 3);
+    tmark(c, 4);
+    eval_backward(c, n, F);
+    if (grad_energy != 1.0) {
+      hipLaunchKernelGGL(k_scale, dim3((unsigned)((3 * n + 255) / 256)), dim3(256), 0, s, F, 3 * n, grad_energy);
+      hipLaunchKernelGGL(k_scale, dim3(1), dim3(64), 0, s, w.virial, (int64_t)9, grad_energy);
+    }
+  } else {
+    launch_zero(s, w.virial, 9);
+  }
+  if (virial) HIPCHK(c, hipMemcpyAsync(virial, w.virial, 9 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(c, hipGetLastError());
+  return DP_OK;
 }
 
 int dp_get_nlist(dp_ctx *c, int32_t *nlist, int32_t *nreal) {
@@ -857,6 +947,7 @@ int dp_md_run(dp_ctx *c, int64_t n, double *coords, double *vel, const int32_t *
     return fail(c, DP_E_ARG, "bad MD arguments");
   if (thermo && thermo_every < 1) return fail(c, DP_E_ARG, "thermo_every must be >= 1");
   HIPCHK(c, hipSetDevice(c->device));
+  c->fwd_ready = false;
   const Dims &d = c->dims;
   const double rlist = d.rcut + skin;
   double L[3];

@@ -134,7 +134,8 @@ struct FitArgs {
   double *G[MAXF + 1];        // gradient wrt Y[l] [rows][fw[l]]; G[0] = dD
   double *eatom;              // [natoms] (original order)
 };
-void launch_fit_f64(hipStream_t s, const FitArgs &a);
+// pass 1: forward layers and E_i; pass 2: backward to dE/dD
+void launch_fit_f64(hipStream_t s, const FitArgs &a, int pass);
 
 // ---- reductions and MD (k_md.hip) ----
 void launch_sum(hipStream_t s, const double *x, int64_t n, double *partial, double *out, double scale);

@@ -51,6 +51,6 @@ struct FitMixArgs {
   float *G[MAXF + 1];         // dE/dY[l]; G[0] = dE/dD
   double *eatom;
 };
-void launch_fit_mix(hipStream_t s, const FitMixArgs &a);
+void launch_fit_mix(hipStream_t s, const FitMixArgs &a, int pass);
 
 }  // namespace dpk

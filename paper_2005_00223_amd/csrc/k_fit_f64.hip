@@ -157,11 +157,11 @@ __global__ void __launch_bounds__(256) k_fit_out(const int32_t *type_start, int 
   if (lane == 0) eatom[atom] = s + fwt[fo.b[t][L]];
 }
 
-void launch_fit_f64(hipStream_t s, const FitArgs &a) {
+void launch_fit_f64(hipStream_t s, const FitArgs &a, int pass) {
   const Dims &d = a.d;
   const int L = d.n_fit;
   const unsigned gm = (unsigned)((a.rows + BM - 1) / BM);
-  for (int l = 0; l < L; ++l) {
+  for (int l = 0; l < L && pass == 1; ++l) {
     GemmArgs g{};
     g.mode = FIT_FWD;
     g.layer = l;
@@ -178,9 +178,10 @@ void launch_fit_f64(hipStream_t s, const FitArgs &a) {
     g.Y = a.Y[l + 1];
     hipLaunchKernelGGL(k_fit_gemm<FIT_FWD>, dim3(gm, (unsigned)((g.N + BN - 1) / BN)), dim3(256), 0, s, g);
   }
-  hipLaunchKernelGGL(k_fit_out, dim3((unsigned)((a.rows + 3) / 4)), dim3(256), 0, s, a.type_start, d.ntypes,
-                     a.atom_of_pos, a.fwt, a.fo, L, d.fw[L], a.Y[L], a.rows, a.eatom);
-  for (int l = L - 1; l >= 0; --l) {
+  if (pass == 1)
+    hipLaunchKernelGGL(k_fit_out, dim3((unsigned)((a.rows + 3) / 4)), dim3(256), 0, s, a.type_start, d.ntypes,
+                       a.atom_of_pos, a.fwt, a.fo, L, d.fw[L], a.Y[L], a.rows, a.eatom);
+  for (int l = L - 1; l >= 0 && pass == 2; --l) {
     GemmArgs g{};
     g.mode = FIT_BWD;
     g.layer = l;

@@ -285,11 +285,11 @@ __global__ void __launch_bounds__(256) k_fitmix_out(const int32_t *type_start, i
 }
 
 template <int P>
-static void run(hipStream_t s, const FitMixArgs &a) {
+static void run(hipStream_t s, const FitMixArgs &a, int pass) {
   const Dims &d = a.d;
   const int L = d.n_fit;
   const unsigned gm = (unsigned)((a.rows + 63) / 64);
-  for (int l = 0; l < L; ++l) {
+  for (int l = 0; l < L && pass == 1; ++l) {
     MG g{};
     g.layer = l;
     g.in = d.fw[l];
@@ -307,9 +307,10 @@ static void run(hipStream_t s, const FitMixArgs &a) {
     if (l < a.n16) hipLaunchKernelGGL((k_fitmix16<P, MF_FWD>), grid, dim3(256), 0, s, g);
     else hipLaunchKernelGGL((k_fitmix32<MF_FWD>), grid, dim3(256), 0, s, g);
   }
-  hipLaunchKernelGGL(k_fitmix_out, dim3((unsigned)((a.rows + 3) / 4)), dim3(256), 0, s, a.type_start, d.ntypes,
-                     a.atom_of_pos, a.w, a.fo, L, d.fw[L], a.Y[L], a.rows, a.eatom);
-  for (int l = L - 1; l >= 0; --l) {
+  if (pass == 1)
+    hipLaunchKernelGGL(k_fitmix_out, dim3((unsigned)((a.rows + 3) / 4)), dim3(256), 0, s, a.type_start, d.ntypes,
+                       a.atom_of_pos, a.w, a.fo, L, d.fw[L], a.Y[L], a.rows, a.eatom);
+  for (int l = L - 1; l >= 0 && pass == 2; --l) {
     MG g{};
     g.layer = l;
     g.in = d.fw[l];
@@ -329,9 +330,9 @@ static void run(hipStream_t s, const FitMixArgs &a) {
   }
 }
 
-void launch_fit_mix(hipStream_t s, const FitMixArgs &a) {
-  if (a.prec == 0) run<0>(s, a);
-  else run<1>(s, a);
+void launch_fit_mix(hipStream_t s, const FitMixArgs &a, int pass) {
+  if (a.prec == 0) run<0>(s, a, pass);
+  else run<1>(s, a, pass);
 }
 
 }  // namespace dpk

@@ -61,6 +61,23 @@ class DPModel:
         L.dp_compute(self.ctx, n, _ptr(x), _ptr(t), _box9(box), _ptr(e), _ptr(f), _ptr(v))
         return e[0], f, v.view(3, 3)
 
+    def energy(self, coords, types, box):
+        """Forward half only (0-d energy tensor); keeps the state for
+        energy_backward."""
+        x = self._dev(coords, torch.float64)
+        t = self._dev(types, torch.int32)
+        e = torch.empty(1, dtype=torch.float64, device=self.device)
+        L.dp_energy(self.ctx, x.shape[0], _ptr(x), _ptr(t), _box9(box), _ptr(e))
+        self._n = x.shape[0]
+        return e[0]
+
+    def energy_backward(self, grad_energy=1.0):
+        """Adjoint of the last energy(): (forces = -g dE/dr [N,3], g * virial [3,3])."""
+        f = torch.empty((self._n, 3), dtype=torch.float64, device=self.device)
+        v = torch.empty(9, dtype=torch.float64, device=self.device)
+        L.dp_energy_backward(self.ctx, float(grad_energy), _ptr(f), _ptr(v))
+        return f, v.view(3, 3)
+
     def nlist(self, natoms, nnei, ntypes, with_list=True):
         """(nlist [N, nnei], nreal [N, ntypes]) of the last evaluation;
         with_list=False fetches only the real-neighbour counts."""
@@ -105,3 +122,24 @@ class DPModel:
 
     def timing(self, name):
         return L.dp_get_timing(self.ctx, name)
+
+
+class DPEnergy(torch.autograd.Function):
+    """E(coords) with the library's hand-written adjoint as the backward.
+
+    forward runs dp_energy (list, environment matrix, embedding +
+    descriptor, fitting net); backward runs dp_energy_backward, the fitting
+    and embedding backward with the ProdForce scatter, and returns
+    grad_E * dE/dcoords = -grad_E * F.  Use as
+    ``E = DPEnergy.apply(coords, model, types, box)``."""
+
+    @staticmethod
+    def forward(ctx, coords, model, types, box):
+        ctx.model = model
+        return model.energy(coords.detach(), types, box)
+
+    @staticmethod
+    def backward(ctx, grad_e):
+        # the library works with one host scalar: a CUDA grad is read back
+        f, _ = ctx.model.energy_backward(float(grad_e))
+        return -f, None, None, None
