@@ -136,16 +136,17 @@ struct Shape {
   // per-wave LDS scratch (bytes)
   static constexpr int P1_H1 = 0;                       // float [16][S1]
   static constexpr int P1_H2 = P1_H1 + 16 * S1 * 4;     // float [16][S2]
-  static constexpr int P1_G = P1_H2 + 16 * S2 * 4;      // float [16][S3]
-  static constexpr int P1_R = P1_G + 16 * S3 * 4;       // float [16][4]
-  static constexpr int P1_T = P1_R + 256;               // float [S3][4]
-  static constexpr int P1_BYTES = P1_T + S3 * 16;
+  static constexpr int P1_G = P1_H2 + 16 * S2 * 4;      // float [16][32]: two output tiles of G
+  static constexpr int P1_R = P1_G + 16 * 32 * 4;       // float [16][4]
+  static constexpr int P1_T = 0;                        // float [S3][4], aliases H1/H2/G at the atom's end
+  static constexpr int P1_BYTES = P1_R + 256;
   static constexpr int P2_H1 = 0;                       // float [2][16][S1] (h, dh)
   static constexpr int P2_H2 = P2_H1 + 2 * 16 * S1 * 4; // float [2][16][S2]
   static constexpr int P2_R = P2_H2 + 2 * 16 * S2 * 4;  // float [16][4]
   static constexpr int P2_GR = P2_R + 256;              // float [64][4]
-  static constexpr int P2_DT = P2_GR + 1024;            // float [S3][4]
-  static constexpr int P2_BYTES = P2_DT + S3 * 16;
+  static constexpr int P2_DT = 0;                       // float [S3][4], aliases H1/H2 at the atom's start
+  static constexpr int P2_BYTES = P2_GR + 1024;
+  static_assert(S3 * 16 <= P1_R && S3 * 16 <= P2_R, "T / dT scratch must fit the aliased buffers");
 };
 
 constexpr int MIX_WAVES = 4;
@@ -216,6 +217,25 @@ __device__ inline void layer_mfma(const unsigned char *Aops, const float *bias, 
     }
 }
 
+// one output tile mt of an MFMA layer (bias-initialised when bias != NULL)
+template <int P, int KS>
+__device__ inline v4f mfma_tile(const unsigned char *Aops, const float *bias, const Split8<P> (&B)[KS], int lane,
+                                int g, int mt) {
+  typedef typename HT<P>::v8 V;
+  v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+  if (bias) {
+    const float4 b = *(const float4 *)(bias + 16 * mt + 4 * g);
+    acc = v4f{b.x, b.y, b.z, b.w};
+  }
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    const V a = *(const V *)(Aops + ((mt * KS + kk) * 64 + lane) * 16);
+    acc = mfma16<P>(a, B[kk].hi, acc);
+    acc = mfma16<P>(a, B[kk].lo, acc);
+  }
+  return acc;
+}
+
 // tangent columns: same A operands, zero initial accumulator
 template <int P, int MT, int KS>
 __device__ inline void layer_mfma_tan(const unsigned char *Aops, const Split8<P> (&B)[KS], int lane, v4f (&acc)[MT]) {
@@ -248,7 +268,7 @@ __device__ inline float skip_val(int f, int mt, int r, const float (&prev)[MTI][
 }
 
 template <int W1, int W2, int W3, int P>
-__global__ void __launch_bounds__(64 * MIX_WAVES) k_embed_fwd_mix(MixArgs a) {
+__global__ void __launch_bounds__(64 * MIX_WAVES, 2) k_embed_fwd_mix(MixArgs a) {
   typedef Shape<W1, W2, W3> S;
   typedef typename HT<P>::v8 V;
   typedef typename HT<P>::e E;
@@ -317,31 +337,36 @@ __global__ void __launch_bounds__(64 * MIX_WAVES) k_embed_fwd_mix(MixArgs a) {
         Split8<P> B3[S::KS3];
 #pragma unroll
         for (int kk = 0; kk < S::KS3; ++kk) B3[kk] = split8<P>(h2[2 * kk], h2[2 * kk + 1]);
-        v4f acc3[S::MT3];
-        layer_mfma<P, S::MT3, S::KS3>(net + S::O_A3, b3, B3, lane, g, acc3);
         wsync();
-        // G -> LDS as [neighbour][feature]
+        // layer 3, G and T += G R^T, one pair of output tiles at a time
 #pragma unroll
-        for (int mt = 0; mt < S::MT3; ++mt) {
-          float gv[4];
+        for (int kp = 0; kp < S::KSC; ++kp) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int f = 16 * mt + 4 * g + r;
-            gv[r] = (f < W3) ? tanh_f(acc3[mt][r]) + skip_val<W2, W3, S::SK3, S::MT2>(f, mt, r, h2, h2s, n, S::S2)
-                             : 0.f;
+          for (int q = 0; q < 2; ++q) {
+            const int mt = 2 * kp + q;
+            float gv[4] = {0.f, 0.f, 0.f, 0.f};
+            if (mt < S::MT3) {
+              const v4f acc3 = mfma_tile<P, S::KS3>(net + S::O_A3, b3, B3, lane, g, mt);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int f = 16 * mt + 4 * g + r;
+                if (f < W3) gv[r] = tanh_f(acc3[r]) + skip_val<W2, W3, S::SK3, S::MT2>(f, mt, r, h2, h2s, n, S::S2);
+              }
+            }
+            *(float4 *)(Gs + n * 32 + 16 * q + 4 * g) = make_float4(gv[0], gv[1], gv[2], gv[3]);
           }
-          *(float4 *)(Gs + n * S::S3 + 16 * mt + 4 * g) = make_float4(gv[0], gv[1], gv[2], gv[3]);
-        }
-        wsync();
-        // T[f][c] += sum_nb G[nb][f] R[nb][c]: A = G^T (rows f), B = R (K = neighbours)
+          wsync();
+          // T[f][c] += sum_nb G[nb][f] R[nb][c]: A = G^T (rows f), B = R (K = neighbours)
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const int nb = 4 * kk + g;
-          const float rb = n < 4 ? Rs[4 * nb + n] : 0.f;
+          for (int kk = 0; kk < 4; ++kk) {
+            const int nb = 4 * kk + g;
+            const float rb = n < 4 ? Rs[4 * nb + n] : 0.f;
 #pragma unroll
-          for (int mt = 0; mt < S::MT3; ++mt) Tacc[mt] = mfma32(Gs[nb * S::S3 + 16 * mt + n], rb, Tacc[mt]);
+            for (int q = 0; q < 2; ++q)
+              if (2 * kp + q < S::MT3) Tacc[2 * kp + q] = mfma32(Gs[nb * 32 + 16 * q + n], rb, Tacc[2 * kp + q]);
+          }
+          wsync();
         }
-        wsync();
       }
     }
     // T / Nc: lane (g, n) holds T[16 mt + 4 g + r][n] for n < 4
@@ -393,7 +418,7 @@ __device__ inline void switch64(double r, double rcs, double rc, double inv_w, d
 }
 
 template <int W1, int W2, int W3, int P>
-__global__ void __launch_bounds__(64 * MIX_WAVES) k_embed_bwd_mix(MixArgs a) {
+__global__ void __launch_bounds__(64 * MIX_WAVES, 2) k_embed_bwd_mix(MixArgs a) {
   typedef Shape<W1, W2, W3> S;
   typedef typename HT<P>::v8 V;
   typedef typename HT<P>::e E;
@@ -451,6 +476,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES) k_embed_bwd_mix(MixArgs a) {
       }
       dTB[kk] = split8<P>(x, y);
     }
+    wsync();
     double fi0 = 0.0, fi1 = 0.0, fi2 = 0.0;
     for (int u = 0; u < d.ntypes; ++u) {
       const unsigned char *net = smem + (t * d.ntypes + u) * S::NET_BYTES;
@@ -505,38 +531,43 @@ __global__ void __launch_bounds__(64 * MIX_WAVES) k_embed_bwd_mix(MixArgs a) {
           B3h[kk] = split8<P>(h2[2 * kk], h2[2 * kk + 1]);
           B3d[kk] = split8<P>(hd2[2 * kk], hd2[2 * kk + 1]);
         }
-        v4f acc3[S::MT3], acc3d[S::MT3];
-        layer_mfma<P, S::MT3, S::KS3>(net + S::O_A3, b3, B3h, lane, g, acc3);
-        layer_mfma_tan<P, S::MT3, S::KS3>(net + S::O_A3, B3d, lane, acc3d);
         wsync();
-        float G[S::KSC * 2][4], Gd[S::KSC * 2][4];
-#pragma unroll
-        for (int mt = 0; mt < S::KSC * 2; ++mt)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int f = 16 * mt + 4 * g + r;
-            float gv = 0.f, dv = 0.f;
-            if (mt < S::MT3 && f < W3) {
-              const float th = tanh_f(acc3[mt < S::MT3 ? mt : 0][r]);
-              gv = th + skip_val<W2, W3, S::SK3, S::MT2>(f, mt, r, h2, h2s, n, S::S2);
-              dv = (1.f - th * th) * acc3d[mt < S::MT3 ? mt : 0][r] +
-                   skip_val<W2, W3, S::SK3, S::MT2>(f, mt, r, hd2, hd2s, n, S::S2);
-            }
-            G[mt][r] = gv;
-            Gd[mt][r] = dv;
-          }
-        // a = G^T dT, b = G'^T dT; lane (g, c) gets rows nb = 4 g + r, column c
+        // layer 3 with tangent, then a = G^T dT and b = G'^T dT, one pair of
+        // output tiles at a time (G and G' never leave registers)
         v4f ca = v4f{0.f, 0.f, 0.f, 0.f}, cb = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kk = 0; kk < S::KSC; ++kk) {
-          const Split8<P> ga = split8<P>(G[2 * kk], G[2 * kk + 1]);
-          const Split8<P> gb = split8<P>(Gd[2 * kk], Gd[2 * kk + 1]);
-          ca = mfma16<P>(ga.hi, dTB[kk].hi, ca);
-          ca = mfma16<P>(ga.hi, dTB[kk].lo, ca);
-          ca = mfma16<P>(ga.lo, dTB[kk].hi, ca);
-          cb = mfma16<P>(gb.hi, dTB[kk].hi, cb);
-          cb = mfma16<P>(gb.hi, dTB[kk].lo, cb);
-          cb = mfma16<P>(gb.lo, dTB[kk].hi, cb);
+        for (int kp = 0; kp < S::KSC; ++kp) {
+          float G[2][4], Gd[2][4];
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int mt = 2 * kp + q;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              G[q][r] = 0.f;
+              Gd[q][r] = 0.f;
+            }
+            if (mt < S::MT3) {
+              const v4f h3 = mfma_tile<P, S::KS3>(net + S::O_A3, b3, B3h, lane, g, mt);
+              const v4f d3 = mfma_tile<P, S::KS3>(net + S::O_A3, nullptr, B3d, lane, g, mt);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                const int f = 16 * mt + 4 * g + r;
+                if (f < W3) {
+                  const float th = tanh_f(h3[r]);
+                  G[q][r] = th + skip_val<W2, W3, S::SK3, S::MT2>(f, mt, r, h2, h2s, n, S::S2);
+                  Gd[q][r] = (1.f - th * th) * d3[r] + skip_val<W2, W3, S::SK3, S::MT2>(f, mt, r, hd2, hd2s, n, S::S2);
+                }
+              }
+            }
+          }
+          const Split8<P> ga = split8<P>(G[0], G[1]);
+          const Split8<P> gb = split8<P>(Gd[0], Gd[1]);
+          ca = mfma16<P>(ga.hi, dTB[kp].hi, ca);
+          ca = mfma16<P>(ga.hi, dTB[kp].lo, ca);
+          ca = mfma16<P>(ga.lo, dTB[kp].hi, ca);
+          cb = mfma16<P>(gb.hi, dTB[kp].hi, cb);
+          cb = mfma16<P>(gb.hi, dTB[kp].lo, cb);
+          cb = mfma16<P>(gb.lo, dTB[kp].hi, cb);
         }
         const int slot0 = n0 & 63;
 #pragma unroll

@@ -59,6 +59,7 @@ class DPModel:
         v = torch.empty(9, dtype=torch.float64, device=self.device)
         L.dp_keep_intermediates(self.ctx, keep_intermediates)
         L.dp_compute(self.ctx, n, _ptr(x), _ptr(t), _box9(box), _ptr(e), _ptr(f), _ptr(v))
+        self._n = n
         return e[0], f, v.view(3, 3)
 
     def energy(self, coords, types, box):
@@ -73,7 +74,7 @@ class DPModel:
 
     def energy_backward(self, grad_energy=1.0):
         """Adjoint of the last energy(): (forces = -g dE/dr [N,3], g * virial [3,3])."""
-        f = torch.empty((self._n, 3), dtype=torch.float64, device=self.device)
+        f = torch.empty((getattr(self, "_n", 0), 3), dtype=torch.float64, device=self.device)
         v = torch.empty(9, dtype=torch.float64, device=self.device)
         L.dp_energy_backward(self.ctx, float(grad_energy), _ptr(f), _ptr(v))
         return f, v.view(3, 3)

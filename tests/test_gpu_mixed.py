@@ -59,7 +59,7 @@ def test_force_rmse_full(name, prec):
     # 16-bit weights shift the energy: about 1e-4 relative in FP16, 2e-3 in BF16
     assert abs(e.item() - r["energy"]) <= (1e-3 if prec == "fp16" else 5e-3) * abs(r["energy"])
     vv = v.cpu().numpy()
-    assert np.abs(vv - r["virial"]).max() <= 1e-3 * np.abs(r["virial"]).max()
+    assert np.abs(vv - r["virial"]).max() <= (1e-3 if prec == "fp16" else 5e-3) * np.abs(r["virial"]).max()
     # the neighbour list does not depend on the precision policy
     nl, _ = m.nlist(n, w["spec"].nnei, w["spec"].ntypes)
     onl, _, _ = _oracle(blob).nlist(w["coords"], w["types"], w["box"])
