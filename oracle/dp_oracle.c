@@ -41,6 +41,7 @@
 
 typedef struct {
   int64_t ntypes, n_emb, n_fit, M2, M1, nnei;
+  int64_t emb_lin;                /* 1: the last embedding layer has no tanh */
   double rcut, rcut_smth, desc_norm;
   int64_t sel[OR_MAXT], off[OR_MAXT + 1];
   int64_t emb_w[OR_MAXL + 1];     /* emb_w[0] = 1, emb_w[n_emb] = M1 */
@@ -88,9 +89,11 @@ void *or_model_new(const void *blob, int64_t nbytes) {
   if (nbytes < 8 || memcmp(p, "DPMIBLOB", 8) != 0) { snprintf(or_err, sizeof or_err, "bad magic"); return NULL; }
   p += 8;
   m = (or_model *)calloc(1, sizeof(or_model));
-  if (rd_i64(&p, end, &ver) || ver != 1) goto bad;
+  if (rd_i64(&p, end, &ver) || (ver != 1 && ver != 2)) goto bad;
   if (rd_i64(&p, end, &m->ntypes) || rd_i64(&p, end, &m->n_emb) || rd_i64(&p, end, &m->n_fit) ||
       rd_i64(&p, end, &m->M2)) goto bad;
+  /* version 2 adds one flag: a linear (activation-free) last embedding layer */
+  if (ver == 2 && (rd_i64(&p, end, &m->emb_lin) || (m->emb_lin != 0 && m->emb_lin != 1))) goto bad;
   if (m->ntypes < 1 || m->ntypes > OR_MAXT || m->n_emb < 1 || m->n_emb > OR_MAXL || m->n_fit < 1 ||
       m->n_fit > OR_MAXL) goto bad;
   if (rd_f64(&p, end, &m->rcut) || rd_f64(&p, end, &m->rcut_smth) || rd_f64(&p, end, &m->desc_norm)) goto bad;
@@ -385,15 +388,15 @@ void or_env_single(const void *h, const double *d, double *R, double *J) {
 /* ------------------------------------------------------------------ */
 /* networks: Fig. 1(e) dense, (f) doubling skip, (g) identity skip        */
 /* ------------------------------------------------------------------ */
-/* One hidden layer: z = h W + b, t = tanh(z);
+/* One hidden layer: z = h W + b, t = tanh(z) (t = z for a linear layer);
  * out == in: h' = h + t;  out == 2 in: h' = (h, h) + t;  else h' = t. */
 static void or_layer_fwd(const double *W, const double *b, int64_t in, int64_t out, const double *h,
-                         double *t, double *hn) {
+                         double *t, double *hn, int lin) {
   int64_t i, o;
   for (o = 0; o < out; ++o) {
     double z = b[o];
     for (i = 0; i < in; ++i) z += h[i] * W[i * out + o];
-    t[o] = tanh(z);
+    t[o] = lin ? z : tanh(z);
   }
   for (o = 0; o < out; ++o) {
     if (out == in) hn[o] = h[o] + t[o];
@@ -404,9 +407,9 @@ static void or_layer_fwd(const double *W, const double *b, int64_t in, int64_t o
 
 /* given dE/dh' and t, return dE/dh */
 static void or_layer_bwd(const double *W, int64_t in, int64_t out, const double *t, const double *gh_out,
-                         double *gz, double *gh_in) {
+                         double *gz, double *gh_in, int lin) {
   int64_t i, o;
-  for (o = 0; o < out; ++o) gz[o] = gh_out[o] * (1.0 - t[o] * t[o]);
+  for (o = 0; o < out; ++o) gz[o] = lin ? gh_out[o] : gh_out[o] * (1.0 - t[o] * t[o]);
   for (i = 0; i < in; ++i) {
     double g = 0.0;
     for (o = 0; o < out; ++o) g += W[i * out + o] * gz[o];
@@ -425,7 +428,7 @@ static void or_embed_fwd(const or_model *m, int t, int u, double s, double *hh, 
   hh[0] = s;
   for (l = 0; l < m->n_emb; ++l)
     or_layer_fwd(m->eW[t][u][l], m->eb[t][u][l], m->emb_w[l], m->emb_w[l + 1], hh + l * OR_WMAX,
-                 tt + l * OR_WMAX, hh + (l + 1) * OR_WMAX);
+                 tt + l * OR_WMAX, hh + (l + 1) * OR_WMAX, m->emb_lin && l == m->n_emb - 1);
   memcpy(G, hh + m->n_emb * OR_WMAX, (size_t)m->M1 * sizeof(double));
 }
 
@@ -435,7 +438,8 @@ static double or_embed_bwd(const or_model *m, int t, int u, const double *tt, co
   int64_t l;
   memcpy(w1, gG, (size_t)m->M1 * sizeof(double));
   for (l = m->n_emb - 1; l >= 0; --l) {
-    or_layer_bwd(m->eW[t][u][l], m->emb_w[l], m->emb_w[l + 1], tt + l * OR_WMAX, w1, gz, w2);
+    or_layer_bwd(m->eW[t][u][l], m->emb_w[l], m->emb_w[l + 1], tt + l * OR_WMAX, w1, gz, w2,
+                 m->emb_lin && l == m->n_emb - 1);
     memcpy(w1, w2, (size_t)m->emb_w[l] * sizeof(double));
   }
   return w1[0];
@@ -460,7 +464,7 @@ static double or_fit_fwd(const or_model *m, int t, const double *Dv, double *hh,
   memcpy(hh, Dv, (size_t)m->fit_w[0] * sizeof(double));
   for (l = 0; l < L; ++l)
     or_layer_fwd(m->fW[t][l], m->fb[t][l], m->fit_w[l], m->fit_w[l + 1], hh + l * OR_WMAX,
-                 tt + l * OR_WMAX, hh + (l + 1) * OR_WMAX);
+                 tt + l * OR_WMAX, hh + (l + 1) * OR_WMAX, 0);
   e = m->fb[t][L][0];
   for (i = 0; i < m->fit_w[L]; ++i) e += hh[L * OR_WMAX + i] * m->fW[t][L][i];
   return e;
@@ -471,7 +475,7 @@ static void or_fit_bwd(const or_model *m, int t, const double *tt, double *gD, d
   int64_t l, i, L = m->n_fit;
   for (i = 0; i < m->fit_w[L]; ++i) w1[i] = m->fW[t][L][i];
   for (l = L - 1; l >= 0; --l) {
-    or_layer_bwd(m->fW[t][l], m->fit_w[l], m->fit_w[l + 1], tt + l * OR_WMAX, w1, gz, w2);
+    or_layer_bwd(m->fW[t][l], m->fit_w[l], m->fit_w[l + 1], tt + l * OR_WMAX, w1, gz, w2, 0);
     memcpy(w1, w2, (size_t)m->fit_w[l] * sizeof(double));
   }
   memcpy(gD, w1, (size_t)m->fit_w[0] * sizeof(double));

@@ -24,6 +24,7 @@ import numpy as np
 
 BLOB_MAGIC = b"DPMIBLOB"
 BLOB_VERSION = 1
+BLOB_VERSION_LINEAR_OUT = 2   # adds the emb_out_linear flag
 
 # Units: A, fs, amu, eV.  1 amu*A^2/fs^2 = 103.6427 eV.
 MVV2E = 103.642696562
@@ -131,6 +132,7 @@ class ModelSpec:
     emb_b: list = field(default_factory=list)
     fit_W: list = field(default_factory=list)   # [t][l] -> (in,out); last is output
     fit_b: list = field(default_factory=list)
+    emb_out_linear: bool = False   # last embedding layer without tanh
 
     @property
     def nnei(self):
@@ -183,10 +185,11 @@ def random_model(ntypes, rcut, rcut_smth, sel, emb=(25, 50, 100), M2=16,
 
 
 def pack_blob(spec: ModelSpec) -> bytes:
-    """Serialise to the DPMIBLOB v1 layout (all little-endian):
+    """Serialise to the DPMIBLOB layout (all little-endian):
 
     8 bytes magic "DPMIBLOB"; int64 version, ntypes, n_emb, n_fit, M2;
-    float64 rcut, rcut_smth, desc_norm; int64 sel[ntypes];
+    version 2 only: int64 emb_out_linear (1 = the last embedding layer is
+    affine, no tanh; version 1 means 0); float64 rcut, rcut_smth, desc_norm; int64 sel[ntypes];
     int64 emb_width[n_emb+1] (emb_width[0] == 1); int64 fit_width[n_fit];
     then float64 arrays: for t, for u, for embedding layer l: W[in][out]
     row-major, b[out]; then for t, for fitting layer l (n_fit hidden layers
@@ -194,7 +197,10 @@ def pack_blob(spec: ModelSpec) -> bytes:
     """
     T = spec.ntypes
     head = BLOB_MAGIC
-    head += struct.pack("<5q", BLOB_VERSION, T, len(spec.emb), len(spec.fit), spec.M2)
+    ver = BLOB_VERSION_LINEAR_OUT if spec.emb_out_linear else BLOB_VERSION
+    head += struct.pack("<5q", ver, T, len(spec.emb), len(spec.fit), spec.M2)
+    if spec.emb_out_linear:
+        head += struct.pack("<q", 1)
     head += struct.pack("<3d", spec.rcut, spec.rcut_smth, spec.desc_norm)
     head += struct.pack(f"<{T}q", *spec.sel)
     head += struct.pack(f"<{len(spec.emb) + 1}q", 1, *spec.emb)
@@ -210,6 +216,55 @@ def pack_blob(spec: ModelSpec) -> bytes:
             parts.append(np.ascontiguousarray(W, dtype="<f8").tobytes())
             parts.append(np.ascontiguousarray(b, dtype="<f8").tobytes())
     return b"".join(parts)
+
+
+STUDENT_H1, STUDENT_H2 = 16, 32
+
+
+def student_np(M1: int) -> int:
+    """Packed parameters per student net: W1[16] b1[16] W2[16][32] b2[32]
+    W3[32][M1] b3[M1]."""
+    return STUDENT_H1 * 2 + STUDENT_H1 * STUDENT_H2 + STUDENT_H2 + STUDENT_H2 * M1 + M1
+
+
+def student_spec(teacher: ModelSpec, params) -> ModelSpec:
+    """The teacher's geometry and fitting nets with student embedding nets
+    1-16-32-M1 (affine last layer) taken from packed parameters
+    params[t*ntypes+u] in the layout of student_np."""
+    import copy
+    T, M1 = teacher.ntypes, teacher.M1
+    P = np.asarray(params, dtype=np.float64).reshape(T * T, student_np(M1))
+    st = copy.deepcopy(teacher)
+    st.emb = (STUDENT_H1, STUDENT_H2, M1)
+    st.emb_out_linear = True
+    h1, h2 = STUDENT_H1, STUDENT_H2
+    cuts = np.cumsum([h1, h1, h1 * h2, h2, h2 * M1, M1])
+    st.emb_W, st.emb_b = [], []
+    for t in range(T):
+        rw, rb = [], []
+        for u in range(T):
+            W1, b1, W2, b2, W3, b3 = np.split(P[t * T + u], cuts[:-1])
+            rw.append([W1.reshape(1, h1), W2.reshape(h1, h2), W3.reshape(h2, M1)])
+            rb.append([b1, b2, b3])
+        st.emb_W.append(rw)
+        st.emb_b.append(rb)
+    return st
+
+
+def random_student_params(teacher: ModelSpec, seed: int, w1_scale: float = 5.0):
+    """Seeded random student parameters [ntypes^2][np] (float32 values):
+    W1 ~ N(0, w1_scale^2), hidden biases N(0,1), W2 and W3 Xavier-normal,
+    b3 N(0, 0.1^2)."""
+    rng = np.random.default_rng(seed)
+    T, M1 = teacher.ntypes, teacher.M1
+    h1, h2 = STUDENT_H1, STUDENT_H2
+    out = []
+    for _ in range(T * T):
+        out.append(np.concatenate([
+            rng.normal(scale=w1_scale, size=h1), rng.normal(size=h1),
+            rng.normal(scale=np.sqrt(2.0 / (h1 + h2)), size=h1 * h2), rng.normal(size=h2),
+            rng.normal(scale=np.sqrt(2.0 / (h2 + M1)), size=h2 * M1), rng.normal(scale=0.1, size=M1)]))
+    return np.array(out).astype(np.float32)
 
 
 # --------------------------------------------------------------------------
