@@ -1,6 +1,14 @@
 #!/usr/bin/env python3
 """Deep Potential MD throughput on one MI355X.
 
+Headline: mixed precision (FP16 matrix-core products) with the student
+embedding net.  The timed region starts with the in-run training of the
+student on the current frame (sampling, teacher targets, Adam, least-squares
+output layer), then runs the MD steps with the student, the full teacher
+nets judging its forces every 20 steps (fallback above 1e-3 eV/A).  The same
+precision without the student, and the FP64 path, are timed after it for
+comparison.
+
 One step = one velocity-Verlet MD step of the whole hot path: periodic wrap,
 device-side skin check (cell list + candidate list rebuilt when an atom has
 moved more than skin/2), formatted neighbour list, environment matrix, fused
@@ -37,10 +45,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic(spec, n_atoms, n_pairs):
+def algorithmic(spec, n_atoms, n_pairs, emb=None):
     """Algorithmic work per evaluation, by kernel (no recompute, no padding):
-    flops for the network kernels, bytes for the list/env kernels."""
-    emb = (1,) + tuple(spec.emb)
+    flops for the network kernels, bytes for the list/env kernels.  `emb`
+    overrides the embedding widths (the student's 16-32-100)."""
+    emb = (1,) + tuple(emb if emb is not None else spec.emb)
     layer_macs = sum(emb[l] * emb[l + 1] for l in range(len(emb) - 1))
     M1, M2 = spec.M1, spec.M2
     fw = (M1 * M2,) + tuple(spec.fit) + (1,)
@@ -86,6 +95,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cu500k")
     ap.add_argument("--precision", default="fp16", choices=["fp64", "fp16", "bf16"])
+    ap.add_argument("--no-student", action="store_true", help="time the teacher nets only")
+    ap.add_argument("--judge-every", type=int, default=20)
+    ap.add_argument("--teacher-steps", type=int, default=5,
+                    help="steps of the same precision without the student, timed for comparison (0 = skip)")
     ap.add_argument("--fp64-steps", type=int, default=3, help="FP64 steps timed for the comparison (0 = skip)")
     ap.add_argument("--rmse-atoms", type=int, default=8, help="atoms sampled for the force RMSE vs the oracle")
     ap.add_argument("--skin", type=float, default=2.0)
@@ -115,7 +128,8 @@ def main():
     spec = w["spec"]
     blob = synth.pack_blob(spec)
     n = len(w["types"])
-    log(f"[bench] workload {args.workload}: {n} atoms, precision {args.precision}")
+    student = not args.no_student
+    log(f"[bench] workload {args.workload}: {n} atoms, precision {args.precision}, student {student}")
     m = DPModel(blob, args.precision)
     dev = m.device
     x = torch.tensor(w["coords"], dtype=torch.float64, device=dev)
@@ -123,25 +137,54 @@ def main():
                      dtype=torch.float64, device=dev)
     t = torch.tensor(w["types"], dtype=torch.int32, device=dev)
     f = torch.zeros((n, 3), dtype=torch.float64, device=dev)
+
+    def md(model, steps, every):
+        return model.md_run(x, v, t, w["box"], w["masses"], w["dt_fs"], steps, skin=args.skin,
+                            thermo_every=every, forces=f)
+
     if args.warmup > 0:
-        m.md_run(x, v, t, w["box"], w["masses"], w["dt_fs"], args.warmup, skin=args.skin,
-                 thermo_every=args.warmup, forces=f)
+        md(m, args.warmup, args.warmup)
+        if student:  # load and run the student kernels once
+            m.student_train(adam_steps=10, ls_samples=8192)
+            m.student_use(True)
+            md(m, 1, 1)
+            m.student_use(False)
     torch.cuda.synchronize()
     log("[bench] warmup done")
+    out_extra = {}
+    if student:
+        m.student_judge(args.judge_every, 1e-3)
     m.enable_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    th = m.md_run(x, v, t, w["box"], w["masses"], w["dt_fs"], args.steps, skin=args.skin,
-                  thermo_every=min(20, args.steps), forces=f)
+    if student:
+        # in-run training on the current frame (its lists are the warmup's last)
+        fit = m.student_train()
+        m.student_use(True)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+    th = md(m, args.steps, min(args.judge_every if student else 20, args.steps))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log("[bench] timed steps done")
     sec = t1 - t0
     s_step = sec / args.steps
+    st = m.stats()
+    if student:
+        out_extra["student"] = {
+            "train_ms": t_train * 1e3, "md_ms_per_step": (sec - t_train) / args.steps * 1e3,
+            "fit_rel_rmse_G": fit, "judge_every": args.judge_every, "judge_max_force_rmse": 1e-3,
+            "last_judge_force_rmse": st["last_judge_rmse"], "teacher_fallbacks": st["teacher_fallbacks"],
+            "student_evals": st["student_evals"],
+            "net": "1-16-32-100 (tanh, tanh + doubling skip, affine) per type pair; Adam 500 x 4096 samples "
+                   "+ FP64 least-squares output layer on 262144 samples, all inside the timed region"}
+        log(f"[bench] student: train {t_train * 1e3:.1f} ms, G rel RMSE {fit:.2e}, judge RMSE "
+            f"{st['last_judge_rmse']:.2e}, fallbacks {st['teacher_fallbacks']}")
     phases = {k: m.timing(k) for k in ("lists", "format", "env", "embed_fwd", "fit", "embed_bwd", "total")}
     _, nr = m.nlist(n, spec.nnei, spec.ntypes, with_list=False)
     n_pairs = float(nr.sum().item())
-    alg = algorithmic(spec, n, n_pairs)
+    used_student = student and st["teacher_fallbacks"] == 0
+    alg = algorithmic(spec, n, n_pairs, emb=(16, 32, spec.M1) if used_student else None)
     kern = max(("format", "env", "embed_fwd", "fit", "embed_bwd"), key=lambda k: phases[k])
     thn = th.cpu().numpy()
     drift = float((thn[-1, 3] - thn[0, 3]) / n) if len(thn) > 1 else 0.0
@@ -153,6 +196,11 @@ def main():
         ach = alg[kern] / (phases[kern] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": ach, "peak": PEAK[pk], "unit": "TFLOP/s", "frac": ach / PEAK[pk]}
     roof.update(kernel=kern, traffic=None)
+    if args.workload.startswith("cu"):
+        wl = (f"{args.workload}: FCC Cu {n} atoms, rc 8 A, sel 512, emb 1-25-50-100, M2 16, fit 240x3, "
+              f"NVE 1 fs, skin {args.skin} A")
+    else:
+        wl = args.workload
     out = {
         "metric": "s/step/atom (E+F+virial), mixed+student vs FP64 at force RMSE <=1e-3 eV/A",
         "value": s_step / n,
@@ -166,16 +214,16 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f16", "bf16": "bf16"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: FCC Cu {n} atoms, rc 8 A, sel 512, emb 1-25-50-100, M2 16, "
-                               f"fit 240x3, NVE 1 fs, skin {args.skin} A" if args.workload.startswith("cu")
-                   else args.workload,
-                   "precision": args.precision, "atoms": n, "real_pairs": int(n_pairs)},
+        "config": {"workload": wl, "precision": args.precision,
+                   "student": "1-16-32-100, trained in the timed region" if student else "none",
+                   "atoms": n, "real_pairs": int(n_pairs)},
         "ns_per_day": w["dt_fs"] * 86400e-6 / s_step,
         "phase_ms": {k: round(v, 4) for k, v in phases.items()},
         "energy_drift_eV_per_atom": drift,
         "roofline": roof,
     }
-    # force accuracy of the timed precision at the final MD frame, on sampled atoms
+    out.update(out_extra)
+    # force accuracy of the timed path at the final MD frame, on sampled atoms
     if args.rmse_atoms > 0:
         from oracle import oracle as O
         e_m, f_m, _ = m.compute(x, t, w["box"])
@@ -193,8 +241,20 @@ def main():
             ref.append(r["force"][k])
         out["force_rmse_vs_oracle"] = float(np.sqrt((np.array(err) ** 2).sum(1).mean()))
         out["force_rms"] = float(np.sqrt((np.array(ref) ** 2).sum(1).mean()))
-        out["force_rmse_sample"] = f"{args.rmse_atoms} random atoms of the final MD frame, oracle local evaluation"
+        out["force_rmse_sample"] = (f"{args.rmse_atoms} random atoms of the final MD frame, "
+                                    f"{'student' if used_student else 'teacher'} nets vs the oracle's teacher")
         log(f"[bench] force RMSE vs oracle {out['force_rmse_vs_oracle']:.3e} eV/A")
+    if args.precision != "fp64" and args.teacher_steps > 0:
+        m.student_use(False)
+        m.enable_timing(False)
+        md(m, 1, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        md(m, args.teacher_steps, args.teacher_steps)
+        torch.cuda.synchronize()
+        sT = (time.perf_counter() - t0) / args.teacher_steps
+        out["mixed_teacher_s_per_step_atom"] = sT / n
+        log(f"[bench] mixed teacher {sT * 1e3:.1f} ms/step")
     if args.precision != "fp64" and args.fp64_steps > 0:
         m64 = DPModel(blob, "fp64")
         f64 = torch.zeros((n, 3), dtype=torch.float64, device=dev)
@@ -209,7 +269,10 @@ def main():
         out["fp64_s_per_step_atom"] = s64 / n
         out["speedup_vs_fp64"] = s64 / s_step
         log(f"[bench] fp64 {s64 * 1e3:.1f} ms/step")
-    if not args.no_cpu_baseline:    print(json.dumps(out), flush=True)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, blob, args.cpu_seconds, log)
+        out["cpu_baseline"]["gpu_over_cpu"] = out["cpu_baseline"]["value"] / out["value"]
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

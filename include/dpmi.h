@@ -80,9 +80,11 @@ typedef struct {
  * (NULL = the null stream).  *out receives the context. */
 int dp_create(dp_ctx **out, int device, void *hip_stream);
 
-/* Load a model blob (host memory, `nbytes` bytes, layout DPMIBLOB v1: magic,
- * int64 version/ntypes/n_emb/n_fit/M2, float64 rcut/rcut_smth/desc_norm,
- * int64 sel[ntypes], emb widths, fit widths, then float64 weights) and keep
+/* Load a model blob (host memory, `nbytes` bytes, layout DPMIBLOB: magic,
+ * int64 version/ntypes/n_emb/n_fit/M2, version 2 only: int64 emb_out_linear
+ * (1 = the last embedding layer is affine), float64 rcut/rcut_smth/
+ * desc_norm, int64 sel[ntypes], emb widths, fit widths, then float64
+ * weights) and keep
  * it on the device in `precision` (DP_FP64 ...).  The blob may be freed
  * after the call.  The descriptor is D = T T_<^T with
  * T = (1/desc_norm) sum_j G(s_j) R_j^T (Fig. 1(b)); one embedding net per
@@ -163,6 +165,90 @@ int dp_md_run(dp_ctx *c, int64_t natoms, double *coords, double *vel, const int3
  * "total" (whole evaluation). */
 int dp_enable_timing(dp_ctx *c, int on);
 int dp_get_timing(dp_ctx *c, const char *name, double *ms);
+
+/* ---------------------------------------------------------------------
+ * Student embedding net (not in the paper: a smaller stand-in for the
+ * embedding nets of Fig. 1(e,f), checked against the full nets while MD
+ * runs).  Per (centre type, neighbour type) pair the student is
+ * 1 -> 16 (tanh) -> 32 (tanh, doubling skip) -> M1 (affine), and it feeds
+ * the teacher's descriptor and fitting net unchanged.  dp_student_train
+ * fits it to the teacher's own G(s) on neighbour distances of the last
+ * evaluated configuration:
+ *   samples  uniform over the real (centre, neighbour) pairs of each type
+ *            pair: attempt a of sample q of net n = t*ntypes+u draws
+ *            x = SplitMix64 output number ((n*2^40 + q)*32 + a) of the
+ *            stream seeded with `seed`; centre = atom number
+ *            (x>>32)*count_t>>32 of type t (atoms of a type in index
+ *            order), slot = (x & 0xffffffff)*sel_u>>32; kept when the
+ *            slot holds a real neighbour (else the next attempt; after 32
+ *            the sample has weight 0).  Adam batch k uses q = k*batch ..;
+ *            the least squares q = 2^36 + ..; the held-out check q = 2^37 + ..
+ *   loss     mean over samples and the M1 outputs of (G_s - G_t)^2, the
+ *            teacher's G_t in FP64
+ *   Adam     (Kingma and Ba, 2015) in FP32, bias-corrected, constant lr
+ *   refit    exact least squares of the affine output layer on the hidden
+ *            features (h2, 1): FP64 normal equations + ridge * trace/33 on
+ *            the diagonal, Cholesky.  Under DP_MIX_* the W2 used for the
+ *            features and the solved W3 are rounded to the 16-bit format of
+ *            the kernels, and b3 takes the mean residual.
+ * ------------------------------------------------------------------- */
+typedef struct {
+  int64_t batch;       /* samples per net per Adam step, a multiple of 64 (4096)  */
+  int64_t adam_steps;  /* Adam steps (500: 2M samples at batch 4096)               */
+  double lr, beta1, beta2, eps; /* 1e-3, 0.9, 0.999, 1e-8                          */
+  int64_t ls_samples;  /* samples per net for the refit, multiple of batch (262144) */
+  double ridge;        /* relative ridge of the normal equations (1e-14)           */
+  uint64_t seed;       /* sampler and initialisation seed                          */
+  int32_t init;        /* 1: fresh initialisation; 0: continue from the current
+                          parameters (dp_student_set_params or an earlier call)    */
+  int32_t refit;       /* 1: least-squares refit and install the student           */
+} dp_student_cfg;
+
+/* Fill *cfg with the defaults listed above. */
+int dp_student_default_cfg(dp_student_cfg *cfg);
+
+/* Train on the configuration of the last evaluation (dp_compute, dp_energy
+ * or the final frame of dp_md_run) and, when cfg->refit, install the
+ * student (it is used once dp_student_use(c, 1) is called).
+ * fit_rmse (host, may be NULL) receives the relative RMSE of G against the
+ * teacher on 4096 held-out samples per net (sqrt(sum err^2 / sum G_t^2),
+ * worst net), or the last Adam loss when cfg->refit is 0.  The student's
+ * mixed-precision kernels exist for M1 = 100 only (DP_E_MODEL otherwise). */
+int dp_student_train(dp_ctx *c, const dp_student_cfg *cfg, double *fit_rmse);
+
+/* FP32 training parameters, [ntypes^2][np] with np = 16+16+16*32+32+32*M1+M1
+ * per net laid out W1[16] b1[16] W2[16][32] b2[32] W3[32][M1] b3[M1]
+ * (row = input feature); host memory.  set resets the Adam moments. */
+int dp_student_get_params(dp_ctx *c, float *params);
+int dp_student_set_params(dp_ctx *c, const float *params);
+
+/* Loss and gradient of one Adam batch (`step` = k above, seed as given) at
+ * the current parameters, without updating them.  Host outputs, any may be
+ * NULL: s [ntypes^2][batch] sampled inputs (0 where the weight is 0),
+ * loss [ntypes^2] (mean squared error per net), grad [ntypes^2][np]. */
+int dp_student_batch_grad(dp_ctx *c, uint64_t seed, int64_t step, int64_t batch, double *s, double *loss,
+                          float *grad);
+
+/* Evaluations (dp_compute, dp_energy, dp_md_run) use the student (on = 1)
+ * or the teacher (0).  DP_E_NOMODEL when no student is installed. */
+int dp_student_use(dp_ctx *c, int on);
+
+/* MD judge: while the student is in use, dp_md_run also evaluates the
+ * teacher every `every` steps (0 = never) on the same configuration and
+ * computes the force RMSE sqrt(mean_i |F_s,i - F_t,i|^2); above
+ * max_force_rmse (eV/A) the run takes the teacher's forces for that step
+ * and uses the teacher for the rest of the run (stats.teacher_fallbacks).
+ * Defaults: every 20 steps, 1e-3 eV/A. */
+int dp_student_judge(dp_ctx *c, int64_t every, double max_force_rmse);
+
+/* The installed student as a model blob (DPMIBLOB version 2: the student
+ * embedding nets with an affine last layer, the teacher's fitting nets):
+ * writes min(cap, size) bytes to buf (host, may be NULL) and the size to
+ * *nbytes.  dp_student_set_model installs a student from such a blob; its
+ * ntypes, rcut, rcut_smth, desc_norm, sel, M2 and fitting nets must match
+ * the teacher's and its embedding must be 1-16-32-M1 affine. */
+int dp_student_get_model(dp_ctx *c, void *buf, size_t cap, size_t *nbytes);
+int dp_student_set_model(dp_ctx *c, const void *blob, size_t nbytes);
 
 const char *dp_last_error(const dp_ctx *c);
 void dp_destroy(dp_ctx *c);

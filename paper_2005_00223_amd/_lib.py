@@ -18,13 +18,21 @@ PRECISION = {"fp64": DP_FP64, "fp16": DP_MIX_FP16, "bf16": DP_MIX_BF16}
 EXPORTS = ("dp_create", "dp_set_model", "dp_set_precision", "dp_compute", "dp_energy", "dp_energy_backward",
            "dp_get_nlist", "dp_keep_intermediates",
            "dp_get_intermediates", "dp_get_stats", "dp_md_run", "dp_enable_timing", "dp_get_timing",
-           "dp_last_error", "dp_destroy")
+           "dp_student_default_cfg", "dp_student_train", "dp_student_get_params", "dp_student_set_params",
+           "dp_student_batch_grad", "dp_student_use", "dp_student_judge", "dp_student_get_model",
+           "dp_student_set_model", "dp_last_error", "dp_destroy")
 
 
 class dp_stats(C.Structure):
     _fields_ = [("natoms", C.c_int64), ("sel_overflow", C.c_int64), ("max_real", C.c_int32 * 8),
                 ("nlist_builds", C.c_int64), ("evaluations", C.c_int64), ("cand_cap", C.c_int64),
                 ("student_evals", C.c_int64), ("teacher_fallbacks", C.c_int64), ("last_judge_rmse", C.c_double)]
+
+
+class dp_student_cfg(C.Structure):
+    _fields_ = [("batch", C.c_int64), ("adam_steps", C.c_int64), ("lr", C.c_double), ("beta1", C.c_double),
+                ("beta2", C.c_double), ("eps", C.c_double), ("ls_samples", C.c_int64), ("ridge", C.c_double),
+                ("seed", C.c_uint64), ("init", C.c_int32), ("refit", C.c_int32)]
 
 
 class DPError(RuntimeError):
@@ -61,6 +69,15 @@ def lib():
         "dp_md_run": (I32, [P, I64, P, P, P, P, P, D, D, I64, I64, P, P]),
         "dp_enable_timing": (I32, [P, I32]),
         "dp_get_timing": (I32, [P, C.c_char_p, C.POINTER(D)]),
+        "dp_student_default_cfg": (I32, [C.POINTER(dp_student_cfg)]),
+        "dp_student_train": (I32, [P, C.POINTER(dp_student_cfg), C.POINTER(D)]),
+        "dp_student_get_params": (I32, [P, P]),
+        "dp_student_set_params": (I32, [P, P]),
+        "dp_student_batch_grad": (I32, [P, C.c_uint64, I64, I64, P, P, P]),
+        "dp_student_use": (I32, [P, I32]),
+        "dp_student_judge": (I32, [P, I64, D]),
+        "dp_student_get_model": (I32, [P, P, C.c_size_t, C.POINTER(C.c_size_t)]),
+        "dp_student_set_model": (I32, [P, C.c_char_p, C.c_size_t]),
         "dp_last_error": (C.c_char_p, [P]),
         "dp_destroy": (None, [P]),
     }
@@ -143,6 +160,50 @@ def dp_get_timing(ctx, name: str) -> float:
     v = C.c_double()
     check(ctx, lib().dp_get_timing(ctx, name.encode(), C.byref(v)))
     return v.value
+
+
+def dp_student_default_cfg() -> dp_student_cfg:
+    cfg = dp_student_cfg()
+    lib().dp_student_default_cfg(C.byref(cfg))
+    return cfg
+
+
+def dp_student_train(ctx, cfg: dp_student_cfg) -> float:
+    r = C.c_double()
+    check(ctx, lib().dp_student_train(ctx, C.byref(cfg), C.byref(r)))
+    return r.value
+
+
+def dp_student_get_params(ctx, out_ptr):
+    return check(ctx, lib().dp_student_get_params(ctx, out_ptr))
+
+
+def dp_student_set_params(ctx, in_ptr):
+    return check(ctx, lib().dp_student_set_params(ctx, in_ptr))
+
+
+def dp_student_batch_grad(ctx, seed, step, batch, s_ptr, loss_ptr, grad_ptr):
+    return check(ctx, lib().dp_student_batch_grad(ctx, int(seed), int(step), int(batch), s_ptr, loss_ptr, grad_ptr))
+
+
+def dp_student_use(ctx, on: bool):
+    return check(ctx, lib().dp_student_use(ctx, int(bool(on))))
+
+
+def dp_student_judge(ctx, every: int, max_force_rmse: float):
+    return check(ctx, lib().dp_student_judge(ctx, int(every), float(max_force_rmse)))
+
+
+def dp_student_get_model(ctx) -> bytes:
+    n = C.c_size_t()
+    check(ctx, lib().dp_student_get_model(ctx, None, 0, C.byref(n)))
+    buf = C.create_string_buffer(n.value)
+    check(ctx, lib().dp_student_get_model(ctx, buf, n.value, C.byref(n)))
+    return buf.raw[:n.value]
+
+
+def dp_student_set_model(ctx, blob: bytes):
+    return check(ctx, lib().dp_student_set_model(ctx, blob, len(blob)))
 
 
 def dp_destroy(ctx):

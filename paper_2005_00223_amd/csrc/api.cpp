@@ -11,6 +11,7 @@
 
 #include "dp_internal.h"
 #include "dp_mix.h"
+#include "dp_student.h"
 #include "dpmi.h"
 
 using namespace dpk;
@@ -29,6 +30,7 @@ constexpr double KB_EV = 8.617333262e-5;
 // ---------------------------------------------------------------------------
 struct HostModel {
   int64_t ntypes = 0, n_emb = 0, n_fit = 0, M2 = 0;
+  int64_t emb_lin = 0;  // 1: affine last embedding layer
   double rcut = 0, rcut_smth = 0, desc_norm = 1;
   std::vector<int64_t> sel, emb_w, fit_w;  // emb_w[0..n_emb], fit_w[0..n_fit+1]
   std::vector<std::vector<double>> eW, eb, fW, fb;
@@ -63,8 +65,11 @@ bool parse_blob(const void *blob, size_t nbytes, HostModel &m, std::string &err)
   char magic[8];
   int64_t version = 0;
   if (!r.bytes(magic, 8) || std::memcmp(magic, "DPMIBLOB", 8) != 0) return err = "blob: bad magic", false;
-  if (!r.i64(version) || version != 1) return err = "blob: unsupported version", false;
+  if (!r.i64(version) || (version != 1 && version != 2)) return err = "blob: unsupported version", false;
   if (!r.i64(m.ntypes) || !r.i64(m.n_emb) || !r.i64(m.n_fit) || !r.i64(m.M2)) return err = "blob: truncated header", false;
+  m.emb_lin = 0;
+  if (version == 2 && (!r.i64(m.emb_lin) || (m.emb_lin != 0 && m.emb_lin != 1)))
+    return err = "blob: bad emb_out_linear flag", false;
   if (m.ntypes < 1 || m.ntypes > MAXT) return err = "blob: ntypes must be 1..8", false;
   if (m.n_emb < 2 || m.n_emb > MAXL) return err = "blob: embedding depth must be 2..4", false;
   if (m.n_fit < 1 || m.n_fit > MAXF) return err = "blob: fitting depth must be 1..4", false;
@@ -111,6 +116,7 @@ struct DevStatus {
   unsigned long long overflow;
   int32_t max_real[MAXT];
   unsigned long long nbuild;
+  double judge_rmse;  // force RMSE of the last student judge
 };
 
 struct Workspace {
@@ -124,6 +130,8 @@ struct Workspace {
       *atom_of_pos, *blk_counts, *type_count, *type_start;
   double *T, *D, *dD, *Y[MAXF + 1], *Tt[MAXF + 1], *G[MAXF + 1], *eatom, *partial, *vir_part, *force_tmp,
       *net_deriv, *energy, *virial, *ke;
+  // student judge: teacher forces / energy / virial, RMSE partial sums
+  double *force_j, *energy_j, *virial_j, *rmse_part;
   // mixed-precision buffers
   float *T32, *D32, *dD32, *Yf[MAXF + 1], *Ttf[MAXF + 1], *Gf[MAXF + 1];
   int prec = -1;  // precision the buffers were laid out for
@@ -132,20 +140,48 @@ struct Workspace {
 
 }  // namespace
 
+// Student training state (buffers for one Adam batch per net).
+struct Student {
+  int nets = 0, M1 = 0, np = 0;
+  int64_t cap = 0;  // samples per net the buffers hold
+  void *base = nullptr;
+  float *params = nullptr, *m = nullptr, *v = nullptr, *gpart = nullptr, *wt = nullptr, *gout = nullptr;
+  double *lpart = nullptr, *s = nullptr, *G = nullptr, *lspart = nullptr, *X = nullptr, *chk = nullptr,
+         *loss = nullptr;
+  int32_t *status = nullptr;
+  bool have_params = false;
+  int64_t t = 0;  // Adam steps taken since initialisation
+};
+
+// One set of embedding nets (the teacher's, or the student's) on the device.
+struct EmbNets {
+  Dims d{};                         // model dims with this set's embedding widths
+  EmbOffsets eo{};
+  double *d_emb = nullptr;          // FP64 padded weights
+  unsigned char *d_mix = nullptr;   // mixed-precision LDS images
+  int mix_shape = -1;
+  bool ready = false;
+};
+
 struct dp_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool has_model = false;
   int precision = DP_FP64;
-  HostModel hm;
-  Dims dims{};
-  EmbOffsets eo{};
+  HostModel hm;                     // teacher
+  Dims dims{};                      // teacher dims (geometry, fitting net)
   FitOffsets fo{};
-  double *d_emb = nullptr, *d_fit = nullptr;
-  // mixed-precision weights (16-bit MFMA operands + f32)
-  unsigned char *d_mix_nets = nullptr, *d_fit_mix = nullptr;
+  double *d_fit = nullptr;
+  // mixed-precision fitting weights (16-bit MFMA operands + f32)
+  unsigned char *d_fit_mix = nullptr;
   FitMixOffsets fmo{};
-  int mix_shape = -1, n16 = 0;
+  int n16 = 0;
+  EmbNets en[2];                    // [0] teacher, [1] student
+  int active = 0;                   // embedding set used by evaluations
+  HostModel shm;                    // student (embedding part; fitting = teacher's)
+  Student *st = nullptr;            // student training state
+  int64_t judge_every = 20;         // MD judge period (0 = off)
+  double judge_max = 1e-3;          // eV/A
   Workspace ws;
   DevStatus *h_status = nullptr;  // pinned
   dp_stats stats{};
@@ -175,6 +211,13 @@ int fail(dp_ctx *c, int code, const std::string &msg) {
 void free_ws(Workspace &w) {
   if (w.base) (void)hipFree(w.base);
   w = Workspace{};
+}
+
+void free_student(dp_ctx *c) {
+  if (!c->st) return;
+  if (c->st->base) (void)hipFree(c->st->base);
+  delete c->st;
+  c->st = nullptr;
 }
 
 // Carve every buffer out of one allocation.  Sizes depend on n (atoms),
@@ -243,6 +286,10 @@ int ensure_ws(dp_ctx *c, int64_t n, int64_t ncell, int cand_cap) {
   add((void **)&w.energy, sizeof(double) * 8);
   add((void **)&w.virial, sizeof(double) * 16);
   add((void **)&w.ke, sizeof(double) * 8);
+  add((void **)&w.force_j, sizeof(double) * 3 * nn);
+  add((void **)&w.energy_j, sizeof(double) * 8);
+  add((void **)&w.virial_j, sizeof(double) * 16);
+  add((void **)&w.rmse_part, sizeof(double) * 256);
   add((void **)&w.status, sizeof(DevStatus));
   for (auto &pr : plan) off += (pr.second + 255) / 256 * 256;
   void *base = nullptr;
@@ -272,12 +319,69 @@ int ensure_ws(dp_ctx *c, int64_t n, int64_t ncell, int cand_cap) {
 // ---------------------------------------------------------------------------
 // device model
 // ---------------------------------------------------------------------------
+// Embedding dims of model m on top of the teacher dims c->dims.
+int emb_dims(dp_ctx *c, const HostModel &m, Dims &d) {
+  d = c->dims;
+  d.n_emb = (int)m.n_emb;
+  d.emb_lin = (int)m.emb_lin;
+  for (int l = 0; l <= MAXL; ++l) d.ew[l] = d.ekp[l] = d.emp[l] = 0;
+  for (int l = 0; l <= d.n_emb; ++l) {
+    d.ew[l] = (int)m.emb_w[l];
+    d.ekp[l] = rup(d.ew[l], 4);
+    d.emp[l] = rup(d.ew[l], 16);
+  }
+  if (d.ew[d.n_emb] != d.M1) return fail(c, DP_E_MODEL, "embedding output width must equal M1");
+  for (int l = 1; l <= d.n_emb; ++l)
+    if (d.emp[l] > 128) return fail(c, DP_E_MODEL, "embedding widths above 128 are not supported");
+  if (dpk::embed_lds_bytes(d, 1) > 65536 || dpk::embed_lds_bytes(d, 2) > 65536)
+    return fail(c, DP_E_MODEL, "embedding net too wide for the per-wave LDS tiles");
+  return DP_OK;
+}
+
+// FP64 padded embedding weights of model m into en.
+int upload_emb(dp_ctx *c, const HostModel &m, EmbNets &en) {
+  int rc = emb_dims(c, m, en.d);
+  if (rc) return rc;
+  const Dims &d = en.d;
+  std::vector<double> E;
+  const int T = d.ntypes;
+  for (int t = 0; t < T; ++t)
+    for (int u = 0; u < T; ++u)
+      for (int l = 0; l < d.n_emb; ++l) {
+        const auto &W = m.eW[m.eidx(t, u, l)];
+        const auto &b = m.eb[m.eidx(t, u, l)];
+        const int in = d.ew[l], out = d.ew[l + 1];
+        if (l == 0) {
+          const int kp = d.ekp[1];
+          en.eo.w[t][u][0] = (int64_t)E.size();
+          E.resize(E.size() + kp, 0.0);
+          for (int o = 0; o < out; ++o) E[en.eo.w[t][u][0] + o] = W[o];
+          en.eo.b[t][u][0] = (int64_t)E.size();
+          E.resize(E.size() + kp, 0.0);
+          for (int o = 0; o < out; ++o) E[en.eo.b[t][u][0] + o] = b[o];
+        } else {
+          const int kp = d.ekp[l], mp = d.emp[l + 1];
+          en.eo.w[t][u][l] = (int64_t)E.size();
+          E.resize(E.size() + (size_t)kp * mp, 0.0);
+          for (int i = 0; i < in; ++i)
+            for (int o = 0; o < out; ++o) E[en.eo.w[t][u][l] + (size_t)i * mp + o] = W[(size_t)i * out + o];
+          en.eo.b[t][u][l] = (int64_t)E.size();
+          E.resize(E.size() + mp, 0.0);
+          for (int o = 0; o < out; ++o) E[en.eo.b[t][u][l] + o] = b[o];
+        }
+      }
+  if (en.d_emb) (void)hipFree(en.d_emb);
+  en.d_emb = nullptr;
+  HIPCHK(c, hipMalloc(&en.d_emb, sizeof(double) * E.size()));
+  HIPCHK(c, hipMemcpy(en.d_emb, E.data(), sizeof(double) * E.size(), hipMemcpyHostToDevice));
+  return DP_OK;
+}
+
 int upload_model(dp_ctx *c) {
   const HostModel &m = c->hm;
   Dims &d = c->dims;
   d = Dims{};
   d.ntypes = (int)m.ntypes;
-  d.n_emb = (int)m.n_emb;
   d.n_fit = (int)m.n_fit;
   d.M1 = (int)m.emb_w[m.n_emb];
   d.M2 = (int)m.M2;
@@ -290,49 +394,23 @@ int upload_model(dp_ctx *c) {
     d.off[t + 1] = d.off[t] + d.sel[t];
   }
   d.nnei = d.off[d.ntypes];
-  for (int l = 0; l <= d.n_emb; ++l) {
-    d.ew[l] = (int)m.emb_w[l];
-    d.ekp[l] = rup(d.ew[l], 4);
-    d.emp[l] = rup(d.ew[l], 16);
-  }
   for (int l = 0; l <= d.n_fit + 1; ++l) d.fw[l] = (int)m.fit_w[l];
   if (d.M2 < 1 || d.M2 > 16 || d.M2 > d.M1) return fail(c, DP_E_MODEL, "M2 must be 1..16 and <= M1");
-  for (int l = 1; l <= d.n_emb; ++l)
-    if (d.emp[l] > 128) return fail(c, DP_E_MODEL, "embedding widths above 128 are not supported");
   if (!(d.rcut > 0 && d.rcut < 42.9)) return fail(c, DP_E_MODEL, "rcut must lie in (0, 42.9) A");
   if (!(d.rcut_smth >= 0 && d.rcut_smth < d.rcut)) return fail(c, DP_E_MODEL, "need 0 <= rcut_smth < rcut");
   if (!(m.desc_norm > 0)) return fail(c, DP_E_MODEL, "desc_norm must be positive");
   if (d.nnei < 1) return fail(c, DP_E_MODEL, "sum of sel must be positive");
-  if (dpk::embed_lds_bytes(d, 1) > 65536 || dpk::embed_lds_bytes(d, 2) > 65536)
-    return fail(c, DP_E_MODEL, "embedding net too wide for the per-wave LDS tiles");
-  // embedding weights, padded
-  std::vector<double> E;
+  // embedding dims are kept in c->dims too (the teacher's)
+  {
+    Dims e;
+    int rc = emb_dims(c, m, e);
+    if (rc) return rc;
+    d = e;
+  }
+  int rc = upload_emb(c, m, c->en[0]);
+  if (rc) return rc;
+  c->en[0].ready = true;
   const int T = d.ntypes;
-  for (int t = 0; t < T; ++t)
-    for (int u = 0; u < T; ++u)
-      for (int l = 0; l < d.n_emb; ++l) {
-        const auto &W = m.eW[m.eidx(t, u, l)];
-        const auto &b = m.eb[m.eidx(t, u, l)];
-        const int in = d.ew[l], out = d.ew[l + 1];
-        if (l == 0) {
-          const int kp = d.ekp[1];
-          c->eo.w[t][u][0] = (int64_t)E.size();
-          E.resize(E.size() + kp, 0.0);
-          for (int o = 0; o < out; ++o) E[c->eo.w[t][u][0] + o] = W[o];
-          c->eo.b[t][u][0] = (int64_t)E.size();
-          E.resize(E.size() + kp, 0.0);
-          for (int o = 0; o < out; ++o) E[c->eo.b[t][u][0] + o] = b[o];
-        } else {
-          const int kp = d.ekp[l], mp = d.emp[l + 1];
-          c->eo.w[t][u][l] = (int64_t)E.size();
-          E.resize(E.size() + (size_t)kp * mp, 0.0);
-          for (int i = 0; i < in; ++i)
-            for (int o = 0; o < out; ++o) E[c->eo.w[t][u][l] + (size_t)i * mp + o] = W[(size_t)i * out + o];
-          c->eo.b[t][u][l] = (int64_t)E.size();
-          E.resize(E.size() + mp, 0.0);
-          for (int o = 0; o < out; ++o) E[c->eo.b[t][u][l] + o] = b[o];
-        }
-      }
   std::vector<double> F;
   for (int t = 0; t < T; ++t)
     for (int l = 0; l <= d.n_fit; ++l) {
@@ -343,12 +421,9 @@ int upload_model(dp_ctx *c) {
       const auto &b = m.fb[m.fidx(t, l)];
       F.insert(F.end(), b.begin(), b.end());
     }
-  if (c->d_emb) (void)hipFree(c->d_emb);
   if (c->d_fit) (void)hipFree(c->d_fit);
-  c->d_emb = c->d_fit = nullptr;
-  HIPCHK(c, hipMalloc(&c->d_emb, sizeof(double) * E.size()));
+  c->d_fit = nullptr;
   HIPCHK(c, hipMalloc(&c->d_fit, sizeof(double) * F.size()));
-  HIPCHK(c, hipMemcpy(c->d_emb, E.data(), sizeof(double) * E.size(), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_fit, F.data(), sizeof(double) * F.size(), hipMemcpyHostToDevice));
   return DP_OK;
 }
@@ -369,17 +444,16 @@ uint16_t h16_bits(double v, int prec) {
   return (uint16_t)(u >> 16);
 }
 
-int upload_mix(dp_ctx *c) {
-  const HostModel &m = c->hm;
-  const Dims &d = c->dims;
+// Mixed-precision LDS images of the embedding nets of m into en.
+int upload_emb_mix(dp_ctx *c, const HostModel &m, EmbNets &en) {
+  const Dims &d = en.d;
   const int prec = c->precision == DP_MIX_FP16 ? 0 : 1;
   const int shape = mix_shape_id(d);
-  if (shape < 0) return fail(c, DP_E_MODEL, "mixed precision supports embedding widths 25-50-100 and 16-32-100");
+  if (shape < 0)
+    return fail(c, DP_E_MODEL,
+                "mixed precision supports embedding widths 25-50-100 and 16-32-100 (tanh or affine last layer)");
   if (mix_lds_bytes(shape, d.ntypes, 2) > 163840 || mix_lds_bytes(shape, d.ntypes, 1) > 163840)
     return fail(c, DP_E_MODEL, "too many atom types for the mixed-precision LDS layout");
-  const int n16 = std::min(2, d.n_fit);
-  for (int l = 0; l <= n16; ++l)
-    if (d.fw[l] % 8 != 0) return fail(c, DP_E_MODEL, "16-bit fitting layers need widths divisible by 8");
   const size_t nb = mix_net_bytes(shape);
   const int T = d.ntypes;
   std::vector<unsigned char> nets(nb * T * T);
@@ -392,6 +466,28 @@ int upload_mix(dp_ctx *c) {
       }
       mix_pack_net(shape, W, b, prec, nets.data() + (size_t)(t * T + u) * nb);
     }
+  if (en.d_mix) (void)hipFree(en.d_mix);
+  en.d_mix = nullptr;
+  HIPCHK(c, hipMalloc(&en.d_mix, nets.size()));
+  HIPCHK(c, hipMemcpy(en.d_mix, nets.data(), nets.size(), hipMemcpyHostToDevice));
+  en.mix_shape = shape;
+  return DP_OK;
+}
+
+int upload_mix(dp_ctx *c) {
+  const HostModel &m = c->hm;
+  const Dims &d = c->dims;
+  const int prec = c->precision == DP_MIX_FP16 ? 0 : 1;
+  const int n16 = std::min(2, d.n_fit);
+  for (int l = 0; l <= n16; ++l)
+    if (d.fw[l] % 8 != 0) return fail(c, DP_E_MODEL, "16-bit fitting layers need widths divisible by 8");
+  int rc = upload_emb_mix(c, m, c->en[0]);
+  if (rc) return rc;
+  if (c->en[1].ready) {
+    rc = upload_emb_mix(c, c->shm, c->en[1]);
+    if (rc) return rc;
+  }
+  const int T = d.ntypes;
   std::vector<unsigned char> F;
   auto align = [&]() { F.resize((F.size() + 255) / 256 * 256, 0); };
   FitMixOffsets fo{};
@@ -424,15 +520,11 @@ int upload_mix(dp_ctx *c) {
       float *b32 = (float *)(F.data() + fo.b32[t][l]);
       for (int o = 0; o < out; ++o) b32[o] = (float)bb[o];
     }
-  if (c->d_mix_nets) (void)hipFree(c->d_mix_nets);
   if (c->d_fit_mix) (void)hipFree(c->d_fit_mix);
-  c->d_mix_nets = c->d_fit_mix = nullptr;
-  HIPCHK(c, hipMalloc(&c->d_mix_nets, nets.size()));
+  c->d_fit_mix = nullptr;
   HIPCHK(c, hipMalloc(&c->d_fit_mix, F.size()));
-  HIPCHK(c, hipMemcpy(c->d_mix_nets, nets.data(), nets.size(), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(c->d_fit_mix, F.data(), F.size(), hipMemcpyHostToDevice));
   c->fmo = fo;
-  c->mix_shape = shape;
   c->n16 = n16;
   return DP_OK;
 }
@@ -485,10 +577,11 @@ inline void tnext(dp_ctx *c) {
 // Arguments of the embedding / fitting launches for the loaded policy.
 EmbedArgs embed_args(dp_ctx *c, int64_t n, int64_t rows, double *F) {
   Workspace &w = c->ws;
+  const EmbNets &en = c->en[c->active];
   EmbedArgs ea{};
-  ea.d = c->dims;
-  ea.eo = c->eo;
-  ea.ew = c->d_emb;
+  ea.d = en.d;
+  ea.eo = en.eo;
+  ea.ew = en.d_emb;
   ea.atom_of_pos = w.atom_of_pos;
   ea.pos_of_atom = w.pos_of_atom;
   ea.type_start = w.type_start;
@@ -529,11 +622,12 @@ FitArgs fit_args(dp_ctx *c, int64_t rows) {
 
 MixArgs mix_args(dp_ctx *c, int64_t rows, double *F) {
   Workspace &w = c->ws;
+  const EmbNets &en = c->en[c->active];
   MixArgs ma{};
-  ma.d = c->dims;
-  ma.shape = c->mix_shape;
+  ma.d = en.d;
+  ma.shape = en.mix_shape;
   ma.prec = c->precision == DP_MIX_FP16 ? 0 : 1;
-  ma.nets = c->d_mix_nets;
+  ma.nets = en.d_mix;
   ma.rows = rows;
   ma.atom_of_pos = w.atom_of_pos;
   ma.xw = w.xw;
@@ -575,20 +669,25 @@ int64_t eval_rows(const dp_ctx *c, int64_t n) {
   return (n + ROW_TILE - 1) / ROW_TILE * ROW_TILE + (int64_t)ROW_TILE * c->dims.ntypes;
 }
 
-// Forward half of an evaluation: formatted list, environment matrix,
-// embedding + descriptor, fitting net forward, energy.  Leaves everything
-// the backward half needs in the workspace.
-void eval_forward(dp_ctx *c, int64_t n, const double L[3]) {
+// Formatted neighbour list and environment matrix of the current frame.
+void eval_lists(dp_ctx *c, int64_t n, const double L[3]) {
   Workspace &w = c->ws;
   const Dims &d = c->dims;
   hipStream_t s = c->stream;
-  const int64_t rows = eval_rows(c, n);
   tmark(c, 1);
   launch_format(s, n, w.xw, d, L, w.cand, w.cand_n, w.cand_cap, w.nlist, w.nreal, &w.status->overflow,
                 w.status->max_real, &w.status->flags);
   tmark(c, 2);
   launch_env(s, n, w.xw, d, L, w.nlist, w.nreal, w.rt, w.dr);
   tmark(c, 3);
+}
+
+// Networks of the forward half with the active embedding set: embedding +
+// descriptor, fitting net forward, energy into E.
+void eval_nets_fwd(dp_ctx *c, int64_t n, double *E) {
+  Workspace &w = c->ws;
+  hipStream_t s = c->stream;
+  const int64_t rows = eval_rows(c, n);
   if (c->precision == DP_FP64) {
     launch_embed_fwd_f64(s, embed_args(c, n, rows, nullptr));
     tmark(c, 4);
@@ -598,12 +697,20 @@ void eval_forward(dp_ctx *c, int64_t n, const double L[3]) {
     tmark(c, 4);
     launch_fit_mix(s, fitmix_args(c, rows), 1);
   }
-  launch_sum(s, w.eatom, n, w.partial, w.energy, 1.0);
+  launch_sum(s, w.eatom, n, w.partial, E, 1.0);
+  if (c->active == 1) c->stats.student_evals += 1;
+}
+
+// Forward half of an evaluation.  Leaves everything the backward half
+// needs in the workspace.
+void eval_forward(dp_ctx *c, int64_t n, const double L[3]) {
+  eval_lists(c, n, L);
+  eval_nets_fwd(c, n, c->ws.energy);
 }
 
 // Backward half (the adjoint): fitting net backward to dE/dD, then the
-// embedding backward with the force and virial scatter into F.
-void eval_backward(dp_ctx *c, int64_t n, double *F) {
+// embedding backward with the force scatter into F and the virial into V.
+void eval_backward(dp_ctx *c, int64_t n, double *F, double *V) {
   Workspace &w = c->ws;
   hipStream_t s = c->stream;
   const int64_t rows = eval_rows(c, n);
@@ -615,7 +722,7 @@ void eval_backward(dp_ctx *c, int64_t n, double *F) {
     tmark(c, 6);
     launch_embed_bwd_f64(s, embed_args(c, n, rows, F), grid);
     tmark(c, 7);
-    launch_sum9(s, w.vir_part, grid, w.virial);
+    launch_sum9(s, w.vir_part, grid, V);
   } else {
     launch_fit_mix(s, fitmix_args(c, rows), 2);
     tmark(c, 5);
@@ -624,14 +731,28 @@ void eval_backward(dp_ctx *c, int64_t n, double *F) {
     tmark(c, 6);
     launch_embed_mix(s, mix_args(c, rows, F), 2, grid);
     tmark(c, 7);
-    launch_sum9(s, w.vir_part, grid, w.virial);
+    launch_sum9(s, w.vir_part, grid, V);
   }
   tnext(c);
 }
 
 void eval_body(dp_ctx *c, int64_t n, const double L[3], double *F) {
   eval_forward(c, n, L);
-  eval_backward(c, n, F);
+  eval_backward(c, n, F, c->ws.virial);
+}
+
+// Student judge on the frame just evaluated (lists, environment and the
+// student's forces F in place): the teacher's networks on the same frame,
+// then the force RMSE into the status block (read by the next status sync).
+void eval_judge(dp_ctx *c, int64_t n) {
+  Workspace &w = c->ws;
+  const bool tim = c->timing;
+  c->timing = false;
+  c->active = 0;
+  eval_nets_fwd(c, n, w.energy_j);
+  eval_backward(c, n, w.force_j, w.virial_j);
+  c->active = 1;
+  c->timing = tim;
 }
 
 void build_lists(dp_ctx *c, int64_t n, const CellGrid &g, double rlist, const uint32_t *cond) {
@@ -650,12 +771,281 @@ int read_status(dp_ctx *c) {
   return DP_OK;
 }
 
+// Judge the student's forces F of the frame just evaluated against the
+// teacher's; on a rejection take the teacher's forces, energy and virial for
+// this frame and switch the context to the teacher.
+int judge_step(dp_ctx *c, int64_t n, double *F) {
+  Workspace &w = c->ws;
+  hipStream_t s = c->stream;
+  eval_judge(c, n);
+  launch_force_rmse(s, F, w.force_j, n, w.rmse_part, &w.status->judge_rmse);
+  HIPCHK(c, hipGetLastError());
+  int rc = read_status(c);
+  if (rc) return rc;
+  const double r = c->h_status->judge_rmse;
+  c->stats.last_judge_rmse = r;
+  if (!(r <= c->judge_max)) {  // a NaN rejects as well
+    HIPCHK(c, hipMemcpyAsync(F, w.force_j, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(w.energy, w.energy_j, sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(w.virial, w.virial_j, sizeof(double) * 9, hipMemcpyDeviceToDevice, s));
+    c->active = 0;
+    c->stats.teacher_fallbacks += 1;
+  }
+  return DP_OK;
+}
+
 __global__ void k_reset_status(DevStatus *st, uint32_t flags) {
   if (threadIdx.x == 0) {
     st->flags = flags;
     st->overflow = 0;
     for (int t = 0; t < MAXT; ++t) st->max_real[t] = 0;
   }
+}
+
+// ---------------------------------------------------------------------------
+// student helpers
+// ---------------------------------------------------------------------------
+constexpr int64_t ST_Q_LS = 1ll << 36;     // first sample index of the refit
+constexpr int64_t ST_Q_CHECK = 1ll << 37;  // first sample index of the held-out check
+constexpr int64_t ST_CHECK_N = 4096;
+
+int ensure_student(dp_ctx *c, int64_t batch) {
+  const int nets = c->dims.ntypes * c->dims.ntypes;
+  const int M1 = c->dims.M1;
+  const StudentLayout L = student_layout(M1);
+  Student *st = c->st;
+  if (st && st->cap >= batch && st->nets == nets && st->M1 == M1) return DP_OK;
+  std::vector<float> keep;
+  bool had = false;
+  int64_t t = 0;
+  if (st && st->have_params && st->nets == nets && st->M1 == M1) {
+    keep.resize((size_t)nets * L.np);
+    HIPCHK(c, hipMemcpy(keep.data(), st->params, sizeof(float) * keep.size(), hipMemcpyDeviceToHost));
+    had = true;
+    t = st->t;
+  }
+  free_student(c);
+  st = new Student();
+  c->st = st;
+  st->nets = nets;
+  st->M1 = M1;
+  st->np = L.np;
+  st->cap = std::max<int64_t>(batch, ST_CHECK_N);
+  const int64_t cap = st->cap, nblk = cap / 64, NE = (int64_t)SNF * SNF + (int64_t)SNF * M1;
+  std::vector<std::pair<void **, size_t>> plan;
+  auto add = [&](void **p, size_t bytes) { plan.push_back({p, bytes}); };
+  add((void **)&st->params, sizeof(float) * nets * L.np);
+  add((void **)&st->m, sizeof(float) * nets * L.np);
+  add((void **)&st->v, sizeof(float) * nets * L.np);
+  add((void **)&st->gout, sizeof(float) * nets * L.np);
+  add((void **)&st->gpart, sizeof(float) * nets * nblk * L.np);
+  add((void **)&st->lpart, sizeof(double) * nets * nblk * 2);
+  add((void **)&st->s, sizeof(double) * nets * cap);
+  add((void **)&st->wt, sizeof(float) * nets * cap);
+  add((void **)&st->G, sizeof(double) * nets * cap * M1);
+  add((void **)&st->lspart, sizeof(double) * nets * st_ls_blocks() * NE);
+  add((void **)&st->X, sizeof(double) * nets * SNF * M1);
+  add((void **)&st->chk, sizeof(double) * nets * nblk * 2);
+  add((void **)&st->loss, sizeof(double) * nets);
+  add((void **)&st->status, sizeof(int32_t) * nets);
+  size_t off = 0;
+  for (auto &pr : plan) off += (pr.second + 255) / 256 * 256;
+  if (hipMalloc(&st->base, off) != hipSuccess) {
+    (void)hipGetLastError();
+    free_student(c);
+    return fail(c, DP_E_OOM, "student buffers: allocation of " + std::to_string(off) + " bytes failed");
+  }
+  size_t o = 0;
+  for (auto &pr : plan) {
+    *pr.first = (char *)st->base + o;
+    o += (pr.second + 255) / 256 * 256;
+  }
+  if (had) {
+    HIPCHK(c, hipMemcpy(st->params, keep.data(), sizeof(float) * keep.size(), hipMemcpyHostToDevice));
+    st->have_params = true;
+    st->t = t;
+  }
+  return DP_OK;
+}
+
+bool lists_ready(const dp_ctx *c) { return c->has_model && c->ws.n_cap >= 0 && c->last_n > 0; }
+
+void st_draw(dp_ctx *c, uint64_t seed, int64_t q0, int64_t batch) {
+  Workspace &w = c->ws;
+  Student *st = c->st;
+  StSampleArgs sa{};
+  sa.d = c->dims;
+  sa.type_count = w.type_count;
+  sa.type_start = w.type_start;
+  sa.atom_of_pos = w.atom_of_pos;
+  sa.nreal = w.nreal;
+  sa.rt = w.rt;
+  sa.seed = seed;
+  sa.q0 = q0;
+  sa.batch = (int)batch;
+  sa.s = st->s;
+  sa.wt = st->wt;
+  launch_st_sample(c->stream, sa);
+  StTeacherArgs ta{};
+  ta.d = c->en[0].d;
+  ta.eo = c->en[0].eo;
+  ta.ew = c->en[0].d_emb;
+  ta.batch = (int)batch;
+  ta.s = st->s;
+  ta.G = st->G;
+  launch_st_teacher(c->stream, ta);
+}
+
+void st_grad(dp_ctx *c, int64_t batch) {
+  Student *st = c->st;
+  StGradArgs ga{};
+  ga.M1 = st->M1;
+  ga.nets = st->nets;
+  ga.batch = (int)batch;
+  ga.params = st->params;
+  ga.s = st->s;
+  ga.wt = st->wt;
+  ga.G = st->G;
+  ga.gpart = st->gpart;
+  ga.lpart = st->lpart;
+  launch_st_grad(c->stream, ga);
+}
+
+void st_adam(dp_ctx *c, int64_t batch, const dp_student_cfg &cfg, float *g_out) {
+  Student *st = c->st;
+  StAdamArgs aa{};
+  aa.M1 = st->M1;
+  aa.nets = st->nets;
+  aa.nblk = (int)(batch / 64);
+  aa.params = st->params;
+  aa.m = st->m;
+  aa.v = st->v;
+  aa.gpart = st->gpart;
+  aa.lpart = st->lpart;
+  aa.lr = (float)cfg.lr;
+  aa.b1 = (float)cfg.beta1;
+  aa.b2 = (float)cfg.beta2;
+  aa.eps = (float)cfg.eps;
+  const double tt = (double)(st->t + 1);
+  aa.c1 = (float)(1.0 / (1.0 - std::pow(cfg.beta1, tt)));
+  aa.c2 = (float)(1.0 / (1.0 - std::pow(cfg.beta2, tt)));
+  aa.loss = st->loss;
+  aa.g_out = g_out;
+  launch_st_adam(c->stream, aa);
+}
+
+// host initialisation: W1 ~ N(0, (2/smax)^2), b1 ~ N(0,1), W2 ~ N(0, 2/48),
+// b2 ~ N(0,1), W3 ~ N(0, 2/(32+M1)), b3 = 0; normal deviates by Box-Muller
+// from SplitMix64 (stream seed ^ 0xa0761d6478bd642f, counters net*2^40 + k)
+void st_init_params(const Student &st, uint64_t seed, const std::vector<double> &smax, std::vector<float> &P) {
+  const StudentLayout L = student_layout(st.M1);
+  P.assign((size_t)st.nets * L.np, 0.f);
+  const uint64_t sd = seed ^ 0xa0761d6478bd642full;
+  for (int net = 0; net < st.nets; ++net) {
+    uint64_t k = 0;
+    auto normal = [&]() {
+      const uint64_t a = sm64(sd, ((uint64_t)net << 40) + k++), b = sm64(sd, ((uint64_t)net << 40) + k++);
+      const double u1 = ((double)(a >> 11) + 0.5) * 0x1.0p-53, u2 = (double)(b >> 11) * 0x1.0p-53;
+      return std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2);
+    };
+    float *p = P.data() + (size_t)net * L.np;
+    const double s1 = 2.0 / std::max(smax[net], 1e-3);
+    for (int i = 0; i < SH1; ++i) p[L.o_w1 + i] = (float)(s1 * normal());
+    for (int i = 0; i < SH1; ++i) p[L.o_b1 + i] = (float)normal();
+    for (int i = 0; i < SH1 * SH2; ++i) p[L.o_w2 + i] = (float)(std::sqrt(2.0 / (SH1 + SH2)) * normal());
+    for (int i = 0; i < SH2; ++i) p[L.o_b2 + i] = (float)normal();
+    for (int i = 0; i < SH2 * st.M1; ++i) p[L.o_w3 + i] = (float)(std::sqrt(2.0 / (SH2 + st.M1)) * normal());
+  }
+}
+
+int quant_of(const dp_ctx *c) {
+  return c->precision == DP_MIX_FP16 ? 0 : (c->precision == DP_MIX_BF16 ? 1 : -1);
+}
+
+// Install student host model `m` (embedding 1-16-32-M1 affine) on the device.
+int install_student(dp_ctx *c, HostModel &&m) {
+  c->en[1].ready = false;
+  c->shm = std::move(m);
+  int rc = upload_emb(c, c->shm, c->en[1]);
+  if (rc) return rc;
+  if (c->precision != DP_FP64) {
+    rc = upload_emb_mix(c, c->shm, c->en[1]);
+    if (rc) return rc;
+  }
+  c->en[1].ready = true;
+  return DP_OK;
+}
+
+// Serialise a host model as a DPMIBLOB (version 2 when the last embedding
+// layer is affine).
+std::vector<unsigned char> write_blob(const HostModel &m) {
+  std::vector<unsigned char> b;
+  auto put = [&](const void *p, size_t n) {
+    const unsigned char *q = (const unsigned char *)p;
+    b.insert(b.end(), q, q + n);
+  };
+  auto i64 = [&](int64_t v) { put(&v, 8); };
+  auto f64 = [&](double v) { put(&v, 8); };
+  put("DPMIBLOB", 8);
+  i64(m.emb_lin ? 2 : 1);
+  i64(m.ntypes);
+  i64(m.n_emb);
+  i64(m.n_fit);
+  i64(m.M2);
+  if (m.emb_lin) i64(1);
+  f64(m.rcut);
+  f64(m.rcut_smth);
+  f64(m.desc_norm);
+  for (auto v : m.sel) i64(v);
+  for (auto v : m.emb_w) i64(v);
+  for (int64_t l = 1; l <= m.n_fit; ++l) i64(m.fit_w[l]);
+  for (int64_t t = 0; t < m.ntypes; ++t)
+    for (int64_t u = 0; u < m.ntypes; ++u)
+      for (int64_t l = 0; l < m.n_emb; ++l) {
+        const auto &W = m.eW[m.eidx(t, u, l)];
+        const auto &bb = m.eb[m.eidx(t, u, l)];
+        put(W.data(), 8 * W.size());
+        put(bb.data(), 8 * bb.size());
+      }
+  for (int64_t t = 0; t < m.ntypes; ++t)
+    for (int64_t l = 0; l <= m.n_fit; ++l) {
+      const auto &W = m.fW[m.fidx(t, l)];
+      const auto &bb = m.fb[m.fidx(t, l)];
+      put(W.data(), 8 * W.size());
+      put(bb.data(), 8 * bb.size());
+    }
+  return b;
+}
+
+// The student host model from FP32 hidden-layer parameters and the FP64
+// output layer X ([nets][33][M1]); W2 rounded as the kernels will hold it.
+HostModel student_model(const dp_ctx *c, const std::vector<float> &P, const std::vector<double> &X, int quant) {
+  HostModel m = c->hm;
+  const int T = (int)m.ntypes, M1 = c->dims.M1;
+  const StudentLayout L = student_layout(M1);
+  m.n_emb = 3;
+  m.emb_lin = 1;
+  m.emb_w = {1, SH1, SH2, M1};
+  m.eW.assign((size_t)T * T * 3, {});
+  m.eb.assign((size_t)T * T * 3, {});
+  for (int t = 0; t < T; ++t)
+    for (int u = 0; u < T; ++u) {
+      const int net = t * T + u;
+      const float *p = P.data() + (size_t)net * L.np;
+      const double *x = X.data() + (size_t)net * SNF * M1;
+      auto &W1 = m.eW[m.eidx(t, u, 0)], &b1 = m.eb[m.eidx(t, u, 0)];
+      auto &W2 = m.eW[m.eidx(t, u, 1)], &b2 = m.eb[m.eidx(t, u, 1)];
+      auto &W3 = m.eW[m.eidx(t, u, 2)], &b3 = m.eb[m.eidx(t, u, 2)];
+      for (int i = 0; i < SH1; ++i) {
+        W1.push_back(p[L.o_w1 + i]);
+        b1.push_back(p[L.o_b1 + i]);
+      }
+      for (int i = 0; i < SH1 * SH2; ++i) W2.push_back(st_round16(p[L.o_w2 + i], quant));
+      for (int j = 0; j < SH2; ++j) b2.push_back(p[L.o_b2 + j]);
+      for (int k = 0; k < SH2 * M1; ++k) W3.push_back(x[k]);
+      for (int o = 0; o < M1; ++o) b3.push_back(x[SH2 * M1 + o]);
+    }
+  return m;
 }
 
 }  // namespace
@@ -690,9 +1080,12 @@ void dp_destroy(dp_ctx *c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   free_ws(c->ws);
-  if (c->d_emb) (void)hipFree(c->d_emb);
+  for (auto &en : c->en) {
+    if (en.d_emb) (void)hipFree(en.d_emb);
+    if (en.d_mix) (void)hipFree(en.d_mix);
+  }
+  free_student(c);
   if (c->d_fit) (void)hipFree(c->d_fit);
-  if (c->d_mix_nets) (void)hipFree(c->d_mix_nets);
   if (c->d_fit_mix) (void)hipFree(c->d_fit_mix);
   if (c->h_status) (void)hipHostFree(c->h_status);
   for (auto &e : c->ev)
@@ -713,6 +1106,9 @@ int dp_set_model(dp_ctx *c, const void *blob, size_t nbytes, int precision) {
   c->hm = std::move(m);
   free_ws(c->ws);
   c->has_model = false;
+  c->active = 0;
+  c->en[1].ready = false;
+  if (c->st) c->st->have_params = false;
   int rc = upload_model(c);
   if (rc) return rc;
   c->precision = precision;
@@ -816,7 +1212,7 @@ static int compute_impl(dp_ctx *c, int64_t n, const double *coords, const int32_
                        w.atom_of_pos, w.rows_cap);
       build_lists(c, n, g, rlist, nullptr);
       eval_forward(c, n, L);
-      if (backward) eval_backward(c, n, F);
+      if (backward) eval_backward(c, n, F, w.virial);
     } else {
       launch_zero(s, w.energy, 1);
       launch_zero(s, w.virial, 9);
@@ -875,7 +1271,7 @@ int dp_energy_backward(dp_ctx *c, double grad_energy, double *forces, double *vi
     tmark(c, 2);
     tmark(c, 3);
     tmark(c, 4);
-    eval_backward(c, n, F);
+    eval_backward(c, n, F, w.virial);
     if (grad_energy != 1.0) {
       hipLaunchKernelGGL(k_scale, dim3((unsigned)((3 * n + 255) / 256)), dim3(256), 0, s, F, 3 * n, grad_energy);
       hipLaunchKernelGGL(k_scale, dim3(1), dim3(64), 0, s, w.virial, (int64_t)9, grad_energy);
@@ -979,6 +1375,11 @@ int dp_md_run(dp_ctx *c, int64_t n, double *coords, double *vel, const int32_t *
   launch_copy_ref(s, n, w.xw, w.xref, &w.status->flags);
   launch_end_rebuild(s, &w.status->flags, &w.status->nbuild);
   eval_body(c, n, L, F);
+  const bool judging = c->active == 1 && c->judge_every > 0;
+  if (judging) {
+    rc = judge_step(c, n, F);
+    if (rc) return rc;
+  }
   if (thermo) {
     launch_kinetic(s, n, vel, types, mass, w.partial, w.ke);
     launch_thermo_row(s, thermo + 6 * row++, 0.0, w.ke, w.energy, w.virial, ndof_kb, inv3v, &w.status->flags);
@@ -993,6 +1394,10 @@ int dp_md_run(dp_ctx *c, int64_t n, double *coords, double *vel, const int32_t *
     launch_copy_ref(s, n, w.xw, w.xref, &w.status->flags);
     launch_end_rebuild(s, &w.status->flags, &w.status->nbuild);
     eval_body(c, n, L, F);
+    if (judging && c->active == 1 && st % c->judge_every == 0) {
+      rc = judge_step(c, n, F);
+      if (rc) return rc;
+    }
     launch_verlet_half(s, n, vel, F, types, inv_m, 0.5 * dt);
     const bool th = thermo && (st % thermo_every == 0);
     if (th) {
@@ -1020,6 +1425,245 @@ int dp_md_run(dp_ctx *c, int64_t n, double *coords, double *vel, const int32_t *
   c->stats.cand_cap = c->ws.cand_cap;
   c->last_n = n;
   return DP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// student embedding net
+// ---------------------------------------------------------------------------
+int dp_student_default_cfg(dp_student_cfg *cfg) {
+  if (!cfg) return DP_E_ARG;
+  cfg->batch = 4096;
+  cfg->adam_steps = 500;
+  cfg->lr = 1e-3;
+  cfg->beta1 = 0.9;
+  cfg->beta2 = 0.999;
+  cfg->eps = 1e-8;
+  cfg->ls_samples = 262144;
+  cfg->ridge = 1e-14;
+  cfg->seed = 20240607ull;
+  cfg->init = 1;
+  cfg->refit = 1;
+  return DP_OK;
+}
+
+int dp_student_train(dp_ctx *c, const dp_student_cfg *cfg, double *fit_rmse) {
+  if (!c || !cfg) return DP_E_ARG;
+  if (!lists_ready(c)) return fail(c, DP_E_NOMODEL, "dp_student_train needs a preceding evaluation");
+  const dp_student_cfg &g = *cfg;
+  if (g.batch < 64 || g.batch % 64 != 0 || g.batch > (1 << 20) || g.adam_steps < 0 || !(g.lr > 0) ||
+      !(g.beta1 >= 0 && g.beta1 < 1) || !(g.beta2 >= 0 && g.beta2 < 1) || !(g.eps > 0) || !(g.ridge >= 0) ||
+      (g.refit && (g.ls_samples < g.batch || g.ls_samples % g.batch != 0)))
+    return fail(c, DP_E_ARG, "bad student configuration");
+  if (c->dims.M1 > 128) return fail(c, DP_E_MODEL, "student nets need M1 <= 128");
+  if (c->precision != DP_FP64 && c->dims.M1 != 100)
+    return fail(c, DP_E_MODEL, "the mixed-precision student kernels exist for M1 = 100 only");
+  HIPCHK(c, hipSetDevice(c->device));
+  int rc = ensure_student(c, g.batch);
+  if (rc) return rc;
+  Student *st = c->st;
+  const StudentLayout L = student_layout(st->M1);
+  hipStream_t s = c->stream;
+  if (g.init || !st->have_params) {
+    // scale of the first layer from the largest s of the first batch
+    st_draw(c, g.seed, 0, g.batch);
+    std::vector<double> sv((size_t)st->nets * g.batch);
+    HIPCHK(c, hipMemcpyAsync(sv.data(), st->s, sizeof(double) * sv.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    std::vector<double> smax(st->nets, 0.0);
+    for (int net = 0; net < st->nets; ++net)
+      for (int64_t q = 0; q < g.batch; ++q) smax[net] = std::max(smax[net], sv[(size_t)net * g.batch + q]);
+    std::vector<float> P;
+    st_init_params(*st, g.seed, smax, P);
+    HIPCHK(c, hipMemcpy(st->params, P.data(), sizeof(float) * P.size(), hipMemcpyHostToDevice));
+    launch_fill_u32(s, (uint32_t *)st->m, (int64_t)st->nets * L.np, 0u);
+    launch_fill_u32(s, (uint32_t *)st->v, (int64_t)st->nets * L.np, 0u);
+    st->have_params = true;
+    st->t = 0;
+  }
+  for (int64_t k = 0; k < g.adam_steps; ++k) {
+    st_draw(c, g.seed, st->t * g.batch, g.batch);
+    st_grad(c, g.batch);
+    st_adam(c, g.batch, g, nullptr);
+    st->t += 1;
+  }
+  HIPCHK(c, hipGetLastError());
+  double result = 0.0;
+  if (g.adam_steps > 0) {
+    std::vector<double> loss(st->nets);
+    HIPCHK(c, hipMemcpyAsync(loss.data(), st->loss, sizeof(double) * st->nets, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (double v : loss) result = std::max(result, v);
+  }
+  if (g.refit) {
+    const int quant = quant_of(c);
+    const int NE = SNF * SNF + SNF * st->M1;
+    launch_fill_u32(s, (uint32_t *)st->lspart, (int64_t)st->nets * st_ls_blocks() * NE * 2, 0u);
+    for (int64_t q = 0; q < g.ls_samples; q += g.batch) {
+      st_draw(c, g.seed, ST_Q_LS + q, g.batch);
+      StLsArgs la{};
+      la.M1 = st->M1;
+      la.nets = st->nets;
+      la.batch = (int)g.batch;
+      la.nblk = st_ls_blocks();
+      la.params = st->params;
+      la.quant = quant;
+      la.s = st->s;
+      la.wt = st->wt;
+      la.G = st->G;
+      la.part = st->lspart;
+      launch_st_ls(s, la);
+    }
+    StSolveArgs va{};
+    va.M1 = st->M1;
+    va.nets = st->nets;
+    va.nblk = st_ls_blocks();
+    va.part = st->lspart;
+    va.ridge = g.ridge;
+    va.quant = quant;
+    va.X = st->X;
+    va.status = st->status;
+    launch_st_solve(s, va);
+    // held-out check of the fitted model
+    st_draw(c, g.seed, ST_Q_CHECK, ST_CHECK_N);
+    StCheckArgs ca{};
+    ca.M1 = st->M1;
+    ca.nets = st->nets;
+    ca.batch = (int)ST_CHECK_N;
+    ca.params = st->params;
+    ca.X = st->X;
+    ca.quant = quant;
+    ca.s = st->s;
+    ca.wt = st->wt;
+    ca.G = st->G;
+    ca.part = st->chk;
+    launch_st_check(s, ca);
+    HIPCHK(c, hipGetLastError());
+    std::vector<int32_t> stat(st->nets);
+    const int64_t ncb = ST_CHECK_N / 64;
+    std::vector<double> chk((size_t)st->nets * ncb * 2);
+    std::vector<float> P((size_t)st->nets * L.np);
+    std::vector<double> X((size_t)st->nets * SNF * st->M1);
+    HIPCHK(c, hipMemcpyAsync(stat.data(), st->status, sizeof(int32_t) * stat.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(chk.data(), st->chk, sizeof(double) * chk.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(P.data(), st->params, sizeof(float) * P.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(X.data(), st->X, sizeof(double) * X.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    result = 0.0;
+    for (int net = 0; net < st->nets; ++net) {
+      if (stat[net] == 2) {
+        // no neighbour of this type pair in the frame: the net is never
+        // evaluated on it; keep an all-zero output layer
+        std::fill(X.begin() + (size_t)net * SNF * st->M1, X.begin() + (size_t)(net + 1) * SNF * st->M1, 0.0);
+        continue;
+      }
+      if (stat[net] != 0)
+        return fail(c, DP_E_MODEL, "student least squares: normal matrix not positive definite (net " +
+                                       std::to_string(net) + "); raise the ridge");
+      double e2 = 0.0, g2 = 0.0;
+      for (int64_t b = 0; b < ncb; ++b) {
+        e2 += chk[((size_t)net * ncb + b) * 2];
+        g2 += chk[((size_t)net * ncb + b) * 2 + 1];
+      }
+      if (g2 > 0) result = std::max(result, std::sqrt(e2 / g2));
+    }
+    rc = install_student(c, student_model(c, P, X, quant));
+    if (rc) return rc;
+  }
+  if (fit_rmse) *fit_rmse = result;
+  return DP_OK;
+}
+
+int dp_student_get_params(dp_ctx *c, float *params) {
+  if (!c || !params) return DP_E_ARG;
+  if (!c->st || !c->st->have_params) return fail(c, DP_E_NOMODEL, "no student parameters");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(params, c->st->params, sizeof(float) * c->st->nets * c->st->np, hipMemcpyDeviceToHost));
+  return DP_OK;
+}
+
+int dp_student_set_params(dp_ctx *c, const float *params) {
+  if (!c || !params) return DP_E_ARG;
+  if (!c->has_model) return fail(c, DP_E_NOMODEL, "no model");
+  HIPCHK(c, hipSetDevice(c->device));
+  int rc = ensure_student(c, c->st ? c->st->cap : 4096);
+  if (rc) return rc;
+  Student *st = c->st;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(st->params, params, sizeof(float) * st->nets * st->np, hipMemcpyHostToDevice));
+  launch_fill_u32(c->stream, (uint32_t *)st->m, (int64_t)st->nets * st->np, 0u);
+  launch_fill_u32(c->stream, (uint32_t *)st->v, (int64_t)st->nets * st->np, 0u);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  st->have_params = true;
+  st->t = 0;
+  return DP_OK;
+}
+
+int dp_student_batch_grad(dp_ctx *c, uint64_t seed, int64_t step, int64_t batch, double *s_out, double *loss,
+                          float *grad) {
+  if (!c) return DP_E_ARG;
+  if (!lists_ready(c)) return fail(c, DP_E_NOMODEL, "dp_student_batch_grad needs a preceding evaluation");
+  if (batch < 64 || batch % 64 != 0 || batch > (1 << 20) || step < 0)
+    return fail(c, DP_E_ARG, "batch must be a positive multiple of 64");
+  if (!c->st || !c->st->have_params) return fail(c, DP_E_NOMODEL, "no student parameters");
+  HIPCHK(c, hipSetDevice(c->device));
+  int rc = ensure_student(c, batch);
+  if (rc) return rc;
+  Student *st = c->st;
+  hipStream_t s = c->stream;
+  dp_student_cfg g;
+  dp_student_default_cfg(&g);
+  st_draw(c, seed, step * batch, batch);
+  st_grad(c, batch);
+  st_adam(c, batch, g, st->gout);
+  HIPCHK(c, hipGetLastError());
+  if (s_out) HIPCHK(c, hipMemcpyAsync(s_out, st->s, sizeof(double) * st->nets * batch, hipMemcpyDeviceToHost, s));
+  if (loss) HIPCHK(c, hipMemcpyAsync(loss, st->loss, sizeof(double) * st->nets, hipMemcpyDeviceToHost, s));
+  if (grad) HIPCHK(c, hipMemcpyAsync(grad, st->gout, sizeof(float) * st->nets * st->np, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return DP_OK;
+}
+
+int dp_student_use(dp_ctx *c, int on) {
+  if (!c) return DP_E_ARG;
+  if (on && !c->en[1].ready) return fail(c, DP_E_NOMODEL, "no student installed");
+  c->active = on ? 1 : 0;
+  c->fwd_ready = false;
+  return DP_OK;
+}
+
+int dp_student_judge(dp_ctx *c, int64_t every, double max_force_rmse) {
+  if (!c) return DP_E_ARG;
+  if (every < 0 || !(max_force_rmse >= 0)) return fail(c, DP_E_ARG, "bad judge settings");
+  c->judge_every = every;
+  c->judge_max = max_force_rmse;
+  return DP_OK;
+}
+
+int dp_student_get_model(dp_ctx *c, void *buf, size_t cap, size_t *nbytes) {
+  if (!c || !nbytes) return DP_E_ARG;
+  if (!c->en[1].ready) return fail(c, DP_E_NOMODEL, "no student installed");
+  const std::vector<unsigned char> b = write_blob(c->shm);
+  *nbytes = b.size();
+  if (buf) std::memcpy(buf, b.data(), std::min(cap, b.size()));
+  return DP_OK;
+}
+
+int dp_student_set_model(dp_ctx *c, const void *blob, size_t nbytes) {
+  if (!c || !blob) return DP_E_ARG;
+  if (!c->has_model) return fail(c, DP_E_NOMODEL, "no teacher model");
+  HIPCHK(c, hipSetDevice(c->device));
+  HostModel m;
+  std::string err;
+  if (!parse_blob(blob, nbytes, m, err)) return fail(c, DP_E_MODEL, err);
+  const HostModel &h = c->hm;
+  const bool same = m.ntypes == h.ntypes && m.rcut == h.rcut && m.rcut_smth == h.rcut_smth &&
+                    m.desc_norm == h.desc_norm && m.sel == h.sel && m.M2 == h.M2 && m.n_fit == h.n_fit &&
+                    m.fit_w == h.fit_w && m.fW == h.fW && m.fb == h.fb;
+  if (!same) return fail(c, DP_E_MODEL, "student blob: geometry or fitting nets differ from the teacher's");
+  if (!(m.n_emb == 3 && m.emb_lin == 1 && m.emb_w[1] == SH1 && m.emb_w[2] == SH2 && m.emb_w[3] == c->dims.M1))
+    return fail(c, DP_E_MODEL, "student blob: embedding must be 1-16-32-M1 with an affine last layer");
+  return install_student(c, std::move(m));
 }
 
 }  // extern "C"

@@ -22,6 +22,7 @@ struct Dims {
   int ew[MAXL + 1];    // embedding widths, ew[0] = 1
   int ekp[MAXL + 1];   // width rounded up to 4 (as a K dimension)
   int emp[MAXL + 1];   // width rounded up to 16 (as an M dimension)
+  int emb_lin;         // 1: the last embedding layer is affine (no tanh)
   int fw[MAXF + 2];    // fitting widths, fw[0] = M1*M2, fw[n_fit+1] = 1
 };
 

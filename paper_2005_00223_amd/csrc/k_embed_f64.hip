@@ -176,7 +176,8 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
                 if (f < rows_out) {
                   double h = 0.0;
                   if (f < out) {
-                    h = tanh(acc[0][mt][r] + bias[f]);
+                    const double z = acc[0][mt][r] + bias[f];
+                    h = (d.emb_lin && l == d.n_emb - 1) ? z : tanh(z);
                     const int sf = skip_src(f, in, out);
                     if (sf >= 0) h += Hin[sf * 16 + n];
                   }
@@ -362,9 +363,11 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_bwd_f64(EmbedArgs a, E
                 const int f = mt * 16 + 4 * r + (lane >> 4), n = lane & 15;
                 double h = 0.0, hd = 0.0;
                 if (f < out) {
-                  const double th = tanh(acc[0][mt][r] + bias[f]);
+                  const double z = acc[0][mt][r] + bias[f];
+                  const bool lin = d.emb_lin && last;
+                  const double th = lin ? z : tanh(z);
                   h = th;
-                  hd = (1.0 - th * th) * acc[1][mt][r];
+                  hd = lin ? acc[1][mt][r] : (1.0 - th * th) * acc[1][mt][r];
                   const int sf = skip_src(f, in, out);
                   if (sf >= 0) {
                     h += Hin[sf * 32 + n];

@@ -267,11 +267,10 @@ __device__ inline float skip_val(int f, int mt, int r, const float (&prev)[MTI][
   return f < IN ? own : other;
 }
 
-template <int W1, int W2, int W3, int P>
+// LIN: the last layer is affine (no tanh), as in the student nets
+template <int W1, int W2, int W3, int LIN, int P>
 __global__ void __launch_bounds__(64 * MIX_WAVES, 2) k_embed_fwd_mix(MixArgs a) {
   typedef Shape<W1, W2, W3> S;
-  typedef typename HT<P>::v8 V;
-  typedef typename HT<P>::e E;
   extern __shared__ __align__(16) unsigned char smem[];
   const Dims &d = a.d;
   const int nnets = d.ntypes * d.ntypes;
@@ -350,7 +349,8 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 2) k_embed_fwd_mix(MixArgs a) 
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const int f = 16 * mt + 4 * g + r;
-                if (f < W3) gv[r] = tanh_f(acc3[r]) + skip_val<W2, W3, S::SK3, S::MT2>(f, mt, r, h2, h2s, n, S::S2);
+                if (f < W3)
+                  gv[r] = (LIN ? acc3[r] : tanh_f(acc3[r])) + skip_val<W2, W3, S::SK3, S::MT2>(f, mt, r, h2, h2s, n, S::S2);
               }
             }
             *(float4 *)(Gs + n * 32 + 16 * q + 4 * g) = make_float4(gv[0], gv[1], gv[2], gv[3]);
@@ -417,11 +417,9 @@ __device__ inline void switch64(double r, double rcs, double rc, double inv_w, d
   }
 }
 
-template <int W1, int W2, int W3, int P>
+template <int W1, int W2, int W3, int LIN, int P>
 __global__ void __launch_bounds__(64 * MIX_WAVES, 2) k_embed_bwd_mix(MixArgs a) {
   typedef Shape<W1, W2, W3> S;
-  typedef typename HT<P>::v8 V;
-  typedef typename HT<P>::e E;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double vred[MIX_WAVES][9];
   const Dims &d = a.d;
@@ -553,9 +551,10 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 2) k_embed_bwd_mix(MixArgs a) 
               for (int r = 0; r < 4; ++r) {
                 const int f = 16 * mt + 4 * g + r;
                 if (f < W3) {
-                  const float th = tanh_f(h3[r]);
+                  const float th = LIN ? h3[r] : tanh_f(h3[r]);
                   G[q][r] = th + skip_val<W2, W3, S::SK3, S::MT2>(f, mt, r, h2, h2s, n, S::S2);
-                  Gd[q][r] = (1.f - th * th) * d3[r] + skip_val<W2, W3, S::SK3, S::MT2>(f, mt, r, hd2, hd2s, n, S::S2);
+                  Gd[q][r] = (LIN ? d3[r] : (1.f - th * th) * d3[r]) +
+                             skip_val<W2, W3, S::SK3, S::MT2>(f, mt, r, hd2, hd2s, n, S::S2);
                 }
               }
             }
@@ -702,16 +701,16 @@ static void pack_net_t(const double *const *W, const double *const *b, int prec,
   for (int f = 0; f < W3; ++f) b3[f] = (float)b[2][f];
 }
 
-template <int W1, int W2, int W3, int P>
+template <int W1, int W2, int W3, int LIN, int P>
 static void launch_t(hipStream_t s, const MixArgs &a, int pass, int grid) {
   typedef Shape<W1, W2, W3> S;
   const int nnets = a.d.ntypes * a.d.ntypes;
   if (pass == 1) {
     const size_t shm = (size_t)nnets * S::NET_BYTES + (size_t)MIX_WAVES * S::P1_BYTES;
-    hipLaunchKernelGGL((k_embed_fwd_mix<W1, W2, W3, P>), dim3(grid), dim3(64 * MIX_WAVES), shm, s, a);
+    hipLaunchKernelGGL((k_embed_fwd_mix<W1, W2, W3, LIN, P>), dim3(grid), dim3(64 * MIX_WAVES), shm, s, a);
   } else {
     const size_t shm = (size_t)nnets * S::NET_BYTES + (size_t)MIX_WAVES * S::P2_BYTES;
-    hipLaunchKernelGGL((k_embed_bwd_mix<W1, W2, W3, P>), dim3(grid), dim3(64 * MIX_WAVES), shm, s, a);
+    hipLaunchKernelGGL((k_embed_bwd_mix<W1, W2, W3, LIN, P>), dim3(grid), dim3(64 * MIX_WAVES), shm, s, a);
   }
 }
 
@@ -721,14 +720,14 @@ static size_t lds_t(int ntypes, int pass) {
   return (size_t)ntypes * ntypes * S::NET_BYTES + (size_t)MIX_WAVES * (pass == 1 ? S::P1_BYTES : S::P2_BYTES);
 }
 
-// supported embedding shapes (widths of the three layers)
-#define DPK_MIX_SHAPES(X) X(25, 50, 100) X(16, 32, 100)
+// supported embedding shapes: widths of the three layers, affine last layer
+#define DPK_MIX_SHAPES(X) X(25, 50, 100, 0) X(16, 32, 100, 0) X(16, 32, 100, 1)
 
 int mix_shape_id(const Dims &d) {
   if (d.n_emb != 3) return -1;
   int id = 0;
-#define X(a_, b_, c_)                                         \
-  if (d.ew[1] == a_ && d.ew[2] == b_ && d.ew[3] == c_) return id; \
+#define X(a_, b_, c_, l_)                                                                  \
+  if (d.ew[1] == a_ && d.ew[2] == b_ && d.ew[3] == c_ && (d.emb_lin != 0) == (l_ != 0)) return id; \
   ++id;
   DPK_MIX_SHAPES(X)
 #undef X
@@ -737,7 +736,7 @@ int mix_shape_id(const Dims &d) {
 
 size_t mix_net_bytes(int shape) {
   int id = 0;
-#define X(a_, b_, c_)                                  \
+#define X(a_, b_, c_, l_)                              \
   if (shape == id) return net_bytes_t<a_, b_, c_>(); \
   ++id;
   DPK_MIX_SHAPES(X)
@@ -747,7 +746,7 @@ size_t mix_net_bytes(int shape) {
 
 size_t mix_lds_bytes(int shape, int ntypes, int pass) {
   int id = 0;
-#define X(a_, b_, c_)                                     \
+#define X(a_, b_, c_, l_)                                 \
   if (shape == id) return lds_t<a_, b_, c_>(ntypes, pass); \
   ++id;
   DPK_MIX_SHAPES(X)
@@ -757,7 +756,7 @@ size_t mix_lds_bytes(int shape, int ntypes, int pass) {
 
 void mix_pack_net(int shape, const double *const *W, const double *const *b, int prec, unsigned char *out) {
   int id = 0;
-#define X(a_, b_, c_)                               \
+#define X(a_, b_, c_, l_)                           \
   if (shape == id) {                                \
     pack_net_t<a_, b_, c_>(W, b, prec, out);        \
     return;                                         \
@@ -776,10 +775,10 @@ int mix_grid(int64_t rows) {
 
 void launch_embed_mix(hipStream_t s, const MixArgs &a, int pass, int grid) {
   int id = 0;
-#define X(a_, b_, c_)                                     \
+#define X(a_, b_, c_, l_)                                 \
   if (a.shape == id) {                                    \
-    if (a.prec == 0) launch_t<a_, b_, c_, 0>(s, a, pass, grid); \
-    else launch_t<a_, b_, c_, 1>(s, a, pass, grid);       \
+    if (a.prec == 0) launch_t<a_, b_, c_, l_, 0>(s, a, pass, grid); \
+    else launch_t<a_, b_, c_, l_, 1>(s, a, pass, grid);   \
     return;                                               \
   }                                                       \
   ++id;

@@ -1,0 +1,497 @@
+// Student embedding net: sampling, teacher targets, training and the
+// output-layer least squares.
+//
+// The student is a smaller embedding net, 1 -> 16 (tanh) -> 32 (tanh with
+// the doubling skip) -> M1 (affine), one per (centre type, neighbour type)
+// pair like the teacher's.  It is fitted to the teacher's own G(s) at
+// neighbour distances of the current configuration:
+//   1. samples: uniform over the real (centre, neighbour) pairs of each
+//      type pair, by rejection (random centre of type t, random slot below
+//      sel_u, kept when the slot holds a real neighbour), with SplitMix64 as
+//      a counter-based generator so that every sample has a fixed identity;
+//   2. targets: the teacher's G(s) in FP64;
+//   3. Adam (Kingma and Ba, 2015) on the mean squared error in FP32;
+//   4. the exact minimiser of the same squared error over the affine output
+//      layer given the trained hidden layers: FP64 normal equations of
+//      (h2, 1) with a small ridge, solved by Cholesky.  When the student will
+//      run in 16-bit precision, W2 is rounded before the features are formed
+//      and W3 after the solve, and b3 then absorbs the mean residual.
+// Training work is small next to an MD step, so these kernels are plain
+// FP32/FP64 VALU code with LDS, written for clarity over speed.
+#include "dp_student.h"
+
+namespace dpk {
+
+// ---------------------------------------------------------------------------
+// 1. samples
+// ---------------------------------------------------------------------------
+__global__ void k_st_sample(StSampleArgs a) {
+  const int net = blockIdx.y;
+  const int T = a.d.ntypes;
+  const int t = net / T, u = net % T;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.batch) return;
+  const int64_t count = a.type_count[t];
+  const int64_t selu = a.d.sel[u];
+  double s = 0.0;
+  float w = 0.f;
+  if (count > 0 && selu > 0) {
+    for (int at = 0; at < ST_ATTEMPTS; ++at) {
+      const uint64_t x = sm64(a.seed, st_ctr(net, a.q0 + q, at));
+      const int64_t k = (int64_t)(((x >> 32) * (uint64_t)count) >> 32);
+      const int64_t slot = (int64_t)(((x & 0xffffffffull) * (uint64_t)selu) >> 32);
+      const int i = a.atom_of_pos[a.type_start[t] + k];
+      if (slot < a.nreal[(int64_t)i * T + u]) {
+        s = a.rt[(int64_t)i * a.d.nnei + a.d.off[u] + slot].x;
+        w = 1.f;
+        break;
+      }
+    }
+  }
+  a.s[(int64_t)net * a.batch + q] = s;
+  a.wt[(int64_t)net * a.batch + q] = w;
+}
+
+void launch_st_sample(hipStream_t st, const StSampleArgs &a) {
+  const int nets = a.d.ntypes * a.d.ntypes;
+  hipLaunchKernelGGL(k_st_sample, dim3((a.batch + 255) / 256, nets), dim3(256), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
+// 2. teacher G(s) in FP64: one thread per sample, activations in LDS
+//    ([feature][64] per buffer, two buffers)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_st_teacher(StTeacherArgs a) {
+  extern __shared__ double tsh[];
+  const Dims &d = a.d;
+  const int net = blockIdx.y;
+  const int t = net / d.ntypes, u = net % d.ntypes;
+  const int tid = threadIdx.x;
+  const int q = blockIdx.x * 64 + tid;
+  int wmax = 1;
+  for (int l = 1; l <= d.n_emb; ++l) wmax = d.ew[l] > wmax ? d.ew[l] : wmax;
+  double *hA = tsh, *hB = tsh + wmax * 64;
+  const double s = q < a.batch ? a.s[(int64_t)net * a.batch + q] : 0.0;
+  {
+    const double *W0 = a.ew + a.eo.w[t][u][0], *b0 = a.ew + a.eo.b[t][u][0];
+    const int out = d.ew[1];
+    const bool lin = d.emb_lin && d.n_emb == 1;
+    for (int o = 0; o < out; ++o) {
+      const double z = s * W0[o] + b0[o];
+      double h = lin ? z : tanh(z);
+      if (out <= 2) h += s;  // identity / doubling skip of the scalar input
+      hA[o * 64 + tid] = h;
+    }
+  }
+  for (int l = 1; l < d.n_emb; ++l) {
+    const int in = d.ew[l], out = d.ew[l + 1], mp = d.emp[l + 1];
+    const double *W = a.ew + a.eo.w[t][u][l], *b = a.ew + a.eo.b[t][u][l];
+    const bool lin = d.emb_lin && l == d.n_emb - 1;
+    for (int o = 0; o < out; ++o) {
+      double z = b[o];
+      for (int i = 0; i < in; ++i) z += hA[i * 64 + tid] * W[(size_t)i * mp + o];
+      double h = lin ? z : tanh(z);
+      if (out == in) h += hA[o * 64 + tid];
+      else if (out == 2 * in) h += hA[(o % in) * 64 + tid];
+      hB[o * 64 + tid] = h;
+    }
+    double *tmp = hA;
+    hA = hB;
+    hB = tmp;
+  }
+  if (q < a.batch) {
+    double *G = a.G + ((int64_t)net * a.batch + q) * d.M1;
+    for (int o = 0; o < d.M1; ++o) G[o] = hA[o * 64 + tid];
+  }
+}
+
+void launch_st_teacher(hipStream_t st, const StTeacherArgs &a) {
+  int wmax = 1;
+  for (int l = 1; l <= a.d.n_emb; ++l) wmax = a.d.ew[l] > wmax ? a.d.ew[l] : wmax;
+  const size_t shm = (size_t)2 * wmax * 64 * sizeof(double);
+  const int nets = a.d.ntypes * a.d.ntypes;
+  hipLaunchKernelGGL(k_st_teacher, dim3((a.batch + 63) / 64, nets), dim3(64), shm, st, a);
+}
+
+// ---------------------------------------------------------------------------
+// student forward in FP32 for one sample: h1, t1, h2, t2 in registers
+// ---------------------------------------------------------------------------
+constexpr int SP = 65;  // LDS row stride (samples), odd to spread banks
+
+__device__ inline void st_hidden_f32(const float *P, const StudentLayout &L, float s, float (&t1)[SH1],
+                                     float (&t2)[SH2], float (&h2)[SH2]) {
+#pragma unroll
+  for (int i = 0; i < SH1; ++i) t1[i] = tanhf(s * P[L.o_w1 + i] + P[L.o_b1 + i]);
+#pragma unroll
+  for (int j = 0; j < SH2; ++j) {
+    float z = P[L.o_b2 + j];
+#pragma unroll
+    for (int i = 0; i < SH1; ++i) z += t1[i] * P[L.o_w2 + i * SH2 + j];
+    t2[j] = tanhf(z);
+    h2[j] = t1[j % SH1] + t2[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3a. squared error and its gradient: one block of 64 threads per 64 samples
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_st_grad(StGradArgs a) {
+  extern __shared__ float gsh[];
+  const int M1 = a.M1;
+  const StudentLayout L = student_layout(M1);
+  const int net = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
+  const int tid = threadIdx.x;
+  float *P = gsh;                  // [np]
+  float *ss = P + L.np;            // [64]
+  float *h1s = ss + 64;            // [SH1][SP]
+  float *dz1s = h1s + SH1 * SP;    // [SH1][SP]
+  float *h2s = dz1s + SH1 * SP;    // [SH2][SP]
+  float *dz2s = h2s + SH2 * SP;    // [SH2][SP]
+  float *rs = dz2s + SH2 * SP;     // [M1][SP]
+  __shared__ double red[2][64];
+  const float *Pg = a.params + (int64_t)net * L.np;
+  for (int e = tid; e < L.np; e += 64) P[e] = Pg[e];
+  __syncthreads();
+  const int64_t q = (int64_t)net * a.batch + (int64_t)blk * 64 + tid;
+  const float s = (float)a.s[q];
+  const float w = a.wt[q];
+  float t1[SH1], t2[SH2], h2[SH2];
+  st_hidden_f32(P, L, s, t1, t2, h2);
+  float dh2[SH2];
+#pragma unroll
+  for (int k = 0; k < SH2; ++k) dh2[k] = 0.f;
+  double lsum = 0.0;
+  const double *Gt = a.G + q * M1;
+  for (int o = 0; o < M1; ++o) {
+    float g = P[L.o_b3 + o];
+#pragma unroll
+    for (int k = 0; k < SH2; ++k) g += h2[k] * P[L.o_w3 + k * M1 + o];
+    const float r = w * (g - (float)Gt[o]);
+    lsum += (double)r * r;
+    rs[o * SP + tid] = r;
+#pragma unroll
+    for (int k = 0; k < SH2; ++k) dh2[k] += P[L.o_w3 + k * M1 + o] * r;
+  }
+  float dz2[SH2];
+#pragma unroll
+  for (int j = 0; j < SH2; ++j) dz2[j] = dh2[j] * (1.f - t2[j] * t2[j]);
+#pragma unroll
+  for (int i = 0; i < SH1; ++i) {
+    float g = dh2[i] + dh2[i + SH1];
+#pragma unroll
+    for (int j = 0; j < SH2; ++j) g += P[L.o_w2 + i * SH2 + j] * dz2[j];
+    dz1s[i * SP + tid] = g * (1.f - t1[i] * t1[i]);
+    h1s[i * SP + tid] = t1[i];
+  }
+#pragma unroll
+  for (int j = 0; j < SH2; ++j) {
+    h2s[j * SP + tid] = h2[j];
+    dz2s[j * SP + tid] = dz2[j];
+  }
+  ss[tid] = s;
+  red[0][tid] = lsum;
+  red[1][tid] = (double)w;
+  __syncthreads();
+  // sums over the 64 samples of the block, parameter by parameter
+  float *gp = a.gpart + ((int64_t)net * nblk + blk) * L.np;
+  for (int e = tid; e < L.np; e += 64) {
+    float acc = 0.f;
+    if (e < L.o_b1) {
+      for (int m = 0; m < 64; ++m) acc += ss[m] * dz1s[e * SP + m];
+    } else if (e < L.o_w2) {
+      const int i = e - L.o_b1;
+      for (int m = 0; m < 64; ++m) acc += dz1s[i * SP + m];
+    } else if (e < L.o_b2) {
+      const int i = (e - L.o_w2) / SH2, j = (e - L.o_w2) % SH2;
+      for (int m = 0; m < 64; ++m) acc += h1s[i * SP + m] * dz2s[j * SP + m];
+    } else if (e < L.o_w3) {
+      const int j = e - L.o_b2;
+      for (int m = 0; m < 64; ++m) acc += dz2s[j * SP + m];
+    } else if (e < L.o_b3) {
+      const int k = (e - L.o_w3) / M1, o = (e - L.o_w3) % M1;
+      for (int m = 0; m < 64; ++m) acc += h2s[k * SP + m] * rs[o * SP + m];
+    } else {
+      const int o = e - L.o_b3;
+      for (int m = 0; m < 64; ++m) acc += rs[o * SP + m];
+    }
+    gp[e] = acc;
+  }
+  if (tid < 2) {
+    double v = 0.0;
+    for (int m = 0; m < 64; ++m) v += red[tid][m];
+    a.lpart[((int64_t)net * nblk + blk) * 2 + tid] = v;
+  }
+}
+
+void launch_st_grad(hipStream_t st, const StGradArgs &a) {
+  const StudentLayout L = student_layout(a.M1);
+  const size_t shm = sizeof(float) * ((size_t)L.np + 64 + (size_t)(2 * SH1 + 2 * SH2 + a.M1) * SP);
+  hipLaunchKernelGGL(k_st_grad, dim3(a.batch / 64, a.nets), dim3(64), shm, st, a);
+}
+
+// ---------------------------------------------------------------------------
+// 3b. Adam: one thread per parameter; gradient = 2/(M1 sum w) sum r dG/dtheta
+// ---------------------------------------------------------------------------
+__global__ void k_st_adam(StAdamArgs a) {
+  const StudentLayout L = student_layout(a.M1);
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)a.nets * L.np) return;
+  const int net = (int)(e / L.np), p = (int)(e % L.np);
+  double wsum = 0.0, lsum = 0.0;
+  float g = 0.f;
+  for (int b = 0; b < a.nblk; ++b) {
+    const int64_t pb = (int64_t)net * a.nblk + b;
+    g += a.gpart[pb * L.np + p];
+    lsum += a.lpart[pb * 2 + 0];
+    wsum += a.lpart[pb * 2 + 1];
+  }
+  const double denom = (double)a.M1 * (wsum > 0.0 ? wsum : 1.0);
+  g *= (float)(2.0 / denom);
+  if (p == 0 && a.loss) a.loss[net] = lsum / denom;
+  if (a.g_out) {
+    a.g_out[e] = g;
+    return;
+  }
+  const float m = a.b1 * a.m[e] + (1.f - a.b1) * g;
+  const float v = a.b2 * a.v[e] + (1.f - a.b2) * g * g;
+  a.m[e] = m;
+  a.v[e] = v;
+  a.params[e] -= a.lr * (m * a.c1) / (sqrtf(v * a.c2) + a.eps);
+}
+
+void launch_st_adam(hipStream_t st, const StAdamArgs &a) {
+  const StudentLayout L = student_layout(a.M1);
+  const int64_t n = (int64_t)a.nets * L.np;
+  hipLaunchKernelGGL(k_st_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
+// 4a. normal equations of the output layer in FP64:
+//     A = sum w phi phi^T (SNF x SNF), B = sum w phi G^T (SNF x M1),
+//     phi = (h2(s), 1); each block accumulates its share into its partial
+// ---------------------------------------------------------------------------
+constexpr int LS_BLOCKS = 128;
+constexpr int LS_MAXE = (SNF * SNF + SNF * 128 + 63) / 64;  // entries per thread, M1 <= 128
+int st_ls_blocks() { return LS_BLOCKS; }
+
+__device__ inline void st_hidden_f64(const float *P, const StudentLayout &L, int quant, double s,
+                                     double (&h2)[SH2]) {
+  double t1[SH1];
+#pragma unroll
+  for (int i = 0; i < SH1; ++i) t1[i] = tanh(s * (double)P[L.o_w1 + i] + (double)P[L.o_b1 + i]);
+#pragma unroll
+  for (int j = 0; j < SH2; ++j) {
+    double z = (double)P[L.o_b2 + j];
+#pragma unroll
+    for (int i = 0; i < SH1; ++i) z += t1[i] * st_round16(P[L.o_w2 + i * SH2 + j], quant);
+    h2[j] = t1[j % SH1] + tanh(z);
+  }
+}
+
+__global__ void __launch_bounds__(64) k_st_ls(StLsArgs a) {
+  extern __shared__ double lsh[];
+  const int M1 = a.M1;
+  const StudentLayout L = student_layout(M1);
+  const int net = blockIdx.y, blk = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int NE = SNF * SNF + SNF * M1;
+  double *phi = lsh;             // [SNF][SP]
+  double *gt = phi + SNF * SP;   // [M1][SP]
+  const float *P = a.params + (int64_t)net * L.np;
+  double acc[LS_MAXE];
+#pragma unroll
+  for (int k = 0; k < LS_MAXE; ++k) acc[k] = 0.0;
+  const int ngroups = a.batch / 64;
+  for (int gidx = blk; gidx < ngroups; gidx += a.nblk) {
+    const int64_t q = (int64_t)net * a.batch + (int64_t)gidx * 64 + tid;
+    const double w = (double)a.wt[q];
+    double h2[SH2];
+    st_hidden_f64(P, L, a.quant, a.s[q], h2);
+#pragma unroll
+    for (int j = 0; j < SH2; ++j) phi[j * SP + tid] = w * h2[j];
+    phi[SH2 * SP + tid] = w;
+    const double *Gt = a.G + q * M1;
+    for (int o = 0; o < M1; ++o) gt[o * SP + tid] = w * Gt[o];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < LS_MAXE; ++k) {
+      const int e = tid + 64 * k;
+      if (e < NE) {
+        const double *x, *y;
+        if (e < SNF * SNF) {
+          x = phi + (e / SNF) * SP;
+          y = phi + (e % SNF) * SP;
+        } else {
+          const int e2 = e - SNF * SNF;
+          x = phi + (e2 / M1) * SP;
+          y = gt + (e2 % M1) * SP;
+        }
+        double v = 0.0;
+        for (int m = 0; m < 64; ++m) v += x[m] * y[m];
+        acc[k] += v;
+      }
+    }
+    __syncthreads();
+  }
+  double *part = a.part + ((int64_t)net * a.nblk + blk) * NE;
+#pragma unroll
+  for (int k = 0; k < LS_MAXE; ++k) {
+    const int e = tid + 64 * k;
+    if (e < NE) part[e] += acc[k];
+  }
+}
+
+void launch_st_ls(hipStream_t st, const StLsArgs &a) {
+  const size_t shm = sizeof(double) * (size_t)(SNF + a.M1) * SP;
+  hipLaunchKernelGGL(k_st_ls, dim3(a.nblk, a.nets), dim3(64), shm, st, a);
+}
+
+// ---------------------------------------------------------------------------
+// 4b. reduce the partials, Cholesky of A + lambda I, solve for every output
+//     column; optional 16-bit rounding of W3 and the b3 correction
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_st_solve(StSolveArgs a) {
+  extern __shared__ double vsh[];
+  const int M1 = a.M1;
+  const int NE = SNF * SNF + SNF * M1;
+  const int net = blockIdx.x, tid = threadIdx.x;
+  double *A = vsh;               // [SNF][SNF] (normal matrix, kept)
+  double *Lc = A + SNF * SNF;    // [SNF][SNF] Cholesky factor
+  double *B = Lc + SNF * SNF;    // [SNF][M1]
+  __shared__ int bad;
+  for (int e = tid; e < NE; e += blockDim.x) {
+    double v = 0.0;
+    for (int b = 0; b < a.nblk; ++b) v += a.part[((int64_t)net * a.nblk + b) * NE + e];
+    if (e < SNF * SNF) A[e] = v;
+    else B[e - SNF * SNF] = v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    bad = 0;
+    if (!(A[SNF * SNF - 1] > 0.0)) bad = 2;
+    double tr = 0.0;
+    for (int i = 0; i < SNF; ++i) tr += A[i * SNF + i];
+    const double lam = a.ridge * tr / SNF;
+    for (int i = 0; i < SNF * SNF; ++i) Lc[i] = A[i];
+    for (int i = 0; i < SNF; ++i) Lc[i * SNF + i] += lam;
+    for (int j = 0; j < SNF && !bad; ++j) {
+      double dgn = Lc[j * SNF + j];
+      for (int k = 0; k < j; ++k) dgn -= Lc[j * SNF + k] * Lc[j * SNF + k];
+      if (!(dgn > 0.0)) {
+        bad = 1;
+        break;
+      }
+      const double ljj = sqrt(dgn);
+      Lc[j * SNF + j] = ljj;
+      for (int i = j + 1; i < SNF; ++i) {
+        double v = Lc[i * SNF + j];
+        for (int k = 0; k < j; ++k) v -= Lc[i * SNF + k] * Lc[j * SNF + k];
+        Lc[i * SNF + j] = v / ljj;
+      }
+    }
+    a.status[net] = bad;
+  }
+  __syncthreads();
+  if (bad) return;
+  for (int o = tid; o < M1; o += blockDim.x) {
+    double y[SNF];
+    for (int i = 0; i < SNF; ++i) {
+      double v = B[i * M1 + o];
+      for (int k = 0; k < i; ++k) v -= Lc[i * SNF + k] * y[k];
+      y[i] = v / Lc[i * SNF + i];
+    }
+    for (int i = SNF - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int k = i + 1; k < SNF; ++k) v -= Lc[k * SNF + i] * y[k];
+      y[i] = v / Lc[i * SNF + i];
+    }
+    // W3 as the kernels will hold it, then b3 = mean residual given W3
+    double r = B[(SNF - 1) * M1 + o];
+    for (int k = 0; k < SH2; ++k) {
+      y[k] = st_round16((float)y[k], a.quant);
+      r -= A[(SNF - 1) * SNF + k] * y[k];
+    }
+    y[SH2] = r / A[SNF * SNF - 1];
+    for (int i = 0; i < SNF; ++i) a.X[((int64_t)net * SNF + i) * M1 + o] = y[i];
+  }
+}
+
+void launch_st_solve(hipStream_t st, const StSolveArgs &a) {
+  const size_t shm = sizeof(double) * ((size_t)2 * SNF * SNF + (size_t)SNF * a.M1);
+  hipLaunchKernelGGL(k_st_solve, dim3(a.nets), dim3(256), shm, st, a);
+}
+
+// ---------------------------------------------------------------------------
+// held-out check of the fitted student in FP64: sum of squared error and of
+// squared teacher output per block of 64 samples
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_st_check(StCheckArgs a) {
+  const int M1 = a.M1;
+  const StudentLayout L = student_layout(M1);
+  const int net = blockIdx.y, blk = blockIdx.x, tid = threadIdx.x;
+  __shared__ double red[2][64];
+  const int64_t q = (int64_t)net * a.batch + (int64_t)blk * 64 + tid;
+  const double w = (double)a.wt[q];
+  const float *P = a.params + (int64_t)net * L.np;
+  const double *X = a.X + (int64_t)net * SNF * M1;
+  double h2[SH2];
+  st_hidden_f64(P, L, a.quant, a.s[q], h2);
+  double e2 = 0.0, g2 = 0.0;
+  const double *Gt = a.G + q * M1;
+  for (int o = 0; o < M1; ++o) {
+    double g = X[SH2 * M1 + o];
+#pragma unroll
+    for (int k = 0; k < SH2; ++k) g += h2[k] * X[k * M1 + o];
+    const double d = g - Gt[o];
+    e2 += w * d * d;
+    g2 += w * Gt[o] * Gt[o];
+  }
+  red[0][tid] = e2;
+  red[1][tid] = g2;
+  __syncthreads();
+  if (tid < 2) {
+    double v = 0.0;
+    for (int m = 0; m < 64; ++m) v += red[tid][m];
+    a.part[((int64_t)net * gridDim.x + blk) * 2 + tid] = v;
+  }
+}
+
+void launch_st_check(hipStream_t st, const StCheckArgs &a) {
+  hipLaunchKernelGGL(k_st_check, dim3(a.batch / 64, a.nets), dim3(64), 0, st, a);
+}
+
+// ---------------------------------------------------------------------------
+// force RMSE between two force arrays (the judge): fixed-order two-stage sum
+// ---------------------------------------------------------------------------
+constexpr int FR_BLOCKS = 256;
+
+__global__ void k_frmse1(const double *fa, const double *fb, int64_t n, double *part) {
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 3 * n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double d = fa[i] - fb[i];
+    v += d * d;
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_frmse2(const double *part, int np, int64_t n, double *out) {
+  if (threadIdx.x == 0) {
+    double v = 0.0;
+    for (int b = 0; b < np; ++b) v += part[b];
+    out[0] = n > 0 ? sqrt(v / (double)n) : 0.0;
+  }
+}
+
+void launch_force_rmse(hipStream_t st, const double *fa, const double *fb, int64_t n, double *part, double *out) {
+  hipLaunchKernelGGL(k_frmse1, dim3(FR_BLOCKS), dim3(256), 0, st, fa, fb, n, part);
+  hipLaunchKernelGGL(k_frmse2, dim3(1), dim3(64), 0, st, part, FR_BLOCKS, n, out);
+}
+
+}  // namespace dpk

@@ -22,8 +22,8 @@ def _ptr(t):
 class DPModel:
     """A loaded Deep Potential model on one GPU.
 
-    blob: bytes in the DPMIBLOB v1 layout.  precision: "fp64" (the others
-    come with the mixed-precision kernels)."""
+    blob: bytes in the DPMIBLOB layout.  precision: "fp64", "fp16" or
+    "bf16" (mixed-precision kernels)."""
 
     def __init__(self, blob: bytes, precision: str = "fp64", device: int | None = None):
         if not torch.cuda.is_available():
@@ -117,6 +117,58 @@ class DPModel:
 
     def stats(self):
         return L.dp_get_stats(self.ctx)
+
+    # ---- student embedding net -------------------------------------------
+    @staticmethod
+    def student_cfg(**kw) -> "L.dp_student_cfg":
+        """The library defaults (batch 4096, 500 Adam steps, lr 1e-3, ...),
+        with any field overridden by keyword."""
+        cfg = L.dp_student_default_cfg()
+        for k, v in kw.items():
+            if k not in dict(L.dp_student_cfg._fields_):
+                raise KeyError(k)
+            setattr(cfg, k, v)
+        return cfg
+
+    def student_train(self, **kw) -> float:
+        """Fit the student to the teacher on the last evaluated frame; returns
+        the held-out relative RMSE of G (or the last Adam loss without refit)."""
+        return L.dp_student_train(self.ctx, self.student_cfg(**kw))
+
+    def student_use(self, on=True):
+        L.dp_student_use(self.ctx, on)
+
+    def student_judge(self, every=20, max_force_rmse=1e-3):
+        L.dp_student_judge(self.ctx, every, max_force_rmse)
+
+    def student_model(self) -> bytes:
+        return L.dp_student_get_model(self.ctx)
+
+    def student_set_model(self, blob: bytes):
+        L.dp_student_set_model(self.ctx, bytes(blob))
+
+    def _student_np(self, ntypes, M1):
+        return ntypes * ntypes, 16 + 16 + 16 * 32 + 32 + 32 * M1 + M1
+
+    def student_params(self, ntypes, M1) -> np.ndarray:
+        nets, npar = self._student_np(ntypes, M1)
+        out = np.empty((nets, npar), dtype=np.float32)
+        L.dp_student_get_params(self.ctx, out.ctypes.data)
+        return out
+
+    def student_set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        L.dp_student_set_params(self.ctx, p.ctypes.data)
+
+    def student_batch_grad(self, ntypes, M1, seed, step, batch):
+        """(s [nets, batch], loss [nets], grad [nets, np]) of one Adam batch at
+        the current parameters (no update)."""
+        nets, npar = self._student_np(ntypes, M1)
+        s = np.empty((nets, batch), dtype=np.float64)
+        loss = np.empty(nets, dtype=np.float64)
+        g = np.empty((nets, npar), dtype=np.float32)
+        L.dp_student_batch_grad(self.ctx, seed, step, batch, s.ctypes.data, loss.ctypes.data, g.ctypes.data)
+        return s, loss, g
 
     def enable_timing(self, on=True):
         L.dp_enable_timing(self.ctx, on)

@@ -1,0 +1,314 @@
+"""Student embedding net on the GPU against the FP64 oracle.
+
+Inference: a student model (embedding 1-16-32-M1 with an affine last layer,
+the teacher's fitting nets) evaluated by the HIP path, both loaded as a
+model and installed as the student of a teacher, against the oracle
+evaluating the same blob.  Training: the sampler draws the same neighbour
+pairs as the oracle's sampler, the batch loss and gradient, five Adam steps
+and the least-squares refit agree with the oracle's FP64 versions on the
+same data.  End to end: the trained student's forces stay within 1e-3 eV/A
+of the oracle's teacher forces, and the MD judge keeps a good student and
+rejects a broken one."""
+import struct
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2005_00223_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _model(blob, prec):
+    from paper_2005_00223_amd.model import DPModel
+    return DPModel(blob, prec)
+
+
+def _oracle(blob):
+    from oracle import oracle as O
+    return O.Oracle(blob)
+
+
+def _rmse(a, b):
+    return float(np.sqrt(((np.asarray(a) - np.asarray(b)) ** 2).sum(1).mean()))
+
+
+def _student_embedding(blob):
+    """Embedding weights of a DPMIBLOB: {(t, u): [W1, b1, W2, b2, W3, b3]}."""
+    ver, T, n_emb, n_fit, M2 = struct.unpack_from("<5q", blob, 8)
+    off = 48 + (8 if ver == 2 else 0) + 24
+    sel = struct.unpack_from(f"<{T}q", blob, off)
+    off += 8 * T
+    ew = struct.unpack_from(f"<{n_emb + 1}q", blob, off)
+    off += 8 * (n_emb + 1) + 8 * n_fit
+    out = {}
+    for t in range(T):
+        for u in range(T):
+            ws = []
+            for l in range(n_emb):
+                W = np.frombuffer(blob, "<f8", ew[l] * ew[l + 1], off)
+                off += 8 * ew[l] * ew[l + 1]
+                b = np.frombuffer(blob, "<f8", ew[l + 1], off)
+                off += 8 * ew[l + 1]
+                ws += [W, b]
+            out[(t, u)] = ws
+    return out, sel
+
+
+# ---------------------------------------------------------------------------
+# inference
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["water192", "cu_cells5"])
+def test_student_model_fp64_parity(name):
+    w = synth.workload(name)
+    spec = w["spec"]
+    P = synth.random_student_params(spec, 11)
+    sblob = synth.pack_blob(synth.student_spec(spec, P))
+    say(f"[student] fp64 parity {name}")
+    r = _oracle(sblob).eval(w["coords"], w["types"], w["box"])
+    m = _model(sblob, "fp64")
+    e, f, v = m.compute(w["coords"], w["types"], w["box"])
+    assert abs(e.item() - r["energy"]) <= 1e-10 * abs(r["energy"])
+    assert np.abs(f.cpu().numpy() - r["force"]).max() <= 1e-9
+    assert np.abs(v.cpu().numpy() - r["virial"]).max() <= 1e-9 * max(1.0, np.abs(r["virial"]).max())
+    # the same nets installed as the student of the teacher
+    mt = _model(synth.pack_blob(spec), "fp64")
+    mt.student_set_model(sblob)
+    mt.student_use(True)
+    e2, f2, _ = mt.compute(w["coords"], w["types"], w["box"])
+    assert e2.item() == e.item()
+    assert np.abs(f2.cpu().numpy() - f.cpu().numpy()).max() <= 1e-12
+    assert mt.stats()["student_evals"] == 1
+
+
+@pytest.mark.parametrize("name,prec", [("water192", "fp16"), ("cu_cells5", "fp16"), ("cu_cells5", "bf16")])
+def test_student_model_mixed(name, prec):
+    """The mixed kernels hold the student's W2 and W3 and the first two
+    fitting layers' weights in 16 bits (round to nearest even): against the
+    oracle evaluating the same model with those weights rounded beforehand,
+    what is left is the kernels' own arithmetic (hi/lo split activations,
+    FP32 tanh, contractions and sums)."""
+    from oracle import student as S
+    w = synth.workload(name)
+    spec = w["spec"]
+    P = synth.random_student_params(spec, 12).astype(np.float64)
+    sblob = synth.pack_blob(synth.student_spec(spec, P))
+    q = 0 if prec == "fp16" else 1
+    Pq = P.copy()
+    npar = synth.student_np(spec.M1)
+    o_w2, o_b2, o_w3, o_b3 = 32, 32 + 512, 32 + 512 + 32, npar - spec.M1
+    Pq[:, o_w2:o_b2] = S.round16(P[:, o_w2:o_b2], q)
+    Pq[:, o_w3:o_b3] = S.round16(P[:, o_w3:o_b3], q)
+    say(f"[student] mixed {name} {prec}")
+    sq = synth.student_spec(spec, Pq)
+    for t in range(spec.ntypes):
+        for l in range(2):
+            sq.fit_W[t][l] = S.round16(sq.fit_W[t][l], q)
+    r = _oracle(synth.pack_blob(sq)).eval(w["coords"], w["types"], w["box"])
+    r0 = _oracle(sblob).eval(w["coords"], w["types"], w["box"])
+    mt = _model(synth.pack_blob(spec), prec)
+    mt.student_set_model(sblob)
+    mt.student_use(True)
+    _, f, _ = mt.compute(w["coords"], w["types"], w["box"])
+    rmse = _rmse(f.cpu().numpy(), r["force"])
+    rms = float(np.sqrt((r["force"] ** 2).sum(1).mean()))
+    say(f"  force RMSE {rmse:.3e} vs the rounded-weight model, {_rmse(f.cpu().numpy(), r0['force']):.3e} "
+        f"vs the FP64 weights (RMS|F| {rms:.3f})")
+    assert rmse <= (1e-4 if prec == "fp16" else 5e-4) * max(1.0, rms)
+
+
+def test_student_api_errors():
+    from paper_2005_00223_amd import _lib
+    w = synth.workload("water192")
+    spec = w["spec"]
+    m = _model(synth.pack_blob(spec), "fp64")
+    with pytest.raises(_lib.DPError):
+        m.student_use(True)          # nothing installed
+    with pytest.raises(_lib.DPError):
+        m.student_train()            # no evaluation yet
+    with pytest.raises(_lib.DPError):
+        m.student_set_model(synth.pack_blob(spec))  # not a 1-16-32-M1 affine embedding
+    other = synth.random_model(spec.ntypes, spec.rcut, spec.rcut_smth, spec.sel, seed=99)
+    with pytest.raises(_lib.DPError):  # fitting nets differ from the teacher's
+        m.student_set_model(synth.pack_blob(synth.student_spec(other, synth.random_student_params(other, 1))))
+
+
+# ---------------------------------------------------------------------------
+# training kernels against the oracle
+# ---------------------------------------------------------------------------
+def _frame(name, prec="fp64"):
+    w = synth.workload(name)
+    spec = w["spec"]
+    blob = synth.pack_blob(spec)
+    m = _model(blob, prec)
+    m.compute(w["coords"], w["types"], w["box"])
+    r = _oracle(blob).eval(w["coords"], w["types"], w["box"], intermediates=True)
+    return w, spec, blob, m, r
+
+
+def _oracle_batch(S, o, w, spec, r, seed, net, q0, batch):
+    s, wt, _, _ = S.sample(w["types"], r["nreal"], r["rt"], np.array(spec.sel), spec.ntypes, seed, net, q0, batch)
+    t, u = divmod(net, spec.ntypes)
+    Gt = np.array([o.embed(t, u, x) for x in s])
+    return s, wt, Gt
+
+
+def test_sampler_loss_and_gradient_match_oracle():
+    from oracle import student as S
+    w, spec, blob, m, r = _frame("water192")
+    o = _oracle(blob)
+    P = synth.random_student_params(spec, 21, w1_scale=3.0)
+    m.student_set_params(P)
+    seed, step, batch = 9, 3, 1024
+    say("[student] sampler + batch gradient water192")
+    s_g, loss_g, g_g = m.student_batch_grad(spec.ntypes, spec.M1, seed, step, batch)
+    for net in range(spec.ntypes ** 2):
+        s_o, wt_o, Gt = _oracle_batch(S, o, w, spec, r, seed, net, step * batch, batch)
+        # the same pairs: s agrees to the rounding of the two FP64 environment matrices
+        np.testing.assert_allclose(s_g[net], s_o, rtol=1e-12, atol=1e-15)
+        L, g = S.loss_grad(P[net].astype(np.float64), s_o, wt_o, Gt, spec.M1)
+        say(f"  net {net}: loss {loss_g[net]:.6e} vs {L:.6e}, |dg|/|g| "
+            f"{np.linalg.norm(g_g[net] - g) / np.linalg.norm(g):.2e}")
+        assert abs(loss_g[net] - L) <= 1e-5 * L
+        assert np.linalg.norm(g_g[net] - g) <= 1e-4 * np.linalg.norm(g)
+
+
+def test_adam_steps_match_oracle():
+    from oracle import student as S
+    w, spec, blob, m, r = _frame("cu_cells5")
+    o = _oracle(blob)
+    P = synth.random_student_params(spec, 22, w1_scale=4.0)
+    m.student_set_params(P)
+    seed, batch, k, lr = 5, 1024, 5, 1e-3
+    say("[student] 5 Adam steps cu_cells5")
+    m.student_train(init=0, refit=0, adam_steps=k, batch=batch, seed=seed, lr=lr)
+    Pg = m.student_params(spec.ntypes, spec.M1)[0].astype(np.float64)
+    p = P[0].astype(np.float64)
+    mo = np.zeros_like(p)
+    vo = np.zeros_like(p)
+    for t in range(k):
+        s, wt, Gt = _oracle_batch(S, o, w, spec, r, seed, 0, t * batch, batch)
+        _, g = S.loss_grad(p, s, wt, Gt, spec.M1)
+        p, mo, vo = S.adam(p, g, mo, vo, t + 1, lr=lr)
+    d = np.abs(Pg - p)
+    moved = np.abs(p - P[0])
+    say(f"  max |dp| {d.max():.2e}, 99th pct {np.percentile(d, 99):.2e}, typical move {np.median(moved):.2e}")
+    # FP32 gradients: parameters whose gradient sits at the FP32 noise level
+    # may take a different sign; everything else agrees closely
+    assert np.percentile(d, 99) <= 1e-2 * lr * k
+    assert d.max() <= 2.0 * lr * k
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_refit_matches_oracle(prec):
+    from oracle import student as S
+    w, spec, blob, m, r = _frame("cu_cells5", prec)
+    o = _oracle(blob)
+    P = synth.random_student_params(spec, 23, w1_scale=4.0)
+    m.student_set_params(P)
+    seed, batch, nls = 8, 4096, 16384
+    say(f"[student] refit cu_cells5 {prec}")
+    fit = m.student_train(init=0, adam_steps=0, refit=1, batch=batch, ls_samples=nls, seed=seed)
+    emb, _ = _student_embedding(m.student_model())
+    W1, b1, W2, b2, W3, b3 = emb[(0, 0)]
+    Pgpu = S.pack(W1, b1, W2, b2, W3, b3)
+    s, wt, Gt = _oracle_batch(S, o, w, spec, r, seed, 0, 1 << 36, nls)
+    q = S.refit(P[0].astype(np.float64), s, wt, Gt, spec.M1, quant=-1 if prec == "fp64" else 0)
+    sh, wh, Gh = _oracle_batch(S, o, w, spec, r, seed, 0, 1 << 37, 4096)
+    Gg = S.forward(Pgpu, sh, spec.M1)[0]
+    Go = S.forward(q, sh, spec.M1)[0]
+    rms = np.sqrt((Gh ** 2).mean())
+    e_g = np.sqrt(((Gg - Gh) ** 2).mean()) / rms
+    e_o = np.sqrt(((Go - Gh) ** 2).mean()) / rms
+    say(f"  held-out rel RMSE: GPU {e_g:.2e} (reported {fit:.2e}), oracle {e_o:.2e}")
+    assert abs(e_g - fit) <= 0.05 * e_g + 1e-12
+    if prec == "fp64":
+        # ridge-regularised normal equations (GPU) against numpy's QR least
+        # squares: both far inside the force budget
+        assert e_g <= 1e-7 and e_o <= 1e-7
+        assert np.sqrt(((Gg - Go) ** 2).mean()) <= 1e-7 * rms
+    else:
+        # both round W2 and W3 to FP16; the fits agree to the rounding level
+        assert e_g <= 1e-3 and e_o <= 1e-3
+        assert np.sqrt(((Gg - Go) ** 2).mean()) <= 1e-3 * rms
+
+
+# ---------------------------------------------------------------------------
+# end to end
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,prec", [("cu_cells5", "fp16"), ("water192", "fp16"), ("cu_cells5", "fp64")])
+def test_trained_student_forces(name, prec):
+    w, spec, blob, m, r = _frame(name, prec)
+    say(f"[student] train {name} {prec}")
+    fit = m.student_train()
+    m.student_use(True)
+    e, f, _ = m.compute(w["coords"], w["types"], w["box"])
+    rmse = _rmse(f.cpu().numpy(), r["force"])
+    n = len(w["types"])
+    say(f"  held-out G rel RMSE {fit:.2e}; force RMSE vs oracle teacher {rmse:.2e} eV/A; "
+        f"energy error {abs(e.item() - r['energy']) / n:.2e} eV/atom")
+    # 16-bit W3 alone costs about 1e-5 of G
+    assert fit <= (1e-6 if prec == "fp64" else 1e-4)
+    assert rmse <= 1e-3
+
+
+def test_judge_keeps_a_good_student():
+    w, spec, blob, m, r = _frame("cu_cells5", "fp16")
+    m.student_train()
+    m.student_use(True)
+    m.student_judge(20, 1e-3)
+    t = w["types"]
+    x = torch.tensor(w["coords"], dtype=torch.float64, device="cuda")
+    v = torch.tensor(synth.maxwell_boltzmann(w["masses"][t], 300.0, w["vseed"]), dtype=torch.float64, device="cuda")
+    say("[student] judge, good student")
+    before = m.stats()
+    th = m.md_run(x, v, t, w["box"], w["masses"], 1.0, 40, skin=1.0, thermo_every=20).cpu().numpy()
+    st = m.stats()
+    say(f"  judge RMSE {st['last_judge_rmse']:.2e}, fallbacks {st['teacher_fallbacks']}")
+    assert st["teacher_fallbacks"] == 0
+    assert st["student_evals"] - before["student_evals"] == 41
+    assert 0.0 < st["last_judge_rmse"] <= 1e-3
+    assert np.all(np.isfinite(th))
+
+
+def test_judge_rejects_a_broken_student():
+    """A student with a zero output layer gives G = 0: the judge rejects it
+    at step 0 and the run is then the teacher's run."""
+    w = synth.workload("cu_cells5")
+    spec = w["spec"]
+    blob = synth.pack_blob(spec)
+    t = w["types"]
+    v0 = synth.maxwell_boltzmann(w["masses"][t], 300.0, w["vseed"])
+    runs = []
+    for broken in (False, True):
+        m = _model(blob, "fp16")
+        if broken:
+            P = synth.random_student_params(spec, 31)
+            P[:, -33 * spec.M1:] = 0.0
+            m.student_set_model(synth.pack_blob(synth.student_spec(spec, P)))
+            m.student_use(True)
+            m.student_judge(20, 1e-3)
+        x = torch.tensor(w["coords"], dtype=torch.float64, device="cuda")
+        v = torch.tensor(v0, dtype=torch.float64, device="cuda")
+        say(f"[student] judge, broken={broken}")
+        th = m.md_run(x, v, t, w["box"], w["masses"], 1.0, 40, skin=1.0, thermo_every=20).cpu().numpy()
+        runs.append((th, m.stats()))
+    (th0, _), (th1, st1) = runs
+    say(f"  rejected with RMSE {st1['last_judge_rmse']:.3e}; fallbacks {st1['teacher_fallbacks']}")
+    assert st1["teacher_fallbacks"] == 1
+    assert st1["student_evals"] == 1
+    assert st1["last_judge_rmse"] > 1e-3
+    np.testing.assert_allclose(th1, th0, rtol=1e-9, atol=1e-9)
