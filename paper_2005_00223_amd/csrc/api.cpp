@@ -133,7 +133,7 @@ struct Workspace {
   // student judge: teacher forces / energy / virial, RMSE partial sums
   double *force_j, *energy_j, *virial_j, *rmse_part;
   // mixed-precision buffers
-  float *T32, *D32, *dD32, *Yf[MAXF + 1], *Ttf[MAXF + 1], *Gf[MAXF + 1];
+  float *T32, *dT32, *tbuf;
   int prec = -1;  // precision the buffers were laid out for
   DevStatus *status;
 };
@@ -270,13 +270,8 @@ int ensure_ws(dp_ctx *c, int64_t n, int64_t ncell, int cand_cap) {
     }
   } else {
     add((void **)&w.T32, sizeof(float) * nn * d.M1 * 4);
-    add((void **)&w.D32, sizeof(float) * rows * d.M1 * d.M2);
-    add((void **)&w.dD32, sizeof(float) * rows * d.M1 * d.M2);
-    for (int l = 1; l <= d.n_fit; ++l) {
-      add((void **)&w.Yf[l], sizeof(float) * rows * d.fw[l]);
-      add((void **)&w.Ttf[l], sizeof(float) * rows * d.fw[l]);
-      if (l < d.n_fit) add((void **)&w.Gf[l], sizeof(float) * rows * d.fw[l]);
-    }
+    add((void **)&w.dT32, sizeof(float) * nn * d.M1 * 4);
+    add((void **)&w.tbuf, sizeof(float) * fit_mix_tbuf_floats(d, rows));
   }
   add((void **)&w.eatom, sizeof(double) * nn);
   add((void **)&w.partial, sizeof(double) * 1024);
@@ -304,7 +299,6 @@ int ensure_ws(dp_ctx *c, int64_t n, int64_t ncell, int cand_cap) {
   }
   if (!nd) w.net_deriv = nullptr;
   w.G[0] = w.dD;
-  w.Gf[0] = w.dD32;
   w.prec = c->precision;
   w.base = base;
   w.bytes = off;
@@ -429,7 +423,7 @@ int upload_model(dp_ctx *c) {
 }
 
 // Mixed-precision weights: per (t,u) the LDS image of the embedding net, and
-// for the fitting net 16-bit W^T / W for the first n16 layers plus f32 copies.
+// the fused fitting net's operand images (16-bit, lane by lane).
 uint16_t h16_bits(double v, int prec) {
   const float f = (float)v;
   if (prec == 0) {
@@ -478,9 +472,10 @@ int upload_mix(dp_ctx *c) {
   const HostModel &m = c->hm;
   const Dims &d = c->dims;
   const int prec = c->precision == DP_MIX_FP16 ? 0 : 1;
+  // layers below n16 hold 16-bit weights, the later hidden layers hi + lo pairs
   const int n16 = std::min(2, d.n_fit);
-  for (int l = 0; l <= n16; ++l)
-    if (d.fw[l] % 8 != 0) return fail(c, DP_E_MODEL, "16-bit fitting layers need widths divisible by 8");
+  const char *why = nullptr;
+  if (!fit_mix_supported(d, &why)) return fail(c, DP_E_MODEL, why);
   int rc = upload_emb_mix(c, m, c->en[0]);
   if (rc) return rc;
   if (c->en[1].ready) {
@@ -488,38 +483,15 @@ int upload_mix(dp_ctx *c) {
     if (rc) return rc;
   }
   const int T = d.ntypes;
-  std::vector<unsigned char> F;
-  auto align = [&]() { F.resize((F.size() + 255) / 256 * 256, 0); };
-  FitMixOffsets fo{};
+  std::vector<const double *> Wp, bp;
   for (int t = 0; t < T; ++t)
     for (int l = 0; l <= d.n_fit; ++l) {
-      const auto &W = m.fW[m.fidx(t, l)];
-      const auto &bb = m.fb[m.fidx(t, l)];
-      const int in = d.fw[l], out = d.fw[l + 1];
-      if (l < n16) {
-        align();
-        fo.wt16[t][l] = (int64_t)F.size();
-        F.resize(F.size() + 2 * (size_t)in * out);
-        uint16_t *wt = (uint16_t *)(F.data() + fo.wt16[t][l]);
-        for (int i = 0; i < in; ++i)
-          for (int o = 0; o < out; ++o) wt[(size_t)o * in + i] = h16_bits(W[(size_t)i * out + o], prec);
-        align();
-        fo.w16[t][l] = (int64_t)F.size();
-        F.resize(F.size() + 2 * (size_t)in * out);
-        uint16_t *wn = (uint16_t *)(F.data() + fo.w16[t][l]);
-        for (size_t q = 0; q < (size_t)in * out; ++q) wn[q] = h16_bits(W[q], prec);
-      }
-      align();
-      fo.w32[t][l] = (int64_t)F.size();
-      F.resize(F.size() + 4 * (size_t)in * out);
-      float *w32 = (float *)(F.data() + fo.w32[t][l]);
-      for (size_t q = 0; q < (size_t)in * out; ++q) w32[q] = (float)W[q];
-      align();
-      fo.b32[t][l] = (int64_t)F.size();
-      F.resize(F.size() + 4 * (size_t)out);
-      float *b32 = (float *)(F.data() + fo.b32[t][l]);
-      for (int o = 0; o < out; ++o) b32[o] = (float)bb[o];
+      Wp.push_back(m.fW[m.fidx(t, l)].data());
+      bp.push_back(m.fb[m.fidx(t, l)].data());
     }
+  std::vector<unsigned char> F;
+  FitMixOffsets fo{};
+  fit_mix_pack(d, prec, n16, Wp.data(), bp.data(), F, fo);
   if (c->d_fit_mix) (void)hipFree(c->d_fit_mix);
   c->d_fit_mix = nullptr;
   HIPCHK(c, hipMalloc(&c->d_fit_mix, F.size()));
@@ -636,8 +608,7 @@ MixArgs mix_args(dp_ctx *c, int64_t rows, double *F) {
   ma.rt = w.rt;
   ma.dr = w.dr;
   ma.T32 = w.T32;
-  ma.D32 = w.D32;
-  ma.dD32 = w.dD32;
+  ma.dT32 = w.dT32;
   ma.force = F;
   ma.vir_part = w.vir_part;
   ma.net_deriv = c->keep ? w.net_deriv : nullptr;
@@ -651,17 +622,15 @@ FitMixArgs fitmix_args(dp_ctx *c, int64_t rows) {
   fa.fo = c->fmo;
   fa.w = c->d_fit_mix;
   fa.prec = c->precision == DP_MIX_FP16 ? 0 : 1;
-  fa.n16 = c->n16;
+  fa.nsplit = c->n16;
   fa.type_start = w.type_start;
   fa.atom_of_pos = w.atom_of_pos;
   fa.rows = rows;
-  fa.X0 = w.D32;
-  for (int l = 0; l <= MAXF; ++l) {
-    fa.Y[l] = w.Yf[l];
-    fa.Tt[l] = w.Ttf[l];
-    fa.G[l] = w.Gf[l];
-  }
+  fa.T32 = w.T32;
+  fa.tbuf = w.tbuf;
+  fa.dT32 = w.dT32;
   fa.eatom = w.eatom;
+  fa.inv_nc = (float)c->dims.inv_nc;
   return fa;
 }
 

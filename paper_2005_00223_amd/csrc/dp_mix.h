@@ -1,5 +1,7 @@
 // Declarations of the mixed-precision (16-bit MFMA + FP32) kernels.
 #pragma once
+#include <vector>
+
 #include "dp_internal.h"
 
 namespace dpk {
@@ -14,9 +16,8 @@ struct MixArgs {
   const double4 *xw;
   const int32_t *nlist, *nreal;
   const double4 *rt, *dr;
-  float *T32;                 // [natoms][M1][4]
-  float *D32;                 // [rows][M1*M2]
-  const float *dD32;          // [rows][M1*M2]
+  float *T32;                 // [natoms][M1][4], T / Nc (pass 1 writes, pass 2 reads nothing of it)
+  const float *dT32;          // [natoms][M1][4], dE/dT of the unscaled sum (pass 2)
   double *force;              // [natoms][3]
   double *vir_part;           // [grid][9]
   double *net_deriv;          // optional [natoms][nnei][4]
@@ -29,28 +30,39 @@ void mix_pack_net(int shape, const double *const *W, const double *const *b, int
 int mix_grid(int64_t rows);
 void launch_embed_mix(hipStream_t s, const MixArgs &a, int pass, int grid);
 
-// fitting net: layers l < n16 use 16-bit products, the rest FP32
+// fused fitting net: byte offsets of the per-type operand images
 struct FitMixOffsets {
-  int64_t wt16[MAXT][MAXF + 1];  // 16-bit W^T [out][in] (forward B operand)
-  int64_t w16[MAXT][MAXF + 1];   // 16-bit W [in][out] (backward B operand)
-  int64_t w32[MAXT][MAXF + 1];   // f32 W [in][out]
-  int64_t b32[MAXT][MAXF + 1];   // f32 b [out]
+  int64_t a0f[MAXT];            // layer 0 forward A operands (W0^T, D-slot order)
+  int64_t a0b[MAXT];            // layer 0 backward A operands (W0, chained order)
+  int64_t ahf[MAXT][MAXF];      // hidden layer l >= 1 forward (W^T)
+  int64_t ahf_lo[MAXT][MAXF];   // rounding remainders of ahf (layers >= nsplit)
+  int64_t ahb[MAXT][MAXF];      // hidden layer l >= 1 backward (W)
+  int64_t ahb_lo[MAXT][MAXF];
+  int64_t bias[MAXT][MAXF];     // f32 [256] per hidden layer
+  int64_t wout[MAXT];           // f32 [256] output weights, [256] = output bias
 };
 
 struct FitMixArgs {
   Dims d;
-  FitMixOffsets fo;           // byte offsets into w
+  FitMixOffsets fo;
   const unsigned char *w;
-  int prec, n16;
+  int prec;                   // 0 = FP16, 1 = BF16
+  int nsplit;                 // hidden layers >= nsplit carry hi + lo weights
   const int32_t *type_start;
   const int32_t *atom_of_pos;
   int64_t rows;
-  const float *X0;            // D [rows][fw0]
-  float *Y[MAXF + 1];         // Y[l] f32 [rows][fw[l]], l >= 1
-  float *Tt[MAXF + 1];        // tanh outputs [rows][fw[l]]
-  float *G[MAXF + 1];         // dE/dY[l]; G[0] = dE/dD
-  double *eatom;
+  const float *T32;           // [natoms][M1][4] (T / Nc)
+  float *tbuf;                // tanh outputs per 16-row tile
+  float *dT32;                // [natoms][M1][4] output of pass 2
+  double *eatom;              // [natoms] output of pass 1
+  float inv_nc;
 };
+
+bool fit_mix_supported(const Dims &d, const char **why);
+void fit_mix_pack(const Dims &d, int prec, int nsplit, const double *const *W, const double *const *b,
+                  std::vector<unsigned char> &buf, FitMixOffsets &fo);
+size_t fit_mix_tbuf_floats(const Dims &d, int64_t rows);
+// pass 1: forward layers and E_i; pass 2: backward to dE/dT
 void launch_fit_mix(hipStream_t s, const FitMixArgs &a, int pass);
 
 }  // namespace dpk

@@ -31,8 +31,9 @@
 // lanes][8] (16-bit), b2[S2] (f32), A3 [MT3][KS3][64][8], b3[S3] (f32).
 //
 // Pass 1: T += G R^T by an LDS transpose of G and v_mfma_f32_16x16x4f32 (K =
-// the 16 neighbours), T /= Nc, D = T T_<^T (f32 MFMA), D stored in FP32.  Pass 2: forward tangent mode (h and dh/ds in
-// two MFMA column sets sharing the A operands), then
+// the 16 neighbours), T /= Nc stored in FP32 (the fitting net forms D from
+// it).  Pass 2: dE/dT from the fitting net's backward, forward tangent mode
+// (h and dh/ds in two MFMA column sets sharing the A operands), then
 //   a = G^T dT, b = G'^T dT as split 16-bit MFMAs (hi hi + hi lo + lo hi)
 //   with G straight from registers,
 //   dE/dR = a + (R . b) e_0, and per 64 neighbours one FP64 pass of
@@ -138,7 +139,6 @@ struct Shape {
   static constexpr int P1_H2 = P1_H1 + 16 * S1 * 4;     // float [16][S2]
   static constexpr int P1_G = P1_H2 + 16 * S2 * 4;      // float [16][32]: two output tiles of G
   static constexpr int P1_R = P1_G + 16 * 32 * 4;       // float [16][4]
-  static constexpr int P1_T = 0;                        // float [S3][4], aliases H1/H2/G at the atom's end
   static constexpr int P1_BYTES = P1_R + 256;
   static constexpr int P2_H1 = 0;                       // float [2][16][S1] (h, dh)
   static constexpr int P2_H2 = P2_H1 + 2 * 16 * S1 * 4; // float [2][16][S2]
@@ -146,7 +146,7 @@ struct Shape {
   static constexpr int P2_GR = P2_R + 256;              // float [64][4]
   static constexpr int P2_DT = 0;                       // float [S3][4], aliases H1/H2 at the atom's start
   static constexpr int P2_BYTES = P2_GR + 1024;
-  static_assert(S3 * 16 <= P1_R && S3 * 16 <= P2_R, "T / dT scratch must fit the aliased buffers");
+  static_assert(S3 * 16 <= P2_R, "dT scratch must fit the aliased buffers");
 };
 
 constexpr int MIX_WAVES = 4;
@@ -283,17 +283,11 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 2) k_embed_fwd_mix(MixArgs a) 
   float *h2s = (float *)(ws + S::P1_H2);
   float *Gs = (float *)(ws + S::P1_G);
   float *Rs = (float *)(ws + S::P1_R);
-  float *Ts = (float *)(ws + S::P1_T);
-  const int MM = d.M1 * d.M2;
   int64_t p0, p1;
   wave_rows(a.rows, p0, p1);
   for (int64_t p = p0; p < p1; ++p) {
     const int i = a.atom_of_pos[p];
-    float *Dp = a.D32 + p * (int64_t)MM;
-    if (i < 0) {
-      for (int o = lane; o < MM; o += 64) Dp[o] = 0.f;
-      continue;
-    }
+    if (i < 0) continue;
     const int t = (int)a.xw[i].w;
     v4f Tacc[S::MT3];
 #pragma unroll
@@ -369,34 +363,16 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 2) k_embed_fwd_mix(MixArgs a) 
         }
       }
     }
-    // T / Nc: lane (g, n) holds T[16 mt + 4 g + r][n] for n < 4
+    // T / Nc: lane (g, n) holds T[16 mt + 4 g + r][n] for n < 4; the
+    // fitting net forms D = T T_<^T itself
     float *Tg = a.T32 + (int64_t)i * d.M1 * 4;
 #pragma unroll
     for (int mt = 0; mt < S::MT3; ++mt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int f = 16 * mt + 4 * g + r;
-        const float v = Tacc[mt][r] * (float)d.inv_nc;
-        if (n < 4) {
-          Ts[4 * f + n] = v;
-          if (f < d.M1) Tg[4 * f + n] = v;
-        }
+        if (n < 4 && f < d.M1) Tg[4 * f + n] = Tacc[mt][r] * (float)d.inv_nc;
       }
-    wsync();
-    // D = T T_<^T, K = 4 components
-    {
-      const float bb = n < d.M2 ? Ts[4 * n + g] : 0.f;
-#pragma unroll
-      for (int mt = 0; mt < S::MT3; ++mt) {
-        const v4f z = mfma32(Ts[4 * (16 * mt + n) + g], bb, v4f{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int f = 16 * mt + 4 * g + r;
-          if (f < d.M1 && n < d.M2) Dp[f * d.M2 + n] = z[r];
-        }
-      }
-    }
-    wsync();
   }
 }
 
@@ -434,7 +410,6 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 2) k_embed_bwd_mix(MixArgs a) 
   float *Rs = (float *)(ws + S::P2_R);
   float *gRs = (float *)(ws + S::P2_GR);
   float *dTs = (float *)(ws + S::P2_DT);
-  const int MM = d.M1 * d.M2;
   const double rc = d.rcut, rcs = d.rcut_smth, inv_w = 1.0 / (d.rcut - d.rcut_smth);
   double vir[9];
 #pragma unroll
@@ -445,20 +420,10 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 2) k_embed_bwd_mix(MixArgs a) 
     const int i = a.atom_of_pos[p];
     if (i < 0) continue;
     const int t = (int)a.xw[i].w;
-    // dT / Nc in LDS, rows f >= M1 zero
+    // dE/dT of the unscaled sum (from the fitting net) in LDS, rows f >= M1 zero
     {
-      const float *Ti = a.T32 + (int64_t)i * d.M1 * 4;
-      const float *dDp = a.dD32 + p * (int64_t)MM;
-      for (int o = lane; o < S::S3 * 4; o += 64) {
-        const int f = o >> 2, c = o & 3;
-        float v = 0.f;
-        if (f < d.M1) {
-          for (int b = 0; b < d.M2; ++b) v += dDp[f * d.M2 + b] * Ti[b * 4 + c];
-          if (f < d.M2)
-            for (int a2 = 0; a2 < d.M1; ++a2) v += dDp[a2 * d.M2 + f] * Ti[a2 * 4 + c];
-        }
-        dTs[o] = v * (float)d.inv_nc;
-      }
+      const float *dTi = a.dT32 + (int64_t)i * d.M1 * 4;
+      for (int o = lane; o < S::S3 * 4; o += 64) dTs[o] = (o >> 2) < d.M1 ? dTi[o] : 0.f;
     }
     wsync();
     // B operand of the contraction: K = G's slots (permuted as the layer chain), N = components

@@ -1,19 +1,34 @@
 // Mixed-precision fitting net (Fig. 1(d,g); Section V-A "Mixed-precision
-// computation"): the first two hidden layers are 16-bit matrix-core GEMMs
-// (v_mfma_f32_16x16x32_{f16,bf16}, FP32 accumulation, 16-bit weights), the
-// remaining hidden layers and the output layer run in FP32
-// (v_mfma_f32_16x16x4f32), tanh and the skip adds in FP32; E_i is converted
-// to FP64 before the reduction.  Backward mirrors it; dE/dD leaves in FP32.
-// The activation operand of each 16-bit GEMM is split into hi + lo 16-bit
-// parts on its way into LDS and multiplied twice, so only the weights are
-// rounded to 16 bits.
+// computation"), fused per tile of 16 type-sorted rows (one wave):
 //
-// Tiles: 64 rows x 64 columns per 256-thread block, four waves of 32 x 32.
-// 16-bit: K steps of 32 staged in LDS as [row][k] (A hi and lo) and [col][k]
-// (B, from a W^T copy in the forward and from W itself in the backward) with
-// a padded row stride of 40 elements, so each lane's eight K values are one
-// conflict-free 16-byte LDS read.
+//   forward   D = T T_<^T is formed on the fly from T (M1 x 4 per atom) as
+//             the B operand of the first layer, so D never reaches HBM; the
+//             hidden layers chain in registers; E_i = Y w_out + b_out.
+//   backward  from the stored tanh outputs: dE/dY through the hidden
+//             layers, then dE/dD = W_0 dz_0 one 16-feature tile (one row a
+//             of D) at a time, contracted at once with T into
+//             dE/dT[a][c] = sum_b dD[a][b] T[b][c] + [a < M2] sum_a' dD[a'][a] T[a'][c],
+//             so dD never reaches HBM either; dE/dT (times 1/Nc) is what the
+//             embedding backward consumes.
+//
+// Layout.  Every layer is computed transposed (Y^T = W^T X^T, rows of the
+// tile as the MFMA N dimension) with v_mfma_f32_16x16x32_{f16,bf16}.  The
+// f32 output leaves lane (g = l/16, n = l%16) with features 16 mt + 4 g + r
+// of row n in register r of output tile mt.  The next layer's k-step kk takes
+// in lane group g the features 16 (2 kk + v/4) + 4 g + v%4 (v = 0..7), which
+// are exactly the registers of output tiles 2 kk and 2 kk + 1, so activations
+// never leave registers; the host stores every weight operand in that
+// permuted K order, lane by lane (16 contiguous bytes per lane).  In the
+// first layer, k-step kk covers D[a][b] with a = 2 kk + g/2 and
+// b = 8 (g%2) + v.
+//
+// Precision.  Activations enter every product as hi + lo 16-bit halves
+// (about 22 bits); the weights of the layers below `nsplit` are rounded to
+// 16 bits (the paper's MIX scheme), the later hidden layers carry hi + lo
+// weights as well (three products), tanh and all sums are FP32, E_i is
+// converted to FP64 for the reduction.
 #include <cstring>
+#include <vector>
 
 #include "dp_mix.h"
 
@@ -33,6 +48,27 @@ template <> struct FT<1> {
   __device__ static v4f mma(v8 a, v8 b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
 };
 
+template <int P>
+struct FSplit {
+  typename FT<P>::v8 hi, lo;
+};
+
+// hi/lo halves of eight FP32 values x[0..3], y[0..3]
+template <int P>
+__device__ inline FSplit<P> fsplit(const float (&x)[4], const float (&y)[4]) {
+  typedef typename FT<P>::e E;
+  FSplit<P> s;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const E a = (E)x[v], b = (E)y[v];
+    s.hi[v] = a;
+    s.hi[v + 4] = b;
+    s.lo[v] = (E)(x[v] - (float)a);
+    s.lo[v + 4] = (E)(y[v] - (float)b);
+  }
+  return s;
+}
+
 __device__ inline float ftanh(float x) {
   const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);
   return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
@@ -45,294 +81,419 @@ __device__ inline int rtype(const int32_t *ts, int ntypes, int64_t r0) {
   return t;
 }
 
-enum { MF_FWD = 0, MF_BWD = 1 };
+constexpr int FIT_WAVES = 4;
 
-struct MG {
-  int layer, K, N, in, out, ntypes, last_hidden;
-  const int32_t *type_start;
-  const unsigned char *w;
-  FitMixOffsets fo;
-  const float *Xf;     // fwd: f32 input [rows][K] (also the skip source)
-  float *Tt;           // tanh out [rows][out]
-  float *Y;            // f32 out [rows][out]
-  const float *gY;     // bwd: dE/dY_out [rows][out]; NULL -> output weights
-  float *gX;           // bwd: dE/dY_in [rows][in]
-};
+// per row tile in tbuf: [layer][mt][lane][4] floats
+template <int MT>
+__device__ inline float *tile_t(float *tbuf, int64_t tile, int nl, int l, int mt) {
+  return tbuf + (((tile * nl + l) * MT + mt) * 64) * 4;
+}
 
-constexpr int TS = 40;  // padded LDS row stride (elements) for 16-bit tiles
-
-template <int P, int MODE>
-__global__ void __launch_bounds__(256) k_fitmix16(MG g) {
-  typedef typename FT<P>::e E;
+template <int P, int MT>
+__global__ void __launch_bounds__(64 * FIT_WAVES, 2) k_fit_fwd(FitMixArgs a) {
   typedef typename FT<P>::v8 V;
-  __shared__ __align__(16) E Ah[64 * TS];
-  __shared__ __align__(16) E Al[64 * TS];
-  __shared__ __align__(16) E Bs[64 * TS];
-  const int64_t r0 = (int64_t)blockIdx.x * 64;
-  const int c0 = blockIdx.y * 64;
-  if (r0 >= g.type_start[g.ntypes]) return;
-  const int t = rtype(g.type_start, g.ntypes, r0);
-  const E *Bt = (const E *)(g.w + (MODE == MF_FWD ? g.fo.wt16[t][g.layer] : g.fo.w16[t][g.layer]));
-  const float *bias = (const float *)(g.w + g.fo.b32[t][g.layer]);
-  const float *wo = (MODE == MF_BWD && g.gY == nullptr) ? (const float *)(g.w + g.fo.w32[t][g.layer + 1]) : nullptr;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wm = wv >> 1, wn = wv & 1;
-  v4f acc[2][2];
+  constexpr int KSH = (MT + 1) / 2;
+  const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+  const int64_t tile = (int64_t)blockIdx.x * FIT_WAVES + (threadIdx.x >> 6);
+  const int64_t p0 = tile * 16;
+  const int ntypes = a.d.ntypes;
+  if (p0 >= a.type_start[ntypes]) return;
+  const int t = rtype(a.type_start, ntypes, p0);
+  const int i = a.atom_of_pos[p0 + n];
+  const int M1 = a.d.M1, NL = a.d.n_fit;
+  const float4 *Ti = (const float4 *)(a.T32 + (int64_t)(i < 0 ? 0 : i) * M1 * 4);
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 Tb[8];
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int v = 0; v < 8; ++v) Tb[v] = i >= 0 ? Ti[8 * (g & 1) + v] : z4;
+  const unsigned char *W = a.w;
+  v4f acc[MT];
+  {
+    const float *b0 = (const float *)(W + a.fo.bias[t][0]);
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = v4f{0.f, 0.f, 0.f, 0.f};
-  const int lr = tid >> 2, lk = (tid & 3) * 8;  // tile loader: row (or col) and 8-wide k chunk
-  for (int k0 = 0; k0 < g.K; k0 += 32) {
-    const int k = k0 + lk;
-    // A tile [64 rows][32 k], split into hi + lo
-    {
-      float x[8];
-      const int64_t row = r0 + lr;
-      if (k < g.K) {
-        if (MODE == MF_FWD) {
-          const float4 *xp = (const float4 *)(g.Xf + row * g.K + k);
-          const float4 a0 = xp[0], a1 = xp[1];
-          x[0] = a0.x; x[1] = a0.y; x[2] = a0.z; x[3] = a0.w;
-          x[4] = a1.x; x[5] = a1.y; x[6] = a1.z; x[7] = a1.w;
-        } else {
-          const float4 *tp = (const float4 *)(g.Tt + row * g.K + k);
-          const float4 t0 = tp[0], t1 = tp[1];
-          const float4 *gp = (const float4 *)(wo ? wo + k : g.gY + row * g.K + k);
-          const float4 a0 = gp[0], a1 = gp[1];
-          const float gy[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-          const float th[8] = {t0.x, t0.y, t0.z, t0.w, t1.x, t1.y, t1.z, t1.w};
-#pragma unroll
-          for (int q = 0; q < 8; ++q) x[q] = gy[q] * (1.f - th[q] * th[q]);
-        }
-      } else {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) x[q] = 0.f;
-      }
-      V hi, lo;
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const E h = (E)x[q];
-        hi[q] = h;
-        lo[q] = (E)(x[q] - (float)h);
-      }
-      *(V *)(Ah + lr * TS + lk) = hi;
-      *(V *)(Al + lr * TS + lk) = lo;
+    for (int mt = 0; mt < MT; ++mt) {
+      const float4 b = *(const float4 *)(b0 + 16 * mt + 4 * g);
+      acc[mt] = v4f{b.x, b.y, b.z, b.w};
     }
-    // B tile as [64 cols][32 k] from Bt [N][K]
-    {
-      V v;
-      const int col = c0 + lr;
-      if (k < g.K && col < g.N) {
-        v = *(const V *)(Bt + (int64_t)col * g.K + k);
-      } else {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = (E)0.f;
-      }
-      *(V *)(Bs + lr * TS + lk) = v;
-    }
-    __syncthreads();
-    V ah[2], al[2], bf[2];
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi) {
-      const int o = (wm * 32 + mi * 16 + (lane & 15)) * TS + 8 * (lane >> 4);
-      ah[mi] = *(const V *)(Ah + o);
-      al[mi] = *(const V *)(Al + o);
-    }
-#pragma unroll
-    for (int ni = 0; ni < 2; ++ni) bf[ni] = *(const V *)(Bs + (wn * 32 + ni * 16 + (lane & 15)) * TS + 8 * (lane >> 4));
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < 2; ++ni) {
-        acc[mi][ni] = FT<P>::mma(ah[mi], bf[ni], acc[mi][ni]);
-        acc[mi][ni] = FT<P>::mma(al[mi], bf[ni], acc[mi][ni]);
-      }
-    __syncthreads();
   }
+  // layer 0: K = M1*16 features of D, formed from T
+  const V *A0 = (const V *)(W + a.fo.a0f[t]);
+  const int KS0 = M1 / 2;
+  for (int kk = 0; kk < KS0; ++kk) {
+    const float4 Ta = i >= 0 ? Ti[2 * kk + (g >> 1)] : z4;
+    float x[4], y[4];
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+    for (int v = 0; v < 4; ++v) {
+      x[v] = Ta.x * Tb[v].x + Ta.y * Tb[v].y + Ta.z * Tb[v].z + Ta.w * Tb[v].w;
+      y[v] = Ta.x * Tb[v + 4].x + Ta.y * Tb[v + 4].y + Ta.z * Tb[v + 4].z + Ta.w * Tb[v + 4].w;
+    }
+    const FSplit<P> B = fsplit<P>(x, y);
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni)
+    for (int mt = 0; mt < MT; ++mt) {
+      const V av = A0[(mt * KS0 + kk) * 64 + lane];
+      acc[mt] = FT<P>::mma(av, B.hi, acc[mt]);
+      acc[mt] = FT<P>::mma(av, B.lo, acc[mt]);
+    }
+  }
+  float Y[MT][4];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    float th[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      th[r] = ftanh(acc[mt][r]);
+      Y[mt][r] = th[r];
+    }
+    *(float4 *)(tile_t<MT>(a.tbuf, tile, NL, 0, mt) + 4 * lane) = make_float4(th[0], th[1], th[2], th[3]);
+  }
+  // hidden layers 1 .. NL-1 (identity skip)
+  for (int l = 1; l < NL; ++l) {
+    const float *bl = (const float *)(W + a.fo.bias[t][l]);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const float4 b = *(const float4 *)(bl + 16 * mt + 4 * g);
+      acc[mt] = v4f{b.x, b.y, b.z, b.w};
+    }
+    const V *Ah = (const V *)(W + a.fo.ahf[t][l]);
+    const bool split = l >= a.nsplit;
+    const V *Al = (const V *)(W + a.fo.ahf_lo[t][l]);
+#pragma unroll
+    for (int kk = 0; kk < KSH; ++kk) {
+      float x[4], y[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        x[v] = Y[2 * kk][v];
+        y[v] = (2 * kk + 1 < MT) ? Y[(2 * kk + 1 < MT) ? 2 * kk + 1 : 0][v] : 0.f;
+      }
+      const FSplit<P> B = fsplit<P>(x, y);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const V ah = Ah[(mt * KSH + kk) * 64 + lane];
+        acc[mt] = FT<P>::mma(ah, B.hi, acc[mt]);
+        acc[mt] = FT<P>::mma(ah, B.lo, acc[mt]);
+        if (split) {
+          const V al = Al[(mt * KSH + kk) * 64 + lane];
+          acc[mt] = FT<P>::mma(al, B.hi, acc[mt]);
+        }
+      }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      float th[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + wm * 32 + mi * 16 + 4 * (lane >> 4) + r;
-        const int col = c0 + wn * 32 + ni * 16 + (lane & 15);
-        if (col >= g.N) continue;
-        const float c = acc[mi][ni][r];
-        if (MODE == MF_FWD) {
-          const float th = ftanh(c + bias[col]);
-          float y = th;
-          if (g.out == g.in) y += g.Xf[row * g.in + col];
-          else if (g.out == 2 * g.in) y += g.Xf[row * g.in + (col >= g.in ? col - g.in : col)];
-          g.Tt[row * g.out + col] = th;
-          g.Y[row * g.out + col] = y;
-        } else {
-          float v = c;
-          if (g.out == g.in || g.out == 2 * g.in) {
-            v += wo ? wo[col] : g.gY[row * g.out + col];
-            if (g.out == 2 * g.in) v += wo ? wo[col + g.in] : g.gY[row * g.out + col + g.in];
-          }
-          g.gX[row * g.in + col] = v;
-        }
+        th[r] = ftanh(acc[mt][r]);
+        Y[mt][r] += th[r];
       }
+      *(float4 *)(tile_t<MT>(a.tbuf, tile, NL, l, mt) + 4 * lane) = make_float4(th[0], th[1], th[2], th[3]);
+    }
+  }
+  // output layer
+  const float *wo = (const float *)(W + a.fo.wout[t]);
+  float e = 0.f;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const float4 w4 = *(const float4 *)(wo + 16 * mt + 4 * g);
+    e += Y[mt][0] * w4.x + Y[mt][1] * w4.y + Y[mt][2] * w4.z + Y[mt][3] * w4.w;
+  }
+  e += __shfl_xor(e, 16);
+  e += __shfl_xor(e, 32);
+  if (g == 0 && i >= 0) a.eatom[i] = (double)e + (double)wo[256];
 }
 
-// FP32 layers: v_mfma_f32_16x16x4f32, K staged in steps of 16
-template <int MODE>
-__global__ void __launch_bounds__(256) k_fitmix32(MG g) {
-  __shared__ float As[64][17];
-  __shared__ float Bs[16][64];
-  const int64_t r0 = (int64_t)blockIdx.x * 64;
-  const int c0 = blockIdx.y * 64;
-  if (r0 >= g.type_start[g.ntypes]) return;
-  const int t = rtype(g.type_start, g.ntypes, r0);
-  const float *W = (const float *)(g.w + g.fo.w32[t][g.layer]);
-  const float *bias = (const float *)(g.w + g.fo.b32[t][g.layer]);
-  const float *wo = (MODE == MF_BWD && g.gY == nullptr) ? (const float *)(g.w + g.fo.w32[t][g.layer + 1]) : nullptr;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wm = wv >> 1, wn = wv & 1;
-  v4f acc[2][2];
+template <int P, int MT>
+__global__ void __launch_bounds__(64 * FIT_WAVES, 2) k_fit_bwd(FitMixArgs a) {
+  typedef typename FT<P>::v8 V;
+  constexpr int KSH = (MT + 1) / 2;
+  __shared__ float4 sh[FIT_WAVES][16][16];  // per wave: sum_b dD[a][b] T[b] for a < 16
+  const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15, wv = threadIdx.x >> 6;
+  const int64_t tile = (int64_t)blockIdx.x * FIT_WAVES + wv;
+  const int64_t p0 = tile * 16;
+  const int ntypes = a.d.ntypes;
+  if (p0 >= a.type_start[ntypes]) return;
+  const int t = rtype(a.type_start, ntypes, p0);
+  const int i = a.atom_of_pos[p0 + n];
+  const int M1 = a.d.M1, NL = a.d.n_fit;
+  const unsigned char *W = a.w;
+  // dE/dY of the last hidden layer = w_out
+  float dY[MT][4];
+  {
+    const float *wo = (const float *)(W + a.fo.wout[t]);
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+    for (int mt = 0; mt < MT; ++mt) {
+      const float4 w4 = *(const float4 *)(wo + 16 * mt + 4 * g);
+      dY[mt][0] = w4.x;
+      dY[mt][1] = w4.y;
+      dY[mt][2] = w4.z;
+      dY[mt][3] = w4.w;
+    }
+  }
+  // hidden layers NL-1 .. 1: dY_{l-1} = W_l dz_l + dY_l, dz_l = dY_l (1 - t_l^2)
+  for (int l = NL - 1; l >= 1; --l) {
+    const V *Ah = (const V *)(W + a.fo.ahb[t][l]);
+    const bool split = l >= a.nsplit;
+    const V *Al = (const V *)(W + a.fo.ahb_lo[t][l]);
+    v4f acc[MT];
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < g.K; k0 += 16) {
+    for (int mt = 0; mt < MT; ++mt) acc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + q * 256;
-      const int rr = e >> 4, kk = e & 15, k = k0 + kk;
-      float v = 0.f;
-      if (k < g.K) {
-        const int64_t row = r0 + rr;
-        if (MODE == MF_FWD) {
-          v = g.Xf[row * g.K + k];
-        } else {
-          const float th = g.Tt[row * g.K + k];
-          const float gy = wo ? wo[k] : g.gY[row * g.K + k];
-          v = gy * (1.f - th * th);
+    for (int kk = 0; kk < KSH; ++kk) {
+      float x[4], y[4];
+      {
+        const float4 t0 = *(const float4 *)(tile_t<MT>(a.tbuf, tile, NL, l, 2 * kk) + 4 * lane);
+        const float tv[4] = {t0.x, t0.y, t0.z, t0.w};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) x[v] = dY[2 * kk][v] * (1.f - tv[v] * tv[v]);
+      }
+      if (2 * kk + 1 < MT) {
+        const int m1 = (2 * kk + 1 < MT) ? 2 * kk + 1 : 0;
+        const float4 t1 = *(const float4 *)(tile_t<MT>(a.tbuf, tile, NL, l, m1) + 4 * lane);
+        const float tv[4] = {t1.x, t1.y, t1.z, t1.w};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) y[v] = dY[m1][v] * (1.f - tv[v] * tv[v]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) y[v] = 0.f;
+      }
+      const FSplit<P> B = fsplit<P>(x, y);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const V ah = Ah[(mt * KSH + kk) * 64 + lane];
+        acc[mt] = FT<P>::mma(ah, B.hi, acc[mt]);
+        acc[mt] = FT<P>::mma(ah, B.lo, acc[mt]);
+        if (split) {
+          const V al = Al[(mt * KSH + kk) * 64 + lane];
+          acc[mt] = FT<P>::mma(al, B.hi, acc[mt]);
         }
       }
-      As[rr][kk] = v;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + q * 256;
-      const int kk = e >> 6, cc = e & 63, k = k0 + kk, c = c0 + cc;
-      float v = 0.f;
-      if (k < g.K && c < g.N) v = (MODE == MF_FWD) ? W[(int64_t)k * g.N + c] : W[(int64_t)c * g.K + k];
-      Bs[kk][cc] = v;
-    }
-    __syncthreads();
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int ks = 0; ks < 16; ks += 4) {
-      float af[2], bf[2];
-#pragma unroll
-      for (int mi = 0; mi < 2; ++mi) af[mi] = As[wm * 32 + mi * 16 + (lane & 15)][ks + (lane >> 4)];
-#pragma unroll
-      for (int ni = 0; ni < 2; ++ni) bf[ni] = Bs[ks + (lane >> 4)][wn * 32 + ni * 16 + (lane & 15)];
-#pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
-          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
-    }
-    __syncthreads();
+      for (int r = 0; r < 4; ++r) dY[mt][r] += acc[mt][r];
   }
+  // dz_0 as the B operands of the first layer's backward
+  FSplit<P> Bz[KSH];
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int kk = 0; kk < KSH; ++kk) {
+    float x[4], y[4];
+    const float4 t0 = *(const float4 *)(tile_t<MT>(a.tbuf, tile, NL, 0, 2 * kk) + 4 * lane);
+    const float tv0[4] = {t0.x, t0.y, t0.z, t0.w};
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni)
+    for (int v = 0; v < 4; ++v) x[v] = dY[2 * kk][v] * (1.f - tv0[v] * tv0[v]);
+    if (2 * kk + 1 < MT) {
+      const int m1 = (2 * kk + 1 < MT) ? 2 * kk + 1 : 0;
+      const float4 t1 = *(const float4 *)(tile_t<MT>(a.tbuf, tile, NL, 0, m1) + 4 * lane);
+      const float tv1[4] = {t1.x, t1.y, t1.z, t1.w};
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + wm * 32 + mi * 16 + 4 * (lane >> 4) + r;
-        const int col = c0 + wn * 32 + ni * 16 + (lane & 15);
-        if (col >= g.N) continue;
-        const float c = acc[mi][ni][r];
-        if (MODE == MF_FWD) {
-          const float th = ftanh(c + bias[col]);
-          float y = th;
-          if (g.out == g.in) y += g.Xf[row * g.in + col];
-          else if (g.out == 2 * g.in) y += g.Xf[row * g.in + (col >= g.in ? col - g.in : col)];
-          g.Tt[row * g.out + col] = th;
-          g.Y[row * g.out + col] = y;
-        } else {
-          float v = c;
-          if (g.out == g.in || g.out == 2 * g.in) {
-            v += wo ? wo[col] : g.gY[row * g.out + col];
-            if (g.out == 2 * g.in) v += wo ? wo[col + g.in] : g.gY[row * g.out + col + g.in];
-          }
-          g.gX[row * g.in + col] = v;
-        }
+      for (int v = 0; v < 4; ++v) y[v] = dY[m1][v] * (1.f - tv1[v] * tv1[v]);
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) y[v] = 0.f;
+    }
+    Bz[kk] = fsplit<P>(x, y);
+  }
+  // dD one row a of D (16 features b) at a time, contracted with T
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 *Ti = (const float4 *)(a.T32 + (int64_t)(i < 0 ? 0 : i) * M1 * 4);
+  float4 Tq[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Tq[r] = i >= 0 ? Ti[4 * g + r] : z4;
+  float dT2[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dT2[r][c] = 0.f;
+  const V *A0 = (const V *)(W + a.fo.a0b[t]);
+  float4 *dTi = (float4 *)(a.dT32 + (int64_t)(i < 0 ? 0 : i) * M1 * 4);
+  const float s = a.inv_nc;
+  for (int aa = 0; aa < M1; ++aa) {
+    v4f c = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < KSH; ++kk) {
+      const V av = A0[(aa * KSH + kk) * 64 + lane];
+      c = FT<P>::mma(av, Bz[kk].hi, c);
+      c = FT<P>::mma(av, Bz[kk].lo, c);
+    }
+    // c[r] = dE/dD[row n][a = aa][b = 4 g + r]
+    const float4 Ta = i >= 0 ? Ti[aa] : z4;
+    float4 pc;
+    pc.x = c[0] * Tq[0].x + c[1] * Tq[1].x + c[2] * Tq[2].x + c[3] * Tq[3].x;
+    pc.y = c[0] * Tq[0].y + c[1] * Tq[1].y + c[2] * Tq[2].y + c[3] * Tq[3].y;
+    pc.z = c[0] * Tq[0].z + c[1] * Tq[1].z + c[2] * Tq[2].z + c[3] * Tq[3].z;
+    pc.w = c[0] * Tq[0].w + c[1] * Tq[1].w + c[2] * Tq[2].w + c[3] * Tq[3].w;
+    pc.x += __shfl_xor(pc.x, 16);
+    pc.y += __shfl_xor(pc.y, 16);
+    pc.z += __shfl_xor(pc.z, 16);
+    pc.w += __shfl_xor(pc.w, 16);
+    pc.x += __shfl_xor(pc.x, 32);
+    pc.y += __shfl_xor(pc.y, 32);
+    pc.z += __shfl_xor(pc.z, 32);
+    pc.w += __shfl_xor(pc.w, 32);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      dT2[r][0] += c[r] * Ta.x;
+      dT2[r][1] += c[r] * Ta.y;
+      dT2[r][2] += c[r] * Ta.z;
+      dT2[r][3] += c[r] * Ta.w;
+    }
+    if (g == 0) {
+      if (aa < 16) sh[wv][n][aa] = pc;
+      else if (i >= 0) dTi[aa] = make_float4(pc.x * s, pc.y * s, pc.z * s, pc.w * s);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (i >= 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int b = 4 * g + r;
+      if (b < M1) {
+        const float4 q = sh[wv][n][b];
+        dTi[b] = make_float4((q.x + dT2[r][0]) * s, (q.y + dT2[r][1]) * s, (q.z + dT2[r][2]) * s,
+                             (q.w + dT2[r][3]) * s);
       }
+    }
+  }
 }
 
-__global__ void __launch_bounds__(256) k_fitmix_out(const int32_t *type_start, int ntypes, const int32_t *atom_of_pos,
-                                                    const unsigned char *w, FitMixOffsets fo, int L, int width,
-                                                    const float *Y, int64_t rows_cap, double *eatom) {
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= rows_cap || row >= type_start[ntypes]) return;
-  const int atom = atom_of_pos[row];
-  if (atom < 0) return;
-  const int t = rtype(type_start, ntypes, row);
-  const float *wv = (const float *)(w + fo.w32[t][L]);
-  float s = 0.f;
-  for (int o = lane; o < width; o += 64) s += Y[row * width + o] * wv[o];
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-  if (lane == 0) eatom[atom] = (double)s + (double)((const float *)(w + fo.b32[t][L]))[0];
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+constexpr int FIT_MT = 15;  // hidden width 240
+
+bool fit_mix_supported(const Dims &d, const char **why) {
+  const int H = d.fw[1];
+  for (int l = 1; l <= d.n_fit; ++l)
+    if (d.fw[l] != H) return *why = "mixed fitting net needs equal hidden widths", false;
+  if (H != 16 * FIT_MT) return *why = "mixed fitting net is built for hidden width 240", false;
+  if (d.M2 != 16) return *why = "mixed fitting net needs M2 = 16", false;
+  if (d.M1 % 2 != 0 || d.M1 > 128) return *why = "mixed fitting net needs an even M1 <= 128", false;
+  if (d.n_fit < 1 || d.n_fit > MAXF) return *why = "mixed fitting net needs 1..4 hidden layers", false;
+  return true;
 }
 
-template <int P>
-static void run(hipStream_t s, const FitMixArgs &a, int pass) {
-  const Dims &d = a.d;
-  const int L = d.n_fit;
-  const unsigned gm = (unsigned)((a.rows + 63) / 64);
-  for (int l = 0; l < L && pass == 1; ++l) {
-    MG g{};
-    g.layer = l;
-    g.in = d.fw[l];
-    g.out = d.fw[l + 1];
-    g.K = g.in;
-    g.N = g.out;
-    g.ntypes = d.ntypes;
-    g.type_start = a.type_start;
-    g.w = a.w;
-    g.fo = a.fo;
-    g.Xf = (l == 0) ? a.X0 : a.Y[l];
-    g.Tt = a.Tt[l + 1];
-    g.Y = a.Y[l + 1];
-    dim3 grid(gm, (unsigned)((g.N + 63) / 64));
-    if (l < a.n16) hipLaunchKernelGGL((k_fitmix16<P, MF_FWD>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((k_fitmix32<MF_FWD>), grid, dim3(256), 0, s, g);
+static inline uint16_t bits16(double v, int prec) {
+  const float f = (float)v;
+  if (prec == 0) {
+    _Float16 h = (_Float16)f;
+    uint16_t u;
+    std::memcpy(&u, &h, 2);
+    return u;
   }
-  if (pass == 1)
-    hipLaunchKernelGGL(k_fitmix_out, dim3((unsigned)((a.rows + 3) / 4)), dim3(256), 0, s, a.type_start, d.ntypes,
-                       a.atom_of_pos, a.w, a.fo, L, d.fw[L], a.Y[L], a.rows, a.eatom);
-  for (int l = L - 1; l >= 0 && pass == 2; --l) {
-    MG g{};
-    g.layer = l;
-    g.in = d.fw[l];
-    g.out = d.fw[l + 1];
-    g.K = g.out;
-    g.N = g.in;
-    g.ntypes = d.ntypes;
-    g.type_start = a.type_start;
-    g.w = a.w;
-    g.fo = a.fo;
-    g.Tt = a.Tt[l + 1];
-    g.gY = (l == L - 1) ? nullptr : a.G[l + 1];
-    g.gX = a.G[l];
-    dim3 grid(gm, (unsigned)((g.N + 63) / 64));
-    if (l < a.n16) hipLaunchKernelGGL((k_fitmix16<P, MF_BWD>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((k_fitmix32<MF_BWD>), grid, dim3(256), 0, s, g);
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+static inline double val16(uint16_t u, int prec) {
+  if (prec == 0) {
+    _Float16 h;
+    std::memcpy(&h, &u, 2);
+    return (double)(float)h;
   }
+  const uint32_t w = (uint32_t)u << 16;
+  float f;
+  std::memcpy(&f, &w, 4);
+  return (double)f;
+}
+
+// 16-bit operand image: nt tiles x ks k-steps x 64 lanes x 8, element value
+// from fn(tile, kk, lane, v) (lo = true: the rounding remainder)
+template <class F>
+static int64_t put_image(std::vector<unsigned char> &buf, int nt, int ks, int prec, bool lo, F fn) {
+  buf.resize((buf.size() + 255) / 256 * 256, 0);
+  const int64_t off = (int64_t)buf.size();
+  buf.resize(buf.size() + (size_t)nt * ks * 64 * 8 * 2, 0);
+  uint16_t *p = (uint16_t *)(buf.data() + off);
+  for (int tl = 0; tl < nt; ++tl)
+    for (int kk = 0; kk < ks; ++kk)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int v = 0; v < 8; ++v) {
+          const double x = fn(tl, kk, lane, v);
+          const uint16_t h = bits16(x, prec);
+          p[(((size_t)tl * ks + kk) * 64 + lane) * 8 + v] = lo ? bits16(x - val16(h, prec), prec) : h;
+        }
+  return off;
+}
+
+static int64_t put_f32(std::vector<unsigned char> &buf, const std::vector<float> &v) {
+  buf.resize((buf.size() + 255) / 256 * 256, 0);
+  const int64_t off = (int64_t)buf.size();
+  buf.resize(buf.size() + 4 * v.size(), 0);
+  std::memcpy(buf.data() + off, v.data(), 4 * v.size());
+  return off;
+}
+
+void fit_mix_pack(const Dims &d, int prec, int nsplit, const double *const *W, const double *const *b,
+                  std::vector<unsigned char> &buf, FitMixOffsets &fo) {
+  const int H = d.fw[1], M1 = d.M1, NL = d.n_fit, MT = FIT_MT, KSH = (MT + 1) / 2, KS0 = M1 / 2;
+  auto kslot = [](int kk, int g, int v) { return 16 * (2 * kk + v / 4) + 4 * g + (v % 4); };
+  fo = FitMixOffsets{};
+  for (int t = 0; t < d.ntypes; ++t) {
+    const double *const *Wt = W + (size_t)t * (NL + 1);
+    const double *const *bt = b + (size_t)t * (NL + 1);
+    const int K0 = d.fw[0];  // M1 * 16
+    // layer 0 forward: A[o][k] = W0[k][o], k of slot (kk, g, v) = (2kk + g/2)*16 + 8(g%2) + v
+    fo.a0f[t] = put_image(buf, MT, KS0, prec, false, [&](int mt, int kk, int lane, int v) {
+      const int g = lane >> 4, o = 16 * mt + (lane & 15);
+      const int k = (2 * kk + (g >> 1)) * 16 + 8 * (g & 1) + v;
+      return (o < H && k < K0) ? Wt[0][(size_t)k * H + o] : 0.0;
+    });
+    // layer 0 backward: A[k][o] = W0[k][o], k = 16 a + lane%16, o = kslot
+    fo.a0b[t] = put_image(buf, M1, KSH, prec, false, [&](int aa, int kk, int lane, int v) {
+      const int k = 16 * aa + (lane & 15), o = kslot(kk, lane >> 4, v);
+      return (o < H && k < K0) ? Wt[0][(size_t)k * H + o] : 0.0;
+    });
+    for (int l = 1; l < NL; ++l) {
+      auto fwd = [&](int mt, int kk, int lane, int v) {
+        const int o = 16 * mt + (lane & 15), k = kslot(kk, lane >> 4, v);
+        return (o < H && k < H) ? Wt[l][(size_t)k * H + o] : 0.0;
+      };
+      auto bwd = [&](int mt, int kk, int lane, int v) {
+        const int k = 16 * mt + (lane & 15), o = kslot(kk, lane >> 4, v);
+        return (o < H && k < H) ? Wt[l][(size_t)k * H + o] : 0.0;
+      };
+      fo.ahf[t][l] = put_image(buf, MT, KSH, prec, false, fwd);
+      fo.ahb[t][l] = put_image(buf, MT, KSH, prec, false, bwd);
+      if (l >= nsplit) {
+        fo.ahf_lo[t][l] = put_image(buf, MT, KSH, prec, true, fwd);
+        fo.ahb_lo[t][l] = put_image(buf, MT, KSH, prec, true, bwd);
+      } else {
+        fo.ahf_lo[t][l] = fo.ahf[t][l];
+        fo.ahb_lo[t][l] = fo.ahb[t][l];
+      }
+    }
+    for (int l = 0; l < NL; ++l) {
+      std::vector<float> bias(256, 0.f);
+      for (int o = 0; o < H; ++o) bias[o] = (float)bt[l][o];
+      fo.bias[t][l] = put_f32(buf, bias);
+    }
+    std::vector<float> wo(260, 0.f);
+    for (int f = 0; f < H; ++f) wo[f] = (float)Wt[NL][f];
+    wo[256] = (float)bt[NL][0];
+    fo.wout[t] = put_f32(buf, wo);
+  }
+  buf.resize((buf.size() + 255) / 256 * 256, 0);
+}
+
+size_t fit_mix_tbuf_floats(const Dims &d, int64_t rows) {
+  return (size_t)((rows + 15) / 16) * d.n_fit * FIT_MT * 256;
 }
 
 void launch_fit_mix(hipStream_t s, const FitMixArgs &a, int pass) {
-  if (a.prec == 0) run<0>(s, a, pass);
-  else run<1>(s, a, pass);
+  const int64_t tiles = (a.rows + 15) / 16;
+  const unsigned grid = (unsigned)((tiles + FIT_WAVES - 1) / FIT_WAVES);
+  if (grid == 0) return;
+  if (pass == 1) {
+    if (a.prec == 0) hipLaunchKernelGGL((k_fit_fwd<0, FIT_MT>), dim3(grid), dim3(64 * FIT_WAVES), 0, s, a);
+    else hipLaunchKernelGGL((k_fit_fwd<1, FIT_MT>), dim3(grid), dim3(64 * FIT_WAVES), 0, s, a);
+  } else {
+    if (a.prec == 0) hipLaunchKernelGGL((k_fit_bwd<0, FIT_MT>), dim3(grid), dim3(64 * FIT_WAVES), 0, s, a);
+    else hipLaunchKernelGGL((k_fit_bwd<1, FIT_MT>), dim3(grid), dim3(64 * FIT_WAVES), 0, s, a);
+  }
 }
 
 }  // namespace dpk
