@@ -6,6 +6,39 @@
 
 namespace dpk {
 
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// hi/lo FP16 halves of eight FP32 values x[0..3], y[0..3]: hi = rn16(x),
+// lo = rn16(x - hi).  The remainder is rounded in one v_fma_mix{lo,hi}_f16
+// per value (FP32 x, FP16 hi operand), two values per register; s_nop 1
+// keeps the two wait states a matrix-core read of a VALU-written register
+// needs.
+__device__ inline unsigned f16_lo_pair(float x, float y, unsigned hi) {
+  unsigned lo;
+  asm("v_fma_mixlo_f16 %0, %1, 1.0, -%3 op_sel_hi:[0,0,1]\n\t"
+      "v_fma_mixhi_f16 %0, %2, 1.0, -%3 op_sel:[0,0,1] op_sel_hi:[0,0,1]\n\t"
+      "s_nop 1"
+      : "=&v"(lo)
+      : "v"(x), "v"(y), "v"(hi));
+  return lo;
+}
+
+__device__ inline void split8_f16(const float (&x)[4], const float (&y)[4], f16x8 &hi, f16x8 &lo) {
+  typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+  typedef unsigned u4v __attribute__((ext_vector_type(4)));
+  const float z[8] = {x[0], x[1], x[2], x[3], y[0], y[1], y[2], y[3]};
+  unsigned H[4], L[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const h2v p = {(_Float16)z[2 * k], (_Float16)z[2 * k + 1]};
+    H[k] = __builtin_bit_cast(unsigned, p);
+    L[k] = f16_lo_pair(z[2 * k], z[2 * k + 1], H[k]);
+  }
+  const u4v hv = {H[0], H[1], H[2], H[3]}, lv = {L[0], L[1], L[2], L[3]};
+  hi = __builtin_bit_cast(f16x8, hv);
+  lo = __builtin_bit_cast(f16x8, lv);
+}
+
 struct MixArgs {
   Dims d;
   int shape;                  // index into the supported embedding shapes

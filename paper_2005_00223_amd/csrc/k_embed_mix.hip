@@ -100,6 +100,13 @@ __device__ inline Split8<P> split8(const float (&x)[4], const float (&y)[4]) {
   return s;
 }
 
+template <>
+__device__ inline Split8<0> split8<0>(const float (&x)[4], const float (&y)[4]) {
+  Split8<0> s;
+  split8_f16(x, y, s.hi, s.lo);
+  return s;
+}
+
 // tanh(x) = 1 - 2 / (exp(2x) + 1) with the hardware exp2 and reciprocal;
 // absolute error about 2e-7, well below the 16-bit storage of the layers.
 __device__ inline float tanh_f(float x) {
@@ -137,8 +144,9 @@ struct Shape {
   // per-wave LDS scratch (bytes)
   static constexpr int P1_H1 = 0;                       // float [16][S1]
   static constexpr int P1_H2 = P1_H1 + 16 * S1 * 4;     // float [16][S2]
-  static constexpr int P1_G = P1_H2 + 16 * S2 * 4;      // float [16][32]: two output tiles of G
-  static constexpr int P1_R = P1_G + 16 * 32 * 4;       // float [16][4]
+  static constexpr int P1_G = P1_H2 + 16 * S2 * 4;      // float [32][GTS]: two output tiles of G, feature-major
+  static constexpr int GTS = 20;                        // row stride (neighbours) of that transpose, 16-byte aligned
+  static constexpr int P1_R = P1_G + 32 * GTS * 4;      // float [16][4]
   static constexpr int P1_BYTES = P1_R + 256;
   static constexpr int P2_H1 = 0;                       // float [2][16][S1] (h, dh)
   static constexpr int P2_H2 = P2_H1 + 2 * 16 * S1 * 4; // float [2][16][S2]
@@ -150,6 +158,13 @@ struct Shape {
 };
 
 constexpr int MIX_WAVES = 4;
+
+// blocks per CU the kernels are compiled for: the student-sized nets leave
+// enough registers and LDS for three
+template <int W2, int PASS>
+struct MixOcc {
+  static constexpr int B = (PASS == 1 || W2 <= 32) ? 3 : 2;
+};
 
 // rows handled by wave gw of nwaves: a contiguous chunk
 __device__ inline void wave_rows(int64_t rows, int64_t &p0, int64_t &p1) {
@@ -164,6 +179,63 @@ __device__ inline void copy_nets(unsigned char *dst, const unsigned char *src, i
   const uint4 *s = (const uint4 *)src;
   uint4 *d = (uint4 *)dst;
   for (int o = threadIdx.x; o < bytes / 16; o += blockDim.x) d[o] = s[o];
+}
+
+// ---------------------------------------------------------------------------
+// T += G R^T over the 16 neighbours of a tile, G transposed through LDS.
+// FP16: v_mfma_f32_16x16x16_f16 with G and R as hi + lo halves (three
+// products, about 22 bits); BF16 (8-bit halves would lose bits): the FP32
+// matrix core, v_mfma_f32_16x16x4f32 over four K-steps of 4 neighbours.
+// ---------------------------------------------------------------------------
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+struct RSplit {
+  f16x4 hi, lo;
+};
+
+__device__ inline void split4_f16(float4 v, f16x4 &hi, f16x4 &lo) {
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  const h2 p0 = {(_Float16)v.x, (_Float16)v.y}, p1 = {(_Float16)v.z, (_Float16)v.w};
+  const unsigned H0 = __builtin_bit_cast(unsigned, p0), H1 = __builtin_bit_cast(unsigned, p1);
+  const u2 hv = {H0, H1}, lv = {f16_lo_pair(v.x, v.y, H0), f16_lo_pair(v.z, v.w, H1)};
+  hi = __builtin_bit_cast(f16x4, hv);
+  lo = __builtin_bit_cast(f16x4, lv);
+}
+
+// lane (g, n): R[4g + v][c = n] for n < 4, else 0
+template <int P>
+__device__ inline RSplit rsplit(const float *Rs, int n, int g) {
+  RSplit r;
+  if (P == 0) {
+    float4 v;
+    v.x = n < 4 ? Rs[4 * (4 * g + 0) + n] : 0.f;
+    v.y = n < 4 ? Rs[4 * (4 * g + 1) + n] : 0.f;
+    v.z = n < 4 ? Rs[4 * (4 * g + 2) + n] : 0.f;
+    v.w = n < 4 ? Rs[4 * (4 * g + 3) + n] : 0.f;
+    split4_f16(v, r.hi, r.lo);
+  }
+  return r;
+}
+
+// grow = G^T row of feature 16 mt + n in the LDS transpose (neighbours
+// contiguous); returns acc + G^T R for output tile mt, lane layout of T
+template <int P>
+__device__ inline v4f tacc16(const float *grow, const RSplit &RB, const float *Rs, int n, int g, v4f acc) {
+  if (P == 0) {
+    f16x4 ahi, alo;
+    split4_f16(*(const float4 *)(grow + 4 * g), ahi, alo);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(ahi, RB.hi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(ahi, RB.lo, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(alo, RB.hi, acc, 0, 0, 0);
+  } else {
+    // K-step kk: neighbours 4kk..4kk+3, lane (g, n) supplies G[4kk + g][16mt + n] and R[4kk + g][n]
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const float rb = n < 4 ? Rs[4 * (4 * kk + g) + n] : 0.f;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(grow[4 * kk + g], rb, acc, 0, 0, 0);
+    }
+  }
+  return acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -269,7 +341,7 @@ __device__ inline float skip_val(int f, int mt, int r, const float (&prev)[MTI][
 
 // LIN: the last layer is affine (no tanh), as in the student nets
 template <int W1, int W2, int W3, int LIN, int P>
-__global__ void __launch_bounds__(64 * MIX_WAVES, 2) k_embed_fwd_mix(MixArgs a) {
+__global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 1>::B)) k_embed_fwd_mix(MixArgs a) {
   typedef Shape<W1, W2, W3> S;
   extern __shared__ __align__(16) unsigned char smem[];
   const Dims &d = a.d;
@@ -313,6 +385,8 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 2) k_embed_fwd_mix(MixArgs a) 
         v4f acc2[S::MT2];
         layer_mfma<P, S::MT2, 1>(net + S::O_A2, b2, B2, lane, g, acc2);
         wsync();
+        // R of the tile's neighbours 4g..4g+3, component n, as the B operand of T += G R^T
+        const RSplit RB = rsplit<P>(Rs, n, g);
         float h2[S::MT2][4];
 #pragma unroll
         for (int mt = 0; mt < S::MT2; ++mt)
@@ -347,17 +421,17 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 2) k_embed_fwd_mix(MixArgs a) 
                   gv[r] = (LIN ? acc3[r] : tanh_f(acc3[r])) + skip_val<W2, W3, S::SK3, S::MT2>(f, mt, r, h2, h2s, n, S::S2);
               }
             }
-            *(float4 *)(Gs + n * 32 + 16 * q + 4 * g) = make_float4(gv[0], gv[1], gv[2], gv[3]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Gs[(16 * q + 4 * g + r) * S::GTS + n] = gv[r];
           }
           wsync();
-          // T[f][c] += sum_nb G[nb][f] R[nb][c]: A = G^T (rows f), B = R (K = neighbours)
+          // T[f][c] += sum_nb G[nb][f] R[nb][c] over the tile's 16 neighbours:
+          // A = G^T (rows f, K = neighbours), B = R (K = neighbours, N = c)
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
-            const int nb = 4 * kk + g;
-            const float rb = n < 4 ? Rs[4 * nb + n] : 0.f;
-#pragma unroll
-            for (int q = 0; q < 2; ++q)
-              if (2 * kp + q < S::MT3) Tacc[2 * kp + q] = mfma32(Gs[nb * 32 + 16 * q + n], rb, Tacc[2 * kp + q]);
+          for (int q = 0; q < 2; ++q) {
+            if (2 * kp + q < S::MT3) {
+              Tacc[2 * kp + q] = tacc16<P>(Gs + (16 * q + n) * S::GTS, RB, Rs, n, g, Tacc[2 * kp + q]);
+            }
           }
           wsync();
         }
@@ -394,7 +468,7 @@ __device__ inline void switch64(double r, double rcs, double rc, double inv_w, d
 }
 
 template <int W1, int W2, int W3, int LIN, int P>
-__global__ void __launch_bounds__(64 * MIX_WAVES, 2) k_embed_bwd_mix(MixArgs a) {
+__global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 2>::B)) k_embed_bwd_mix(MixArgs a) {
   typedef Shape<W1, W2, W3> S;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double vred[MIX_WAVES][9];

@@ -69,6 +69,13 @@ __device__ inline FSplit<P> fsplit(const float (&x)[4], const float (&y)[4]) {
   return s;
 }
 
+template <>
+__device__ inline FSplit<0> fsplit<0>(const float (&x)[4], const float (&y)[4]) {
+  FSplit<0> s;
+  split8_f16(x, y, s.hi, s.lo);
+  return s;
+}
+
 __device__ inline float ftanh(float x) {
   const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);
   return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);

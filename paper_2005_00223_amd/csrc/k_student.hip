@@ -16,8 +16,9 @@
 //      (h2, 1) with a small ridge, solved by Cholesky.  When the student will
 //      run in 16-bit precision, W2 is rounded before the features are formed
 //      and W3 after the solve, and b3 then absorbs the mean residual.
-// Training work is small next to an MD step, so these kernels are plain
-// FP32/FP64 VALU code with LDS, written for clarity over speed.
+// Training work is small next to an MD run, so these kernels are plain
+// FP32/FP64 VALU code with LDS; they spread each sample over several threads
+// so that a batch of a few thousand samples still fills the chip.
 #include "dp_student.h"
 
 namespace dpk {
@@ -58,59 +59,64 @@ void launch_st_sample(hipStream_t st, const StSampleArgs &a) {
 }
 
 // ---------------------------------------------------------------------------
-// 2. teacher G(s) in FP64: one thread per sample, activations in LDS
-//    ([feature][64] per buffer, two buffers)
+// 2. teacher G(s) in FP64: a block of 256 threads takes 16 samples, 16
+//    threads per sample; each thread computes every 16th output feature of
+//    a layer, the activations of the block's samples live in LDS
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_st_teacher(StTeacherArgs a) {
+constexpr int TCH_SAMPLES = 16;
+
+__global__ void __launch_bounds__(256) k_st_teacher(StTeacherArgs a) {
   extern __shared__ double tsh[];
   const Dims &d = a.d;
   const int net = blockIdx.y;
   const int t = net / d.ntypes, u = net % d.ntypes;
-  const int tid = threadIdx.x;
-  const int q = blockIdx.x * 64 + tid;
+  const int j = threadIdx.x & 15, ql = threadIdx.x >> 4;
+  const int q = blockIdx.x * TCH_SAMPLES + ql;
   int wmax = 1;
   for (int l = 1; l <= d.n_emb; ++l) wmax = d.ew[l] > wmax ? d.ew[l] : wmax;
-  double *hA = tsh, *hB = tsh + wmax * 64;
+  double *hA = tsh + ql * wmax, *hB = tsh + (TCH_SAMPLES + ql) * wmax;
   const double s = q < a.batch ? a.s[(int64_t)net * a.batch + q] : 0.0;
   {
     const double *W0 = a.ew + a.eo.w[t][u][0], *b0 = a.ew + a.eo.b[t][u][0];
     const int out = d.ew[1];
     const bool lin = d.emb_lin && d.n_emb == 1;
-    for (int o = 0; o < out; ++o) {
+    for (int o = j; o < out; o += 16) {
       const double z = s * W0[o] + b0[o];
       double h = lin ? z : tanh(z);
       if (out <= 2) h += s;  // identity / doubling skip of the scalar input
-      hA[o * 64 + tid] = h;
+      hA[o] = h;
     }
   }
+  __syncthreads();
   for (int l = 1; l < d.n_emb; ++l) {
     const int in = d.ew[l], out = d.ew[l + 1], mp = d.emp[l + 1];
     const double *W = a.ew + a.eo.w[t][u][l], *b = a.ew + a.eo.b[t][u][l];
     const bool lin = d.emb_lin && l == d.n_emb - 1;
-    for (int o = 0; o < out; ++o) {
+    for (int o = j; o < out; o += 16) {
       double z = b[o];
-      for (int i = 0; i < in; ++i) z += hA[i * 64 + tid] * W[(size_t)i * mp + o];
+      for (int i = 0; i < in; ++i) z += hA[i] * W[(size_t)i * mp + o];
       double h = lin ? z : tanh(z);
-      if (out == in) h += hA[o * 64 + tid];
-      else if (out == 2 * in) h += hA[(o % in) * 64 + tid];
-      hB[o * 64 + tid] = h;
+      if (out == in) h += hA[o];
+      else if (out == 2 * in) h += hA[o % in];
+      hB[o] = h;
     }
+    __syncthreads();
     double *tmp = hA;
     hA = hB;
     hB = tmp;
   }
   if (q < a.batch) {
     double *G = a.G + ((int64_t)net * a.batch + q) * d.M1;
-    for (int o = 0; o < d.M1; ++o) G[o] = hA[o * 64 + tid];
+    for (int o = j; o < d.M1; o += 16) G[o] = hA[o];
   }
 }
 
 void launch_st_teacher(hipStream_t st, const StTeacherArgs &a) {
   int wmax = 1;
   for (int l = 1; l <= a.d.n_emb; ++l) wmax = a.d.ew[l] > wmax ? a.d.ew[l] : wmax;
-  const size_t shm = (size_t)2 * wmax * 64 * sizeof(double);
+  const size_t shm = (size_t)2 * TCH_SAMPLES * wmax * sizeof(double);
   const int nets = a.d.ntypes * a.d.ntypes;
-  hipLaunchKernelGGL(k_st_teacher, dim3((a.batch + 63) / 64, nets), dim3(64), shm, st, a);
+  hipLaunchKernelGGL(k_st_teacher, dim3((a.batch + TCH_SAMPLES - 1) / TCH_SAMPLES, nets), dim3(256), shm, st, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -133,26 +139,31 @@ __device__ inline void st_hidden_f32(const float *P, const StudentLayout &L, flo
 }
 
 // ---------------------------------------------------------------------------
-// 3a. squared error and its gradient: one block of 64 threads per 64 samples
+// 3a. squared error and its gradient: one block of 256 threads per 64
+//     samples; wave w takes output features [w*oc, (w+1)*oc) of every sample,
+//     the four partial dE/dh2 meet in LDS
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_st_grad(StGradArgs a) {
+constexpr int GR_WAVES = 4;
+
+__global__ void __launch_bounds__(64 * GR_WAVES) k_st_grad(StGradArgs a) {
   extern __shared__ float gsh[];
   const int M1 = a.M1;
   const StudentLayout L = student_layout(M1);
   const int net = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
-  const int tid = threadIdx.x;
-  float *P = gsh;                  // [np]
-  float *ss = P + L.np;            // [64]
-  float *h1s = ss + 64;            // [SH1][SP]
-  float *dz1s = h1s + SH1 * SP;    // [SH1][SP]
-  float *h2s = dz1s + SH1 * SP;    // [SH2][SP]
-  float *dz2s = h2s + SH2 * SP;    // [SH2][SP]
-  float *rs = dz2s + SH2 * SP;     // [M1][SP]
-  __shared__ double red[2][64];
+  const int tid = threadIdx.x, m = tid & 63, wv = tid >> 6;
+  float *P = gsh;                   // [np]
+  float *ss = P + L.np;             // [64]
+  float *h1s = ss + 64;             // [SH1][SP]
+  float *dz1s = h1s + SH1 * SP;     // [SH1][SP]
+  float *h2s = dz1s + SH1 * SP;     // [SH2][SP]
+  float *dz2s = h2s + SH2 * SP;     // [SH2][SP]
+  float *rs = dz2s + SH2 * SP;      // [M1][SP]
+  float *dhp = rs + M1 * SP;        // [GR_WAVES][SH2][SP] partial dE/dh2
+  __shared__ double red[2][64 * GR_WAVES];
   const float *Pg = a.params + (int64_t)net * L.np;
-  for (int e = tid; e < L.np; e += 64) P[e] = Pg[e];
+  for (int e = tid; e < L.np; e += 64 * GR_WAVES) P[e] = Pg[e];
   __syncthreads();
-  const int64_t q = (int64_t)net * a.batch + (int64_t)blk * 64 + tid;
+  const int64_t q = (int64_t)net * a.batch + (int64_t)blk * 64 + m;
   const float s = (float)a.s[q];
   const float w = a.wt[q];
   float t1[SH1], t2[SH2], h2[SH2];
@@ -162,71 +173,82 @@ __global__ void __launch_bounds__(64) k_st_grad(StGradArgs a) {
   for (int k = 0; k < SH2; ++k) dh2[k] = 0.f;
   double lsum = 0.0;
   const double *Gt = a.G + q * M1;
-  for (int o = 0; o < M1; ++o) {
+  const int oc = (M1 + GR_WAVES - 1) / GR_WAVES;
+  const int o0 = wv * oc, o1 = o0 + oc < M1 ? o0 + oc : M1;
+  for (int o = o0; o < o1; ++o) {
     float g = P[L.o_b3 + o];
 #pragma unroll
     for (int k = 0; k < SH2; ++k) g += h2[k] * P[L.o_w3 + k * M1 + o];
     const float r = w * (g - (float)Gt[o]);
     lsum += (double)r * r;
-    rs[o * SP + tid] = r;
+    rs[o * SP + m] = r;
 #pragma unroll
     for (int k = 0; k < SH2; ++k) dh2[k] += P[L.o_w3 + k * M1 + o] * r;
   }
-  float dz2[SH2];
 #pragma unroll
-  for (int j = 0; j < SH2; ++j) dz2[j] = dh2[j] * (1.f - t2[j] * t2[j]);
-#pragma unroll
-  for (int i = 0; i < SH1; ++i) {
-    float g = dh2[i] + dh2[i + SH1];
-#pragma unroll
-    for (int j = 0; j < SH2; ++j) g += P[L.o_w2 + i * SH2 + j] * dz2[j];
-    dz1s[i * SP + tid] = g * (1.f - t1[i] * t1[i]);
-    h1s[i * SP + tid] = t1[i];
-  }
-#pragma unroll
-  for (int j = 0; j < SH2; ++j) {
-    h2s[j * SP + tid] = h2[j];
-    dz2s[j * SP + tid] = dz2[j];
-  }
-  ss[tid] = s;
+  for (int k = 0; k < SH2; ++k) dhp[(wv * SH2 + k) * SP + m] = dh2[k];
   red[0][tid] = lsum;
-  red[1][tid] = (double)w;
+  red[1][tid] = wv == 0 ? (double)w : 0.0;
+  __syncthreads();
+  if (wv == 0) {
+#pragma unroll
+    for (int k = 0; k < SH2; ++k)
+      dh2[k] = dhp[k * SP + m] + dhp[(SH2 + k) * SP + m] + dhp[(2 * SH2 + k) * SP + m] + dhp[(3 * SH2 + k) * SP + m];
+    float dz2[SH2];
+#pragma unroll
+    for (int j = 0; j < SH2; ++j) dz2[j] = dh2[j] * (1.f - t2[j] * t2[j]);
+#pragma unroll
+    for (int i = 0; i < SH1; ++i) {
+      float g = dh2[i] + dh2[i + SH1];
+#pragma unroll
+      for (int j = 0; j < SH2; ++j) g += P[L.o_w2 + i * SH2 + j] * dz2[j];
+      dz1s[i * SP + m] = g * (1.f - t1[i] * t1[i]);
+      h1s[i * SP + m] = t1[i];
+    }
+#pragma unroll
+    for (int j = 0; j < SH2; ++j) {
+      h2s[j * SP + m] = h2[j];
+      dz2s[j * SP + m] = dz2[j];
+    }
+    ss[m] = s;
+  }
   __syncthreads();
   // sums over the 64 samples of the block, parameter by parameter
   float *gp = a.gpart + ((int64_t)net * nblk + blk) * L.np;
-  for (int e = tid; e < L.np; e += 64) {
+  for (int e = tid; e < L.np; e += 64 * GR_WAVES) {
     float acc = 0.f;
     if (e < L.o_b1) {
-      for (int m = 0; m < 64; ++m) acc += ss[m] * dz1s[e * SP + m];
+      for (int k = 0; k < 64; ++k) acc += ss[k] * dz1s[e * SP + k];
     } else if (e < L.o_w2) {
       const int i = e - L.o_b1;
-      for (int m = 0; m < 64; ++m) acc += dz1s[i * SP + m];
+      for (int k = 0; k < 64; ++k) acc += dz1s[i * SP + k];
     } else if (e < L.o_b2) {
       const int i = (e - L.o_w2) / SH2, j = (e - L.o_w2) % SH2;
-      for (int m = 0; m < 64; ++m) acc += h1s[i * SP + m] * dz2s[j * SP + m];
+      for (int k = 0; k < 64; ++k) acc += h1s[i * SP + k] * dz2s[j * SP + k];
     } else if (e < L.o_w3) {
       const int j = e - L.o_b2;
-      for (int m = 0; m < 64; ++m) acc += dz2s[j * SP + m];
+      for (int k = 0; k < 64; ++k) acc += dz2s[j * SP + k];
     } else if (e < L.o_b3) {
-      const int k = (e - L.o_w3) / M1, o = (e - L.o_w3) % M1;
-      for (int m = 0; m < 64; ++m) acc += h2s[k * SP + m] * rs[o * SP + m];
+      const int kk = (e - L.o_w3) / M1, o = (e - L.o_w3) % M1;
+      for (int k = 0; k < 64; ++k) acc += h2s[kk * SP + k] * rs[o * SP + k];
     } else {
       const int o = e - L.o_b3;
-      for (int m = 0; m < 64; ++m) acc += rs[o * SP + m];
+      for (int k = 0; k < 64; ++k) acc += rs[o * SP + k];
     }
     gp[e] = acc;
   }
   if (tid < 2) {
     double v = 0.0;
-    for (int m = 0; m < 64; ++m) v += red[tid][m];
+    for (int k = 0; k < 64 * GR_WAVES; ++k) v += red[tid][k];
     a.lpart[((int64_t)net * nblk + blk) * 2 + tid] = v;
   }
 }
 
 void launch_st_grad(hipStream_t st, const StGradArgs &a) {
   const StudentLayout L = student_layout(a.M1);
-  const size_t shm = sizeof(float) * ((size_t)L.np + 64 + (size_t)(2 * SH1 + 2 * SH2 + a.M1) * SP);
-  hipLaunchKernelGGL(k_st_grad, dim3(a.batch / 64, a.nets), dim3(64), shm, st, a);
+  const size_t shm =
+      sizeof(float) * ((size_t)L.np + 64 + (size_t)(2 * SH1 + 2 * SH2 + a.M1 + GR_WAVES * SH2) * SP);
+  hipLaunchKernelGGL(k_st_grad, dim3(a.batch / 64, a.nets), dim3(64 * GR_WAVES), shm, st, a);
 }
 
 // ---------------------------------------------------------------------------
