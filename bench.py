@@ -65,6 +65,43 @@ def algorithmic(spec, n_atoms, n_pairs, emb=None):
     }
 
 
+# kernel name in the profiles and the sources whose hash the PMC summary records
+PHASE_KERNEL = {
+    ("embed_bwd", "fp16", True): ("k_embed_bwd_mix<16, 32, 100, 1, 0>", "k_embed_mix"),
+    ("embed_fwd", "fp16", True): ("k_embed_fwd_mix<16, 32, 100, 1, 0>", "k_embed_mix"),
+    ("embed_bwd", "fp16", False): ("k_embed_bwd_mix<25, 50, 100, 0, 0>", "k_embed_mix"),
+    ("embed_fwd", "fp16", False): ("k_embed_fwd_mix<25, 50, 100, 0, 0>", "k_embed_mix"),
+    ("format", "fp16", True): ("k_format", "k_nlist"),
+    ("env", "fp16", True): ("k_env", "k_env"),
+}
+HASH_FILES = {"k_embed_mix": ("k_embed_mix.hip", "dp_mix.h", "dp_internal.h"),
+              "k_fit_mix": ("k_fit_mix.hip", "dp_mix.h", "dp_internal.h"),
+              "k_nlist": ("k_nlist.hip", "dp_internal.h"), "k_env": ("k_env.hip", "dp_internal.h")}
+
+
+def pmc_traffic(phase, precision, student):
+    """HBM bytes per launch of the phase's kernel from the committed
+    rocprofv3 PMC summary (FETCH_SIZE and WRITE_SIZE scaled by the copy
+    calibration recorded there), or None when there is no summary or the
+    kernel's sources changed after the counters were taken."""
+    import hashlib
+    key = PHASE_KERNEL.get((phase, precision, student))
+    path = os.path.join(HERE, "profiles", "cu500k_fp16_student_pmc.txt")
+    if key is None or not os.path.exists(path):
+        return None
+    name, src = key
+    text = open(path).read()
+    h = hashlib.sha256()
+    for f in HASH_FILES[src]:
+        h.update(open(os.path.join(HERE, "paper_2005_00223_amd", "csrc", f), "rb").read())
+    if f"# source-hash {src}: {h.hexdigest()[:16]}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("dpk::" + name + " "):
+            return float(line.split()[-1]) * 1e9
+    return None
+
+
 def cpu_baseline(w, blob, seconds, log_fn):
     """Time the FP64 CPU oracle on a bounded sample of centre atoms of the
     same workload; returns s per atom per evaluation (= per MD step)."""
@@ -197,7 +234,9 @@ def main():
         pk = {"fp64": "f64_mfma", "fp32": "f32_valu", "fp16": "f16_mfma", "bf16": "bf16_mfma"}[args.precision]
         ach = alg[kern] / (phases[kern] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": ach, "peak": PEAK[pk], "unit": "TFLOP/s", "frac": ach / PEAK[pk]}
-    roof.update(kernel=kern, traffic=None)
+    roof.update(kernel=kern, traffic=pmc_traffic(kern, args.precision, used_student))
+    if roof["traffic"] is not None:
+        roof["traffic_GBps_at_phase_time"] = roof["traffic"] / (phases[kern] * 1e-3) / 1e9
     if args.workload.startswith("cu"):
         wl = (f"{args.workload}: FCC Cu {n} atoms, rc 8 A, sel 512, emb 1-25-50-100, M2 16, fit 240x3, "
               f"NVE 1 fs, skin {args.skin} A")

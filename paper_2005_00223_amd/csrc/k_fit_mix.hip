@@ -89,6 +89,25 @@ __device__ inline int rtype(const int32_t *ts, int ntypes, int64_t r0) {
 }
 
 constexpr int FIT_WAVES = 4;
+constexpr int F0_CK = 2;  // first-layer k-steps per staged chunk (forward)
+constexpr int F0_CA = 4;  // rows of D per staged chunk (backward)
+
+// One 1 KB operand block (64 lanes x 16 B) from global memory straight into
+// LDS (global_load_lds_dwordx4, no registers); lds must be wave-uniform.
+__device__ inline void dma_1k(const unsigned char *src, unsigned char *lds, int lane) {
+  __builtin_amdgcn_global_load_lds((const void *)(src + 16 * lane), (__attribute__((address_space(3))) void *)lds, 16,
+                                   0, 0);
+}
+
+// the waves of the block stage blocks [b0, b0 + nb) of an image into buf
+__device__ inline void dma_blocks(const unsigned char *img, int64_t b0, int nb, unsigned char *buf, int wv, int lane) {
+  for (int b = wv; b < nb; b += FIT_WAVES) dma_1k(img + (b0 + b) * 1024, buf + b * 1024, lane);
+}
+
+__device__ inline void dma_wait_all() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+}
 
 // per row tile in tbuf: [layer][mt][lane][4] floats
 template <int MT>
@@ -100,11 +119,14 @@ template <int P, int MT>
 __global__ void __launch_bounds__(64 * FIT_WAVES, 2) k_fit_fwd(FitMixArgs a) {
   typedef typename FT<P>::v8 V;
   constexpr int KSH = (MT + 1) / 2;
-  const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
-  const int64_t tile = (int64_t)blockIdx.x * FIT_WAVES + (threadIdx.x >> 6);
+  __shared__ __align__(16) unsigned char stage[2][F0_CK * MT * 1024];
+  const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15, wv = threadIdx.x >> 6;
+  const int64_t tile = (int64_t)blockIdx.x * FIT_WAVES + wv;
   const int64_t p0 = tile * 16;
   const int ntypes = a.d.ntypes;
-  if (p0 >= a.type_start[ntypes]) return;
+  // a block's 64 rows share one type (types are padded to 64 rows) or lie
+  // past the end: the exit is block-uniform, so the barriers below are safe
+  if ((int64_t)blockIdx.x * 16 * FIT_WAVES >= a.type_start[ntypes]) return;
   const int t = rtype(a.type_start, ntypes, p0);
   const int i = a.atom_of_pos[p0 + n];
   const int M1 = a.d.M1, NL = a.d.n_fit;
@@ -123,24 +145,41 @@ __global__ void __launch_bounds__(64 * FIT_WAVES, 2) k_fit_fwd(FitMixArgs a) {
       acc[mt] = v4f{b.x, b.y, b.z, b.w};
     }
   }
-  // layer 0: K = M1*16 features of D, formed from T
-  const V *A0 = (const V *)(W + a.fo.a0f[t]);
+  // layer 0: K = M1*16 features of D, formed from T.  The A operands
+  // ([kk][mt] blocks of 1 KB) stream through LDS in chunks of F0_CK k-steps,
+  // the next chunk loading while this one is used.
+  const unsigned char *A0 = W + a.fo.a0f[t];
   const int KS0 = M1 / 2;
-  for (int kk = 0; kk < KS0; ++kk) {
-    const float4 Ta = i >= 0 ? Ti[2 * kk + (g >> 1)] : z4;
-    float x[4], y[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      x[v] = Ta.x * Tb[v].x + Ta.y * Tb[v].y + Ta.z * Tb[v].z + Ta.w * Tb[v].w;
-      y[v] = Ta.x * Tb[v + 4].x + Ta.y * Tb[v + 4].y + Ta.z * Tb[v + 4].z + Ta.w * Tb[v + 4].w;
+  const int nch = (KS0 + F0_CK - 1) / F0_CK;
+  dma_blocks(A0, 0, (KS0 < F0_CK ? KS0 : F0_CK) * MT, stage[0], wv, lane);
+  dma_wait_all();
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) {
+      const int k1 = (c + 1) * F0_CK, nk = (KS0 - k1 < F0_CK) ? KS0 - k1 : F0_CK;
+      dma_blocks(A0, (int64_t)k1 * MT, nk * MT, stage[(c + 1) & 1], wv, lane);
     }
-    const FSplit<P> B = fsplit<P>(x, y);
+    const unsigned char *buf = stage[c & 1];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const V av = A0[(mt * KS0 + kk) * 64 + lane];
-      acc[mt] = FT<P>::mma(av, B.hi, acc[mt]);
-      acc[mt] = FT<P>::mma(av, B.lo, acc[mt]);
+    for (int q = 0; q < F0_CK; ++q) {
+      const int kk = c * F0_CK + q;
+      if (kk < KS0) {
+        const float4 Ta = i >= 0 ? Ti[2 * kk + (g >> 1)] : z4;
+        float x[4], y[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          x[v] = Ta.x * Tb[v].x + Ta.y * Tb[v].y + Ta.z * Tb[v].z + Ta.w * Tb[v].w;
+          y[v] = Ta.x * Tb[v + 4].x + Ta.y * Tb[v + 4].y + Ta.z * Tb[v + 4].z + Ta.w * Tb[v + 4].w;
+        }
+        const FSplit<P> B = fsplit<P>(x, y);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const V av = *(const V *)(buf + (q * MT + mt) * 1024 + 16 * lane);
+          acc[mt] = FT<P>::mma(av, B.hi, acc[mt]);
+          acc[mt] = FT<P>::mma(av, B.lo, acc[mt]);
+        }
+      }
     }
+    dma_wait_all();
   }
   float Y[MT][4];
 #pragma unroll
@@ -213,11 +252,12 @@ __global__ void __launch_bounds__(64 * FIT_WAVES, 2) k_fit_bwd(FitMixArgs a) {
   typedef typename FT<P>::v8 V;
   constexpr int KSH = (MT + 1) / 2;
   __shared__ float4 sh[FIT_WAVES][16][16];  // per wave: sum_b dD[a][b] T[b] for a < 16
+  __shared__ __align__(16) unsigned char stage[2][F0_CA * KSH * 1024];
   const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15, wv = threadIdx.x >> 6;
   const int64_t tile = (int64_t)blockIdx.x * FIT_WAVES + wv;
   const int64_t p0 = tile * 16;
   const int ntypes = a.d.ntypes;
-  if (p0 >= a.type_start[ntypes]) return;
+  if ((int64_t)blockIdx.x * 16 * FIT_WAVES >= a.type_start[ntypes]) return;  // block-uniform
   const int t = rtype(a.type_start, ntypes, p0);
   const int i = a.atom_of_pos[p0 + n];
   const int M1 = a.d.M1, NL = a.d.n_fit;
@@ -311,14 +351,25 @@ __global__ void __launch_bounds__(64 * FIT_WAVES, 2) k_fit_bwd(FitMixArgs a) {
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int c = 0; c < 4; ++c) dT2[r][c] = 0.f;
-  const V *A0 = (const V *)(W + a.fo.a0b[t]);
+  // A operands ([aa][kk] blocks of 1 KB) stream through LDS, F0_CA rows of
+  // D per chunk, the next chunk loading while this one is used
+  const unsigned char *A0 = W + a.fo.a0b[t];
   float4 *dTi = (float4 *)(a.dT32 + (int64_t)(i < 0 ? 0 : i) * M1 * 4);
   const float s = a.inv_nc;
+  const int nch = (M1 + F0_CA - 1) / F0_CA;
+  dma_blocks(A0, 0, (M1 < F0_CA ? M1 : F0_CA) * KSH, stage[0], wv, lane);
+  dma_wait_all();
   for (int aa = 0; aa < M1; ++aa) {
+    const int ch = aa / F0_CA, q = aa % F0_CA;
+    if (q == 0 && ch + 1 < nch) {
+      const int a1 = (ch + 1) * F0_CA, na = (M1 - a1 < F0_CA) ? M1 - a1 : F0_CA;
+      dma_blocks(A0, (int64_t)a1 * KSH, na * KSH, stage[(ch + 1) & 1], wv, lane);
+    }
+    const unsigned char *buf = stage[ch & 1] + q * KSH * 1024;
     v4f c = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kk = 0; kk < KSH; ++kk) {
-      const V av = A0[(aa * KSH + kk) * 64 + lane];
+      const V av = *(const V *)(buf + kk * 1024 + 16 * lane);
       c = FT<P>::mma(av, Bz[kk].hi, c);
       c = FT<P>::mma(av, Bz[kk].lo, c);
     }
@@ -348,6 +399,7 @@ __global__ void __launch_bounds__(64 * FIT_WAVES, 2) k_fit_bwd(FitMixArgs a) {
       if (aa < 16) sh[wv][n][aa] = pc;
       else if (i >= 0) dTi[aa] = make_float4(pc.x * s, pc.y * s, pc.z * s, pc.w * s);
     }
+    if (q == F0_CA - 1 || aa == M1 - 1) dma_wait_all();
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -443,8 +495,9 @@ void fit_mix_pack(const Dims &d, int prec, int nsplit, const double *const *W, c
     const double *const *Wt = W + (size_t)t * (NL + 1);
     const double *const *bt = b + (size_t)t * (NL + 1);
     const int K0 = d.fw[0];  // M1 * 16
-    // layer 0 forward: A[o][k] = W0[k][o], k of slot (kk, g, v) = (2kk + g/2)*16 + 8(g%2) + v
-    fo.a0f[t] = put_image(buf, MT, KS0, prec, false, [&](int mt, int kk, int lane, int v) {
+    // layer 0 forward, blocks in [kk][mt] order: A[o][k] = W0[k][o], k of
+    // slot (kk, g, v) = (2kk + g/2)*16 + 8(g%2) + v
+    fo.a0f[t] = put_image(buf, KS0, MT, prec, false, [&](int kk, int mt, int lane, int v) {
       const int g = lane >> 4, o = 16 * mt + (lane & 15);
       const int k = (2 * kk + (g >> 1)) * 16 + 8 * (g & 1) + v;
       return (o < H && k < K0) ? Wt[0][(size_t)k * H + o] : 0.0;
