@@ -467,6 +467,73 @@ __device__ inline void switch64(double r, double rcs, double rc, double inv_w, d
   }
 }
 
+// FP64 force pass for one real slot: g = dE/dR of the slot (FP32 from the
+// networks), chain rule through R(r_ij) in FP64, F_i accumulated by the
+// caller, F_j -= g_ij by an atomic, virial -= g_ij (x) r_ij.
+__device__ inline void force_pair(const MixArgs &a, int64_t slot, float4 gr, double rc, double rcs, double inv_w,
+                                  double &fi0, double &fi1, double &fi2, double (&vir)[9]) {
+  const double g0 = gr.x, g1 = gr.y, g2 = gr.z, g3 = gr.w;
+  const double4 D4 = a.dr[slot];
+  const int j = a.nlist[slot];
+  if (a.net_deriv) {
+    double *nd = a.net_deriv + slot * 4;
+    nd[0] = g0; nd[1] = g1; nd[2] = g2; nd[3] = g3;
+  }
+  const double dx = D4.x, dy = D4.y, dz = D4.z, r = D4.w;
+  double sw, dsw;
+  switch64(r, rcs, rc, inv_w, sw, dsw);
+  const double ir = 1.0 / r;
+  const double sv = sw * ir;
+  const double ds = (dsw * r - sw) * ir * ir;
+  const double tt = sv * ir;
+  const double dtt = dsw * ir * ir - 2.0 * sw * ir * ir * ir;
+  const double gd = g1 * dx + g2 * dy + g3 * dz;
+  const double cc = (g0 * ds + dtt * gd) * ir;
+  const double gx = cc * dx + tt * g1, gy = cc * dy + tt * g2, gz = cc * dz + tt * g3;
+  fi0 += gx;
+  fi1 += gy;
+  fi2 += gz;
+  unsafeAtomicAdd(a.force + 3 * (int64_t)j + 0, -gx);
+  unsafeAtomicAdd(a.force + 3 * (int64_t)j + 1, -gy);
+  unsafeAtomicAdd(a.force + 3 * (int64_t)j + 2, -gz);
+  vir[0] -= gx * dx; vir[1] -= gx * dy; vir[2] -= gx * dz;
+  vir[3] -= gy * dx; vir[4] -= gy * dy; vir[5] -= gy * dz;
+  vir[6] -= gz * dx; vir[7] -= gz * dy; vir[8] -= gz * dz;
+}
+
+// wave sum of the centre atom's force, one atomic per component
+__device__ inline void finish_atom_force(const MixArgs &a, int i, int lane, double fi0, double fi1, double fi2) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    fi0 += __shfl_xor(fi0, o);
+    fi1 += __shfl_xor(fi1, o);
+    fi2 += __shfl_xor(fi2, o);
+  }
+  if (lane == 0) {
+    unsafeAtomicAdd(a.force + 3 * (int64_t)i + 0, fi0);
+    unsafeAtomicAdd(a.force + 3 * (int64_t)i + 1, fi1);
+    unsafeAtomicAdd(a.force + 3 * (int64_t)i + 2, fi2);
+  }
+}
+
+// block partial of the virial (fixed order: lanes, then waves)
+__device__ inline void finish_block_virial(const MixArgs &a, const double (&vir)[9], double (&vred)[MIX_WAVES][9],
+                                           int lane, int wv) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    double v = vir[k];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
+    if (lane == 0) vred[wv][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 9) {
+    double v = 0.0;
+    for (int w = 0; w < MIX_WAVES; ++w) v += vred[w][threadIdx.x];
+    a.vir_part[(int64_t)blockIdx.x * 9 + threadIdx.x] = v;
+  }
+}
+
 template <int W1, int W2, int W3, int LIN, int P>
 __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 2>::B)) k_embed_bwd_mix(MixArgs a) {
   typedef Shape<W1, W2, W3> S;
@@ -624,71 +691,306 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 2>::B)) k_embed_bw
           const int q = c0 + lane;
           if (q < cnt) {
             const float4 gr = *(const float4 *)(gRs + 4 * lane);
-            const double g0 = gr.x, g1 = gr.y, g2 = gr.z, g3 = gr.w;
-            const double4 D4 = a.dr[base + q];
-            const int j = a.nlist[base + q];
-            if (a.net_deriv) {
-              double *nd = a.net_deriv + (base + q) * 4;
-              nd[0] = g0; nd[1] = g1; nd[2] = g2; nd[3] = g3;
-            }
-            const double dx = D4.x, dy = D4.y, dz = D4.z, r = D4.w;
-            double sw, dsw;
-            switch64(r, rcs, rc, inv_w, sw, dsw);
-            const double ir = 1.0 / r;
-            const double sv = sw * ir;
-            const double ds = (dsw * r - sw) * ir * ir;
-            const double tt = sv * ir;
-            const double dtt = dsw * ir * ir - 2.0 * sw * ir * ir * ir;
-            const double gd = g1 * dx + g2 * dy + g3 * dz;
-            const double cc = (g0 * ds + dtt * gd) * ir;
-            const double gx = cc * dx + tt * g1, gy = cc * dy + tt * g2, gz = cc * dz + tt * g3;
-            fi0 += gx;
-            fi1 += gy;
-            fi2 += gz;
-            unsafeAtomicAdd(a.force + 3 * (int64_t)j + 0, -gx);
-            unsafeAtomicAdd(a.force + 3 * (int64_t)j + 1, -gy);
-            unsafeAtomicAdd(a.force + 3 * (int64_t)j + 2, -gz);
-            vir[0] -= gx * dx; vir[1] -= gx * dy; vir[2] -= gx * dz;
-            vir[3] -= gy * dx; vir[4] -= gy * dy; vir[5] -= gy * dz;
-            vir[6] -= gz * dx; vir[7] -= gz * dy; vir[8] -= gz * dz;
+            force_pair(a, base + q, gr, rc, rcs, inv_w, fi0, fi1, fi2, vir);
           }
           wsync();
         }
       }
     }
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      fi0 += __shfl_xor(fi0, o);
-      fi1 += __shfl_xor(fi1, o);
-      fi2 += __shfl_xor(fi2, o);
-    }
-    if (lane == 0) {
-      unsafeAtomicAdd(a.force + 3 * (int64_t)i + 0, fi0);
-      unsafeAtomicAdd(a.force + 3 * (int64_t)i + 1, fi1);
-      unsafeAtomicAdd(a.force + 3 * (int64_t)i + 2, fi2);
-    }
+    finish_atom_force(a, i, lane, fi0, fi1, fi2);
   }
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    double v = vir[k];
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
-    if (lane == 0) vred[wv][k] = v;
-  }
+  finish_block_virial(a, vir, vred, lane, wv);
+}
+
+// ---------------------------------------------------------------------------
+// affine last layer (the student nets): G = W3^T h2 + b3 is linear in h2, so
+//   T   = sum_nb G R^T = W3^T (sum_nb h2 R^T) + b3 (sum_nb R)^T
+//   G^T dT  = h2^T (W3 dT) + b3^T dT,   G'^T dT = h2'^T (W3 dT)
+// and the third layer leaves the per-neighbour work: per neighbour only the
+// 32 x 4 sum H = sum h2 R^T (pass 1) or the contraction with the 32 x 4
+// matrix M = W3 dT (pass 2) remains, W3 is applied once per (atom, net).
+// H in its MFMA accumulator layout is exactly the K-permuted B operand of the
+// layer-3 image W3^T, and M in its accumulator layout is exactly the A
+// operand of the per-neighbour contraction.
+// ---------------------------------------------------------------------------
+template <int W1, int W2, int W3>
+struct LinShape {
+  typedef Shape<W1, W2, W3> S;
+  static_assert(S::S2 == 32 && S::KS3 == 1, "affine kernels take the 32-slot second layer as one K-step");
+  static_assert(S::SK3 == 0, "affine kernels assume no skip into the last layer");
+  static constexpr int KF = (W3 + 31) / 32;             // K-steps of M = W3 dT over the outputs
+  static constexpr int O_A3B = S::NET_BYTES;            // W3 as [k][f] A operands: [2][KF][64 lanes][8]
+  static constexpr int NET_BYTES = O_A3B + 2 * KF * 1024;
+  static constexpr int P1_H1 = 0;                       // float [16][S1]
+  static constexpr int P1_HT = P1_H1 + 16 * S::S1 * 4;  // float [32][GTS]: h2 transposed (features x neighbours)
+  static constexpr int P1_R = P1_HT + 32 * S::GTS * 4;  // float [16][4]
+  static constexpr int P1_BYTES = P1_R + 256;
+  static constexpr int P2_H1 = 0;                       // float [2][16][S1] (h, dh)
+  static constexpr int P2_DT = P2_H1 + 2 * 16 * S::S1 * 4;  // float [S3][4]
+  static constexpr int P2_GR = P2_DT + S::S3 * 16;      // float [64][4]
+  static constexpr int P2_BYTES = P2_GR + 1024;
+};
+
+template <int W1, int W2, int W3, int P>
+__global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_fwd_lin(MixArgs a) {
+  typedef Shape<W1, W2, W3> S;
+  typedef LinShape<W1, W2, W3> LS;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Dims &d = a.d;
+  const int nnets = d.ntypes * d.ntypes;
+  copy_nets(smem, a.nets, nnets * LS::NET_BYTES);
   __syncthreads();
-  if (threadIdx.x < 9) {
-    double v = 0.0;
-    for (int w = 0; w < MIX_WAVES; ++w) v += vred[w][threadIdx.x];
-    a.vir_part[(int64_t)blockIdx.x * 9 + threadIdx.x] = v;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, n = lane & 15;
+  unsigned char *ws = smem + nnets * LS::NET_BYTES + wv * LS::P1_BYTES;
+  float *h1s = (float *)(ws + LS::P1_H1);
+  float *Hs = (float *)(ws + LS::P1_HT);
+  float *Rs = (float *)(ws + LS::P1_R);
+  int64_t p0, p1;
+  wave_rows(a.rows, p0, p1);
+  for (int64_t p = p0; p < p1; ++p) {
+    const int i = a.atom_of_pos[p];
+    if (i < 0) continue;
+    const int t = (int)a.xw[i].w;
+    v4f Tacc[S::MT3];
+#pragma unroll
+    for (int mt = 0; mt < S::MT3; ++mt) Tacc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int u = 0; u < d.ntypes; ++u) {
+      const unsigned char *net = smem + (t * d.ntypes + u) * LS::NET_BYTES;
+      const float *w1 = (const float *)(net + S::O_W1), *b1 = (const float *)(net + S::O_B1);
+      const float *b2 = (const float *)(net + S::O_B2), *b3 = (const float *)(net + S::O_B3);
+      const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
+      if (cnt == 0) continue;
+      const int64_t base = (int64_t)i * d.nnei + d.off[u];
+      v4f Hacc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+      float sr0 = 0.f, sr1 = 0.f, sr2 = 0.f, sr3 = 0.f;  // this lane's neighbours: sum of R
+      for (int n0 = 0; n0 < cnt; n0 += 16) {
+        const bool valid = n0 + n < cnt;
+        const double4 r4 = valid ? a.rt[base + n0 + n] : make_double4(0.0, 0.0, 0.0, 0.0);
+        const float s = (float)r4.x;
+        if (g == 0) *(float4 *)(Rs + 4 * n) = make_float4((float)r4.x, (float)r4.y, (float)r4.z, (float)r4.w);
+        sr0 += (float)r4.x;
+        sr1 += (float)r4.y;
+        sr2 += (float)r4.z;
+        sr3 += (float)r4.w;
+        float h1[2][4], hd_unused[2][4];
+        layer1<W1, false>(w1, b1, s, g, h1, hd_unused);
+        if (S::SK2 == 2)
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt)
+            *(float4 *)(h1s + n * S::S1 + 16 * mt + 4 * g) = make_float4(h1[mt][0], h1[mt][1], h1[mt][2], h1[mt][3]);
+        Split8<P> B2[1] = {split8<P>(h1[0], h1[1])};
+        v4f acc2[S::MT2];
+        layer_mfma<P, S::MT2, 1>(net + S::O_A2, b2, B2, lane, g, acc2);
+        wsync();
+        // h2, written transposed (features x neighbours) for H += h2^T R
+#pragma unroll
+        for (int mt = 0; mt < S::MT2; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int f = 16 * mt + 4 * g + r;
+            float v = 0.f;
+            if (16 * mt < W2 && f < W2) v = tanh_f(acc2[mt][r]) + skip_val<W1, W2, S::SK2, 2>(f, mt, r, h1, h1s, n, S::S1);
+            Hs[f * S::GTS + n] = v;
+          }
+        wsync();
+        const RSplit RB = rsplit<P>(Rs, n, g);
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) Hacc[mt] = tacc16<P>(Hs + (16 * mt + n) * S::GTS, RB, Rs, n, g, Hacc[mt]);
+        wsync();
+      }
+      // T += W3^T H: H (lane (g, n): H[16 mt + 4 g + r][c = n]) is the K-permuted B operand
+      float hx[4], hy[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        hx[r] = Hacc[0][r];
+        hy[r] = Hacc[1][r];
+      }
+      const Split8<P> HB[1] = {split8<P>(hx, hy)};
+#pragma unroll
+      for (int mt = 0; mt < S::MT3; ++mt) {
+        const v4f z = mfma_tile<P, 1>(net + S::O_A3, nullptr, HB, lane, g, mt);
+        Tacc[mt] += z;
+      }
+      // + b3 (sum R)^T: sum over the 16 neighbour lanes of a row, component c = n
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        sr0 += __shfl_xor(sr0, o);
+        sr1 += __shfl_xor(sr1, o);
+        sr2 += __shfl_xor(sr2, o);
+        sr3 += __shfl_xor(sr3, o);
+      }
+      const float src = n == 0 ? sr0 : (n == 1 ? sr1 : (n == 2 ? sr2 : (n == 3 ? sr3 : 0.f)));
+#pragma unroll
+      for (int mt = 0; mt < S::MT3; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int f = 16 * mt + 4 * g + r;
+          if (f < W3) Tacc[mt][r] += b3[f] * src;
+        }
+    }
+    float *Tg = a.T32 + (int64_t)i * d.M1 * 4;
+#pragma unroll
+    for (int mt = 0; mt < S::MT3; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int f = 16 * mt + 4 * g + r;
+        if (n < 4 && f < d.M1) Tg[4 * f + n] = Tacc[mt][r] * (float)d.inv_nc;
+      }
   }
+}
+
+template <int W1, int W2, int W3, int P>
+__global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_bwd_lin(MixArgs a) {
+  typedef Shape<W1, W2, W3> S;
+  typedef LinShape<W1, W2, W3> LS;
+  typedef typename HT<P>::v8 V;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double vred[MIX_WAVES][9];
+  const Dims &d = a.d;
+  const int nnets = d.ntypes * d.ntypes;
+  copy_nets(smem, a.nets, nnets * LS::NET_BYTES);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, n = lane & 15;
+  unsigned char *ws = smem + nnets * LS::NET_BYTES + wv * LS::P2_BYTES;
+  float *h1s = (float *)(ws + LS::P2_H1), *hd1s = h1s + 16 * S::S1;
+  float *dTs = (float *)(ws + LS::P2_DT);
+  float *gRs = (float *)(ws + LS::P2_GR);
+  const double rc = d.rcut, rcs = d.rcut_smth, inv_w = 1.0 / (d.rcut - d.rcut_smth);
+  double vir[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) vir[k] = 0.0;
+  int64_t p0, p1;
+  wave_rows(a.rows, p0, p1);
+  for (int64_t p = p0; p < p1; ++p) {
+    const int i = a.atom_of_pos[p];
+    if (i < 0) continue;
+    const int t = (int)a.xw[i].w;
+    {
+      const float *dTi = a.dT32 + (int64_t)i * d.M1 * 4;
+      for (int o = lane; o < S::S3 * 4; o += 64) dTs[o] = (o >> 2) < d.M1 ? dTi[o] : 0.f;
+    }
+    wsync();
+    // B operands of M = W3 dT: K = outputs f = 32 kk + 8 g + v, N = components c = n
+    Split8<P> dB[LS::KF];
+#pragma unroll
+    for (int kk = 0; kk < LS::KF; ++kk) {
+      float x[4], y[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int f0 = 32 * kk + 8 * g + v, f1 = f0 + 4;
+        x[v] = (n < 4 && f0 < W3) ? dTs[4 * f0 + n] : 0.f;
+        y[v] = (n < 4 && f1 < W3) ? dTs[4 * f1 + n] : 0.f;
+      }
+      dB[kk] = split8<P>(x, y);
+    }
+    double fi0 = 0.0, fi1 = 0.0, fi2 = 0.0;
+    for (int u = 0; u < d.ntypes; ++u) {
+      const unsigned char *net = smem + (t * d.ntypes + u) * LS::NET_BYTES;
+      const float *w1 = (const float *)(net + S::O_W1), *b1 = (const float *)(net + S::O_B1);
+      const float *b2 = (const float *)(net + S::O_B2), *b3 = (const float *)(net + S::O_B3);
+      const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
+      if (cnt == 0) continue;
+      const int64_t base = (int64_t)i * d.nnei + d.off[u];
+      // M = W3 dT (lane (g, n): M[16 mt + 4 g + r][c = n]) and q = b3^T dT
+      v4f Macc[2];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        Macc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < LS::KF; ++kk) {
+          const V av = *(const V *)(net + LS::O_A3B + ((mt * LS::KF + kk) * 64 + lane) * 16);
+          Macc[mt] = mfma16<P>(av, dB[kk].hi, Macc[mt]);
+          Macc[mt] = mfma16<P>(av, dB[kk].lo, Macc[mt]);
+        }
+      }
+      float q = 0.f;
+      if (n < 4)
+        for (int f = g; f < W3; f += 4) q += b3[f] * dTs[4 * f + n];
+      q += __shfl_xor(q, 16);
+      q += __shfl_xor(q, 32);
+      const float q0 = __shfl(q, 0), q1 = __shfl(q, 1), q2 = __shfl(q, 2), q3 = __shfl(q, 3);
+      float mx[4], my[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        mx[r] = Macc[0][r];
+        my[r] = Macc[1][r];
+      }
+      const Split8<P> MA = split8<P>(mx, my);
+      for (int n0 = 0; n0 < cnt; n0 += 16) {
+        const bool valid = n0 + n < cnt;
+        const double4 r4 = valid ? a.rt[base + n0 + n] : make_double4(0.0, 0.0, 0.0, 0.0);
+        const float s = (float)r4.x;
+        float h1[2][4], hd1[2][4];
+        layer1<W1, true>(w1, b1, s, g, h1, hd1);
+        if (S::SK2 == 2)
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt) {
+            *(float4 *)(h1s + n * S::S1 + 16 * mt + 4 * g) = make_float4(h1[mt][0], h1[mt][1], h1[mt][2], h1[mt][3]);
+            *(float4 *)(hd1s + n * S::S1 + 16 * mt + 4 * g) =
+                make_float4(hd1[mt][0], hd1[mt][1], hd1[mt][2], hd1[mt][3]);
+          }
+        Split8<P> B2h[1] = {split8<P>(h1[0], h1[1])}, B2d[1] = {split8<P>(hd1[0], hd1[1])};
+        v4f acc2[S::MT2], acc2d[S::MT2];
+        layer_mfma<P, S::MT2, 1>(net + S::O_A2, b2, B2h, lane, g, acc2);
+        layer_mfma_tan<P, S::MT2, 1>(net + S::O_A2, B2d, lane, acc2d);
+        wsync();
+        float h2[S::MT2][4], hd2[S::MT2][4];
+#pragma unroll
+        for (int mt = 0; mt < S::MT2; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int f = 16 * mt + 4 * g + r;
+            float hv = 0.f, dv = 0.f;
+            if (16 * mt < W2 && f < W2) {
+              const float th = tanh_f(acc2[mt][r]);
+              hv = th + skip_val<W1, W2, S::SK2, 2>(f, mt, r, h1, h1s, n, S::S1);
+              dv = (1.f - th * th) * acc2d[mt][r] + skip_val<W1, W2, S::SK2, 2>(f, mt, r, hd1, hd1s, n, S::S1);
+            }
+            h2[mt][r] = hv;
+            hd2[mt][r] = dv;
+          }
+        const Split8<P> B3h = split8<P>(h2[0], h2[1]), B3d = split8<P>(hd2[0], hd2[1]);
+        // a = M^T h2 and b = M^T h2' (lane (g, n): component c = 4 g + r of neighbour n)
+        v4f ca = v4f{0.f, 0.f, 0.f, 0.f}, cb = v4f{0.f, 0.f, 0.f, 0.f};
+        ca = mfma16<P>(MA.hi, B3h.hi, ca);
+        ca = mfma16<P>(MA.hi, B3h.lo, ca);
+        ca = mfma16<P>(MA.lo, B3h.hi, ca);
+        cb = mfma16<P>(MA.hi, B3d.hi, cb);
+        cb = mfma16<P>(MA.hi, B3d.lo, cb);
+        cb = mfma16<P>(MA.lo, B3d.hi, cb);
+        const int slot0 = n0 & 63;
+        if (g == 0) {
+          // dE/dR = a + q + (R . b) e_0
+          const float bd = (float)r4.x * cb[0] + (float)r4.y * cb[1] + (float)r4.z * cb[2] + (float)r4.w * cb[3];
+          *(float4 *)(gRs + 4 * (slot0 + n)) = make_float4(ca[0] + q0 + bd, ca[1] + q1, ca[2] + q2, ca[3] + q3);
+        }
+        wsync();
+        // every 64 neighbours (or at the end of the type block): FP64 force pass
+        if (((n0 + 16) & 63) == 0 || n0 + 16 >= cnt) {
+          const int c0 = n0 & ~63;
+          const int qq = c0 + lane;
+          if (qq < cnt) {
+            const float4 gr = *(const float4 *)(gRs + 4 * lane);
+            force_pair(a, base + qq, gr, rc, rcs, inv_w, fi0, fi1, fi2, vir);
+          }
+          wsync();
+        }
+      }
+    }
+    finish_atom_force(a, i, lane, fi0, fi1, fi2);
+  }
+  finish_block_virial(a, vir, vred, lane, wv);
 }
 
 // ---------------------------------------------------------------------------
 // host side: weight packing and dispatch
 // ---------------------------------------------------------------------------
-template <int W1, int W2, int W3>
+template <int W1, int W2, int W3, int LIN>
 static size_t net_bytes_t() {
-  return Shape<W1, W2, W3>::NET_BYTES;
+  if constexpr (LIN) return LinShape<W1, W2, W3>::NET_BYTES;
+  else return Shape<W1, W2, W3>::NET_BYTES;
 }
 
 static inline uint16_t to_f16(float x) {
@@ -707,10 +1009,10 @@ static inline uint16_t to_bf16(float x) {
 }
 
 // Pack one net (t,u) into the LDS image; W[l] are row-major [in][out] doubles.
-template <int W1, int W2, int W3>
+template <int W1, int W2, int W3, int LIN>
 static void pack_net_t(const double *const *W, const double *const *b, int prec, unsigned char *out) {
   typedef Shape<W1, W2, W3> S;
-  std::memset(out, 0, S::NET_BYTES);
+  std::memset(out, 0, net_bytes_t<W1, W2, W3, LIN>());
   float *w1 = (float *)(out + S::O_W1), *b1 = (float *)(out + S::O_B1);
   for (int f = 0; f < W1; ++f) {
     w1[f] = (float)W[0][f];
@@ -738,12 +1040,36 @@ static void pack_net_t(const double *const *W, const double *const *b, int prec,
         }
   float *b3 = (float *)(out + S::O_B3);
   for (int f = 0; f < W3; ++f) b3[f] = (float)b[2][f];
+  if constexpr (LIN) {
+    // W3 itself as A operands of M = W3 dT: rows k = 16 mt + lane%16,
+    // K = outputs f = 32 kk + 8 (lane/16) + v in natural order
+    typedef LinShape<W1, W2, W3> LS;
+    uint16_t *A3B = (uint16_t *)(out + LS::O_A3B);
+    for (int mt = 0; mt < 2; ++mt)
+      for (int kk = 0; kk < LS::KF; ++kk)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int v = 0; v < 8; ++v) {
+            const int k = 16 * mt + (lane & 15), f = 32 * kk + 8 * (lane >> 4) + v;
+            A3B[((mt * LS::KF + kk) * 64 + lane) * 8 + v] = (k < W2 && f < W3) ? h16(W[2][k * W3 + f]) : 0;
+          }
+  }
 }
 
 template <int W1, int W2, int W3, int LIN, int P>
 static void launch_t(hipStream_t s, const MixArgs &a, int pass, int grid) {
   typedef Shape<W1, W2, W3> S;
   const int nnets = a.d.ntypes * a.d.ntypes;
+  if constexpr (LIN) {
+    typedef LinShape<W1, W2, W3> LS;
+    if (pass == 1) {
+      const size_t shm = (size_t)nnets * LS::NET_BYTES + (size_t)MIX_WAVES * LS::P1_BYTES;
+      hipLaunchKernelGGL((k_embed_fwd_lin<W1, W2, W3, P>), dim3(grid), dim3(64 * MIX_WAVES), shm, s, a);
+    } else {
+      const size_t shm = (size_t)nnets * LS::NET_BYTES + (size_t)MIX_WAVES * LS::P2_BYTES;
+      hipLaunchKernelGGL((k_embed_bwd_lin<W1, W2, W3, P>), dim3(grid), dim3(64 * MIX_WAVES), shm, s, a);
+    }
+    return;
+  }
   if (pass == 1) {
     const size_t shm = (size_t)nnets * S::NET_BYTES + (size_t)MIX_WAVES * S::P1_BYTES;
     hipLaunchKernelGGL((k_embed_fwd_mix<W1, W2, W3, LIN, P>), dim3(grid), dim3(64 * MIX_WAVES), shm, s, a);
@@ -753,10 +1079,15 @@ static void launch_t(hipStream_t s, const MixArgs &a, int pass, int grid) {
   }
 }
 
-template <int W1, int W2, int W3>
+template <int W1, int W2, int W3, int LIN>
 static size_t lds_t(int ntypes, int pass) {
-  typedef Shape<W1, W2, W3> S;
-  return (size_t)ntypes * ntypes * S::NET_BYTES + (size_t)MIX_WAVES * (pass == 1 ? S::P1_BYTES : S::P2_BYTES);
+  if constexpr (LIN) {
+    typedef LinShape<W1, W2, W3> LS;
+    return (size_t)ntypes * ntypes * LS::NET_BYTES + (size_t)MIX_WAVES * (pass == 1 ? LS::P1_BYTES : LS::P2_BYTES);
+  } else {
+    typedef Shape<W1, W2, W3> S;
+    return (size_t)ntypes * ntypes * S::NET_BYTES + (size_t)MIX_WAVES * (pass == 1 ? S::P1_BYTES : S::P2_BYTES);
+  }
 }
 
 // supported embedding shapes: widths of the three layers, affine last layer
@@ -775,8 +1106,8 @@ int mix_shape_id(const Dims &d) {
 
 size_t mix_net_bytes(int shape) {
   int id = 0;
-#define X(a_, b_, c_, l_)                              \
-  if (shape == id) return net_bytes_t<a_, b_, c_>(); \
+#define X(a_, b_, c_, l_)                                  \
+  if (shape == id) return net_bytes_t<a_, b_, c_, l_>(); \
   ++id;
   DPK_MIX_SHAPES(X)
 #undef X
@@ -785,8 +1116,8 @@ size_t mix_net_bytes(int shape) {
 
 size_t mix_lds_bytes(int shape, int ntypes, int pass) {
   int id = 0;
-#define X(a_, b_, c_, l_)                                 \
-  if (shape == id) return lds_t<a_, b_, c_>(ntypes, pass); \
+#define X(a_, b_, c_, l_)                                     \
+  if (shape == id) return lds_t<a_, b_, c_, l_>(ntypes, pass); \
   ++id;
   DPK_MIX_SHAPES(X)
 #undef X
@@ -797,7 +1128,7 @@ void mix_pack_net(int shape, const double *const *W, const double *const *b, int
   int id = 0;
 #define X(a_, b_, c_, l_)                           \
   if (shape == id) {                                \
-    pack_net_t<a_, b_, c_>(W, b, prec, out);        \
+    pack_net_t<a_, b_, c_, l_>(W, b, prec, out);    \
     return;                                         \
   }                                                 \
   ++id;
