@@ -48,7 +48,7 @@ enum {
   DP_E_HIP = -7,       /* a HIP runtime call failed                         */
   DP_E_NONFINITE = -8, /* non-finite energy (MD driver)                     */
   DP_E_CAP = -9        /* more neighbours within rc of one atom than the
-                          per-atom sort buffer (1024) holds                 */
+                          per-atom sort buffer (512) holds                  */
 };
 
 /* Precision policies (after the paper's MIX-16 scheme, Section V-A

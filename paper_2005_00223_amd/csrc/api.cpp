@@ -1196,7 +1196,7 @@ static int compute_impl(dp_ctx *c, int64_t n, const double *coords, const int32_
     if (rc) return rc;
     const uint32_t fl = c->h_status->flags;
     if (fl & FLAG_BAD_TYPE) return fail(c, DP_E_TYPE, "atom type out of range");
-    if (fl & FLAG_KEY_CAP) return fail(c, DP_E_CAP, "more than 1024 neighbours within rcut of one atom");
+    if (fl & FLAG_KEY_CAP) return fail(c, DP_E_CAP, "more than 512 neighbours within rcut of one atom");
     if (fl & FLAG_CAND_CAP) {
       cap *= 2;
       if (c->timing && c->nev > 0) --c->nev;
@@ -1380,7 +1380,7 @@ int dp_md_run(dp_ctx *c, int64_t n, double *coords, double *vel, const int32_t *
       if (rc) return rc;
       const uint32_t fl = c->h_status->flags;
       if (fl & FLAG_BAD_TYPE) return fail(c, DP_E_TYPE, "atom type out of range");
-      if (fl & FLAG_KEY_CAP) return fail(c, DP_E_CAP, "more than 1024 neighbours within rcut of one atom");
+      if (fl & FLAG_KEY_CAP) return fail(c, DP_E_CAP, "more than 512 neighbours within rcut of one atom");
       if (fl & FLAG_CAND_CAP) return fail(c, DP_E_CAP, "skin candidate list overflow; use a smaller skin");
       if (fl & FLAG_NONFINITE) return fail(c, DP_E_NONFINITE, "non-finite energy at step " + std::to_string(st));
     }

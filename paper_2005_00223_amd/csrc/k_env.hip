@@ -14,6 +14,8 @@
 
 namespace dpk {
 
+constexpr int ENV_BATCH = 4;  // gathers in flight per lane
+
 __device__ inline double env_min_image(double v, double L) {
   if (v > 0.5 * L) v -= L;
   else if (v < -0.5 * L) v += L;
@@ -32,27 +34,41 @@ __global__ void __launch_bounds__(256) k_env(int64_t n, const double4 *__restric
   for (int u = 0; u < d.ntypes; ++u) {
     int cnt = nreal[i * d.ntypes + u];
     int64_t base = i * (int64_t)d.nnei + d.off[u];
-    for (int q = lane; q < cnt; q += 64) {
-      int j = nlist[base + q];
-      double4 pj = xw[j];
-      double dx = env_min_image(pj.x - p.x, L0);
-      double dy = env_min_image(pj.y - p.y, L1);
-      double dz = env_min_image(pj.z - p.z, L2);
-      double r = sqrt(dx * dx + dy * dy + dz * dz);
-      double sw;
-      if (r < rcs) {
-        sw = 1.0;
-      } else if (r < rc) {
-        double x = (r - rcs) * inv_w;
-        sw = x * x * x * (-6.0 * x * x + 15.0 * x - 10.0) + 1.0;
-      } else {
-        sw = 0.0;
+    for (int q0 = 0; q0 < cnt; q0 += 64 * ENV_BATCH) {
+      // issue the list loads, then the position gathers, of ENV_BATCH rounds
+      int jb[ENV_BATCH];
+      double4 pb[ENV_BATCH];
+#pragma unroll
+      for (int v = 0; v < ENV_BATCH; ++v) {
+        const int q = q0 + 64 * v + lane;
+        jb[v] = q < cnt ? nlist[base + q] : -1;
       }
-      double inv_r = 1.0 / r;
-      double s = sw * inv_r;
-      double t = s * inv_r;
-      rt[base + q] = make_double4(s, t * dx, t * dy, t * dz);
-      dr[base + q] = make_double4(dx, dy, dz, r);
+#pragma unroll
+      for (int v = 0; v < ENV_BATCH; ++v) pb[v] = jb[v] >= 0 ? xw[jb[v]] : p;
+#pragma unroll
+      for (int v = 0; v < ENV_BATCH; ++v) {
+        const int q = q0 + 64 * v + lane;
+        if (jb[v] < 0) continue;
+        const double4 pj = pb[v];
+        double dx = env_min_image(pj.x - p.x, L0);
+        double dy = env_min_image(pj.y - p.y, L1);
+        double dz = env_min_image(pj.z - p.z, L2);
+        double r = sqrt(dx * dx + dy * dy + dz * dz);
+        double sw;
+        if (r < rcs) {
+          sw = 1.0;
+        } else if (r < rc) {
+          double x = (r - rcs) * inv_w;
+          sw = x * x * x * (-6.0 * x * x + 15.0 * x - 10.0) + 1.0;
+        } else {
+          sw = 0.0;
+        }
+        double inv_r = 1.0 / r;
+        double s = sw * inv_r;
+        double t = s * inv_r;
+        rt[base + q] = make_double4(s, t * dx, t * dy, t * dz);
+        dr[base + q] = make_double4(dx, dy, dz, r);
+      }
     }
   }
 }

@@ -305,10 +305,17 @@ void launch_candidates(hipStream_t s, int64_t n, const double4 *xw, const CellGr
 }
 
 // ---------------------------------------------------------------------------
-// formatting (Section V-A): one wave per atom, keys in LDS, rank sort
+// formatting (Section V-A): one wave per atom, keys in LDS.  The keys are
+// ranked exactly by a bucketed counting sort: bucket = type * FMT_NB +
+// (quantised distance * FMT_NB) / (quantised rc + 1), monotone in the key,
+// so rank = (keys in lower buckets, from a prefix scan of the bucket
+// histogram) + (smaller keys of the same bucket, from the bucket's linked
+// list in LDS).
 // ---------------------------------------------------------------------------
 constexpr int FMT_WAVES = 4;
-constexpr int FMT_CAP = 1024;
+constexpr int FMT_CAP = KEY_CAP;
+constexpr int FMT_NB = 32;   // distance buckets per type
+constexpr int FMT_BATCH = 4; // candidate gathers in flight per lane
 
 __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__restrict__ xw, Dims d, double L0,
                                                 double L1, double L2, const int32_t *__restrict__ cand,
@@ -316,22 +323,44 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
                                                 int32_t *__restrict__ nlist, int32_t *__restrict__ nreal,
                                                 unsigned long long *overflow, int32_t *max_real, uint32_t *flags) {
   __shared__ unsigned long long keys[FMT_WAVES][FMT_CAP];
+  __shared__ int16_t next[FMT_WAVES][FMT_CAP];
+  __shared__ int32_t head[FMT_WAVES][MAXT * FMT_NB];
+  __shared__ int32_t bstart[FMT_WAVES][MAXT * FMT_NB];
   __shared__ int32_t kcount[FMT_WAVES];
   __shared__ int32_t tcnt[FMT_WAVES][MAXT];
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int64_t i = (int64_t)blockIdx.x * FMT_WAVES + wv;
   if (i >= n) return;
+  const int nb_tot = d.ntypes * FMT_NB;
   if (lane == 0) kcount[wv] = 0;
   if (lane < MAXT) tcnt[wv][lane] = 0;
+  for (int b = lane; b < nb_tot; b += 64) {
+    head[wv][b] = -1;
+    bstart[wv][b] = 0;
+  }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const unsigned long long qlim = (unsigned long long)floor(d.rcut * 1e8) + 1ull;
   double4 p = xw[i];
   int nc = cand_n[i];
   const int32_t *ci = cand + i * (int64_t)cap;
-  for (int q = lane; q < nc; q += 64) {
-    int32_t j = ci[q];
-    double4 pj = xw[j];
+  for (int q0 = 0; q0 < nc; q0 += 64 * FMT_BATCH) {
+    // issue the index loads, then the position gathers, of FMT_BATCH rounds
+    int32_t jb[FMT_BATCH];
+    double4 pb[FMT_BATCH];
+#pragma unroll
+    for (int u = 0; u < FMT_BATCH; ++u) {
+      const int q = q0 + 64 * u + lane;
+      jb[u] = q < nc ? ci[q] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < FMT_BATCH; ++u) pb[u] = jb[u] >= 0 ? xw[jb[u]] : p;
+#pragma unroll
+    for (int u = 0; u < FMT_BATCH; ++u) {
+    const int32_t j = jb[u];
+    if (j < 0) continue;
+    const double4 pj = pb[u];
     double dx = min_image(pj.x - p.x, L0);
     double dy = min_image(pj.y - p.y, L1);
     double dz = min_image(pj.z - p.z, L2);
@@ -343,8 +372,14 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
       int tj = (int)pj.w;
       unsigned long long key = ((unsigned long long)tj << 58) | (qd << 26) | (unsigned long long)j;
       int slot = atomicAdd(&kcount[wv], 1);
-      if (slot < FMT_CAP) keys[wv][slot] = key;
+      if (slot < FMT_CAP) {
+        keys[wv][slot] = key;
+        const int b = tj * FMT_NB + (int)((qd * FMT_NB) / qlim);
+        next[wv][slot] = (int16_t)atomicExch(&head[wv][b], slot);
+        atomicAdd(&bstart[wv][b], 1);
+      }
       atomicAdd(&tcnt[wv][tj], 1);
+    }
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -355,6 +390,28 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
     if (lane == 0) atomicOr(flags, FLAG_KEY_CAP);
     k = FMT_CAP;
   }
+  // exclusive scan of the bucket histogram: lane takes a run of buckets
+  {
+    const int per = (nb_tot + 63) / 64;
+    const int b0 = lane * per;
+    int run = 0;
+    for (int b = b0; b < b0 + per && b < nb_tot; ++b) run += bstart[wv][b];
+    int incl = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o);
+      if (lane >= o) incl += v;
+    }
+    int acc = incl - run;
+    for (int b = b0; b < b0 + per && b < nb_tot; ++b) {
+      const int c = bstart[wv][b];
+      bstart[wv][b] = acc;
+      acc += c;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   int tstart[MAXT], treal[MAXT];
   {
     int run = 0;
@@ -366,12 +423,13 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
     }
   }
   int32_t *row = nlist + i * (int64_t)d.nnei;
-  // rank of each key among all keys of this atom (keys are distinct)
+  // exact rank of each key (keys are distinct)
   for (int q = lane; q < k; q += 64) {
-    unsigned long long key = keys[wv][q];
-    int rank = 0;
-    for (int r = 0; r < k; ++r) rank += (keys[wv][r] < key) ? 1 : 0;
-    int t = (int)(key >> 58);
+    const unsigned long long key = keys[wv][q];
+    const int t = (int)(key >> 58);
+    const int b = t * FMT_NB + (int)((((key >> 26) & 0xffffffffull) * FMT_NB) / qlim);
+    int rank = bstart[wv][b];
+    for (int m = head[wv][b]; m >= 0; m = next[wv][m]) rank += (keys[wv][m] < key) ? 1 : 0;
     int pos = rank - tstart[t];
     // pos < 0 can only happen when the key buffer overflowed (flagged above)
     if (pos >= 0 && pos < d.sel[t]) row[d.off[t] + pos] = (int32_t)(key & ((1ull << 26) - 1ull));
@@ -385,7 +443,11 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
   if (lane < d.ntypes) {
     int c = tcnt[wv][lane];
     nreal[i * d.ntypes + lane] = treal[lane];
-    atomicMax(&max_real[lane], c);
+    // the maximum only grows during the launch, so a stale read can only
+    // cost an extra atomic; skipping the rest keeps 500k waves from
+    // serialising on one address
+    if (c > __hip_atomic_load(&max_real[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(&max_real[lane], c);
     if (c > d.sel[lane]) atomicAdd(overflow, (unsigned long long)(c - d.sel[lane]));
   }
 }
