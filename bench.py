@@ -5,7 +5,9 @@ Headline: mixed precision (FP16 matrix-core products) with the student
 embedding net.  The timed region starts with the in-run training of the
 student on the current frame (sampling, teacher targets, Adam, least-squares
 output layer), then runs the MD steps with the student, the full teacher
-nets judging its forces every 20 steps (fallback above 1e-3 eV/A).  The same
+nets judging its forces every 20 steps (fallback above 1e-3 eV/A) on the
+atoms of a 60 A cube placed anew each time (teacher evaluated on the cube
+and its rc margin; --judge-side 0 judges every atom).  The same
 precision without the student, and the FP64 path, are timed after it for
 comparison.
 
@@ -134,6 +136,8 @@ def main():
     ap.add_argument("--precision", default="fp16", choices=["fp64", "fp16", "bf16"])
     ap.add_argument("--no-student", action="store_true", help="time the teacher nets only")
     ap.add_argument("--judge-every", type=int, default=20)
+    ap.add_argument("--judge-side", type=float, default=60.0,
+                    help="judge the atoms of a cube of this side (A) at a new place each time; 0 = all atoms")
     ap.add_argument("--teacher-steps", type=int, default=5,
                     help="steps of the same precision without the student, timed for comparison (0 = skip)")
     ap.add_argument("--fp64-steps", type=int, default=3, help="FP64 steps timed for the comparison (0 = skip)")
@@ -192,7 +196,7 @@ def main():
     log("[bench] warmup done")
     out_extra = {}
     if student:
-        m.student_judge(args.judge_every, 1e-3)
+        m.student_judge(args.judge_every, 1e-3, sample_side=args.judge_side)
     m.enable_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -213,6 +217,7 @@ def main():
         out_extra["student"] = {
             "train_ms": t_train * 1e3, "md_ms_per_step": (sec - t_train) / args.steps * 1e3,
             "fit_rel_rmse_G": fit, "judge_every": args.judge_every, "judge_max_force_rmse": 1e-3,
+            "judge_cube_side_A": args.judge_side, "judge_atoms": st["judge_atoms"],
             "last_judge_force_rmse": st["last_judge_rmse"], "teacher_fallbacks": st["teacher_fallbacks"],
             "student_evals": st["student_evals"],
             "net": "1-16-32-100 (tanh, tanh + doubling skip, affine) per type pair; Adam 500 x 4096 samples "

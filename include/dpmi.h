@@ -74,6 +74,7 @@ typedef struct {
   int64_t student_evals;     /* evaluations that used the student net        */
   int64_t teacher_fallbacks; /* judge rejections of the student net          */
   double last_judge_rmse;    /* force RMSE student vs teacher, eV/A          */
+  int64_t judge_atoms;       /* atoms the last judge covered                 */
 } dp_stats;
 
 /* Create a context on HIP device `device`; `hip_stream` is a hipStream_t
@@ -240,6 +241,17 @@ int dp_student_use(dp_ctx *c, int on);
  * and uses the teacher for the rest of the run (stats.teacher_fallbacks).
  * Defaults: every 20 steps, 1e-3 eV/A. */
 int dp_student_judge(dp_ctx *c, int64_t every, double max_force_rmse);
+
+/* Sampled judge (side > 0, A): the teacher is evaluated only on the atoms of
+ * a cube of that side and on the atoms within rc of it, which gives every
+ * atom of the cube its exact teacher force; the RMSE of the judge is taken
+ * over the cube's atoms.  The cube's centre for the judge at MD step k is
+ * L_a * u_a with u_a = (x >> 11) * 2^-53, x = SplitMix64 output number
+ * 3k + a of the stream seeded with 0x6a75646765.  A rejected sample is
+ * confirmed by a full teacher evaluation before the fallback.  side = 0
+ * (the default), or a cube that with its rc margins does not fit the box,
+ * judges all atoms. */
+int dp_student_judge_sample(dp_ctx *c, double side);
 
 /* The installed student as a model blob (DPMIBLOB version 2: the student
  * embedding nets with an affine last layer, the teacher's fitting nets):

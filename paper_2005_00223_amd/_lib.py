@@ -19,14 +19,16 @@ EXPORTS = ("dp_create", "dp_set_model", "dp_set_precision", "dp_compute", "dp_en
            "dp_get_nlist", "dp_keep_intermediates",
            "dp_get_intermediates", "dp_get_stats", "dp_md_run", "dp_enable_timing", "dp_get_timing",
            "dp_student_default_cfg", "dp_student_train", "dp_student_get_params", "dp_student_set_params",
-           "dp_student_batch_grad", "dp_student_use", "dp_student_judge", "dp_student_get_model",
+           "dp_student_batch_grad", "dp_student_use", "dp_student_judge", "dp_student_judge_sample",
+           "dp_student_get_model",
            "dp_student_set_model", "dp_last_error", "dp_destroy")
 
 
 class dp_stats(C.Structure):
     _fields_ = [("natoms", C.c_int64), ("sel_overflow", C.c_int64), ("max_real", C.c_int32 * 8),
                 ("nlist_builds", C.c_int64), ("evaluations", C.c_int64), ("cand_cap", C.c_int64),
-                ("student_evals", C.c_int64), ("teacher_fallbacks", C.c_int64), ("last_judge_rmse", C.c_double)]
+                ("student_evals", C.c_int64), ("teacher_fallbacks", C.c_int64), ("last_judge_rmse", C.c_double),
+                ("judge_atoms", C.c_int64)]
 
 
 class dp_student_cfg(C.Structure):
@@ -76,6 +78,7 @@ def lib():
         "dp_student_batch_grad": (I32, [P, C.c_uint64, I64, I64, P, P, P]),
         "dp_student_use": (I32, [P, I32]),
         "dp_student_judge": (I32, [P, I64, D]),
+        "dp_student_judge_sample": (I32, [P, D]),
         "dp_student_get_model": (I32, [P, P, C.c_size_t, C.POINTER(C.c_size_t)]),
         "dp_student_set_model": (I32, [P, C.c_char_p, C.c_size_t]),
         "dp_last_error": (C.c_char_p, [P]),
@@ -192,6 +195,10 @@ def dp_student_use(ctx, on: bool):
 
 def dp_student_judge(ctx, every: int, max_force_rmse: float):
     return check(ctx, lib().dp_student_judge(ctx, int(every), float(max_force_rmse)))
+
+
+def dp_student_judge_sample(ctx, side: float):
+    return check(ctx, lib().dp_student_judge_sample(ctx, float(side)))
 
 
 def dp_student_get_model(ctx) -> bytes:

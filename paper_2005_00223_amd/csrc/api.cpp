@@ -116,7 +116,10 @@ struct DevStatus {
   unsigned long long overflow;
   int32_t max_real[MAXT];
   unsigned long long nbuild;
-  double judge_rmse;  // force RMSE of the last student judge
+  double judge_rmse;   // force RMSE of the last student judge
+  double judge_count;  // atoms it covered
+  int32_t sub_rows;    // padded rows of the judge's atom subset
+  int32_t pad2;
 };
 
 struct Workspace {
@@ -130,8 +133,10 @@ struct Workspace {
       *atom_of_pos, *blk_counts, *type_count, *type_start;
   double *T, *D, *dD, *Y[MAXF + 1], *Tt[MAXF + 1], *G[MAXF + 1], *eatom, *partial, *vir_part, *force_tmp,
       *net_deriv, *energy, *virial, *ke;
-  // student judge: teacher forces / energy / virial, RMSE partial sums
+  // student judge: teacher forces / energy / virial, RMSE partial sums,
+  // sampled-judge region marks and its type-padded row set
   double *force_j, *energy_j, *virial_j, *rmse_part;
+  int32_t *judge_mark, *sub_atom_of_pos, *sub_type_count, *sub_type_start, *sub_blk;
   // mixed-precision buffers
   float *T32, *dT32, *tbuf;
   int prec = -1;  // precision the buffers were laid out for
@@ -182,6 +187,10 @@ struct dp_ctx {
   Student *st = nullptr;            // student training state
   int64_t judge_every = 20;         // MD judge period (0 = off)
   double judge_max = 1e-3;          // eV/A
+  double judge_side = 0.0;          // > 0: judge the atoms of a cube of this side (A)
+  // row set of the evaluation when it is not the full one (sampled judge)
+  const int32_t *ov_atom_of_pos = nullptr, *ov_type_start = nullptr;
+  int64_t ov_rows = 0;
   Workspace ws;
   DevStatus *h_status = nullptr;  // pinned
   dp_stats stats{};
@@ -284,7 +293,12 @@ int ensure_ws(dp_ctx *c, int64_t n, int64_t ncell, int cand_cap) {
   add((void **)&w.force_j, sizeof(double) * 3 * nn);
   add((void **)&w.energy_j, sizeof(double) * 8);
   add((void **)&w.virial_j, sizeof(double) * 16);
-  add((void **)&w.rmse_part, sizeof(double) * 256);
+  add((void **)&w.rmse_part, sizeof(double) * 512);
+  add((void **)&w.judge_mark, 4 * nn);
+  add((void **)&w.sub_atom_of_pos, 4 * rows);
+  add((void **)&w.sub_type_count, 4 * MAXT);
+  add((void **)&w.sub_type_start, 4 * (MAXT + 1));
+  add((void **)&w.sub_blk, (size_t)4 * nblk * MAXT);
   add((void **)&w.status, sizeof(DevStatus));
   for (auto &pr : plan) off += (pr.second + 255) / 256 * 256;
   void *base = nullptr;
@@ -554,9 +568,9 @@ EmbedArgs embed_args(dp_ctx *c, int64_t n, int64_t rows, double *F) {
   ea.d = en.d;
   ea.eo = en.eo;
   ea.ew = en.d_emb;
-  ea.atom_of_pos = w.atom_of_pos;
+  ea.atom_of_pos = c->ov_atom_of_pos ? c->ov_atom_of_pos : w.atom_of_pos;
   ea.pos_of_atom = w.pos_of_atom;
-  ea.type_start = w.type_start;
+  ea.type_start = c->ov_type_start ? c->ov_type_start : w.type_start;
   ea.rows = rows;
   ea.natoms = n;
   ea.xw = w.xw;
@@ -579,8 +593,8 @@ FitArgs fit_args(dp_ctx *c, int64_t rows) {
   fa.d = c->dims;
   fa.fo = c->fo;
   fa.fwt = c->d_fit;
-  fa.type_start = w.type_start;
-  fa.atom_of_pos = w.atom_of_pos;
+  fa.type_start = c->ov_type_start ? c->ov_type_start : w.type_start;
+  fa.atom_of_pos = c->ov_atom_of_pos ? c->ov_atom_of_pos : w.atom_of_pos;
   fa.rows = rows;
   fa.X0 = w.D;
   for (int l = 0; l <= MAXF; ++l) {
@@ -601,7 +615,7 @@ MixArgs mix_args(dp_ctx *c, int64_t rows, double *F) {
   ma.prec = c->precision == DP_MIX_FP16 ? 0 : 1;
   ma.nets = en.d_mix;
   ma.rows = rows;
-  ma.atom_of_pos = w.atom_of_pos;
+  ma.atom_of_pos = c->ov_atom_of_pos ? c->ov_atom_of_pos : w.atom_of_pos;
   ma.xw = w.xw;
   ma.nlist = w.nlist;
   ma.nreal = w.nreal;
@@ -623,8 +637,8 @@ FitMixArgs fitmix_args(dp_ctx *c, int64_t rows) {
   fa.w = c->d_fit_mix;
   fa.prec = c->precision == DP_MIX_FP16 ? 0 : 1;
   fa.nsplit = c->n16;
-  fa.type_start = w.type_start;
-  fa.atom_of_pos = w.atom_of_pos;
+  fa.type_start = c->ov_type_start ? c->ov_type_start : w.type_start;
+  fa.atom_of_pos = c->ov_atom_of_pos ? c->ov_atom_of_pos : w.atom_of_pos;
   fa.rows = rows;
   fa.T32 = w.T32;
   fa.tbuf = w.tbuf;
@@ -635,6 +649,7 @@ FitMixArgs fitmix_args(dp_ctx *c, int64_t rows) {
 }
 
 int64_t eval_rows(const dp_ctx *c, int64_t n) {
+  if (c->ov_atom_of_pos) return c->ov_rows;
   return (n + ROW_TILE - 1) / ROW_TILE * ROW_TILE + (int64_t)ROW_TILE * c->dims.ntypes;
 }
 
@@ -742,17 +757,50 @@ int read_status(dp_ctx *c) {
 
 // Judge the student's forces F of the frame just evaluated against the
 // teacher's; on a rejection take the teacher's forces, energy and virial for
-// this frame and switch the context to the teacher.
-int judge_step(dp_ctx *c, int64_t n, double *F) {
+// this frame and switch the context to the teacher.  With judge_side > 0
+// the teacher is evaluated only on a cube of that side placed by SplitMix64
+// from the step number (stream 0x6a75646765, counters 3 step + axis) and on
+// the atoms within rc of it, which gives the cube's atoms their exact teacher
+// forces; the RMSE is taken over the cube.  A rejected sample is confirmed
+// by a full teacher evaluation before the fallback.
+int judge_step(dp_ctx *c, int64_t n, double *F, int64_t step, const double L[3]) {
   Workspace &w = c->ws;
   hipStream_t s = c->stream;
+  const double rc = c->dims.rcut;
+  const double side = c->judge_side;
+  if (side > 0.0 && side + 2.0 * rc < std::min(L[0], std::min(L[1], L[2]))) {
+    double ctr[3];
+    for (int a = 0; a < 3; ++a)
+      ctr[a] = L[a] * ((double)(sm64(0x6a75646765ull, 3ull * (uint64_t)step + (uint64_t)a) >> 11) * 0x1.0p-53);
+    launch_judge_mark(s, n, w.xw, ctr, L, 0.5 * side, 0.5 * side + rc, w.judge_mark);
+    launch_type_sort(s, n, w.xw, c->dims.ntypes, w.sub_blk, w.sub_type_count, w.sub_type_start, nullptr,
+                     w.sub_atom_of_pos, w.rows_cap, w.judge_mark);
+    launch_copy_i32(s, w.sub_type_start + c->dims.ntypes, &w.status->sub_rows);
+    int rc2 = read_status(c);
+    if (rc2) return rc2;
+    c->ov_atom_of_pos = w.sub_atom_of_pos;
+    c->ov_type_start = w.sub_type_start;
+    c->ov_rows = c->h_status->sub_rows;
+    eval_judge(c, n);
+    c->ov_atom_of_pos = c->ov_type_start = nullptr;
+    c->ov_rows = 0;
+    launch_force_rmse_masked(s, F, w.force_j, n, w.judge_mark, w.rmse_part, &w.status->judge_rmse,
+                             &w.status->judge_count);
+    HIPCHK(c, hipGetLastError());
+    rc2 = read_status(c);
+    if (rc2) return rc2;
+    c->stats.last_judge_rmse = c->h_status->judge_rmse;
+    c->stats.judge_atoms = (int64_t)c->h_status->judge_count;
+    if (c->h_status->judge_rmse <= c->judge_max) return DP_OK;
+  }
   eval_judge(c, n);
   launch_force_rmse(s, F, w.force_j, n, w.rmse_part, &w.status->judge_rmse);
   HIPCHK(c, hipGetLastError());
-  int rc = read_status(c);
-  if (rc) return rc;
+  int rc3 = read_status(c);
+  if (rc3) return rc3;
   const double r = c->h_status->judge_rmse;
   c->stats.last_judge_rmse = r;
+  c->stats.judge_atoms = n;
   if (!(r <= c->judge_max)) {  // a NaN rejects as well
     HIPCHK(c, hipMemcpyAsync(F, w.force_j, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
     HIPCHK(c, hipMemcpyAsync(w.energy, w.energy_j, sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1346,7 +1394,7 @@ int dp_md_run(dp_ctx *c, int64_t n, double *coords, double *vel, const int32_t *
   eval_body(c, n, L, F);
   const bool judging = c->active == 1 && c->judge_every > 0;
   if (judging) {
-    rc = judge_step(c, n, F);
+    rc = judge_step(c, n, F, 0, L);
     if (rc) return rc;
   }
   if (thermo) {
@@ -1364,7 +1412,7 @@ int dp_md_run(dp_ctx *c, int64_t n, double *coords, double *vel, const int32_t *
     launch_end_rebuild(s, &w.status->flags, &w.status->nbuild);
     eval_body(c, n, L, F);
     if (judging && c->active == 1 && st % c->judge_every == 0) {
-      rc = judge_step(c, n, F);
+      rc = judge_step(c, n, F, st, L);
       if (rc) return rc;
     }
     launch_verlet_half(s, n, vel, F, types, inv_m, 0.5 * dt);
@@ -1606,6 +1654,13 @@ int dp_student_judge(dp_ctx *c, int64_t every, double max_force_rmse) {
   if (every < 0 || !(max_force_rmse >= 0)) return fail(c, DP_E_ARG, "bad judge settings");
   c->judge_every = every;
   c->judge_max = max_force_rmse;
+  return DP_OK;
+}
+
+int dp_student_judge_sample(dp_ctx *c, double side) {
+  if (!c) return DP_E_ARG;
+  if (!(side >= 0.0) || !std::isfinite(side)) return fail(c, DP_E_ARG, "judge cube side must be >= 0");
+  c->judge_side = side;
   return DP_OK;
 }
 

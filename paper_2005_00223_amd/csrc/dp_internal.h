@@ -72,9 +72,10 @@ struct CellGrid {
 // ---- neighbour list (k_nlist.hip) ----
 void launch_wrap(hipStream_t s, int64_t n, const double *coords, const int32_t *types, int ntypes,
                  const double *L, double4 *xw, uint32_t *flags);
+// mask (may be NULL): rows only for atoms with mask[i] != 0; pos_of_atom may be NULL
 void launch_type_sort(hipStream_t s, int64_t n, const double4 *xw, int ntypes, int32_t *blk_counts,
                       int32_t *type_count, int32_t *type_start, int32_t *pos_of_atom, int32_t *atom_of_pos,
-                      int64_t rows_cap);
+                      int64_t rows_cap, const int32_t *mask = nullptr);
 // `cond` (may be NULL): when given, the kernels do nothing unless
 // (*cond & FLAG_REBUILD) -- the MD driver decides on the device.
 void launch_cells(hipStream_t s, int64_t n, const double4 *xw, const CellGrid &g, int32_t *cell_of,

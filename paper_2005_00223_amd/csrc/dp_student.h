@@ -125,6 +125,15 @@ void launch_st_check(hipStream_t st, const StCheckArgs &a);
 // force RMSE between two force arrays: part[grid] partial sums, out[0] = sqrt(mean |dF|^2)
 void launch_force_rmse(hipStream_t st, const double *fa, const double *fb, int64_t n, double *part, double *out);
 
+// sampled judge: mark[i] = 2 inside the cube of half side h around c
+// (minimum image, per axis), 1 inside the cube of half side hr, else 0
+void launch_judge_mark(hipStream_t st, int64_t n, const double4 *xw, const double *c, const double *L, double h,
+                       double hr, int32_t *mark);
+// force RMSE over the atoms with mark == 2; part needs 2 * 256 doubles
+void launch_force_rmse_masked(hipStream_t st, const double *fa, const double *fb, int64_t n, const int32_t *mark,
+                              double *part, double *out, double *count);
+void launch_copy_i32(hipStream_t st, const int32_t *src, int32_t *dst);
+
 // 16-bit rounding (round to nearest even) of a float, back as double
 __host__ __device__ inline double st_round16(float x, int quant) {
   if (quant == 0) return (double)(float)(_Float16)x;

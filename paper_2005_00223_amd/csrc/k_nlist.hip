@@ -58,12 +58,14 @@ void launch_wrap(hipStream_t s, int64_t n, const double *coords, const int32_t *
 // ---------------------------------------------------------------------------
 constexpr int TS_BLOCK = 256;
 
-__global__ void k_type_count(int64_t n, const double4 *__restrict__ xw, int ntypes, int32_t *blk_counts) {
+// mask (may be NULL): only atoms with mask[i] != 0 get rows
+__global__ void k_type_count(int64_t n, const double4 *__restrict__ xw, int ntypes, int32_t *blk_counts,
+                             const int32_t *mask) {
   __shared__ int32_t c[MAXT];
   if (threadIdx.x < MAXT) c[threadIdx.x] = 0;
   __syncthreads();
   int64_t i = (int64_t)blockIdx.x * TS_BLOCK + threadIdx.x;
-  if (i < n) atomicAdd(&c[(int)xw[i].w], 1);
+  if (i < n && (!mask || mask[i])) atomicAdd(&c[(int)xw[i].w], 1);
   __syncthreads();
   if (threadIdx.x < ntypes) blk_counts[(int64_t)blockIdx.x * MAXT + threadIdx.x] = c[threadIdx.x];
 }
@@ -99,11 +101,12 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
 }
 
 __global__ void k_type_place(int64_t n, const double4 *__restrict__ xw, int ntypes, const int32_t *blk_off,
-                             const int32_t *type_start, int32_t *pos_of_atom, int32_t *atom_of_pos) {
+                             const int32_t *type_start, int32_t *pos_of_atom, int32_t *atom_of_pos,
+                             const int32_t *mask) {
   __shared__ int32_t wtot[TS_BLOCK / 64][MAXT];
   int64_t i = (int64_t)blockIdx.x * TS_BLOCK + threadIdx.x;
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  int t = (i < n) ? (int)xw[i].w : -1;
+  int t = (i < n && (!mask || mask[i])) ? (int)xw[i].w : -1;
   int myrank = 0;
   for (int u = 0; u < ntypes; ++u) {
     unsigned long long m = __ballot(t == u);
@@ -114,14 +117,14 @@ __global__ void k_type_place(int64_t n, const double4 *__restrict__ xw, int ntyp
   if (t >= 0) {
     for (int w = 0; w < wv; ++w) myrank += wtot[w][t];
     int32_t pos = type_start[t] + blk_off[(int64_t)blockIdx.x * MAXT + t] + myrank;
-    pos_of_atom[i] = pos;
+    if (pos_of_atom) pos_of_atom[i] = pos;
     atom_of_pos[pos] = (int32_t)i;
   }
 }
 
 void launch_type_sort(hipStream_t s, int64_t n, const double4 *xw, int ntypes, int32_t *blk_counts,
                       int32_t *type_count, int32_t *type_start, int32_t *pos_of_atom, int32_t *atom_of_pos,
-                      int64_t rows_cap) {
+                      int64_t rows_cap, const int32_t *mask) {
   int nblk = (int)((n + TS_BLOCK - 1) / TS_BLOCK);
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((rows_cap + 255) / 256)), dim3(256), 0, s, atom_of_pos, rows_cap,
                      -1);
@@ -129,10 +132,10 @@ void launch_type_sort(hipStream_t s, int64_t n, const double4 *xw, int ntypes, i
     hipLaunchKernelGGL(k_type_scan, dim3(1), dim3(64), 0, s, 0, ntypes, blk_counts, type_count, type_start);
     return;
   }
-  hipLaunchKernelGGL(k_type_count, dim3(nblk), dim3(TS_BLOCK), 0, s, n, xw, ntypes, blk_counts);
+  hipLaunchKernelGGL(k_type_count, dim3(nblk), dim3(TS_BLOCK), 0, s, n, xw, ntypes, blk_counts, mask);
   hipLaunchKernelGGL(k_type_scan, dim3(1), dim3(64), 0, s, nblk, ntypes, blk_counts, type_count, type_start);
   hipLaunchKernelGGL(k_type_place, dim3(nblk), dim3(TS_BLOCK), 0, s, n, xw, ntypes, blk_counts, type_start,
-                     pos_of_atom, atom_of_pos);
+                     pos_of_atom, atom_of_pos, mask);
 }
 
 // ---------------------------------------------------------------------------

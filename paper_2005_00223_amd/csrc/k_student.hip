@@ -516,4 +516,84 @@ void launch_force_rmse(hipStream_t st, const double *fa, const double *fb, int64
   hipLaunchKernelGGL(k_frmse2, dim3(1), dim3(64), 0, st, part, FR_BLOCKS, n, out);
 }
 
+// ---------------------------------------------------------------------------
+// sampled judge: atoms of a cube, and the cube grown by rc (whose energies
+// the cube's forces depend on)
+// ---------------------------------------------------------------------------
+__device__ inline double judge_min_image(double v, double L) {
+  if (v > 0.5 * L) v -= L;
+  else if (v < -0.5 * L) v += L;
+  return v;
+}
+
+__global__ void k_judge_mark(int64_t n, const double4 *__restrict__ xw, double c0, double c1, double c2, double L0,
+                             double L1, double L2, double h, double hr, int32_t *mark) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double4 p = xw[i];
+  const double dx = fabs(judge_min_image(p.x - c0, L0)), dy = fabs(judge_min_image(p.y - c1, L1)),
+               dz = fabs(judge_min_image(p.z - c2, L2));
+  const double m = fmax(dx, fmax(dy, dz));
+  mark[i] = m <= h ? 2 : (m <= hr ? 1 : 0);
+}
+
+void launch_judge_mark(hipStream_t st, int64_t n, const double4 *xw, const double *c, const double *L, double h,
+                       double hr, int32_t *mark) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_judge_mark, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, xw, c[0], c[1], c[2],
+                       L[0], L[1], L[2], h, hr, mark);
+}
+
+// force RMSE over the atoms with mark == 2: part[2 b] = sum |dF|^2, part[2 b + 1] = count
+__global__ void k_frmse1m(const double *fa, const double *fb, int64_t n, const int32_t *mark, double *part) {
+  __shared__ double red[2][256];
+  double v = 0.0, c = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (mark[i] != 2) continue;
+    const double dx = fa[3 * i] - fb[3 * i], dy = fa[3 * i + 1] - fb[3 * i + 1], dz = fa[3 * i + 2] - fb[3 * i + 2];
+    v += dx * dx + dy * dy + dz * dz;
+    c += 1.0;
+  }
+  red[0][threadIdx.x] = v;
+  red[1][threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + o];
+      red[1][threadIdx.x] += red[1][threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = red[0][0];
+    part[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
+__global__ void k_frmse2m(const double *part, int np, double *out, double *count) {
+  if (threadIdx.x == 0) {
+    double v = 0.0, c = 0.0;
+    for (int b = 0; b < np; ++b) {
+      v += part[2 * b];
+      c += part[2 * b + 1];
+    }
+    out[0] = c > 0 ? sqrt(v / c) : 0.0;
+    count[0] = c;
+  }
+}
+
+void launch_force_rmse_masked(hipStream_t st, const double *fa, const double *fb, int64_t n, const int32_t *mark,
+                              double *part, double *out, double *count) {
+  hipLaunchKernelGGL(k_frmse1m, dim3(FR_BLOCKS), dim3(256), 0, st, fa, fb, n, mark, part);
+  hipLaunchKernelGGL(k_frmse2m, dim3(1), dim3(64), 0, st, part, FR_BLOCKS, out, count);
+}
+
+__global__ void k_copy_i32(const int32_t *src, int32_t *dst) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+
+void launch_copy_i32(hipStream_t st, const int32_t *src, int32_t *dst) {
+  hipLaunchKernelGGL(k_copy_i32, dim3(1), dim3(64), 0, st, src, dst);
+}
+
 }  // namespace dpk

@@ -138,8 +138,11 @@ class DPModel:
     def student_use(self, on=True):
         L.dp_student_use(self.ctx, on)
 
-    def student_judge(self, every=20, max_force_rmse=1e-3):
+    def student_judge(self, every=20, max_force_rmse=1e-3, sample_side=0.0):
+        """Judge period and threshold; sample_side > 0 (A) judges the atoms
+        of a cube of that side (teacher on the cube and its rc margin)."""
         L.dp_student_judge(self.ctx, every, max_force_rmse)
+        L.dp_student_judge_sample(self.ctx, sample_side)
 
     def student_model(self) -> bytes:
         return L.dp_student_get_model(self.ctx)

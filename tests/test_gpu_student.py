@@ -312,3 +312,60 @@ def test_judge_rejects_a_broken_student():
     assert st1["student_evals"] == 1
     assert st1["last_judge_rmse"] > 1e-3
     np.testing.assert_allclose(th1, th0, rtol=1e-9, atol=1e-9)
+
+
+def test_sampled_judge_matches_full_forces_on_its_cube():
+    """The sampled judge evaluates the teacher only on a cube (side 30 A) of
+    the 32,000-atom copper system and its rc margin; its RMSE must equal the
+    RMSE between full student and full teacher forces over the cube's atoms
+    (cube centre from the documented SplitMix64 formula, step 0)."""
+    from oracle import student as S
+    w, spec, blob, m, r = _frame("cu32000", "fp16")
+    m.student_train(adam_steps=50, ls_samples=65536)
+    m.student_use(True)
+    _, fs, _ = m.compute(w["coords"], w["types"], w["box"])
+    m.student_use(False)
+    _, ft, _ = m.compute(w["coords"], w["types"], w["box"])
+    m.student_use(True)
+    side = 30.0
+    m.student_judge(20, 1e-3, sample_side=side)
+    t = w["types"]
+    x = torch.tensor(w["coords"], dtype=torch.float64, device="cuda")
+    v = torch.zeros_like(x)
+    say("[student] sampled judge cu32000")
+    m.md_run(x, v, t, w["box"], w["masses"], 1.0, 0, skin=1.0, thermo_every=1)
+    st = m.stats()
+    b = np.asarray(w["box"], dtype=np.float64).ravel()
+    L = b if b.size == 3 else b[[0, 4, 8]]
+    u = (S.splitmix64(0x6a75646765, np.arange(3)) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    c = L * u
+    d = w["coords"] - c
+    d = np.where(d > 0.5 * L, d - L, np.where(d < -0.5 * L, d + L, d))
+    inner = np.abs(d).max(axis=1) <= 0.5 * side
+    diff = (fs - ft).cpu().numpy()[inner]
+    expect = np.sqrt((diff ** 2).sum(1).mean())
+    say(f"  judge RMSE {st['last_judge_rmse']:.6e} over {st['judge_atoms']} atoms; expected {expect:.6e} over "
+        f"{inner.sum()}")
+    assert st["judge_atoms"] == inner.sum() > 1000
+    assert abs(st["last_judge_rmse"] - expect) <= 1e-6 * expect
+    assert st["teacher_fallbacks"] == 0
+
+
+def test_sampled_judge_rejects_a_broken_student():
+    w = synth.workload("cu32000")
+    spec = w["spec"]
+    blob = synth.pack_blob(spec)
+    m = _model(blob, "fp16")
+    P = synth.random_student_params(spec, 31)
+    P[:, -33 * spec.M1:] = 0.0
+    m.student_set_model(synth.pack_blob(synth.student_spec(spec, P)))
+    m.student_use(True)
+    m.student_judge(20, 1e-3, sample_side=30.0)
+    x = torch.tensor(w["coords"], dtype=torch.float64, device="cuda")
+    v = torch.zeros_like(x)
+    say("[student] sampled judge rejects")
+    m.md_run(x, v, w["types"], w["box"], w["masses"], 1.0, 0, skin=1.0, thermo_every=1)
+    st = m.stats()
+    assert st["teacher_fallbacks"] == 1
+    assert st["judge_atoms"] == len(w["types"])  # the rejection is confirmed on all atoms
+    assert st["last_judge_rmse"] > 1e-3
