@@ -23,8 +23,8 @@
 // exactly the registers of output tiles 2kk and 2kk+1.  The host stores the
 // weight A operands in this permuted order, lane by lane, so activations go
 // from one layer to the next without leaving registers.  Skip partners that
-// live in another lane (the doubling skip) are read back from a per-wave LDS
-// copy of the previous layer.
+// live in another lane (a doubling skip whose input width is not a multiple
+// of 16) are read back from a per-wave LDS copy of the previous layer.
 //
 // The weights of every (centre type, neighbour type) net are copied into LDS
 // once per block.  Per net: w1[32], b1[32] (f32, by slot), A2 [MT2][KS2][64
@@ -135,6 +135,10 @@ struct Shape {
   static constexpr int SK1 = (W1 <= 2) ? 1 : 0;    // first layer adds s (out = in or 2 in of a scalar)
   static constexpr int SK2 = skip_kind(W1, W2);
   static constexpr int SK3 = skip_kind(W2, W3);
+  // a doubling skip reads another lane's value (through LDS) unless the input
+  // width is a multiple of the 16-slot tile
+  static constexpr bool XL2 = SK2 == 2 && W1 % 16 != 0;
+  static constexpr bool XL3 = SK3 == 2 && W2 % 16 != 0;
   // per-net byte offsets in the LDS copy
   static constexpr int O_W1 = 0, O_B1 = 128, O_A2 = 256;
   static constexpr int O_B2 = O_A2 + MT2 * 1 * 1024;
@@ -334,6 +338,13 @@ __device__ inline float skip_val(int f, int mt, int r, const float (&prev)[MTI][
   if (SK == 1) return (mt < MTI) ? prev[mt < MTI ? mt : 0][r] : 0.f;
   // doubling
   float own = (mt < MTI) ? prev[mt < MTI ? mt : 0][r] : 0.f;
+  if constexpr (IN % 16 == 0) {
+    // partner slot f - IN = 16 (mt - IN/16) + 4 g + r is held by this lane
+    constexpr int DM = IN / 16;
+    const int ms = mt - DM;
+    const float part = (ms >= 0 && ms < MTI) ? prev[(ms >= 0 && ms < MTI) ? ms : 0][r] : 0.f;
+    return f < IN ? own : part;
+  }
   const int src = f >= IN ? f - IN : 0;
   const float other = prev_lds[n * stride + src];
   return f < IN ? own : other;
@@ -377,7 +388,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 1>::B)) k_embed_fw
         if (g == 0) *(float4 *)(Rs + 4 * n) = make_float4((float)r4.x, (float)r4.y, (float)r4.z, (float)r4.w);
         float h1[2][4], hd_unused[2][4];
         layer1<W1, false>(w1, b1, s, g, h1, hd_unused);
-        if (S::SK2 == 2)
+        if (S::XL2)
 #pragma unroll
           for (int mt = 0; mt < 2; ++mt)
             *(float4 *)(h1s + n * S::S1 + 16 * mt + 4 * g) = make_float4(h1[mt][0], h1[mt][1], h1[mt][2], h1[mt][3]);
@@ -397,7 +408,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 1>::B)) k_embed_fw
             if (16 * mt < W2 && f < W2) v = tanh_f(acc2[mt][r]) + skip_val<W1, W2, S::SK2, 2>(f, mt, r, h1, h1s, n, S::S1);
             h2[mt][r] = v;
           }
-        if (S::SK3 == 2)
+        if (S::XL3)
 #pragma unroll
           for (int mt = 0; mt < S::MT2; ++mt)
             *(float4 *)(h2s + n * S::S2 + 16 * mt + 4 * g) = make_float4(h2[mt][0], h2[mt][1], h2[mt][2], h2[mt][3]);
@@ -595,7 +606,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 2>::B)) k_embed_bw
         if (g == 0) *(float4 *)(Rs + 4 * n) = make_float4((float)r4.x, (float)r4.y, (float)r4.z, (float)r4.w);
         float h1[2][4], hd1[2][4];
         layer1<W1, true>(w1, b1, s, g, h1, hd1);
-        if (S::SK2 == 2)
+        if (S::XL2)
 #pragma unroll
           for (int mt = 0; mt < 2; ++mt) {
             *(float4 *)(h1s + n * S::S1 + 16 * mt + 4 * g) = make_float4(h1[mt][0], h1[mt][1], h1[mt][2], h1[mt][3]);
@@ -622,7 +633,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 2>::B)) k_embed_bw
             h2[mt][r] = hv;
             hd2[mt][r] = dv;
           }
-        if (S::SK3 == 2)
+        if (S::XL3)
 #pragma unroll
           for (int mt = 0; mt < S::MT2; ++mt) {
             *(float4 *)(h2s + n * S::S2 + 16 * mt + 4 * g) = make_float4(h2[mt][0], h2[mt][1], h2[mt][2], h2[mt][3]);
@@ -775,7 +786,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_fwd_lin(MixArgs a) 
         sr3 += (float)r4.w;
         float h1[2][4], hd_unused[2][4];
         layer1<W1, false>(w1, b1, s, g, h1, hd_unused);
-        if (S::SK2 == 2)
+        if (S::XL2)
 #pragma unroll
           for (int mt = 0; mt < 2; ++mt)
             *(float4 *)(h1s + n * S::S1 + 16 * mt + 4 * g) = make_float4(h1[mt][0], h1[mt][1], h1[mt][2], h1[mt][3]);
@@ -924,7 +935,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_bwd_lin(MixArgs a) 
         const float s = (float)r4.x;
         float h1[2][4], hd1[2][4];
         layer1<W1, true>(w1, b1, s, g, h1, hd1);
-        if (S::SK2 == 2)
+        if (S::XL2)
 #pragma unroll
           for (int mt = 0; mt < 2; ++mt) {
             *(float4 *)(h1s + n * S::S1 + 16 * mt + 4 * g) = make_float4(h1[mt][0], h1[mt][1], h1[mt][2], h1[mt][3]);
