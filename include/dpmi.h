@@ -75,6 +75,7 @@ typedef struct {
   int64_t teacher_fallbacks; /* judge rejections of the student net          */
   double last_judge_rmse;    /* force RMSE student vs teacher, eV/A          */
   int64_t judge_atoms;       /* atoms the last judge covered                 */
+  int64_t cell_scatter;      /* backward passes with the cell-ordered scatter */
 } dp_stats;
 
 /* Create a context on HIP device `device`; `hip_stream` is a hipStream_t
@@ -140,6 +141,18 @@ int dp_keep_intermediates(dp_ctx *c, int keep);
 int dp_get_intermediates(dp_ctx *c, double *atom_e, double *T, double *D, double *net_deriv);
 
 int dp_get_stats(dp_ctx *c, dp_stats *out);
+
+/* Neighbour-force scatter of the mixed-precision backward with a student
+ * (affine-last-layer) net set; the sums are FP64 either way, only their
+ * order differs.
+ *   mode 0 (default): cell-ordered -- when the list grid has 3 to 255 cells
+ *     per axis, one workgroup per cell accumulates the pair forces on the
+ *     27 surrounding cells' atoms in LDS and a gather pass adds the 27
+ *     parts of each atom (no global atomics; atoms beyond 128 per cell fall
+ *     back to atomics); otherwise as mode 1;
+ *   mode 1: every pair force is added to F with FP64 global atomics.
+ * Returns DP_E_ARG for another mode. */
+int dp_set_force_scatter(dp_ctx *c, int mode);
 
 /* Velocity-Verlet NVE run (Section VI: the MD loop; 0.5 fs water, 1 fs Cu).
  *   coords, vel [natoms][3] device double (A, A/fs), updated in place;

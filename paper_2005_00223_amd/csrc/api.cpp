@@ -137,6 +137,9 @@ struct Workspace {
   // sampled-judge region marks and its type-padded row set
   double *force_j, *energy_j, *virial_j, *rmse_part;
   int32_t *judge_mark, *sub_atom_of_pos, *sub_type_count, *sub_type_start, *sub_blk;
+  // cell-ordered force scatter: per-atom cell codes, per-cell force parts [27][n][3]
+  uint32_t *cell_code;
+  double *cell_part;
   // mixed-precision buffers
   float *T32, *dT32, *tbuf;
   int prec = -1;  // precision the buffers were laid out for
@@ -183,6 +186,9 @@ struct dp_ctx {
   int n16 = 0;
   EmbNets en[2];                    // [0] teacher, [1] student
   int active = 0;                   // embedding set used by evaluations
+  CellGrid cgrid{};                 // grid of the last cell-list build
+  bool cgrid_ok = false;
+  int scatter = 0;                  // dp_set_force_scatter mode
   HostModel shm;                    // student (embedding part; fitting = teacher's)
   Student *st = nullptr;            // student training state
   int64_t judge_every = 20;         // MD judge period (0 = off)
@@ -254,6 +260,8 @@ int ensure_ws(dp_ctx *c, int64_t n, int64_t ncell, int cand_cap) {
   add((void **)&w.xref, sizeof(double4) * nn);
   add((void **)&w.cell_of, 4 * nn);
   add((void **)&w.cell_atoms, 4 * nn);
+  add((void **)&w.cell_code, 4 * nn);
+  if (mixed) add((void **)&w.cell_part, sizeof(double) * 81 * nn);
   add((void **)&w.cell_start, 4 * (nc + 1));
   add((void **)&w.cell_fill, 4 * nc);
   add((void **)&w.scan_tmp, 4 * nc);
@@ -312,6 +320,8 @@ int ensure_ws(dp_ctx *c, int64_t n, int64_t ncell, int cand_cap) {
     o += (pr.second + 255) / 256 * 256;
   }
   if (!nd) w.net_deriv = nullptr;
+  if (!mixed) w.cell_part = nullptr;
+  c->cgrid_ok = false;
   w.G[0] = w.dD;
   w.prec = c->precision;
   w.base = base;
@@ -692,6 +702,28 @@ void eval_forward(dp_ctx *c, int64_t n, const double L[3]) {
   eval_nets_fwd(c, n, c->ws.energy);
 }
 
+// Whether the mixed backward of this evaluation can scatter the pair forces
+// cell by cell (full evaluation, cell list of these lists with 3..255 cells
+// per axis, an affine-last-layer net set whose kernel fits the LDS); fills
+// the kernel arguments.
+bool cell_scatter_args(dp_ctx *c, int64_t n, const MixArgs &ma, CellArgs &ca, int &threads, size_t &lds) {
+  Workspace &w = c->ws;
+  if (c->scatter != 0 || c->ov_atom_of_pos || !c->cgrid_ok || !w.cell_part || n <= 0) return false;
+  for (int a = 0; a < 3; ++a)
+    if (c->cgrid.nc[a] < 3 || c->cgrid.nc[a] > 255) return false;
+  if (!embed_cells_config(ma, CELL_CAP, &threads, &lds)) return false;
+  ca.cell_start = w.cell_start;
+  ca.cell_atoms = w.cell_atoms;
+  ca.cell_of = w.cell_of;
+  ca.code = w.cell_code;
+  for (int a = 0; a < 3; ++a) ca.nc[a] = c->cgrid.nc[a];
+  ca.cap = CELL_CAP;
+  ca.ncell = (int64_t)ca.nc[0] * ca.nc[1] * ca.nc[2];
+  ca.n = n;
+  ca.part = w.cell_part;
+  return true;
+}
+
 // Backward half (the adjoint): fitting net backward to dE/dD, then the
 // embedding backward with the force scatter into F and the virial into V.
 void eval_backward(dp_ctx *c, int64_t n, double *F, double *V) {
@@ -711,11 +743,24 @@ void eval_backward(dp_ctx *c, int64_t n, double *F, double *V) {
     launch_fit_mix(s, fitmix_args(c, rows), 2);
     tmark(c, 5);
     launch_zero(s, F, 3 * n);
-    const int grid = mix_grid(rows);
     tmark(c, 6);
-    launch_embed_mix(s, mix_args(c, rows, F), 2, grid);
-    tmark(c, 7);
-    launch_sum9(s, w.vir_part, grid, V);
+    const MixArgs ma = mix_args(c, rows, F);
+    CellArgs ca{};
+    int threads = 0;
+    size_t lds = 0;
+    if (cell_scatter_args(c, n, ma, ca, threads, lds)) {
+      const int grid = cells_grid(ca.ncell);
+      launch_embed_cells(s, ma, ca, grid, threads, lds);
+      launch_cell_gather(s, ca, F);
+      tmark(c, 7);
+      launch_sum9(s, w.vir_part, grid, V);
+      c->stats.cell_scatter += 1;
+    } else {
+      const int grid = mix_grid(rows);
+      launch_embed_mix(s, ma, 2, grid);
+      tmark(c, 7);
+      launch_sum9(s, w.vir_part, grid, V);
+    }
   }
   tnext(c);
 }
@@ -741,7 +786,10 @@ void eval_judge(dp_ctx *c, int64_t n) {
 
 void build_lists(dp_ctx *c, int64_t n, const CellGrid &g, double rlist, const uint32_t *cond) {
   Workspace &w = c->ws;
-  launch_cells(c->stream, n, w.xw, g, w.cell_of, w.cell_start, w.cell_fill, w.cell_atoms, w.scan_tmp, cond);
+  launch_cells(c->stream, n, w.xw, g, w.cell_of, w.cell_start, w.cell_fill, w.cell_atoms, w.cell_code, w.scan_tmp,
+               cond);
+  c->cgrid = g;
+  c->cgrid_ok = true;
   launch_candidates(c->stream, n, w.xw, g, w.cell_start, w.cell_atoms, rlist, w.cand_cap, w.cand, w.cand_n,
                     &w.status->flags, cond);
 }
@@ -1348,6 +1396,13 @@ int dp_get_intermediates(dp_ctx *c, double *atom_e, double *T, double *D, double
 int dp_get_stats(dp_ctx *c, dp_stats *out) {
   if (!c || !out) return DP_E_ARG;
   *out = c->stats;
+  return DP_OK;
+}
+
+int dp_set_force_scatter(dp_ctx *c, int mode) {
+  if (!c) return DP_E_ARG;
+  if (mode != 0 && mode != 1) return fail(c, DP_E_ARG, "force scatter mode must be 0 or 1");
+  c->scatter = mode;
   return DP_OK;
 }
 

@@ -78,9 +78,10 @@ void launch_type_sort(hipStream_t s, int64_t n, const double4 *xw, int ntypes, i
                       int64_t rows_cap, const int32_t *mask = nullptr);
 // `cond` (may be NULL): when given, the kernels do nothing unless
 // (*cond & FLAG_REBUILD) -- the MD driver decides on the device.
+// cell_code (may be NULL): per-atom cell coordinates and index inside the cell
 void launch_cells(hipStream_t s, int64_t n, const double4 *xw, const CellGrid &g, int32_t *cell_of,
-                  int32_t *cell_start, int32_t *cell_fill, int32_t *cell_atoms, int32_t *scan_tmp,
-                  const uint32_t *cond);
+                  int32_t *cell_start, int32_t *cell_fill, int32_t *cell_atoms, uint32_t *cell_code,
+                  int32_t *scan_tmp, const uint32_t *cond);
 void launch_candidates(hipStream_t s, int64_t n, const double4 *xw, const CellGrid &g, const int32_t *cell_start,
                        const int32_t *cell_atoms, double rlist, int cand_cap, int32_t *cand, int32_t *cand_n,
                        uint32_t *flags, const uint32_t *cond);

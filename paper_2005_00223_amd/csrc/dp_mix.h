@@ -91,6 +91,26 @@ struct FitMixArgs {
   float inv_nc;
 };
 
+// cell-ordered backward of the affine-last-layer nets (k_embed_bwd_cells)
+constexpr int CELL_WAVES = 12;   // waves per workgroup at most
+constexpr int CELL_CAP = 128;    // atoms per cell kept in LDS; the rest use global atomics
+struct CellArgs {
+  const int32_t *cell_start;     // [ncell + 1]
+  const int32_t *cell_atoms;     // [n] atoms in cell order
+  const int32_t *cell_of;        // [n]
+  const uint32_t *code;          // [n] cx << 24 | cy << 16 | cz << 8 | min(index in cell, 255)
+  int nc[3];
+  int cap;
+  int64_t ncell, n;
+  double *part;                  // [27][n][3] per-cell parts of the forces, cell order
+};
+// workgroup size and LDS bytes of the cell kernel, or false when the net
+// shape or the LDS budget does not allow it
+bool embed_cells_config(const MixArgs &a, int cap, int *threads, size_t *lds);
+int cells_grid(int64_t ncell);
+void launch_embed_cells(hipStream_t s, const MixArgs &a, const CellArgs &ca, int grid, int threads, size_t lds);
+void launch_cell_gather(hipStream_t s, const CellArgs &ca, double *F);
+
 bool fit_mix_supported(const Dims &d, const char **why);
 void fit_mix_pack(const Dims &d, int prec, int nsplit, const double *const *W, const double *const *b,
                   std::vector<unsigned char> &buf, FitMixOffsets &fo);

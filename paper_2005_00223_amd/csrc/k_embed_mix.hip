@@ -382,8 +382,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 1>::B)) k_embed_fw
       const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
       const int64_t base = (int64_t)i * d.nnei + d.off[u];
       for (int n0 = 0; n0 < cnt; n0 += 16) {
-        const bool valid = n0 + n < cnt;
-        const double4 r4 = valid ? a.rt[base + n0 + n] : make_double4(0.0, 0.0, 0.0, 0.0);
+        const double4 r4 = n0 + n < cnt ? a.rt[base + n0 + n] : make_double4(0.0, 0.0, 0.0, 0.0);
         const float s = (float)r4.x;
         if (g == 0) *(float4 *)(Rs + 4 * n) = make_float4((float)r4.x, (float)r4.y, (float)r4.z, (float)r4.w);
         float h1[2][4], hd_unused[2][4];
@@ -481,15 +480,12 @@ __device__ inline void switch64(double r, double rcs, double rc, double inv_w, d
 // FP64 force pass for one real slot: g = dE/dR of the slot (FP32 from the
 // networks), chain rule through R(r_ij) in FP64, F_i accumulated by the
 // caller, F_j -= g_ij by an atomic, virial -= g_ij (x) r_ij.
-__device__ inline void force_pair(const MixArgs &a, int64_t slot, float4 gr, double rc, double rcs, double inv_w,
-                                  double &fi0, double &fi1, double &fi2, double (&vir)[9]) {
+// FP64 force of one pair from dE/dR (gr) and the neighbour's displacement
+// D4 = (dx, dy, dz, r): g = dE/dr_ij (F_i += g, F_j -= g), accumulated into
+// fi and the virial
+__device__ inline void pair_force(const double4 &D4, float4 gr, double rc, double rcs, double inv_w, double &gx,
+                                  double &gy, double &gz, double &fi0, double &fi1, double &fi2, double (&vir)[9]) {
   const double g0 = gr.x, g1 = gr.y, g2 = gr.z, g3 = gr.w;
-  const double4 D4 = a.dr[slot];
-  const int j = a.nlist[slot];
-  if (a.net_deriv) {
-    double *nd = a.net_deriv + slot * 4;
-    nd[0] = g0; nd[1] = g1; nd[2] = g2; nd[3] = g3;
-  }
   const double dx = D4.x, dy = D4.y, dz = D4.z, r = D4.w;
   double sw, dsw;
   switch64(r, rcs, rc, inv_w, sw, dsw);
@@ -500,16 +496,30 @@ __device__ inline void force_pair(const MixArgs &a, int64_t slot, float4 gr, dou
   const double dtt = dsw * ir * ir - 2.0 * sw * ir * ir * ir;
   const double gd = g1 * dx + g2 * dy + g3 * dz;
   const double cc = (g0 * ds + dtt * gd) * ir;
-  const double gx = cc * dx + tt * g1, gy = cc * dy + tt * g2, gz = cc * dz + tt * g3;
+  gx = cc * dx + tt * g1;
+  gy = cc * dy + tt * g2;
+  gz = cc * dz + tt * g3;
   fi0 += gx;
   fi1 += gy;
   fi2 += gz;
-  unsafeAtomicAdd(a.force + 3 * (int64_t)j + 0, -gx);
-  unsafeAtomicAdd(a.force + 3 * (int64_t)j + 1, -gy);
-  unsafeAtomicAdd(a.force + 3 * (int64_t)j + 2, -gz);
   vir[0] -= gx * dx; vir[1] -= gx * dy; vir[2] -= gx * dz;
   vir[3] -= gy * dx; vir[4] -= gy * dy; vir[5] -= gy * dz;
   vir[6] -= gz * dx; vir[7] -= gz * dy; vir[8] -= gz * dz;
+}
+
+// pair_force with the neighbour's share scattered by global atomics;
+// D4 = dr[slot] and j = nlist[slot]
+__device__ inline void force_pair(const MixArgs &a, int64_t slot, const double4 &D4, int j, float4 gr, double rc,
+                                  double rcs, double inv_w, double &fi0, double &fi1, double &fi2, double (&vir)[9]) {
+  if (a.net_deriv) {
+    double *nd = a.net_deriv + slot * 4;
+    nd[0] = gr.x; nd[1] = gr.y; nd[2] = gr.z; nd[3] = gr.w;
+  }
+  double gx, gy, gz;
+  pair_force(D4, gr, rc, rcs, inv_w, gx, gy, gz, fi0, fi1, fi2, vir);
+  unsafeAtomicAdd(a.force + 3 * (int64_t)j + 0, -gx);
+  unsafeAtomicAdd(a.force + 3 * (int64_t)j + 1, -gy);
+  unsafeAtomicAdd(a.force + 3 * (int64_t)j + 2, -gz);
 }
 
 // wave sum of the centre atom's force, one atomic per component
@@ -600,8 +610,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 2>::B)) k_embed_bw
       const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
       const int64_t base = (int64_t)i * d.nnei + d.off[u];
       for (int n0 = 0; n0 < cnt; n0 += 16) {
-        const bool valid = n0 + n < cnt;
-        const double4 r4 = valid ? a.rt[base + n0 + n] : make_double4(0.0, 0.0, 0.0, 0.0);
+        const double4 r4 = n0 + n < cnt ? a.rt[base + n0 + n] : make_double4(0.0, 0.0, 0.0, 0.0);
         const float s = (float)r4.x;
         if (g == 0) *(float4 *)(Rs + 4 * n) = make_float4((float)r4.x, (float)r4.y, (float)r4.z, (float)r4.w);
         float h1[2][4], hd1[2][4];
@@ -702,7 +711,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 2>::B)) k_embed_bw
           const int q = c0 + lane;
           if (q < cnt) {
             const float4 gr = *(const float4 *)(gRs + 4 * lane);
-            force_pair(a, base + q, gr, rc, rcs, inv_w, fi0, fi1, fi2, vir);
+            force_pair(a, base + q, a.dr[base + q], a.nlist[base + q], gr, rc, rcs, inv_w, fi0, fi1, fi2, vir);
           }
           wsync();
         }
@@ -775,9 +784,11 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_fwd_lin(MixArgs a) 
       const int64_t base = (int64_t)i * d.nnei + d.off[u];
       v4f Hacc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
       float sr0 = 0.f, sr1 = 0.f, sr2 = 0.f, sr3 = 0.f;  // this lane's neighbours: sum of R
+      double4 r4n = n < cnt ? a.rt[base + n] : make_double4(0.0, 0.0, 0.0, 0.0);
       for (int n0 = 0; n0 < cnt; n0 += 16) {
-        const bool valid = n0 + n < cnt;
-        const double4 r4 = valid ? a.rt[base + n0 + n] : make_double4(0.0, 0.0, 0.0, 0.0);
+        // this tile's environment rows; the next tile's are loaded meanwhile
+        const double4 r4 = r4n;
+        if (n0 + 16 < cnt) r4n = n0 + 16 + n < cnt ? a.rt[base + n0 + 16 + n] : make_double4(0.0, 0.0, 0.0, 0.0);
         const float s = (float)r4.x;
         if (g == 0) *(float4 *)(Rs + 4 * n) = make_float4((float)r4.x, (float)r4.y, (float)r4.z, (float)r4.w);
         sr0 += (float)r4.x;
@@ -851,40 +862,63 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_fwd_lin(MixArgs a) 
   }
 }
 
-template <int W1, int W2, int W3, int P>
-__global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_bwd_lin(MixArgs a) {
+// LDS force accumulation of the cell-ordered backward: the block owns one
+// cell of the list grid, facc[27][cap][3] holds the forces on the atoms of the
+// 27 cells around it (slot = offset (dx, dy, dz) in {-1, 0, 1}^3, then the
+// atom's index inside its cell)
+struct CellCtx {
+  double *facc;
+  const uint32_t *code;   // per atom: cx << 24 | cy << 16 | cz << 8 | min(index in cell, 255)
+  int cx, cy, cz, nc0, nc1, nc2, cap;
+};
+
+// LDS slot of an atom with cell code `code`, or -1 when it lies outside the
+// 27 cells or past the capacity (its force then goes to global memory)
+__device__ inline int cell_slot(const CellCtx &cc, uint32_t code) {
+  int dx = (int)(code >> 24) - cc.cx, dy = (int)((code >> 16) & 255u) - cc.cy, dz = (int)((code >> 8) & 255u) - cc.cz;
+  if (dx > 1) dx -= cc.nc0;
+  else if (dx < -1) dx += cc.nc0;
+  if (dy > 1) dy -= cc.nc1;
+  else if (dy < -1) dy += cc.nc1;
+  if (dz > 1) dz -= cc.nc2;
+  else if (dz < -1) dz += cc.nc2;
+  const int l = (int)(code & 255u);
+  if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1 || l >= cc.cap) return -1;
+  return ((dx + 1) * 9 + (dy + 1) * 3 + (dz + 1)) * cc.cap + l;
+}
+
+// backward of one atom i with an affine-last-layer net set: dE/dR per
+// neighbour, the FP64 pair forces, F_i and the virial.  CELL: neighbour and
+// own forces go to the block's LDS accumulator (li = index of i in its
+// cell), else straight to global memory with atomics.
+template <int W1, int W2, int W3, int P, bool CELL>
+__device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char *smem, float *h1s, float *hd1s,
+                                    float *dTs, float *gRs, int lane, double (&vir)[9], const CellCtx &cc, int li) {
   typedef Shape<W1, W2, W3> S;
   typedef LinShape<W1, W2, W3> LS;
   typedef typename HT<P>::v8 V;
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double vred[MIX_WAVES][9];
   const Dims &d = a.d;
-  const int nnets = d.ntypes * d.ntypes;
-  copy_nets(smem, a.nets, nnets * LS::NET_BYTES);
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int g = lane >> 4, n = lane & 15;
-  unsigned char *ws = smem + nnets * LS::NET_BYTES + wv * LS::P2_BYTES;
-  float *h1s = (float *)(ws + LS::P2_H1), *hd1s = h1s + 16 * S::S1;
-  float *dTs = (float *)(ws + LS::P2_DT);
-  float *gRs = (float *)(ws + LS::P2_GR);
   const double rc = d.rcut, rcs = d.rcut_smth, inv_w = 1.0 / (d.rcut - d.rcut_smth);
-  double vir[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) vir[k] = 0.0;
-  int64_t p0, p1;
-  wave_rows(a.rows, p0, p1);
-  for (int64_t p = p0; p < p1; ++p) {
-    const int i = a.atom_of_pos[p];
-    if (i < 0) continue;
-    const int t = (int)a.xw[i].w;
-    {
-      const float *dTi = a.dT32 + (int64_t)i * d.M1 * 4;
-      for (int o = lane; o < S::S3 * 4; o += 64) dTs[o] = (o >> 2) < d.M1 ? dTi[o] : 0.f;
-    }
-    wsync();
-    // B operands of M = W3 dT: K = outputs f = 32 kk + 8 g + v, N = components c = n
-    Split8<P> dB[LS::KF];
+  const int t = (int)a.xw[i].w;
+  {
+    const float *dTi = a.dT32 + (int64_t)i * d.M1 * 4;
+    for (int o = lane; o < S::S3 * 4; o += 64) dTs[o] = (o >> 2) < d.M1 ? dTi[o] : 0.f;
+  }
+  wsync();
+  double fi0 = 0.0, fi1 = 0.0, fi2 = 0.0;
+  for (int u = 0; u < d.ntypes; ++u) {
+    const unsigned char *net = smem + (t * d.ntypes + u) * LS::NET_BYTES;
+    const float *w1 = (const float *)(net + S::O_W1), *b1 = (const float *)(net + S::O_B1);
+    const float *b2 = (const float *)(net + S::O_B2), *b3 = (const float *)(net + S::O_B3);
+    const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
+    if (cnt == 0) continue;
+    const int64_t base = (int64_t)i * d.nnei + d.off[u];
+    // M = W3 dT (lane (g, n): M[16 mt + 4 g + r][c = n]) and q = b3^T dT; the
+    // B operands of W3 dT (K = outputs f = 32 kk + 8 g + v, N = components
+    // c = n) are rebuilt per net so that they hold no registers in the
+    // neighbour loop
+    v4f Macc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
     for (int kk = 0; kk < LS::KF; ++kk) {
       float x[4], y[4];
@@ -894,105 +928,260 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_bwd_lin(MixArgs a) 
         x[v] = (n < 4 && f0 < W3) ? dTs[4 * f0 + n] : 0.f;
         y[v] = (n < 4 && f1 < W3) ? dTs[4 * f1 + n] : 0.f;
       }
-      dB[kk] = split8<P>(x, y);
-    }
-    double fi0 = 0.0, fi1 = 0.0, fi2 = 0.0;
-    for (int u = 0; u < d.ntypes; ++u) {
-      const unsigned char *net = smem + (t * d.ntypes + u) * LS::NET_BYTES;
-      const float *w1 = (const float *)(net + S::O_W1), *b1 = (const float *)(net + S::O_B1);
-      const float *b2 = (const float *)(net + S::O_B2), *b3 = (const float *)(net + S::O_B3);
-      const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
-      if (cnt == 0) continue;
-      const int64_t base = (int64_t)i * d.nnei + d.off[u];
-      // M = W3 dT (lane (g, n): M[16 mt + 4 g + r][c = n]) and q = b3^T dT
-      v4f Macc[2];
+      const Split8<P> dB = split8<P>(x, y);
 #pragma unroll
       for (int mt = 0; mt < 2; ++mt) {
-        Macc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kk = 0; kk < LS::KF; ++kk) {
-          const V av = *(const V *)(net + LS::O_A3B + ((mt * LS::KF + kk) * 64 + lane) * 16);
-          Macc[mt] = mfma16<P>(av, dB[kk].hi, Macc[mt]);
-          Macc[mt] = mfma16<P>(av, dB[kk].lo, Macc[mt]);
-        }
-      }
-      float q = 0.f;
-      if (n < 4)
-        for (int f = g; f < W3; f += 4) q += b3[f] * dTs[4 * f + n];
-      q += __shfl_xor(q, 16);
-      q += __shfl_xor(q, 32);
-      const float q0 = __shfl(q, 0), q1 = __shfl(q, 1), q2 = __shfl(q, 2), q3 = __shfl(q, 3);
-      float mx[4], my[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        mx[r] = Macc[0][r];
-        my[r] = Macc[1][r];
-      }
-      const Split8<P> MA = split8<P>(mx, my);
-      for (int n0 = 0; n0 < cnt; n0 += 16) {
-        const bool valid = n0 + n < cnt;
-        const double4 r4 = valid ? a.rt[base + n0 + n] : make_double4(0.0, 0.0, 0.0, 0.0);
-        const float s = (float)r4.x;
-        float h1[2][4], hd1[2][4];
-        layer1<W1, true>(w1, b1, s, g, h1, hd1);
-        if (S::XL2)
-#pragma unroll
-          for (int mt = 0; mt < 2; ++mt) {
-            *(float4 *)(h1s + n * S::S1 + 16 * mt + 4 * g) = make_float4(h1[mt][0], h1[mt][1], h1[mt][2], h1[mt][3]);
-            *(float4 *)(hd1s + n * S::S1 + 16 * mt + 4 * g) =
-                make_float4(hd1[mt][0], hd1[mt][1], hd1[mt][2], hd1[mt][3]);
-          }
-        Split8<P> B2h[1] = {split8<P>(h1[0], h1[1])}, B2d[1] = {split8<P>(hd1[0], hd1[1])};
-        v4f acc2[S::MT2], acc2d[S::MT2];
-        layer_mfma<P, S::MT2, 1>(net + S::O_A2, b2, B2h, lane, g, acc2);
-        layer_mfma_tan<P, S::MT2, 1>(net + S::O_A2, B2d, lane, acc2d);
-        wsync();
-        float h2[S::MT2][4], hd2[S::MT2][4];
-#pragma unroll
-        for (int mt = 0; mt < S::MT2; ++mt)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int f = 16 * mt + 4 * g + r;
-            float hv = 0.f, dv = 0.f;
-            if (16 * mt < W2 && f < W2) {
-              const float th = tanh_f(acc2[mt][r]);
-              hv = th + skip_val<W1, W2, S::SK2, 2>(f, mt, r, h1, h1s, n, S::S1);
-              dv = (1.f - th * th) * acc2d[mt][r] + skip_val<W1, W2, S::SK2, 2>(f, mt, r, hd1, hd1s, n, S::S1);
-            }
-            h2[mt][r] = hv;
-            hd2[mt][r] = dv;
-          }
-        const Split8<P> B3h = split8<P>(h2[0], h2[1]), B3d = split8<P>(hd2[0], hd2[1]);
-        // a = M^T h2 and b = M^T h2' (lane (g, n): component c = 4 g + r of neighbour n)
-        v4f ca = v4f{0.f, 0.f, 0.f, 0.f}, cb = v4f{0.f, 0.f, 0.f, 0.f};
-        ca = mfma16<P>(MA.hi, B3h.hi, ca);
-        ca = mfma16<P>(MA.hi, B3h.lo, ca);
-        ca = mfma16<P>(MA.lo, B3h.hi, ca);
-        cb = mfma16<P>(MA.hi, B3d.hi, cb);
-        cb = mfma16<P>(MA.hi, B3d.lo, cb);
-        cb = mfma16<P>(MA.lo, B3d.hi, cb);
-        const int slot0 = n0 & 63;
-        if (g == 0) {
-          // dE/dR = a + q + (R . b) e_0
-          const float bd = (float)r4.x * cb[0] + (float)r4.y * cb[1] + (float)r4.z * cb[2] + (float)r4.w * cb[3];
-          *(float4 *)(gRs + 4 * (slot0 + n)) = make_float4(ca[0] + q0 + bd, ca[1] + q1, ca[2] + q2, ca[3] + q3);
-        }
-        wsync();
-        // every 64 neighbours (or at the end of the type block): FP64 force pass
-        if (((n0 + 16) & 63) == 0 || n0 + 16 >= cnt) {
-          const int c0 = n0 & ~63;
-          const int qq = c0 + lane;
-          if (qq < cnt) {
-            const float4 gr = *(const float4 *)(gRs + 4 * lane);
-            force_pair(a, base + qq, gr, rc, rcs, inv_w, fi0, fi1, fi2, vir);
-          }
-          wsync();
-        }
+        const V av = *(const V *)(net + LS::O_A3B + ((mt * LS::KF + kk) * 64 + lane) * 16);
+        Macc[mt] = mfma16<P>(av, dB.hi, Macc[mt]);
+        Macc[mt] = mfma16<P>(av, dB.lo, Macc[mt]);
       }
     }
-    finish_atom_force(a, i, lane, fi0, fi1, fi2);
+    float q = 0.f;
+    if (n < 4)
+      for (int f = g; f < W3; f += 4) q += b3[f] * dTs[4 * f + n];
+    q += __shfl_xor(q, 16);
+    q += __shfl_xor(q, 32);
+    const float q0 = __shfl(q, 0), q1 = __shfl(q, 1), q2 = __shfl(q, 2), q3 = __shfl(q, 3);
+    float mx[4], my[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      mx[r] = Macc[0][r];
+      my[r] = Macc[1][r];
+    }
+    const Split8<P> MA = split8<P>(mx, my);
+    double4 r4n = n < cnt ? a.rt[base + n] : make_double4(0.0, 0.0, 0.0, 0.0);
+    // force-pass operands of the current 64-neighbour chunk, loaded a chunk ahead
+    double4 drc = lane < cnt ? a.dr[base + lane] : make_double4(0.0, 0.0, 1.0, 1.0);
+    int jc = lane < cnt ? a.nlist[base + lane] : 0;
+    uint32_t codec = 0;
+    for (int n0 = 0; n0 < cnt; n0 += 16) {
+      // this tile's environment rows; the next tile's are loaded meanwhile
+      const double4 r4 = r4n;
+      if (n0 + 16 < cnt) r4n = n0 + 16 + n < cnt ? a.rt[base + n0 + 16 + n] : make_double4(0.0, 0.0, 0.0, 0.0);
+      const float s = (float)r4.x;
+      float h1[2][4], hd1[2][4];
+      layer1<W1, true>(w1, b1, s, g, h1, hd1);
+      if (S::XL2)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+          *(float4 *)(h1s + n * S::S1 + 16 * mt + 4 * g) = make_float4(h1[mt][0], h1[mt][1], h1[mt][2], h1[mt][3]);
+          *(float4 *)(hd1s + n * S::S1 + 16 * mt + 4 * g) =
+              make_float4(hd1[mt][0], hd1[mt][1], hd1[mt][2], hd1[mt][3]);
+        }
+      Split8<P> B2h[1] = {split8<P>(h1[0], h1[1])}, B2d[1] = {split8<P>(hd1[0], hd1[1])};
+      v4f acc2[S::MT2], acc2d[S::MT2];
+      layer_mfma<P, S::MT2, 1>(net + S::O_A2, b2, B2h, lane, g, acc2);
+      layer_mfma_tan<P, S::MT2, 1>(net + S::O_A2, B2d, lane, acc2d);
+      wsync();
+      float h2[S::MT2][4], hd2[S::MT2][4];
+#pragma unroll
+      for (int mt = 0; mt < S::MT2; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int f = 16 * mt + 4 * g + r;
+          float hv = 0.f, dv = 0.f;
+          if (16 * mt < W2 && f < W2) {
+            const float th = tanh_f(acc2[mt][r]);
+            hv = th + skip_val<W1, W2, S::SK2, 2>(f, mt, r, h1, h1s, n, S::S1);
+            dv = (1.f - th * th) * acc2d[mt][r] + skip_val<W1, W2, S::SK2, 2>(f, mt, r, hd1, hd1s, n, S::S1);
+          }
+          h2[mt][r] = hv;
+          hd2[mt][r] = dv;
+        }
+      const Split8<P> B3h = split8<P>(h2[0], h2[1]), B3d = split8<P>(hd2[0], hd2[1]);
+      // a = M^T h2 and b = M^T h2' (lane (g, n): component c = 4 g + r of neighbour n)
+      v4f ca = v4f{0.f, 0.f, 0.f, 0.f}, cb = v4f{0.f, 0.f, 0.f, 0.f};
+      ca = mfma16<P>(MA.hi, B3h.hi, ca);
+      ca = mfma16<P>(MA.hi, B3h.lo, ca);
+      ca = mfma16<P>(MA.lo, B3h.hi, ca);
+      cb = mfma16<P>(MA.hi, B3d.hi, cb);
+      cb = mfma16<P>(MA.hi, B3d.lo, cb);
+      cb = mfma16<P>(MA.lo, B3d.hi, cb);
+      const int slot0 = n0 & 63;
+      if (g == 0) {
+        // dE/dR = a + q + (R . b) e_0
+        const float bd = (float)r4.x * cb[0] + (float)r4.y * cb[1] + (float)r4.z * cb[2] + (float)r4.w * cb[3];
+        *(float4 *)(gRs + 4 * (slot0 + n)) = make_float4(ca[0] + q0 + bd, ca[1] + q1, ca[2] + q2, ca[3] + q3);
+      }
+      // cell code of this chunk's neighbours (jc arrived during the tile)
+      if (CELL && slot0 == 0) codec = cc.code[jc];
+      wsync();
+      // every 64 neighbours (or at the end of the type block): FP64 force pass
+      if (((n0 + 16) & 63) == 0 || n0 + 16 >= cnt) {
+        const int c0 = n0 & ~63;
+        const int qq = c0 + lane;
+        if (qq < cnt) {
+          const float4 gr = *(const float4 *)(gRs + 4 * lane);
+          double gx, gy, gz;
+          pair_force(drc, gr, rc, rcs, inv_w, gx, gy, gz, fi0, fi1, fi2, vir);
+          if (a.net_deriv) {
+            double *nd = a.net_deriv + (base + qq) * 4;
+            nd[0] = gr.x; nd[1] = gr.y; nd[2] = gr.z; nd[3] = gr.w;
+          }
+          const int slot = CELL ? cell_slot(cc, codec) : -1;
+          if (slot >= 0) {
+            atomicAdd(cc.facc + 3 * slot + 0, -gx);
+            atomicAdd(cc.facc + 3 * slot + 1, -gy);
+            atomicAdd(cc.facc + 3 * slot + 2, -gz);
+          } else {
+            unsafeAtomicAdd(a.force + 3 * (int64_t)jc + 0, -gx);
+            unsafeAtomicAdd(a.force + 3 * (int64_t)jc + 1, -gy);
+            unsafeAtomicAdd(a.force + 3 * (int64_t)jc + 2, -gz);
+          }
+        }
+        if (qq + 64 < cnt) {
+          drc = a.dr[base + qq + 64];
+          jc = a.nlist[base + qq + 64];
+        }
+        wsync();
+      }
+    }
+  }
+  // F_i: wave sum, one add per component
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    fi0 += __shfl_xor(fi0, o);
+    fi1 += __shfl_xor(fi1, o);
+    fi2 += __shfl_xor(fi2, o);
+  }
+  if (lane == 0) {
+    if (CELL && li < cc.cap) {
+      double *f = cc.facc + 3 * (13 * cc.cap + li);
+      atomicAdd(f + 0, fi0);
+      atomicAdd(f + 1, fi1);
+      atomicAdd(f + 2, fi2);
+    } else {
+      unsafeAtomicAdd(a.force + 3 * (int64_t)i + 0, fi0);
+      unsafeAtomicAdd(a.force + 3 * (int64_t)i + 1, fi1);
+      unsafeAtomicAdd(a.force + 3 * (int64_t)i + 2, fi2);
+    }
+  }
+}
+
+template <int W1, int W2, int W3, int P>
+__global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_bwd_lin(MixArgs a) {
+  typedef LinShape<W1, W2, W3> LS;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double vred[MIX_WAVES][9];
+  const int nnets = a.d.ntypes * a.d.ntypes;
+  copy_nets(smem, a.nets, nnets * LS::NET_BYTES);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  unsigned char *ws = smem + nnets * LS::NET_BYTES + wv * LS::P2_BYTES;
+  float *h1s = (float *)(ws + LS::P2_H1), *hd1s = h1s + 16 * Shape<W1, W2, W3>::S1;
+  float *dTs = (float *)(ws + LS::P2_DT);
+  float *gRs = (float *)(ws + LS::P2_GR);
+  double vir[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) vir[k] = 0.0;
+  const CellCtx cc{};
+  int64_t p0, p1;
+  wave_rows(a.rows, p0, p1);
+  for (int64_t p = p0; p < p1; ++p) {
+    const int i = a.atom_of_pos[p];
+    if (i < 0) continue;
+    lin_bwd_atom<W1, W2, W3, P, false>(a, i, smem, h1s, hd1s, dTs, gRs, lane, vir, cc, 0);
   }
   finish_block_virial(a, vir, vred, lane, wv);
+}
+
+// Cell-ordered backward (affine-last-layer nets): block b takes cells b,
+// b + grid, ... of the list grid (side >= the list radius, >= 3 cells per
+// axis, so every neighbour of a cell's atoms lies in the 27 cells around it).
+// The waves take the cell's atoms in turn; every pair force lands in the LDS
+// accumulator, which is then copied to part[26 - s][position][3] for the 27
+// neighbour cells (s = offset of the destination cell seen from this one,
+// 26 - s = this cell seen from the destination).  Each part entry is written
+// by exactly one cell, so no global atomics are needed; k_cell_gather adds
+// the 27 parts of every atom.  Atoms past the capacity use global atomics.
+template <int W1, int W2, int W3>
+struct CellShape {
+  typedef Shape<W1, W2, W3> S;
+  static_assert(!S::XL2, "the cell kernel keeps no cross-lane skip scratch");
+  static constexpr int W_DT = 0;                        // float [S3][4]
+  static constexpr int W_GR = S::S3 * 16;               // float [64][4]
+  static constexpr int W_BYTES = W_GR + 1024;
+};
+
+template <int W1, int W2, int W3, int P>
+__global__ void __launch_bounds__(64 * CELL_WAVES, 1) k_embed_bwd_cells(MixArgs a, CellArgs ca) {
+  typedef LinShape<W1, W2, W3> LS;
+  typedef CellShape<W1, W2, W3> CS;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double vred[CELL_WAVES][9];
+  const int nnets = a.d.ntypes * a.d.ntypes;
+  const int nw = blockDim.x >> 6;
+  copy_nets(smem, a.nets, nnets * LS::NET_BYTES);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  unsigned char *ws = smem + nnets * LS::NET_BYTES + wv * CS::W_BYTES;
+  float *dTs = (float *)(ws + CS::W_DT);
+  float *gRs = (float *)(ws + CS::W_GR);
+  double *facc = (double *)(smem + nnets * LS::NET_BYTES + nw * CS::W_BYTES);
+  const int nacc = 27 * 3 * ca.cap;
+  double vir[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) vir[k] = 0.0;
+  for (int64_t c = blockIdx.x; c < ca.ncell; c += gridDim.x) {
+    for (int o = threadIdx.x; o < nacc; o += blockDim.x) facc[o] = 0.0;
+    __syncthreads();
+    CellCtx cc;
+    cc.facc = facc;
+    cc.code = ca.code;
+    cc.nc0 = ca.nc[0];
+    cc.nc1 = ca.nc[1];
+    cc.nc2 = ca.nc[2];
+    cc.cap = ca.cap;
+    cc.cz = (int)(c % cc.nc2);
+    cc.cy = (int)((c / cc.nc2) % cc.nc1);
+    cc.cx = (int)(c / ((int64_t)cc.nc1 * cc.nc2));
+    const int b = ca.cell_start[c], e = ca.cell_start[c + 1];
+    for (int k = b + wv; k < e; k += nw)
+      lin_bwd_atom<W1, W2, W3, P, true>(a, ca.cell_atoms[k], smem, nullptr, nullptr, dTs, gRs, lane, vir, cc, k - b);
+    __syncthreads();
+    for (int s = 0; s < 27; ++s) {
+      const int x = (cc.cx + s / 9 - 1 + cc.nc0) % cc.nc0, y = (cc.cy + (s / 3) % 3 - 1 + cc.nc1) % cc.nc1,
+                z = (cc.cz + s % 3 - 1 + cc.nc2) % cc.nc2;
+      const int64_t c2 = ((int64_t)x * cc.nc1 + y) * cc.nc2 + z;
+      const int b2 = ca.cell_start[c2], m2 = min(ca.cell_start[c2 + 1] - b2, ca.cap);
+      double *dst = ca.part + ((int64_t)(26 - s) * ca.n + b2) * 3;
+      const double *src = facc + 3 * s * ca.cap;
+      for (int o = threadIdx.x; o < 3 * m2; o += blockDim.x) dst[o] = src[o];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    double v = vir[k];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
+    if (lane == 0) vred[wv][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 9) {
+    double v = 0.0;
+    for (int w = 0; w < nw; ++w) v += vred[w][threadIdx.x];
+    a.vir_part[(int64_t)blockIdx.x * 9 + threadIdx.x] = v;
+  }
+}
+
+// F[j] += the 27 parts of the atom at cell-ordered position p
+__global__ void k_cell_gather(CellArgs ca, double *F) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ca.n) return;
+  const int j = ca.cell_atoms[p];
+  const int l = (int)(p - ca.cell_start[ca.cell_of[j]]);
+  if (l >= ca.cap) return;
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+#pragma unroll 9
+  for (int s = 0; s < 27; ++s) {
+    const double *q = ca.part + ((int64_t)s * ca.n + p) * 3;
+    fx += q[0];
+    fy += q[1];
+    fz += q[2];
+  }
+  F[3 * (int64_t)j + 0] += fx;
+  F[3 * (int64_t)j + 1] += fy;
+  F[3 * (int64_t)j + 2] += fz;
 }
 
 // ---------------------------------------------------------------------------
@@ -1165,6 +1354,74 @@ void launch_embed_mix(hipStream_t s, const MixArgs &a, int pass, int grid) {
   ++id;
   DPK_MIX_SHAPES(X)
 #undef X
+}
+
+// ---------------------------------------------------------------------------
+// cell-ordered backward: configuration and launch
+// ---------------------------------------------------------------------------
+constexpr size_t CELL_LDS_MAX = 160 * 1024;  // LDS of one CU
+
+template <int W1, int W2, int W3, int LIN>
+static bool cells_config_t(int nnets, int cap, int *threads, size_t *lds) {
+  if constexpr (LIN == 0 || Shape<W1, W2, W3>::XL2) {
+    return false;
+  } else {
+    const size_t fixed = (size_t)nnets * LinShape<W1, W2, W3>::NET_BYTES + (size_t)27 * 3 * cap * sizeof(double);
+    const size_t budget = CELL_LDS_MAX - sizeof(double) * CELL_WAVES * 9;
+    for (int nw = CELL_WAVES; nw >= 4; nw -= 4) {
+      const size_t b = fixed + (size_t)nw * CellShape<W1, W2, W3>::W_BYTES;
+      if (b <= budget) {
+        *threads = 64 * nw;
+        *lds = b;
+        return true;
+      }
+    }
+    return false;
+  }
+}
+
+template <int W1, int W2, int W3, int LIN, int P>
+static void launch_cells_t(hipStream_t s, const MixArgs &a, const CellArgs &ca, int grid, int threads, size_t lds) {
+  if constexpr (LIN != 0 && !Shape<W1, W2, W3>::XL2) {
+    (void)hipFuncSetAttribute((const void *)k_embed_bwd_cells<W1, W2, W3, P>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_embed_bwd_cells<W1, W2, W3, P>), dim3(grid), dim3(threads), lds, s, a, ca);
+  }
+}
+
+bool embed_cells_config(const MixArgs &a, int cap, int *threads, size_t *lds) {
+  if (cap < 1 || cap > 255) return false;
+  const int nnets = a.d.ntypes * a.d.ntypes;
+  int id = 0;
+#define X(a_, b_, c_, l_)                                                    \
+  if (a.shape == id) return cells_config_t<a_, b_, c_, l_>(nnets, cap, threads, lds); \
+  ++id;
+  DPK_MIX_SHAPES(X)
+#undef X
+  return false;
+}
+
+int cells_grid(int64_t ncell) {
+  int64_t g = ncell < 2048 ? ncell : 2048;
+  return (int)(g < 1 ? 1 : g);
+}
+
+void launch_embed_cells(hipStream_t s, const MixArgs &a, const CellArgs &ca, int grid, int threads, size_t lds) {
+  int id = 0;
+#define X(a_, b_, c_, l_)                                                          \
+  if (a.shape == id) {                                                             \
+    if (a.prec == 0) launch_cells_t<a_, b_, c_, l_, 0>(s, a, ca, grid, threads, lds); \
+    else launch_cells_t<a_, b_, c_, l_, 1>(s, a, ca, grid, threads, lds);          \
+    return;                                                                        \
+  }                                                                                \
+  ++id;
+  DPK_MIX_SHAPES(X)
+#undef X
+}
+
+void launch_cell_gather(hipStream_t s, const CellArgs &ca, double *F) {
+  if (ca.n <= 0) return;
+  hipLaunchKernelGGL(k_cell_gather, dim3((unsigned)((ca.n + 255) / 256)), dim3(256), 0, s, ca, F);
 }
 
 }  // namespace dpk

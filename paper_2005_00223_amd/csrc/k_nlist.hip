@@ -201,19 +201,26 @@ __global__ void __launch_bounds__(1024) k_scan_single(const int32_t *in, int64_t
   if (threadIdx.x == 0) out[m] = carry;
 }
 
-__global__ void k_cell_fill(int64_t n, const int32_t *cell_of, const int32_t *cell_start, int32_t *cell_fill,
-                            int32_t *cell_atoms, const uint32_t *cond) {
+// code[i] = cx << 24 | cy << 16 | cz << 8 | min(index inside the cell, 255)
+// (cell coordinates modulo 256; used only with at most 255 cells per axis)
+__global__ void k_cell_fill(int64_t n, CellGrid g, const int32_t *cell_of, const int32_t *cell_start,
+                            int32_t *cell_fill, int32_t *cell_atoms, uint32_t *code, const uint32_t *cond) {
   if (skip_build(cond)) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int c = cell_of[i];
   int p = atomicAdd(&cell_fill[c], 1);
   cell_atoms[cell_start[c] + p] = (int32_t)i;
+  if (code) {
+    const int cz = c % g.nc[2], cy = (c / g.nc[2]) % g.nc[1], cx = c / (g.nc[1] * g.nc[2]);
+    code[i] = ((uint32_t)(cx & 255) << 24) | ((uint32_t)(cy & 255) << 16) | ((uint32_t)(cz & 255) << 8) |
+              (uint32_t)(p < 255 ? p : 255);
+  }
 }
 
 void launch_cells(hipStream_t s, int64_t n, const double4 *xw, const CellGrid &g, int32_t *cell_of,
-                  int32_t *cell_start, int32_t *cell_fill, int32_t *cell_atoms, int32_t *scan_tmp,
-                  const uint32_t *cond) {
+                  int32_t *cell_start, int32_t *cell_fill, int32_t *cell_atoms, uint32_t *cell_code,
+                  int32_t *scan_tmp, const uint32_t *cond) {
   int64_t ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
   unsigned gc = (unsigned)((ncell + 255) / 256);
   hipLaunchKernelGGL(k_fill_cond, dim3(gc), dim3(256), 0, s, scan_tmp, ncell, 0, cond);
@@ -223,8 +230,8 @@ void launch_cells(hipStream_t s, int64_t n, const double4 *xw, const CellGrid &g
                        scan_tmp, cond);
   hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, s, scan_tmp, ncell, cell_start, cond);
   if (n > 0)
-    hipLaunchKernelGGL(k_cell_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, cell_of, cell_start,
-                       cell_fill, cell_atoms, cond);
+    hipLaunchKernelGGL(k_cell_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, g, cell_of,
+                       cell_start, cell_fill, cell_atoms, cell_code, cond);
 }
 
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {

@@ -118,6 +118,11 @@ class DPModel:
     def stats(self):
         return L.dp_get_stats(self.ctx)
 
+    def set_force_scatter(self, mode: int):
+        """0: cell-ordered LDS scatter where the path allows it (default);
+        1: FP64 global atomics for every pair force."""
+        L.dp_set_force_scatter(self.ctx, mode)
+
     # ---- student embedding net -------------------------------------------
     @staticmethod
     def student_cfg(**kw) -> "L.dp_student_cfg":
