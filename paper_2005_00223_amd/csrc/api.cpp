@@ -129,6 +129,7 @@ struct Workspace {
   int cand_cap = 0;
   bool nd = false;
   double4 *xw = nullptr, *xref = nullptr, *rt = nullptr, *dr = nullptr;
+  float4 *rt32 = nullptr;  // mixed precision: the environment matrix in FP32
   int32_t *cell_of, *cell_atoms, *cell_start, *cell_fill, *scan_tmp, *cand, *cand_n, *nlist, *nreal, *pos_of_atom,
       *atom_of_pos, *blk_counts, *type_count, *type_start;
   double *T, *D, *dD, *Y[MAXF + 1], *Tt[MAXF + 1], *G[MAXF + 1], *eatom, *partial, *vir_part, *force_tmp,
@@ -274,7 +275,8 @@ int ensure_ws(dp_ctx *c, int64_t n, int64_t ncell, int cand_cap) {
   add((void **)&w.blk_counts, (size_t)4 * nblk * MAXT);
   add((void **)&w.type_count, 4 * MAXT);
   add((void **)&w.type_start, 4 * (MAXT + 1));
-  add((void **)&w.rt, sizeof(double4) * nn * d.nnei);
+  if (mixed) add((void **)&w.rt32, sizeof(float4) * nn * d.nnei);
+  else add((void **)&w.rt, sizeof(double4) * nn * d.nnei);
   add((void **)&w.dr, sizeof(double4) * nn * d.nnei);
   if (!mixed) {
     add((void **)&w.T, sizeof(double) * nn * d.M1 * 4);
@@ -321,6 +323,8 @@ int ensure_ws(dp_ctx *c, int64_t n, int64_t ncell, int cand_cap) {
   }
   if (!nd) w.net_deriv = nullptr;
   if (!mixed) w.cell_part = nullptr;
+  if (mixed) w.rt = nullptr;
+  else w.rt32 = nullptr;
   c->cgrid_ok = false;
   w.G[0] = w.dD;
   w.prec = c->precision;
@@ -629,7 +633,7 @@ MixArgs mix_args(dp_ctx *c, int64_t rows, double *F) {
   ma.xw = w.xw;
   ma.nlist = w.nlist;
   ma.nreal = w.nreal;
-  ma.rt = w.rt;
+  ma.rt = w.rt32;
   ma.dr = w.dr;
   ma.T32 = w.T32;
   ma.dT32 = w.dT32;
@@ -672,7 +676,7 @@ void eval_lists(dp_ctx *c, int64_t n, const double L[3]) {
   launch_format(s, n, w.xw, d, L, w.cand, w.cand_n, w.cand_cap, w.nlist, w.nreal, &w.status->overflow,
                 w.status->max_real, &w.status->flags);
   tmark(c, 2);
-  launch_env(s, n, w.xw, d, L, w.nlist, w.nreal, w.rt, w.dr);
+  launch_env(s, n, w.xw, d, L, w.nlist, w.nreal, w.rt, w.rt32, w.dr);
   tmark(c, 3);
 }
 
@@ -944,7 +948,7 @@ void st_draw(dp_ctx *c, uint64_t seed, int64_t q0, int64_t batch) {
   sa.type_start = w.type_start;
   sa.atom_of_pos = w.atom_of_pos;
   sa.nreal = w.nreal;
-  sa.rt = w.rt;
+  sa.dr = w.dr;
   sa.seed = seed;
   sa.q0 = q0;
   sa.batch = (int)batch;

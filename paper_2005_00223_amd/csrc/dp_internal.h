@@ -96,8 +96,24 @@ void launch_copy_ref(hipStream_t s, int64_t n, const double4 *xw, double4 *xref,
 void launch_end_rebuild(hipStream_t s, uint32_t *flags, unsigned long long *nbuild);
 
 // ---- environment matrix (k_env.hip) ----
+// s(r) = sw(r) / r with the quintic switch, FP64; the one expression both the
+// environment kernel and the student sampler evaluate
+__device__ inline double env_s(double r, double rcs, double rc, double inv_w) {
+  double sw;
+  if (r < rcs) {
+    sw = 1.0;
+  } else if (r < rc) {
+    const double x = (r - rcs) * inv_w;
+    sw = x * x * x * (-6.0 * x * x + 15.0 * x - 10.0) + 1.0;
+  } else {
+    sw = 0.0;
+  }
+  return sw * (1.0 / r);
+}
+// exactly one of rt (FP64 evaluation) and rt32 (mixed precision, the same
+// values rounded to FP32, which is all the mixed kernels read) is non-NULL
 void launch_env(hipStream_t s, int64_t n, const double4 *xw, const Dims &d, const double *L, const int32_t *nlist,
-                const int32_t *nreal, double4 *rt, double4 *dr);
+                const int32_t *nreal, double4 *rt, float4 *rt32, double4 *dr);
 
 // ---- FP64 embedding + descriptor (k_embed_f64.hip) ----
 struct EmbedArgs {

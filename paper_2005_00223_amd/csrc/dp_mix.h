@@ -48,7 +48,8 @@ struct MixArgs {
   const int32_t *atom_of_pos;
   const double4 *xw;
   const int32_t *nlist, *nreal;
-  const double4 *rt, *dr;
+  const float4 *rt;           // environment matrix rows, FP32
+  const double4 *dr;
   float *T32;                 // [natoms][M1][4], T / Nc (pass 1 writes, pass 2 reads nothing of it)
   const float *dT32;          // [natoms][M1][4], dE/dT of the unscaled sum (pass 2)
   double *force;              // [natoms][3]

@@ -47,7 +47,7 @@ struct StSampleArgs {
   const int32_t *type_start;   // [ntypes] first type-sorted position
   const int32_t *atom_of_pos;  // [rows]
   const int32_t *nreal;        // [natoms][ntypes]
-  const double4 *rt;           // [natoms][nnei], .x = s
+  const double4 *dr;           // [natoms][nnei], .w = r (s = sw(r) / r is recomputed)
   uint64_t seed;
   int64_t q0;                  // index of the batch's first sample
   int batch;                   // samples per net

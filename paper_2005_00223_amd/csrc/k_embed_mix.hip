@@ -3,8 +3,9 @@
 // after the first are 16-bit matrix-core products (FP16 or BF16,
 // v_mfma_f32_16x16x32) with FP32 accumulation and 16-bit weights; the
 // rank-1 first layer, tanh, the skip adds and the descriptor contractions
-// stay in FP32; distances, the environment matrix, the force Jacobian and
-// every force/virial sum stay in FP64.
+// stay in FP32; the environment matrix is computed in FP64 and read as FP32
+// (the precision every product above takes it in); distances, the force
+// Jacobian and every force/virial sum stay in FP64.
 //
 // Unlike the paper, activations are not rounded to 16 bits: each 16-bit
 // operand that carries an activation is split into hi = rn16(x) and
@@ -382,9 +383,9 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 1>::B)) k_embed_fw
       const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
       const int64_t base = (int64_t)i * d.nnei + d.off[u];
       for (int n0 = 0; n0 < cnt; n0 += 16) {
-        const double4 r4 = n0 + n < cnt ? a.rt[base + n0 + n] : make_double4(0.0, 0.0, 0.0, 0.0);
-        const float s = (float)r4.x;
-        if (g == 0) *(float4 *)(Rs + 4 * n) = make_float4((float)r4.x, (float)r4.y, (float)r4.z, (float)r4.w);
+        const float4 r4 = n0 + n < cnt ? a.rt[base + n0 + n] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float s = r4.x;
+        if (g == 0) *(float4 *)(Rs + 4 * n) = make_float4(r4.x, r4.y, r4.z, r4.w);
         float h1[2][4], hd_unused[2][4];
         layer1<W1, false>(w1, b1, s, g, h1, hd_unused);
         if (S::XL2)
@@ -610,9 +611,9 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 2>::B)) k_embed_bw
       const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
       const int64_t base = (int64_t)i * d.nnei + d.off[u];
       for (int n0 = 0; n0 < cnt; n0 += 16) {
-        const double4 r4 = n0 + n < cnt ? a.rt[base + n0 + n] : make_double4(0.0, 0.0, 0.0, 0.0);
-        const float s = (float)r4.x;
-        if (g == 0) *(float4 *)(Rs + 4 * n) = make_float4((float)r4.x, (float)r4.y, (float)r4.z, (float)r4.w);
+        const float4 r4 = n0 + n < cnt ? a.rt[base + n0 + n] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float s = r4.x;
+        if (g == 0) *(float4 *)(Rs + 4 * n) = make_float4(r4.x, r4.y, r4.z, r4.w);
         float h1[2][4], hd1[2][4];
         layer1<W1, true>(w1, b1, s, g, h1, hd1);
         if (S::XL2)
@@ -784,17 +785,17 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_fwd_lin(MixArgs a) 
       const int64_t base = (int64_t)i * d.nnei + d.off[u];
       v4f Hacc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
       float sr0 = 0.f, sr1 = 0.f, sr2 = 0.f, sr3 = 0.f;  // this lane's neighbours: sum of R
-      double4 r4n = n < cnt ? a.rt[base + n] : make_double4(0.0, 0.0, 0.0, 0.0);
+      float4 r4n = n < cnt ? a.rt[base + n] : make_float4(0.f, 0.f, 0.f, 0.f);
       for (int n0 = 0; n0 < cnt; n0 += 16) {
         // this tile's environment rows; the next tile's are loaded meanwhile
-        const double4 r4 = r4n;
-        if (n0 + 16 < cnt) r4n = n0 + 16 + n < cnt ? a.rt[base + n0 + 16 + n] : make_double4(0.0, 0.0, 0.0, 0.0);
-        const float s = (float)r4.x;
-        if (g == 0) *(float4 *)(Rs + 4 * n) = make_float4((float)r4.x, (float)r4.y, (float)r4.z, (float)r4.w);
-        sr0 += (float)r4.x;
-        sr1 += (float)r4.y;
-        sr2 += (float)r4.z;
-        sr3 += (float)r4.w;
+        const float4 r4 = r4n;
+        if (n0 + 16 < cnt) r4n = n0 + 16 + n < cnt ? a.rt[base + n0 + 16 + n] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float s = r4.x;
+        if (g == 0) *(float4 *)(Rs + 4 * n) = make_float4(r4.x, r4.y, r4.z, r4.w);
+        sr0 += r4.x;
+        sr1 += r4.y;
+        sr2 += r4.z;
+        sr3 += r4.w;
         float h1[2][4], hd_unused[2][4];
         layer1<W1, false>(w1, b1, s, g, h1, hd_unused);
         if (S::XL2)
@@ -949,16 +950,16 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
       my[r] = Macc[1][r];
     }
     const Split8<P> MA = split8<P>(mx, my);
-    double4 r4n = n < cnt ? a.rt[base + n] : make_double4(0.0, 0.0, 0.0, 0.0);
+    float4 r4n = n < cnt ? a.rt[base + n] : make_float4(0.f, 0.f, 0.f, 0.f);
     // force-pass operands of the current 64-neighbour chunk, loaded a chunk ahead
     double4 drc = lane < cnt ? a.dr[base + lane] : make_double4(0.0, 0.0, 1.0, 1.0);
     int jc = lane < cnt ? a.nlist[base + lane] : 0;
     uint32_t codec = 0;
     for (int n0 = 0; n0 < cnt; n0 += 16) {
       // this tile's environment rows; the next tile's are loaded meanwhile
-      const double4 r4 = r4n;
-      if (n0 + 16 < cnt) r4n = n0 + 16 + n < cnt ? a.rt[base + n0 + 16 + n] : make_double4(0.0, 0.0, 0.0, 0.0);
-      const float s = (float)r4.x;
+      const float4 r4 = r4n;
+      if (n0 + 16 < cnt) r4n = n0 + 16 + n < cnt ? a.rt[base + n0 + 16 + n] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float s = r4.x;
       float h1[2][4], hd1[2][4];
       layer1<W1, true>(w1, b1, s, g, h1, hd1);
       if (S::XL2)
@@ -1000,7 +1001,7 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
       const int slot0 = n0 & 63;
       if (g == 0) {
         // dE/dR = a + q + (R . b) e_0
-        const float bd = (float)r4.x * cb[0] + (float)r4.y * cb[1] + (float)r4.z * cb[2] + (float)r4.w * cb[3];
+        const float bd = r4.x * cb[0] + r4.y * cb[1] + r4.z * cb[2] + r4.w * cb[3];
         *(float4 *)(gRs + 4 * (slot0 + n)) = make_float4(ca[0] + q0 + bd, ca[1] + q1, ca[2] + q2, ca[3] + q3);
       }
       // cell code of this chunk's neighbours (jc arrived during the tile)

@@ -4,12 +4,15 @@
 //   R = (s, s dx/r, s dy/r, s dz/r),  s = sw(r)/r,
 //   sw = 1 (r < rcs), u^3 (-6u^2 + 15u - 10) + 1 (rcs <= r < rc), 0 (r >= rc),
 //   u = (r - rcs)/(rc - rcs)  (quintic switch, C2 in the displacements).
-// Output rt[i][slot] = R and dr[i][slot] = (dx, dy, dz, r), double.  Padded
-// slots are not written (every consumer stops at the real count).
+// Output rt[i][slot] = R and dr[i][slot] = (dx, dy, dz, r), double; for the
+// mixed-precision path R is stored rounded to FP32 instead (its kernels read
+// nothing else of it).  Padded slots are not written (every consumer stops
+// at the real count).
 //
 // One wave per centre atom; the lanes stride over the atom's real slots so
 // that the two output streams are written contiguously.  HBM-bound:
-// per real slot 4 B nlist + 32 B neighbour position (L2/MALL) in, 64 B out.
+// per real slot 4 B nlist + 32 B neighbour position (L2/MALL) in, 64 B out
+// (48 B with the FP32 R).
 #include "dp_internal.h"
 
 namespace dpk {
@@ -22,9 +25,17 @@ __device__ inline double env_min_image(double v, double L) {
   return v;
 }
 
+__device__ inline void put_rt(double4 *rt, int64_t k, double a, double b, double c, double e) {
+  rt[k] = make_double4(a, b, c, e);
+}
+__device__ inline void put_rt(float4 *rt, int64_t k, double a, double b, double c, double e) {
+  rt[k] = make_float4((float)a, (float)b, (float)c, (float)e);
+}
+
+template <typename RT>
 __global__ void __launch_bounds__(256) k_env(int64_t n, const double4 *__restrict__ xw, Dims d, double L0, double L1,
                                              double L2, const int32_t *__restrict__ nlist,
-                                             const int32_t *__restrict__ nreal, double4 *__restrict__ rt,
+                                             const int32_t *__restrict__ nreal, RT *__restrict__ rt,
                                              double4 *__restrict__ dr) {
   int lane = threadIdx.x & 63;
   int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -54,19 +65,9 @@ __global__ void __launch_bounds__(256) k_env(int64_t n, const double4 *__restric
         double dy = env_min_image(pj.y - p.y, L1);
         double dz = env_min_image(pj.z - p.z, L2);
         double r = sqrt(dx * dx + dy * dy + dz * dz);
-        double sw;
-        if (r < rcs) {
-          sw = 1.0;
-        } else if (r < rc) {
-          double x = (r - rcs) * inv_w;
-          sw = x * x * x * (-6.0 * x * x + 15.0 * x - 10.0) + 1.0;
-        } else {
-          sw = 0.0;
-        }
-        double inv_r = 1.0 / r;
-        double s = sw * inv_r;
-        double t = s * inv_r;
-        rt[base + q] = make_double4(s, t * dx, t * dy, t * dz);
+        const double s = env_s(r, rcs, rc, inv_w);
+        double t = s * (1.0 / r);
+        put_rt(rt, base + q, s, t * dx, t * dy, t * dz);
         dr[base + q] = make_double4(dx, dy, dz, r);
       }
     }
@@ -74,10 +75,14 @@ __global__ void __launch_bounds__(256) k_env(int64_t n, const double4 *__restric
 }
 
 void launch_env(hipStream_t s, int64_t n, const double4 *xw, const Dims &d, const double *L, const int32_t *nlist,
-                const int32_t *nreal, double4 *rt, double4 *dr) {
+                const int32_t *nreal, double4 *rt, float4 *rt32, double4 *dr) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_env, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, xw, d, L[0], L[1], L[2], nlist, nreal,
-                     rt, dr);
+  if (rt32)
+    hipLaunchKernelGGL(k_env<float4>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, xw, d, L[0], L[1], L[2],
+                       nlist, nreal, rt32, dr);
+  else
+    hipLaunchKernelGGL(k_env<double4>, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, xw, d, L[0], L[1], L[2],
+                       nlist, nreal, rt, dr);
 }
 
 }  // namespace dpk
