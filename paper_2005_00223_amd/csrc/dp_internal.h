@@ -12,7 +12,7 @@ constexpr int MAXT = 8;        // atom types
 constexpr int MAXL = 4;        // embedding layers
 constexpr int MAXF = 4;        // hidden fitting layers
 constexpr int KEY_CAP = 512;   // neighbours within rc per atom held by the LDS sort
-constexpr int ROW_TILE = 64;   // fitting-net row tile; each type's rows are padded to it
+constexpr int ROW_TILE = 128;  // fitting-net row tile; each type's rows are padded to it
 
 // Geometry / model dimensions passed by value to every kernel.
 struct Dims {

@@ -89,8 +89,19 @@ __device__ inline int rtype(const int32_t *ts, int ntypes, int64_t r0) {
 }
 
 constexpr int FIT_WAVES = 4;
-constexpr int F0_CK = 2;  // first-layer k-steps per staged chunk (forward)
-constexpr int F0_CA = 4;  // rows of D per staged chunk (backward)
+constexpr int FIT_NT = 2;                           // 16-row tiles per wave
+constexpr int FIT_ROWS = 16 * FIT_NT * FIT_WAVES;   // rows per workgroup
+constexpr int FIT_MT = 15;                          // hidden width 240 = 15 output tiles
+constexpr int FIT_KSH = (FIT_MT + 1) / 2;           // k-steps of a hidden layer
+constexpr int STAGE_BYTES = 60 * 1024;              // one half of the double-buffered operand stage
+constexpr int F0_CK = 4;                            // layer-0 k-steps per staged chunk (forward)
+constexpr int FH_CK = 2;                            // hidden-layer k-steps per chunk (hi, then lo)
+constexpr int F0_CA = 7;                            // rows of D per staged chunk (backward)
+constexpr int FH_NC = FIT_KSH / FH_CK;              // chunks per hidden layer
+static_assert(FIT_ROWS == ROW_TILE, "a workgroup's rows must share one type");
+static_assert(F0_CK * FIT_MT * 1024 <= STAGE_BYTES && 2 * FH_CK * FIT_MT * 1024 <= STAGE_BYTES &&
+                  F0_CA * FIT_KSH * 1024 <= STAGE_BYTES && FIT_KSH % FH_CK == 0,
+              "staged chunks must fit one half of the stage");
 
 // One 1 KB operand block (64 lanes x 16 B) from global memory straight into
 // LDS (global_load_lds_dwordx4, no registers); lds must be wave-uniform.
@@ -115,303 +126,404 @@ __device__ inline float *tile_t(float *tbuf, int64_t tile, int nl, int l, int mt
   return tbuf + (((tile * nl + l) * MT + mt) * 64) * 4;
 }
 
-template <int P, int MT>
-__global__ void __launch_bounds__(64 * FIT_WAVES, 2) k_fit_fwd(FitMixArgs a) {
-  typedef typename FT<P>::v8 V;
-  constexpr int KSH = (MT + 1) / 2;
-  __shared__ __align__(16) unsigned char stage[2][F0_CK * MT * 1024];
-  const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15, wv = threadIdx.x >> 6;
-  const int64_t tile = (int64_t)blockIdx.x * FIT_WAVES + wv;
-  const int64_t p0 = tile * 16;
-  const int ntypes = a.d.ntypes;
-  // a block's 64 rows share one type (types are padded to 64 rows) or lie
-  // past the end: the exit is block-uniform, so the barriers below are safe
-  if ((int64_t)blockIdx.x * 16 * FIT_WAVES >= a.type_start[ntypes]) return;
-  const int t = rtype(a.type_start, ntypes, p0);
-  const int i = a.atom_of_pos[p0 + n];
-  const int M1 = a.d.M1, NL = a.d.n_fit;
-  const float4 *Ti = (const float4 *)(a.T32 + (int64_t)(i < 0 ? 0 : i) * M1 * 4);
-  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-  float4 Tb[8];
-#pragma unroll
-  for (int v = 0; v < 8; ++v) Tb[v] = i >= 0 ? Ti[8 * (g & 1) + v] : z4;
-  const unsigned char *W = a.w;
-  v4f acc[MT];
-  {
-    const float *b0 = (const float *)(W + a.fo.bias[t][0]);
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const float4 b = *(const float4 *)(b0 + 16 * mt + 4 * g);
-      acc[mt] = v4f{b.x, b.y, b.z, b.w};
-    }
+// Staged chunk gc of the forward: layer-0 chunks (F0_CK k-steps of the
+// [kk][mt] image), then FH_NC chunks per hidden layer (FH_CK k-steps of the
+// hi image, followed by the same k-steps of the lo image when the layer
+// carries one).
+__device__ inline void fwd_issue(const FitMixArgs &a, int t, int gc, int n0c, unsigned char *buf, int wv, int lane) {
+  if (gc < n0c) {
+    const int KS0 = a.d.M1 / 2, k0 = gc * F0_CK, nk = KS0 - k0 < F0_CK ? KS0 - k0 : F0_CK;
+    dma_blocks(a.w + a.fo.a0f[t], (int64_t)k0 * FIT_MT, nk * FIT_MT, buf, wv, lane);
+  } else {
+    const int h = gc - n0c, l = 1 + h / FH_NC, c = h % FH_NC;
+    dma_blocks(a.w + a.fo.ahf[t][l], (int64_t)c * FH_CK * FIT_MT, FH_CK * FIT_MT, buf, wv, lane);
+    if (l >= a.nsplit)
+      dma_blocks(a.w + a.fo.ahf_lo[t][l], (int64_t)c * FH_CK * FIT_MT, FH_CK * FIT_MT, buf + FH_CK * FIT_MT * 1024,
+                 wv, lane);
   }
-  // layer 0: K = M1*16 features of D, formed from T.  The A operands
-  // ([kk][mt] blocks of 1 KB) stream through LDS in chunks of F0_CK k-steps,
-  // the next chunk loading while this one is used.
-  const unsigned char *A0 = W + a.fo.a0f[t];
-  const int KS0 = M1 / 2;
-  const int nch = (KS0 + F0_CK - 1) / F0_CK;
-  dma_blocks(A0, 0, (KS0 < F0_CK ? KS0 : F0_CK) * MT, stage[0], wv, lane);
-  dma_wait_all();
-  for (int c = 0; c < nch; ++c) {
-    if (c + 1 < nch) {
-      const int k1 = (c + 1) * F0_CK, nk = (KS0 - k1 < F0_CK) ? KS0 - k1 : F0_CK;
-      dma_blocks(A0, (int64_t)k1 * MT, nk * MT, stage[(c + 1) & 1], wv, lane);
-    }
-    const unsigned char *buf = stage[c & 1];
+}
+
+// Staged chunk gc of the backward: FH_NC chunks per hidden layer from the
+// last down to layer 1, then layer-0 chunks of F0_CA rows of D ([aa][kk]).
+__device__ inline void bwd_issue(const FitMixArgs &a, int t, int gc, unsigned char *buf, int wv, int lane) {
+  const int nh = (a.d.n_fit - 1) * FH_NC;
+  if (gc < nh) {
+    const int l = a.d.n_fit - 1 - gc / FH_NC, c = gc % FH_NC;
+    dma_blocks(a.w + a.fo.ahb[t][l], (int64_t)c * FH_CK * FIT_MT, FH_CK * FIT_MT, buf, wv, lane);
+    if (l >= a.nsplit)
+      dma_blocks(a.w + a.fo.ahb_lo[t][l], (int64_t)c * FH_CK * FIT_MT, FH_CK * FIT_MT, buf + FH_CK * FIT_MT * 1024,
+                 wv, lane);
+  } else {
+    const int M1 = a.d.M1, a0 = (gc - nh) * F0_CA, na = M1 - a0 < F0_CA ? M1 - a0 : F0_CA;
+    dma_blocks(a.w + a.fo.a0b[t], (int64_t)a0 * FIT_KSH, na * FIT_KSH, buf, wv, lane);
+  }
+}
+
+// One hidden layer over its FH_NC staged chunks: acc[nt][mt] += A X for the
+// wave's tiles, X of k-step kk = the split halves xs[nt][kk] built by bx(nt,
+// kk, x, y) on the fly; SPLIT adds the lo weights (three products).  Every
+// chunk prefetches the next one of the sequence (issue) and ends with the
+// block barrier.
+template <int P, int MT, bool SPLIT, class Issue, class BX>
+__device__ inline void hidden_layer(unsigned char (*stage)[STAGE_BYTES], int &gc, int nchunks, Issue issue, BX bx,
+                                    v4f (&acc)[FIT_NT][MT], int lane) {
+  typedef typename FT<P>::v8 V;
 #pragma unroll
-    for (int q = 0; q < F0_CK; ++q) {
-      const int kk = c * F0_CK + q;
-      if (kk < KS0) {
-        const float4 Ta = i >= 0 ? Ti[2 * kk + (g >> 1)] : z4;
+  for (int c = 0; c < FH_NC; ++c, ++gc) {
+    if (gc + 1 < nchunks) issue(gc + 1, stage[(gc + 1) & 1]);
+    const unsigned char *buf = stage[gc & 1];
+#pragma unroll
+    for (int q = 0; q < FH_CK; ++q) {
+      const int kk = c * FH_CK + q;
+      FSplit<P> B[FIT_NT];
+#pragma unroll
+      for (int nt = 0; nt < FIT_NT; ++nt) {
         float x[4], y[4];
+        bx(nt, kk, x, y);
+        B[nt] = fsplit<P>(x, y);
+      }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          x[v] = Ta.x * Tb[v].x + Ta.y * Tb[v].y + Ta.z * Tb[v].z + Ta.w * Tb[v].w;
-          y[v] = Ta.x * Tb[v + 4].x + Ta.y * Tb[v + 4].y + Ta.z * Tb[v + 4].z + Ta.w * Tb[v + 4].w;
+      for (int mt = 0; mt < MT; ++mt) {
+        const V ah = *(const V *)(buf + (q * MT + mt) * 1024 + 16 * lane);
+#pragma unroll
+        for (int nt = 0; nt < FIT_NT; ++nt) {
+          acc[nt][mt] = FT<P>::mma(ah, B[nt].hi, acc[nt][mt]);
+          acc[nt][mt] = FT<P>::mma(ah, B[nt].lo, acc[nt][mt]);
         }
-        const FSplit<P> B = fsplit<P>(x, y);
+        if (SPLIT) {
+          const V al = *(const V *)(buf + ((FH_CK + q) * MT + mt) * 1024 + 16 * lane);
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-          const V av = *(const V *)(buf + (q * MT + mt) * 1024 + 16 * lane);
-          acc[mt] = FT<P>::mma(av, B.hi, acc[mt]);
-          acc[mt] = FT<P>::mma(av, B.lo, acc[mt]);
+          for (int nt = 0; nt < FIT_NT; ++nt) acc[nt][mt] = FT<P>::mma(al, B[nt].hi, acc[nt][mt]);
         }
       }
     }
     dma_wait_all();
   }
-  float Y[MT][4];
+}
+
+// Forward: one workgroup = FIT_ROWS rows of one type, one wave = FIT_NT
+// tiles of 16 rows sharing every operand read from LDS.
+template <int P, int MT>
+__global__ void __launch_bounds__(64 * FIT_WAVES, 1) k_fit_fwd(FitMixArgs a) {
+  typedef typename FT<P>::v8 V;
+  constexpr int NT = FIT_NT;
+  __shared__ __align__(16) unsigned char stage[2][STAGE_BYTES];
+  const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15, wv = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * FIT_ROWS;
+  const int ntypes = a.d.ntypes;
+  // a block's rows share one type (types are padded to FIT_ROWS rows) or lie
+  // past the end: the exit is block-uniform, so the barriers below are safe
+  if (r0 >= a.type_start[ntypes]) return;
+  const int t = rtype(a.type_start, ntypes, r0);
+  const int M1 = a.d.M1, NL = a.d.n_fit, KS0 = M1 / 2;
+  const int64_t tile0 = r0 / 16 + (int64_t)wv * NT;
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  int ia[NT];
+  const float4 *Ti[NT];
+  float4 Tb[NT][8];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    float th[4];
+  for (int nt = 0; nt < NT; ++nt) {
+    ia[nt] = a.atom_of_pos[(tile0 + nt) * 16 + n];
+    Ti[nt] = (const float4 *)(a.T32 + (int64_t)(ia[nt] < 0 ? 0 : ia[nt]) * M1 * 4);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      th[r] = ftanh(acc[mt][r]);
-      Y[mt][r] = th[r];
-    }
-    *(float4 *)(tile_t<MT>(a.tbuf, tile, NL, 0, mt) + 4 * lane) = make_float4(th[0], th[1], th[2], th[3]);
+    for (int v = 0; v < 8; ++v) Tb[nt][v] = (ia[nt] >= 0 && 8 * (g & 1) + v < M1) ? Ti[nt][8 * (g & 1) + v] : z4;
   }
-  // hidden layers 1 .. NL-1 (identity skip)
-  for (int l = 1; l < NL; ++l) {
-    const float *bl = (const float *)(W + a.fo.bias[t][l]);
+  const unsigned char *W = a.w;
+  const int n0c = (KS0 + F0_CK - 1) / F0_CK, nchunks = n0c + (NL - 1) * FH_NC;
+  auto issue = [&](int c, unsigned char *buf) { fwd_issue(a, t, c, n0c, buf, wv, lane); };
+  issue(0, stage[0]);
+  v4f acc[NT][MT];
+  {
+    const float *b0 = (const float *)(W + a.fo.bias[t][0]);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-      const float4 b = *(const float4 *)(bl + 16 * mt + 4 * g);
-      acc[mt] = v4f{b.x, b.y, b.z, b.w};
+      const float4 b = *(const float4 *)(b0 + 16 * mt + 4 * g);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[nt][mt] = v4f{b.x, b.y, b.z, b.w};
     }
-    const V *Ah = (const V *)(W + a.fo.ahf[t][l]);
-    const bool split = l >= a.nsplit;
-    const V *Al = (const V *)(W + a.fo.ahf_lo[t][l]);
+  }
+  // layer 0: K = M1*16 features of D = T T<^T, formed from T as the B operand
+  float4 Ta[NT];
 #pragma unroll
-    for (int kk = 0; kk < KSH; ++kk) {
-      float x[4], y[4];
+  for (int nt = 0; nt < NT; ++nt) Ta[nt] = ia[nt] >= 0 ? Ti[nt][g >> 1] : z4;
+  dma_wait_all();
+  int gc = 0;
+  for (int c = 0; c < n0c; ++c, ++gc) {
+    if (gc + 1 < nchunks) issue(gc + 1, stage[(gc + 1) & 1]);
+    const unsigned char *buf = stage[gc & 1];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        x[v] = Y[2 * kk][v];
-        y[v] = (2 * kk + 1 < MT) ? Y[(2 * kk + 1 < MT) ? 2 * kk + 1 : 0][v] : 0.f;
-      }
-      const FSplit<P> B = fsplit<P>(x, y);
+    for (int q = 0; q < F0_CK; ++q) {
+      const int kk = c * F0_CK + q;
+      if (kk < KS0) {
+        FSplit<P> B[NT];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const V ah = Ah[(mt * KSH + kk) * 64 + lane];
-        acc[mt] = FT<P>::mma(ah, B.hi, acc[mt]);
-        acc[mt] = FT<P>::mma(ah, B.lo, acc[mt]);
-        if (split) {
-          const V al = Al[(mt * KSH + kk) * 64 + lane];
-          acc[mt] = FT<P>::mma(al, B.hi, acc[mt]);
+        for (int nt = 0; nt < NT; ++nt) {
+          const float4 ta = Ta[nt];
+          float x[4], y[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            x[v] = ta.x * Tb[nt][v].x + ta.y * Tb[nt][v].y + ta.z * Tb[nt][v].z + ta.w * Tb[nt][v].w;
+            y[v] = ta.x * Tb[nt][v + 4].x + ta.y * Tb[nt][v + 4].y + ta.z * Tb[nt][v + 4].z + ta.w * Tb[nt][v + 4].w;
+          }
+          B[nt] = fsplit<P>(x, y);
+          // next k-step's row a of T, in flight during this one's products
+          if (kk + 1 < KS0) Ta[nt] = ia[nt] >= 0 ? Ti[nt][2 * (kk + 1) + (g >> 1)] : z4;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+          const V av = *(const V *)(buf + (q * MT + mt) * 1024 + 16 * lane);
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            acc[nt][mt] = FT<P>::mma(av, B[nt].hi, acc[nt][mt]);
+            acc[nt][mt] = FT<P>::mma(av, B[nt].lo, acc[nt][mt]);
+          }
         }
       }
     }
+    dma_wait_all();
+  }
+  float Y[NT][MT][4];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       float th[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        th[r] = ftanh(acc[mt][r]);
-        Y[mt][r] += th[r];
+        th[r] = ftanh(acc[nt][mt][r]);
+        Y[nt][mt][r] = th[r];
       }
-      *(float4 *)(tile_t<MT>(a.tbuf, tile, NL, l, mt) + 4 * lane) = make_float4(th[0], th[1], th[2], th[3]);
+      *(float4 *)(tile_t<MT>(a.tbuf, tile0 + nt, NL, 0, mt) + 4 * lane) = make_float4(th[0], th[1], th[2], th[3]);
     }
+  // hidden layers 1 .. NL-1 (identity skip): the B operand of k-step kk is
+  // made of output tiles 2kk and 2kk+1 of the layer below
+  auto bx = [&](int nt, int kk, float (&x)[4], float (&y)[4]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      x[v] = Y[nt][2 * kk][v];
+      y[v] = (2 * kk + 1 < MT) ? Y[nt][(2 * kk + 1 < MT) ? 2 * kk + 1 : 0][v] : 0.f;
+    }
+  };
+  for (int l = 1; l < NL; ++l) {
+    const float *bl = (const float *)(W + a.fo.bias[t][l]);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const float4 b = *(const float4 *)(bl + 16 * mt + 4 * g);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[nt][mt] = v4f{b.x, b.y, b.z, b.w};
+    }
+    if (l >= a.nsplit) hidden_layer<P, MT, true>(stage, gc, nchunks, issue, bx, acc, lane);
+    else hidden_layer<P, MT, false>(stage, gc, nchunks, issue, bx, acc, lane);
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        float th[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          th[r] = ftanh(acc[nt][mt][r]);
+          Y[nt][mt][r] += th[r];
+        }
+        *(float4 *)(tile_t<MT>(a.tbuf, tile0 + nt, NL, l, mt) + 4 * lane) = make_float4(th[0], th[1], th[2], th[3]);
+      }
   }
   // output layer
   const float *wo = (const float *)(W + a.fo.wout[t]);
-  float e = 0.f;
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    const float4 w4 = *(const float4 *)(wo + 16 * mt + 4 * g);
-    e += Y[mt][0] * w4.x + Y[mt][1] * w4.y + Y[mt][2] * w4.z + Y[mt][3] * w4.w;
+  for (int nt = 0; nt < NT; ++nt) {
+    float e = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const float4 w4 = *(const float4 *)(wo + 16 * mt + 4 * g);
+      e += Y[nt][mt][0] * w4.x + Y[nt][mt][1] * w4.y + Y[nt][mt][2] * w4.z + Y[nt][mt][3] * w4.w;
+    }
+    e += __shfl_xor(e, 16);
+    e += __shfl_xor(e, 32);
+    if (g == 0 && ia[nt] >= 0) a.eatom[ia[nt]] = (double)e + (double)wo[256];
   }
-  e += __shfl_xor(e, 16);
-  e += __shfl_xor(e, 32);
-  if (g == 0 && i >= 0) a.eatom[i] = (double)e + (double)wo[256];
 }
 
 template <int P, int MT>
-__global__ void __launch_bounds__(64 * FIT_WAVES, 2) k_fit_bwd(FitMixArgs a) {
+__global__ void __launch_bounds__(64 * FIT_WAVES, 1) k_fit_bwd(FitMixArgs a) {
   typedef typename FT<P>::v8 V;
-  constexpr int KSH = (MT + 1) / 2;
-  __shared__ float4 sh[FIT_WAVES][16][16];  // per wave: sum_b dD[a][b] T[b] for a < 16
-  __shared__ __align__(16) unsigned char stage[2][F0_CA * KSH * 1024];
+  constexpr int NT = FIT_NT, KSH = (MT + 1) / 2;
+  __shared__ float4 sh[FIT_WAVES][NT][16][16];  // per tile: sum_b dD[a][b] T[b] for a < 16
+  __shared__ __align__(16) unsigned char stage[2][STAGE_BYTES];
   const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15, wv = threadIdx.x >> 6;
-  const int64_t tile = (int64_t)blockIdx.x * FIT_WAVES + wv;
-  const int64_t p0 = tile * 16;
+  const int64_t r0 = (int64_t)blockIdx.x * FIT_ROWS;
   const int ntypes = a.d.ntypes;
-  if ((int64_t)blockIdx.x * 16 * FIT_WAVES >= a.type_start[ntypes]) return;  // block-uniform
-  const int t = rtype(a.type_start, ntypes, p0);
-  const int i = a.atom_of_pos[p0 + n];
+  if (r0 >= a.type_start[ntypes]) return;  // block-uniform
+  const int t = rtype(a.type_start, ntypes, r0);
   const int M1 = a.d.M1, NL = a.d.n_fit;
+  const int64_t tile0 = r0 / 16 + (int64_t)wv * NT;
   const unsigned char *W = a.w;
+  int ia[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) ia[nt] = a.atom_of_pos[(tile0 + nt) * 16 + n];
+  const int n0c = (M1 + F0_CA - 1) / F0_CA, nchunks = (NL - 1) * FH_NC + n0c;
+  auto issue = [&](int c, unsigned char *buf) { bwd_issue(a, t, c, buf, wv, lane); };
+  issue(0, stage[0]);
   // dE/dY of the last hidden layer = w_out
-  float dY[MT][4];
+  float dY[NT][MT][4];
   {
     const float *wo = (const float *)(W + a.fo.wout[t]);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       const float4 w4 = *(const float4 *)(wo + 16 * mt + 4 * g);
-      dY[mt][0] = w4.x;
-      dY[mt][1] = w4.y;
-      dY[mt][2] = w4.z;
-      dY[mt][3] = w4.w;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        dY[nt][mt][0] = w4.x;
+        dY[nt][mt][1] = w4.y;
+        dY[nt][mt][2] = w4.z;
+        dY[nt][mt][3] = w4.w;
+      }
     }
   }
-  // hidden layers NL-1 .. 1: dY_{l-1} = W_l dz_l + dY_l, dz_l = dY_l (1 - t_l^2)
+  dma_wait_all();
+  int gc = 0;
+  // hidden layers NL-1 .. 1: dY_{l-1} = W_l dz_l + dY_l, dz_l = dY_l (1 - t_l^2);
+  // the tanh outputs of k-step kk (tiles 2kk, 2kk+1) are loaded two k-steps ahead
   for (int l = NL - 1; l >= 1; --l) {
-    const V *Ah = (const V *)(W + a.fo.ahb[t][l]);
-    const bool split = l >= a.nsplit;
-    const V *Al = (const V *)(W + a.fo.ahb_lo[t][l]);
-    v4f acc[MT];
+    float4 tp[2][NT][2];
+    auto tload = [&](int kk, float4 (&dst)[NT][2]) {
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) acc[mt] = v4f{0.f, 0.f, 0.f, 0.f};
+      for (int nt = 0; nt < NT; ++nt) {
+        dst[nt][0] = *(const float4 *)(tile_t<MT>(a.tbuf, tile0 + nt, NL, l, 2 * kk) + 4 * lane);
+        const int m1 = (2 * kk + 1 < MT) ? 2 * kk + 1 : 2 * kk;
+        dst[nt][1] = *(const float4 *)(tile_t<MT>(a.tbuf, tile0 + nt, NL, l, m1) + 4 * lane);
+      }
+    };
+    tload(0, tp[0]);
+    tload(1, tp[1]);
+    v4f acc[NT][MT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[nt][mt] = v4f{0.f, 0.f, 0.f, 0.f};
+    auto bx = [&](int nt, int kk, float (&x)[4], float (&y)[4]) {
+      const float4 t0 = tp[kk & 1][nt][0], t1 = tp[kk & 1][nt][1];
+      const float tv0[4] = {t0.x, t0.y, t0.z, t0.w}, tv1[4] = {t1.x, t1.y, t1.z, t1.w};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        x[v] = dY[nt][2 * kk][v] * (1.f - tv0[v] * tv0[v]);
+        y[v] = (2 * kk + 1 < MT) ? dY[nt][(2 * kk + 1 < MT) ? 2 * kk + 1 : 0][v] * (1.f - tv1[v] * tv1[v]) : 0.f;
+      }
+      if (nt == NT - 1 && kk + 2 < KSH) tload(kk + 2, tp[kk & 1]);
+    };
+    if (l >= a.nsplit) hidden_layer<P, MT, true>(stage, gc, nchunks, issue, bx, acc, lane);
+    else hidden_layer<P, MT, false>(stage, gc, nchunks, issue, bx, acc, lane);
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dY[nt][mt][r] += acc[nt][mt][r];
+  }
+  // dz_0 as the B operands of the first layer's backward
+  FSplit<P> Bz[NT][KSH];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
     for (int kk = 0; kk < KSH; ++kk) {
       float x[4], y[4];
-      {
-        const float4 t0 = *(const float4 *)(tile_t<MT>(a.tbuf, tile, NL, l, 2 * kk) + 4 * lane);
-        const float tv[4] = {t0.x, t0.y, t0.z, t0.w};
+      const float4 t0 = *(const float4 *)(tile_t<MT>(a.tbuf, tile0 + nt, NL, 0, 2 * kk) + 4 * lane);
+      const float tv0[4] = {t0.x, t0.y, t0.z, t0.w};
 #pragma unroll
-        for (int v = 0; v < 4; ++v) x[v] = dY[2 * kk][v] * (1.f - tv[v] * tv[v]);
-      }
+      for (int v = 0; v < 4; ++v) x[v] = dY[nt][2 * kk][v] * (1.f - tv0[v] * tv0[v]);
       if (2 * kk + 1 < MT) {
         const int m1 = (2 * kk + 1 < MT) ? 2 * kk + 1 : 0;
-        const float4 t1 = *(const float4 *)(tile_t<MT>(a.tbuf, tile, NL, l, m1) + 4 * lane);
-        const float tv[4] = {t1.x, t1.y, t1.z, t1.w};
+        const float4 t1 = *(const float4 *)(tile_t<MT>(a.tbuf, tile0 + nt, NL, 0, m1) + 4 * lane);
+        const float tv1[4] = {t1.x, t1.y, t1.z, t1.w};
 #pragma unroll
-        for (int v = 0; v < 4; ++v) y[v] = dY[m1][v] * (1.f - tv[v] * tv[v]);
+        for (int v = 0; v < 4; ++v) y[v] = dY[nt][m1][v] * (1.f - tv1[v] * tv1[v]);
       } else {
 #pragma unroll
         for (int v = 0; v < 4; ++v) y[v] = 0.f;
       }
-      const FSplit<P> B = fsplit<P>(x, y);
+      Bz[nt][kk] = fsplit<P>(x, y);
+    }
+  // dD one row a of D (16 features b) at a time, contracted with T:
+  //   dE/dT[a][c] = sum_b dD[a][b] T[b][c] + [a < M2] sum_a' dD[a'][a] T[a'][c]
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 *Ti[NT];
+  float4 *dTi[NT];
+  float4 Tq[NT][4], Ta[NT];
+  float dT2[NT][4][4];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const V ah = Ah[(mt * KSH + kk) * 64 + lane];
-        acc[mt] = FT<P>::mma(ah, B.hi, acc[mt]);
-        acc[mt] = FT<P>::mma(ah, B.lo, acc[mt]);
-        if (split) {
-          const V al = Al[(mt * KSH + kk) * 64 + lane];
-          acc[mt] = FT<P>::mma(al, B.hi, acc[mt]);
+  for (int nt = 0; nt < NT; ++nt) {
+    Ti[nt] = (const float4 *)(a.T32 + (int64_t)(ia[nt] < 0 ? 0 : ia[nt]) * M1 * 4);
+    dTi[nt] = (float4 *)(a.dT32 + (int64_t)(ia[nt] < 0 ? 0 : ia[nt]) * M1 * 4);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Tq[nt][r] = (ia[nt] >= 0 && 4 * g + r < M1) ? Ti[nt][4 * g + r] : z4;
+    Ta[nt] = ia[nt] >= 0 ? Ti[nt][0] : z4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) dT2[nt][r][c] = 0.f;
+  }
+  const float s = a.inv_nc;
+  for (int ch = 0; ch < n0c; ++ch, ++gc) {
+    if (gc + 1 < nchunks) issue(gc + 1, stage[(gc + 1) & 1]);
+    const unsigned char *buf = stage[gc & 1];
+    for (int q = 0; q < F0_CA; ++q) {
+      const int aa = ch * F0_CA + q;
+      if (aa >= M1) break;
+      v4f cc[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) cc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < KSH; ++kk) {
+        const V av = *(const V *)(buf + (q * KSH + kk) * 1024 + 16 * lane);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          cc[nt] = FT<P>::mma(av, Bz[nt][kk].hi, cc[nt]);
+          cc[nt] = FT<P>::mma(av, Bz[nt][kk].lo, cc[nt]);
+        }
+      }
+      // cc[nt][r] = dE/dD[row n][a = aa][b = 4 g + r]
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const v4f c = cc[nt];
+        const float4 ta = Ta[nt];
+        if (aa + 1 < M1) Ta[nt] = ia[nt] >= 0 ? Ti[nt][aa + 1] : z4;
+        float4 pc;
+        pc.x = c[0] * Tq[nt][0].x + c[1] * Tq[nt][1].x + c[2] * Tq[nt][2].x + c[3] * Tq[nt][3].x;
+        pc.y = c[0] * Tq[nt][0].y + c[1] * Tq[nt][1].y + c[2] * Tq[nt][2].y + c[3] * Tq[nt][3].y;
+        pc.z = c[0] * Tq[nt][0].z + c[1] * Tq[nt][1].z + c[2] * Tq[nt][2].z + c[3] * Tq[nt][3].z;
+        pc.w = c[0] * Tq[nt][0].w + c[1] * Tq[nt][1].w + c[2] * Tq[nt][2].w + c[3] * Tq[nt][3].w;
+        pc.x += __shfl_xor(pc.x, 16);
+        pc.y += __shfl_xor(pc.y, 16);
+        pc.z += __shfl_xor(pc.z, 16);
+        pc.w += __shfl_xor(pc.w, 16);
+        pc.x += __shfl_xor(pc.x, 32);
+        pc.y += __shfl_xor(pc.y, 32);
+        pc.z += __shfl_xor(pc.z, 32);
+        pc.w += __shfl_xor(pc.w, 32);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          dT2[nt][r][0] += c[r] * ta.x;
+          dT2[nt][r][1] += c[r] * ta.y;
+          dT2[nt][r][2] += c[r] * ta.z;
+          dT2[nt][r][3] += c[r] * ta.w;
+        }
+        if (g == 0) {
+          if (aa < 16) sh[wv][nt][n][aa] = pc;
+          else if (ia[nt] >= 0) dTi[nt][aa] = make_float4(pc.x * s, pc.y * s, pc.z * s, pc.w * s);
         }
       }
     }
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) dY[mt][r] += acc[mt][r];
+    dma_wait_all();
   }
-  // dz_0 as the B operands of the first layer's backward
-  FSplit<P> Bz[KSH];
 #pragma unroll
-  for (int kk = 0; kk < KSH; ++kk) {
-    float x[4], y[4];
-    const float4 t0 = *(const float4 *)(tile_t<MT>(a.tbuf, tile, NL, 0, 2 * kk) + 4 * lane);
-    const float tv0[4] = {t0.x, t0.y, t0.z, t0.w};
-#pragma unroll
-    for (int v = 0; v < 4; ++v) x[v] = dY[2 * kk][v] * (1.f - tv0[v] * tv0[v]);
-    if (2 * kk + 1 < MT) {
-      const int m1 = (2 * kk + 1 < MT) ? 2 * kk + 1 : 0;
-      const float4 t1 = *(const float4 *)(tile_t<MT>(a.tbuf, tile, NL, 0, m1) + 4 * lane);
-      const float tv1[4] = {t1.x, t1.y, t1.z, t1.w};
-#pragma unroll
-      for (int v = 0; v < 4; ++v) y[v] = dY[m1][v] * (1.f - tv1[v] * tv1[v]);
-    } else {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) y[v] = 0.f;
-    }
-    Bz[kk] = fsplit<P>(x, y);
-  }
-  // dD one row a of D (16 features b) at a time, contracted with T
-  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-  const float4 *Ti = (const float4 *)(a.T32 + (int64_t)(i < 0 ? 0 : i) * M1 * 4);
-  float4 Tq[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) Tq[r] = i >= 0 ? Ti[4 * g + r] : z4;
-  float dT2[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) dT2[r][c] = 0.f;
-  // A operands ([aa][kk] blocks of 1 KB) stream through LDS, F0_CA rows of
-  // D per chunk, the next chunk loading while this one is used
-  const unsigned char *A0 = W + a.fo.a0b[t];
-  float4 *dTi = (float4 *)(a.dT32 + (int64_t)(i < 0 ? 0 : i) * M1 * 4);
-  const float s = a.inv_nc;
-  const int nch = (M1 + F0_CA - 1) / F0_CA;
-  dma_blocks(A0, 0, (M1 < F0_CA ? M1 : F0_CA) * KSH, stage[0], wv, lane);
-  dma_wait_all();
-  for (int aa = 0; aa < M1; ++aa) {
-    const int ch = aa / F0_CA, q = aa % F0_CA;
-    if (q == 0 && ch + 1 < nch) {
-      const int a1 = (ch + 1) * F0_CA, na = (M1 - a1 < F0_CA) ? M1 - a1 : F0_CA;
-      dma_blocks(A0, (int64_t)a1 * KSH, na * KSH, stage[(ch + 1) & 1], wv, lane);
-    }
-    const unsigned char *buf = stage[ch & 1] + q * KSH * 1024;
-    v4f c = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kk = 0; kk < KSH; ++kk) {
-      const V av = *(const V *)(buf + kk * 1024 + 16 * lane);
-      c = FT<P>::mma(av, Bz[kk].hi, c);
-      c = FT<P>::mma(av, Bz[kk].lo, c);
-    }
-    // c[r] = dE/dD[row n][a = aa][b = 4 g + r]
-    const float4 Ta = i >= 0 ? Ti[aa] : z4;
-    float4 pc;
-    pc.x = c[0] * Tq[0].x + c[1] * Tq[1].x + c[2] * Tq[2].x + c[3] * Tq[3].x;
-    pc.y = c[0] * Tq[0].y + c[1] * Tq[1].y + c[2] * Tq[2].y + c[3] * Tq[3].y;
-    pc.z = c[0] * Tq[0].z + c[1] * Tq[1].z + c[2] * Tq[2].z + c[3] * Tq[3].z;
-    pc.w = c[0] * Tq[0].w + c[1] * Tq[1].w + c[2] * Tq[2].w + c[3] * Tq[3].w;
-    pc.x += __shfl_xor(pc.x, 16);
-    pc.y += __shfl_xor(pc.y, 16);
-    pc.z += __shfl_xor(pc.z, 16);
-    pc.w += __shfl_xor(pc.w, 16);
-    pc.x += __shfl_xor(pc.x, 32);
-    pc.y += __shfl_xor(pc.y, 32);
-    pc.z += __shfl_xor(pc.z, 32);
-    pc.w += __shfl_xor(pc.w, 32);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      dT2[r][0] += c[r] * Ta.x;
-      dT2[r][1] += c[r] * Ta.y;
-      dT2[r][2] += c[r] * Ta.z;
-      dT2[r][3] += c[r] * Ta.w;
-    }
-    if (g == 0) {
-      if (aa < 16) sh[wv][n][aa] = pc;
-      else if (i >= 0) dTi[aa] = make_float4(pc.x * s, pc.y * s, pc.z * s, pc.w * s);
-    }
-    if (q == F0_CA - 1 || aa == M1 - 1) dma_wait_all();
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (i >= 0) {
+  for (int nt = 0; nt < NT; ++nt) {
+    if (ia[nt] < 0) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int b = 4 * g + r;
       if (b < M1) {
-        const float4 q = sh[wv][n][b];
-        dTi[b] = make_float4((q.x + dT2[r][0]) * s, (q.y + dT2[r][1]) * s, (q.z + dT2[r][2]) * s,
-                             (q.w + dT2[r][3]) * s);
+        const float4 q = sh[wv][nt][n][b];
+        dTi[nt][b] = make_float4((q.x + dT2[nt][r][0]) * s, (q.y + dT2[nt][r][1]) * s, (q.z + dT2[nt][r][2]) * s,
+                                 (q.w + dT2[nt][r][3]) * s);
       }
     }
   }
@@ -420,8 +532,6 @@ __global__ void __launch_bounds__(64 * FIT_WAVES, 2) k_fit_bwd(FitMixArgs a) {
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-constexpr int FIT_MT = 15;  // hidden width 240
-
 bool fit_mix_supported(const Dims &d, const char **why) {
   const int H = d.fw[1];
   for (int l = 1; l <= d.n_fit; ++l)
@@ -516,11 +626,14 @@ void fit_mix_pack(const Dims &d, int prec, int nsplit, const double *const *W, c
         const int k = 16 * mt + (lane & 15), o = kslot(kk, lane >> 4, v);
         return (o < H && k < H) ? Wt[l][(size_t)k * H + o] : 0.0;
       };
-      fo.ahf[t][l] = put_image(buf, MT, KSH, prec, false, fwd);
-      fo.ahb[t][l] = put_image(buf, MT, KSH, prec, false, bwd);
+      // blocks in [kk][mt] order: a staged chunk of k-steps is contiguous
+      auto fwd_km = [&](int kk, int mt, int lane, int v) { return fwd(mt, kk, lane, v); };
+      auto bwd_km = [&](int kk, int mt, int lane, int v) { return bwd(mt, kk, lane, v); };
+      fo.ahf[t][l] = put_image(buf, KSH, MT, prec, false, fwd_km);
+      fo.ahb[t][l] = put_image(buf, KSH, MT, prec, false, bwd_km);
       if (l >= nsplit) {
-        fo.ahf_lo[t][l] = put_image(buf, MT, KSH, prec, true, fwd);
-        fo.ahb_lo[t][l] = put_image(buf, MT, KSH, prec, true, bwd);
+        fo.ahf_lo[t][l] = put_image(buf, KSH, MT, prec, true, fwd_km);
+        fo.ahb_lo[t][l] = put_image(buf, KSH, MT, prec, true, bwd_km);
       } else {
         fo.ahf_lo[t][l] = fo.ahf[t][l];
         fo.ahb_lo[t][l] = fo.ahb[t][l];
@@ -544,8 +657,7 @@ size_t fit_mix_tbuf_floats(const Dims &d, int64_t rows) {
 }
 
 void launch_fit_mix(hipStream_t s, const FitMixArgs &a, int pass) {
-  const int64_t tiles = (a.rows + 15) / 16;
-  const unsigned grid = (unsigned)((tiles + FIT_WAVES - 1) / FIT_WAVES);
+  const unsigned grid = (unsigned)((a.rows + FIT_ROWS - 1) / FIT_ROWS);
   if (grid == 0) return;
   if (pass == 1) {
     if (a.prec == 0) hipLaunchKernelGGL((k_fit_fwd<0, FIT_MT>), dim3(grid), dim3(64 * FIT_WAVES), 0, s, a);
