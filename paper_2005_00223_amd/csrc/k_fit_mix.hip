@@ -88,8 +88,8 @@ __device__ inline int rtype(const int32_t *ts, int ntypes, int64_t r0) {
   return t;
 }
 
-constexpr int FIT_WAVES = 4;
-constexpr int FIT_NT = 2;                           // 16-row tiles per wave
+constexpr int FIT_WAVES = 8;
+constexpr int FIT_NT = 1;                           // 16-row tiles per wave
 constexpr int FIT_ROWS = 16 * FIT_NT * FIT_WAVES;   // rows per workgroup
 constexpr int FIT_MT = 15;                          // hidden width 240 = 15 output tiles
 constexpr int FIT_KSH = (FIT_MT + 1) / 2;           // k-steps of a hidden layer
