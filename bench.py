@@ -47,34 +47,50 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic(spec, n_atoms, n_pairs, emb=None):
+def algorithmic(spec, n_atoms, n_pairs, emb=None, affine=False, mixed=True):
     """Algorithmic work per evaluation, by kernel (no recompute, no padding):
     flops for the network kernels, bytes for the list/env kernels.  `emb`
-    overrides the embedding widths (the student's 16-32-100)."""
+    overrides the embedding widths (the student's 16-32-100); `affine`: the
+    last embedding layer is affine, so T = W3^T (sum h2 R^T) + b3 (sum R)^T
+    and its products move from per pair to per atom."""
     emb = (1,) + tuple(emb if emb is not None else spec.emb)
-    layer_macs = sum(emb[l] * emb[l + 1] for l in range(len(emb) - 1))
     M1, M2 = spec.M1, spec.M2
     fw = (M1 * M2,) + tuple(spec.fit) + (1,)
     fit_macs = sum(fw[l] * fw[l + 1] for l in range(len(fw) - 1))
-    return {
+    if affine:
+        W1, W2 = emb[1], emb[2]
+        hidden = W1 + W1 * W2          # layers 1 and 2 per pair
+        # per pair: h2 R^T (4 W2); per atom: W3^T H (4 W2 M1), b3 sum R (4 M1), D (4 M1 M2)
+        e_fwd = 2.0 * n_pairs * (hidden + 4 * W2) + 2.0 * n_atoms * (4 * W2 * M1 + 4 * M1 + 4 * M1 * M2)
+        # per pair: h, h' through layers 1-2 (2 hidden), M^T h2 and M^T h2' (8 W2);
+        # per atom: M = W3 dT (4 W2 M1), b3^T dT (4 M1), dT from dD (8 M1 M2)
+        e_bwd = 2.0 * n_pairs * (2 * hidden + 8 * W2) + 2.0 * n_atoms * (4 * W2 * M1 + 4 * M1 + 8 * M1 * M2)
+    else:
+        layer_macs = sum(emb[l] * emb[l + 1] for l in range(len(emb) - 1))
         # G(s) forward + T += G R^T per pair, D = T T<^T per atom
-        "embed_fwd": 2.0 * n_pairs * (layer_macs + 4 * M1) + 2.0 * n_atoms * (4 * M1 * M2),
+        e_fwd = 2.0 * n_pairs * (layer_macs + 4 * M1) + 2.0 * n_atoms * (4 * M1 * M2)
         # dE/dR = G^T dT, dE/dG = dT R, reverse through the layers per pair; dT per atom
-        "embed_bwd": 2.0 * n_pairs * (layer_macs + 8 * M1) + 2.0 * n_atoms * (8 * M1 * M2),
+        e_bwd = 2.0 * n_pairs * (layer_macs + 8 * M1) + 2.0 * n_atoms * (8 * M1 * M2)
+    return {
+        "embed_fwd": e_fwd,
+        "embed_bwd": e_bwd,
         "fit": 2.0 * n_atoms * 2 * fit_macs,
-        # bytes: per real slot nlist 4 B + neighbour position 32 B in, R and (d, r) 64 B out
-        "env": n_pairs * (4 + 32 + 64.0) + n_atoms * (32 + 4 * spec.ntypes),
+        # bytes: per real slot nlist 4 B + neighbour position 32 B in, R (FP32 in
+        # mixed precision: 16 B, else 32 B) and (d, r) 32 B out
+        "env": n_pairs * (4 + 32 + (16 if mixed else 32) + 32.0) + n_atoms * (32 + 4 * spec.ntypes),
     }
 
 
 # kernel name in the profiles and the sources whose hash the PMC summary records
 PHASE_KERNEL = {
-    ("embed_bwd", "fp16", True): ("k_embed_bwd_mix<16, 32, 100, 1, 0>", "k_embed_mix"),
-    ("embed_fwd", "fp16", True): ("k_embed_fwd_mix<16, 32, 100, 1, 0>", "k_embed_mix"),
-    ("embed_bwd", "fp16", False): ("k_embed_bwd_mix<25, 50, 100, 0, 0>", "k_embed_mix"),
-    ("embed_fwd", "fp16", False): ("k_embed_fwd_mix<25, 50, 100, 0, 0>", "k_embed_mix"),
-    ("format", "fp16", True): ("k_format", "k_nlist"),
-    ("env", "fp16", True): ("k_env", "k_env"),
+    ("embed_bwd", "fp16", True): (("k_embed_bwd_cells<16, 32, 100, 0>", "k_cell_gather"), "k_embed_mix"),
+    ("embed_fwd", "fp16", True): (("k_embed_fwd_lin<16, 32, 100, 0>",), "k_embed_mix"),
+    ("embed_bwd", "fp16", False): (("k_embed_bwd_mix<25, 50, 100, 0, 0>",), "k_embed_mix"),
+    ("embed_fwd", "fp16", False): (("k_embed_fwd_mix<25, 50, 100, 0, 0>",), "k_embed_mix"),
+    ("fit", "fp16", True): (("k_fit_fwd<0, 15>", "k_fit_bwd<0, 15>"), "k_fit_mix"),
+    ("fit", "fp16", False): (("k_fit_fwd<0, 15>", "k_fit_bwd<0, 15>"), "k_fit_mix"),
+    ("format", "fp16", True): (("k_format",), "k_nlist"),
+    ("env", "fp16", True): (("k_env<HIP_vector_type<float, 4u> >",), "k_env"),
 }
 HASH_FILES = {"k_embed_mix": ("k_embed_mix.hip", "dp_mix.h", "dp_internal.h"),
               "k_fit_mix": ("k_fit_mix.hip", "dp_mix.h", "dp_internal.h"),
@@ -82,26 +98,30 @@ HASH_FILES = {"k_embed_mix": ("k_embed_mix.hip", "dp_mix.h", "dp_internal.h"),
 
 
 def pmc_traffic(phase, precision, student):
-    """HBM bytes per launch of the phase's kernel from the committed
-    rocprofv3 PMC summary (FETCH_SIZE and WRITE_SIZE scaled by the copy
-    calibration recorded there), or None when there is no summary or the
-    kernel's sources changed after the counters were taken."""
+    """HBM bytes per evaluation of the phase's kernels from the committed
+    rocprofv3 PMC summary (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by
+    the copy calibration recorded there, summed over the phase's kernels),
+    or None when there is no summary or the sources changed after the
+    counters were taken."""
     import hashlib
     key = PHASE_KERNEL.get((phase, precision, student))
     path = os.path.join(HERE, "profiles", "cu500k_fp16_student_pmc.txt")
     if key is None or not os.path.exists(path):
         return None
-    name, src = key
+    names, src = key
     text = open(path).read()
     h = hashlib.sha256()
     for f in HASH_FILES[src]:
         h.update(open(os.path.join(HERE, "paper_2005_00223_amd", "csrc", f), "rb").read())
     if f"# source-hash {src}: {h.hexdigest()[:16]}" not in text:
         return None
-    for line in text.splitlines():
-        if line.startswith("dpk::" + name + " "):
-            return float(line.split()[-1]) * 1e9
-    return None
+    total = 0.0
+    for name in names:
+        rows = [ln for ln in text.splitlines() if ln.startswith("dpk::" + name + " ")]
+        if not rows:
+            return None
+        total += float(rows[0].split()[-1]) * 1e9
+    return total
 
 
 def cpu_baseline(w, blob, seconds, log_fn):
@@ -228,7 +248,8 @@ def main():
     _, nr = m.nlist(n, spec.nnei, spec.ntypes, with_list=False)
     n_pairs = float(nr.sum().item())
     used_student = student and st["teacher_fallbacks"] == 0
-    alg = algorithmic(spec, n, n_pairs, emb=(16, 32, spec.M1) if used_student else None)
+    alg = algorithmic(spec, n, n_pairs, emb=(16, 32, spec.M1) if used_student else None, affine=used_student,
+                      mixed=args.precision != "fp64")
     kern = max(("format", "env", "embed_fwd", "fit", "embed_bwd"), key=lambda k: phases[k])
     thn = th.cpu().numpy()
     drift = float((thn[-1, 3] - thn[0, 3]) / n) if len(thn) > 1 else 0.0
