@@ -1357,9 +1357,11 @@ int dp_get_nlist(dp_ctx *c, int32_t *nlist, int32_t *nreal) {
   if (!c || (!nlist && !nreal)) return DP_E_ARG;
   if (!c->has_model || c->ws.n_cap < 0) return fail(c, DP_E_NOMODEL, "no evaluation yet");
   const int64_t n = c->last_n;
-  if (nlist)
+  if (nlist) {
+    launch_pad_nlist(c->stream, n, c->dims, c->ws.nreal, c->ws.nlist);
     HIPCHK(c, hipMemcpyAsync(nlist, c->ws.nlist, sizeof(int32_t) * n * c->dims.nnei, hipMemcpyDeviceToDevice,
                              c->stream));
+  }
   if (nreal)
     HIPCHK(c, hipMemcpyAsync(nreal, c->ws.nreal, sizeof(int32_t) * n * c->dims.ntypes, hipMemcpyDeviceToDevice,
                              c->stream));

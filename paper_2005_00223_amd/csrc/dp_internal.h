@@ -89,6 +89,9 @@ void launch_fill_u32(hipStream_t s, uint32_t *p, int64_t n, uint32_t v);
 void launch_format(hipStream_t s, int64_t n, const double4 *xw, const Dims &d, const double *L, const int32_t *cand,
                    const int32_t *cand_n, int cand_cap, int32_t *nlist, int32_t *nreal,
                    unsigned long long *overflow, int32_t *max_real, uint32_t *flags);
+// -1 padding of the formatted list past each type's real count (the
+// formatting kernel writes the real slots only)
+void launch_pad_nlist(hipStream_t s, int64_t n, const Dims &d, const int32_t *nreal, int32_t *nlist);
 void launch_max_disp(hipStream_t s, int64_t n, const double4 *xw, const double4 *xref, const double *L,
                      double half_skin, uint32_t *flags);
 void launch_copy_ref(hipStream_t s, int64_t n, const double4 *xw, double4 *xref, const uint32_t *cond);

@@ -336,14 +336,17 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
   __shared__ int16_t next[FMT_WAVES][FMT_CAP];
   __shared__ int32_t head[FMT_WAVES][MAXT * FMT_NB];
   __shared__ int32_t bstart[FMT_WAVES][MAXT * FMT_NB];
-  __shared__ int32_t kcount[FMT_WAVES];
-  __shared__ int32_t tcnt[FMT_WAVES][MAXT];
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int64_t i = (int64_t)blockIdx.x * FMT_WAVES + wv;
   if (i >= n) return;
   const int nb_tot = d.ntypes * FMT_NB;
-  if (lane == 0) kcount[wv] = 0;
-  if (lane < MAXT) tcnt[wv][lane] = 0;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  // keys stored and neighbours within rc per type, wave-uniform: ballot
+  // prefix counts instead of atomics on one LDS address
+  int kc = 0;
+  int tc[MAXT];
+#pragma unroll
+  for (int t = 0; t < MAXT; ++t) tc[t] = 0;
   for (int b = lane; b < nb_tot; b += 64) {
     head[wv][b] = -1;
     bstart[wv][b] = 0;
@@ -368,34 +371,37 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
     for (int u = 0; u < FMT_BATCH; ++u) pb[u] = jb[u] >= 0 ? xw[jb[u]] : p;
 #pragma unroll
     for (int u = 0; u < FMT_BATCH; ++u) {
-    const int32_t j = jb[u];
-    if (j < 0) continue;
-    const double4 pj = pb[u];
-    double dx = min_image(pj.x - p.x, L0);
-    double dy = min_image(pj.y - p.y, L1);
-    double dz = min_image(pj.z - p.z, L2);
-    double r2 = dx * dx + dy * dy;
-    r2 = r2 + dz * dz;
-    double r = sqrt(r2);
-    if (r <= d.rcut) {
-      unsigned long long qd = (unsigned long long)floor(r * 1e8);
-      int tj = (int)pj.w;
-      unsigned long long key = ((unsigned long long)tj << 58) | (qd << 26) | (unsigned long long)j;
-      int slot = atomicAdd(&kcount[wv], 1);
-      if (slot < FMT_CAP) {
+      const int32_t j = jb[u];
+      const double4 pj = pb[u];  // = p for lanes without a candidate (r = 0, not kept)
+      double dx = min_image(pj.x - p.x, L0);
+      double dy = min_image(pj.y - p.y, L1);
+      double dz = min_image(pj.z - p.z, L2);
+      double r2 = dx * dx + dy * dy;
+      r2 = r2 + dz * dz;
+      double r = sqrt(r2);
+      const bool keep = j >= 0 && r <= d.rcut;
+      const unsigned long long m = __ballot(keep);
+      if (m == 0ull) continue;
+      const int tj = (int)pj.w;
+      const int slot = kc + __popcll(m & below);
+      kc += __popcll(m);
+#pragma unroll
+      for (int t = 0; t < MAXT; ++t)
+        if (t < d.ntypes) tc[t] += __popcll(__ballot(keep && tj == t));
+      if (keep && slot < FMT_CAP) {
+        unsigned long long qd = (unsigned long long)floor(r * 1e8);
+        unsigned long long key = ((unsigned long long)tj << 58) | (qd << 26) | (unsigned long long)j;
         keys[wv][slot] = key;
         const int b = tj * FMT_NB + (int)((qd * FMT_NB) / qlim);
         next[wv][slot] = (int16_t)atomicExch(&head[wv][b], slot);
         atomicAdd(&bstart[wv][b], 1);
       }
-      atomicAdd(&tcnt[wv][tj], 1);
-    }
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  int k = kcount[wv];
+  int k = kc;
   if (k > FMT_CAP) {
     if (lane == 0) atomicOr(flags, FLAG_KEY_CAP);
     k = FMT_CAP;
@@ -425,11 +431,12 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
   int tstart[MAXT], treal[MAXT];
   {
     int run = 0;
-    for (int t = 0; t < d.ntypes; ++t) {
-      int c = tcnt[wv][t];
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t) {
+      const int c = t < d.ntypes ? tc[t] : 0;
       tstart[t] = run;
       run += c;
-      treal[t] = c < d.sel[t] ? c : d.sel[t];
+      treal[t] = t < d.ntypes ? (c < d.sel[t] ? c : d.sel[t]) : 0;
     }
   }
   int32_t *row = nlist + i * (int64_t)d.nnei;
@@ -440,19 +447,25 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
     const int b = t * FMT_NB + (int)((((key >> 26) & 0xffffffffull) * FMT_NB) / qlim);
     int rank = bstart[wv][b];
     for (int m = head[wv][b]; m >= 0; m = next[wv][m]) rank += (keys[wv][m] < key) ? 1 : 0;
-    int pos = rank - tstart[t];
+    int ts = 0;
+#pragma unroll
+    for (int u = 0; u < MAXT; ++u)
+      if (u == t) ts = tstart[u];
+    int pos = rank - ts;
     // pos < 0 can only happen when the key buffer overflowed (flagged above)
     if (pos >= 0 && pos < d.sel[t]) row[d.off[t] + pos] = (int32_t)(key & ((1ull << 26) - 1ull));
   }
-  // padding
-  for (int sl = lane; sl < d.nnei; sl += 64) {
-    int t = 0;
-    while (t + 1 < d.ntypes && sl >= d.off[t + 1]) ++t;
-    if (sl - d.off[t] >= treal[t]) row[sl] = -1;
-  }
+  // only the real slots are written; k_pad_nlist fills the -1 padding when
+  // the list is copied out (every device consumer stops at the real count)
   if (lane < d.ntypes) {
-    int c = tcnt[wv][lane];
-    nreal[i * d.ntypes + lane] = treal[lane];
+    int c = 0, cr = 0;
+#pragma unroll
+    for (int t = 0; t < MAXT; ++t)
+      if (t == lane) {
+        c = tc[t];
+        cr = treal[t];
+      }
+    nreal[i * d.ntypes + lane] = cr;
     // the maximum only grows during the launch, so a stale read can only
     // cost an extra atomic; skipping the rest keeps 500k waves from
     // serialising on one address
@@ -468,6 +481,22 @@ void launch_format(hipStream_t s, int64_t n, const double4 *xw, const Dims &d, c
   if (n <= 0) return;
   hipLaunchKernelGGL(k_format, dim3((unsigned)((n + FMT_WAVES - 1) / FMT_WAVES)), dim3(64 * FMT_WAVES), 0, s, n, xw, d,
                      L[0], L[1], L[2], cand, cand_n, cand_cap, nlist, nreal, overflow, max_real, flags);
+}
+
+// -1 in every slot past a type's real count
+__global__ void k_pad_nlist(int64_t n, Dims d, const int32_t *__restrict__ nreal, int32_t *__restrict__ nlist) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  for (int t = 0; t < d.ntypes; ++t) {
+    const int r = nreal[i * d.ntypes + t];
+    for (int sl = r + lane; sl < d.sel[t]; sl += 64) nlist[i * (int64_t)d.nnei + d.off[t] + sl] = -1;
+  }
+}
+
+void launch_pad_nlist(hipStream_t s, int64_t n, const Dims &d, const int32_t *nreal, int32_t *nlist) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_pad_nlist, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, d, nreal, nlist);
 }
 
 // ---------------------------------------------------------------------------
