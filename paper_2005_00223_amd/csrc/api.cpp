@@ -152,7 +152,8 @@ struct Workspace {
 // Student training state (buffers for one Adam batch per net).
 struct Student {
   int nets = 0, M1 = 0, np = 0;
-  int64_t cap = 0;  // samples per net the buffers hold
+  int64_t cap = 0;       // samples per net of one batch the per-batch buffers hold
+  int64_t cap_draw = 0;  // samples per net one draw (several batches) can hold
   void *base = nullptr;
   float *params = nullptr, *m = nullptr, *v = nullptr, *gpart = nullptr, *wt = nullptr, *gout = nullptr;
   double *lpart = nullptr, *s = nullptr, *G = nullptr, *lspart = nullptr, *X = nullptr, *chk = nullptr,
@@ -877,13 +878,21 @@ __global__ void k_reset_status(DevStatus *st, uint32_t flags) {
 constexpr int64_t ST_Q_LS = 1ll << 36;     // first sample index of the refit
 constexpr int64_t ST_Q_CHECK = 1ll << 37;  // first sample index of the held-out check
 constexpr int64_t ST_CHECK_N = 4096;
+constexpr int64_t ST_DRAW_MAX = 64;         // batches drawn (samples + teacher targets) per launch, at most
+constexpr int64_t ST_DRAW_SAMPLES = 262144; // and at most this many samples per net
+
+// samples per net one draw holds for batches of `batch`
+int64_t draw_capacity(int64_t batch) {
+  return std::max<int64_t>(ST_CHECK_N, std::max<int64_t>(batch, std::min<int64_t>(batch * ST_DRAW_MAX, ST_DRAW_SAMPLES)));
+}
 
 int ensure_student(dp_ctx *c, int64_t batch) {
   const int nets = c->dims.ntypes * c->dims.ntypes;
   const int M1 = c->dims.M1;
   const StudentLayout L = student_layout(M1);
   Student *st = c->st;
-  if (st && st->cap >= batch && st->nets == nets && st->M1 == M1) return DP_OK;
+  if (st && st->cap >= batch && st->cap_draw >= draw_capacity(batch) && st->nets == nets && st->M1 == M1)
+    return DP_OK;
   std::vector<float> keep;
   bool had = false;
   int64_t t = 0;
@@ -900,7 +909,8 @@ int ensure_student(dp_ctx *c, int64_t batch) {
   st->M1 = M1;
   st->np = L.np;
   st->cap = std::max<int64_t>(batch, ST_CHECK_N);
-  const int64_t cap = st->cap, nblk = cap / 64, NE = (int64_t)SNF * SNF + (int64_t)SNF * M1;
+  st->cap_draw = draw_capacity(batch);
+  const int64_t cap = st->cap, capd = st->cap_draw, nblk = cap / 64, NE = (int64_t)SNF * SNF + (int64_t)SNF * M1;
   std::vector<std::pair<void **, size_t>> plan;
   auto add = [&](void **p, size_t bytes) { plan.push_back({p, bytes}); };
   add((void **)&st->params, sizeof(float) * nets * L.np);
@@ -909,9 +919,9 @@ int ensure_student(dp_ctx *c, int64_t batch) {
   add((void **)&st->gout, sizeof(float) * nets * L.np);
   add((void **)&st->gpart, sizeof(float) * nets * nblk * L.np);
   add((void **)&st->lpart, sizeof(double) * nets * nblk * 2);
-  add((void **)&st->s, sizeof(double) * nets * cap);
-  add((void **)&st->wt, sizeof(float) * nets * cap);
-  add((void **)&st->G, sizeof(double) * nets * cap * M1);
+  add((void **)&st->s, sizeof(double) * nets * capd);
+  add((void **)&st->wt, sizeof(float) * nets * capd);
+  add((void **)&st->G, sizeof(double) * nets * capd * M1);
   add((void **)&st->lspart, sizeof(double) * nets * st_ls_blocks() * NE);
   add((void **)&st->X, sizeof(double) * nets * SNF * M1);
   add((void **)&st->chk, sizeof(double) * nets * nblk * 2);
@@ -939,7 +949,9 @@ int ensure_student(dp_ctx *c, int64_t batch) {
 
 bool lists_ready(const dp_ctx *c) { return c->has_model && c->ws.n_cap >= 0 && c->last_n > 0; }
 
-void st_draw(dp_ctx *c, uint64_t seed, int64_t q0, int64_t batch) {
+// nb consecutive batches of samples (indices q0 .. q0 + nb * batch - 1 per
+// net) and their teacher targets, laid out [nb][nets][batch]
+void st_draw(dp_ctx *c, uint64_t seed, int64_t q0, int64_t batch, int nb = 1) {
   Workspace &w = c->ws;
   Student *st = c->st;
   StSampleArgs sa{};
@@ -952,6 +964,7 @@ void st_draw(dp_ctx *c, uint64_t seed, int64_t q0, int64_t batch) {
   sa.seed = seed;
   sa.q0 = q0;
   sa.batch = (int)batch;
+  sa.nb = nb;
   sa.s = st->s;
   sa.wt = st->wt;
   launch_st_sample(c->stream, sa);
@@ -960,21 +973,24 @@ void st_draw(dp_ctx *c, uint64_t seed, int64_t q0, int64_t batch) {
   ta.eo = c->en[0].eo;
   ta.ew = c->en[0].d_emb;
   ta.batch = (int)batch;
+  ta.nb = nb;
   ta.s = st->s;
   ta.G = st->G;
   launch_st_teacher(c->stream, ta);
 }
 
-void st_grad(dp_ctx *c, int64_t batch) {
+// gradient of batch k of the last draw
+void st_grad(dp_ctx *c, int64_t batch, int k = 0) {
   Student *st = c->st;
+  const int64_t o = (int64_t)k * st->nets * batch;
   StGradArgs ga{};
   ga.M1 = st->M1;
   ga.nets = st->nets;
   ga.batch = (int)batch;
   ga.params = st->params;
-  ga.s = st->s;
-  ga.wt = st->wt;
-  ga.G = st->G;
+  ga.s = st->s + o;
+  ga.wt = st->wt + o;
+  ga.G = st->G + o * st->M1;
   ga.gpart = st->gpart;
   ga.lpart = st->lpart;
   launch_st_grad(c->stream, ga);
@@ -1558,11 +1574,16 @@ int dp_student_train(dp_ctx *c, const dp_student_cfg *cfg, double *fit_rmse) {
     st->have_params = true;
     st->t = 0;
   }
-  for (int64_t k = 0; k < g.adam_steps; ++k) {
-    st_draw(c, g.seed, st->t * g.batch, g.batch);
-    st_grad(c, g.batch);
-    st_adam(c, g.batch, g, nullptr);
-    st->t += 1;
+  const int64_t nbmax = st->cap_draw / g.batch;
+  for (int64_t k0 = 0; k0 < g.adam_steps; k0 += nbmax) {
+    // batches t .. t + nb - 1 (sample indices t * batch ...) in one draw
+    const int nb = (int)std::min<int64_t>(nbmax, g.adam_steps - k0);
+    st_draw(c, g.seed, st->t * g.batch, g.batch, nb);
+    for (int k = 0; k < nb; ++k) {
+      st_grad(c, g.batch, k);
+      st_adam(c, g.batch, g, nullptr);
+      st->t += 1;
+    }
   }
   HIPCHK(c, hipGetLastError());
   double result = 0.0;
@@ -1576,20 +1597,25 @@ int dp_student_train(dp_ctx *c, const dp_student_cfg *cfg, double *fit_rmse) {
     const int quant = quant_of(c);
     const int NE = SNF * SNF + SNF * st->M1;
     launch_fill_u32(s, (uint32_t *)st->lspart, (int64_t)st->nets * st_ls_blocks() * NE * 2, 0u);
-    for (int64_t q = 0; q < g.ls_samples; q += g.batch) {
-      st_draw(c, g.seed, ST_Q_LS + q, g.batch);
-      StLsArgs la{};
-      la.M1 = st->M1;
-      la.nets = st->nets;
-      la.batch = (int)g.batch;
-      la.nblk = st_ls_blocks();
-      la.params = st->params;
-      la.quant = quant;
-      la.s = st->s;
-      la.wt = st->wt;
-      la.G = st->G;
-      la.part = st->lspart;
-      launch_st_ls(s, la);
+    const int64_t nls = g.ls_samples / g.batch;
+    for (int64_t b0 = 0; b0 < nls; b0 += nbmax) {
+      const int nb = (int)std::min<int64_t>(nbmax, nls - b0);
+      st_draw(c, g.seed, ST_Q_LS + b0 * g.batch, g.batch, nb);
+      for (int k = 0; k < nb; ++k) {
+        const int64_t o = (int64_t)k * st->nets * g.batch;
+        StLsArgs la{};
+        la.M1 = st->M1;
+        la.nets = st->nets;
+        la.batch = (int)g.batch;
+        la.nblk = st_ls_blocks();
+        la.params = st->params;
+        la.quant = quant;
+        la.s = st->s + o;
+        la.wt = st->wt + o;
+        la.G = st->G + o * st->M1;
+        la.part = st->lspart;
+        launch_st_ls(s, la);
+      }
     }
     StSolveArgs va{};
     va.M1 = st->M1;

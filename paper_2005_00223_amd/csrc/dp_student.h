@@ -49,10 +49,11 @@ struct StSampleArgs {
   const int32_t *nreal;        // [natoms][ntypes]
   const double4 *dr;           // [natoms][nnei], .w = r (s = sw(r) / r is recomputed)
   uint64_t seed;
-  int64_t q0;                  // index of the batch's first sample
-  int batch;                   // samples per net
-  double *s;                   // [nets][batch]
-  float *wt;                   // [nets][batch] 1 = drawn, 0 = no neighbour found
+  int64_t q0;                  // index of the first batch's first sample
+  int batch;                   // samples per net and batch
+  int nb;                      // consecutive batches drawn (sample indices q0 .. q0 + nb * batch - 1)
+  double *s;                   // [nb][nets][batch]
+  float *wt;                   // [nb][nets][batch] 1 = drawn, 0 = no neighbour found
 };
 void launch_st_sample(hipStream_t st, const StSampleArgs &a);
 
@@ -61,8 +62,9 @@ struct StTeacherArgs {
   EmbOffsets eo;
   const double *ew;            // teacher FP64 padded weights
   int batch;
-  const double *s;             // [nets][batch]
-  double *G;                   // [nets][batch][M1]
+  int nb;                      // batches, as drawn by the sampler
+  const double *s;             // [nb][nets][batch]
+  double *G;                   // [nb][nets][batch][M1]
 };
 void launch_st_teacher(hipStream_t st, const StTeacherArgs &a);
 

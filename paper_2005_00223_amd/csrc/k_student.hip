@@ -29,6 +29,7 @@ namespace dpk {
 __global__ void k_st_sample(StSampleArgs a) {
   const int net = blockIdx.y;
   const int T = a.d.ntypes;
+  const int64_t nbk = blockIdx.z;  // batch of the draw
   const int t = net / T, u = net % T;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= a.batch) return;
@@ -38,7 +39,7 @@ __global__ void k_st_sample(StSampleArgs a) {
   float w = 0.f;
   if (count > 0 && selu > 0) {
     for (int at = 0; at < ST_ATTEMPTS; ++at) {
-      const uint64_t x = sm64(a.seed, st_ctr(net, a.q0 + q, at));
+      const uint64_t x = sm64(a.seed, st_ctr(net, a.q0 + nbk * a.batch + q, at));
       const int64_t k = (int64_t)(((x >> 32) * (uint64_t)count) >> 32);
       const int64_t slot = (int64_t)(((x & 0xffffffffull) * (uint64_t)selu) >> 32);
       const int i = a.atom_of_pos[a.type_start[t] + k];
@@ -50,13 +51,14 @@ __global__ void k_st_sample(StSampleArgs a) {
       }
     }
   }
-  a.s[(int64_t)net * a.batch + q] = s;
-  a.wt[(int64_t)net * a.batch + q] = w;
+  const int64_t o = (nbk * T * T + net) * a.batch + q;
+  a.s[o] = s;
+  a.wt[o] = w;
 }
 
 void launch_st_sample(hipStream_t st, const StSampleArgs &a) {
   const int nets = a.d.ntypes * a.d.ntypes;
-  hipLaunchKernelGGL(k_st_sample, dim3((a.batch + 255) / 256, nets), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_st_sample, dim3((a.batch + 255) / 256, nets, a.nb), dim3(256), 0, st, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -73,10 +75,11 @@ __global__ void __launch_bounds__(256) k_st_teacher(StTeacherArgs a) {
   const int t = net / d.ntypes, u = net % d.ntypes;
   const int j = threadIdx.x & 15, ql = threadIdx.x >> 4;
   const int q = blockIdx.x * TCH_SAMPLES + ql;
+  const int64_t row = ((int64_t)blockIdx.z * d.ntypes * d.ntypes + net) * a.batch;  // first sample of (batch, net)
   int wmax = 1;
   for (int l = 1; l <= d.n_emb; ++l) wmax = d.ew[l] > wmax ? d.ew[l] : wmax;
   double *hA = tsh + ql * wmax, *hB = tsh + (TCH_SAMPLES + ql) * wmax;
-  const double s = q < a.batch ? a.s[(int64_t)net * a.batch + q] : 0.0;
+  const double s = q < a.batch ? a.s[row + q] : 0.0;
   {
     const double *W0 = a.ew + a.eo.w[t][u][0], *b0 = a.ew + a.eo.b[t][u][0];
     const int out = d.ew[1];
@@ -107,7 +110,7 @@ __global__ void __launch_bounds__(256) k_st_teacher(StTeacherArgs a) {
     hB = tmp;
   }
   if (q < a.batch) {
-    double *G = a.G + ((int64_t)net * a.batch + q) * d.M1;
+    double *G = a.G + (row + q) * d.M1;
     for (int o = j; o < d.M1; o += 16) G[o] = hA[o];
   }
 }
@@ -117,7 +120,8 @@ void launch_st_teacher(hipStream_t st, const StTeacherArgs &a) {
   for (int l = 1; l <= a.d.n_emb; ++l) wmax = a.d.ew[l] > wmax ? a.d.ew[l] : wmax;
   const size_t shm = (size_t)2 * TCH_SAMPLES * wmax * sizeof(double);
   const int nets = a.d.ntypes * a.d.ntypes;
-  hipLaunchKernelGGL(k_st_teacher, dim3((a.batch + TCH_SAMPLES - 1) / TCH_SAMPLES, nets), dim3(256), shm, st, a);
+  hipLaunchKernelGGL(k_st_teacher, dim3((a.batch + TCH_SAMPLES - 1) / TCH_SAMPLES, nets, a.nb), dim3(256), shm, st,
+                     a);
 }
 
 // ---------------------------------------------------------------------------
