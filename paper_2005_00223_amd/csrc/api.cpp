@@ -189,6 +189,7 @@ struct dp_ctx {
   EmbNets en[2];                    // [0] teacher, [1] student
   int active = 0;                   // embedding set used by evaluations
   CellGrid cgrid{};                 // grid of the last cell-list build
+  double box_L[3] = {0.0, 0.0, 0.0};  // box lengths of the last lists
   bool cgrid_ok = false;
   int scatter = 0;                  // dp_set_force_scatter mode
   HostModel shm;                    // student (embedding part; fitting = teacher's)
@@ -278,7 +279,7 @@ int ensure_ws(dp_ctx *c, int64_t n, int64_t ncell, int cand_cap) {
   add((void **)&w.type_start, 4 * (MAXT + 1));
   if (mixed) add((void **)&w.rt32, sizeof(float4) * nn * d.nnei);
   else add((void **)&w.rt, sizeof(double4) * nn * d.nnei);
-  add((void **)&w.dr, sizeof(double4) * nn * d.nnei);
+  if (!mixed) add((void **)&w.dr, sizeof(double4) * nn * d.nnei);
   if (!mixed) {
     add((void **)&w.T, sizeof(double) * nn * d.M1 * 4);
     add((void **)&w.D, sizeof(double) * rows * d.M1 * d.M2);
@@ -324,7 +325,7 @@ int ensure_ws(dp_ctx *c, int64_t n, int64_t ncell, int cand_cap) {
   }
   if (!nd) w.net_deriv = nullptr;
   if (!mixed) w.cell_part = nullptr;
-  if (mixed) w.rt = nullptr;
+  if (mixed) w.rt = w.dr = nullptr;
   else w.rt32 = nullptr;
   c->cgrid_ok = false;
   w.G[0] = w.dD;
@@ -635,7 +636,7 @@ MixArgs mix_args(dp_ctx *c, int64_t rows, double *F) {
   ma.nlist = w.nlist;
   ma.nreal = w.nreal;
   ma.rt = w.rt32;
-  ma.dr = w.dr;
+  for (int k = 0; k < 3; ++k) ma.L[k] = c->box_L[k];
   ma.T32 = w.T32;
   ma.dT32 = w.dT32;
   ma.force = F;
@@ -671,6 +672,7 @@ int64_t eval_rows(const dp_ctx *c, int64_t n) {
 // Formatted neighbour list and environment matrix of the current frame.
 void eval_lists(dp_ctx *c, int64_t n, const double L[3]) {
   Workspace &w = c->ws;
+  for (int k = 0; k < 3; ++k) c->box_L[k] = L[k];
   const Dims &d = c->dims;
   hipStream_t s = c->stream;
   tmark(c, 1);
@@ -960,7 +962,9 @@ void st_draw(dp_ctx *c, uint64_t seed, int64_t q0, int64_t batch, int nb = 1) {
   sa.type_start = w.type_start;
   sa.atom_of_pos = w.atom_of_pos;
   sa.nreal = w.nreal;
-  sa.dr = w.dr;
+  sa.xw = w.xw;
+  sa.nlist = w.nlist;
+  for (int k = 0; k < 3; ++k) sa.L[k] = c->box_L[k];
   sa.seed = seed;
   sa.q0 = q0;
   sa.batch = (int)batch;

@@ -113,8 +113,21 @@ __device__ inline double env_s(double r, double rcs, double rc, double inv_w) {
   }
   return sw * (1.0 / r);
 }
+// displacement d = x_j - x_i (one minimum-image correction per axis) and
+// r = |d| of a pair from the wrapped positions: (dx, dy, dz, r)
+__device__ inline double4 pair_disp(const double4 &pi, const double4 &pj, double L0, double L1, double L2) {
+  double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+  if (dx > 0.5 * L0) dx -= L0;
+  else if (dx < -0.5 * L0) dx += L0;
+  if (dy > 0.5 * L1) dy -= L1;
+  else if (dy < -0.5 * L1) dy += L1;
+  if (dz > 0.5 * L2) dz -= L2;
+  else if (dz < -0.5 * L2) dz += L2;
+  return make_double4(dx, dy, dz, sqrt(dx * dx + dy * dy + dz * dz));
+}
 // exactly one of rt (FP64 evaluation) and rt32 (mixed precision, the same
-// values rounded to FP32, which is all the mixed kernels read) is non-NULL
+// values rounded to FP32, which is all the mixed kernels read) is non-NULL;
+// dr (may be NULL: the mixed kernels recompute it from the positions)
 void launch_env(hipStream_t s, int64_t n, const double4 *xw, const Dims &d, const double *L, const int32_t *nlist,
                 const int32_t *nreal, double4 *rt, float4 *rt32, double4 *dr);
 

@@ -49,7 +49,7 @@ struct MixArgs {
   const double4 *xw;
   const int32_t *nlist, *nreal;
   const float4 *rt;           // environment matrix rows, FP32
-  const double4 *dr;
+  double L[3];                // box lengths (the force pass recomputes displacements)
   float *T32;                 // [natoms][M1][4], T / Nc (pass 1 writes, pass 2 reads nothing of it)
   const float *dT32;          // [natoms][M1][4], dE/dT of the unscaled sum (pass 2)
   double *force;              // [natoms][3]

@@ -47,7 +47,9 @@ struct StSampleArgs {
   const int32_t *type_start;   // [ntypes] first type-sorted position
   const int32_t *atom_of_pos;  // [rows]
   const int32_t *nreal;        // [natoms][ntypes]
-  const double4 *dr;           // [natoms][nnei], .w = r (s = sw(r) / r is recomputed)
+  const double4 *xw;           // [natoms] wrapped positions (s = sw(r) / r is recomputed)
+  const int32_t *nlist;        // [natoms][nnei]
+  double L[3];                 // box lengths
   uint64_t seed;
   int64_t q0;                  // index of the first batch's first sample
   int batch;                   // samples per net and batch

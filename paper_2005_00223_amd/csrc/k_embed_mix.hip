@@ -582,7 +582,8 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 2>::B)) k_embed_bw
   for (int64_t p = p0; p < p1; ++p) {
     const int i = a.atom_of_pos[p];
     if (i < 0) continue;
-    const int t = (int)a.xw[i].w;
+    const double4 xi = a.xw[i];
+    const int t = (int)xi.w;
     // dE/dT of the unscaled sum (from the fitting net) in LDS, rows f >= M1 zero
     {
       const float *dTi = a.dT32 + (int64_t)i * d.M1 * 4;
@@ -712,7 +713,9 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 2>::B)) k_embed_bw
           const int q = c0 + lane;
           if (q < cnt) {
             const float4 gr = *(const float4 *)(gRs + 4 * lane);
-            force_pair(a, base + q, a.dr[base + q], a.nlist[base + q], gr, rc, rcs, inv_w, fi0, fi1, fi2, vir);
+            const int j = a.nlist[base + q];
+            force_pair(a, base + q, pair_disp(xi, a.xw[j], a.L[0], a.L[1], a.L[2]), j, gr, rc, rcs, inv_w, fi0,
+                       fi1, fi2, vir);
           }
           wsync();
         }
@@ -901,7 +904,8 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
   const Dims &d = a.d;
   const int g = lane >> 4, n = lane & 15;
   const double rc = d.rcut, rcs = d.rcut_smth, inv_w = 1.0 / (d.rcut - d.rcut_smth);
-  const int t = (int)a.xw[i].w;
+  const double4 xi = a.xw[i];
+  const int t = (int)xi.w;
   {
     const float *dTi = a.dT32 + (int64_t)i * d.M1 * 4;
     for (int o = lane; o < S::S3 * 4; o += 64) dTs[o] = (o >> 2) < d.M1 ? dTi[o] : 0.f;
@@ -952,7 +956,7 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
     const Split8<P> MA = split8<P>(mx, my);
     float4 r4n = n < cnt ? a.rt[base + n] : make_float4(0.f, 0.f, 0.f, 0.f);
     // force-pass operands of the current 64-neighbour chunk, loaded a chunk ahead
-    double4 drc = lane < cnt ? a.dr[base + lane] : make_double4(0.0, 0.0, 1.0, 1.0);
+    double4 pjc = xi;  // neighbour positions of the chunk, gathered at its first tile
     int jc = lane < cnt ? a.nlist[base + lane] : 0;
     uint32_t codec = 0;
     for (int n0 = 0; n0 < cnt; n0 += 16) {
@@ -1004,8 +1008,11 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
         const float bd = r4.x * cb[0] + r4.y * cb[1] + r4.z * cb[2] + r4.w * cb[3];
         *(float4 *)(gRs + 4 * (slot0 + n)) = make_float4(ca[0] + q0 + bd, ca[1] + q1, ca[2] + q2, ca[3] + q3);
       }
-      // cell code of this chunk's neighbours (jc arrived during the tile)
-      if (CELL && slot0 == 0) codec = cc.code[jc];
+      // positions and cell codes of this chunk's neighbours (jc arrived during the tile)
+      if (slot0 == 0) {
+        pjc = a.xw[jc];
+        if (CELL) codec = cc.code[jc];
+      }
       wsync();
       // every 64 neighbours (or at the end of the type block): FP64 force pass
       if (((n0 + 16) & 63) == 0 || n0 + 16 >= cnt) {
@@ -1014,7 +1021,7 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
         if (qq < cnt) {
           const float4 gr = *(const float4 *)(gRs + 4 * lane);
           double gx, gy, gz;
-          pair_force(drc, gr, rc, rcs, inv_w, gx, gy, gz, fi0, fi1, fi2, vir);
+          pair_force(pair_disp(xi, pjc, a.L[0], a.L[1], a.L[2]), gr, rc, rcs, inv_w, gx, gy, gz, fi0, fi1, fi2, vir);
           if (a.net_deriv) {
             double *nd = a.net_deriv + (base + qq) * 4;
             nd[0] = gr.x; nd[1] = gr.y; nd[2] = gr.z; nd[3] = gr.w;
@@ -1031,7 +1038,6 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
           }
         }
         if (qq + 64 < cnt) {
-          drc = a.dr[base + qq + 64];
           jc = a.nlist[base + qq + 64];
         }
         wsync();

@@ -6,24 +6,20 @@
 //   u = (r - rcs)/(rc - rcs)  (quintic switch, C2 in the displacements).
 // Output rt[i][slot] = R and dr[i][slot] = (dx, dy, dz, r), double; for the
 // mixed-precision path R is stored rounded to FP32 instead (its kernels read
-// nothing else of it).  Padded slots are not written (every consumer stops
+// nothing else of it) and dr is not stored (its force pass recomputes the
+// displacement from the positions).  Padded slots are not written (every consumer stops
 // at the real count).
 //
 // One wave per centre atom; the lanes stride over the atom's real slots so
 // that the two output streams are written contiguously.  HBM-bound:
 // per real slot 4 B nlist + 32 B neighbour position (L2/MALL) in, 64 B out
-// (48 B with the FP32 R).
+// (16 B with the FP32 R and no dr).
 #include "dp_internal.h"
 
 namespace dpk {
 
 constexpr int ENV_BATCH = 4;  // gathers in flight per lane
 
-__device__ inline double env_min_image(double v, double L) {
-  if (v > 0.5 * L) v -= L;
-  else if (v < -0.5 * L) v += L;
-  return v;
-}
 
 __device__ inline void put_rt(double4 *rt, int64_t k, double a, double b, double c, double e) {
   rt[k] = make_double4(a, b, c, e);
@@ -61,14 +57,11 @@ __global__ void __launch_bounds__(256) k_env(int64_t n, const double4 *__restric
         const int q = q0 + 64 * v + lane;
         if (jb[v] < 0) continue;
         const double4 pj = pb[v];
-        double dx = env_min_image(pj.x - p.x, L0);
-        double dy = env_min_image(pj.y - p.y, L1);
-        double dz = env_min_image(pj.z - p.z, L2);
-        double r = sqrt(dx * dx + dy * dy + dz * dz);
-        const double s = env_s(r, rcs, rc, inv_w);
-        double t = s * (1.0 / r);
-        put_rt(rt, base + q, s, t * dx, t * dy, t * dz);
-        dr[base + q] = make_double4(dx, dy, dz, r);
+        const double4 D = pair_disp(p, pj, L0, L1, L2);
+        const double s = env_s(D.w, rcs, rc, inv_w);
+        const double t = s * (1.0 / D.w);
+        put_rt(rt, base + q, s, t * D.x, t * D.y, t * D.z);
+        if (dr) dr[base + q] = D;
       }
     }
   }

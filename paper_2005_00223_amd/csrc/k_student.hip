@@ -44,8 +44,9 @@ __global__ void k_st_sample(StSampleArgs a) {
       const int64_t slot = (int64_t)(((x & 0xffffffffull) * (uint64_t)selu) >> 32);
       const int i = a.atom_of_pos[a.type_start[t] + k];
       if (slot < a.nreal[(int64_t)i * T + u]) {
-        const double r = a.dr[(int64_t)i * a.d.nnei + a.d.off[u] + slot].w;
-        s = env_s(r, a.d.rcut_smth, a.d.rcut, 1.0 / (a.d.rcut - a.d.rcut_smth));
+        const int j = a.nlist[(int64_t)i * a.d.nnei + a.d.off[u] + slot];
+        const double4 D = pair_disp(a.xw[i], a.xw[j], a.L[0], a.L[1], a.L[2]);
+        s = env_s(D.w, a.d.rcut_smth, a.d.rcut, 1.0 / (a.d.rcut - a.d.rcut_smth));
         w = 1.f;
         break;
       }
