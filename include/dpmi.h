@@ -76,6 +76,7 @@ typedef struct {
   double last_judge_rmse;    /* force RMSE student vs teacher, eV/A          */
   int64_t judge_atoms;       /* atoms the last judge covered                 */
   int64_t cell_scatter;      /* backward passes with the cell-ordered scatter */
+  int64_t table_evals;       /* student evaluations with the tabulated layers */
 } dp_stats;
 
 /* Create a context on HIP device `device`; `hip_stream` is a hipStream_t
@@ -273,6 +274,18 @@ int dp_student_judge_sample(dp_ctx *c, double side);
  * ntypes, rcut, rcut_smth, desc_norm, sel, M2 and fitting nets must match
  * the teacher's and its embedding must be 1-16-32-M1 affine. */
 int dp_student_get_model(dp_ctx *c, void *buf, size_t cap, size_t *nbytes);
+
+/* Tabulated student layers (mixed precision only; default on).  The first
+ * two layers of a student net map the scalar s to h2(s); on the first
+ * student evaluation after the student or the precision changes, h2 and
+ * dh2/ds are tabulated in FP64 (weights as the 16-bit kernels hold them) on
+ * 81 points over [0, 1.25 x the largest s of that frame] and then
+ * interpolated by cubic Hermite polynomials per neighbour; a 16-neighbour
+ * tile with any s beyond the range evaluates the layers.  on = 0 always
+ * evaluates the layers.  The table's own error is far below the student's
+ * fitting error (GPU test: forces within 1e-5 eV/A of the evaluated
+ * layers). */
+int dp_student_table(dp_ctx *c, int on);
 int dp_student_set_model(dp_ctx *c, const void *blob, size_t nbytes);
 
 const char *dp_last_error(const dp_ctx *c);

@@ -17,7 +17,7 @@ PRECISION = {"fp64": DP_FP64, "fp16": DP_MIX_FP16, "bf16": DP_MIX_BF16}
 
 EXPORTS = ("dp_create", "dp_set_model", "dp_set_precision", "dp_compute", "dp_energy", "dp_energy_backward",
            "dp_get_nlist", "dp_keep_intermediates",
-           "dp_get_intermediates", "dp_get_stats", "dp_set_force_scatter", "dp_md_run", "dp_enable_timing", "dp_get_timing",
+           "dp_get_intermediates", "dp_get_stats", "dp_set_force_scatter", "dp_student_table", "dp_md_run", "dp_enable_timing", "dp_get_timing",
            "dp_student_default_cfg", "dp_student_train", "dp_student_get_params", "dp_student_set_params",
            "dp_student_batch_grad", "dp_student_use", "dp_student_judge", "dp_student_judge_sample",
            "dp_student_get_model",
@@ -28,7 +28,7 @@ class dp_stats(C.Structure):
     _fields_ = [("natoms", C.c_int64), ("sel_overflow", C.c_int64), ("max_real", C.c_int32 * 8),
                 ("nlist_builds", C.c_int64), ("evaluations", C.c_int64), ("cand_cap", C.c_int64),
                 ("student_evals", C.c_int64), ("teacher_fallbacks", C.c_int64), ("last_judge_rmse", C.c_double),
-                ("judge_atoms", C.c_int64), ("cell_scatter", C.c_int64)]
+                ("judge_atoms", C.c_int64), ("cell_scatter", C.c_int64), ("table_evals", C.c_int64)]
 
 
 class dp_student_cfg(C.Structure):
@@ -69,6 +69,7 @@ def lib():
         "dp_get_intermediates": (I32, [P, P, P, P, P]),
         "dp_get_stats": (I32, [P, C.POINTER(dp_stats)]),
         "dp_set_force_scatter": (I32, [P, I32]),
+        "dp_student_table": (I32, [P, I32]),
         "dp_md_run": (I32, [P, I64, P, P, P, P, P, D, D, I64, I64, P, P]),
         "dp_enable_timing": (I32, [P, I32]),
         "dp_get_timing": (I32, [P, C.c_char_p, C.POINTER(D)]),
@@ -158,6 +159,10 @@ def dp_md_run(ctx, natoms, x_ptr, v_ptr, t_ptr, box9, masses, dt, skin, nsteps, 
 
 def dp_set_force_scatter(ctx, mode: int):
     return check(ctx, lib().dp_set_force_scatter(ctx, int(mode)))
+
+
+def dp_student_table(ctx, on: bool):
+    return check(ctx, lib().dp_student_table(ctx, int(bool(on))))
 
 
 def dp_enable_timing(ctx, on: bool):

@@ -119,7 +119,7 @@ struct DevStatus {
   double judge_rmse;   // force RMSE of the last student judge
   double judge_count;  // atoms it covered
   int32_t sub_rows;    // padded rows of the judge's atom subset
-  int32_t pad2;
+  uint32_t smax_bits;  // largest s of the frame (float bits), for the student table
 };
 
 struct Workspace {
@@ -170,6 +170,9 @@ struct EmbNets {
   double *d_emb = nullptr;          // FP64 padded weights
   unsigned char *d_mix = nullptr;   // mixed-precision LDS images
   int mix_shape = -1;
+  float *d_tab = nullptr;           // tabulated second layer (student nets, mixed precision)
+  double tab_shi = 0.0;             // its range of s
+  bool tab_ok = false;
   bool ready = false;
 };
 
@@ -192,6 +195,7 @@ struct dp_ctx {
   double box_L[3] = {0.0, 0.0, 0.0};  // box lengths of the last lists
   bool cgrid_ok = false;
   int scatter = 0;                  // dp_set_force_scatter mode
+  bool use_tab = true;              // dp_student_table
   HostModel shm;                    // student (embedding part; fitting = teacher's)
   Student *st = nullptr;            // student training state
   int64_t judge_every = 20;         // MD judge period (0 = off)
@@ -470,6 +474,7 @@ uint16_t h16_bits(double v, int prec) {
 
 // Mixed-precision LDS images of the embedding nets of m into en.
 int upload_emb_mix(dp_ctx *c, const HostModel &m, EmbNets &en) {
+  en.tab_ok = false;  // the table follows the weights and the precision
   const Dims &d = en.d;
   const int prec = c->precision == DP_MIX_FP16 ? 0 : 1;
   const int shape = mix_shape_id(d);
@@ -642,6 +647,12 @@ MixArgs mix_args(dp_ctx *c, int64_t rows, double *F) {
   ma.force = F;
   ma.vir_part = w.vir_part;
   ma.net_deriv = c->keep ? w.net_deriv : nullptr;
+  ma.tab = nullptr;
+  if (c->active == 1 && c->use_tab && en.tab_ok) {
+    ma.tab = en.d_tab;
+    ma.tab_inv_ds = (float)(TAB_K / en.tab_shi);
+    ma.tab_shi = (float)en.tab_shi;
+  }
   return ma;
 }
 
@@ -683,6 +694,32 @@ void eval_lists(dp_ctx *c, int64_t n, const double L[3]) {
   tmark(c, 3);
 }
 
+// Table of the active student nets (mixed precision): built on the first
+// evaluation after the nets or the precision change, over s in
+// [0, 1.25 x the largest s of that frame]; tiles with a larger s evaluate the
+// layers instead.
+int ensure_table(dp_ctx *c, int64_t n) {
+  EmbNets &en = c->en[c->active];
+  if (c->active != 1 || !c->use_tab || c->precision == DP_FP64 || en.tab_ok || n <= 0) return DP_OK;
+  if (!mix_tab_fits(en.mix_shape, c->dims.ntypes)) return DP_OK;
+  Workspace &w = c->ws;
+  hipStream_t s = c->stream;
+  launch_fill_u32(s, &w.status->smax_bits, 1, 0u);
+  launch_smax(s, n, c->dims, w.nreal, w.rt32, &w.status->smax_bits);
+  uint32_t bits = 0;
+  HIPCHK(c, hipMemcpyAsync(&bits, &w.status->smax_bits, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  float smax;
+  std::memcpy(&smax, &bits, 4);
+  const double shi = smax > 0.f ? 1.25 * (double)smax : 1.0;
+  if (!en.d_tab) HIPCHK(c, hipMalloc(&en.d_tab, (size_t)c->dims.ntypes * c->dims.ntypes * TAB_BYTES));
+  launch_student_table(s, en.d, en.eo, en.d_emb, c->precision == DP_MIX_FP16 ? 0 : 1, shi, en.d_tab);
+  HIPCHK(c, hipGetLastError());
+  en.tab_shi = shi;
+  en.tab_ok = true;
+  return DP_OK;
+}
+
 // Networks of the forward half with the active embedding set: embedding +
 // descriptor, fitting net forward, energy into E.
 void eval_nets_fwd(dp_ctx *c, int64_t n, double *E) {
@@ -694,7 +731,10 @@ void eval_nets_fwd(dp_ctx *c, int64_t n, double *E) {
     tmark(c, 4);
     launch_fit_f64(s, fit_args(c, rows), 1);
   } else {
-    launch_embed_mix(s, mix_args(c, rows, nullptr), 1, mix_grid(rows));
+    (void)ensure_table(c, n);  // a failed table build leaves tab_ok false: the layers are evaluated
+    const MixArgs ma = mix_args(c, rows, nullptr);
+    if (ma.tab) c->stats.table_evals += 1;
+    launch_embed_mix(s, ma, 1, mix_grid(rows));
     tmark(c, 4);
     launch_fit_mix(s, fitmix_args(c, rows), 1);
   }
@@ -1172,6 +1212,7 @@ void dp_destroy(dp_ctx *c) {
   for (auto &en : c->en) {
     if (en.d_emb) (void)hipFree(en.d_emb);
     if (en.d_mix) (void)hipFree(en.d_mix);
+    if (en.d_tab) (void)hipFree(en.d_tab);
   }
   free_student(c);
   if (c->d_fit) (void)hipFree(c->d_fit);
@@ -1422,6 +1463,12 @@ int dp_get_intermediates(dp_ctx *c, double *atom_e, double *T, double *D, double
 int dp_get_stats(dp_ctx *c, dp_stats *out) {
   if (!c || !out) return DP_E_ARG;
   *out = c->stats;
+  return DP_OK;
+}
+
+int dp_student_table(dp_ctx *c, int on) {
+  if (!c) return DP_E_ARG;
+  c->use_tab = on != 0;
   return DP_OK;
 }
 

@@ -55,10 +55,26 @@ struct MixArgs {
   double *force;              // [natoms][3]
   double *vir_part;           // [grid][9]
   double *net_deriv;          // optional [natoms][nnei][4]
+  // tabulated second layer of a student net (NULL: evaluate the layers):
+  // per net [TAB_K + 1][TAB_STRIDE] floats, row k = s_k = k ds, features f
+  // at (2f, 2f+1) = (h2(s_k), ds dh2/ds(s_k)); s above tab_shi takes the
+  // layers themselves
+  const float *tab;
+  float tab_inv_ds, tab_shi;
 };
+
+constexpr int TAB_K = 80;                         // intervals of the student table
+constexpr int TAB_STRIDE = 68;                    // floats per row: 32 features x 2 + 4 (LDS bank spread)
+constexpr int TAB_BYTES = (TAB_K + 1) * TAB_STRIDE * 4;
+// second layer of each student net tabulated (cubic Hermite data) over [0, shi]
+void launch_student_table(hipStream_t s, const Dims &d, const EmbOffsets &eo, const double *ew, int prec, double shi,
+                          float *tab);
+// largest s of the frame (nearest neighbour of every atom and type) into *smax (bits of a float)
+void launch_smax(hipStream_t s, int64_t n, const Dims &d, const int32_t *nreal, const float4 *rt, uint32_t *smax);
 
 int mix_shape_id(const Dims &d);
 size_t mix_net_bytes(int shape);
+bool mix_tab_fits(int shape, int ntypes);  // affine-net kernels fit the LDS with the student table
 size_t mix_lds_bytes(int shape, int ntypes, int pass);
 void mix_pack_net(int shape, const double *const *W, const double *const *b, int prec, unsigned char *out);
 int mix_grid(int64_t rows);

@@ -737,6 +737,33 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 2>::B)) k_embed_bw
 // layer-3 image W3^T, and M in its accumulator layout is exactly the A
 // operand of the per-neighbour contraction.
 // ---------------------------------------------------------------------------
+// Tabulated second layer at s (0 <= s <= the table's range): lane group g
+// gets features f = 16 mt + 4 g + r, r = 0..3 (the MFMA output layout);
+// cubic Hermite interpolation between rows k and k + 1; D: also dh2/ds.
+template <bool D>
+__device__ inline void tab_h2(const float *tab, float s, float inv_ds, int g, float (&h)[2][4], float (&dh)[2][4]) {
+  const float x = s * inv_ds;
+  int k = (int)x;
+  k = k < TAB_K - 1 ? k : TAB_K - 1;
+  const float t = x - (float)k, t2 = t * t, t3 = t2 * t;
+  const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t, h01 = 3.f * t2 - 2.f * t3, h11 = t3 - t2;
+  const float e00 = 6.f * (t2 - t), e10 = 3.f * t2 - 4.f * t + 1.f, e11 = 3.f * t2 - 2.f * t;
+  const float *r0 = tab + k * TAB_STRIDE, *r1 = r0 + TAB_STRIDE;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    const int c = 2 * (16 * mt + 4 * g);
+    const float4 a0 = *(const float4 *)(r0 + c), a1 = *(const float4 *)(r0 + c + 4);
+    const float4 b0 = *(const float4 *)(r1 + c), b1 = *(const float4 *)(r1 + c + 4);
+    const float y0[4] = {a0.x, a0.z, a1.x, a1.z}, m0[4] = {a0.y, a0.w, a1.y, a1.w};
+    const float y1[4] = {b0.x, b0.z, b1.x, b1.z}, m1[4] = {b0.y, b0.w, b1.y, b1.w};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      h[mt][r] = h00 * y0[r] + h10 * m0[r] + h01 * y1[r] + h11 * m1[r];
+      if (D) dh[mt][r] = (e00 * (y0[r] - y1[r]) + e10 * m0[r] + e11 * m1[r]) * inv_ds;
+    }
+  }
+}
+
 template <int W1, int W2, int W3>
 struct LinShape {
   typedef Shape<W1, W2, W3> S;
@@ -745,12 +772,13 @@ struct LinShape {
   static constexpr int KF = (W3 + 31) / 32;             // K-steps of M = W3 dT over the outputs
   static constexpr int O_A3B = S::NET_BYTES;            // W3 as [k][f] A operands: [2][KF][64 lanes][8]
   static constexpr int NET_BYTES = O_A3B + 2 * KF * 1024;
-  static constexpr int P1_H1 = 0;                       // float [16][S1]
-  static constexpr int P1_HT = P1_H1 + 16 * S::S1 * 4;  // float [32][GTS]: h2 transposed (features x neighbours)
+  static constexpr int XL = S::XL2 ? 1 : 0;             // cross-lane skip scratch needed
+  static constexpr int P1_H1 = 0;                       // float [16][S1] (cross-lane skips only)
+  static constexpr int P1_HT = P1_H1 + XL * 16 * S::S1 * 4;  // float [32][GTS]: h2 transposed (features x neighbours)
   static constexpr int P1_R = P1_HT + 32 * S::GTS * 4;  // float [16][4]
   static constexpr int P1_BYTES = P1_R + 256;
-  static constexpr int P2_H1 = 0;                       // float [2][16][S1] (h, dh)
-  static constexpr int P2_DT = P2_H1 + 2 * 16 * S::S1 * 4;  // float [S3][4]
+  static constexpr int P2_H1 = 0;                       // float [2][16][S1] (h, dh; cross-lane skips only)
+  static constexpr int P2_DT = P2_H1 + XL * 2 * 16 * S::S1 * 4;  // float [S3][4]
   static constexpr int P2_GR = P2_DT + S::S3 * 16;      // float [64][4]
   static constexpr int P2_BYTES = P2_GR + 1024;
 };
@@ -763,10 +791,13 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_fwd_lin(MixArgs a) 
   const Dims &d = a.d;
   const int nnets = d.ntypes * d.ntypes;
   copy_nets(smem, a.nets, nnets * LS::NET_BYTES);
+  const int tab_bytes = a.tab ? nnets * TAB_BYTES : 0;  // student table after the nets
+  if (a.tab) copy_nets(smem + nnets * LS::NET_BYTES, (const unsigned char *)a.tab, tab_bytes);
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int g = lane >> 4, n = lane & 15;
-  unsigned char *ws = smem + nnets * LS::NET_BYTES + wv * LS::P1_BYTES;
+  const float *tabs = (const float *)(smem + nnets * LS::NET_BYTES);
+  unsigned char *ws = smem + nnets * LS::NET_BYTES + tab_bytes + wv * LS::P1_BYTES;
   float *h1s = (float *)(ws + LS::P1_H1);
   float *Hs = (float *)(ws + LS::P1_HT);
   float *Rs = (float *)(ws + LS::P1_R);
@@ -799,26 +830,39 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_fwd_lin(MixArgs a) 
         sr1 += r4.y;
         sr2 += r4.z;
         sr3 += r4.w;
-        float h1[2][4], hd_unused[2][4];
-        layer1<W1, false>(w1, b1, s, g, h1, hd_unused);
-        if (S::XL2)
+        float h2[2][4];
+        if (a.tab && __ballot(s > a.tab_shi) == 0ull) {
+          // every neighbour of the tile inside the table's range
+          float unused[2][4];
+          tab_h2<false>(tabs + (t * d.ntypes + u) * (TAB_BYTES / 4), s, a.tab_inv_ds, g, h2, unused);
+        } else {
+          float h1[2][4], hd_unused[2][4];
+          layer1<W1, false>(w1, b1, s, g, h1, hd_unused);
+          if (S::XL2)
 #pragma unroll
-          for (int mt = 0; mt < 2; ++mt)
-            *(float4 *)(h1s + n * S::S1 + 16 * mt + 4 * g) = make_float4(h1[mt][0], h1[mt][1], h1[mt][2], h1[mt][3]);
-        Split8<P> B2[1] = {split8<P>(h1[0], h1[1])};
-        v4f acc2[S::MT2];
-        layer_mfma<P, S::MT2, 1>(net + S::O_A2, b2, B2, lane, g, acc2);
-        wsync();
+            for (int mt = 0; mt < 2; ++mt)
+              *(float4 *)(h1s + n * S::S1 + 16 * mt + 4 * g) =
+                  make_float4(h1[mt][0], h1[mt][1], h1[mt][2], h1[mt][3]);
+          Split8<P> B2[1] = {split8<P>(h1[0], h1[1])};
+          v4f acc2[S::MT2];
+          layer_mfma<P, S::MT2, 1>(net + S::O_A2, b2, B2, lane, g, acc2);
+          wsync();
+#pragma unroll
+          for (int mt = 0; mt < S::MT2; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int f = 16 * mt + 4 * g + r;
+              float v = 0.f;
+              if (16 * mt < W2 && f < W2)
+                v = tanh_f(acc2[mt][r]) + skip_val<W1, W2, S::SK2, 2>(f, mt, r, h1, h1s, n, S::S1);
+              h2[mt][r] = v;
+            }
+        }
         // h2, written transposed (features x neighbours) for H += h2^T R
 #pragma unroll
         for (int mt = 0; mt < S::MT2; ++mt)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int f = 16 * mt + 4 * g + r;
-            float v = 0.f;
-            if (16 * mt < W2 && f < W2) v = tanh_f(acc2[mt][r]) + skip_val<W1, W2, S::SK2, 2>(f, mt, r, h1, h1s, n, S::S1);
-            Hs[f * S::GTS + n] = v;
-          }
+          for (int r = 0; r < 4; ++r) Hs[(16 * mt + 4 * g + r) * S::GTS + n] = h2[mt][r];
         wsync();
         const RSplit RB = rsplit<P>(Rs, n, g);
 #pragma unroll
@@ -896,8 +940,9 @@ __device__ inline int cell_slot(const CellCtx &cc, uint32_t code) {
 // own forces go to the block's LDS accumulator (li = index of i in its
 // cell), else straight to global memory with atomics.
 template <int W1, int W2, int W3, int P, bool CELL>
-__device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char *smem, float *h1s, float *hd1s,
-                                    float *dTs, float *gRs, int lane, double (&vir)[9], const CellCtx &cc, int li) {
+__device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char *smem, const float *tabs, float *h1s,
+                                    float *hd1s, float *dTs, float *gRs, int lane, double (&vir)[9], const CellCtx &cc,
+                                    int li) {
   typedef Shape<W1, W2, W3> S;
   typedef LinShape<W1, W2, W3> LS;
   typedef typename HT<P>::v8 V;
@@ -964,35 +1009,40 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
       const float4 r4 = r4n;
       if (n0 + 16 < cnt) r4n = n0 + 16 + n < cnt ? a.rt[base + n0 + 16 + n] : make_float4(0.f, 0.f, 0.f, 0.f);
       const float s = r4.x;
-      float h1[2][4], hd1[2][4];
-      layer1<W1, true>(w1, b1, s, g, h1, hd1);
-      if (S::XL2)
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-          *(float4 *)(h1s + n * S::S1 + 16 * mt + 4 * g) = make_float4(h1[mt][0], h1[mt][1], h1[mt][2], h1[mt][3]);
-          *(float4 *)(hd1s + n * S::S1 + 16 * mt + 4 * g) =
-              make_float4(hd1[mt][0], hd1[mt][1], hd1[mt][2], hd1[mt][3]);
-        }
-      Split8<P> B2h[1] = {split8<P>(h1[0], h1[1])}, B2d[1] = {split8<P>(hd1[0], hd1[1])};
-      v4f acc2[S::MT2], acc2d[S::MT2];
-      layer_mfma<P, S::MT2, 1>(net + S::O_A2, b2, B2h, lane, g, acc2);
-      layer_mfma_tan<P, S::MT2, 1>(net + S::O_A2, B2d, lane, acc2d);
-      wsync();
       float h2[S::MT2][4], hd2[S::MT2][4];
+      if (tabs && __ballot(s > a.tab_shi) == 0ull) {
+        // every neighbour of the tile inside the table's range
+        tab_h2<true>(tabs + (t * d.ntypes + u) * (TAB_BYTES / 4), s, a.tab_inv_ds, g, h2, hd2);
+      } else {
+        float h1[2][4], hd1[2][4];
+        layer1<W1, true>(w1, b1, s, g, h1, hd1);
+        if (S::XL2)
 #pragma unroll
-      for (int mt = 0; mt < S::MT2; ++mt)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int f = 16 * mt + 4 * g + r;
-          float hv = 0.f, dv = 0.f;
-          if (16 * mt < W2 && f < W2) {
-            const float th = tanh_f(acc2[mt][r]);
-            hv = th + skip_val<W1, W2, S::SK2, 2>(f, mt, r, h1, h1s, n, S::S1);
-            dv = (1.f - th * th) * acc2d[mt][r] + skip_val<W1, W2, S::SK2, 2>(f, mt, r, hd1, hd1s, n, S::S1);
+          for (int mt = 0; mt < 2; ++mt) {
+            *(float4 *)(h1s + n * S::S1 + 16 * mt + 4 * g) = make_float4(h1[mt][0], h1[mt][1], h1[mt][2], h1[mt][3]);
+            *(float4 *)(hd1s + n * S::S1 + 16 * mt + 4 * g) =
+                make_float4(hd1[mt][0], hd1[mt][1], hd1[mt][2], hd1[mt][3]);
           }
-          h2[mt][r] = hv;
-          hd2[mt][r] = dv;
-        }
+        Split8<P> B2h[1] = {split8<P>(h1[0], h1[1])}, B2d[1] = {split8<P>(hd1[0], hd1[1])};
+        v4f acc2[S::MT2], acc2d[S::MT2];
+        layer_mfma<P, S::MT2, 1>(net + S::O_A2, b2, B2h, lane, g, acc2);
+        layer_mfma_tan<P, S::MT2, 1>(net + S::O_A2, B2d, lane, acc2d);
+        wsync();
+#pragma unroll
+        for (int mt = 0; mt < S::MT2; ++mt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int f = 16 * mt + 4 * g + r;
+            float hv = 0.f, dv = 0.f;
+            if (16 * mt < W2 && f < W2) {
+              const float th = tanh_f(acc2[mt][r]);
+              hv = th + skip_val<W1, W2, S::SK2, 2>(f, mt, r, h1, h1s, n, S::S1);
+              dv = (1.f - th * th) * acc2d[mt][r] + skip_val<W1, W2, S::SK2, 2>(f, mt, r, hd1, hd1s, n, S::S1);
+            }
+            h2[mt][r] = hv;
+            hd2[mt][r] = dv;
+          }
+      }
       const Split8<P> B3h = split8<P>(h2[0], h2[1]), B3d = split8<P>(hd2[0], hd2[1]);
       // a = M^T h2 and b = M^T h2' (lane (g, n): component c = 4 g + r of neighbour n)
       v4f ca = v4f{0.f, 0.f, 0.f, 0.f}, cb = v4f{0.f, 0.f, 0.f, 0.f};
@@ -1072,9 +1122,12 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_bwd_lin(MixArgs a) 
   __shared__ double vred[MIX_WAVES][9];
   const int nnets = a.d.ntypes * a.d.ntypes;
   copy_nets(smem, a.nets, nnets * LS::NET_BYTES);
+  const int tab_bytes = a.tab ? nnets * TAB_BYTES : 0;  // student table after the nets
+  if (a.tab) copy_nets(smem + nnets * LS::NET_BYTES, (const unsigned char *)a.tab, tab_bytes);
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  unsigned char *ws = smem + nnets * LS::NET_BYTES + wv * LS::P2_BYTES;
+  const float *tabs = a.tab ? (const float *)(smem + nnets * LS::NET_BYTES) : nullptr;
+  unsigned char *ws = smem + nnets * LS::NET_BYTES + tab_bytes + wv * LS::P2_BYTES;
   float *h1s = (float *)(ws + LS::P2_H1), *hd1s = h1s + 16 * Shape<W1, W2, W3>::S1;
   float *dTs = (float *)(ws + LS::P2_DT);
   float *gRs = (float *)(ws + LS::P2_GR);
@@ -1087,7 +1140,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_bwd_lin(MixArgs a) 
   for (int64_t p = p0; p < p1; ++p) {
     const int i = a.atom_of_pos[p];
     if (i < 0) continue;
-    lin_bwd_atom<W1, W2, W3, P, false>(a, i, smem, h1s, hd1s, dTs, gRs, lane, vir, cc, 0);
+    lin_bwd_atom<W1, W2, W3, P, false>(a, i, smem, tabs, h1s, hd1s, dTs, gRs, lane, vir, cc, 0);
   }
   finish_block_virial(a, vir, vred, lane, wv);
 }
@@ -1119,11 +1172,14 @@ __global__ void __launch_bounds__(64 * CELL_WAVES, 1) k_embed_bwd_cells(MixArgs 
   const int nnets = a.d.ntypes * a.d.ntypes;
   const int nw = blockDim.x >> 6;
   copy_nets(smem, a.nets, nnets * LS::NET_BYTES);
+  const int tab_bytes = a.tab ? nnets * TAB_BYTES : 0;  // student table after the nets
+  if (a.tab) copy_nets(smem + nnets * LS::NET_BYTES, (const unsigned char *)a.tab, tab_bytes);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  unsigned char *ws = smem + nnets * LS::NET_BYTES + wv * CS::W_BYTES;
+  const float *tabs = a.tab ? (const float *)(smem + nnets * LS::NET_BYTES) : nullptr;
+  unsigned char *ws = smem + nnets * LS::NET_BYTES + tab_bytes + wv * CS::W_BYTES;
   float *dTs = (float *)(ws + CS::W_DT);
   float *gRs = (float *)(ws + CS::W_GR);
-  double *facc = (double *)(smem + nnets * LS::NET_BYTES + nw * CS::W_BYTES);
+  double *facc = (double *)(smem + nnets * LS::NET_BYTES + tab_bytes + nw * CS::W_BYTES);
   const int nacc = 27 * 3 * ca.cap;
   double vir[9];
 #pragma unroll
@@ -1143,7 +1199,8 @@ __global__ void __launch_bounds__(64 * CELL_WAVES, 1) k_embed_bwd_cells(MixArgs 
     cc.cx = (int)(c / ((int64_t)cc.nc1 * cc.nc2));
     const int b = ca.cell_start[c], e = ca.cell_start[c + 1];
     for (int k = b + wv; k < e; k += nw)
-      lin_bwd_atom<W1, W2, W3, P, true>(a, ca.cell_atoms[k], smem, nullptr, nullptr, dTs, gRs, lane, vir, cc, k - b);
+      lin_bwd_atom<W1, W2, W3, P, true>(a, ca.cell_atoms[k], smem, tabs, nullptr, nullptr, dTs, gRs, lane, vir, cc,
+                                        k - b);
     __syncthreads();
     for (int s = 0; s < 27; ++s) {
       const int x = (cc.cx + s / 9 - 1 + cc.nc0) % cc.nc0, y = (cc.cy + (s / 3) % 3 - 1 + cc.nc1) % cc.nc1,
@@ -1268,11 +1325,12 @@ static void launch_t(hipStream_t s, const MixArgs &a, int pass, int grid) {
   const int nnets = a.d.ntypes * a.d.ntypes;
   if constexpr (LIN) {
     typedef LinShape<W1, W2, W3> LS;
+    const size_t tab = a.tab ? (size_t)nnets * TAB_BYTES : 0;
     if (pass == 1) {
-      const size_t shm = (size_t)nnets * LS::NET_BYTES + (size_t)MIX_WAVES * LS::P1_BYTES;
+      const size_t shm = (size_t)nnets * LS::NET_BYTES + tab + (size_t)MIX_WAVES * LS::P1_BYTES;
       hipLaunchKernelGGL((k_embed_fwd_lin<W1, W2, W3, P>), dim3(grid), dim3(64 * MIX_WAVES), shm, s, a);
     } else {
-      const size_t shm = (size_t)nnets * LS::NET_BYTES + (size_t)MIX_WAVES * LS::P2_BYTES;
+      const size_t shm = (size_t)nnets * LS::NET_BYTES + tab + (size_t)MIX_WAVES * LS::P2_BYTES;
       hipLaunchKernelGGL((k_embed_bwd_lin<W1, W2, W3, P>), dim3(grid), dim3(64 * MIX_WAVES), shm, s, a);
     }
     return;
@@ -1297,6 +1355,18 @@ static size_t lds_t(int ntypes, int pass) {
   }
 }
 
+// whether the affine-net kernels of a shape fit the LDS with the student table
+template <int W1, int W2, int W3, int LIN>
+static bool tab_fits_t(int ntypes) {
+  if constexpr (LIN == 0 || Shape<W1, W2, W3>::XL2 || W2 != 32) {
+    return false;
+  } else {
+    typedef LinShape<W1, W2, W3> LS;
+    const size_t base = (size_t)ntypes * ntypes * (LS::NET_BYTES + TAB_BYTES);
+    return base + (size_t)MIX_WAVES * LS::P1_BYTES <= 163840 && base + (size_t)MIX_WAVES * LS::P2_BYTES <= 163840;
+  }
+}
+
 // supported embedding shapes: widths of the three layers, affine last layer
 #define DPK_MIX_SHAPES(X) X(25, 50, 100, 0) X(16, 32, 100, 0) X(16, 32, 100, 1)
 
@@ -1309,6 +1379,16 @@ int mix_shape_id(const Dims &d) {
   DPK_MIX_SHAPES(X)
 #undef X
   return -1;
+}
+
+bool mix_tab_fits(int shape, int ntypes) {
+  int id = 0;
+#define X(a_, b_, c_, l_)                                     \
+  if (shape == id) return tab_fits_t<a_, b_, c_, l_>(ntypes); \
+  ++id;
+  DPK_MIX_SHAPES(X)
+#undef X
+  return false;
 }
 
 size_t mix_net_bytes(int shape) {
@@ -1364,16 +1444,96 @@ void launch_embed_mix(hipStream_t s, const MixArgs &a, int pass, int grid) {
 }
 
 // ---------------------------------------------------------------------------
+// student table: the second layer of an affine-last-layer net, h2(s) and
+// dh2/ds, is a function of the scalar s alone, so it is tabulated once per
+// installed student on s_k = k ds (k = 0..TAB_K) in FP64 with the weights
+// the kernels hold (layer 1 in FP32, W2 rounded to 16 bits) and interpolated
+// per neighbour by cubic Hermite polynomials (the idea of tabulating the
+// embedding net of a trained Deep Potential: Lu et al., J. Chem. Theory
+// Comput. 18, 5559 (2022)).  Interpolation error of h2 ~ ds^4 max|h2^(4)| / 384.
+// ---------------------------------------------------------------------------
+__device__ inline double round16_dev(double v, int prec) {
+  const float x = (float)v;
+  if (prec == 0) return (double)(float)(_Float16)x;
+  uint32_t u = __builtin_bit_cast(uint32_t, x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  u &= 0xffff0000u;
+  return (double)__builtin_bit_cast(float, u);
+}
+
+__global__ void k_student_table(Dims d, EmbOffsets eo, const double *__restrict__ ew, int prec, double ds,
+                                float *__restrict__ tab) {
+  const int net = blockIdx.y;
+  const int t = net / d.ntypes, u = net % d.ntypes;
+  const int W1 = d.ew[1], W2 = d.ew[2];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (TAB_K + 1) * W2) return;
+  const int k = idx / W2, f = idx % W2;
+  const double sv = k * ds;
+  const double *W0 = ew + eo.w[t][u][0], *b0 = ew + eo.b[t][u][0];
+  const double *Wl = ew + eo.w[t][u][1], *bl = ew + eo.b[t][u][1];
+  const int mp = d.emp[2];
+  double z = (double)(float)bl[f], dz = 0.0, hs = 0.0, dhs = 0.0;
+  for (int i = 0; i < W1; ++i) {
+    const double w = (double)(float)W0[i], b = (double)(float)b0[i];
+    const double h = tanh(sv * w + b), dh = (1.0 - h * h) * w;
+    const double wq = round16_dev(Wl[(size_t)i * mp + f], prec);
+    z += wq * h;
+    dz += wq * dh;
+    if (i == f % W1) {
+      hs = h;
+      dhs = dh;
+    }
+  }
+  const double th = tanh(z);
+  double y = th, dy = (1.0 - th * th) * dz;
+  if (W2 == W1 || W2 == 2 * W1) {  // identity / doubling skip
+    y += hs;
+    dy += dhs;
+  }
+  float *row = tab + ((int64_t)net * (TAB_K + 1) + k) * TAB_STRIDE;
+  row[2 * f] = (float)y;
+  row[2 * f + 1] = (float)(ds * dy);
+}
+
+void launch_student_table(hipStream_t s, const Dims &d, const EmbOffsets &eo, const double *ew, int prec, double shi,
+                          float *tab) {
+  const int nets = d.ntypes * d.ntypes, n = (TAB_K + 1) * d.ew[2];
+  hipLaunchKernelGGL(k_student_table, dim3((n + 127) / 128, nets), dim3(128), 0, s, d, eo, ew, prec, shi / TAB_K, tab);
+}
+
+// per atom the first real slot of each type block is its nearest neighbour
+// of that type (the list is distance-sorted), so the largest s is the
+// largest s of those slots; s >= 0, so its float bits order as unsigned
+__global__ void k_smax(int64_t n, Dims d, const int32_t *__restrict__ nreal, const float4 *__restrict__ rt,
+                       uint32_t *smax) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float m = 0.f;
+  if (i < n)
+    for (int u = 0; u < d.ntypes; ++u)
+      if (nreal[i * d.ntypes + u] > 0) m = fmaxf(m, rt[i * d.nnei + d.off[u]].x);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) atomicMax(smax, __builtin_bit_cast(uint32_t, m));
+}
+
+void launch_smax(hipStream_t s, int64_t n, const Dims &d, const int32_t *nreal, const float4 *rt, uint32_t *smax) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_smax, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, d, nreal, rt, smax);
+}
+
+// ---------------------------------------------------------------------------
 // cell-ordered backward: configuration and launch
 // ---------------------------------------------------------------------------
 constexpr size_t CELL_LDS_MAX = 160 * 1024;  // LDS of one CU
 
 template <int W1, int W2, int W3, int LIN>
-static bool cells_config_t(int nnets, int cap, int *threads, size_t *lds) {
+static bool cells_config_t(int nnets, int cap, size_t tab, int *threads, size_t *lds) {
   if constexpr (LIN == 0 || Shape<W1, W2, W3>::XL2) {
     return false;
   } else {
-    const size_t fixed = (size_t)nnets * LinShape<W1, W2, W3>::NET_BYTES + (size_t)27 * 3 * cap * sizeof(double);
+    const size_t fixed =
+        (size_t)nnets * LinShape<W1, W2, W3>::NET_BYTES + tab + (size_t)27 * 3 * cap * sizeof(double);
     const size_t budget = CELL_LDS_MAX - sizeof(double) * CELL_WAVES * 9;
     for (int nw = CELL_WAVES; nw >= 4; nw -= 4) {
       const size_t b = fixed + (size_t)nw * CellShape<W1, W2, W3>::W_BYTES;
@@ -1400,8 +1560,9 @@ bool embed_cells_config(const MixArgs &a, int cap, int *threads, size_t *lds) {
   if (cap < 1 || cap > 255) return false;
   const int nnets = a.d.ntypes * a.d.ntypes;
   int id = 0;
-#define X(a_, b_, c_, l_)                                                    \
-  if (a.shape == id) return cells_config_t<a_, b_, c_, l_>(nnets, cap, threads, lds); \
+  const size_t tab = a.tab ? (size_t)nnets * TAB_BYTES : 0;
+#define X(a_, b_, c_, l_)                                                         \
+  if (a.shape == id) return cells_config_t<a_, b_, c_, l_>(nnets, cap, tab, threads, lds); \
   ++id;
   DPK_MIX_SHAPES(X)
 #undef X

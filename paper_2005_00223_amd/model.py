@@ -118,6 +118,10 @@ class DPModel:
     def stats(self):
         return L.dp_get_stats(self.ctx)
 
+    def student_table(self, on: bool):
+        """Tabulated student layers (default on; mixed precision only)."""
+        L.dp_student_table(self.ctx, on)
+
     def set_force_scatter(self, mode: int):
         """0: cell-ordered LDS scatter where the path allows it (default);
         1: FP64 global atomics for every pair force."""
