@@ -47,19 +47,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic(spec, n_atoms, n_pairs, emb=None, affine=False, mixed=True):
+def algorithmic(spec, n_atoms, n_pairs, emb=None, affine=False, mixed=True, table=False):
     """Algorithmic work per evaluation, by kernel (no recompute, no padding):
     flops for the network kernels, bytes for the list/env kernels.  `emb`
     overrides the embedding widths (the student's 16-32-100); `affine`: the
     last embedding layer is affine, so T = W3^T (sum h2 R^T) + b3 (sum R)^T
-    and its products move from per pair to per atom."""
+    and its products move from per pair to per atom; `table`: h2(s) (and
+    dh2/ds) come from the cubic Hermite table, 4 multiply-adds per feature
+    each, instead of the first two layers."""
     emb = (1,) + tuple(emb if emb is not None else spec.emb)
     M1, M2 = spec.M1, spec.M2
     fw = (M1 * M2,) + tuple(spec.fit) + (1,)
     fit_macs = sum(fw[l] * fw[l + 1] for l in range(len(fw) - 1))
     if affine:
         W1, W2 = emb[1], emb[2]
-        hidden = W1 + W1 * W2          # layers 1 and 2 per pair
+        hidden = 4 * W2 if table else W1 + W1 * W2   # h2 per pair: table or layers 1 and 2
         # per pair: h2 R^T (4 W2); per atom: W3^T H (4 W2 M1), b3 sum R (4 M1), D (4 M1 M2)
         e_fwd = 2.0 * n_pairs * (hidden + 4 * W2) + 2.0 * n_atoms * (4 * W2 * M1 + 4 * M1 + 4 * M1 * M2)
         # per pair: h, h' through layers 1-2 (2 hidden), M^T h2 and M^T h2' (8 W2);
@@ -76,8 +78,8 @@ def algorithmic(spec, n_atoms, n_pairs, emb=None, affine=False, mixed=True):
         "embed_bwd": e_bwd,
         "fit": 2.0 * n_atoms * 2 * fit_macs,
         # bytes: per real slot nlist 4 B + neighbour position 32 B in, R (FP32 in
-        # mixed precision: 16 B, else 32 B) and (d, r) 32 B out
-        "env": n_pairs * (4 + 32 + (16 if mixed else 32) + 32.0) + n_atoms * (32 + 4 * spec.ntypes),
+        # mixed precision: 16 B, and no (d, r); else 32 B and (d, r) 32 B) out
+        "env": n_pairs * (4 + 32 + (16.0 if mixed else 64.0)) + n_atoms * (32 + 4 * spec.ntypes),
     }
 
 
@@ -249,7 +251,7 @@ def main():
     n_pairs = float(nr.sum().item())
     used_student = student and st["teacher_fallbacks"] == 0
     alg = algorithmic(spec, n, n_pairs, emb=(16, 32, spec.M1) if used_student else None, affine=used_student,
-                      mixed=args.precision != "fp64")
+                      mixed=args.precision != "fp64", table=used_student and st["table_evals"] > 0)
     kern = max(("format", "env", "embed_fwd", "fit", "embed_bwd"), key=lambda k: phases[k])
     thn = th.cpu().numpy()
     drift = float((thn[-1, 3] - thn[0, 3]) / n) if len(thn) > 1 else 0.0
