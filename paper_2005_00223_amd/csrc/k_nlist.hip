@@ -317,14 +317,24 @@ void launch_candidates(hipStream_t s, int64_t n, const double4 *xw, const CellGr
 // ---------------------------------------------------------------------------
 // formatting (Section V-A): one wave per atom, keys in LDS.  The keys are
 // ranked exactly by a bucketed counting sort: bucket = type * FMT_NB +
-// (quantised distance * FMT_NB) / (quantised rc + 1), monotone in the key,
-// so rank = (keys in lower buckets, from a prefix scan of the bucket
+// floor(FMT_NB (quantised distance / (quantised rc + 1))^3), monotone in the
+// key and holding equal expected counts (neighbours grow like r^3), so
+// rank = (keys in lower buckets, from a prefix scan of the bucket
 // histogram) + (smaller keys of the same bucket, from the bucket's linked
 // list in LDS).
 // ---------------------------------------------------------------------------
 constexpr int FMT_WAVES = 4;
 constexpr int FMT_CAP = KEY_CAP;
-constexpr int FMT_NB = 32;   // distance buckets per type
+constexpr int FMT_NB = 64;   // distance buckets per type
+
+// bucket of a key with type t and quantised distance qd < qlim; monotone
+// non-decreasing in (t, qd) (every step is), the same expression at insertion
+// and at ranking
+__device__ inline int fmt_bucket(int t, unsigned long long qd, unsigned long long qlim) {
+  const float x = (float)qd / (float)qlim;
+  const int b = (int)(x * x * x * (float)FMT_NB);
+  return t * FMT_NB + (b < FMT_NB - 1 ? b : FMT_NB - 1);
+}
 constexpr int FMT_BATCH = 4; // candidate gathers in flight per lane
 
 __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__restrict__ xw, Dims d, double L0,
@@ -392,7 +402,7 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
         unsigned long long qd = (unsigned long long)floor(r * 1e8);
         unsigned long long key = ((unsigned long long)tj << 58) | (qd << 26) | (unsigned long long)j;
         keys[wv][slot] = key;
-        const int b = tj * FMT_NB + (int)((qd * FMT_NB) / qlim);
+        const int b = fmt_bucket(tj, qd, qlim);
         next[wv][slot] = (int16_t)atomicExch(&head[wv][b], slot);
         atomicAdd(&bstart[wv][b], 1);
       }
@@ -444,7 +454,7 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
   for (int q = lane; q < k; q += 64) {
     const unsigned long long key = keys[wv][q];
     const int t = (int)(key >> 58);
-    const int b = t * FMT_NB + (int)((((key >> 26) & 0xffffffffull) * FMT_NB) / qlim);
+    const int b = fmt_bucket(t, (key >> 26) & 0xffffffffull, qlim);
     int rank = bstart[wv][b];
     for (int m = head[wv][b]; m >= 0; m = next[wv][m]) rank += (keys[wv][m] < key) ? 1 : 0;
     int ts = 0;
