@@ -156,7 +156,7 @@ struct Student {
   int64_t cap_draw = 0;  // samples per net one draw (several batches) can hold
   void *base = nullptr;
   float *params = nullptr, *m = nullptr, *v = nullptr, *gpart = nullptr, *wt = nullptr, *gout = nullptr;
-  double *lpart = nullptr, *s = nullptr, *G = nullptr, *lspart = nullptr, *X = nullptr, *chk = nullptr,
+  double *lpart = nullptr, *s = nullptr, *G = nullptr, *lspart = nullptr, *lsfold = nullptr, *X = nullptr, *chk = nullptr,
          *loss = nullptr;
   int32_t *status = nullptr;
   bool have_params = false;
@@ -965,6 +965,7 @@ int ensure_student(dp_ctx *c, int64_t batch) {
   add((void **)&st->wt, sizeof(float) * nets * capd);
   add((void **)&st->G, sizeof(double) * nets * capd * M1);
   add((void **)&st->lspart, sizeof(double) * nets * st_ls_blocks() * NE);
+  add((void **)&st->lsfold, sizeof(double) * nets * ST_LS_FOLD * NE);
   add((void **)&st->X, sizeof(double) * nets * SNF * M1);
   add((void **)&st->chk, sizeof(double) * nets * nblk * 2);
   add((void **)&st->loss, sizeof(double) * nets);
@@ -1652,27 +1653,26 @@ int dp_student_train(dp_ctx *c, const dp_student_cfg *cfg, double *fit_rmse) {
     for (int64_t b0 = 0; b0 < nls; b0 += nbmax) {
       const int nb = (int)std::min<int64_t>(nbmax, nls - b0);
       st_draw(c, g.seed, ST_Q_LS + b0 * g.batch, g.batch, nb);
-      for (int k = 0; k < nb; ++k) {
-        const int64_t o = (int64_t)k * st->nets * g.batch;
-        StLsArgs la{};
-        la.M1 = st->M1;
-        la.nets = st->nets;
-        la.batch = (int)g.batch;
-        la.nblk = st_ls_blocks();
-        la.params = st->params;
-        la.quant = quant;
-        la.s = st->s + o;
-        la.wt = st->wt + o;
-        la.G = st->G + o * st->M1;
-        la.part = st->lspart;
-        launch_st_ls(s, la);
-      }
+      StLsArgs la{};
+      la.M1 = st->M1;
+      la.nets = st->nets;
+      la.batch = (int)g.batch;
+      la.nblk = st_ls_blocks();
+      la.nb = nb;
+      la.params = st->params;
+      la.quant = quant;
+      la.s = st->s;
+      la.wt = st->wt;
+      la.G = st->G;
+      la.part = st->lspart;
+      launch_st_ls(s, la);
     }
+    launch_st_lsfold(s, st->M1, st->nets, st_ls_blocks(), st->lspart, st->lsfold);
     StSolveArgs va{};
     va.M1 = st->M1;
     va.nets = st->nets;
-    va.nblk = st_ls_blocks();
-    va.part = st->lspart;
+    va.nblk = ST_LS_FOLD;
+    va.part = st->lsfold;
     va.ridge = g.ridge;
     va.quant = quant;
     va.X = st->X;

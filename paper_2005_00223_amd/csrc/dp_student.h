@@ -93,7 +93,8 @@ struct StAdamArgs {
 void launch_st_adam(hipStream_t st, const StAdamArgs &a);
 
 struct StLsArgs {
-  int M1, nets, batch, nblk;   // nblk blocks per net share the batch
+  int M1, nets, batch, nblk;   // nblk blocks per net share the samples
+  int nb;                      // batches of the draw ([nb][nets][batch] layout)
   const float *params;
   int quant;                   // -1 exact, 0 FP16, 1 BF16 rounding of W2
   const double *s;
@@ -103,6 +104,9 @@ struct StLsArgs {
 };
 void launch_st_ls(hipStream_t st, const StLsArgs &a);
 int st_ls_blocks();
+constexpr int ST_LS_FOLD = 32;  // slices the least-squares partials are folded into before the solve
+// fold[net][slice][e] = sum of part[net][b][e] over the slice's blocks b (nblk % ST_LS_FOLD == 0)
+void launch_st_lsfold(hipStream_t st, int M1, int nets, int nblk, const double *part, double *fold);
 
 struct StSolveArgs {
   int M1, nets, nblk;

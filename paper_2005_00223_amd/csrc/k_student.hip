@@ -298,8 +298,9 @@ void launch_st_adam(hipStream_t st, const StAdamArgs &a) {
 //     A = sum w phi phi^T (SNF x SNF), B = sum w phi G^T (SNF x M1),
 //     phi = (h2(s), 1); each block accumulates its share into its partial
 // ---------------------------------------------------------------------------
-constexpr int LS_BLOCKS = 128;
+constexpr int LS_BLOCKS = 2048;  // enough 64-sample groups in flight for a whole draw
 constexpr int LS_MAXE = (SNF * SNF + SNF * 128 + 63) / 64;  // entries per thread, M1 <= 128
+static_assert(LS_BLOCKS % ST_LS_FOLD == 0, "the fold takes equal runs of blocks");
 int st_ls_blocks() { return LS_BLOCKS; }
 
 __device__ inline void st_hidden_f64(const float *P, const StudentLayout &L, int quant, double s,
@@ -329,9 +330,10 @@ __global__ void __launch_bounds__(64) k_st_ls(StLsArgs a) {
   double acc[LS_MAXE];
 #pragma unroll
   for (int k = 0; k < LS_MAXE; ++k) acc[k] = 0.0;
-  const int ngroups = a.batch / 64;
+  const int gpb = a.batch / 64, ngroups = gpb * a.nb;  // 64-sample groups per batch, in the draw
   for (int gidx = blk; gidx < ngroups; gidx += a.nblk) {
-    const int64_t q = (int64_t)net * a.batch + (int64_t)gidx * 64 + tid;
+    const int kb = gidx / gpb, gq = gidx % gpb;
+    const int64_t q = ((int64_t)kb * a.nets + net) * a.batch + (int64_t)gq * 64 + tid;
     const double w = (double)a.wt[q];
     double h2[SH2];
     st_hidden_f64(P, L, a.quant, a.s[q], h2);
@@ -372,6 +374,20 @@ __global__ void __launch_bounds__(64) k_st_ls(StLsArgs a) {
 void launch_st_ls(hipStream_t st, const StLsArgs &a) {
   const size_t shm = sizeof(double) * (size_t)(SNF + a.M1) * SP;
   hipLaunchKernelGGL(k_st_ls, dim3(a.nblk, a.nets), dim3(64), shm, st, a);
+}
+
+__global__ void k_st_lsfold(int NE, int nblk, const double *__restrict__ part, double *__restrict__ fold) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x, net = blockIdx.y, sl = blockIdx.z;
+  if (e >= NE) return;
+  const int per = nblk / ST_LS_FOLD;
+  double v = 0.0;
+  for (int b = sl * per; b < (sl + 1) * per; ++b) v += part[((int64_t)net * nblk + b) * NE + e];
+  fold[((int64_t)net * ST_LS_FOLD + sl) * NE + e] = v;
+}
+
+void launch_st_lsfold(hipStream_t st, int M1, int nets, int nblk, const double *part, double *fold) {
+  const int NE = SNF * SNF + SNF * M1;
+  hipLaunchKernelGGL(k_st_lsfold, dim3((NE + 255) / 256, nets, ST_LS_FOLD), dim3(256), 0, st, NE, nblk, part, fold);
 }
 
 // ---------------------------------------------------------------------------
