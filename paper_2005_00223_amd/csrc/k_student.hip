@@ -149,7 +149,8 @@ __device__ inline void st_hidden_f32(const float *P, const StudentLayout &L, flo
 //     samples; wave w takes output features [w*oc, (w+1)*oc) of every sample,
 //     the four partial dE/dh2 meet in LDS
 // ---------------------------------------------------------------------------
-constexpr int GR_WAVES = 4;
+constexpr int GR_WAVES = 8;
+constexpr int GSP = 68;  // LDS row stride of the gradient kernel (samples): 16-byte rows for float4 sums
 
 __global__ void __launch_bounds__(64 * GR_WAVES) k_st_grad(StGradArgs a) {
   extern __shared__ float gsh[];
@@ -158,13 +159,13 @@ __global__ void __launch_bounds__(64 * GR_WAVES) k_st_grad(StGradArgs a) {
   const int net = blockIdx.y, blk = blockIdx.x, nblk = gridDim.x;
   const int tid = threadIdx.x, m = tid & 63, wv = tid >> 6;
   float *P = gsh;                   // [np]
-  float *ss = P + L.np;             // [64]
-  float *h1s = ss + 64;             // [SH1][SP]
-  float *dz1s = h1s + SH1 * SP;     // [SH1][SP]
-  float *h2s = dz1s + SH1 * SP;     // [SH2][SP]
-  float *dz2s = h2s + SH2 * SP;     // [SH2][SP]
-  float *rs = dz2s + SH2 * SP;      // [M1][SP]
-  float *dhp = rs + M1 * SP;        // [GR_WAVES][SH2][SP] partial dE/dh2
+  float *ss = P + ((L.np + 3) & ~3); // [64], 16-byte aligned
+  float *h1s = ss + 64;             // [SH1][GSP]
+  float *dz1s = h1s + SH1 * GSP;     // [SH1][GSP]
+  float *h2s = dz1s + SH1 * GSP;     // [SH2][GSP]
+  float *dz2s = h2s + SH2 * GSP;     // [SH2][GSP]
+  float *rs = dz2s + SH2 * GSP;      // [M1][GSP]
+  float *dhp = rs + M1 * GSP;        // [GR_WAVES][SH2][GSP] partial dE/dh2
   __shared__ double red[2][64 * GR_WAVES];
   const float *Pg = a.params + (int64_t)net * L.np;
   for (int e = tid; e < L.np; e += 64 * GR_WAVES) P[e] = Pg[e];
@@ -187,19 +188,24 @@ __global__ void __launch_bounds__(64 * GR_WAVES) k_st_grad(StGradArgs a) {
     for (int k = 0; k < SH2; ++k) g += h2[k] * P[L.o_w3 + k * M1 + o];
     const float r = w * (g - (float)Gt[o]);
     lsum += (double)r * r;
-    rs[o * SP + m] = r;
+    rs[o * GSP + m] = r;
 #pragma unroll
     for (int k = 0; k < SH2; ++k) dh2[k] += P[L.o_w3 + k * M1 + o] * r;
   }
 #pragma unroll
-  for (int k = 0; k < SH2; ++k) dhp[(wv * SH2 + k) * SP + m] = dh2[k];
+  for (int k = 0; k < SH2; ++k) dhp[(wv * SH2 + k) * GSP + m] = dh2[k];
   red[0][tid] = lsum;
   red[1][tid] = wv == 0 ? (double)w : 0.0;
   __syncthreads();
   if (wv == 0) {
 #pragma unroll
     for (int k = 0; k < SH2; ++k)
-      dh2[k] = dhp[k * SP + m] + dhp[(SH2 + k) * SP + m] + dhp[(2 * SH2 + k) * SP + m] + dhp[(3 * SH2 + k) * SP + m];
+    {
+      float v = 0.f;
+#pragma unroll
+      for (int w2 = 0; w2 < GR_WAVES; ++w2) v += dhp[(w2 * SH2 + k) * GSP + m];
+      dh2[k] = v;
+    }
     float dz2[SH2];
 #pragma unroll
     for (int j = 0; j < SH2; ++j) dz2[j] = dh2[j] * (1.f - t2[j] * t2[j]);
@@ -208,38 +214,54 @@ __global__ void __launch_bounds__(64 * GR_WAVES) k_st_grad(StGradArgs a) {
       float g = dh2[i] + dh2[i + SH1];
 #pragma unroll
       for (int j = 0; j < SH2; ++j) g += P[L.o_w2 + i * SH2 + j] * dz2[j];
-      dz1s[i * SP + m] = g * (1.f - t1[i] * t1[i]);
-      h1s[i * SP + m] = t1[i];
+      dz1s[i * GSP + m] = g * (1.f - t1[i] * t1[i]);
+      h1s[i * GSP + m] = t1[i];
     }
 #pragma unroll
     for (int j = 0; j < SH2; ++j) {
-      h2s[j * SP + m] = h2[j];
-      dz2s[j * SP + m] = dz2[j];
+      h2s[j * GSP + m] = h2[j];
+      dz2s[j * GSP + m] = dz2[j];
     }
     ss[m] = s;
   }
   __syncthreads();
   // sums over the 64 samples of the block, parameter by parameter
   float *gp = a.gpart + ((int64_t)net * nblk + blk) * L.np;
+  // 64-sample dot products and sums in float4 steps (rows are 16-byte aligned)
+  auto dot64 = [](const float *x, const float *y) {
+    float acc = 0.f;
+#pragma unroll 4
+    for (int k = 0; k < 64; k += 4) {
+      const float4 u = *(const float4 *)(x + k), v = *(const float4 *)(y + k);
+      acc += (u.x * v.x + u.y * v.y) + (u.z * v.z + u.w * v.w);
+    }
+    return acc;
+  };
+  auto sum64 = [](const float *x) {
+    float acc = 0.f;
+#pragma unroll 4
+    for (int k = 0; k < 64; k += 4) {
+      const float4 u = *(const float4 *)(x + k);
+      acc += (u.x + u.y) + (u.z + u.w);
+    }
+    return acc;
+  };
   for (int e = tid; e < L.np; e += 64 * GR_WAVES) {
     float acc = 0.f;
     if (e < L.o_b1) {
-      for (int k = 0; k < 64; ++k) acc += ss[k] * dz1s[e * SP + k];
+      acc = dot64(ss, dz1s + e * GSP);
     } else if (e < L.o_w2) {
-      const int i = e - L.o_b1;
-      for (int k = 0; k < 64; ++k) acc += dz1s[i * SP + k];
+      acc = sum64(dz1s + (e - L.o_b1) * GSP);
     } else if (e < L.o_b2) {
       const int i = (e - L.o_w2) / SH2, j = (e - L.o_w2) % SH2;
-      for (int k = 0; k < 64; ++k) acc += h1s[i * SP + k] * dz2s[j * SP + k];
+      acc = dot64(h1s + i * GSP, dz2s + j * GSP);
     } else if (e < L.o_w3) {
-      const int j = e - L.o_b2;
-      for (int k = 0; k < 64; ++k) acc += dz2s[j * SP + k];
+      acc = sum64(dz2s + (e - L.o_b2) * GSP);
     } else if (e < L.o_b3) {
       const int kk = (e - L.o_w3) / M1, o = (e - L.o_w3) % M1;
-      for (int k = 0; k < 64; ++k) acc += h2s[kk * SP + k] * rs[o * SP + k];
+      acc = dot64(h2s + kk * GSP, rs + o * GSP);
     } else {
-      const int o = e - L.o_b3;
-      for (int k = 0; k < 64; ++k) acc += rs[o * SP + k];
+      acc = sum64(rs + (e - L.o_b3) * GSP);
     }
     gp[e] = acc;
   }
@@ -253,7 +275,7 @@ __global__ void __launch_bounds__(64 * GR_WAVES) k_st_grad(StGradArgs a) {
 void launch_st_grad(hipStream_t st, const StGradArgs &a) {
   const StudentLayout L = student_layout(a.M1);
   const size_t shm =
-      sizeof(float) * ((size_t)L.np + 64 + (size_t)(2 * SH1 + 2 * SH2 + a.M1 + GR_WAVES * SH2) * SP);
+      sizeof(float) * ((size_t)((L.np + 3) & ~3) + 64 + (size_t)(2 * SH1 + 2 * SH2 + a.M1 + GR_WAVES * SH2) * GSP);
   hipLaunchKernelGGL(k_st_grad, dim3(a.batch / 64, a.nets), dim3(64 * GR_WAVES), shm, st, a);
 }
 
