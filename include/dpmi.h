@@ -77,6 +77,7 @@ typedef struct {
   int64_t judge_atoms;       /* atoms the last judge covered                 */
   int64_t cell_scatter;      /* backward passes with the cell-ordered scatter */
   int64_t table_evals;       /* student evaluations with the tabulated layers */
+  int64_t wide_evals;        /* evaluations through the wide-net GEMM path */
 } dp_stats;
 
 /* Create a context on HIP device `device`; `hip_stream` is a hipStream_t

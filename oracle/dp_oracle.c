@@ -38,6 +38,7 @@
 
 #define OR_MAXT 8
 #define OR_MAXL 8
+#define OR_WMAX 32768 /* widest layer input or output, D = M1*M2 included */
 
 typedef struct {
   int64_t ntypes, n_emb, n_fit, M2, M1, nnei;
@@ -110,6 +111,8 @@ void *or_model_new(const void *blob, int64_t nbytes) {
   m->fit_w[0] = m->M1 * m->M2;
   for (l = 1; l <= m->n_fit; ++l) if (rd_i64(&p, end, &m->fit_w[l]) || m->fit_w[l] < 1) goto bad;
   m->fit_w[m->n_fit + 1] = 1;
+  for (l = 0; l <= m->n_emb; ++l) if (m->emb_w[l] > OR_WMAX) goto bad;
+  for (l = 0; l <= m->n_fit; ++l) if (m->fit_w[l] > OR_WMAX) goto bad;
   {
     int64_t total = 0;
     for (t = 0; t < m->ntypes; ++t)
@@ -419,7 +422,6 @@ static void or_layer_bwd(const double *W, int64_t in, int64_t out, const double 
   }
 }
 
-#define OR_WMAX 4096
 
 /* Embedding net of pair (t,u) at input s; stores per-layer tanh outputs in
  * tt (row l at tt + l*OR_WMAX) and per-layer inputs in hh.  G -> out. */

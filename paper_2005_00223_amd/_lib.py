@@ -28,7 +28,8 @@ class dp_stats(C.Structure):
     _fields_ = [("natoms", C.c_int64), ("sel_overflow", C.c_int64), ("max_real", C.c_int32 * 8),
                 ("nlist_builds", C.c_int64), ("evaluations", C.c_int64), ("cand_cap", C.c_int64),
                 ("student_evals", C.c_int64), ("teacher_fallbacks", C.c_int64), ("last_judge_rmse", C.c_double),
-                ("judge_atoms", C.c_int64), ("cell_scatter", C.c_int64), ("table_evals", C.c_int64)]
+                ("judge_atoms", C.c_int64), ("cell_scatter", C.c_int64), ("table_evals", C.c_int64),
+                ("wide_evals", C.c_int64)]
 
 
 class dp_student_cfg(C.Structure):

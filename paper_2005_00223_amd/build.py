@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libdpmi.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.cpp", "k_nlist.hip", "k_env.hip", "k_embed_f64.hip", "k_fit_f64.hip", "k_md.hip",
-           "k_embed_mix.hip", "k_fit_mix.hip", "k_student.hip"]
+           "k_embed_mix.hip", "k_embed_wide.hip", "k_fit_mix.hip", "k_student.hip"]
 EXACT_FP = {"k_nlist.hip"}
 
 

@@ -11,6 +11,7 @@
 
 #include "dp_internal.h"
 #include "dp_mix.h"
+#include "dp_wide.h"
 #include "dp_student.h"
 #include "dpmi.h"
 
@@ -171,6 +172,9 @@ struct EmbNets {
   unsigned char *d_mix = nullptr;   // mixed-precision LDS images
   int mix_shape = -1;
   float *d_tab = nullptr;           // tabulated second layer (student nets, mixed precision)
+  unsigned char *d_wide = nullptr;  // wide nets (mixed precision): packed GEMM weights
+  WideNet wnet[WIDE_NETS]{};        // their per-net offsets
+  bool wide = false;
   double tab_shi = 0.0;             // its range of s
   bool tab_ok = false;
   bool ready = false;
@@ -214,6 +218,18 @@ struct dp_ctx {
   int64_t ev_cap = 0;   // evaluations the event ring holds
   int64_t last_n = 0;
   bool fwd_ready = false;  // dp_energy ran; dp_energy_backward may follow
+  // wide embedding path: pair offsets, per-net counts, two activation buffers
+  struct {
+    int32_t *poff = nullptr, *cnt = nullptr;
+    int64_t n_cap = 0;
+    uint16_t *X[2] = {nullptr, nullptr};
+    size_t x_cap = 0;  // elements per activation buffer
+    int64_t row0[WIDE_NETS + 1]{};
+    int32_t cnt_h[WIDE_NETS]{};
+    int out = 0;       // buffer holding G after the forward
+    bool ok = false;   // the forward of this evaluation ran
+  } wb;
+  int pending_rc = DP_OK;  // an error inside an evaluation (reported by read_status)
   std::string err;
 };
 
@@ -233,6 +249,16 @@ int fail(dp_ctx *c, int code, const std::string &msg) {
 void free_ws(Workspace &w) {
   if (w.base) (void)hipFree(w.base);
   w = Workspace{};
+}
+
+void free_wide(dp_ctx *c) {
+  for (void *p : {(void *)c->wb.poff, (void *)c->wb.X[0], (void *)c->wb.X[1]})
+    if (p) (void)hipFree(p);
+  c->wb.poff = c->wb.cnt = nullptr;
+  c->wb.X[0] = c->wb.X[1] = nullptr;
+  c->wb.n_cap = 0;
+  c->wb.x_cap = 0;
+  c->wb.ok = false;
 }
 
 void free_student(dp_ctx *c) {
@@ -360,10 +386,17 @@ int emb_dims(dp_ctx *c, const HostModel &m, Dims &d) {
   }
   if (d.ew[d.n_emb] != d.M1) return fail(c, DP_E_MODEL, "embedding output width must equal M1");
   for (int l = 1; l <= d.n_emb; ++l)
-    if (d.emp[l] > 128) return fail(c, DP_E_MODEL, "embedding widths above 128 are not supported");
-  if (dpk::embed_lds_bytes(d, 1) > 65536 || dpk::embed_lds_bytes(d, 2) > 65536)
-    return fail(c, DP_E_MODEL, "embedding net too wide for the per-wave LDS tiles");
+    if (d.ew[l] > 2048) return fail(c, DP_E_MODEL, "embedding widths above 2048 are not supported");
   return DP_OK;
+}
+
+// Whether the FP64 embedding kernels take these widths (per-wave LDS tiles).
+bool f64_emb_ok(const Dims &d, const char **why) {
+  for (int l = 1; l <= d.n_emb; ++l)
+    if (d.emp[l] > 128) return *why = "FP64 embedding kernels take widths up to 128 (wider nets: mixed precision)", false;
+  if (dpk::embed_lds_bytes(d, 1) > 65536 || dpk::embed_lds_bytes(d, 2) > 65536)
+    return *why = "embedding net too wide for the per-wave LDS tiles", false;
+  return true;
 }
 
 // FP64 padded embedding weights of model m into en.
@@ -478,9 +511,33 @@ int upload_emb_mix(dp_ctx *c, const HostModel &m, EmbNets &en) {
   const Dims &d = en.d;
   const int prec = c->precision == DP_MIX_FP16 ? 0 : 1;
   const int shape = mix_shape_id(d);
-  if (shape < 0)
-    return fail(c, DP_E_MODEL,
-                "mixed precision supports embedding widths 25-50-100 and 16-32-100 (tanh or affine last layer)");
+  if (en.d_wide) (void)hipFree(en.d_wide);
+  en.d_wide = nullptr;
+  en.wide = false;
+  if (shape < 0) {
+    // nets wider than the register-resident kernels: the GEMM path
+    const char *why = nullptr;
+    if (!wide_supported(d, &why))
+      return fail(c, DP_E_MODEL,
+                  std::string("mixed precision takes embedding widths 25-50-100 and 16-32-100 (register-resident) "
+                              "or wide nets: ") + why);
+    const int T = d.ntypes;
+    std::vector<unsigned char> buf;
+    for (int t = 0; t < T; ++t)
+      for (int u = 0; u < T; ++u) {
+        const double *W[MAXL], *b[MAXL];
+        for (int l = 0; l < d.n_emb; ++l) {
+          W[l] = m.eW[m.eidx(t, u, l)].data();
+          b[l] = m.eb[m.eidx(t, u, l)].data();
+        }
+        wide_pack_net(d, W, b, prec, buf, en.wnet[t * T + u]);
+      }
+    HIPCHK(c, hipMalloc(&en.d_wide, buf.size()));
+    HIPCHK(c, hipMemcpy(en.d_wide, buf.data(), buf.size(), hipMemcpyHostToDevice));
+    en.wide = true;
+    en.mix_shape = -1;
+    return DP_OK;
+  }
   if (mix_lds_bytes(shape, d.ntypes, 2) > 163840 || mix_lds_bytes(shape, d.ntypes, 1) > 163840)
     return fail(c, DP_E_MODEL, "too many atom types for the mixed-precision LDS layout");
   const size_t nb = mix_net_bytes(shape);
@@ -720,6 +777,106 @@ int ensure_table(dp_ctx *c, int64_t n) {
   return DP_OK;
 }
 
+// Arguments of the wide-path kernels (buffers as laid out by wide_forward).
+WideArgs wide_args(dp_ctx *c, int64_t n) {
+  Workspace &w = c->ws;
+  const EmbNets &en = c->en[c->active];
+  WideArgs a{};
+  a.d = en.d;
+  a.prec = c->precision == DP_MIX_FP16 ? 0 : 1;
+  a.n = n;
+  a.xw = w.xw;
+  a.nlist = w.nlist;
+  a.nreal = w.nreal;
+  a.rt = w.rt32;
+  for (int k = 0; k < 3; ++k) a.L[k] = c->box_L[k];
+  a.poff = c->wb.poff;
+  a.cnt = c->wb.cnt;
+  const int nets = en.d.ntypes * en.d.ntypes;
+  for (int k = 0; k < nets; ++k) {
+    a.row0[k] = c->wb.row0[k];
+    a.w0[k] = (const float *)(en.d_wide + en.wnet[k].w[0]);
+    a.b0[k] = (const float *)(en.d_wide + en.wnet[k].b[0]);
+  }
+  a.X0 = c->wb.X[0];
+  a.G = c->wb.X[c->wb.out];
+  a.T32 = w.T32;
+  a.dT32 = w.dT32;
+  a.vir_part = w.vir_part;
+  a.net_deriv = c->keep ? w.net_deriv : nullptr;
+  return a;
+}
+
+// Wide embedding nets, forward: pair counts (one host read-back: the
+// activation rows are laid out per net from them), layer 0, the GEMM layers
+// (value and tangent rows), T.  Buffers grow by 1/4 beyond the need.
+int wide_forward(dp_ctx *c, int64_t n) {
+  auto &wb = c->wb;
+  const EmbNets &en = c->en[c->active];
+  const Dims &d = en.d;
+  hipStream_t s = c->stream;
+  const int T = d.ntypes, nets = T * T;
+  wb.ok = false;
+  if (n > wb.n_cap) {
+    if (wb.poff) (void)hipFree(wb.poff);
+    wb.poff = wb.cnt = nullptr;
+    wb.n_cap = 0;
+    const int64_t cap = n + n / 4;
+    if (hipMalloc(&wb.poff, sizeof(int32_t) * ((size_t)cap * T + WIDE_NETS)) != hipSuccess)
+      return fail(c, DP_E_OOM, "wide embedding: out of device memory (pair offsets)");
+    wb.cnt = wb.poff + (size_t)cap * T;
+    wb.n_cap = cap;
+  }
+  launch_fill_u32(s, (uint32_t *)wb.cnt, nets, 0u);
+  WideArgs a = wide_args(c, n);
+  launch_wide_count(s, a);
+  HIPCHK(c, hipMemcpyAsync(wb.cnt_h, wb.cnt, sizeof(int32_t) * nets, hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  wb.row0[0] = 0;
+  for (int k = 0; k < nets; ++k)
+    wb.row0[k + 1] = wb.row0[k] + (2 * (int64_t)wb.cnt_h[k] + WIDE_BM - 1) / WIDE_BM * WIDE_BM;
+  int maxw = 0;
+  for (int l = 1; l <= d.n_emb; ++l) maxw = std::max(maxw, d.ew[l]);
+  const size_t need = (size_t)wb.row0[nets] * maxw;
+  if (need > wb.x_cap) {
+    for (auto &x : wb.X) {
+      if (x) (void)hipFree(x);
+      x = nullptr;
+    }
+    wb.x_cap = 0;
+    const size_t cap = need + need / 4;
+    if (hipMalloc(&wb.X[0], 2 * cap) != hipSuccess || hipMalloc(&wb.X[1], 2 * cap) != hipSuccess)
+      return fail(c, DP_E_OOM, "wide embedding: out of device memory (activations)");
+    wb.x_cap = cap;
+  }
+  wb.out = 0;
+  a = wide_args(c, n);
+  launch_wide_l0(s, a);
+  int cur = 0;
+  for (int l = 1; l < d.n_emb; ++l) {
+    const int K = d.ew[l], N = d.ew[l + 1];
+    for (int k = 0; k < nets; ++k) {
+      if (wb.cnt_h[k] == 0) continue;
+      WideGemm g{};
+      g.A = wb.X[cur] + wb.row0[k] * K;
+      g.Bt = (const uint16_t *)(en.d_wide + en.wnet[k].w[l]);
+      g.bias = (const float *)(en.d_wide + en.wnet[k].b[l]);
+      g.Y = wb.X[cur ^ 1] + wb.row0[k] * N;
+      g.rows = wb.row0[k + 1] - wb.row0[k];
+      g.K = K;
+      g.N = N;
+      g.skip = N == K ? 1 : (N == 2 * K ? 2 : 0);
+      launch_wide_gemm(s, g, a.prec);
+    }
+    cur ^= 1;
+  }
+  wb.out = cur;
+  a = wide_args(c, n);
+  launch_wide_T(s, a);
+  wb.ok = true;
+  return DP_OK;
+}
+
 // Networks of the forward half with the active embedding set: embedding +
 // descriptor, fitting net forward, energy into E.
 void eval_nets_fwd(dp_ctx *c, int64_t n, double *E) {
@@ -732,9 +889,15 @@ void eval_nets_fwd(dp_ctx *c, int64_t n, double *E) {
     launch_fit_f64(s, fit_args(c, rows), 1);
   } else {
     (void)ensure_table(c, n);  // a failed table build leaves tab_ok false: the layers are evaluated
-    const MixArgs ma = mix_args(c, rows, nullptr);
-    if (ma.tab) c->stats.table_evals += 1;
-    launch_embed_mix(s, ma, 1, mix_grid(rows));
+    if (c->en[c->active].wide) {
+      const int rc = wide_forward(c, n);
+      if (rc) c->pending_rc = rc;
+      c->stats.wide_evals += 1;
+    } else {
+      const MixArgs ma = mix_args(c, rows, nullptr);
+      if (ma.tab) c->stats.table_evals += 1;
+      launch_embed_mix(s, ma, 1, mix_grid(rows));
+    }
     tmark(c, 4);
     launch_fit_mix(s, fitmix_args(c, rows), 1);
   }
@@ -791,6 +954,20 @@ void eval_backward(dp_ctx *c, int64_t n, double *F, double *V) {
     tmark(c, 5);
     launch_zero(s, F, 3 * n);
     tmark(c, 6);
+    if (c->en[c->active].wide) {
+      if (c->wb.ok) {
+        WideArgs a = wide_args(c, n);
+        a.force = F;
+        launch_wide_bwd(s, a);
+        tmark(c, 7);
+        launch_sum9(s, w.vir_part, (int)std::min<int64_t>(n, WIDE_GRID), V);
+      } else {
+        tmark(c, 7);
+        launch_zero(s, V, 9);
+      }
+      tnext(c);
+      return;
+    }
     const MixArgs ma = mix_args(c, rows, F);
     CellArgs ca{};
     int threads = 0;
@@ -844,6 +1021,11 @@ void build_lists(dp_ctx *c, int64_t n, const CellGrid &g, double rlist, const ui
 int read_status(dp_ctx *c) {
   HIPCHK(c, hipMemcpyAsync(c->h_status, c->ws.status, sizeof(DevStatus), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->pending_rc != DP_OK) {
+    const int rc = c->pending_rc;
+    c->pending_rc = DP_OK;
+    return rc;
+  }
   c->stats.sel_overflow = (int64_t)c->h_status->overflow;
   for (int t = 0; t < MAXT; ++t) c->stats.max_real[t] = c->h_status->max_real[t];
   c->stats.nlist_builds = (int64_t)c->h_status->nbuild;
@@ -1214,7 +1396,9 @@ void dp_destroy(dp_ctx *c) {
     if (en.d_emb) (void)hipFree(en.d_emb);
     if (en.d_mix) (void)hipFree(en.d_mix);
     if (en.d_tab) (void)hipFree(en.d_tab);
+    if (en.d_wide) (void)hipFree(en.d_wide);
   }
+  free_wide(c);
   free_student(c);
   if (c->d_fit) (void)hipFree(c->d_fit);
   if (c->d_fit_mix) (void)hipFree(c->d_fit_mix);
@@ -1242,6 +1426,8 @@ int dp_set_model(dp_ctx *c, const void *blob, size_t nbytes, int precision) {
   if (c->st) c->st->have_params = false;
   int rc = upload_model(c);
   if (rc) return rc;
+  const char *why = nullptr;
+  if (precision == DP_FP64 && !f64_emb_ok(c->dims, &why)) return fail(c, DP_E_MODEL, why);
   c->precision = precision;
   if (precision != DP_FP64) {
     rc = upload_mix(c);
@@ -1256,6 +1442,8 @@ int dp_set_precision(dp_ctx *c, int precision) {
   if (!c->has_model) return fail(c, DP_E_NOMODEL, "no model");
   if (precision != DP_FP64 && precision != DP_MIX_FP16 && precision != DP_MIX_BF16)
     return fail(c, DP_E_ARG, "unsupported precision policy");
+  const char *why = nullptr;
+  if (precision == DP_FP64 && !f64_emb_ok(c->dims, &why)) return fail(c, DP_E_MODEL, why);
   const int old = c->precision;
   c->precision = precision;
   if (precision != DP_FP64) {

@@ -108,13 +108,6 @@ __device__ inline Split8<0> split8<0>(const float (&x)[4], const float (&y)[4]) 
   return s;
 }
 
-// tanh(x) = 1 - 2 / (exp(2x) + 1) with the hardware exp2 and reciprocal;
-// absolute error about 2e-7, well below the 16-bit storage of the layers.
-__device__ inline float tanh_f(float x) {
-  const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);
-  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
-}
-
 __device__ inline void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -464,50 +457,6 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 1>::B)) k_embed_fw
 // ---------------------------------------------------------------------------
 // pass 2
 // ---------------------------------------------------------------------------
-__device__ inline void switch64(double r, double rcs, double rc, double inv_w, double &sw, double &dsw) {
-  if (r < rcs) {
-    sw = 1.0;
-    dsw = 0.0;
-  } else if (r < rc) {
-    const double x = (r - rcs) * inv_w;
-    sw = x * x * x * (-6.0 * x * x + 15.0 * x - 10.0) + 1.0;
-    dsw = x * x * (-30.0 * x * x + 60.0 * x - 30.0) * inv_w;
-  } else {
-    sw = 0.0;
-    dsw = 0.0;
-  }
-}
-
-// FP64 force pass for one real slot: g = dE/dR of the slot (FP32 from the
-// networks), chain rule through R(r_ij) in FP64, F_i accumulated by the
-// caller, F_j -= g_ij by an atomic, virial -= g_ij (x) r_ij.
-// FP64 force of one pair from dE/dR (gr) and the neighbour's displacement
-// D4 = (dx, dy, dz, r): g = dE/dr_ij (F_i += g, F_j -= g), accumulated into
-// fi and the virial
-__device__ inline void pair_force(const double4 &D4, float4 gr, double rc, double rcs, double inv_w, double &gx,
-                                  double &gy, double &gz, double &fi0, double &fi1, double &fi2, double (&vir)[9]) {
-  const double g0 = gr.x, g1 = gr.y, g2 = gr.z, g3 = gr.w;
-  const double dx = D4.x, dy = D4.y, dz = D4.z, r = D4.w;
-  double sw, dsw;
-  switch64(r, rcs, rc, inv_w, sw, dsw);
-  const double ir = 1.0 / r;
-  const double sv = sw * ir;
-  const double ds = (dsw * r - sw) * ir * ir;
-  const double tt = sv * ir;
-  const double dtt = dsw * ir * ir - 2.0 * sw * ir * ir * ir;
-  const double gd = g1 * dx + g2 * dy + g3 * dz;
-  const double cc = (g0 * ds + dtt * gd) * ir;
-  gx = cc * dx + tt * g1;
-  gy = cc * dy + tt * g2;
-  gz = cc * dz + tt * g3;
-  fi0 += gx;
-  fi1 += gy;
-  fi2 += gz;
-  vir[0] -= gx * dx; vir[1] -= gx * dy; vir[2] -= gx * dz;
-  vir[3] -= gy * dx; vir[4] -= gy * dy; vir[5] -= gy * dz;
-  vir[6] -= gz * dx; vir[7] -= gz * dy; vir[8] -= gz * dz;
-}
-
 // pair_force with the neighbour's share scattered by global atomics;
 // D4 = dr[slot] and j = nlist[slot]
 __device__ inline void force_pair(const MixArgs &a, int64_t slot, const double4 &D4, int j, float4 gr, double rc,
@@ -1368,7 +1317,7 @@ static bool tab_fits_t(int ntypes) {
 }
 
 // supported embedding shapes: widths of the three layers, affine last layer
-#define DPK_MIX_SHAPES(X) X(25, 50, 100, 0) X(16, 32, 100, 0) X(16, 32, 100, 1)
+#define DPK_MIX_SHAPES(X) X(25, 50, 100, 0) X(16, 32, 100, 0) X(16, 32, 100, 1) X(32, 64, 128, 0)
 
 int mix_shape_id(const Dims &d) {
   if (d.n_emb != 3) return -1;

@@ -1,0 +1,489 @@
+// Wide embedding nets in mixed precision (the embedding-size study of the
+// paper's Sec. VI-D / Fig. 7: last-layer matrices up to 1024 x 2048).
+//
+// Widths of 256 and more do not fit the register-resident per-neighbour
+// kernels, so this path runs the embedding net over all real neighbour pairs
+// as 16-bit MFMA GEMMs (v_mfma_f32_16x16x32_{f16,bf16}, FP32 accumulation),
+// the regime in which the paper found MIX-16 to scale with the matrix size:
+//
+//   count   pairs per (centre type, neighbour type) net, per-atom offsets
+//   layer 0 1 -> W1 on the VALU: h = tanh(s w + b) and dh/ds = (1 - h^2) w
+//   GEMMs   layer l >= 1: Z = H W_l over rows (value, tangent) interleaved,
+//           epilogue h' = skip(h) + tanh(z + b), dh'/ds = skip(dh/ds) +
+//           (1 - tanh^2) dz/ds  (forward-mode tangent, so dG/ds is carried
+//           through the same GEMMs as G: no backward GEMMs are needed)
+//   T       T_i = (1/Nc) sum_j G_j R_j^T per atom (FP32 sums)
+//   (fitting net: the mixed fitting kernels, D = T T<^T formed on the fly)
+//   bwd     per pair dE/dR_j = G_j^T dT_i, dE/ds_j = (dT_i R_j) . dG_j/ds,
+//           then the FP64 force Jacobian, F_j atomics and the virial.
+//
+// Activations are stored in 16 bits without a hi/lo split (the paper's
+// MIX-16 storage), so this path's accuracy is that of MIX-16 (~1e-3
+// relative), not that of the split register-resident kernels.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <vector>
+
+#include "dp_wide.h"
+
+namespace dpk {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <int P> struct WT;
+template <> struct WT<0> {
+  typedef _Float16 v8 __attribute__((ext_vector_type(8)));
+  __device__ static v4f mma(v8 a, v8 b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0); }
+  __device__ static float get(uint16_t u) { return (float)__builtin_bit_cast(_Float16, u); }
+  __device__ static uint16_t put(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+};
+template <> struct WT<1> {
+  typedef __bf16 v8 __attribute__((ext_vector_type(8)));
+  __device__ static v4f mma(v8 a, v8 b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+  __device__ static float get(uint16_t u) { return __builtin_bit_cast(float, (uint32_t)u << 16); }
+  __device__ static uint16_t put(float x) {  // round to nearest even
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+  }
+};
+
+template <int P>
+__device__ inline uint4 pack8(const float (&x)[8]) {
+  uint32_t w[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = (uint32_t)WT<P>::put(x[2 * k]) | ((uint32_t)WT<P>::put(x[2 * k + 1]) << 16);
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// ---------------------------------------------------------------------------
+// pair counts: atom i's pairs of net (t_i, u) start at pair poff[i][u] of
+// that net (wave prefix sums, one atomic per wave and net)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_wide_count(WideArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, T = a.d.ntypes;
+  const int t = i < a.n ? (int)a.xw[i].w : -1;
+  for (int net = 0; net < T * T; ++net) {
+    const int u = net % T;
+    const bool mine = i < a.n && t == net / T;
+    const int c = mine ? a.nreal[i * T + u] : 0;
+    int x = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    const int total = __shfl(x, 63);
+    int base = 0;
+    if (lane == 63 && total > 0) base = atomicAdd(a.cnt + net, total);
+    base = __shfl(base, 63);
+    if (mine) a.poff[i * T + u] = base + x - c;
+  }
+}
+
+void launch_wide_count(hipStream_t s, const WideArgs &a) {
+  if (a.n <= 0) return;
+  hipLaunchKernelGGL(k_wide_count, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------------------
+// layer 0 (1 -> W1): value and tangent rows of every real pair, 8 features
+// per thread
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ void __launch_bounds__(256) k_wide_l0(WideArgs a) {
+  const int T = a.d.ntypes, W1 = a.d.ew[1], C = W1 / 8;
+  for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+    const int t = (int)a.xw[i].w;
+    for (int u = 0; u < T; ++u) {
+      const int net = t * T + u, nr = a.nreal[i * T + u];
+      const int64_t rb = a.row0[net] + 2 * (int64_t)a.poff[i * T + u];
+      const float4 *R = a.rt + i * a.d.nnei + a.d.off[u];
+      const float *w0 = a.w0[net], *b0 = a.b0[net];
+      for (int e = threadIdx.x; e < nr * C; e += blockDim.x) {
+        const int k = e / C, c = e % C;
+        const float s = R[k].x;
+        float y[8], dy[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const float w = w0[8 * c + q];
+          const float h = tanh_f(s * w + b0[8 * c + q]);
+          y[q] = h;
+          dy[q] = (1.f - h * h) * w;
+        }
+        uint16_t *row = a.X0 + (rb + 2 * k) * W1 + 8 * c;
+        *(uint4 *)row = pack8<P>(y);
+        *(uint4 *)(row + W1) = pack8<P>(dy);
+      }
+    }
+  }
+}
+
+void launch_wide_l0(hipStream_t s, const WideArgs &a) {
+  if (a.n <= 0) return;
+  const unsigned grid = (unsigned)(a.n < WIDE_GRID ? a.n : WIDE_GRID);
+  if (a.prec == 0) hipLaunchKernelGGL(k_wide_l0<0>, dim3(grid), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_wide_l0<1>, dim3(grid), dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------------------
+// GEMM with the layer epilogue.  128 x 128 output tile per workgroup of four
+// waves (2 x 2, 64 x 64 each = 4 x 4 MFMA tiles), K staged through LDS 64 at
+// a time (double buffered, register prefetch of the next stage), LDS rows
+// padded to 72 elements (144 B) so that the 16 rows a fragment read touches
+// fall on distinct banks.  Output lane (g, c) of an MFMA tile holds rows
+// 4g..4g+3 of feature c: rows (4g, 4g+1) and (4g+2, 4g+3) are (value,
+// tangent) pairs, so the epilogue has both in registers.
+// ---------------------------------------------------------------------------
+constexpr int WIDE_LS = WIDE_BK + 8;  // LDS row stride (elements)
+
+template <int P>
+__global__ void __launch_bounds__(256, 2) k_wide_gemm(WideGemm g, int nbm, int nbn) {
+  typedef typename WT<P>::v8 V;
+  __shared__ __align__(16) uint16_t sA[2][WIDE_BM * WIDE_LS];
+  __shared__ __align__(16) uint16_t sB[2][WIDE_BN * WIDE_LS];
+  // workgroups are dealt round-robin to the eight XCDs: give each XCD a
+  // contiguous run of tiles (same row block, successive column blocks) so
+  // that the row block is fetched into that XCD's L2 once
+  const int ntile = nbm * nbn, per = gridDim.x / 8;
+  const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (tile >= ntile) return;  // whole workgroup: before any barrier
+  const int bm = tile / nbn, bn = tile % nbn;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv & 1, wn = wv >> 1;
+  const int K = g.K, N = g.N;
+  const uint16_t *Ag = g.A + (int64_t)bm * WIDE_BM * K;
+  const uint16_t *Bg = g.Bt + (int64_t)bn * WIDE_BN * K;
+  uint4 ra[4], rb[4];
+  auto gload = [&](int kt) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = tid + 256 * q, row = c >> 3, c8 = c & 7;
+      ra[q] = *(const uint4 *)(Ag + (int64_t)row * K + kt * WIDE_BK + 8 * c8);
+      rb[q] = *(const uint4 *)(Bg + (int64_t)row * K + kt * WIDE_BK + 8 * c8);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = tid + 256 * q, row = c >> 3, c8 = c & 7;
+      *(uint4 *)(&sA[buf][row * WIDE_LS + 8 * c8]) = ra[q];
+      *(uint4 *)(&sB[buf][row * WIDE_LS + 8 * c8]) = rb[q];
+    }
+  };
+  v4f acc[4][4];
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int nkt = K / WIDE_BK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  const int fr = lane & 15, fk = 8 * (lane >> 4);
+  for (int kt = 0; kt < nkt; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nkt) gload(kt + 1);
+#pragma unroll
+    for (int ks = 0; ks < WIDE_BK / 32; ++ks) {
+      V af[4], bf[4];
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi)
+        af[mi] = *(const V *)(&sA[buf][(64 * wm + 16 * mi + fr) * WIDE_LS + 32 * ks + fk]);
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni)
+        bf[ni] = *(const V *)(&sB[buf][(64 * wn + 16 * ni + fr) * WIDE_LS + 32 * ks + fk]);
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = WT<P>::mma(af[mi], bf[ni], acc[mi][ni]);
+    }
+    if (kt + 1 < nkt) lstore(buf ^ 1);
+    __syncthreads();
+  }
+  // epilogue: y = skip(h) + tanh(z + b), dy = skip(dh) + (1 - tanh^2) dz
+  const int g4 = lane >> 4;
+#pragma unroll
+  for (int ni = 0; ni < 4; ++ni) {
+    const int n = bn * WIDE_BN + 64 * wn + 16 * ni + fr;
+    const float bias = g.bias[n];
+    const int sc = g.skip == 1 ? n : (n < K ? n : n - K);
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi) {
+      const int64_t r = (int64_t)bm * WIDE_BM + 64 * wm + 16 * mi + 4 * g4;
+      const v4f c = acc[mi][ni];
+#pragma unroll
+      for (int pr = 0; pr < 2; ++pr) {
+        const int64_t rv = r + 2 * pr;
+        const float h = tanh_f(c[2 * pr] + bias);
+        float y = h, dy = (1.f - h * h) * c[2 * pr + 1];
+        if (g.skip) {
+          y += WT<P>::get(g.A[rv * K + sc]);
+          dy += WT<P>::get(g.A[(rv + 1) * K + sc]);
+        }
+        g.Y[rv * N + n] = WT<P>::put(y);
+        g.Y[(rv + 1) * N + n] = WT<P>::put(dy);
+      }
+    }
+  }
+}
+
+void launch_wide_gemm(hipStream_t s, const WideGemm &g, int prec) {
+  if (g.rows <= 0) return;
+  const int nbm = (int)(g.rows / WIDE_BM), nbn = g.N / WIDE_BN;
+  const unsigned grid = (unsigned)((nbm * nbn + 7) / 8 * 8);
+  if (prec == 0) hipLaunchKernelGGL(k_wide_gemm<0>, dim3(grid), dim3(256), 0, s, g, nbm, nbn);
+  else hipLaunchKernelGGL(k_wide_gemm<1>, dim3(grid), dim3(256), 0, s, g, nbm, nbn);
+}
+
+// ---------------------------------------------------------------------------
+// T_i = (1/Nc) sum_j G_j R_j^T.  Thread (group, c) sums features 8c..8c+7
+// over the pairs k = group (mod groups); the groups' partial sums are added
+// in group order.
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ void __launch_bounds__(256) k_wide_T(WideArgs a) {
+  __shared__ float4 part[256 * 8];
+  const int T = a.d.ntypes, M1 = a.d.M1, C = M1 / 8, NG = 256 / C;
+  const int tid = threadIdx.x, c = tid % C, grp = tid / C;
+  const float inv_nc = (float)a.d.inv_nc;
+  for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+    const int t = (int)a.xw[i].w;
+    float4 acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int u = 0; u < T; ++u) {
+      const int net = t * T + u, nr = a.nreal[i * T + u];
+      const int64_t rb = a.row0[net] + 2 * (int64_t)a.poff[i * T + u];
+      const float4 *R = a.rt + i * a.d.nnei + a.d.off[u];
+      for (int k = grp; k < nr; k += NG) {
+        const uint4 gv = *(const uint4 *)(a.G + (rb + 2 * k) * M1 + 8 * c);
+        const float4 r = R[k];
+        const uint32_t w[4] = {gv.x, gv.y, gv.z, gv.w};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const float x = WT<P>::get((uint16_t)(w[q >> 1] >> (16 * (q & 1))));
+          acc[q].x += x * r.x;
+          acc[q].y += x * r.y;
+          acc[q].z += x * r.z;
+          acc[q].w += x * r.w;
+        }
+      }
+    }
+    float4 *Tg = (float4 *)(a.T32 + (i * M1 + 8 * c) * 4);
+    if (NG == 1) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        Tg[q] = make_float4(acc[q].x * inv_nc, acc[q].y * inv_nc, acc[q].z * inv_nc, acc[q].w * inv_nc);
+      continue;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) part[tid * 8 + q] = acc[q];
+    __syncthreads();
+    if (grp == 0) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        float4 v = part[c * 8 + q];
+        for (int h = 1; h < NG; ++h) {
+          const float4 p = part[(h * C + c) * 8 + q];
+          v.x += p.x;
+          v.y += p.y;
+          v.z += p.z;
+          v.w += p.w;
+        }
+        Tg[q] = make_float4(v.x * inv_nc, v.y * inv_nc, v.z * inv_nc, v.w * inv_nc);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+void launch_wide_T(hipStream_t s, const WideArgs &a) {
+  if (a.n <= 0) return;
+  const unsigned grid = (unsigned)(a.n < WIDE_GRID ? a.n : WIDE_GRID);
+  if (a.prec == 0) hipLaunchKernelGGL(k_wide_T<0>, dim3(grid), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_wide_T<1>, dim3(grid), dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------------------
+// backward: per pair gR = G^T dT (4 values) and gs = (dT R) . dG/ds, summed
+// over features by the wave (lane l takes features 4l + 256m); every 64
+// pairs each lane runs the FP64 force pass of one of them.  dT of the atom
+// is staged in LDS.
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ void __launch_bounds__(256) k_wide_bwd(WideArgs a) {
+  __shared__ float4 dts[2048];
+  __shared__ double vred[4][9];
+  const int T = a.d.ntypes, M1 = a.d.M1, NS = M1 / 256;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const double rc = a.d.rcut, rcs = a.d.rcut_smth, inv_w = 1.0 / (rc - rcs);
+  double vir[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) vir[k] = 0.0;
+  for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
+    __syncthreads();  // the previous atom's dT is no longer read
+    const float4 *dTg = (const float4 *)(a.dT32 + i * M1 * 4);
+    for (int f = tid; f < M1; f += 256) dts[f] = dTg[f];
+    __syncthreads();
+    const int t = (int)a.xw[i].w;
+    int nru[WIDE_MAXT], np = 0;
+    for (int u = 0; u < T; ++u) {
+      nru[u] = a.nreal[i * T + u];
+      np += nru[u];
+    }
+    if (wv * 64 >= np) continue;
+    const double4 xi = a.xw[i];
+    double fi0 = 0.0, fi1 = 0.0, fi2 = 0.0;
+    for (int q0 = wv * 64; q0 < np; q0 += 256) {
+      const int nq = np - q0 < 64 ? np - q0 : 64;
+      float4 mine = make_float4(0.f, 0.f, 0.f, 0.f);
+      int64_t mslot = 0;
+      for (int jj = 0; jj < nq; ++jj) {
+        int u = 0, k = q0 + jj;
+        while (k >= nru[u]) k -= nru[u++];
+        const int net = t * T + u;
+        const int64_t row = a.row0[net] + 2 * ((int64_t)a.poff[i * T + u] + k);
+        const int64_t slot = i * a.d.nnei + a.d.off[u] + k;
+        const float4 R = a.rt[slot];
+        float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f, gs = 0.f;
+        for (int m = 0; m < NS; ++m) {
+          const int f = 4 * lane + 256 * m;
+          const uint2 hv = *(const uint2 *)(a.G + row * M1 + f);
+          const uint2 ht = *(const uint2 *)(a.G + (row + 1) * M1 + f);
+          const uint32_t wv4[2] = {hv.x, hv.y}, wt4[2] = {ht.x, ht.y};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const float x = WT<P>::get((uint16_t)(wv4[e >> 1] >> (16 * (e & 1))));
+            const float xt = WT<P>::get((uint16_t)(wt4[e >> 1] >> (16 * (e & 1))));
+            const float4 d = dts[f + e];
+            g0 += x * d.x;
+            g1 += x * d.y;
+            g2 += x * d.z;
+            g3 += x * d.w;
+            gs += xt * (d.x * R.x + d.y * R.y + d.z * R.z + d.w * R.w);
+          }
+        }
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          g0 += __shfl_xor(g0, o);
+          g1 += __shfl_xor(g1, o);
+          g2 += __shfl_xor(g2, o);
+          g3 += __shfl_xor(g3, o);
+          gs += __shfl_xor(gs, o);
+        }
+        if (lane == jj) {
+          mine = make_float4(g0 + gs, g1, g2, g3);
+          mslot = slot;
+        }
+      }
+      if (lane < nq) {
+        const int j = a.nlist[mslot];
+        if (a.net_deriv) {
+          double *nd = a.net_deriv + mslot * 4;
+          nd[0] = mine.x;
+          nd[1] = mine.y;
+          nd[2] = mine.z;
+          nd[3] = mine.w;
+        }
+        double gx, gy, gz;
+        pair_force(pair_disp(xi, a.xw[j], a.L[0], a.L[1], a.L[2]), mine, rc, rcs, inv_w, gx, gy, gz, fi0, fi1, fi2,
+                   vir);
+        unsafeAtomicAdd(a.force + 3 * (int64_t)j + 0, -gx);
+        unsafeAtomicAdd(a.force + 3 * (int64_t)j + 1, -gy);
+        unsafeAtomicAdd(a.force + 3 * (int64_t)j + 2, -gz);
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      fi0 += __shfl_xor(fi0, o);
+      fi1 += __shfl_xor(fi1, o);
+      fi2 += __shfl_xor(fi2, o);
+    }
+    if (lane == 0) {
+      unsafeAtomicAdd(a.force + 3 * i + 0, fi0);
+      unsafeAtomicAdd(a.force + 3 * i + 1, fi1);
+      unsafeAtomicAdd(a.force + 3 * i + 2, fi2);
+    }
+  }
+  // block partial of the virial (lanes, then waves in order)
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    double v = vir[k];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
+    if (lane == 0) vred[wv][k] = v;
+  }
+  __syncthreads();
+  if (tid < 9) a.vir_part[(int64_t)blockIdx.x * 9 + tid] = ((vred[0][tid] + vred[1][tid]) + vred[2][tid]) + vred[3][tid];
+}
+
+void launch_wide_bwd(hipStream_t s, const WideArgs &a) {
+  if (a.n <= 0) return;
+  const unsigned grid = (unsigned)(a.n < WIDE_GRID ? a.n : WIDE_GRID);
+  if (a.prec == 0) hipLaunchKernelGGL(k_wide_bwd<0>, dim3(grid), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_wide_bwd<1>, dim3(grid), dim3(256), 0, s, a);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+bool wide_supported(const Dims &d, const char **why) {
+  if (d.ntypes > WIDE_MAXT) return *why = "wide embedding nets take at most 4 atom types", false;
+  if (d.n_emb < 2) return *why = "wide embedding nets need two or more layers", false;
+  if (d.emb_lin) return *why = "wide embedding nets need a tanh last layer", false;
+  for (int l = 1; l < d.n_emb; ++l) {
+    if (d.ew[l] % WIDE_BK != 0) return *why = "wide embedding: hidden widths must be multiples of 64", false;
+    if (d.ew[l + 1] % WIDE_BN != 0) return *why = "wide embedding: widths after layer 1 must be multiples of 128", false;
+  }
+  if (d.M1 % 256 != 0 || d.M1 > 2048) return *why = "wide embedding: M1 must be a multiple of 256, at most 2048", false;
+  return true;
+}
+
+static uint16_t bits16(double v, int prec) {
+  const float f = (float)v;
+  if (prec == 0) {
+    const _Float16 h = (_Float16)f;
+    uint16_t u;
+    std::memcpy(&u, &h, 2);
+    return u;
+  }
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+void wide_pack_net(const Dims &d, const double *const *W, const double *const *b, int prec,
+                   std::vector<unsigned char> &buf, WideNet &o) {
+  auto grow = [&](size_t bytes) {
+    const size_t at = (buf.size() + 255) / 256 * 256;
+    buf.resize(at + bytes, 0);
+    return (int64_t)at;
+  };
+  for (int l = 0; l < d.n_emb; ++l) {
+    const int in = d.ew[l], out = d.ew[l + 1];
+    if (l == 0) {
+      o.w[0] = grow(sizeof(float) * out);
+      for (int f = 0; f < out; ++f) {
+        const float v = (float)W[0][f];
+        std::memcpy(buf.data() + o.w[0] + 4 * f, &v, 4);
+      }
+    } else {
+      o.w[l] = grow(sizeof(uint16_t) * (size_t)in * out);
+      for (int n = 0; n < out; ++n)
+        for (int k = 0; k < in; ++k) {
+          const uint16_t v = bits16(W[l][(size_t)k * out + n], prec);
+          std::memcpy(buf.data() + o.w[l] + 2 * ((size_t)n * in + k), &v, 2);
+        }
+    }
+    o.b[l] = grow(sizeof(float) * out);
+    for (int f = 0; f < out; ++f) {
+      const float v = (float)b[l][f];
+      std::memcpy(buf.data() + o.b[l] + 4 * f, &v, 4);
+    }
+  }
+}
+
+}  // namespace dpk

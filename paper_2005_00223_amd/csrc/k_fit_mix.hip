@@ -538,7 +538,7 @@ bool fit_mix_supported(const Dims &d, const char **why) {
     if (d.fw[l] != H) return *why = "mixed fitting net needs equal hidden widths", false;
   if (H != 16 * FIT_MT) return *why = "mixed fitting net is built for hidden width 240", false;
   if (d.M2 != 16) return *why = "mixed fitting net needs M2 = 16", false;
-  if (d.M1 % 2 != 0 || d.M1 > 128) return *why = "mixed fitting net needs an even M1 <= 128", false;
+  if (d.M1 % 2 != 0 || d.M1 > 2048) return *why = "mixed fitting net needs an even M1 <= 2048", false;
   if (d.n_fit < 1 || d.n_fit > MAXF) return *why = "mixed fitting net needs 1..4 hidden layers", false;
   return true;
 }

@@ -312,6 +312,10 @@ def workload(name):
         x, t, box = water_system(16, 49.7, 0.1, seed=4, reps=(2, 1, 1))
         return dict(name=name, coords=x, types=t, box=box, masses=np.array([MASS["O"], MASS["H"]]),
                     spec=water_model(0), dt_fs=0.5, temp=300.0, vseed=104)
+    if name == "cu13500":       # 15^3 FCC cells: the embedding-size sweep (Fig. 7) workload
+        x, t, box = fcc_copper(15, 3.634, 0.05, seed=8)
+        return dict(name=name, coords=x, types=t, box=box, masses=np.array([MASS["Cu"]]),
+                    spec=copper_model(1), dt_fs=1.0, temp=300.0, vseed=108)
     if name == "cu500k":        # 50^3 FCC cells
         x, t, box = fcc_copper(50, 3.634, 0.05, seed=5)
         return dict(name=name, coords=x, types=t, box=box, masses=np.array([MASS["Cu"]]),

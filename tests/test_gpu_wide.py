@@ -1,0 +1,141 @@
+"""Wide embedding nets (the embedding-size study of Sec. VI-D, Fig. 7)
+through the 16-bit GEMM path, against the FP64 oracle.
+
+The oracle runs the same model with its 16-bit weights rounded beforehand
+(GEMM layers of the embedding nets, the first two fitting layers), so the
+difference left is the path's own: activations and their tangents stored in
+16 bits between layers (the paper's MIX-16 storage, no hi/lo split), FP32
+GEMM accumulation and FP32 sums of T.  Cases: the study's smallest matrix
+(64 x 128, net 32-64-128, on the register-resident kernels), the smallest
+wide net
+(64-128-256) in FP16 and BF16, 256-512-1024, the largest net of the study
+(512-1024-2048), and two atom types (four nets, one GEMM row block each).
+The full-size sweep workload (13,500 copper atoms, rc 8 A) is checked on the
+per-atom energies of sampled atoms, which the oracle evaluates centre by
+centre."""
+import copy
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2005_00223_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _quantised(spec, prec):
+    """The model with the weights the 16-bit kernels hold, in FP64."""
+    from oracle import student as S
+    q = copy.deepcopy(spec)
+    p = 0 if prec == "fp16" else 1
+    for t in range(spec.ntypes):
+        for u in range(spec.ntypes):
+            for l in range(1, len(spec.emb)):
+                q.emb_W[t][u][l] = S.round16(spec.emb_W[t][u][l], p)
+        for l in range(2):
+            q.fit_W[t][l] = S.round16(spec.fit_W[t][l], p)
+    return q
+
+
+def _system(name):
+    if name == "cu3":  # 3^3 FCC cells, 108 atoms, 10.9 A box, strongly disordered
+        return synth.fcc_copper(3, 3.634, 0.25, seed=7)
+    w = synth.workload(name)
+    return w["coords"], w["types"], w["box"]
+
+
+def _model(name, rc, emb, seed=21):
+    if name == "cu3":
+        return synth.random_model(1, rc, 1.0, (64,), emb=emb, seed=seed)
+    return synth.random_model(2, rc, 0.5, (46, 92), emb=emb, seed=seed)
+
+
+# relative force RMSE, relative energy, relative virial bars per precision:
+# 16-bit storage of every activation and tangent (unit roundoff u = 2^-11
+# FP16, 2^-8 BF16) leaves a few u of relative error per feature, and the
+# forces carry it at about 2u (measured); the bars are 10u for forces and
+# the virial.  Energies are dominated by the fitting biases and agree far
+# better; their bars are u/5.
+BARS = {"fp16": (5e-3, 1e-4, 5e-3), "bf16": (4e-2, 8e-4, 4e-2)}
+
+
+@pytest.mark.parametrize("sysname,rc,emb,prec", [
+    ("cu3", 4.5, (32, 64, 128), "fp16"),
+    ("cu3", 4.5, (64, 128, 256), "fp16"),
+    ("cu3", 4.5, (64, 128, 256), "bf16"),
+    ("cu3", 4.5, (256, 512, 1024), "fp16"),
+    ("cu3", 3.7, (512, 1024, 2048), "fp16"),
+    ("water192", 6.0, (64, 128, 256), "fp16"),
+])
+def test_wide_matches_oracle(sysname, rc, emb, prec):
+    from oracle import oracle as O
+    from paper_2005_00223_amd.model import DPModel
+    x, t, box = _system(sysname)
+    spec = _model(sysname, rc, emb)
+    say(f"[wide] {sysname} rc {rc} emb {emb} {prec}: {len(t)} atoms")
+    m = DPModel(synth.pack_blob(spec), prec)
+    e, f, v = m.compute(x, t, box)
+    st = m.stats()
+    # 32-64-128 runs the register-resident kernels (hi/lo split activations)
+    assert st["wide_evals"] == (0 if emb[-1] <= 128 else 1)
+    f = f.cpu().numpy()
+    v = np.asarray(v.cpu().numpy()).reshape(-1)
+    r = O.Oracle(synth.pack_blob(_quantised(spec, prec))).eval(x, t, box)
+    rms = float(np.sqrt((r["force"] ** 2).sum(1).mean()))
+    df = float(np.sqrt(((f - r["force"]) ** 2).sum(1).mean()))
+    de = abs(float(e) - r["energy"])
+    vo = np.asarray(r["virial"]).reshape(-1)
+    dv = float(np.abs(v - vo).max())
+    vs = max(1e-12, float(np.abs(vo).max()))
+    say(f"  force RMSE {df:.3e} (RMS|F| {rms:.3e}, rel {df / rms:.2e}), |dE| {de:.3e} "
+        f"(E {r['energy']:.4e}, rel {de / abs(r['energy']):.2e}), max|dV| {dv:.3e} (rel {dv / vs:.2e})")
+    bf, be, bv = BARS[prec]
+    assert np.isfinite(f).all()
+    assert df <= bf * rms
+    assert de <= be * abs(r["energy"])
+    assert dv <= bv * vs
+
+
+def test_wide_rejected_in_fp64():
+    """FP64 kernels hold widths up to 128; a wide net asks for mixed precision."""
+    from paper_2005_00223_amd.model import DPModel
+    spec = _model("cu3", 4.5, (64, 128, 256))
+    with pytest.raises(Exception) as ei:
+        DPModel(synth.pack_blob(spec), "fp64")
+    say(f"[wide] fp64 refusal: {ei.value}")
+    assert "mixed" in str(ei.value)
+
+
+def test_wide_sweep_workload_atom_energies():
+    """Largest net of the study on the full sweep workload: per-atom energies
+    of 8 sampled atoms against the oracle's per-centre evaluation."""
+    from oracle import oracle as O
+    from paper_2005_00223_amd.model import DPModel
+    w = synth.workload("cu13500")
+    spec = synth.copper_model(1, emb=(512, 1024, 2048))
+    n = len(w["types"])
+    m = DPModel(synth.pack_blob(spec), "fp16")
+    say(f"[wide] sweep workload {n} atoms, emb 512-1024-2048")
+    e, f, v = m.compute(w["coords"], w["types"], w["box"], keep_intermediates=True)
+    ae = m.intermediates(n, spec.M1, spec.M2, spec.nnei, which=("atom_e",))["atom_e"].cpu().numpy()
+    assert abs(ae.sum() - float(e)) <= 1e-9 * max(1.0, abs(float(e)))
+    idx = np.random.default_rng(5).choice(n, 8, replace=False)
+    r = O.Oracle(synth.pack_blob(_quantised(spec, "fp16"))).eval(w["coords"], w["types"], w["box"], centres=idx)
+    ref = r["atom_e"]  # in the order of the centres
+    d = np.abs(ae[idx] - ref)
+    say(f"  sampled |dE_i| max {d.max():.3e} (|E_i| ~ {np.abs(ref).mean():.3e})")
+    assert np.isfinite(f.cpu().numpy()).all()
+    assert (d <= 2e-3 * np.maximum(1.0, np.abs(ref))).all()
