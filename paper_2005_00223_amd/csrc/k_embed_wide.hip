@@ -145,46 +145,60 @@ __global__ void __launch_bounds__(256, 2) k_wide_gemm(WideGemm g, int nbm, int n
   __shared__ __align__(16) uint16_t sA[2][WIDE_BM * WIDE_LS];
   __shared__ __align__(16) uint16_t sB[2][WIDE_BN * WIDE_LS];
   // workgroups are dealt round-robin to the eight XCDs: give each XCD a
-  // contiguous run of tiles (same row block, successive column blocks) so
-  // that the row block is fetched into that XCD's L2 once
+  // contiguous run of tiles, ordered in groups of 8 row blocks x all column
+  // blocks, column block outer, so that an XCD's L2 holds the group's row
+  // blocks (8 x 128 x K) while the weight columns stream past once per group
   const int ntile = nbm * nbn, per = gridDim.x / 8;
   const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
   if (tile >= ntile) return;  // whole workgroup: before any barrier
-  const int bm = tile / nbn, bn = tile % nbn;
+  constexpr int GM = 8;
+  const int grp = tile / (GM * nbn), in = tile % (GM * nbn);
+  const int gm = nbm - grp * GM < GM ? nbm - grp * GM : GM;
+  const int bm = grp * GM + in % gm, bn = in / gm;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv & 1, wn = wv >> 1;
   const int K = g.K, N = g.N;
   const uint16_t *Ag = g.A + (int64_t)bm * WIDE_BM * K;
   const uint16_t *Bg = g.Bt + (int64_t)bn * WIDE_BN * K;
-  uint4 ra[4], rb[4];
-  auto gload = [&](int kt) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = tid + 256 * q, row = c >> 3, c8 = c & 7;
-      ra[q] = *(const uint4 *)(Ag + (int64_t)row * K + kt * WIDE_BK + 8 * c8);
-      rb[q] = *(const uint4 *)(Bg + (int64_t)row * K + kt * WIDE_BK + 8 * c8);
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = tid + 256 * q, row = c >> 3, c8 = c & 7;
-      *(uint4 *)(&sA[buf][row * WIDE_LS + 8 * c8]) = ra[q];
-      *(uint4 *)(&sB[buf][row * WIDE_LS + 8 * c8]) = rb[q];
-    }
-  };
+  // this thread's four 16-byte pieces of each operand tile: row (tid + 256 q) / 8,
+  // column 8 ((tid + 256 q) % 8) of the stage
+  const int lr = tid >> 3, lc = 8 * (tid & 7);
+  const uint16_t *ag = Ag + (int64_t)lr * K + lc, *bg = Bg + (int64_t)lr * K + lc;
+  const int64_t rstep = (int64_t)32 * K;  // 32 rows further
+  const int lo = lr * WIDE_LS + lc, lstep = 32 * WIDE_LS;
   v4f acc[4][4];
 #pragma unroll
   for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
     for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = v4f{0.f, 0.f, 0.f, 0.f};
   const int nkt = K / WIDE_BK;
-  gload(0);
-  lstore(0);
+  uint4 a0 = *(const uint4 *)(ag), a1 = *(const uint4 *)(ag + rstep), a2 = *(const uint4 *)(ag + 2 * rstep),
+        a3 = *(const uint4 *)(ag + 3 * rstep);
+  uint4 b0 = *(const uint4 *)(bg), b1 = *(const uint4 *)(bg + rstep), b2 = *(const uint4 *)(bg + 2 * rstep),
+        b3 = *(const uint4 *)(bg + 3 * rstep);
+  *(uint4 *)(&sA[0][lo]) = a0;
+  *(uint4 *)(&sA[0][lo + lstep]) = a1;
+  *(uint4 *)(&sA[0][lo + 2 * lstep]) = a2;
+  *(uint4 *)(&sA[0][lo + 3 * lstep]) = a3;
+  *(uint4 *)(&sB[0][lo]) = b0;
+  *(uint4 *)(&sB[0][lo + lstep]) = b1;
+  *(uint4 *)(&sB[0][lo + 2 * lstep]) = b2;
+  *(uint4 *)(&sB[0][lo + 3 * lstep]) = b3;
   __syncthreads();
   const int fr = lane & 15, fk = 8 * (lane >> 4);
   for (int kt = 0; kt < nkt; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < nkt) gload(kt + 1);
+    const bool more = kt + 1 < nkt;
+    if (more) {  // next stage into registers while this one is multiplied
+      const int ko = (kt + 1) * WIDE_BK;
+      a0 = *(const uint4 *)(ag + ko);
+      a1 = *(const uint4 *)(ag + rstep + ko);
+      a2 = *(const uint4 *)(ag + 2 * rstep + ko);
+      a3 = *(const uint4 *)(ag + 3 * rstep + ko);
+      b0 = *(const uint4 *)(bg + ko);
+      b1 = *(const uint4 *)(bg + rstep + ko);
+      b2 = *(const uint4 *)(bg + 2 * rstep + ko);
+      b3 = *(const uint4 *)(bg + 3 * rstep + ko);
+    }
 #pragma unroll
     for (int ks = 0; ks < WIDE_BK / 32; ++ks) {
       V af[4], bf[4];
@@ -199,7 +213,17 @@ __global__ void __launch_bounds__(256, 2) k_wide_gemm(WideGemm g, int nbm, int n
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = WT<P>::mma(af[mi], bf[ni], acc[mi][ni]);
     }
-    if (kt + 1 < nkt) lstore(buf ^ 1);
+    if (more) {
+      uint16_t *sa = sA[buf ^ 1], *sb = sB[buf ^ 1];
+      *(uint4 *)(&sa[lo]) = a0;
+      *(uint4 *)(&sa[lo + lstep]) = a1;
+      *(uint4 *)(&sa[lo + 2 * lstep]) = a2;
+      *(uint4 *)(&sa[lo + 3 * lstep]) = a3;
+      *(uint4 *)(&sb[lo]) = b0;
+      *(uint4 *)(&sb[lo + lstep]) = b1;
+      *(uint4 *)(&sb[lo + 2 * lstep]) = b2;
+      *(uint4 *)(&sb[lo + 3 * lstep]) = b3;
+    }
     __syncthreads();
   }
   // epilogue: y = skip(h) + tanh(z + b), dy = skip(dh) + (1 - tanh^2) dz
