@@ -131,19 +131,27 @@ void launch_wide_l0(hipStream_t s, const WideArgs &a) {
 // ---------------------------------------------------------------------------
 // GEMM with the layer epilogue.  128 x 128 output tile per workgroup of four
 // waves (2 x 2, 64 x 64 each = 4 x 4 MFMA tiles), K staged through LDS 64 at
-// a time (double buffered, register prefetch of the next stage), LDS rows
-// padded to 72 elements (144 B) so that the 16 rows a fragment read touches
-// fall on distinct banks.  Output lane (g, c) of an MFMA tile holds rows
-// 4g..4g+3 of feature c: rows (4g, 4g+1) and (4g+2, 4g+3) are (value,
-// tangent) pairs, so the epilogue has both in registers.
+// a time, double buffered.  The operands go global -> LDS by direct loads
+// (global_load_lds_dwordx4, no registers): a 1 KB block holds 8 rows x 64 k,
+// lane l loading 16 bytes of row l / 8 (eight lanes cover a row's 128
+// contiguous bytes) into slot l; the 16-byte chunk c of row r sits in slot
+// c ^ r of that row, so the eight rows a fragment read touches at one chunk
+// fall on different banks.  Output lane (g, c) of an MFMA tile holds rows 4g..4g+3 of
+// feature c: rows (4g, 4g+1) and (4g+2, 4g+3) are (value, tangent) pairs, so
+// tanh and its derivative are applied there; the results are then staged in
+// LDS (FP32) and written, with the skip connection added, 16 bytes per lane.
 // ---------------------------------------------------------------------------
-constexpr int WIDE_LS = WIDE_BK + 8;  // LDS row stride (elements)
+constexpr int WIDE_STAGE = 2 * (WIDE_BM + WIDE_BN) * WIDE_BK;  // bytes of one stage (A then B)
+constexpr int WIDE_EPS = 36;                                    // FP32 row stride of the epilogue staging
+
+__device__ inline void wide_dma(const uint16_t *src, unsigned char *lds) {
+  __builtin_amdgcn_global_load_lds((const void *)src, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
+}
 
 template <int P>
 __global__ void __launch_bounds__(256, 2) k_wide_gemm(WideGemm g, int nbm, int nbn) {
   typedef typename WT<P>::v8 V;
-  __shared__ __align__(16) uint16_t sA[2][WIDE_BM * WIDE_LS];
-  __shared__ __align__(16) uint16_t sB[2][WIDE_BN * WIDE_LS];
+  __shared__ __align__(16) unsigned char lds[2 * WIDE_STAGE];
   // workgroups are dealt round-robin to the eight XCDs: give each XCD a
   // contiguous run of tiles, ordered in groups of 8 row blocks x all column
   // blocks, column block outer, so that an XCD's L2 holds the group's row
@@ -157,99 +165,100 @@ __global__ void __launch_bounds__(256, 2) k_wide_gemm(WideGemm g, int nbm, int n
   const int bm = grp * GM + in % gm, bn = in / gm;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv & 1, wn = wv >> 1;
   const int K = g.K, N = g.N;
-  const uint16_t *Ag = g.A + (int64_t)bm * WIDE_BM * K;
-  const uint16_t *Bg = g.Bt + (int64_t)bn * WIDE_BN * K;
-  // this thread's four 16-byte pieces of each operand tile: row (tid + 256 q) / 8,
-  // column 8 ((tid + 256 q) % 8) of the stage
-  const int lr = tid >> 3, lc = 8 * (tid & 7);
-  const uint16_t *ag = Ag + (int64_t)lr * K + lc, *bg = Bg + (int64_t)lr * K + lc;
-  const int64_t rstep = (int64_t)32 * K;  // 32 rows further
-  const int lo = lr * WIDE_LS + lc, lstep = 32 * WIDE_LS;
+  // blocks of a stage: A rows 8 b..8 b+7 in block b (0..15), B rows in blocks
+  // 16..31; wave w loads blocks w + 4 j, lane l row l / 8, chunk (l % 8) ^ (l / 8)
+  const int fr = lane & 15;
+  const uint16_t *src[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int b = wv + 4 * j, isb = b >> 4, rb = b & 15;
+    const uint16_t *base = isb ? g.Bt + (int64_t)bn * WIDE_BN * K : g.A + (int64_t)bm * WIDE_BM * K;
+    src[j] = base + (int64_t)(8 * rb + (lane >> 3)) * K + 8 * ((lane & 7) ^ (lane >> 3));
+  }
+  // fragment reads: row fr of a 16-row group = block 2 group + fr / 8, row fr % 8,
+  // chunk 4 ks + lane / 16 at slot chunk ^ (fr % 8)
+  const int rr = fr & 7, rbk = fr >> 3;
+  auto issue = [&](int kt, int st) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) wide_dma(src[j] + kt * WIDE_BK, lds + st * WIDE_STAGE + (wv + 4 * j) * 1024);
+  };
   v4f acc[4][4];
 #pragma unroll
   for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
     for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = v4f{0.f, 0.f, 0.f, 0.f};
   const int nkt = K / WIDE_BK;
-  uint4 a0 = *(const uint4 *)(ag), a1 = *(const uint4 *)(ag + rstep), a2 = *(const uint4 *)(ag + 2 * rstep),
-        a3 = *(const uint4 *)(ag + 3 * rstep);
-  uint4 b0 = *(const uint4 *)(bg), b1 = *(const uint4 *)(bg + rstep), b2 = *(const uint4 *)(bg + 2 * rstep),
-        b3 = *(const uint4 *)(bg + 3 * rstep);
-  *(uint4 *)(&sA[0][lo]) = a0;
-  *(uint4 *)(&sA[0][lo + lstep]) = a1;
-  *(uint4 *)(&sA[0][lo + 2 * lstep]) = a2;
-  *(uint4 *)(&sA[0][lo + 3 * lstep]) = a3;
-  *(uint4 *)(&sB[0][lo]) = b0;
-  *(uint4 *)(&sB[0][lo + lstep]) = b1;
-  *(uint4 *)(&sB[0][lo + 2 * lstep]) = b2;
-  *(uint4 *)(&sB[0][lo + 3 * lstep]) = b3;
+  issue(0, 0);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  const int fr = lane & 15, fk = 8 * (lane >> 4);
   for (int kt = 0; kt < nkt; ++kt) {
-    const int buf = kt & 1;
-    const bool more = kt + 1 < nkt;
-    if (more) {  // next stage into registers while this one is multiplied
-      const int ko = (kt + 1) * WIDE_BK;
-      a0 = *(const uint4 *)(ag + ko);
-      a1 = *(const uint4 *)(ag + rstep + ko);
-      a2 = *(const uint4 *)(ag + 2 * rstep + ko);
-      a3 = *(const uint4 *)(ag + 3 * rstep + ko);
-      b0 = *(const uint4 *)(bg + ko);
-      b1 = *(const uint4 *)(bg + rstep + ko);
-      b2 = *(const uint4 *)(bg + 2 * rstep + ko);
-      b3 = *(const uint4 *)(bg + 3 * rstep + ko);
-    }
+    const int st = kt & 1;
+    if (kt + 1 < nkt) issue(kt + 1, st ^ 1);
+    const unsigned char *sb = lds + st * WIDE_STAGE;
 #pragma unroll
-    for (int ks = 0; ks < WIDE_BK / 32; ++ks) {
+    for (int ks = 0; ks < 2; ++ks) {
+      const int off = (rr * 8 + ((4 * ks + (lane >> 4)) ^ rr)) * 16 + rbk * 1024;
       V af[4], bf[4];
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi)
-        af[mi] = *(const V *)(&sA[buf][(64 * wm + 16 * mi + fr) * WIDE_LS + 32 * ks + fk]);
+      for (int mi = 0; mi < 4; ++mi) af[mi] = *(const V *)(sb + 2 * (4 * wm + mi) * 1024 + off);
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni)
-        bf[ni] = *(const V *)(&sB[buf][(64 * wn + 16 * ni + fr) * WIDE_LS + 32 * ks + fk]);
+      for (int ni = 0; ni < 4; ++ni) bf[ni] = *(const V *)(sb + (16 + 2 * (4 * wn + ni)) * 1024 + off);
 #pragma unroll
       for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = WT<P>::mma(af[mi], bf[ni], acc[mi][ni]);
     }
-    if (more) {
-      uint16_t *sa = sA[buf ^ 1], *sb = sB[buf ^ 1];
-      *(uint4 *)(&sa[lo]) = a0;
-      *(uint4 *)(&sa[lo + lstep]) = a1;
-      *(uint4 *)(&sa[lo + 2 * lstep]) = a2;
-      *(uint4 *)(&sa[lo + 3 * lstep]) = a3;
-      *(uint4 *)(&sb[lo]) = b0;
-      *(uint4 *)(&sb[lo + lstep]) = b1;
-      *(uint4 *)(&sb[lo + 2 * lstep]) = b2;
-      *(uint4 *)(&sb[lo + 3 * lstep]) = b3;
-    }
-    __syncthreads();
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the next stage
+    __syncthreads();                // everyone's, and this stage is no longer read
   }
-  // epilogue: y = skip(h) + tanh(z + b), dy = skip(dh) + (1 - tanh^2) dz
+  // epilogue, in two halves of the wave's 64 columns: y = tanh(z + b) and
+  // dy = (1 - tanh^2) dz in the MFMA layout -> LDS (64 rows x 32 columns,
+  // FP32) -> per lane 8 consecutive columns of one row, plus the skip, out
+  float *ep = (float *)lds + wv * 64 * WIDE_EPS;
   const int g4 = lane >> 4;
+  const int64_t row0 = (int64_t)bm * WIDE_BM + 64 * wm;
 #pragma unroll
-  for (int ni = 0; ni < 4; ++ni) {
-    const int n = bn * WIDE_BN + 64 * wn + 16 * ni + fr;
-    const float bias = g.bias[n];
-    const int sc = g.skip == 1 ? n : (n < K ? n : n - K);
+  for (int half = 0; half < 2; ++half) {
 #pragma unroll
-    for (int mi = 0; mi < 4; ++mi) {
-      const int64_t r = (int64_t)bm * WIDE_BM + 64 * wm + 16 * mi + 4 * g4;
-      const v4f c = acc[mi][ni];
+    for (int nh = 0; nh < 2; ++nh) {
+      const int ni = 2 * half + nh;
+      const float bias = g.bias[bn * WIDE_BN + 64 * wn + 16 * ni + fr];
 #pragma unroll
-      for (int pr = 0; pr < 2; ++pr) {
-        const int64_t rv = r + 2 * pr;
-        const float h = tanh_f(c[2 * pr] + bias);
-        float y = h, dy = (1.f - h * h) * c[2 * pr + 1];
-        if (g.skip) {
-          y += WT<P>::get(g.A[rv * K + sc]);
-          dy += WT<P>::get(g.A[(rv + 1) * K + sc]);
+      for (int mi = 0; mi < 4; ++mi) {
+        const v4f c = acc[mi][ni];
+#pragma unroll
+        for (int pr = 0; pr < 2; ++pr) {
+          const float h = tanh_f(c[2 * pr] + bias);
+          const int r = 16 * mi + 4 * g4 + 2 * pr;
+          ep[r * WIDE_EPS + 16 * nh + fr] = h;
+          ep[(r + 1) * WIDE_EPS + 16 * nh + fr] = (1.f - h * h) * c[2 * pr + 1];
         }
-        g.Y[rv * N + n] = WT<P>::put(y);
-        g.Y[(rv + 1) * N + n] = WT<P>::put(dy);
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int cq = lane & 3, rq = lane >> 2;
+    const int n = bn * WIDE_BN + 64 * wn + 32 * half + 8 * cq;
+    const int sc = g.skip == 1 ? n : (n < K ? n : n - K);
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int r = 16 * it + rq;
+      const float4 y0 = *(const float4 *)(ep + r * WIDE_EPS + 8 * cq);
+      const float4 y1 = *(const float4 *)(ep + r * WIDE_EPS + 8 * cq + 4);
+      float y[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
+      const int64_t row = row0 + r;
+      if (g.skip) {
+        const uint4 hv = *(const uint4 *)(g.A + row * K + sc);
+        const uint32_t hw[4] = {hv.x, hv.y, hv.z, hv.w};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) y[q] += WT<P>::get((uint16_t)(hw[q >> 1] >> (16 * (q & 1))));
+      }
+      *(uint4 *)(g.Y + row * N + n) = pack8<P>(y);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
