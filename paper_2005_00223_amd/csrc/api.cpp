@@ -834,7 +834,7 @@ int wide_forward(dp_ctx *c, int64_t n) {
   HIPCHK(c, hipStreamSynchronize(s));
   wb.row0[0] = 0;
   for (int k = 0; k < nets; ++k)
-    wb.row0[k + 1] = wb.row0[k] + (2 * (int64_t)wb.cnt_h[k] + WIDE_BM - 1) / WIDE_BM * WIDE_BM;
+    wb.row0[k + 1] = wb.row0[k] + (2 * (int64_t)wb.cnt_h[k] + WIDE_ROWPAD - 1) / WIDE_ROWPAD * WIDE_ROWPAD;
   int maxw = 0;
   for (int l = 1; l <= d.n_emb; ++l) maxw = std::max(maxw, d.ew[l]);
   const size_t need = (size_t)wb.row0[nets] * maxw;

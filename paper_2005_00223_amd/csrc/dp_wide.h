@@ -10,8 +10,9 @@ namespace dpk {
 
 constexpr int WIDE_MAXT = 4;                      // atom types the wide path takes
 constexpr int WIDE_NETS = WIDE_MAXT * WIDE_MAXT;  // embedding nets (t, u)
-constexpr int WIDE_BM = 128;                      // GEMM row tile (pair rows)
-constexpr int WIDE_BN = 128;                      // GEMM column tile (features)
+constexpr int WIDE_BM = 128;                      // smallest GEMM row tile (pair rows)
+constexpr int WIDE_BN = 128;                      // smallest GEMM column tile (features)
+constexpr int WIDE_ROWPAD = 256;                  // rows of each net padded to the largest row tile
 constexpr int WIDE_BK = 64;                       // GEMM depth per LDS stage
 constexpr int WIDE_GRID = 2048;                   // workgroups of the per-atom kernels
 
@@ -46,7 +47,7 @@ struct WideGemm {
   const uint16_t *Bt;  // [N][K] weights, transposed
   const float *bias;   // [N]
   uint16_t *Y;         // [rows][N] layer output
-  int64_t rows;        // multiple of WIDE_BM
+  int64_t rows;        // multiple of WIDE_ROWPAD
   int K, N;            // K % WIDE_BK == 0, N % WIDE_BN == 0
   int skip;            // 0 none, 1 identity (N == K), 2 doubling (N == 2K)
 };

@@ -141,38 +141,49 @@ void launch_wide_l0(hipStream_t s, const WideArgs &a) {
 // tanh and its derivative are applied there; the results are then staged in
 // LDS (FP32) and written, with the skip connection added, 16 bytes per lane.
 // ---------------------------------------------------------------------------
-constexpr int WIDE_STAGE = 2 * (WIDE_BM + WIDE_BN) * WIDE_BK;  // bytes of one stage (A then B)
+// tile shapes: BIG = 0: 128 x 128, four waves of 64 x 64; BIG = 1: 256 x 256,
+// eight waves of 64 x 128 (more MFMA work per LDS byte read, for N % 256 == 0)
+template <int BIG>
+struct GT {
+  static constexpr int BM = BIG ? 256 : 128, BN = BIG ? 256 : 128, NT = BIG ? 8 : 4;  // NT: 16-col tiles per wave
+  static constexpr int WM = BM / 64, WAVES = WM * (BN / (16 * NT));
+  static constexpr int STAGE = 2 * (BM + BN) * WIDE_BK;  // bytes of one stage (A then B)
+  static constexpr int NBLK = (BM + BN) / 8;             // 1 KB blocks per stage
+  static_assert(NBLK == 8 * WAVES, "eight blocks per wave and stage");
+};
 constexpr int WIDE_EPS = 36;                                    // FP32 row stride of the epilogue staging
 
 __device__ inline void wide_dma(const uint16_t *src, unsigned char *lds) {
   __builtin_amdgcn_global_load_lds((const void *)src, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
 }
 
-template <int P>
-__global__ void __launch_bounds__(256, 2) k_wide_gemm(WideGemm g, int nbm, int nbn) {
+template <int P, int BIG>
+__global__ void __launch_bounds__(64 * GT<BIG>::WAVES, BIG ? 1 : 2) k_wide_gemm(WideGemm g, int nbm, int nbn) {
   typedef typename WT<P>::v8 V;
-  __shared__ __align__(16) unsigned char lds[2 * WIDE_STAGE];
+  typedef GT<BIG> S;
+  constexpr int NT = S::NT;
+  __shared__ __align__(16) unsigned char lds[2 * S::STAGE];
   // workgroups are dealt round-robin to the eight XCDs: give each XCD a
-  // contiguous run of tiles, ordered in groups of 8 row blocks x all column
+  // contiguous run of tiles, ordered in groups of GM row blocks x all column
   // blocks, column block outer, so that an XCD's L2 holds the group's row
-  // blocks (8 x 128 x K) while the weight columns stream past once per group
+  // blocks (1024 rows x K) while the weight columns stream past once per group
   const int ntile = nbm * nbn, per = gridDim.x / 8;
   const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
   if (tile >= ntile) return;  // whole workgroup: before any barrier
-  constexpr int GM = 8;
+  constexpr int GM = BIG ? 4 : 8;
   const int grp = tile / (GM * nbn), in = tile % (GM * nbn);
   const int gm = nbm - grp * GM < GM ? nbm - grp * GM : GM;
   const int bm = grp * GM + in % gm, bn = in / gm;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv & 1, wn = wv >> 1;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv % S::WM, wn = wv / S::WM;
   const int K = g.K, N = g.N;
-  // blocks of a stage: A rows 8 b..8 b+7 in block b (0..15), B rows in blocks
-  // 16..31; wave w loads blocks w + 4 j, lane l row l / 8, chunk (l % 8) ^ (l / 8)
+  // blocks of a stage: A rows 8 b..8 b+7 in block b (b < BM / 8), then the B
+  // rows; wave w loads blocks w + WAVES j, lane l row l / 8, chunk (l % 8) ^ (l / 8)
   const int fr = lane & 15;
   const uint16_t *src[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int b = wv + 4 * j, isb = b >> 4, rb = b & 15;
-    const uint16_t *base = isb ? g.Bt + (int64_t)bn * WIDE_BN * K : g.A + (int64_t)bm * WIDE_BM * K;
+    const int b = wv + S::WAVES * j, isb = b >= S::BM / 8, rb = isb ? b - S::BM / 8 : b;
+    const uint16_t *base = isb ? g.Bt + (int64_t)bn * S::BN * K : g.A + (int64_t)bm * S::BM * K;
     src[j] = base + (int64_t)(8 * rb + (lane >> 3)) * K + 8 * ((lane & 7) ^ (lane >> 3));
   }
   // fragment reads: row fr of a 16-row group = block 2 group + fr / 8, row fr % 8,
@@ -180,13 +191,13 @@ __global__ void __launch_bounds__(256, 2) k_wide_gemm(WideGemm g, int nbm, int n
   const int rr = fr & 7, rbk = fr >> 3;
   auto issue = [&](int kt, int st) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) wide_dma(src[j] + kt * WIDE_BK, lds + st * WIDE_STAGE + (wv + 4 * j) * 1024);
+    for (int j = 0; j < 8; ++j) wide_dma(src[j] + kt * WIDE_BK, lds + st * S::STAGE + (wv + S::WAVES * j) * 1024);
   };
-  v4f acc[4][4];
+  v4f acc[4][NT];
 #pragma unroll
   for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int ni = 0; ni < NT; ++ni) acc[mi][ni] = v4f{0.f, 0.f, 0.f, 0.f};
   const int nkt = K / WIDE_BK;
   issue(0, 0);
   __builtin_amdgcn_s_waitcnt(0);
@@ -194,35 +205,35 @@ __global__ void __launch_bounds__(256, 2) k_wide_gemm(WideGemm g, int nbm, int n
   for (int kt = 0; kt < nkt; ++kt) {
     const int st = kt & 1;
     if (kt + 1 < nkt) issue(kt + 1, st ^ 1);
-    const unsigned char *sb = lds + st * WIDE_STAGE;
+    const unsigned char *sb = lds + st * S::STAGE;
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
       const int off = (rr * 8 + ((4 * ks + (lane >> 4)) ^ rr)) * 16 + rbk * 1024;
-      V af[4], bf[4];
+      V af[4], bf[NT];
 #pragma unroll
       for (int mi = 0; mi < 4; ++mi) af[mi] = *(const V *)(sb + 2 * (4 * wm + mi) * 1024 + off);
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni) bf[ni] = *(const V *)(sb + (16 + 2 * (4 * wn + ni)) * 1024 + off);
+      for (int ni = 0; ni < NT; ++ni) bf[ni] = *(const V *)(sb + (S::BM / 8 + 2 * (NT * wn + ni)) * 1024 + off);
 #pragma unroll
       for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = WT<P>::mma(af[mi], bf[ni], acc[mi][ni]);
+        for (int ni = 0; ni < NT; ++ni) acc[mi][ni] = WT<P>::mma(af[mi], bf[ni], acc[mi][ni]);
     }
     __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the next stage
     __syncthreads();                // everyone's, and this stage is no longer read
   }
-  // epilogue, in two halves of the wave's 64 columns: y = tanh(z + b) and
+  // epilogue, 32 of the wave's columns at a time: y = tanh(z + b) and
   // dy = (1 - tanh^2) dz in the MFMA layout -> LDS (64 rows x 32 columns,
   // FP32) -> per lane 8 consecutive columns of one row, plus the skip, out
   float *ep = (float *)lds + wv * 64 * WIDE_EPS;
   const int g4 = lane >> 4;
-  const int64_t row0 = (int64_t)bm * WIDE_BM + 64 * wm;
+  const int64_t row0 = (int64_t)bm * S::BM + 64 * wm;
 #pragma unroll
-  for (int half = 0; half < 2; ++half) {
+  for (int half = 0; half < NT / 2; ++half) {
 #pragma unroll
     for (int nh = 0; nh < 2; ++nh) {
       const int ni = 2 * half + nh;
-      const float bias = g.bias[bn * WIDE_BN + 64 * wn + 16 * ni + fr];
+      const float bias = g.bias[bn * S::BN + 16 * NT * wn + 16 * ni + fr];
 #pragma unroll
       for (int mi = 0; mi < 4; ++mi) {
         const v4f c = acc[mi][ni];
@@ -239,7 +250,7 @@ __global__ void __launch_bounds__(256, 2) k_wide_gemm(WideGemm g, int nbm, int n
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int cq = lane & 3, rq = lane >> 2;
-    const int n = bn * WIDE_BN + 64 * wn + 32 * half + 8 * cq;
+    const int n = bn * S::BN + 16 * NT * wn + 32 * half + 8 * cq;
     const int sc = g.skip == 1 ? n : (n < K ? n : n - K);
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
@@ -264,10 +275,19 @@ __global__ void __launch_bounds__(256, 2) k_wide_gemm(WideGemm g, int nbm, int n
 
 void launch_wide_gemm(hipStream_t s, const WideGemm &g, int prec) {
   if (g.rows <= 0) return;
-  const int nbm = (int)(g.rows / WIDE_BM), nbn = g.N / WIDE_BN;
+  if (g.N % GT<1>::BN == 0 && g.rows % GT<1>::BM == 0) {
+    typedef GT<1> S;
+    const int nbm = (int)(g.rows / S::BM), nbn = g.N / S::BN;
+    const unsigned grid = (unsigned)((nbm * nbn + 7) / 8 * 8);
+    if (prec == 0) hipLaunchKernelGGL((k_wide_gemm<0, 1>), dim3(grid), dim3(64 * S::WAVES), 0, s, g, nbm, nbn);
+    else hipLaunchKernelGGL((k_wide_gemm<1, 1>), dim3(grid), dim3(64 * S::WAVES), 0, s, g, nbm, nbn);
+    return;
+  }
+  typedef GT<0> S;
+  const int nbm = (int)(g.rows / S::BM), nbn = g.N / S::BN;
   const unsigned grid = (unsigned)((nbm * nbn + 7) / 8 * 8);
-  if (prec == 0) hipLaunchKernelGGL(k_wide_gemm<0>, dim3(grid), dim3(256), 0, s, g, nbm, nbn);
-  else hipLaunchKernelGGL(k_wide_gemm<1>, dim3(grid), dim3(256), 0, s, g, nbm, nbn);
+  if (prec == 0) hipLaunchKernelGGL((k_wide_gemm<0, 0>), dim3(grid), dim3(64 * S::WAVES), 0, s, g, nbm, nbn);
+  else hipLaunchKernelGGL((k_wide_gemm<1, 0>), dim3(grid), dim3(64 * S::WAVES), 0, s, g, nbm, nbn);
 }
 
 // ---------------------------------------------------------------------------
