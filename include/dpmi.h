@@ -92,7 +92,12 @@ int dp_create(dp_ctx **out, int device, void *hip_stream);
  * it on the device in `precision` (DP_FP64 ...).  The blob may be freed
  * after the call.  The descriptor is D = T T_<^T with
  * T = (1/desc_norm) sum_j G(s_j) R_j^T (Fig. 1(b)); one embedding net per
- * (centre type, neighbour type) pair and one fitting net per centre type. */
+ * (centre type, neighbour type) pair and one fitting net per centre type.
+ * Embedding widths up to 128 run in every precision; wider nets (up to
+ * 2048, the embedding-size study of Sec. VI-D / Fig. 7: hidden widths
+ * multiples of 64, later widths multiples of 128, M1 a multiple of 256, at
+ * most 4 atom types) run in DP_MIX_FP16 / DP_MIX_BF16 only, as 16-bit GEMMs
+ * over all neighbour pairs; DP_FP64 with such a net returns DP_E_MODEL. */
 int dp_set_model(dp_ctx *c, const void *blob, size_t nbytes, int precision);
 
 /* Change the precision policy of the loaded model (weights are re-cast
