@@ -139,3 +139,60 @@ def test_wide_sweep_workload_atom_energies():
     say(f"  sampled |dE_i| max {d.max():.3e} (|E_i| ~ {np.abs(ref).mean():.3e})")
     assert np.isfinite(f.cpu().numpy()).all()
     assert (d <= 2e-3 * np.maximum(1.0, np.abs(ref))).all()
+
+
+def test_wide_net_deriv_and_atom_energies():
+    """dE/dR of every real slot (the per-pair contraction of the backward
+    kernel, before the FP64 force pass) and the per-atom energies."""
+    from oracle import oracle as O
+    from paper_2005_00223_amd.model import DPModel
+    x, t, box = _system("cu3")
+    spec = _model("cu3", 4.5, (64, 128, 256))
+    n = len(t)
+    say("[wide] net_deriv cu3 64-128-256 fp16")
+    m = DPModel(synth.pack_blob(spec), "fp16")
+    m.compute(x, t, box, keep_intermediates=True)
+    g = {k: v.cpu().numpy() for k, v in m.intermediates(n, spec.M1, spec.M2, spec.nnei,
+                                                        which=("atom_e", "net_deriv")).items()}
+    r = O.Oracle(synth.pack_blob(_quantised(spec, "fp16"))).eval(x, t, box, intermediates=True)
+    real = r["nlist"] >= 0
+    nd, rd = g["net_deriv"][real], r["net_deriv"][real]
+    rel = float(np.linalg.norm(nd - rd) / np.linalg.norm(rd))
+    de = np.abs(g["atom_e"] - r["atom_e"])
+    say(f"  dE/dR relative error {rel:.2e}, max |dE_i| {de.max():.2e}")
+    assert rel <= 5e-3
+    assert (de <= 1e-4 * np.maximum(1.0, np.abs(r["atom_e"]))).all()
+
+
+def test_wide_md_matches_oracle_verlet():
+    """20 NVE steps of water (two types, four wide nets) against the oracle's
+    velocity Verlet on the pre-rounded model."""
+    from oracle import oracle as O
+    from paper_2005_00223_amd.model import DPModel
+    w = synth.workload("water192")
+    spec = _model("water192", 6.0, (64, 128, 256))
+    t = w["types"]
+    v0 = synth.maxwell_boltzmann(w["masses"][t], 300.0, w["vseed"])
+    say("[wide] md water192 64-128-256 fp16, 20 steps")
+    m = DPModel(synth.pack_blob(spec), "fp16")
+    x = torch.tensor(w["coords"], dtype=torch.float64, device="cuda")
+    v = torch.tensor(v0, dtype=torch.float64, device="cuda")
+    th = m.md_run(x, v, t, w["box"], w["masses"], 0.5, 20, skin=0.2, thermo_every=5)
+    assert m.stats()["wide_evals"] >= 20
+    ox, ov, oth = O.Oracle(synth.pack_blob(_quantised(spec, "fp16"))).verlet(
+        w["coords"], v0, t, w["box"], w["masses"], 0.5, 20, every=5)
+    d = x.cpu().numpy() - ox
+    d -= w["box"] * np.round(d / w["box"])
+    th = th.cpu().numpy()
+    say(f"  max |dx| {np.abs(d).max():.2e} A, PE {th[-1, 2]:.6e} vs {oth[-1, 2]:.6e}")
+    assert np.abs(d).max() < 1e-5
+    assert np.abs(th[:, 2] - oth[:, 2]).max() <= 1e-4 * np.abs(oth[:, 2]).max()
+
+
+def test_wide_empty_system():
+    from paper_2005_00223_amd.model import DPModel
+    spec = _model("cu3", 4.5, (64, 128, 256))
+    m = DPModel(synth.pack_blob(spec), "fp16")
+    e, f, v = m.compute(np.zeros((0, 3)), np.zeros(0, dtype=np.int32), np.full(3, 10.9))
+    assert e.item() == 0.0 and f.shape == (0, 3)
+    assert np.all(v.cpu().numpy() == 0.0)
