@@ -141,16 +141,27 @@ void launch_wide_l0(hipStream_t s, const WideArgs &a) {
 // tanh and its derivative are applied there; the results are then staged in
 // LDS (FP32) and written, with the skip connection added, 16 bytes per lane.
 // ---------------------------------------------------------------------------
-// tile shapes: BIG = 0: 128 x 128, four waves of 64 x 64; BIG = 1: 256 x 256,
-// eight waves of 64 x 128 (more MFMA work per LDS byte read, for N % 256 == 0)
+// tile shapes: BIG = 0: 128 x 128, four waves of 64 x 64; BIG = 1:
+// 256 x 256, eight waves of 64 x 128 (more MFMA work per LDS byte read).
+// Two stages: measured on the largest layer (K 1024, N 2048), three stages
+// of 256 x 128 tiles ran 20% slower than two of 256 x 256.
 template <int BIG>
 struct GT {
   static constexpr int BM = BIG ? 256 : 128, BN = BIG ? 256 : 128, NT = BIG ? 8 : 4;  // NT: 16-col tiles per wave
   static constexpr int WM = BM / 64, WAVES = WM * (BN / (16 * NT));
+  static constexpr int NSTAGE = 2;
   static constexpr int STAGE = 2 * (BM + BN) * WIDE_BK;  // bytes of one stage (A then B)
   static constexpr int NBLK = (BM + BN) / 8;             // 1 KB blocks per stage
-  static_assert(NBLK == 8 * WAVES, "eight blocks per wave and stage");
+  static constexpr int NBPW = NBLK / WAVES;              // blocks each wave loads per stage
+  static_assert(NBLK == NBPW * WAVES, "equal shares of a stage");
+  static_assert(NSTAGE * STAGE <= 160 * 1024, "stages fit the LDS");
 };
+
+// s_waitcnt with vmcnt(n) only (expcnt and lgkmcnt left at their maxima)
+template <int n>
+__device__ inline void wait_vmcnt() {
+  __builtin_amdgcn_s_waitcnt((n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14));
+}
 constexpr int WIDE_EPS = 36;                                    // FP32 row stride of the epilogue staging
 
 __device__ inline void wide_dma(const uint16_t *src, unsigned char *lds) {
@@ -162,7 +173,8 @@ __global__ void __launch_bounds__(64 * GT<BIG>::WAVES, BIG ? 1 : 2) k_wide_gemm(
   typedef typename WT<P>::v8 V;
   typedef GT<BIG> S;
   constexpr int NT = S::NT;
-  __shared__ __align__(16) unsigned char lds[2 * S::STAGE];
+  constexpr int NS = S::NSTAGE, NB = S::NBPW;
+  __shared__ __align__(16) unsigned char lds[NS * S::STAGE];
   // workgroups are dealt round-robin to the eight XCDs: give each XCD a
   // contiguous run of tiles, ordered in groups of GM row blocks x all column
   // blocks, column block outer, so that an XCD's L2 holds the group's row
@@ -179,9 +191,9 @@ __global__ void __launch_bounds__(64 * GT<BIG>::WAVES, BIG ? 1 : 2) k_wide_gemm(
   // blocks of a stage: A rows 8 b..8 b+7 in block b (b < BM / 8), then the B
   // rows; wave w loads blocks w + WAVES j, lane l row l / 8, chunk (l % 8) ^ (l / 8)
   const int fr = lane & 15;
-  const uint16_t *src[8];
+  const uint16_t *src[NB];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
+  for (int j = 0; j < NB; ++j) {
     const int b = wv + S::WAVES * j, isb = b >= S::BM / 8, rb = isb ? b - S::BM / 8 : b;
     const uint16_t *base = isb ? g.Bt + (int64_t)bn * S::BN * K : g.A + (int64_t)bm * S::BM * K;
     src[j] = base + (int64_t)(8 * rb + (lane >> 3)) * K + 8 * ((lane & 7) ^ (lane >> 3));
@@ -191,7 +203,7 @@ __global__ void __launch_bounds__(64 * GT<BIG>::WAVES, BIG ? 1 : 2) k_wide_gemm(
   const int rr = fr & 7, rbk = fr >> 3;
   auto issue = [&](int kt, int st) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) wide_dma(src[j] + kt * WIDE_BK, lds + st * S::STAGE + (wv + S::WAVES * j) * 1024);
+    for (int j = 0; j < NB; ++j) wide_dma(src[j] + kt * WIDE_BK, lds + st * S::STAGE + (wv + S::WAVES * j) * 1024);
   };
   v4f acc[4][NT];
 #pragma unroll
@@ -200,12 +212,16 @@ __global__ void __launch_bounds__(64 * GT<BIG>::WAVES, BIG ? 1 : 2) k_wide_gemm(
     for (int ni = 0; ni < NT; ++ni) acc[mi][ni] = v4f{0.f, 0.f, 0.f, 0.f};
   const int nkt = K / WIDE_BK;
   issue(0, 0);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
+  if (NS > 2 && nkt > 1) issue(1, 1);
   for (int kt = 0; kt < nkt; ++kt) {
-    const int st = kt & 1;
-    if (kt + 1 < nkt) issue(kt + 1, st ^ 1);
-    const unsigned char *sb = lds + st * S::STAGE;
+    // stage kt has landed for this wave (with three stages the next one may
+    // still be in flight), then for all waves; the buffer refilled below was
+    // last read in iteration kt - 1, which every wave has finished
+    if (NS > 2 && kt + 1 < nkt) wait_vmcnt<NB>();
+    else wait_vmcnt<0>();
+    __syncthreads();
+    if (kt + NS - 1 < nkt) issue(kt + NS - 1, (kt + NS - 1) % NS);
+    const unsigned char *sb = lds + (kt % NS) * S::STAGE;
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
       const int off = (rr * 8 + ((4 * ks + (lane >> 4)) ^ rr)) * 16 + rbk * 1024;
@@ -219,9 +235,8 @@ __global__ void __launch_bounds__(64 * GT<BIG>::WAVES, BIG ? 1 : 2) k_wide_gemm(
 #pragma unroll
         for (int ni = 0; ni < NT; ++ni) acc[mi][ni] = WT<P>::mma(af[mi], bf[ni], acc[mi][ni]);
     }
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the next stage
-    __syncthreads();                // everyone's, and this stage is no longer read
   }
+  __syncthreads();  // the stages are no longer read: the epilogue reuses the LDS
   // epilogue, 32 of the wave's columns at a time: y = tanh(z + b) and
   // dy = (1 - tanh^2) dz in the MFMA layout -> LDS (64 rows x 32 columns,
   // FP32) -> per lane 8 consecutive columns of one row, plus the skip, out

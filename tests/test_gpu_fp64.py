@@ -238,6 +238,30 @@ def test_deterministic_nlist_and_energy():
 # ---------------------------------------------------------------------------
 # MD driver
 # ---------------------------------------------------------------------------
+def test_md_resume_equals_continuous_run():
+    """Checkpoint / resume: the MD state is the caller's (x, v); 10 steps,
+    then 10 more from the returned arrays, equal 20 steps in one call (the
+    list is rebuilt at the start of each call; the FP64 forces do not depend
+    on the candidate list, only their atomic summation order may differ)."""
+    w = work("water192")
+    say("[md] resume water192 10 + 10 steps")
+    t = w["types"]
+    v0 = synth.maxwell_boltzmann(w["masses"][t], 300.0, w["vseed"])
+    m = gpu_model(w)
+    runs = []
+    for parts in ((20,), (10, 10)):
+        x = torch.tensor(w["coords"], dtype=torch.float64, device="cuda")
+        v = torch.tensor(v0, dtype=torch.float64, device="cuda")
+        for k in parts:
+            m.md_run(x, v, t, w["box"], w["masses"], 0.5, k, skin=0.2, thermo_every=k)
+        runs.append((x.cpu().numpy(), v.cpu().numpy()))
+    d = runs[0][0] - runs[1][0]
+    d -= w["box"] * np.round(d / w["box"])
+    say(f"  max |dx| {np.abs(d).max():.2e}, max |dv| {np.abs(runs[0][1] - runs[1][1]).max():.2e}")
+    assert np.abs(d).max() < 1e-11
+    assert np.abs(runs[0][1] - runs[1][1]).max() < 1e-11
+
+
 def test_md_matches_oracle_verlet():
     w = work("water192")
     say("[md] water192 20 steps")
