@@ -325,6 +325,7 @@ __global__ void __launch_bounds__(256) k_wide_T(WideArgs a) {
       const int net = t * T + u, nr = a.nreal[i * T + u];
       const int64_t rb = a.row0[net] + 2 * (int64_t)a.poff[i * T + u];
       const float4 *R = a.rt + i * a.d.nnei + a.d.off[u];
+#pragma unroll 4
       for (int k = grp; k < nr; k += NG) {
         const uint4 gv = *(const uint4 *)(a.G + (rb + 2 * k) * M1 + 8 * c);
         const float4 r = R[k];
@@ -380,11 +381,11 @@ void launch_wide_T(hipStream_t s, const WideArgs &a) {
 // pairs each lane runs the FP64 force pass of one of them.  dT of the atom
 // is staged in LDS.
 // ---------------------------------------------------------------------------
-template <int P>
+template <int P, int NS>
 __global__ void __launch_bounds__(256) k_wide_bwd(WideArgs a) {
   __shared__ float4 dts[2048];
   __shared__ double vred[4][9];
-  const int T = a.d.ntypes, M1 = a.d.M1, NS = M1 / 256;
+  const int T = a.d.ntypes, M1 = 256 * NS;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double rc = a.d.rcut, rcs = a.d.rcut_smth, inv_w = 1.0 / (rc - rcs);
   double vir[9];
@@ -416,11 +417,16 @@ __global__ void __launch_bounds__(256) k_wide_bwd(WideArgs a) {
         const int64_t slot = i * a.d.nnei + a.d.off[u] + k;
         const float4 R = a.rt[slot];
         float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f, gs = 0.f;
+        uint2 hv[NS], ht[NS];  // all of the pair's loads in flight before any use
+#pragma unroll
+        for (int m = 0; m < NS; ++m) {
+          hv[m] = *(const uint2 *)(a.G + row * M1 + 4 * lane + 256 * m);
+          ht[m] = *(const uint2 *)(a.G + (row + 1) * M1 + 4 * lane + 256 * m);
+        }
+#pragma unroll
         for (int m = 0; m < NS; ++m) {
           const int f = 4 * lane + 256 * m;
-          const uint2 hv = *(const uint2 *)(a.G + row * M1 + f);
-          const uint2 ht = *(const uint2 *)(a.G + (row + 1) * M1 + f);
-          const uint32_t wv4[2] = {hv.x, hv.y}, wt4[2] = {ht.x, ht.y};
+          const uint32_t wv4[2] = {hv[m].x, hv[m].y}, wt4[2] = {ht[m].x, ht[m].y};
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const float x = WT<P>::get((uint16_t)(wv4[e >> 1] >> (16 * (e & 1))));
@@ -490,8 +496,18 @@ __global__ void __launch_bounds__(256) k_wide_bwd(WideArgs a) {
 void launch_wide_bwd(hipStream_t s, const WideArgs &a) {
   if (a.n <= 0) return;
   const unsigned grid = (unsigned)(a.n < WIDE_GRID ? a.n : WIDE_GRID);
-  if (a.prec == 0) hipLaunchKernelGGL(k_wide_bwd<0>, dim3(grid), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_wide_bwd<1>, dim3(grid), dim3(256), 0, s, a);
+  // M1 = 256 NS, NS = 1..8 (the widths the path takes)
+  switch (a.d.M1 / 256) {
+#define WIDE_BWD_CASE(ns)                                                                                  \
+  case ns:                                                                                                 \
+    if (a.prec == 0) hipLaunchKernelGGL((k_wide_bwd<0, ns>), dim3(grid), dim3(256), 0, s, a);             \
+    else hipLaunchKernelGGL((k_wide_bwd<1, ns>), dim3(grid), dim3(256), 0, s, a);                         \
+    break;
+    WIDE_BWD_CASE(1) WIDE_BWD_CASE(2) WIDE_BWD_CASE(3) WIDE_BWD_CASE(4) WIDE_BWD_CASE(5) WIDE_BWD_CASE(6)
+    WIDE_BWD_CASE(7) WIDE_BWD_CASE(8)
+#undef WIDE_BWD_CASE
+    default: break;
+  }
 }
 
 // ---------------------------------------------------------------------------
