@@ -45,3 +45,29 @@ def test_null_context_errors_without_gpu():
     assert L.dp_compute(None, 0, None, None, None, None, None, None) == _lib.DP_E_ARG
     assert L.dp_set_model(None, b"", 0, 0) == _lib.DP_E_ARG
     L.dp_destroy(None)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes mirrors of the structs in include/dpmi.h have the
+    C layout (size and every field offset), checked with the host compiler."""
+    import subprocess
+    from paper_2005_00223_amd import _lib
+    structs = {"dp_stats": _lib.dp_stats, "dp_student_cfg": _lib.dp_student_cfg}
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "dpmi.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        name, field, value = line.split()
+        got[(name, field)] = int(value)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)
