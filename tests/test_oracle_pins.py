@@ -295,6 +295,21 @@ def test_forces_central_fd(oracle_mod, name):
         np.testing.assert_allclose(r["force"][k], fd, rtol=0, atol=tol)
 
 
+def test_forces_central_fd_wide_net(oracle_mod):
+    """A net of the embedding-size study (128-256-512: D has 8,192 features,
+    more than the oracle's former per-layer scratch) on 108 disordered
+    copper atoms, rc 4.5 A: forces equal central differences of the energy."""
+    x, t, box = synth.fcc_copper(3, 3.634, 0.25, seed=7)
+    spec = synth.random_model(1, 4.5, 1.0, (64,), emb=(128, 256, 512), seed=21)
+    o = oracle_mod.Oracle(synth.pack_blob(spec))
+    r = o.eval(x, t, box)
+    nl, _, _ = o.nlist(x, t, box)
+    for k in np.random.default_rng(8).choice(len(t), size=3, replace=False):
+        fd, tol = _local_fd_force(o, x, t, box, k, nl)
+        assert tol < 1e-6
+        np.testing.assert_allclose(r["force"][k], fd, rtol=0, atol=tol)
+
+
 def test_total_energy_fd_and_force_sum(water):
     w, o = water
     x, t, box = w["coords"], w["types"], w["box"]
