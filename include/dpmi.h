@@ -97,7 +97,11 @@ int dp_create(dp_ctx **out, int device, void *hip_stream);
  * 2048, the embedding-size study of Sec. VI-D / Fig. 7: hidden widths
  * multiples of 64, later widths multiples of 128, M1 a multiple of 256, at
  * most 4 atom types) run in DP_MIX_FP16 / DP_MIX_BF16 only, as 16-bit GEMMs
- * over all neighbour pairs; DP_FP64 with such a net returns DP_E_MODEL. */
+ * over all neighbour pairs; DP_FP64 with such a net returns DP_E_MODEL.
+ * Their evaluations read the per-net pair counts back to the host once
+ * (one synchronisation of the context's stream) to lay out the GEMM rows,
+ * and their activation buffers (8 bytes per real pair and feature of the
+ * widest layer) are kept until the next dp_set_model or dp_destroy. */
 int dp_set_model(dp_ctx *c, const void *blob, size_t nbytes, int precision);
 
 /* Change the precision policy of the loaded model (weights are re-cast

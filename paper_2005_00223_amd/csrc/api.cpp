@@ -1420,6 +1420,7 @@ int dp_set_model(dp_ctx *c, const void *blob, size_t nbytes, int precision) {
   if (!parse_blob(blob, nbytes, m, err)) return fail(c, DP_E_MODEL, err);
   c->hm = std::move(m);
   free_ws(c->ws);
+  free_wide(c);
   c->has_model = false;
   c->active = 0;
   c->en[1].ready = false;
