@@ -162,7 +162,6 @@ template <int n>
 __device__ inline void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14));
 }
-constexpr int WIDE_EPS = 36;                                    // FP32 row stride of the epilogue staging
 
 __device__ inline void wide_dma(const uint16_t *src, unsigned char *lds) {
   __builtin_amdgcn_global_load_lds((const void *)src, (__attribute__((address_space(3))) void *)lds, 16, 0, 0);
@@ -237,43 +236,44 @@ __global__ void __launch_bounds__(64 * GT<BIG>::WAVES, BIG ? 1 : 2) k_wide_gemm(
     }
   }
   __syncthreads();  // the stages are no longer read: the epilogue reuses the LDS
-  // epilogue, 32 of the wave's columns at a time: y = tanh(z + b) and
-  // dy = (1 - tanh^2) dz in the MFMA layout -> LDS (64 rows x 32 columns,
-  // FP32) -> per lane 8 consecutive columns of one row, plus the skip, out
-  float *ep = (float *)lds + wv * 64 * WIDE_EPS;
-  const int g4 = lane >> 4;
+  // epilogue, 16 rows at a time: y = tanh(z + b) and dy = (1 - tanh^2) dz in
+  // the MFMA layout -> LDS (16 rows x the wave's 16 NT columns, FP32) -> per
+  // lane 8 consecutive columns of one row, plus the skip, out; a store
+  // instruction covers whole rows of the wave's columns (full 128-byte lines)
+  constexpr int EPS = 16 * NT + 4;  // FP32 row stride of the staging (bank spread)
+  constexpr int CPR = 2 * NT;       // lanes per row (8 columns each)
+  constexpr int RPI = 64 / CPR;     // rows per store instruction
+  float *ep = (float *)lds + wv * 16 * EPS;
+  const int g4 = lane >> 4, cq = lane % CPR, rq = lane / CPR;
   const int64_t row0 = (int64_t)bm * S::BM + 64 * wm;
+  const int n = bn * S::BN + 16 * NT * wn + 8 * cq;
+  const int sc = g.skip == 1 ? n : (n < K ? n : n - K);
+  float bias[NT];
 #pragma unroll
-  for (int half = 0; half < NT / 2; ++half) {
+  for (int ni = 0; ni < NT; ++ni) bias[ni] = g.bias[bn * S::BN + 16 * NT * wn + 16 * ni + fr];
 #pragma unroll
-    for (int nh = 0; nh < 2; ++nh) {
-      const int ni = 2 * half + nh;
-      const float bias = g.bias[bn * S::BN + 16 * NT * wn + 16 * ni + fr];
+  for (int mi = 0; mi < 4; ++mi) {
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi) {
-        const v4f c = acc[mi][ni];
+    for (int ni = 0; ni < NT; ++ni) {
+      const v4f c = acc[mi][ni];
 #pragma unroll
-        for (int pr = 0; pr < 2; ++pr) {
-          const float h = tanh_f(c[2 * pr] + bias);
-          const int r = 16 * mi + 4 * g4 + 2 * pr;
-          ep[r * WIDE_EPS + 16 * nh + fr] = h;
-          ep[(r + 1) * WIDE_EPS + 16 * nh + fr] = (1.f - h * h) * c[2 * pr + 1];
-        }
+      for (int pr = 0; pr < 2; ++pr) {
+        const float h = tanh_f(c[2 * pr] + bias[ni]);
+        const int r = 4 * g4 + 2 * pr;
+        ep[r * EPS + 16 * ni + fr] = h;
+        ep[(r + 1) * EPS + 16 * ni + fr] = (1.f - h * h) * c[2 * pr + 1];
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int cq = lane & 3, rq = lane >> 2;
-    const int n = bn * S::BN + 16 * NT * wn + 32 * half + 8 * cq;
-    const int sc = g.skip == 1 ? n : (n < K ? n : n - K);
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
-      const int r = 16 * it + rq;
-      const float4 y0 = *(const float4 *)(ep + r * WIDE_EPS + 8 * cq);
-      const float4 y1 = *(const float4 *)(ep + r * WIDE_EPS + 8 * cq + 4);
+    for (int it = 0; it < 16 / RPI; ++it) {
+      const int r = RPI * it + rq;
+      const float4 y0 = *(const float4 *)(ep + r * EPS + 8 * cq);
+      const float4 y1 = *(const float4 *)(ep + r * EPS + 8 * cq + 4);
       float y[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
-      const int64_t row = row0 + r;
+      const int64_t row = row0 + 16 * mi + r;
       if (g.skip) {
         const uint4 hv = *(const uint4 *)(g.A + row * K + sc);
         const uint32_t hw[4] = {hv.x, hv.y, hv.z, hv.w};
