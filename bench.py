@@ -156,7 +156,9 @@ def sweep(args, log_fn):
     of the whole path.  FLOPs are the method's algorithmic count per step
     (embedding forward + backward per real pair, descriptor, fitting
     forward + backward); nets up to 128 wide run the register-resident
-    kernels, wider ones the 16-bit GEMM path."""
+    kernels, wider ones the 16-bit GEMM path, with its activations stored as
+    one 16-bit value (mix16, the paper's MIX-16) and/or as hi + lo halves
+    (split, two products per weight)."""
     import torch
     from paper_2005_00223_amd import synth
     from paper_2005_00223_amd.model import DPModel
@@ -167,40 +169,46 @@ def sweep(args, log_fn):
         a, b = (int(v) for v in size.lower().split("x"))
         emb = (a // 2, a, b)
         spec = synth.copper_model(1, emb=emb)
-        m = DPModel(synth.pack_blob(spec), args.precision)
-        x = torch.tensor(w["coords"], dtype=torch.float64, device=m.device)
-        v = torch.tensor(synth.maxwell_boltzmann(w["masses"][w["types"]], w["temp"], w["vseed"]),
-                         dtype=torch.float64, device=m.device)
-        t = torch.tensor(w["types"], dtype=torch.int32, device=m.device)
-        f = torch.zeros((n, 3), dtype=torch.float64, device=m.device)
+        for storage in args.wide_storage.split(","):
+            m = DPModel(synth.pack_blob(spec), args.precision)
+            m.set_wide_storage(0 if storage == "split" else 1)
+            x = torch.tensor(w["coords"], dtype=torch.float64, device=m.device)
+            v = torch.tensor(synth.maxwell_boltzmann(w["masses"][w["types"]], w["temp"], w["vseed"]),
+                             dtype=torch.float64, device=m.device)
+            t = torch.tensor(w["types"], dtype=torch.int32, device=m.device)
+            f = torch.zeros((n, 3), dtype=torch.float64, device=m.device)
 
-        def md(k):
-            return m.md_run(x, v, t, w["box"], w["masses"], w["dt_fs"], k, skin=args.skin, thermo_every=k, forces=f)
+            def md(k):
+                return m.md_run(x, v, t, w["box"], w["masses"], w["dt_fs"], k, skin=args.skin, thermo_every=k, forces=f)
 
-        md(max(1, args.warmup))
-        m.enable_timing(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        md(args.steps)
-        torch.cuda.synchronize()
-        sec = (time.perf_counter() - t0) / args.steps
-        phases = {k: m.timing(k) for k in ("format", "env", "embed_fwd", "fit", "embed_bwd", "total")}
-        m.enable_timing(False)
-        _, nr = m.nlist(n, spec.nnei, spec.ntypes, with_list=False)
-        pairs = float(nr.sum().item())
-        alg = algorithmic(spec, n, pairs)
-        flops = alg["embed_fwd"] + alg["embed_bwd"] + alg["fit"]
-        st = m.stats()
-        row = {"matrix": f"{a}x{b}", "emb": list(emb), "path": "gemm" if st["wide_evals"] > 0 else "fused",
-               "ms_per_step": sec * 1e3, "tflops": flops / sec / 1e12,
-               "embed_tflops": (alg["embed_fwd"] + alg["embed_bwd"]) / ((phases["embed_fwd"] + phases["embed_bwd"])
-                                                                        * 1e-3) / 1e12,
-               "gflop_per_step": flops / 1e9, "phase_ms": {k: round(vv, 4) for k, vv in phases.items()}}
-        log_fn(f"[sweep] {a}x{b} ({row['path']}): {sec * 1e3:.2f} ms/step, {row['tflops']:.1f} TFLOP/s, "
-               f"embedding {row['embed_tflops']:.1f} TFLOP/s")
-        rows.append(row)
-        del m, x, v, t, f
-        torch.cuda.empty_cache()
+            md(max(1, args.warmup))
+            m.enable_timing(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            md(args.steps)
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / args.steps
+            phases = {k: m.timing(k) for k in ("format", "env", "embed_fwd", "fit", "embed_bwd", "total")}
+            m.enable_timing(False)
+            _, nr = m.nlist(n, spec.nnei, spec.ntypes, with_list=False)
+            pairs = float(nr.sum().item())
+            alg = algorithmic(spec, n, pairs)
+            flops = alg["embed_fwd"] + alg["embed_bwd"] + alg["fit"]
+            st = m.stats()
+            wide = st["wide_evals"] > 0
+            row = {"matrix": f"{a}x{b}", "emb": list(emb), "path": "gemm" if wide else "fused",
+                   "storage": storage if wide else "split",
+                   "ms_per_step": sec * 1e3, "tflops": flops / sec / 1e12,
+                   "embed_tflops": (alg["embed_fwd"] + alg["embed_bwd"]) / ((phases["embed_fwd"] + phases["embed_bwd"])
+                                                                            * 1e-3) / 1e12,
+                   "gflop_per_step": flops / 1e9, "phase_ms": {k: round(vv, 4) for k, vv in phases.items()}}
+            log_fn(f"[sweep] {a}x{b} ({row['path']}, {row['storage']}): {sec * 1e3:.2f} ms/step, {row['tflops']:.1f} TFLOP/s, "
+                   f"embedding {row['embed_tflops']:.1f} TFLOP/s")
+            rows.append(row)
+            del m, x, v, t, f
+            torch.cuda.empty_cache()
+            if not wide:
+                break  # the register-resident kernels have one storage
     pk = {"fp16": "f16_mfma", "bf16": "bf16_mfma"}[args.precision]
     return {"metric": "embedding-size study: FLOP/s of MD steps vs last-layer matrix (Fig. 7)", "unit": "TFLOP/s",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "dtype": args.precision, "data": "synthetic",
@@ -231,6 +239,8 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="embedding-size study (Fig. 7) on 13,500 copper atoms instead of the headline run")
     ap.add_argument("--sweep-sizes", default="64x128,128x256,256x512,512x1024,1024x2048")
+    ap.add_argument("--wide-storage", default="mix16,split",
+                    help="activation storage of the GEMM path in the sweep: mix16, split or both")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (traffic-counter calibration)")
     args = ap.parse_args()

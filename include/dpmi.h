@@ -165,6 +165,19 @@ int dp_get_stats(dp_ctx *c, dp_stats *out);
  * Returns DP_E_ARG for another mode. */
 int dp_set_force_scatter(dp_ctx *c, int mode);
 
+/* Storage of the per-pair activations of wide embedding nets (widths above
+ * 128, the embedding-size study of Sec. VI-D / Fig. 7; see dp_set_model).
+ *   mode 0 (default): each activation and tangent as a hi + lo pair of
+ *     16-bit values, both multiplied by the 16-bit weights (two products),
+ *     as the register-resident kernels do: forces within ~1e-5 relative of
+ *     the FP64 evaluation with the same 16-bit weights;
+ *   mode 1: one 16-bit value each, the paper's MIX-16 storage (Sec. V-A):
+ *     half the products and the activation memory; dE/dR of each pair
+ *     within ~2 units of 16-bit roundoff, forces of near-symmetric
+ *     structures (small differences of large pair terms) at a few percent.
+ * Takes effect from the next evaluation.  Returns DP_E_ARG for another mode. */
+int dp_set_wide_storage(dp_ctx *c, int mode);
+
 /* Velocity-Verlet NVE run (Section VI: the MD loop; 0.5 fs water, 1 fs Cu).
  *   coords, vel [natoms][3] device double (A, A/fs), updated in place;
  *   types [natoms] device int32; box [9] host; masses [ntypes] host amu;

@@ -17,7 +17,7 @@ PRECISION = {"fp64": DP_FP64, "fp16": DP_MIX_FP16, "bf16": DP_MIX_BF16}
 
 EXPORTS = ("dp_create", "dp_set_model", "dp_set_precision", "dp_compute", "dp_energy", "dp_energy_backward",
            "dp_get_nlist", "dp_keep_intermediates",
-           "dp_get_intermediates", "dp_get_stats", "dp_set_force_scatter", "dp_student_table", "dp_md_run", "dp_enable_timing", "dp_get_timing",
+           "dp_get_intermediates", "dp_get_stats", "dp_set_force_scatter", "dp_set_wide_storage", "dp_student_table", "dp_md_run", "dp_enable_timing", "dp_get_timing",
            "dp_student_default_cfg", "dp_student_train", "dp_student_get_params", "dp_student_set_params",
            "dp_student_batch_grad", "dp_student_use", "dp_student_judge", "dp_student_judge_sample",
            "dp_student_get_model",
@@ -70,6 +70,7 @@ def lib():
         "dp_get_intermediates": (I32, [P, P, P, P, P]),
         "dp_get_stats": (I32, [P, C.POINTER(dp_stats)]),
         "dp_set_force_scatter": (I32, [P, I32]),
+        "dp_set_wide_storage": (I32, [P, I32]),
         "dp_student_table": (I32, [P, I32]),
         "dp_md_run": (I32, [P, I64, P, P, P, P, P, D, D, I64, I64, P, P]),
         "dp_enable_timing": (I32, [P, I32]),
@@ -160,6 +161,10 @@ def dp_md_run(ctx, natoms, x_ptr, v_ptr, t_ptr, box9, masses, dt, skin, nsteps, 
 
 def dp_set_force_scatter(ctx, mode: int):
     return check(ctx, lib().dp_set_force_scatter(ctx, int(mode)))
+
+
+def dp_set_wide_storage(ctx, mode: int):
+    return check(ctx, lib().dp_set_wide_storage(ctx, int(mode)))
 
 
 def dp_student_table(ctx, on: bool):

@@ -230,6 +230,7 @@ struct dp_ctx {
     bool ok = false;   // the forward of this evaluation ran
   } wb;
   int pending_rc = DP_OK;  // an error inside an evaluation (reported by read_status)
+  int wide_split = 1;      // wide nets: activations stored as hi + lo 16-bit halves (0: one 16-bit value)
   std::string err;
 };
 
@@ -784,6 +785,7 @@ WideArgs wide_args(dp_ctx *c, int64_t n) {
   WideArgs a{};
   a.d = en.d;
   a.prec = c->precision == DP_MIX_FP16 ? 0 : 1;
+  a.split = c->wide_split;
   a.n = n;
   a.xw = w.xw;
   a.nlist = w.nlist;
@@ -837,7 +839,7 @@ int wide_forward(dp_ctx *c, int64_t n) {
     wb.row0[k + 1] = wb.row0[k] + (2 * (int64_t)wb.cnt_h[k] + WIDE_ROWPAD - 1) / WIDE_ROWPAD * WIDE_ROWPAD;
   int maxw = 0;
   for (int l = 1; l <= d.n_emb; ++l) maxw = std::max(maxw, d.ew[l]);
-  const size_t need = (size_t)wb.row0[nets] * maxw;
+  const size_t need = (size_t)wb.row0[nets] * maxw * (1 + c->wide_split);
   if (need > wb.x_cap) {
     for (auto &x : wb.X) {
       if (x) (void)hipFree(x);
@@ -854,18 +856,20 @@ int wide_forward(dp_ctx *c, int64_t n) {
   launch_wide_l0(s, a);
   int cur = 0;
   for (int l = 1; l < d.n_emb; ++l) {
-    const int K = d.ew[l], N = d.ew[l + 1];
+    const int Kb = d.ew[l], N = d.ew[l + 1], sp = c->wide_split;
     for (int k = 0; k < nets; ++k) {
       if (wb.cnt_h[k] == 0) continue;
       WideGemm g{};
-      g.A = wb.X[cur] + wb.row0[k] * K;
+      g.A = wb.X[cur] + wb.row0[k] * (Kb << sp);
       g.Bt = (const uint16_t *)(en.d_wide + en.wnet[k].w[l]);
       g.bias = (const float *)(en.d_wide + en.wnet[k].b[l]);
-      g.Y = wb.X[cur ^ 1] + wb.row0[k] * N;
+      g.Y = wb.X[cur ^ 1] + wb.row0[k] * (N << sp);
       g.rows = wb.row0[k + 1] - wb.row0[k];
-      g.K = K;
+      g.K = Kb << sp;
+      g.Kb = Kb;
       g.N = N;
-      g.skip = N == K ? 1 : (N == 2 * K ? 2 : 0);
+      g.split = sp;
+      g.skip = N == Kb ? 1 : (N == 2 * Kb ? 2 : 0);
       launch_wide_gemm(s, g, a.prec);
     }
     cur ^= 1;
@@ -1653,6 +1657,13 @@ int dp_get_intermediates(dp_ctx *c, double *atom_e, double *T, double *D, double
 int dp_get_stats(dp_ctx *c, dp_stats *out) {
   if (!c || !out) return DP_E_ARG;
   *out = c->stats;
+  return DP_OK;
+}
+
+int dp_set_wide_storage(dp_ctx *c, int mode) {
+  if (!c) return DP_E_ARG;
+  if (mode != 0 && mode != 1) return fail(c, DP_E_ARG, "wide storage mode must be 0 (hi + lo) or 1 (16-bit)");
+  c->wide_split = mode == 0 ? 1 : 0;
   return DP_OK;
 }
 

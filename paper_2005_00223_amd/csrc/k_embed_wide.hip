@@ -57,6 +57,28 @@ __device__ inline uint4 pack8(const float (&x)[8]) {
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
+// 8 values as 16-bit hi = rn16(x) and lo = rn16(x - hi)
+template <int P>
+__device__ inline void pack8_split(const float (&x)[8], uint4 &hi, uint4 &lo) {
+  float r[8];
+  uint16_t h[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    h[q] = WT<P>::put(x[q]);
+    r[q] = x[q] - WT<P>::get(h[q]);
+  }
+  hi = make_uint4((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16),
+                  (uint32_t)h[4] | ((uint32_t)h[5] << 16), (uint32_t)h[6] | ((uint32_t)h[7] << 16));
+  lo = pack8<P>(r);
+}
+
+// the value of feature f of an activation row (split: hi + lo)
+template <int P>
+__device__ inline float act(const uint16_t *row, int f, int width, int split) {
+  const float v = WT<P>::get(row[f]);
+  return split ? v + WT<P>::get(row[width + f]) : v;
+}
+
 // ---------------------------------------------------------------------------
 // pair counts: atom i's pairs of net (t_i, u) start at pair poff[i][u] of
 // that net (wave prefix sums, one atomic per wave and net)
@@ -113,9 +135,20 @@ __global__ void __launch_bounds__(256) k_wide_l0(WideArgs a) {
           y[q] = h;
           dy[q] = (1.f - h * h) * w;
         }
-        uint16_t *row = a.X0 + (rb + 2 * k) * W1 + 8 * c;
-        *(uint4 *)row = pack8<P>(y);
-        *(uint4 *)(row + W1) = pack8<P>(dy);
+        const int ld = W1 << a.split;  // row length
+        uint16_t *row = a.X0 + (rb + 2 * k) * ld + 8 * c;
+        if (a.split) {
+          uint4 hi, lo;
+          pack8_split<P>(y, hi, lo);
+          *(uint4 *)row = hi;
+          *(uint4 *)(row + W1) = lo;
+          pack8_split<P>(dy, hi, lo);
+          *(uint4 *)(row + ld) = hi;
+          *(uint4 *)(row + ld + W1) = lo;
+        } else {
+          *(uint4 *)row = pack8<P>(y);
+          *(uint4 *)(row + ld) = pack8<P>(dy);
+        }
       }
     }
   }
@@ -186,7 +219,7 @@ __global__ void __launch_bounds__(64 * GT<BIG>::WAVES, BIG ? 1 : 2) k_wide_gemm(
   const int gm = nbm - grp * GM < GM ? nbm - grp * GM : GM;
   const int bm = grp * GM + in % gm, bn = in / gm;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, wm = wv % S::WM, wn = wv / S::WM;
-  const int K = g.K, N = g.N;
+  const int K = g.K, Kb = g.Kb, N = g.N, ldy = g.N << g.split;
   // blocks of a stage: A rows 8 b..8 b+7 in block b (b < BM / 8), then the B
   // rows; wave w loads blocks w + WAVES j, lane l row l / 8, chunk (l % 8) ^ (l / 8)
   const int fr = lane & 15;
@@ -194,15 +227,20 @@ __global__ void __launch_bounds__(64 * GT<BIG>::WAVES, BIG ? 1 : 2) k_wide_gemm(
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     const int b = wv + S::WAVES * j, isb = b >= S::BM / 8, rb = isb ? b - S::BM / 8 : b;
-    const uint16_t *base = isb ? g.Bt + (int64_t)bn * S::BN * K : g.A + (int64_t)bm * S::BM * K;
-    src[j] = base + (int64_t)(8 * rb + (lane >> 3)) * K + 8 * ((lane & 7) ^ (lane >> 3));
+    const uint16_t *base = isb ? g.Bt + (int64_t)bn * S::BN * Kb : g.A + (int64_t)bm * S::BM * K;
+    src[j] = base + (int64_t)(8 * rb + (lane >> 3)) * (isb ? Kb : K) + 8 * ((lane & 7) ^ (lane >> 3));
   }
+  // the B rows hold Kb values: a split input's second half reuses them
+  bool bblk[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) bblk[j] = wv + S::WAVES * j >= S::BM / 8;
   // fragment reads: row fr of a 16-row group = block 2 group + fr / 8, row fr % 8,
   // chunk 4 ks + lane / 16 at slot chunk ^ (fr % 8)
   const int rr = fr & 7, rbk = fr >> 3;
   auto issue = [&](int kt, int st) {
 #pragma unroll
-    for (int j = 0; j < NB; ++j) wide_dma(src[j] + kt * WIDE_BK, lds + st * S::STAGE + (wv + S::WAVES * j) * 1024);
+    for (int j = 0; j < NB; ++j)
+      wide_dma(src[j] + (bblk[j] ? (kt * WIDE_BK) % Kb : kt * WIDE_BK), lds + st * S::STAGE + (wv + S::WAVES * j) * 1024);
   };
   v4f acc[4][NT];
 #pragma unroll
@@ -247,7 +285,7 @@ __global__ void __launch_bounds__(64 * GT<BIG>::WAVES, BIG ? 1 : 2) k_wide_gemm(
   const int g4 = lane >> 4, cq = lane % CPR, rq = lane / CPR;
   const int64_t row0 = (int64_t)bm * S::BM + 64 * wm;
   const int n = bn * S::BN + 16 * NT * wn + 8 * cq;
-  const int sc = g.skip == 1 ? n : (n < K ? n : n - K);
+  const int sc = g.skip == 1 ? n : (n < Kb ? n : n - Kb);
   float bias[NT];
 #pragma unroll
   for (int ni = 0; ni < NT; ++ni) bias[ni] = g.bias[bn * S::BN + 16 * NT * wn + 16 * ni + fr];
@@ -275,12 +313,22 @@ __global__ void __launch_bounds__(64 * GT<BIG>::WAVES, BIG ? 1 : 2) k_wide_gemm(
       float y[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
       const int64_t row = row0 + 16 * mi + r;
       if (g.skip) {
-        const uint4 hv = *(const uint4 *)(g.A + row * K + sc);
-        const uint32_t hw[4] = {hv.x, hv.y, hv.z, hv.w};
 #pragma unroll
-        for (int q = 0; q < 8; ++q) y[q] += WT<P>::get((uint16_t)(hw[q >> 1] >> (16 * (q & 1))));
+        for (int half = 0; half <= g.split; ++half) {
+          const uint4 hv = *(const uint4 *)(g.A + row * K + half * Kb + sc);
+          const uint32_t hw[4] = {hv.x, hv.y, hv.z, hv.w};
+#pragma unroll
+          for (int q = 0; q < 8; ++q) y[q] += WT<P>::get((uint16_t)(hw[q >> 1] >> (16 * (q & 1))));
+        }
       }
-      *(uint4 *)(g.Y + row * N + n) = pack8<P>(y);
+      if (g.split) {
+        uint4 hi, lo;
+        pack8_split<P>(y, hi, lo);
+        *(uint4 *)(g.Y + row * ldy + n) = hi;
+        *(uint4 *)(g.Y + row * ldy + N + n) = lo;
+      } else {
+        *(uint4 *)(g.Y + row * ldy + n) = pack8<P>(y);
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -325,9 +373,11 @@ __global__ void __launch_bounds__(256) k_wide_T(WideArgs a) {
       const int net = t * T + u, nr = a.nreal[i * T + u];
       const int64_t rb = a.row0[net] + 2 * (int64_t)a.poff[i * T + u];
       const float4 *R = a.rt + i * a.d.nnei + a.d.off[u];
+      const int ld = M1 << a.split;  // row length; T is linear in G: hi and lo rows add
 #pragma unroll 4
-      for (int k = grp; k < nr; k += NG) {
-        const uint4 gv = *(const uint4 *)(a.G + (rb + 2 * k) * M1 + 8 * c);
+      for (int e = grp; e < (nr << a.split); e += NG) {
+        const int k = e >> a.split, half = e & a.split;
+        const uint4 gv = *(const uint4 *)(a.G + (rb + 2 * k) * ld + half * M1 + 8 * c);
         const float4 r = R[k];
         const uint32_t w[4] = {gv.x, gv.y, gv.z, gv.w};
 #pragma unroll
@@ -381,7 +431,7 @@ void launch_wide_T(hipStream_t s, const WideArgs &a) {
 // pairs each lane runs the FP64 force pass of one of them.  dT of the atom
 // is staged in LDS.
 // ---------------------------------------------------------------------------
-template <int P, int NS>
+template <int P, int NS, int SP>
 __global__ void __launch_bounds__(256) k_wide_bwd(WideArgs a) {
   __shared__ float4 dts[2048];
   __shared__ double vred[4][9];
@@ -417,26 +467,39 @@ __global__ void __launch_bounds__(256) k_wide_bwd(WideArgs a) {
         const int64_t slot = i * a.d.nnei + a.d.off[u] + k;
         const float4 R = a.rt[slot];
         float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f, gs = 0.f;
-        uint2 hv[NS], ht[NS];  // all of the pair's loads in flight before any use
+        // gR and gs are linear in G and dG/ds: with split rows the hi and lo
+        // halves are contracted one after the other
+        constexpr int ld = M1 << SP;
+#pragma unroll 1
+        for (int half = 0; half <= SP; ++half) {
+          const uint16_t *gv0 = a.G + row * ld + half * M1, *gt0 = gv0 + ld;
+          // steps whose loads are in flight together: all of them up to 4, else
+          // the largest divisor of NS up to 4 (register budget)
+          constexpr int MG = NS <= 4 ? NS : (NS % 4 == 0 ? 4 : (NS % 3 == 0 ? 3 : (NS % 2 == 0 ? 2 : 1)));
+#pragma unroll 1
+          for (int m0 = 0; m0 < NS; m0 += MG) {
+            uint2 hv[MG], ht[MG];
 #pragma unroll
-        for (int m = 0; m < NS; ++m) {
-          hv[m] = *(const uint2 *)(a.G + row * M1 + 4 * lane + 256 * m);
-          ht[m] = *(const uint2 *)(a.G + (row + 1) * M1 + 4 * lane + 256 * m);
-        }
+            for (int m = 0; m < MG; ++m) {
+              hv[m] = *(const uint2 *)(gv0 + 4 * lane + 256 * (m0 + m));
+              ht[m] = *(const uint2 *)(gt0 + 4 * lane + 256 * (m0 + m));
+            }
 #pragma unroll
-        for (int m = 0; m < NS; ++m) {
-          const int f = 4 * lane + 256 * m;
-          const uint32_t wv4[2] = {hv[m].x, hv[m].y}, wt4[2] = {ht[m].x, ht[m].y};
+            for (int m = 0; m < MG; ++m) {
+              const int f = 4 * lane + 256 * (m0 + m);
+              const uint32_t wv4[2] = {hv[m].x, hv[m].y}, wt4[2] = {ht[m].x, ht[m].y};
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const float x = WT<P>::get((uint16_t)(wv4[e >> 1] >> (16 * (e & 1))));
-            const float xt = WT<P>::get((uint16_t)(wt4[e >> 1] >> (16 * (e & 1))));
-            const float4 d = dts[f + e];
-            g0 += x * d.x;
-            g1 += x * d.y;
-            g2 += x * d.z;
-            g3 += x * d.w;
-            gs += xt * (d.x * R.x + d.y * R.y + d.z * R.z + d.w * R.w);
+              for (int e = 0; e < 4; ++e) {
+                const float x = WT<P>::get((uint16_t)(wv4[e >> 1] >> (16 * (e & 1))));
+                const float xt = WT<P>::get((uint16_t)(wt4[e >> 1] >> (16 * (e & 1))));
+                const float4 d = dts[f + e];
+                g0 += x * d.x;
+                g1 += x * d.y;
+                g2 += x * d.z;
+                g3 += x * d.w;
+                gs += xt * (d.x * R.x + d.y * R.y + d.z * R.z + d.w * R.w);
+              }
+            }
           }
         }
 #pragma unroll
@@ -500,8 +563,13 @@ void launch_wide_bwd(hipStream_t s, const WideArgs &a) {
   switch (a.d.M1 / 256) {
 #define WIDE_BWD_CASE(ns)                                                                                  \
   case ns:                                                                                                 \
-    if (a.prec == 0) hipLaunchKernelGGL((k_wide_bwd<0, ns>), dim3(grid), dim3(256), 0, s, a);             \
-    else hipLaunchKernelGGL((k_wide_bwd<1, ns>), dim3(grid), dim3(256), 0, s, a);                         \
+    if (a.split) {                                                                                         \
+      if (a.prec == 0) hipLaunchKernelGGL((k_wide_bwd<0, ns, 1>), dim3(grid), dim3(256), 0, s, a);        \
+      else hipLaunchKernelGGL((k_wide_bwd<1, ns, 1>), dim3(grid), dim3(256), 0, s, a);                    \
+    } else {                                                                                               \
+      if (a.prec == 0) hipLaunchKernelGGL((k_wide_bwd<0, ns, 0>), dim3(grid), dim3(256), 0, s, a);        \
+      else hipLaunchKernelGGL((k_wide_bwd<1, ns, 0>), dim3(grid), dim3(256), 0, s, a);                    \
+    }                                                                                                      \
     break;
     WIDE_BWD_CASE(1) WIDE_BWD_CASE(2) WIDE_BWD_CASE(3) WIDE_BWD_CASE(4) WIDE_BWD_CASE(5) WIDE_BWD_CASE(6)
     WIDE_BWD_CASE(7) WIDE_BWD_CASE(8)

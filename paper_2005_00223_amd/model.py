@@ -127,6 +127,11 @@ class DPModel:
         1: FP64 global atomics for every pair force."""
         L.dp_set_force_scatter(self.ctx, mode)
 
+    def set_wide_storage(self, mode: int):
+        """Wide embedding nets: 0 = activations as hi + lo 16-bit pairs
+        (default, accurate); 1 = one 16-bit value each (MIX-16 storage)."""
+        L.dp_set_wide_storage(self.ctx, mode)
+
     # ---- student embedding net -------------------------------------------
     @staticmethod
     def student_cfg(**kw) -> "L.dp_student_cfg":

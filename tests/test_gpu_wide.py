@@ -70,23 +70,34 @@ def _model(name, rc, emb, seed=21):
 # the virial.  Energies are dominated by the fitting biases and agree far
 # better; their bars are u/5.
 BARS = {"fp16": (5e-3, 1e-4, 5e-3), "bf16": (4e-2, 8e-4, 4e-2)}
+# split storage (hi + lo halves, two products): the activations carry ~2^-22
+# (FP16) / ~2^-16 (BF16) relative; what remains in the forces is FP32
+# accumulation, ~1e-5 (measured 3e-6 - 1.4e-5): bars 2e-4 / 1e-3.  Energies
+# are limited by the fitting net's arithmetic, as with either storage.
+BARS_SPLIT = {"fp16": (2e-4, 1e-4, 2e-4), "bf16": (1e-3, 8e-4, 1e-3)}
 
 
-@pytest.mark.parametrize("sysname,rc,emb,prec", [
-    ("cu3", 4.5, (32, 64, 128), "fp16"),
-    ("cu3", 4.5, (64, 128, 256), "fp16"),
-    ("cu3", 4.5, (64, 128, 256), "bf16"),
-    ("cu3", 4.5, (256, 512, 1024), "fp16"),
-    ("cu3", 3.7, (512, 1024, 2048), "fp16"),
-    ("water192", 6.0, (64, 128, 256), "fp16"),
+@pytest.mark.parametrize("sysname,rc,emb,prec,storage", [
+    ("cu3", 4.5, (32, 64, 128), "fp16", "split"),
+    ("cu3", 4.5, (64, 128, 256), "fp16", "mix16"),
+    ("cu3", 4.5, (64, 128, 256), "fp16", "split"),
+    ("cu3", 4.5, (64, 128, 256), "bf16", "mix16"),
+    ("cu3", 4.5, (64, 128, 256), "bf16", "split"),
+    ("cu3", 4.5, (256, 512, 1024), "fp16", "mix16"),
+    ("cu3", 4.5, (256, 512, 1024), "fp16", "split"),
+    ("cu3", 3.7, (512, 1024, 2048), "fp16", "mix16"),
+    ("cu3", 3.7, (512, 1024, 2048), "fp16", "split"),
+    ("water192", 6.0, (64, 128, 256), "fp16", "mix16"),
+    ("water192", 6.0, (64, 128, 256), "fp16", "split"),
 ])
-def test_wide_matches_oracle(sysname, rc, emb, prec):
+def test_wide_matches_oracle(sysname, rc, emb, prec, storage):
     from oracle import oracle as O
     from paper_2005_00223_amd.model import DPModel
     x, t, box = _system(sysname)
     spec = _model(sysname, rc, emb)
-    say(f"[wide] {sysname} rc {rc} emb {emb} {prec}: {len(t)} atoms")
+    say(f"[wide] {sysname} rc {rc} emb {emb} {prec} {storage}: {len(t)} atoms")
     m = DPModel(synth.pack_blob(spec), prec)
+    m.set_wide_storage(0 if storage == "split" else 1)
     e, f, v = m.compute(x, t, box)
     st = m.stats()
     # 32-64-128 runs the register-resident kernels (hi/lo split activations)
@@ -102,7 +113,8 @@ def test_wide_matches_oracle(sysname, rc, emb, prec):
     vs = max(1e-12, float(np.abs(vo).max()))
     say(f"  force RMSE {df:.3e} (RMS|F| {rms:.3e}, rel {df / rms:.2e}), |dE| {de:.3e} "
         f"(E {r['energy']:.4e}, rel {de / abs(r['energy']):.2e}), max|dV| {dv:.3e} (rel {dv / vs:.2e})")
-    bf, be, bv = BARS[prec]
+    # nets up to 128 wide run the register-resident kernels whatever the storage
+    bf, be, bv = (BARS_SPLIT if storage == "split" and emb[-1] > 128 else BARS)[prec]
     assert np.isfinite(f).all()
     assert df <= bf * rms
     assert de <= be * abs(r["energy"])
@@ -198,24 +210,27 @@ def test_wide_empty_system():
     assert np.all(v.cpu().numpy() == 0.0)
 
 
-def test_wide_sweep_workload_sampled_forces():
+@pytest.mark.parametrize("storage", ["split", "mix16"])
+def test_wide_sweep_workload_sampled_forces(storage):
     """128-256-512 (both GEMM tile shapes) on the full sweep workload.  dE/dR
     of every real slot of 4 sampled atoms (what the GEMM path computes per
-    pair; the oracle evaluates each atom as its only centre) within 10u, and
-    the total force on 2 sampled atoms (the oracle takes the atom and its
-    neighbours as centres, which gives that force exactly).  Forces of this
-    nearly perfect lattice (0.05 A jitter) are small differences of large
-    pair terms: with dE/dR at ~2u the force RMSE is 3.5% of RMS|F| here
-    (0.7% at 0.25 A jitter), per atom up to ~9% (2,916-atom run), so the
-    per-atom force bar is 15% of RMS|F|."""
+    pair; the oracle evaluates each atom as its only centre), and the total
+    force on 2 sampled atoms (the oracle takes the atom and its neighbours as
+    centres, which gives that force exactly).  Split storage: dE/dR within
+    1e-4 relative and forces within 1e-3 eV/A.  MIX-16 storage: dE/dR within
+    10u; forces of this nearly perfect lattice (0.05 A jitter) are small
+    differences of large pair terms, so with dE/dR at ~2u the force RMSE is
+    3.5% of RMS|F| (0.7% at 0.25 A jitter), per atom up to ~9% (2,916-atom
+    run): the per-atom bar is 15% of RMS|F|."""
     from oracle import oracle as O
     from paper_2005_00223_amd.model import DPModel
     w = synth.workload("cu13500")
     spec = synth.copper_model(1, emb=(128, 256, 512))
     x, t, box = w["coords"], w["types"], w["box"]
     n = len(t)
-    say(f"[wide] sweep workload {n} atoms, emb 128-256-512, sampled dE/dR and forces")
+    say(f"[wide] sweep workload {n} atoms, emb 128-256-512, {storage}, sampled dE/dR and forces")
     m = DPModel(synth.pack_blob(spec), "fp16")
+    m.set_wide_storage(0 if storage == "split" else 1)
     e, f, v = m.compute(x, t, box, keep_intermediates=True)
     assert m.stats()["wide_evals"] >= 1
     nd = m.intermediates(n, spec.M1, spec.M2, spec.nnei, which=("net_deriv",))["net_deriv"].cpu().numpy()
@@ -229,11 +244,11 @@ def test_wide_sweep_workload_sampled_forces():
         rd = r["net_deriv"][0][real]
         rel = float(np.linalg.norm(nd[k][real] - rd) / np.linalg.norm(rd))
         say(f"  atom {k}: dE/dR relative error {rel:.2e} over {int(real.sum())} slots")
-        assert rel <= 5e-3
+        assert rel <= (1e-4 if storage == "split" else 5e-3)
     nl, _, _ = o.nlist(x, t, box)
     for k in rng.choice(n, size=2, replace=False):
         cen = np.unique(np.concatenate([[k], nl[k][nl[k] >= 0]]))
         fk = o.eval(x, t, box, centres=cen)["force"][k]
         d = float(np.linalg.norm(f[k] - fk))
         say(f"  atom {k}: |dF| {d:.3e} (|F| {np.linalg.norm(fk):.3e}, RMS|F| {rms:.3e})")
-        assert d <= 0.15 * rms
+        assert d <= (1e-3 if storage == "split" else 0.15 * rms)
