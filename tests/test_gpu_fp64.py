@@ -276,4 +276,8 @@ def test_md_matches_oracle_verlet():
     d -= w["box"] * np.round(d / w["box"])
     assert np.abs(d).max() < 1e-9
     f_tol(v.cpu().numpy(), ov, 1e-9)
-    rel_tol(th.cpu().numpy()[:, 1:4], oth[:, 1:4], 1e-9)
+    thg = th.cpu().numpy()
+    # all six columns: step, KE, PE, KE + PE, T, P (P carries the virial)
+    np.testing.assert_array_equal(thg[:, 0], oth[:, 0])
+    for c in range(1, 6):
+        rel_tol(thg[:, c], oth[:, c], 1e-9)

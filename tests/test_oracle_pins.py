@@ -450,3 +450,118 @@ def test_maxwell_boltzmann_exact_temperature():
     ke = 0.5 * synth.MVV2E * (m[:, None] * v * v).sum()
     np.testing.assert_allclose(2 * ke / ((3 * 300 - 3) * synth.KB_EV), 300.0, rtol=1e-12)
     np.testing.assert_allclose((m[:, None] * v).sum(0), 0.0, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# MD units and thermo columns (Section VI: NVE runs in metal units, thermo
+# output of kinetic, potential and total energy, temperature and pressure).
+# The conversion factors below are derived here from the SI definitions
+# (CODATA 2018: e and k_B exact, the atomic mass constant measured), not
+# taken from the oracle or the structure generator.
+# ---------------------------------------------------------------------------
+_E_CHARGE = 1.602176634e-19      # J per eV (exact)
+_K_BOLTZ = 1.380649e-23          # J/K (exact)
+_AMU = 1.66053906660e-27         # kg
+_MVV2E_SI = _AMU * (1e-10 / 1e-15) ** 2 / _E_CHARGE     # amu A^2/fs^2 -> eV
+_ACC_SI = _E_CHARGE / 1e-10 / _AMU * 1e-15 ** 2 / 1e-10  # eV/(A amu) -> A/fs^2
+_KB_SI = _K_BOLTZ / _E_CHARGE                             # eV/K
+
+
+def _zero_force_model():
+    """Water model with the output weights zeroed: E_i = b4 = 0 for every
+    atom, so forces and virial vanish (weight surgery, Fig. 1(g))."""
+    spec = synth.water_model(0)
+    for t in range(spec.ntypes):
+        spec.fit_W[t][3][:] = 0.0
+        spec.fit_b[t][3][:] = 0.0
+    return spec
+
+
+def test_md_unit_constants_from_si():
+    """The two conversions the integrator needs, written out from SI."""
+    np.testing.assert_allclose(_MVV2E_SI, 103.6427, rtol=1e-6)
+    np.testing.assert_allclose(_ACC_SI, 9.648533212e-3, rtol=1e-9)
+    np.testing.assert_allclose(_ACC_SI * _MVV2E_SI, 1.0, rtol=1e-12)
+    np.testing.assert_allclose(_KB_SI, 8.617333262e-5, rtol=1e-9)
+
+
+def test_thermo_kinetic_temperature_ideal_gas(oracle_mod):
+    """Zero-force model, 0 steps: thermo row 0 holds KE = sum m v^2 / 2 in
+    eV, T from equipartition over 3N - 3 degrees of freedom, and the ideal
+    gas pressure P V = 2 KE / 3 = (N - 1) k_B T (no virial term)."""
+    w = synth.workload("water192")
+    o = oracle_mod.Oracle(synth.pack_blob(_zero_force_model()))
+    t = w["types"]
+    n = len(t)
+    rng = np.random.default_rng(11)
+    v = rng.normal(scale=0.01, size=(n, 3))          # A/fs, arbitrary
+    m = w["masses"][t]
+    _, _, th = o.verlet(w["coords"], v, t, w["box"], w["masses"], 0.5, 0, every=1)
+    ke = 0.5 * (m[:, None] * v * v).sum() * _MVV2E_SI
+    vol = float(np.prod(w["box"]))
+    np.testing.assert_allclose(th[0, 1], ke, rtol=1e-9)
+    np.testing.assert_allclose(th[0, 2], 0.0, atol=1e-12)
+    np.testing.assert_allclose(th[0, 3], ke, rtol=1e-9)
+    np.testing.assert_allclose(th[0, 4], 2 * ke / ((3 * n - 3) * _KB_SI), rtol=1e-9)
+    np.testing.assert_allclose(th[0, 5] * vol, (n - 1) * _KB_SI * th[0, 4], rtol=1e-9)
+    np.testing.assert_allclose(th[0, 5] * vol, 2 * ke / 3, rtol=1e-9)
+
+
+def test_verlet_free_flight_and_kick_units(oracle_mod):
+    """Free flight: with zero forces x advances by dt v per step and v
+    stays.  Kick: a dimer released at rest moves, after one step, to
+    x0 + dt^2 F0/(2m) and has v = dt (F0 + F1)/(2m), with the force-to-
+    acceleration factor from SI."""
+    w = synth.workload("water192")
+    o0 = oracle_mod.Oracle(synth.pack_blob(_zero_force_model()))
+    t, box = w["types"], w["box"]
+    rng = np.random.default_rng(12)
+    v = rng.normal(scale=0.01, size=(len(t), 3))
+    x1, v1, _ = o0.verlet(w["coords"], v, t, box, w["masses"], 0.5, 4, every=4)
+    d = x1 - (w["coords"] + 4 * 0.5 * v)
+    d -= box * np.round(d / box)
+    assert np.abs(d).max() < 1e-12
+    np.testing.assert_array_equal(v1, v)
+
+    spec = synth.water_model(0)
+    o = oracle_mod.Oracle(synth.pack_blob(spec))
+    boxd = np.full(3, 20.0)
+    types = np.array([0, 1], dtype=np.int32)
+    x0 = np.array([[5.0, 5.0, 5.0], [6.0, 5.5, 4.2]])
+    masses = np.array([synth.MASS["O"], synth.MASS["H"]])
+    dt = 0.5
+    f0 = o.eval(x0, types, boxd)["force"]
+    xe = x0 + 0.5 * dt * dt * f0 / masses[types][:, None] * _ACC_SI
+    f1 = o.eval(xe, types, boxd)["force"]
+    ve = 0.5 * dt * (f0 + f1) / masses[types][:, None] * _ACC_SI
+    xs, vs, _ = o.verlet(x0, np.zeros((2, 3)), types, boxd, masses, dt, 1, every=1)
+    assert np.abs(f0).max() > 1e-2        # the kick is not vacuous
+    np.testing.assert_allclose(xs, xe, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(vs, ve, rtol=1e-9, atol=1e-15)
+
+
+def test_thermo_pressure_is_minus_dE_dV(oracle_mod):
+    """At rest the pressure column is the configurational pressure
+    -dE/dV under isotropic scaling of the box and all positions (central
+    difference of the energy); with velocities it adds 2 KE / (3 V)."""
+    w = synth.workload("water192")
+    o = oracle_mod.Oracle(synth.pack_blob(w["spec"]))
+    x, t, box = w["coords"], w["types"], w["box"]
+    _, _, th = o.verlet(x, np.zeros_like(x), t, box, w["masses"], 0.5, 0, every=1)
+    eps = 1e-5
+    e = []
+    for sgn in (1, -1):
+        s = 1 + sgn * eps
+        e.append(o.eval(x * s, t, box * s)["energy"])
+    vol = float(np.prod(box))
+    dV = vol * ((1 + eps) ** 3 - (1 - eps) ** 3)
+    p_fd = -(e[0] - e[1]) / dV
+    assert abs(p_fd) > 1e-4
+    np.testing.assert_allclose(th[0, 5], p_fd, rtol=1e-6)
+    np.testing.assert_allclose(th[0, 1], 0.0, atol=0)
+    # with velocities: P = (2 KE + tr Xi) / (3 V), the two parts pinned apart
+    rng = np.random.default_rng(13)
+    v = rng.normal(scale=0.01, size=x.shape)
+    _, _, thv = o.verlet(x, v, t, box, w["masses"], 0.5, 0, every=1)
+    ke = 0.5 * (w["masses"][t][:, None] * v * v).sum() * _MVV2E_SI
+    np.testing.assert_allclose(thv[0, 5], p_fd + 2 * ke / (3 * vol), rtol=1e-6)
