@@ -150,7 +150,7 @@ def cpu_baseline(w, blob, seconds, log_fn):
 
 
 def sweep(args, log_fn):
-    """Embedding-size study (Sec. VI-D, Fig. 7): the copper sweep workload
+    """Embedding-size study (Sec. VII-D, Fig. 7): the copper sweep workload
     (15^3 FCC cells, 13,500 atoms, rc 8 A, sel 512) with embedding nets
     (W/2, W, 2W) for last-layer matrices W x 2W, teacher nets only, MD steps
     of the whole path.  FLOPs are the method's algorithmic count per step

@@ -5,8 +5,8 @@
  * Potential energy E = sum_i E_i, the forces F = -dE/dr and the virial
  * Xi = -sum_{i,j} g_ij (x) r_ij, the quantities the paper's MD step spends
  * its time on (Section III, "Deep Potential Molecular Dynamics" and Fig. 1;
- * Section V-A on the neighbour-list format and the custom Environment,
- * ProdForce and ProdVirial operators; Section V-A "Mixed-precision
+ * Section V-B on the neighbour-list format and the custom Environment,
+ * ProdForce and ProdVirial operators; Section V-B "Mixed-precision
  * computation" for the precision modes).  Every step runs in hand-written
  * HIP kernels on the stream given to dp_create.
  *
@@ -51,7 +51,7 @@ enum {
                           per-atom sort buffer (512) holds                  */
 };
 
-/* Precision policies (after the paper's MIX-16 scheme, Section V-A
+/* Precision policies (after the paper's MIX-16 scheme, Section V-B
  * "Mixed-precision computation").
  * DP_FP64: everything in double.
  * DP_MIX_FP16 / DP_MIX_BF16: embedding layers after the first and the first
@@ -94,7 +94,7 @@ int dp_create(dp_ctx **out, int device, void *hip_stream);
  * T = (1/desc_norm) sum_j G(s_j) R_j^T (Fig. 1(b)); one embedding net per
  * (centre type, neighbour type) pair and one fitting net per centre type.
  * Embedding widths up to 128 run in every precision; wider nets (up to
- * 2048, the embedding-size study of Sec. VI-D / Fig. 7: hidden widths
+ * 2048, the embedding-size study of Sec. VII-D / Fig. 7: hidden widths
  * multiples of 64, later widths multiples of 128, M1 a multiple of 256, at
  * most 4 atom types) run in DP_MIX_FP16 / DP_MIX_BF16 only, as 16-bit GEMMs
  * over all neighbour pairs; DP_FP64 with such a net returns DP_E_MODEL.
@@ -117,7 +117,7 @@ int dp_set_precision(dp_ctx *c, int precision);
  *   forces [natoms][3] device, double, eV/A         (may be NULL)
  *   virial [9]         device, double, eV, row-major Xi_ab (may be NULL)
  * The neighbour list is built from scratch (cell list, cutoff rc, no skin),
- * formatted as in Section V-A (type-sorted, then by distance with ties by
+ * formatted as in Section V-B (type-sorted, then by distance with ties by
  * index, nearest sel kept per type, -1 padded). */
 int dp_compute(dp_ctx *c, int64_t natoms, const double *coords, const int32_t *types, const double *box,
                double *energy, double *forces, double *virial);
@@ -166,12 +166,12 @@ int dp_get_stats(dp_ctx *c, dp_stats *out);
 int dp_set_force_scatter(dp_ctx *c, int mode);
 
 /* Storage of the per-pair activations of wide embedding nets (widths above
- * 128, the embedding-size study of Sec. VI-D / Fig. 7; see dp_set_model).
+ * 128, the embedding-size study of Sec. VII-D / Fig. 7; see dp_set_model).
  *   mode 0 (default): each activation and tangent as a hi + lo pair of
  *     16-bit values, both multiplied by the 16-bit weights (two products),
  *     as the register-resident kernels do: forces within ~1e-5 relative of
  *     the FP64 evaluation with the same 16-bit weights;
- *   mode 1: one 16-bit value each, the paper's MIX-16 storage (Sec. V-A):
+ *   mode 1: one 16-bit value each, the paper's MIX-16 storage (Sec. V-B):
  *     half the products and the activation memory; dE/dR of each pair
  *     within ~2 units of 16-bit roundoff, forces of near-symmetric
  *     structures (small differences of large pair terms) at a few percent.

@@ -3,7 +3,7 @@
  *
  * Plain, slow, FP64 CPU reference of the Deep Potential (smooth edition)
  * energy / force / virial evaluation that the paper accelerates
- * (Section III "Deep Potential Molecular Dynamics", Fig. 1; Section V-A,
+ * (Section III "Deep Potential Molecular Dynamics", Fig. 1; Section V-B,
  * "Increasing computational granularity" and "Optimization of Customized
  * TensorFlow Operators").  Only the tests, the smoke check and the CPU
  * baseline leg of the benchmark may load it; the product path never does.
@@ -11,7 +11,7 @@
  *
  * Every function follows the plain definition, step by step:
  *   wrap -> neighbour set {j : |r_ij| <= rc}, r_ij = r_j - r_i
- *   -> type-sorted, distance-sorted, sel-padded list (Section V-A: sort by
+ *   -> type-sorted, distance-sorted, sel-padded list (Section V-B: sort by
  *      type, then distance; keep the nearest sel per type; pad with -1;
  *      ties broken by index as in the packed 64-bit key)
  *   -> environment matrix rows (s, s x/r, s y/r, s z/r), s = sw(r)/r
@@ -186,7 +186,7 @@ static double or_disp(const double *xi, const double *xj, const double *L, doubl
 }
 
 /* ------------------------------------------------------------------ */
-/* neighbour list: Section V-A formatting                              */
+/* neighbour list: Section V-B formatting                              */
 /* ------------------------------------------------------------------ */
 typedef struct { int64_t type; uint64_t q; int64_t j; } or_key;
 

@@ -1,7 +1,7 @@
 // Host runtime of the C ABI declared in include/dpmi.h: model-blob parsing,
 // device weight layout, the workspace arena (allocated once, grown only when
 // a larger system arrives -- the paper's "trunk of GPU memory", Section
-// V-A), and the launch sequence of one evaluation and of the MD loop.
+// V-B), and the launch sequence of one evaluation and of the MD loop.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -227,6 +227,7 @@ struct dp_ctx {
     int64_t row0[WIDE_NETS + 1]{};
     int32_t cnt_h[WIDE_NETS]{};
     int out = 0;       // buffer holding G after the forward
+    int split = 1;     // activation storage the forward laid the rows out with
     bool ok = false;   // the forward of this evaluation ran
   } wb;
   int pending_rc = DP_OK;  // an error inside an evaluation (reported by read_status)
@@ -785,7 +786,7 @@ WideArgs wide_args(dp_ctx *c, int64_t n) {
   WideArgs a{};
   a.d = en.d;
   a.prec = c->precision == DP_MIX_FP16 ? 0 : 1;
-  a.split = c->wide_split;
+  a.split = c->wb.split;
   a.n = n;
   a.xw = w.xw;
   a.nlist = w.nlist;
@@ -819,6 +820,7 @@ int wide_forward(dp_ctx *c, int64_t n) {
   hipStream_t s = c->stream;
   const int T = d.ntypes, nets = T * T;
   wb.ok = false;
+  wb.split = c->wide_split;
   if (n > wb.n_cap) {
     if (wb.poff) (void)hipFree(wb.poff);
     wb.poff = wb.cnt = nullptr;
@@ -839,7 +841,7 @@ int wide_forward(dp_ctx *c, int64_t n) {
     wb.row0[k + 1] = wb.row0[k] + (2 * (int64_t)wb.cnt_h[k] + WIDE_ROWPAD - 1) / WIDE_ROWPAD * WIDE_ROWPAD;
   int maxw = 0;
   for (int l = 1; l <= d.n_emb; ++l) maxw = std::max(maxw, d.ew[l]);
-  const size_t need = (size_t)wb.row0[nets] * maxw * (1 + c->wide_split);
+  const size_t need = (size_t)wb.row0[nets] * maxw * (1 + wb.split);
   if (need > wb.x_cap) {
     for (auto &x : wb.X) {
       if (x) (void)hipFree(x);
@@ -856,7 +858,7 @@ int wide_forward(dp_ctx *c, int64_t n) {
   launch_wide_l0(s, a);
   int cur = 0;
   for (int l = 1; l < d.n_emb; ++l) {
-    const int Kb = d.ew[l], N = d.ew[l + 1], sp = c->wide_split;
+    const int Kb = d.ew[l], N = d.ew[l + 1], sp = wb.split;
     for (int k = 0; k < nets; ++k) {
       if (wb.cnt_h[k] == 0) continue;
       WideGemm g{};
@@ -1281,6 +1283,7 @@ int quant_of(const dp_ctx *c) {
 // Install student host model `m` (embedding 1-16-32-M1 affine) on the device.
 int install_student(dp_ctx *c, HostModel &&m) {
   c->en[1].ready = false;
+  c->fwd_ready = false;  // a pending backward would meet other nets
   c->shm = std::move(m);
   int rc = upload_emb(c, c->shm, c->en[1]);
   if (rc) return rc;
@@ -1419,6 +1422,7 @@ int dp_set_model(dp_ctx *c, const void *blob, size_t nbytes, int precision) {
   if (precision != DP_FP64 && precision != DP_MIX_FP16 && precision != DP_MIX_BF16)
     return fail(c, DP_E_ARG, "unsupported precision policy");
   HIPCHK(c, hipSetDevice(c->device));
+  c->fwd_ready = false;  // the workspace a pending backward needs is freed below
   HostModel m;
   std::string err;
   if (!parse_blob(blob, nbytes, m, err)) return fail(c, DP_E_MODEL, err);
@@ -1450,6 +1454,7 @@ int dp_set_precision(dp_ctx *c, int precision) {
   const char *why = nullptr;
   if (precision == DP_FP64 && !f64_emb_ok(c->dims, &why)) return fail(c, DP_E_MODEL, why);
   const int old = c->precision;
+  c->fwd_ready = false;  // the forward's buffers belong to the old precision
   c->precision = precision;
   if (precision != DP_FP64) {
     int rc = upload_mix(c);
@@ -1463,6 +1468,7 @@ int dp_set_precision(dp_ctx *c, int precision) {
 
 int dp_keep_intermediates(dp_ctx *c, int keep) {
   if (!c) return DP_E_ARG;
+  if ((keep != 0) != c->keep) c->fwd_ready = false;  // the backward's outputs changed
   c->keep = keep != 0;
   return DP_OK;
 }
@@ -1664,11 +1670,13 @@ int dp_set_wide_storage(dp_ctx *c, int mode) {
   if (!c) return DP_E_ARG;
   if (mode != 0 && mode != 1) return fail(c, DP_E_ARG, "wide storage mode must be 0 (hi + lo) or 1 (16-bit)");
   c->wide_split = mode == 0 ? 1 : 0;
+  c->fwd_ready = false;
   return DP_OK;
 }
 
 int dp_student_table(dp_ctx *c, int on) {
   if (!c) return DP_E_ARG;
+  if ((on != 0) != c->use_tab) c->fwd_ready = false;  // forward and backward would use other layers
   c->use_tab = on != 0;
   return DP_OK;
 }

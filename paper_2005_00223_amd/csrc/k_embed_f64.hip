@@ -1,5 +1,5 @@
 // Double-precision embedding net + descriptor, fused per centre atom so the
-// embedding matrix G never reaches HBM (Section V-A, "Increasing
+// embedding matrix G never reaches HBM (Section V-B, "Increasing
 // computational granularity": the type-sorted, padded list lets every tile
 // of neighbours use one net without branching).
 //

@@ -1,5 +1,5 @@
 // Mixed-precision embedding net + descriptor (after the paper's MIX-16
-// scheme, Section V-A "Mixed-precision computation"): the embedding layers
+// scheme, Section V-B "Mixed-precision computation"): the embedding layers
 // after the first are 16-bit matrix-core products (FP16 or BF16,
 // v_mfma_f32_16x16x32) with FP32 accumulation and 16-bit weights; the
 // rank-1 first layer, tanh, the skip adds and the descriptor contractions

@@ -1,5 +1,5 @@
 // Wide embedding nets in mixed precision (the embedding-size study of the
-// paper's Sec. VI-D / Fig. 7: last-layer matrices up to 1024 x 2048).
+// paper's Sec. VII-D / Fig. 7: last-layer matrices up to 1024 x 2048).
 //
 // Widths of 256 and more do not fit the register-resident per-neighbour
 // kernels, so this path runs the embedding net over all real neighbour pairs
@@ -17,9 +17,16 @@
 //   bwd     per pair dE/dR_j = G_j^T dT_i, dE/ds_j = (dT_i R_j) . dG_j/ds,
 //           then the FP64 force Jacobian, F_j atomics and the virial.
 //
-// Activations are stored in 16 bits without a hi/lo split (the paper's
-// MIX-16 storage), so this path's accuracy is that of MIX-16 (~1e-3
-// relative), not that of the split register-resident kernels.
+// Activations are stored in one of two ways.  By default each value is kept
+// as a hi + lo pair of 16-bit numbers whose sum is the FP32 activation to
+// about 2^-22 relative; every GEMM multiplies both halves by the same 16-bit
+// weights (K runs over [hi | lo]) and T and the backward contract the two
+// halves in turn (they are linear in G).  Forces then come within about
+// 1e-5 relative of FP64 arithmetic on the same rounded weights.  The other
+// storage (split = 0) keeps one 16-bit value per activation, the paper's
+// MIX-16 scheme (Sec. V-B): half the products and activation bytes, with
+// each pair's dE/dR within about two 16-bit roundings (2u) of the exact
+// value.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -363,13 +370,16 @@ __global__ void __launch_bounds__(256) k_wide_T(WideArgs a) {
   __shared__ float4 part[256 * 8];
   const int T = a.d.ntypes, M1 = a.d.M1, C = M1 / 8, NG = 256 / C;
   const int tid = threadIdx.x, c = tid % C, grp = tid / C;
+  // when C does not divide 256 the threads past NG * C have no group: they
+  // neither sum nor store (they still reach every barrier)
+  const bool active = grp < NG;
   const float inv_nc = (float)a.d.inv_nc;
   for (int64_t i = blockIdx.x; i < a.n; i += gridDim.x) {
     const int t = (int)a.xw[i].w;
     float4 acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int u = 0; u < T; ++u) {
+    for (int u = 0; u < T && active; ++u) {
       const int net = t * T + u, nr = a.nreal[i * T + u];
       const int64_t rb = a.row0[net] + 2 * (int64_t)a.poff[i * T + u];
       const float4 *R = a.rt + i * a.d.nnei + a.d.off[u];
@@ -392,6 +402,7 @@ __global__ void __launch_bounds__(256) k_wide_T(WideArgs a) {
     }
     float4 *Tg = (float4 *)(a.T32 + (i * M1 + 8 * c) * 4);
     if (NG == 1) {
+      if (!active) continue;
 #pragma unroll
       for (int q = 0; q < 8; ++q)
         Tg[q] = make_float4(acc[q].x * inv_nc, acc[q].y * inv_nc, acc[q].z * inv_nc, acc[q].w * inv_nc);

@@ -1,4 +1,4 @@
-// Environment matrix (the paper's "Environment" operator, Section V-A and
+// Environment matrix (the paper's "Environment" operator, Section V-B and
 // Table III): for every real slot of the formatted list,
 //   d = r_j - r_i (minimum image), r = |d|,
 //   R = (s, s dx/r, s dy/r, s dz/r),  s = sw(r)/r,

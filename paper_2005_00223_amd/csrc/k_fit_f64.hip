@@ -6,7 +6,7 @@
 //   Y_{l+1} = t (+ Y_l if out == in, + (Y_l, Y_l) if out == 2 in).
 // The bias add, tanh, skip add and the store of t (kept for the backward,
 // the paper's fused TANH/TANHGrad idea) all sit in the GEMM epilogue
-// (Section V-B, "Replace MATMUL and SUM" and "Replace CONCAT and SUM").
+// (Section V-C, "Replace MATMUL and SUM" and "Replace CONCAT and SUM").
 // Output layer: E_i = Y_L . w + b (one wave per row).
 // Backward layer l: gZ = gY_{l+1} (1 - t^2) is formed while the A tile is
 // loaded, gY_l = gZ W^T (+ the skip's pass-through), gY_0 = dE/dD.

@@ -1,4 +1,4 @@
-// Mixed-precision fitting net (Fig. 1(d,g); Section V-A "Mixed-precision
+// Mixed-precision fitting net (Fig. 1(d,g); Section V-B "Mixed-precision
 // computation"), fused per tile of 16 type-sorted rows (one wave):
 //
 //   forward   D = T T_<^T is formed on the fly from T (M1 x 4 per atom) as

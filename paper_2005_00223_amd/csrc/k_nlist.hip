@@ -1,5 +1,5 @@
 // Neighbour-list kernels: periodic wrap, per-type row ordering, cell list,
-// skin candidate list and the formatted list of Section V-A (type-sorted,
+// skin candidate list and the formatted list of Section V-B (type-sorted,
 // distance-sorted with index tie-break, nearest sel per type kept, -1
 // padded).  The distance of every pair is the IEEE result of
 //   d = x_j - x_i (one minimum-image correction), r = sqrt((dx dx + dy dy) + dz dz)
@@ -315,7 +315,7 @@ void launch_candidates(hipStream_t s, int64_t n, const double4 *xw, const CellGr
 }
 
 // ---------------------------------------------------------------------------
-// formatting (Section V-A): one wave per atom, keys in LDS.  The keys are
+// formatting (Section V-B): one wave per atom, keys in LDS.  The keys are
 // ranked exactly by a bucketed counting sort: bucket = type * FMT_NB +
 // floor(FMT_NB (quantised distance / (quantised rc + 1))^3), monotone in the
 // key and holding equal expected counts (neighbours grow like r^3), so

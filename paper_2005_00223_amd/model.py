@@ -32,6 +32,7 @@ class DPModel:
         stream = torch.cuda.current_stream(self.device)
         self.ctx = L.dp_create(self.device.index, stream.cuda_stream)
         self.precision = precision
+        self.eval_id = 0   # bumped by every call that replaces the library's forward state
         L.dp_set_model(self.ctx, bytes(blob), L.PRECISION[precision])
 
     def __del__(self):
@@ -41,6 +42,7 @@ class DPModel:
             self.ctx = None
 
     def set_precision(self, precision: str):
+        self.eval_id += 1
         L.dp_set_precision(self.ctx, L.PRECISION[precision])
         self.precision = precision
 
@@ -57,6 +59,7 @@ class DPModel:
         e = torch.empty(1, dtype=torch.float64, device=self.device)
         f = torch.empty((n, 3), dtype=torch.float64, device=self.device)
         v = torch.empty(9, dtype=torch.float64, device=self.device)
+        self.eval_id += 1
         L.dp_keep_intermediates(self.ctx, keep_intermediates)
         L.dp_compute(self.ctx, n, _ptr(x), _ptr(t), _box9(box), _ptr(e), _ptr(f), _ptr(v))
         self._n = n
@@ -68,6 +71,7 @@ class DPModel:
         x = self._dev(coords, torch.float64)
         t = self._dev(types, torch.int32)
         e = torch.empty(1, dtype=torch.float64, device=self.device)
+        self.eval_id += 1
         L.dp_energy(self.ctx, x.shape[0], _ptr(x), _ptr(t), _box9(box), _ptr(e))
         self._n = x.shape[0]
         return e[0]
@@ -111,6 +115,7 @@ class DPModel:
         rows = nsteps // thermo_every + 1 if thermo_every > 0 else 0
         th = torch.zeros((max(rows, 1), 6), dtype=torch.float64, device=self.device)
         m = list(np.asarray(masses, dtype=np.float64)) + [1.0] * (8 - len(masses))
+        self.eval_id += 1
         L.dp_md_run(self.ctx, n, _ptr(coords), _ptr(vel), _ptr(t), _box9(box), m, dt, skin, nsteps,
                     max(thermo_every, 1), _ptr(th) if rows else None, _ptr(forces))
         return th[:rows]
@@ -120,6 +125,7 @@ class DPModel:
 
     def student_table(self, on: bool):
         """Tabulated student layers (default on; mixed precision only)."""
+        self.eval_id += 1
         L.dp_student_table(self.ctx, on)
 
     def set_force_scatter(self, mode: int):
@@ -130,6 +136,7 @@ class DPModel:
     def set_wide_storage(self, mode: int):
         """Wide embedding nets: 0 = activations as hi + lo 16-bit pairs
         (default, accurate); 1 = one 16-bit value each (MIX-16 storage)."""
+        self.eval_id += 1
         L.dp_set_wide_storage(self.ctx, mode)
 
     # ---- student embedding net -------------------------------------------
@@ -147,9 +154,11 @@ class DPModel:
     def student_train(self, **kw) -> float:
         """Fit the student to the teacher on the last evaluated frame; returns
         the held-out relative RMSE of G (or the last Adam loss without refit)."""
+        self.eval_id += 1
         return L.dp_student_train(self.ctx, self.student_cfg(**kw))
 
     def student_use(self, on=True):
+        self.eval_id += 1
         L.dp_student_use(self.ctx, on)
 
     def student_judge(self, every=20, max_force_rmse=1e-3, sample_side=0.0):
@@ -162,6 +171,7 @@ class DPModel:
         return L.dp_student_get_model(self.ctx)
 
     def student_set_model(self, blob: bytes):
+        self.eval_id += 1
         L.dp_student_set_model(self.ctx, bytes(blob))
 
     def _student_np(self, ntypes, M1):
@@ -195,21 +205,60 @@ class DPModel:
 
 
 class DPEnergy(torch.autograd.Function):
-    """E(coords) with the library's hand-written adjoint as the backward.
+    """E(coords[, strain]) with the library's hand-written adjoint as the
+    backward.
 
     forward runs dp_energy (list, environment matrix, embedding +
     descriptor, fitting net); backward runs dp_energy_backward, the fitting
-    and embedding backward with the ProdForce scatter, and returns
-    grad_E * dE/dcoords = -grad_E * F.  Use as
-    ``E = DPEnergy.apply(coords, model, types, box)``."""
+    and embedding backward with the ProdForce and ProdVirial passes, and
+    returns grad_E * dE/dcoords = -grad_E * F and, when a strain tensor is
+    given, grad_E * dE/dstrain = -grad_E * virial.  Use as
+    ``E = DPEnergy.apply(coords, model, types, box)`` or
+    ``E = DPEnergy.apply(coords, model, types, box, strain)``.
+
+    strain: a 3x3 double tensor eps (usually zeros with requires_grad): the
+    energy is evaluated at x -> (I + eps) x with the box scaled the same way
+    (diagonal eps only, as boxes are orthorhombic; off-diagonal entries must
+    be zero, their gradient is still returned).  The virial is
+    Xi = -dE/deps at eps = 0 (Sec. V-B, ProdVirial).
+
+    Each forward records the model's evaluation id; if other evaluations ran
+    on the model before this backward (two applies in one graph, or a
+    compute in between), the backward first re-runs the forward on the
+    saved coordinates (with the model's settings at that time), so every
+    gradient belongs to its own coordinates."""
 
     @staticmethod
-    def forward(ctx, coords, model, types, box):
-        ctx.model = model
-        return model.energy(coords.detach(), types, box)
+    def forward(ctx, coords, model, types, box, strain=None):
+        x = coords.detach()
+        b = np.asarray(_box9(box), dtype=np.float64).reshape(3, 3)
+        a = None
+        if strain is not None:
+            eps = strain.detach().to("cpu", torch.float64).numpy().reshape(3, 3)
+            if np.any(eps - np.diag(np.diag(eps))):
+                raise ValueError("DPEnergy: only a diagonal strain can be applied (orthorhombic boxes)")
+            a = np.eye(3) + eps
+            x = x @ torch.as_tensor(a.T, dtype=x.dtype, device=x.device)
+            b = b @ a.T
+        ctx.model, ctx.types, ctx.box, ctx.a = model, types, b.reshape(9), a
+        ctx.x = x
+        e = model.energy(x, types, ctx.box)
+        ctx.eval_id = model.eval_id
+        return e
 
     @staticmethod
     def backward(ctx, grad_e):
+        m = ctx.model
+        if m.eval_id != ctx.eval_id:
+            m.energy(ctx.x, ctx.types, ctx.box)
+            ctx.eval_id = m.eval_id
         # the library works with one host scalar: a CUDA grad is read back
-        f, _ = ctx.model.energy_backward(float(grad_e))
-        return -f, None, None, None
+        f, vir = m.energy_backward(float(grad_e))
+        gs = None
+        if ctx.a is None:
+            gx = -f
+        else:
+            at = torch.as_tensor(ctx.a, dtype=f.dtype, device=f.device)
+            gx = -f @ at
+            gs = -vir @ torch.linalg.inv(at).T
+        return gx, None, None, None, gs

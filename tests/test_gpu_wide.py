@@ -1,11 +1,12 @@
-"""Wide embedding nets (the embedding-size study of Sec. VI-D, Fig. 7)
+"""Wide embedding nets (the embedding-size study of Sec. VII-D, Fig. 7)
 through the 16-bit GEMM path, against the FP64 oracle.
 
 The oracle runs the same model with its 16-bit weights rounded beforehand
 (GEMM layers of the embedding nets, the first two fitting layers), so the
-difference left is the path's own: activations and their tangents stored in
-16 bits between layers (the paper's MIX-16 storage, no hi/lo split), FP32
-GEMM accumulation and FP32 sums of T.  Cases: the study's smallest matrix
+difference left is the path's own: activations and their tangents stored
+between layers either as one 16-bit value (the paper's MIX-16 storage) or as
+hi + lo 16-bit halves (the default), FP32 GEMM accumulation and FP32 sums
+of T.  Cases: the study's smallest matrix
 (64 x 128, net 32-64-128, on the register-resident kernels), the smallest
 wide net
 (64-128-256) in FP16 and BF16, 256-512-1024, the largest net of the study
@@ -87,6 +88,10 @@ BARS_SPLIT = {"fp16": (2e-4, 1e-4, 2e-4), "bf16": (1e-3, 8e-4, 1e-3)}
     ("cu3", 4.5, (256, 512, 1024), "fp16", "split"),
     ("cu3", 3.7, (512, 1024, 2048), "fp16", "mix16"),
     ("cu3", 3.7, (512, 1024, 2048), "fp16", "split"),
+    # M1 = 1280: 160 feature columns per T workgroup, which does not divide
+    # its 256 threads (the threads past 160 must stay idle)
+    ("cu3", 3.7, (320, 640, 1280), "fp16", "mix16"),
+    ("cu3", 3.7, (320, 640, 1280), "fp16", "split"),
     ("water192", 6.0, (64, 128, 256), "fp16", "mix16"),
     ("water192", 6.0, (64, 128, 256), "fp16", "split"),
 ])

@@ -25,7 +25,7 @@ def cu(oracle_mod):
 
 
 # ---------------------------------------------------------------------------
-# neighbour list (Section V-A: type, then distance; nearest sel kept; -1 pad;
+# neighbour list (Section V-B: type, then distance; nearest sel kept; -1 pad;
 # ties by index as in the packed key)
 # ---------------------------------------------------------------------------
 def _numpy_bruteforce_nlist(x, types, box, rc, sel):
