@@ -122,6 +122,27 @@ int dp_set_precision(dp_ctx *c, int precision);
 int dp_compute(dp_ctx *c, int64_t natoms, const double *coords, const int32_t *types, const double *box,
                double *energy, double *forces, double *virial);
 
+/* dp_compute without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Arguments, results and errors as for dp_compute;
+ * the caller still passes coords, types and the outputs.  The workspace is
+ * a static device array of 256 MiB, one per GPU, held until the process
+ * ends, instead of the context's own: a system whose workspace does not fit
+ * it returns DP_E_CAP before any kernel is queued (as a rough guide, for
+ * the 1-25-50-100 nets: about 4,600 water or 3,200 copper atoms (sel 138 /
+ * 512) in DP_FP64, about 25,000 water or 14,000 copper atoms in
+ * DP_MIX_FP16 / DP_MIX_BF16); wide embedding nets (widths above
+ * 128) return DP_E_MODEL.  With a student in use whose layer table no
+ * dp_compute has built yet, the student's layers are evaluated instead of
+ * the table.  The call calls no hipMalloc, hipFree or other allocating
+ * routine.  Every call on one GPU, from any context, uses the same array and
+ * leaves its contents behind (each call rewrites what it reads): calls that
+ * overlap in time on one GPU race and must be serialised by the caller.
+ * The context's own workspace, its last lists and a pending dp_energy are
+ * left untouched (dp_get_nlist etc. still refer to the last dp_compute). */
+int dp_compute_noalloc(dp_ctx *c, int64_t natoms, const double *coords, const int32_t *types, const double *box,
+                       double *energy, double *forces, double *virial);
+
 /* The two halves of dp_compute, for reverse-mode frameworks
  * (torch.autograd.Function): dp_energy runs the forward half only (list,
  * environment matrix, embedding + descriptor, fitting net, energy) and keeps

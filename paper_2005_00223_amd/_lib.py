@@ -15,7 +15,7 @@ DP_OK, DP_E_ARG, DP_E_NOMODEL, DP_E_MODEL, DP_E_BOX, DP_E_TYPE, DP_E_OOM, DP_E_H
 DP_FP64, DP_MIX_FP16, DP_MIX_BF16 = 0, 2, 3
 PRECISION = {"fp64": DP_FP64, "fp16": DP_MIX_FP16, "bf16": DP_MIX_BF16}
 
-EXPORTS = ("dp_create", "dp_set_model", "dp_set_precision", "dp_compute", "dp_energy", "dp_energy_backward",
+EXPORTS = ("dp_create", "dp_set_model", "dp_set_precision", "dp_compute", "dp_compute_noalloc", "dp_energy", "dp_energy_backward",
            "dp_get_nlist", "dp_keep_intermediates",
            "dp_get_intermediates", "dp_get_stats", "dp_set_force_scatter", "dp_set_wide_storage", "dp_student_table", "dp_md_run", "dp_enable_timing", "dp_get_timing",
            "dp_student_default_cfg", "dp_student_train", "dp_student_get_params", "dp_student_set_params",
@@ -63,6 +63,7 @@ def lib():
         "dp_set_model": (I32, [P, C.c_char_p, C.c_size_t, I32]),
         "dp_set_precision": (I32, [P, I32]),
         "dp_compute": (I32, [P, I64, P, P, P, P, P, P]),
+        "dp_compute_noalloc": (I32, [P, I64, P, P, P, P, P, P]),
         "dp_energy": (I32, [P, I64, P, P, P, P]),
         "dp_energy_backward": (I32, [P, D, P, P]),
         "dp_get_nlist": (I32, [P, P, P]),
@@ -123,6 +124,11 @@ def dp_set_precision(ctx, precision: int):
 def dp_compute(ctx, natoms, coords_ptr, types_ptr, box9, e_ptr, f_ptr, v_ptr):
     box = (C.c_double * 9)(*[float(b) for b in box9])
     return check(ctx, lib().dp_compute(ctx, int(natoms), coords_ptr, types_ptr, box, e_ptr, f_ptr, v_ptr))
+
+
+def dp_compute_noalloc(ctx, natoms, coords_ptr, types_ptr, box9, e_ptr, f_ptr, v_ptr):
+    box = (C.c_double * 9)(*[float(b) for b in box9])
+    return check(ctx, lib().dp_compute_noalloc(ctx, int(natoms), coords_ptr, types_ptr, box, e_ptr, f_ptr, v_ptr))
 
 
 def dp_energy(ctx, natoms, coords_ptr, types_ptr, box9, e_ptr):

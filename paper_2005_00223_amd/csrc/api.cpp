@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,44 @@ using namespace dpk;
 namespace dpk {
 size_t embed_lds_bytes(const Dims &d, int pass);
 }
+
+// Workspace of the no-allocation entry point (dp_compute_noalloc): a static
+// device array, one copy per GPU, held until the process ends.  Host code
+// never hands this name to a kernel or a copy (on the host it is only a
+// stand-in); it uses the device address that hipGetSymbolAddress returns,
+// looked up once per device with that device current (scratch_address).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_done[SCRATCH_DEVICES];
+void *g_scratch_ptr[SCRATCH_DEVICES];
+hipError_t g_scratch_rc[SCRATCH_DEVICES];
+
+// Device address of `scratch` on `device`, which must be the current device.
+// NULL (and the HIP error in *rc) when the lookup failed.
+void *scratch_address(int device, hipError_t *rc) {
+  if (device < 0 || device >= SCRATCH_DEVICES) {
+    *rc = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_done[device]) {
+    void *p = nullptr;
+    g_scratch_rc[device] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (g_scratch_rc[device] != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    g_scratch_ptr[device] = p;
+    g_scratch_done[device] = true;
+  }
+  *rc = g_scratch_rc[device];
+  return g_scratch_ptr[device];
+}
+}  // namespace
 
 namespace {
 
@@ -129,6 +168,7 @@ struct Workspace {
   int64_t n_cap = -1, rows_cap = 0, ncell_cap = 0;
   int cand_cap = 0;
   bool nd = false;
+  bool owned = true;  // base came from hipMalloc (false: the static scratch array)
   double4 *xw = nullptr, *xref = nullptr, *rt = nullptr, *dr = nullptr;
   float4 *rt32 = nullptr;  // mixed precision: the environment matrix in FP32
   int32_t *cell_of, *cell_atoms, *cell_start, *cell_fill, *scan_tmp, *cand, *cand_n, *nlist, *nreal, *pos_of_atom,
@@ -232,6 +272,13 @@ struct dp_ctx {
   } wb;
   int pending_rc = DP_OK;  // an error inside an evaluation (reported by read_status)
   int wide_split = 1;      // wide nets: activations stored as hi + lo 16-bit halves (0: one 16-bit value)
+  // no-allocation entry point: the device address of this GPU's static
+  // scratch array (NULL if its lookup failed, scratch_rc says why), the
+  // workspace laid out on it, and whether an evaluation runs on it now
+  void *scratch = nullptr;
+  hipError_t scratch_rc = hipSuccess;
+  Workspace ws_na;
+  bool noalloc = false;
   std::string err;
 };
 
@@ -249,7 +296,7 @@ int fail(dp_ctx *c, int code, const std::string &msg) {
   } while (0)
 
 void free_ws(Workspace &w) {
-  if (w.base) (void)hipFree(w.base);
+  if (w.base && w.owned) (void)hipFree(w.base);
   w = Workspace{};
 }
 
@@ -270,27 +317,19 @@ void free_student(dp_ctx *c) {
   c->st = nullptr;
 }
 
-// Carve every buffer out of one allocation.  Sizes depend on n (atoms),
-// the cell count and the candidate capacity.
-int ensure_ws(dp_ctx *c, int64_t n, int64_t ncell, int cand_cap) {
-  Workspace &w = c->ws;
+// Lay every buffer of the workspace out in one block: returns the block's
+// size for nn atoms, nc cells and cc candidate slots per atom, and, when
+// base is not NULL, points the buffers of w into the block at base.
+size_t ws_carve(const dp_ctx *c, Workspace &w, int64_t nn, int64_t nc, int cc, bool nd, char *base) {
   const Dims &d = c->dims;
-  const bool need_nd = c->keep;
   const bool mixed = c->precision != DP_FP64;
-  if (n <= w.n_cap && ncell <= w.ncell_cap && cand_cap <= w.cand_cap && (!need_nd || w.nd) &&
-      w.prec == c->precision)
-    return DP_OK;
-  int64_t nn = std::max<int64_t>(n, w.n_cap > 0 ? (w.n_cap * 5) / 4 : n);
-  nn = std::max<int64_t>(nn, 1);
-  int64_t nc = std::max<int64_t>(ncell, w.ncell_cap);
-  int cc = std::max(cand_cap, w.cand_cap);
-  bool nd = need_nd || w.nd;
-  free_ws(w);
   const int64_t rows = (nn + ROW_TILE - 1) / ROW_TILE * ROW_TILE + (int64_t)ROW_TILE * d.ntypes;
   const int64_t nblk = (nn + 255) / 256 + 1;
   size_t off = 0;
-  std::vector<std::pair<void **, size_t>> plan;
-  auto add = [&](void **p, size_t bytes) { plan.push_back({p, bytes}); };
+  auto add = [&](void **p, size_t bytes) {
+    if (base) *p = base + off;
+    off += (bytes + 255) / 256 * 256;
+  };
   add((void **)&w.xw, sizeof(double4) * nn);
   add((void **)&w.xref, sizeof(double4) * nn);
   add((void **)&w.cell_of, 4 * nn);
@@ -344,31 +383,63 @@ int ensure_ws(dp_ctx *c, int64_t n, int64_t ncell, int cand_cap) {
   add((void **)&w.sub_type_start, 4 * (MAXT + 1));
   add((void **)&w.sub_blk, (size_t)4 * nblk * MAXT);
   add((void **)&w.status, sizeof(DevStatus));
-  for (auto &pr : plan) off += (pr.second + 255) / 256 * 256;
+  if (base) {
+    if (!nd) w.net_deriv = nullptr;
+    if (!mixed) w.cell_part = nullptr;
+    if (mixed) w.rt = w.dr = nullptr;
+    else w.rt32 = nullptr;
+    w.G[0] = w.dD;
+    w.prec = c->precision;
+    w.base = base;
+    w.bytes = off;
+    w.n_cap = nn;
+    w.rows_cap = rows;
+    w.ncell_cap = nc;
+    w.cand_cap = cc;
+    w.nd = nd;
+  }
+  return off;
+}
+
+// Make the workspace hold n atoms, ncell cells and cand_cap candidates per
+// atom.  Normally one allocation, grown by a quarter beyond the need; in
+// the no-allocation entry point the block is the device's static scratch
+// array instead, laid out for exactly this call (an error if too small).
+int ensure_ws(dp_ctx *c, int64_t n, int64_t ncell, int cand_cap) {
+  Workspace &w = c->ws;
+  const bool need_nd = c->keep;
+  if (n <= w.n_cap && ncell <= w.ncell_cap && cand_cap <= w.cand_cap && (!need_nd || w.nd) &&
+      w.prec == c->precision)
+    return DP_OK;
+  if (c->noalloc) {
+    Workspace nw{};
+    const size_t need = ws_carve(c, nw, n, ncell, cand_cap, need_nd, nullptr);
+    if (need > NOALLOC_SCRATCH_BYTES)
+      return fail(c, DP_E_CAP, "dp_compute_noalloc: this system needs a workspace of " + std::to_string(need) +
+                                   " bytes, more than the " + std::to_string(NOALLOC_SCRATCH_BYTES) +
+                                   "-byte static scratch holds (use dp_compute)");
+    nw.owned = false;
+    ws_carve(c, nw, n, ncell, cand_cap, need_nd, (char *)c->scratch);
+    w = nw;
+    c->cgrid_ok = false;
+    return DP_OK;
+  }
+  int64_t nn = std::max<int64_t>(n, w.n_cap > 0 ? (w.n_cap * 5) / 4 : n);
+  nn = std::max<int64_t>(nn, 1);
+  int64_t nc = std::max<int64_t>(ncell, w.ncell_cap);
+  int cc = std::max(cand_cap, w.cand_cap);
+  bool nd = need_nd || w.nd;
+  free_ws(w);
+  Workspace nw{};
+  const size_t off = ws_carve(c, nw, nn, nc, cc, nd, nullptr);
   void *base = nullptr;
   if (hipMalloc(&base, off) != hipSuccess) {
     (void)hipGetLastError();
     return fail(c, DP_E_OOM, "workspace allocation of " + std::to_string(off) + " bytes failed");
   }
-  size_t o = 0;
-  for (auto &pr : plan) {
-    *pr.first = (char *)base + o;
-    o += (pr.second + 255) / 256 * 256;
-  }
-  if (!nd) w.net_deriv = nullptr;
-  if (!mixed) w.cell_part = nullptr;
-  if (mixed) w.rt = w.dr = nullptr;
-  else w.rt32 = nullptr;
+  ws_carve(c, nw, nn, nc, cc, nd, (char *)base);
+  w = nw;
   c->cgrid_ok = false;
-  w.G[0] = w.dD;
-  w.prec = c->precision;
-  w.base = base;
-  w.bytes = off;
-  w.n_cap = nn;
-  w.rows_cap = rows;
-  w.ncell_cap = nc;
-  w.cand_cap = cc;
-  w.nd = nd;
   return DP_OK;
 }
 
@@ -771,7 +842,10 @@ int ensure_table(dp_ctx *c, int64_t n) {
   float smax;
   std::memcpy(&smax, &bits, 4);
   const double shi = smax > 0.f ? 1.25 * (double)smax : 1.0;
-  if (!en.d_tab) HIPCHK(c, hipMalloc(&en.d_tab, (size_t)c->dims.ntypes * c->dims.ntypes * TAB_BYTES));
+  if (!en.d_tab) {
+    if (c->noalloc) return DP_OK;  // no table yet and no allocation allowed: the layers are evaluated
+    HIPCHK(c, hipMalloc(&en.d_tab, (size_t)c->dims.ntypes * c->dims.ntypes * TAB_BYTES));
+  }
   launch_student_table(s, en.d, en.eo, en.d_emb, c->precision == DP_MIX_FP16 ? 0 : 1, shi, en.d_tab);
   HIPCHK(c, hipGetLastError());
   en.tab_shi = shi;
@@ -1389,6 +1463,7 @@ int dp_create(dp_ctx **out, int device, void *hip_stream) {
     delete c;
     return DP_E_HIP;
   }
+  c->scratch = scratch_address(device, &c->scratch_rc);
   *out = c;
   return DP_OK;
 }
@@ -1428,6 +1503,7 @@ int dp_set_model(dp_ctx *c, const void *blob, size_t nbytes, int precision) {
   if (!parse_blob(blob, nbytes, m, err)) return fail(c, DP_E_MODEL, err);
   c->hm = std::move(m);
   free_ws(c->ws);
+  c->ws_na = Workspace{};  // laid out on the static scratch: nothing to free
   free_wide(c);
   c->has_model = false;
   c->active = 0;
@@ -1581,6 +1657,36 @@ __global__ void k_scale(double *x, int64_t n, double a) {
 int dp_compute(dp_ctx *c, int64_t n, const double *coords, const int32_t *types, const double *box, double *energy,
                double *forces, double *virial) {
   return compute_impl(c, n, coords, types, box, energy, forces, virial, true);
+}
+
+int dp_compute_noalloc(dp_ctx *c, int64_t n, const double *coords, const int32_t *types, const double *box,
+                       double *energy, double *forces, double *virial) {
+  if (!c) return DP_E_ARG;
+  if (!c->has_model) return fail(c, DP_E_NOMODEL, "evaluation before dp_set_model");
+  if (!c->scratch)
+    return fail(c, DP_E_HIP, std::string("dp_compute_noalloc: the static scratch array has no device address: ") +
+                                 hipGetErrorString(c->scratch_rc));
+  if (c->en[c->active].wide)
+    return fail(c, DP_E_MODEL, "dp_compute_noalloc: wide embedding nets (widths above 128) lay out their "
+                               "activation buffers per evaluation; use dp_compute");
+  // The context's own workspace, and the state that describes its lists and
+  // a pending dp_energy, are left as they are.
+  const int64_t last_n = c->last_n;
+  const bool fwd_ready = c->fwd_ready, cgrid_ok = c->cgrid_ok;
+  const CellGrid cgrid = c->cgrid;
+  double box_L[3];
+  std::memcpy(box_L, c->box_L, sizeof box_L);
+  std::swap(c->ws, c->ws_na);
+  c->noalloc = true;
+  const int rc = compute_impl(c, n, coords, types, box, energy, forces, virial, true);
+  c->noalloc = false;
+  std::swap(c->ws, c->ws_na);
+  c->last_n = last_n;
+  c->fwd_ready = fwd_ready;
+  c->cgrid_ok = cgrid_ok;
+  c->cgrid = cgrid;
+  std::memcpy(c->box_L, box_L, sizeof box_L);
+  return rc;
 }
 
 int dp_energy(dp_ctx *c, int64_t n, const double *coords, const int32_t *types, const double *box, double *energy) {
