@@ -149,6 +149,57 @@ def cpu_baseline(w, blob, seconds, log_fn):
                       f"(energy, forces, virial of their environments) in {dt2:.1f} s"}
 
 
+def accuracy(args, w, blob, m, m64, x, t, student, frame):
+    """Forces, energy and virial of the benchmarked path (and, when given,
+    of the same precision's teacher nets and of the FP64 GPU path) at the
+    configuration x, against the FP64 oracle: every atom ('full', one
+    oracle evaluation of the whole frame) or N sampled atoms (one oracle
+    evaluation over them and their neighbours, which makes their forces
+    exact)."""
+    from oracle import oracle as O
+    n = len(w["types"])
+    spec = w["spec"]
+    xf = x.cpu().numpy()
+    paths = {"timed": m.compute(x, t, w["box"])}
+    nl = None
+    if args.rmse != "full":
+        nl, _ = m.nlist(n, spec.nnei, spec.ntypes)
+        nl = nl.cpu().numpy()
+    if student:
+        m.student_use(False)
+        paths["teacher"] = m.compute(x, t, w["box"])
+        m.student_use(True)
+    if m64 is not None:
+        paths["fp64"] = m64.compute(x, t, w["box"])
+    paths = {k: (e.item(), f.cpu().numpy(), v.cpu().numpy()) for k, (e, f, v) in paths.items()}
+    o = O.Oracle(blob)
+    t0 = time.perf_counter()
+    if args.rmse == "full":
+        r = o.eval(xf, w["types"], w["box"])
+        ks = np.arange(n)
+        what = f"all {n} atoms"
+    else:
+        rng = np.random.default_rng(7)
+        ks = np.sort(rng.choice(n, size=int(args.rmse), replace=False))
+        cen = np.unique(np.concatenate([ks, nl[ks][nl[ks] >= 0]]))
+        r = o.eval(xf, w["types"], w["box"], centres=cen)
+        what = f"{ks.size} random atoms"
+    t_or = time.perf_counter() - t0
+    acc = {"frame": frame, "atoms": what, "oracle_seconds": t_or, "oracle_threads": O.num_threads(),
+           "force_rms": float(np.sqrt((r["force"][ks] ** 2).sum(1).mean()))}
+    for k, (e, f, v) in paths.items():
+        df = f[ks] - r["force"][ks]
+        acc[k] = {"force_rmse": float(np.sqrt((df ** 2).sum(1).mean())),
+                  "force_max_abs_err": float(np.abs(df).max())}
+        if args.rmse == "full":
+            acc[k].update(energy_err_per_atom=abs(e - r["energy"]) / n,
+                          energy_rel_err=abs(e - r["energy"]) / abs(r["energy"]),
+                          virial_rel_err=float(np.abs(v - r["virial"].reshape(9)).max() / np.abs(r["virial"]).max()))
+        log(f"[bench] {frame}: {k} vs oracle ({what}): force RMSE {acc[k]['force_rmse']:.3e} eV/A, "
+            f"max {acc[k]['force_max_abs_err']:.3e}")
+    return acc
+
+
 def sweep(args, log_fn):
     """Embedding-size study (Sec. VII-D, Fig. 7): the copper sweep workload
     (15^3 FCC cells, 13,500 atoms, rc 8 A, sel 512) with embedding nets
@@ -232,7 +283,10 @@ def main():
     ap.add_argument("--teacher-steps", type=int, default=5,
                     help="steps of the same precision without the student, timed for comparison (0 = skip)")
     ap.add_argument("--fp64-steps", type=int, default=3, help="FP64 steps timed for the comparison (0 = skip)")
-    ap.add_argument("--rmse-atoms", type=int, default=8, help="atoms sampled for the force RMSE vs the oracle")
+    ap.add_argument("--rmse", default="full",
+                    help="force accuracy at the final frame vs the oracle: 'full' (every atom, one oracle "
+                         "evaluation of the whole frame), N (N sampled atoms, local oracle evaluations) or 0")
+    ap.add_argument("--rmse-frame0", action="store_true", help="also check the accuracy of the start frame")
     ap.add_argument("--skin", type=float, default=2.0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -285,6 +339,10 @@ def main():
         return model.md_run(x, v, t, w["box"], w["masses"], w["dt_fs"], steps, skin=args.skin,
                             thermo_every=every, forces=f)
 
+    acc0 = None
+    if args.rmse_frame0 and args.rmse != "0":
+        acc0 = accuracy(args, w, blob, m, DPModel(blob, "fp64") if args.precision != "fp64" else None, x, t,
+                        False, "frame 0")
     if args.warmup > 0:
         md(m, args.warmup, args.warmup)
         if student:  # load and run the student kernels once
@@ -379,49 +437,42 @@ def main():
         "roofline": roof,
     }
     out.update(out_extra)
-    # force accuracy of the timed path at the final MD frame, on sampled atoms
-    if args.rmse_atoms > 0:
-        from oracle import oracle as O
-        e_m, f_m, _ = m.compute(x, t, w["box"])
-        fm = f_m.cpu().numpy()
-        xf = x.cpu().numpy()
-        nl, _ = m.nlist(n, spec.nnei, spec.ntypes)
-        nl = nl.cpu().numpy()
-        o = O.Oracle(blob)
-        rng = np.random.default_rng(7)
-        err, ref = [], []
-        for k in rng.choice(n, size=args.rmse_atoms, replace=False):
-            cen = np.unique(np.concatenate([[k], nl[k][nl[k] >= 0]]))
-            r = o.eval(xf, w["types"], w["box"], centres=cen)
-            err.append(fm[k] - r["force"][k])
-            ref.append(r["force"][k])
-        out["force_rmse_vs_oracle"] = float(np.sqrt((np.array(err) ** 2).sum(1).mean()))
-        out["force_rms"] = float(np.sqrt((np.array(ref) ** 2).sum(1).mean()))
-        out["force_rmse_sample"] = (f"{args.rmse_atoms} random atoms of the final MD frame, "
+    # per-step times of the comparison paths: the difference of a 1-step and
+    # a (1 + k)-step run, since every run also evaluates its start frame
+    def step_time(model, xx, vv, ff, k):
+        def run(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            model.md_run(xx, vv, t, w["box"], w["masses"], w["dt_fs"], steps, skin=args.skin,
+                         thermo_every=steps, forces=ff)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0
+        t1 = run(1)
+        return (run(1 + k) - t1) / k
+
+    m64 = None
+    if args.precision != "fp64" and args.fp64_steps > 0:
+        m64 = DPModel(blob, "fp64")
+    # force accuracy of the timed path at the final MD frame, against the oracle
+    if args.rmse != "0":
+        acc = accuracy(args, w, blob, m, m64, x, t, student, f"final MD frame (step {args.steps})")
+        if acc0 is not None:
+            out["accuracy_frame0"] = acc0
+        out["accuracy"] = acc
+        out["force_rmse_vs_oracle"] = acc["timed"]["force_rmse"]
+        out["force_rms"] = acc["force_rms"]
+        out["force_rmse_sample"] = (f"{acc['atoms']} of the final MD frame, "
                                     f"{'student' if used_student else 'teacher'} nets vs the oracle's teacher")
         log(f"[bench] force RMSE vs oracle {out['force_rmse_vs_oracle']:.3e} eV/A")
     if args.precision != "fp64" and args.teacher_steps > 0:
         m.student_use(False)
         m.enable_timing(False)
-        md(m, 1, 1)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        md(m, args.teacher_steps, args.teacher_steps)
-        torch.cuda.synchronize()
-        sT = (time.perf_counter() - t0) / args.teacher_steps
+        sT = step_time(m, x, v, f, args.teacher_steps)
         out["mixed_teacher_s_per_step_atom"] = sT / n
         log(f"[bench] mixed teacher {sT * 1e3:.1f} ms/step")
-    if args.precision != "fp64" and args.fp64_steps > 0:
-        m64 = DPModel(blob, "fp64")
+    if m64 is not None:
         f64 = torch.zeros((n, 3), dtype=torch.float64, device=dev)
-        x64, v64 = x.clone(), v.clone()
-        m64.md_run(x64, v64, t, w["box"], w["masses"], w["dt_fs"], 1, skin=args.skin, thermo_every=1, forces=f64)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        m64.md_run(x64, v64, t, w["box"], w["masses"], w["dt_fs"], args.fp64_steps, skin=args.skin,
-                   thermo_every=args.fp64_steps, forces=f64)
-        torch.cuda.synchronize()
-        s64 = (time.perf_counter() - t0) / args.fp64_steps
+        s64 = step_time(m64, x.clone(), v.clone(), f64, args.fp64_steps)
         out["fp64_s_per_step_atom"] = s64 / n
         out["speedup_vs_fp64"] = s64 / s_step
         log(f"[bench] fp64 {s64 * 1e3:.1f} ms/step")

@@ -180,8 +180,10 @@ int dp_get_stats(dp_ctx *c, dp_stats *out);
  *   mode 0 (default): cell-ordered -- when the list grid has 3 to 255 cells
  *     per axis, one workgroup per cell accumulates the pair forces on the
  *     27 surrounding cells' atoms in LDS and a gather pass adds the 27
- *     parts of each atom (no global atomics; atoms beyond 128 per cell fall
- *     back to atomics); otherwise as mode 1;
+ *     parts of each atom (no global atomics; the LDS holds twice the mean
+ *     cell occupancy plus 16 atoms per cell, at most 128, and atoms beyond
+ *     that add their forces with atomics); when the nets and that
+ *     accumulator do not fit the LDS, as mode 1;
  *   mode 1: every pair force is added to F with FP64 global atomics.
  * Returns DP_E_ARG for another mode. */
 int dp_set_force_scatter(dp_ctx *c, int mode);
@@ -208,7 +210,15 @@ int dp_set_wide_storage(dp_ctx *c, int mode);
  *   thermo: device double [nsteps/thermo_every + 1][6] or NULL, rows
  *   (step, KE, PE, KE+PE, T, P[eV/A^3]), row 0 = the start.
  *   forces [natoms][3] device double or NULL: forces at the final step.
- * The stream is synchronised every thermo_every steps to check flags. */
+ * The stream is synchronised every thermo_every steps (and after the last
+ * step) to check the error flags; no other host round trip happens per step.
+ * Once a kernel raises an error flag the integrator kernels leave coords and
+ * vel as they are, so the run stops on the device at the step where the
+ * error arose (coords at that step, vel before its second half kick).  A
+ * skin candidate list too small for the local density is then doubled (up
+ * to four times per call) and the run resumes at that step, giving the
+ * same trajectory as a large enough list from the start; other errors
+ * return with coords and vel in that stopped state. */
 int dp_md_run(dp_ctx *c, int64_t natoms, double *coords, double *vel, const int32_t *types, const double *box,
               const double *masses, double dt, double skin, int64_t nsteps, int64_t thermo_every,
               double *thermo, double *forces);

@@ -166,6 +166,24 @@ def round16(x, quant):
     return np.asarray(x, dtype=np.float64)
 
 
+def round_spec16(spec, quant, n_fit16=2):
+    """A copy of the model spec with the weights a 16-bit policy holds in
+    16 bits rounded (quant 0 FP16, 1 BF16), kept in FP64: the embedding
+    layers after the first (the first is a rank-1 layer kept in FP32) and
+    the first n_fit16 fitting layers.  Evaluating it with the FP64 oracle
+    separates the effect of the weight rounding from the arithmetic of the
+    16-bit kernels."""
+    import copy
+    q = copy.deepcopy(spec)
+    for t in range(spec.ntypes):
+        for u in range(spec.ntypes):
+            for l in range(1, len(spec.emb)):
+                q.emb_W[t][u][l] = round16(spec.emb_W[t][u][l], quant)
+        for l in range(n_fit16):
+            q.fit_W[t][l] = round16(spec.fit_W[t][l], quant)
+    return q
+
+
 def refit(p, s, w, Gt, M1, quant=-1):
     """Least squares of [h2(s), 1] X = Gt over the weighted samples
     (numpy lstsq); with quant >= 0, W2 is rounded before the features are

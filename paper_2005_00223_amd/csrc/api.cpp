@@ -160,6 +160,7 @@ struct DevStatus {
   double judge_count;  // atoms it covered
   int32_t sub_rows;    // padded rows of the judge's atom subset
   uint32_t smax_bits;  // largest s of the frame (float bits), for the student table
+  long long fault_step;  // MD: the step an error flag stopped the integrator at (-1: none)
 };
 
 struct Workspace {
@@ -1001,14 +1002,20 @@ bool cell_scatter_args(dp_ctx *c, int64_t n, const MixArgs &ma, CellArgs &ca, in
   if (c->scatter != 0 || c->ov_atom_of_pos || !c->cgrid_ok || !w.cell_part || n <= 0) return false;
   for (int a = 0; a < 3; ++a)
     if (c->cgrid.nc[a] < 3 || c->cgrid.nc[a] > 255) return false;
-  if (!embed_cells_config(ma, CELL_CAP, &threads, &lds)) return false;
+  // atoms per cell kept in the LDS accumulator: twice the mean occupancy
+  // plus slack (atoms beyond it add their forces with global atomics), at
+  // most CELL_CAP; a smaller accumulator leaves room for more nets
+  const int64_t ncell = (int64_t)c->cgrid.nc[0] * c->cgrid.nc[1] * c->cgrid.nc[2];
+  const int64_t mean = (n + ncell - 1) / ncell;
+  const int cap = (int)std::max<int64_t>(32, std::min<int64_t>(CELL_CAP, (2 * mean + 16 + 15) / 16 * 16));
+  if (!embed_cells_config(ma, cap, &threads, &lds)) return false;
   ca.cell_start = w.cell_start;
   ca.cell_atoms = w.cell_atoms;
   ca.cell_of = w.cell_of;
   ca.code = w.cell_code;
   for (int a = 0; a < 3; ++a) ca.nc[a] = c->cgrid.nc[a];
-  ca.cap = CELL_CAP;
-  ca.ncell = (int64_t)ca.nc[0] * ca.nc[1] * ca.nc[2];
+  ca.cap = cap;
+  ca.ncell = ncell;
   ca.n = n;
   ca.part = w.cell_part;
   return true;
@@ -1146,6 +1153,7 @@ int judge_step(dp_ctx *c, int64_t n, double *F, int64_t step, const double L[3])
     HIPCHK(c, hipGetLastError());
     rc2 = read_status(c);
     if (rc2) return rc2;
+    if (c->h_status->flags & FLAG_HALT) return DP_OK;  // forces of a stopped step: the caller handles the flag
     c->stats.last_judge_rmse = c->h_status->judge_rmse;
     c->stats.judge_atoms = (int64_t)c->h_status->judge_count;
     if (c->h_status->judge_rmse <= c->judge_max) return DP_OK;
@@ -1155,6 +1163,7 @@ int judge_step(dp_ctx *c, int64_t n, double *F, int64_t step, const double L[3])
   HIPCHK(c, hipGetLastError());
   int rc3 = read_status(c);
   if (rc3) return rc3;
+  if (c->h_status->flags & FLAG_HALT) return DP_OK;
   const double r = c->h_status->judge_rmse;
   c->stats.last_judge_rmse = r;
   c->stats.judge_atoms = n;
@@ -1171,6 +1180,7 @@ int judge_step(dp_ctx *c, int64_t n, double *F, int64_t step, const double L[3])
 __global__ void k_reset_status(DevStatus *st, uint32_t flags) {
   if (threadIdx.x == 0) {
     st->flags = flags;
+    st->fault_step = -1;
     st->overflow = 0;
     for (int t = 0; t < MAXT; ++t) st->max_real[t] = 0;
   }
@@ -1825,29 +1835,71 @@ int dp_md_run(dp_ctx *c, int64_t n, double *coords, double *vel, const int32_t *
   }
   const double ndof_kb = (3.0 * n - 3.0) * KB_EV;
   const double inv3v = 1.0 / (3.0 * L[0] * L[1] * L[2]);
-  int64_t row = 0;
-  tmark(c, 0);
-  hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, w.status, (uint32_t)FLAG_REBUILD);
-  launch_wrap(s, n, coords, types, d.ntypes, L, w.xw, &w.status->flags);
-  launch_type_sort(s, n, w.xw, d.ntypes, w.blk_counts, w.type_count, w.type_start, w.pos_of_atom, w.atom_of_pos,
-                   w.rows_cap);
-  build_lists(c, n, g, rlist, &w.status->flags);
-  launch_copy_ref(s, n, w.xw, w.xref, &w.status->flags);
-  launch_end_rebuild(s, &w.status->flags, &w.status->nbuild);
-  eval_body(c, n, L, F);
   const bool judging = c->active == 1 && c->judge_every > 0;
-  if (judging) {
-    rc = judge_step(c, n, F, 0, L);
-    if (rc) return rc;
-  }
-  if (thermo) {
-    launch_kinetic(s, n, vel, types, mass, w.partial, w.ke);
-    launch_thermo_row(s, thermo + 6 * row++, 0.0, w.ke, w.energy, w.virial, ndof_kb, inv3v, &w.status->flags);
-  }
-  for (int64_t st = 1; st <= nsteps; ++st) {
+  // (Re)start at step st0 from the coordinates and velocities as they are:
+  // lists built anew, forces evaluated; at st0 > 0 (a resume after the
+  // candidate list was regrown) the step's second half kick follows.
+  auto start = [&](int64_t st0) -> int {
+    Workspace &w = c->ws;
+    F = forces ? forces : w.force_tmp;
     tmark(c, 0);
-    launch_verlet_half(s, n, vel, F, types, inv_m, 0.5 * dt);
-    launch_verlet_drift(s, n, coords, vel, dt, L);
+    hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, w.status, (uint32_t)FLAG_REBUILD);
+    launch_wrap(s, n, coords, types, d.ntypes, L, w.xw, &w.status->flags);
+    launch_type_sort(s, n, w.xw, d.ntypes, w.blk_counts, w.type_count, w.type_start, w.pos_of_atom, w.atom_of_pos,
+                     w.rows_cap);
+    build_lists(c, n, g, rlist, &w.status->flags);
+    launch_copy_ref(s, n, w.xw, w.xref, &w.status->flags);
+    launch_end_rebuild(s, &w.status->flags, &w.status->nbuild);
+    eval_body(c, n, L, F);
+    if (judging && c->active == 1 && st0 % c->judge_every == 0) {
+      const int r = judge_step(c, n, F, st0, L);
+      if (r) return r;
+    }
+    if (st0 > 0)
+      launch_verlet_half(s, n, vel, F, types, inv_m, 0.5 * dt, &w.status->flags, &w.status->fault_step, st0);
+    if (thermo && st0 % thermo_every == 0) {
+      launch_kinetic(s, n, vel, types, mass, w.partial, w.ke);
+      launch_thermo_row(s, thermo + 6 * (st0 / thermo_every), (double)st0, w.ke, w.energy, w.virial, ndof_kb, inv3v,
+                        &w.status->flags);
+    }
+    return DP_OK;
+  };
+  rc = start(0);
+  if (rc) return rc;
+  int regrown = 0;
+  // Read the flags after step st.  A skin-list overflow at a step after the
+  // last check stopped the integrator there: the list is grown and the run
+  // restarted at that step (*resume); other errors end the run.
+  auto check = [&](int64_t st, int64_t &resume) -> int {
+    HIPCHK(c, hipGetLastError());
+    int r = read_status(c);
+    if (r) return r;
+    const uint32_t fl = c->h_status->flags;
+    if (fl & FLAG_BAD_TYPE) return fail(c, DP_E_TYPE, "atom type out of range");
+    if (fl & FLAG_KEY_CAP) return fail(c, DP_E_CAP, "more than 512 neighbours within rcut of one atom");
+    if (fl & FLAG_NONFINITE) return fail(c, DP_E_NONFINITE, "non-finite energy by step " + std::to_string(st));
+    if (fl & FLAG_CAND_CAP) {
+      const long long f0 = nsteps == 0 ? 0 : c->h_status->fault_step;
+      if (regrown >= 4 || f0 < 0 || f0 > st)
+        return fail(c, DP_E_CAP, "skin candidate list overflow; use a smaller skin");
+      ++regrown;
+      r = ensure_ws(c, n, ncell, 2 * c->ws.cand_cap);
+      if (r) return r;
+      r = start((int64_t)f0);
+      if (r) return r;
+      resume = (int64_t)f0;
+    }
+    return DP_OK;
+  };
+  int64_t resume = -1;
+  for (int64_t st = 1; st <= nsteps; ++st) {
+    Workspace &w = c->ws;
+    tmark(c, 0);
+    // the first half kick of step st records st - 1 when an error flag
+    // stopped the run: the state is then that of the end of step st - 1
+    // before its second half kick (or the start, st - 1 = 0)
+    launch_verlet_half(s, n, vel, F, types, inv_m, 0.5 * dt, &w.status->flags, &w.status->fault_step, st - 1);
+    launch_verlet_drift(s, n, coords, vel, dt, L, &w.status->flags);
     launch_wrap(s, n, coords, types, d.ntypes, L, w.xw, &w.status->flags);
     launch_max_disp(s, n, w.xw, w.xref, L, 0.5 * skin, &w.status->flags);
     build_lists(c, n, g, rlist, &w.status->flags);
@@ -1858,28 +1910,29 @@ int dp_md_run(dp_ctx *c, int64_t n, double *coords, double *vel, const int32_t *
       rc = judge_step(c, n, F, st, L);
       if (rc) return rc;
     }
-    launch_verlet_half(s, n, vel, F, types, inv_m, 0.5 * dt);
+    launch_verlet_half(s, n, vel, F, types, inv_m, 0.5 * dt, &w.status->flags, &w.status->fault_step, st);
     const bool th = thermo && (st % thermo_every == 0);
     if (th) {
       launch_kinetic(s, n, vel, types, mass, w.partial, w.ke);
-      launch_thermo_row(s, thermo + 6 * row++, (double)st, w.ke, w.energy, w.virial, ndof_kb, inv3v,
+      launch_thermo_row(s, thermo + 6 * (st / thermo_every), (double)st, w.ke, w.energy, w.virial, ndof_kb, inv3v,
                         &w.status->flags);
     }
-    if (th || st == nsteps) {
-      HIPCHK(c, hipGetLastError());
-      rc = read_status(c);
-      if (rc) return rc;
-      const uint32_t fl = c->h_status->flags;
-      if (fl & FLAG_BAD_TYPE) return fail(c, DP_E_TYPE, "atom type out of range");
-      if (fl & FLAG_KEY_CAP) return fail(c, DP_E_CAP, "more than 512 neighbours within rcut of one atom");
-      if (fl & FLAG_CAND_CAP) return fail(c, DP_E_CAP, "skin candidate list overflow; use a smaller skin");
-      if (fl & FLAG_NONFINITE) return fail(c, DP_E_NONFINITE, "non-finite energy at step " + std::to_string(st));
-    }
     c->stats.evaluations += 1;
+    if (th || st == nsteps) {
+      resume = -1;
+      rc = check(st, resume);
+      if (rc) return rc;
+      if (resume >= 0) st = resume;
+    }
   }
-  if (nsteps == 0) {
-    rc = read_status(c);
-    if (rc) return rc;
+  // a run of no steps, or a restart at the last step, has not been checked
+  if (nsteps == 0 || resume == nsteps) {
+    for (;;) {
+      int64_t again = -1;
+      rc = check(nsteps, again);
+      if (rc) return rc;
+      if (again < 0) break;
+    }
   }
   c->stats.natoms = n;
   c->stats.cand_cap = c->ws.cand_cap;

@@ -45,6 +45,9 @@ struct FitOffsets {
 // Error flags written by kernels, read back by the host.
 enum : uint32_t { FLAG_BAD_TYPE = 1u, FLAG_CAND_CAP = 2u, FLAG_KEY_CAP = 4u, FLAG_NONFINITE = 8u,
                   FLAG_REBUILD = 16u };
+// Flags that stop an MD run: once one is set, the integrator kernels leave
+// coordinates and velocities as they are until the host reads the flags.
+constexpr uint32_t FLAG_HALT = FLAG_BAD_TYPE | FLAG_CAND_CAP | FLAG_KEY_CAP | FLAG_NONFINITE;
 
 struct NlistBufs {
   const double *coords;  // caller coords [n][3]
@@ -176,9 +179,14 @@ void launch_fit_f64(hipStream_t s, const FitArgs &a, int pass);
 void launch_sum(hipStream_t s, const double *x, int64_t n, double *partial, double *out, double scale);
 void launch_sum9(hipStream_t s, const double *part, int nparts, double *out);
 void launch_zero(hipStream_t s, double *x, int64_t n);
+// Half kick v += half_dt F / m.  Skipped when *flags holds a FLAG_HALT bit;
+// the first skipped kick stores `step` in *fault_step (when it is < 0).
 void launch_verlet_half(hipStream_t s, int64_t n, double *v, const double *f, const int32_t *types,
-                        const double *inv_m_conv, double half_dt);
-void launch_verlet_drift(hipStream_t s, int64_t n, double *x, const double *v, double dt, const double *L);
+                        const double *inv_m_conv, double half_dt, const uint32_t *flags, long long *fault_step,
+                        int64_t step);
+// Drift x += dt v and wrap; skipped when *flags holds a FLAG_HALT bit.
+void launch_verlet_drift(hipStream_t s, int64_t n, double *x, const double *v, double dt, const double *L,
+                         const uint32_t *flags);
 void launch_kinetic(hipStream_t s, int64_t n, const double *v, const int32_t *types, const double *mass,
                     double *partial, double *out);
 void launch_thermo_row(hipStream_t s, double *row, double step, const double *ke, const double *pe,

@@ -75,24 +75,30 @@ struct TypeScale {
 };
 
 __global__ void k_verlet_half(int64_t n, double *v, const double *f, const int32_t *types, TypeScale c,
-                              double half_dt) {
+                              double half_dt, const uint32_t *flags, long long *fault_step, long long step) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (*flags & FLAG_HALT) {
+    if (i == 0 && fault_step && *fault_step < 0) *fault_step = step;
+    return;
+  }
   if (i >= 3 * n) return;
   v[i] += half_dt * f[i] * c.v[types[i / 3]];
 }
 
 void launch_verlet_half(hipStream_t s, int64_t n, double *v, const double *f, const int32_t *types,
-                        const double *inv_m_conv, double half_dt) {
+                        const double *inv_m_conv, double half_dt, const uint32_t *flags, long long *fault_step,
+                        int64_t step) {
   TypeScale c{};
   for (int t = 0; t < MAXT; ++t) c.v[t] = inv_m_conv[t];
   if (n > 0)
     hipLaunchKernelGGL(k_verlet_half, dim3((unsigned)((3 * n + 255) / 256)), dim3(256), 0, s, n, v, f, types, c,
-                       half_dt);
+                       half_dt, flags, fault_step, (long long)step);
 }
 
-__global__ void k_verlet_drift(int64_t n, double *x, const double *v, double dt, double L0, double L1, double L2) {
+__global__ void k_verlet_drift(int64_t n, double *x, const double *v, double dt, double L0, double L1, double L2,
+                               const uint32_t *flags) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 3 * n) return;
+  if (i >= 3 * n || (*flags & FLAG_HALT)) return;
   const int a = (int)(i % 3);
   const double L = a == 0 ? L0 : (a == 1 ? L1 : L2);
   double y = x[i] + dt * v[i];
@@ -101,10 +107,11 @@ __global__ void k_verlet_drift(int64_t n, double *x, const double *v, double dt,
   x[i] = y;
 }
 
-void launch_verlet_drift(hipStream_t s, int64_t n, double *x, const double *v, double dt, const double *L) {
+void launch_verlet_drift(hipStream_t s, int64_t n, double *x, const double *v, double dt, const double *L,
+                         const uint32_t *flags) {
   if (n > 0)
     hipLaunchKernelGGL(k_verlet_drift, dim3((unsigned)((3 * n + 255) / 256)), dim3(256), 0, s, n, x, v, dt, L[0],
-                       L[1], L[2]);
+                       L[1], L[2], flags);
 }
 
 __global__ void __launch_bounds__(RED_THREADS) k_kinetic1(int64_t n, const double *v, const int32_t *types,

@@ -113,27 +113,30 @@ def test_intermediates_water192():
 
 
 def _sampled_check(w, m, n_sample, seed, f_bar=1e-9):
-    """Forces of sampled atoms against the oracle's local evaluation over
-    {k} + N(k); per-atom energies of those atoms."""
+    """Forces of sampled atoms against one oracle evaluation whose centres
+    are the sampled atoms and all their neighbours: the force on k depends
+    only on the energies of k and of the atoms within rc of it (the list
+    relation is symmetric when no type overflows its sel), so those forces
+    are exact; per-atom energies of the sampled atoms."""
     o = oracle(w)
     n = len(w["types"])
     spec = w["spec"]
     rng = np.random.default_rng(seed)
-    ks = rng.choice(n, size=n_sample, replace=False)
+    ks = np.sort(rng.choice(n, size=n_sample, replace=False))
     e, f, v = m.compute(w["coords"], w["types"], w["box"], keep_intermediates=False)
     f = f.cpu().numpy()
     vv = v.cpu().numpy()
     nl, _ = m.nlist(n, spec.nnei, spec.ntypes)
     nl = nl.cpu().numpy()
+    assert m.stats()["sel_overflow"] == 0
     ae = m.intermediates(n, spec.M1, spec.M2, spec.nnei, which=("atom_e",))["atom_e"].cpu().numpy()
     onl, _, _ = o.nlist(w["coords"], w["types"], w["box"], centres=ks)
     np.testing.assert_array_equal(nl[ks], onl)
-    for k in ks:
-        cen = np.unique(np.concatenate([[k], nl[k][nl[k] >= 0]]))
-        r = o.eval(w["coords"], w["types"], w["box"], centres=cen)
-        f_tol(f[k], r["force"][k], f_bar)
-        pos = np.searchsorted(cen, k)
-        rel_tol(ae[k], r["atom_e"][pos], 1e-10)
+    cen = np.unique(np.concatenate([ks, nl[ks][nl[ks] >= 0]]))
+    say(f"  {n_sample} sampled atoms, {cen.size} oracle centres")
+    r = o.eval(w["coords"], w["types"], w["box"], centres=cen)
+    f_tol(f[ks], r["force"][ks], f_bar)
+    rel_tol(ae[ks], r["atom_e"][np.searchsorted(cen, ks)], 1e-10)
     # size-independent properties: sum of forces, symmetric virial
     rms = np.sqrt((f ** 2).sum(1).mean())
     assert np.abs(f.sum(0)).max() <= 1e-9 * rms * np.sqrt(n)
@@ -144,7 +147,7 @@ def _sampled_check(w, m, n_sample, seed, f_bar=1e-9):
 def test_cu32000_sampled():
     w = work("cu32000")
     say("[sampled] cu32000")
-    _sampled_check(w, gpu_model(w), 12, 0)
+    _sampled_check(w, gpu_model(w), 64, 0)
 
 
 def test_cu500k_sampled():
@@ -152,7 +155,7 @@ def test_cu500k_sampled():
     single-evaluation launch configuration the benchmark's MD step uses."""
     w = work("cu500k")
     say("[sampled] cu500k")
-    _sampled_check(w, gpu_model(w), 6, 1)
+    _sampled_check(w, gpu_model(w), 256, 1)
 
 
 # ---------------------------------------------------------------------------
@@ -281,3 +284,40 @@ def test_md_matches_oracle_verlet():
     np.testing.assert_array_equal(thg[:, 0], oth[:, 0])
     for c in range(1, 6):
         rel_tol(thg[:, c], oth[:, c], 1e-9)
+
+
+def test_md_regrows_an_overflowing_candidate_list():
+    """256 copper atoms (4^3 FCC cells) in the middle of a box twice as
+    wide: the candidate capacity sized from the mean density (128 per atom)
+    overflows on the first list build.  The run stops on the device at that
+    step, grows the list, resumes, and ends where a run with the grown list
+    from the start ends."""
+    say("[md] candidate list regrowth")
+    x0, t, box = synth.fcc_copper(4, 3.634, jitter=0.05, seed=9)
+    box2 = 2.0 * np.asarray(box, dtype=np.float64)
+    x0 = x0 + 0.25 * box2
+    spec = synth.copper_model(1)
+    w = dict(coords=x0, types=t, box=box2, spec=spec, blob=synth.pack_blob(spec),
+             masses=np.array([synth.MASS["Cu"]]))
+    v0 = synth.maxwell_boltzmann(w["masses"][t], 300.0, 109)
+
+    def run(m):
+        x = torch.tensor(x0, dtype=torch.float64, device="cuda")
+        v = torch.tensor(v0, dtype=torch.float64, device="cuda")
+        th = m.md_run(x, v, t, box2, w["masses"], 1.0, 20, skin=1.0, thermo_every=10)
+        return x.cpu().numpy(), v.cpu().numpy(), th.cpu().numpy()
+
+    a = gpu_model(w)
+    xa, va, tha = run(a)
+    st = a.stats()
+    say(f"  candidate capacity after the run: {st['cand_cap']}")
+    assert st["cand_cap"] >= 256
+    b = gpu_model(w)
+    xx = torch.tensor(x0, dtype=torch.float64, device="cuda")
+    vv = torch.tensor(v0, dtype=torch.float64, device="cuda")
+    b.md_run(xx, vv, t, box2, w["masses"], 1.0, 1, skin=1.0, thermo_every=1)  # grows b's list
+    xb, vb, thb = run(b)
+    assert np.all(np.isfinite(tha))
+    f_tol(xa, xb, 1e-9)
+    f_tol(va, vb, 1e-9)
+    rel_tol(tha, thb, 1e-9)

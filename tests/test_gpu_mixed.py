@@ -1,10 +1,11 @@
 """Mixed-precision HIP path (16-bit matrix-core products, FP32 tanh and
 contractions, FP64 geometry and sums) against the FP64 oracle.
 
-Bar: force RMSE <= 1e-3 eV/A for FP16 on every workload (RMS|F| is about
-1 eV/A for these models).  BF16 keeps 8-bit weights, which a CPU rounding
-emulation puts at about 3e-4 eV/A (copper) and 1.4e-3 eV/A (water), so its
-water bar is 3e-3.  The neighbour list is the FP64 one, bit for bit."""
+Bars: the kernels' arithmetic against the oracle on the weights the kernels
+hold (16-bit weights rounded beforehand), then force RMSE <= 1e-3 eV/A
+against the model itself for FP16 on every workload (RMS|F| is about 1 eV/A
+for these models); BF16's bar is the CPU-emulated weight rounding error plus
+the kernel bar.  The neighbour list is the FP64 one, bit for bit."""
 import sys
 
 import numpy as np
@@ -37,59 +38,109 @@ def _oracle(blob):
     return O.Oracle(blob)
 
 
-BARS = {("water192", "fp16"): 1e-3, ("cu_cells5", "fp16"): 1e-3, ("water192", "bf16"): 3e-3,
-        ("cu_cells5", "bf16"): 1e-3}
+# 500 and 32,000 copper atoms (the second is the mixed-precision
+# configuration of the copper model at full size), 192 water atoms
+CASES = [("cu_cells5", "bf16"), ("cu_cells5", "fp16"), ("cu32000", "bf16"), ("cu32000", "fp16"),
+         ("water192", "bf16"), ("water192", "fp16")]
+
+# Bars of the kernels' own arithmetic, against the oracle on the same model
+# with the 16-bit weights rounded beforehand (oracle.student.round_spec16):
+# what is left is the hi + lo split of the activations entering the 16-bit
+# products, FP32 accumulation inside the matrix cores and FP32 tanh.  BF16
+# halves keep 8 + 8 bits (unit 2^-17); the FP16 split nominally keeps 22
+# bits, but its low half is subnormal, and keeps fewer bits, wherever
+# |x| < 2^-3 (most tanh outputs and every backward activation), and the
+# matrix cores' internal sums are not IEEE-rounded, so FP16 is held to 16
+# bits.  Bars: FP16 2^-14 (4 units of 2^-16), BF16 2^-12 (32 units of
+# 2^-17), for forces relative to RMS|F|, the virial relative to its largest
+# element and the energy relative to itself.  Measured (cu 500 / cu 32,000 /
+# water 192): FP16 forces 7.7e-6 / 7.9e-6 / 5.6e-6, energy 1.5e-5 / 1.5e-5 /
+# 2.6e-6; BF16 forces 6.5e-5 / 6.2e-5 / 8.7e-6, energy 1.2e-6 / 1.3e-6 /
+# 2.9e-7.
+KBAR = {"fp16": 2.0 ** -14, "bf16": 2.0 ** -12}
+EBAR = KBAR
 
 
-@pytest.mark.parametrize("name,prec", sorted(BARS))
+@pytest.mark.parametrize("name,prec", CASES)
 def test_force_rmse_full(name, prec):
+    """Every atom against the oracle: first on the weights the kernels hold
+    (the kernel arithmetic alone, bars above), then on the model itself.
+    North star: force RMSE <= 1e-3 eV/A.  FP16 meets it on every workload.
+    BF16's 8-bit weights alone (the rounded model in the oracle, a CPU
+    emulation with no GPU code) cost more on water; its bar there is that
+    emulated weight error plus the kernel bar (triangle inequality), and the
+    test states the RMSE it reaches."""
+    from oracle import student as S
     w = synth.workload(name)
     blob = synth.pack_blob(w["spec"])
     n = len(w["types"])
     say(f"[mixed] {name} {prec}")
     m = _model(blob, prec)
     e, f, v = m.compute(w["coords"], w["types"], w["box"])
+    e, f, v = e.item(), f.cpu().numpy(), v.cpu().numpy()
     r = _oracle(blob).eval(w["coords"], w["types"], w["box"])
-    f = f.cpu().numpy()
-    rmse = np.sqrt(((f - r["force"]) ** 2).sum(1).mean())
+    q = _oracle(synth.pack_blob(S.round_spec16(w["spec"], 0 if prec == "fp16" else 1))).eval(
+        w["coords"], w["types"], w["box"])
     rms = np.sqrt((r["force"] ** 2).sum(1).mean())
-    say(f"  force RMSE {rmse:.3e} eV/A (RMS|F| {rms:.3f}), energy error per atom "
-        f"{abs(e.item() - r['energy']) / n:.3e} eV")
-    assert rmse <= BARS[(name, prec)]
-    # 16-bit weights shift the energy: about 1e-4 relative in FP16, 2e-3 in BF16
-    assert abs(e.item() - r["energy"]) <= (1e-3 if prec == "fp16" else 5e-3) * abs(r["energy"])
-    vv = v.cpu().numpy()
-    assert np.abs(vv - r["virial"]).max() <= (1e-3 if prec == "fp16" else 5e-3) * np.abs(r["virial"]).max()
+
+    def frmse(a, b):
+        return float(np.sqrt(((a - b) ** 2).sum(1).mean()))
+
+    kf = frmse(f, q["force"]) / rms
+    ke = abs(e - q["energy"]) / abs(q["energy"])
+    kv = np.abs(v - q["virial"]).max() / np.abs(q["virial"]).max()
+    emu = frmse(q["force"], r["force"])
+    rmse = frmse(f, r["force"])
+    say(f"  kernel arithmetic (vs rounded-weight oracle): force {kf:.2e} x RMS|F|, energy {ke:.2e} rel, "
+        f"virial {kv:.2e} rel")
+    say(f"  vs the model: force RMSE {rmse:.3e} eV/A (RMS|F| {rms:.3f}; weight rounding alone {emu:.3e}), "
+        f"energy error per atom {abs(e - r['energy']) / n:.3e} eV")
+    assert kf <= KBAR[prec] and ke <= EBAR[prec] and kv <= KBAR[prec]
+    if prec == "fp16":
+        assert rmse <= 1e-3
+    else:
+        assert rmse <= emu + KBAR[prec] * rms
     # the neighbour list does not depend on the precision policy
     nl, _ = m.nlist(n, w["spec"].nnei, w["spec"].ntypes)
     onl, _, _ = _oracle(blob).nlist(w["coords"], w["types"], w["box"])
     np.testing.assert_array_equal(nl.cpu().numpy(), onl)
 
 
-@pytest.mark.parametrize("name", ["cu32000", "cu500k"])
-def test_force_rmse_sampled_fp16(name):
-    """Full-size copper: forces of sampled atoms against the oracle's local
-    evaluation over {k} and its neighbours."""
+def _sampled_rmse(w, blob, f, nl, n_sample, seed):
+    """Force RMSE of n_sample random atoms against one oracle evaluation
+    whose centres are those atoms and all their neighbours (which makes
+    their oracle forces exact); returns (rmse, RMS|F| of the sample)."""
+    n = len(w["types"])
+    rng = np.random.default_rng(seed)
+    ks = np.sort(rng.choice(n, size=n_sample, replace=False))
+    cen = np.unique(np.concatenate([ks, nl[ks][nl[ks] >= 0]]))
+    r = _oracle(blob).eval(w["coords"], w["types"], w["box"], centres=cen)
+    d = f[ks] - r["force"][ks]
+    return float(np.sqrt((d ** 2).sum(1).mean())), float(np.sqrt((r["force"][ks] ** 2).sum(1).mean()))
+
+
+@pytest.mark.parametrize("name,student", [("cu32000", False), ("cu500k", False), ("cu500k", True)])
+def test_force_rmse_sampled_fp16(name, student):
+    """Full-size copper: forces of 256 sampled atoms against the oracle (the
+    teacher nets), with the teacher's 16-bit kernels or with a student
+    trained in place (the benchmark's path: table, cell-ordered scatter)."""
     w = synth.workload(name)
     spec = w["spec"]
     blob = synth.pack_blob(spec)
     n = len(w["types"])
-    say(f"[mixed sampled] {name} fp16")
+    say(f"[mixed sampled] {name} fp16 student={student}")
     m = _model(blob, "fp16")
     e, f, v = m.compute(w["coords"], w["types"], w["box"])
+    if student:
+        m.student_train()
+        m.student_use(True)
+        e, f, v = m.compute(w["coords"], w["types"], w["box"])
+        st = m.stats()
+        assert st["table_evals"] > 0 and st["cell_scatter"] > 0
     f = f.cpu().numpy()
     nl, _ = m.nlist(n, spec.nnei, spec.ntypes)
-    nl = nl.cpu().numpy()
-    o = _oracle(blob)
-    rng = np.random.default_rng(2)
-    ks = rng.choice(n, size=12, replace=False)
-    err = []
-    for k in ks:
-        cen = np.unique(np.concatenate([[k], nl[k][nl[k] >= 0]]))
-        r = o.eval(w["coords"], w["types"], w["box"], centres=cen)
-        err.append(f[k] - r["force"][k])
-    rmse = np.sqrt((np.array(err) ** 2).sum(1).mean())
-    say(f"  sampled force RMSE {rmse:.3e} eV/A over {len(ks)} atoms")
+    rmse, rms = _sampled_rmse(w, blob, f, nl.cpu().numpy(), 256, 2)
+    say(f"  sampled force RMSE {rmse:.3e} eV/A over 256 atoms (RMS|F| {rms:.3f})")
     assert rmse <= 1e-3
     assert np.isfinite(e.item())
 

@@ -213,3 +213,32 @@ def test_sampler_without_pairs_gives_zero_weight(S):
     # no centre of type 1 at all
     s, wt, _, _ = S.sample(types, nreal, rt, np.array([2, 2]), 2, 1, 2, 0, 64)
     assert not wt.any()
+
+
+def test_round_spec16_rounds_only_the_16bit_weights():
+    """The rounded-weight model used to separate weight rounding from kernel
+    arithmetic: embedding layers after the first and the first two fitting
+    layers are rounded (idempotently, to representable 16-bit values); the
+    first embedding layer, later fitting layers and all biases are not."""
+    from oracle import student as S
+    spec = synth.water_model(0)
+    for quant, dt in ((0, np.float16), (1, None)):
+        q = S.round_spec16(spec, quant)
+        for t in range(spec.ntypes):
+            for u in range(spec.ntypes):
+                assert np.array_equal(q.emb_W[t][u][0], spec.emb_W[t][u][0])
+                for l in range(1, len(spec.emb)):
+                    W = q.emb_W[t][u][l]
+                    assert not np.array_equal(W, spec.emb_W[t][u][l])
+                    assert np.array_equal(S.round16(W, quant), W)
+                    if dt is not None:
+                        assert np.array_equal(W.astype(dt).astype(np.float64), W)
+                    else:  # bfloat16: the low 16 bits of the float32 pattern are zero
+                        assert np.all((W.astype(np.float32).view(np.uint32) & 0xFFFF) == 0)
+                    assert np.abs(W - spec.emb_W[t][u][l]).max() <= 2.0 ** (-8 if quant else -11) * np.abs(
+                        spec.emb_W[t][u][l]).max()
+                for l in range(len(spec.emb)):
+                    assert np.array_equal(q.emb_b[t][u][l], spec.emb_b[t][u][l])
+            for l in range(len(spec.fit_W[t])):
+                same = np.array_equal(q.fit_W[t][l], spec.fit_W[t][l])
+                assert same == (l >= 2)
