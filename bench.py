@@ -171,7 +171,7 @@ def accuracy(args, w, blob, m, m64, x, t, student, frame):
         m.student_use(True)
     if m64 is not None:
         paths["fp64"] = m64.compute(x, t, w["box"])
-    paths = {k: (e.item(), f.cpu().numpy(), v.cpu().numpy()) for k, (e, f, v) in paths.items()}
+    paths = {k: (e.item(), f.cpu().numpy(), v.cpu().numpy().reshape(9)) for k, (e, f, v) in paths.items()}
     o = O.Oracle(blob)
     t0 = time.perf_counter()
     if args.rmse == "full":

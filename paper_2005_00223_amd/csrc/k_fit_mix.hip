@@ -218,6 +218,8 @@ __global__ void __launch_bounds__(64 * FIT_WAVES, 1) k_fit_fwd(FitMixArgs a) {
   const int M1 = a.d.M1, NL = a.d.n_fit, KS0 = M1 / 2;
   const int64_t tile0 = r0 / 16 + (int64_t)wv * NT;
   const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  // padding rows (ia < 0) read atom 0's T, scaled by 0 in Tb: every load is
+  // unconditional, so none of them waits behind a branch (M1 >= 16)
   int ia[NT];
   const float4 *Ti[NT];
   float4 Tb[NT][8];
@@ -225,8 +227,12 @@ __global__ void __launch_bounds__(64 * FIT_WAVES, 1) k_fit_fwd(FitMixArgs a) {
   for (int nt = 0; nt < NT; ++nt) {
     ia[nt] = a.atom_of_pos[(tile0 + nt) * 16 + n];
     Ti[nt] = (const float4 *)(a.T32 + (int64_t)(ia[nt] < 0 ? 0 : ia[nt]) * M1 * 4);
+    const float live = ia[nt] >= 0 ? 1.f : 0.f;
 #pragma unroll
-    for (int v = 0; v < 8; ++v) Tb[nt][v] = (ia[nt] >= 0 && 8 * (g & 1) + v < M1) ? Ti[nt][8 * (g & 1) + v] : z4;
+    for (int v = 0; v < 8; ++v) {
+      const float4 q = Ti[nt][8 * (g & 1) + v];
+      Tb[nt][v] = make_float4(q.x * live, q.y * live, q.z * live, q.w * live);
+    }
   }
   const unsigned char *W = a.w;
   const int n0c = (KS0 + F0_CK - 1) / F0_CK, nchunks = n0c + (NL - 1) * FH_NC;
@@ -245,7 +251,7 @@ __global__ void __launch_bounds__(64 * FIT_WAVES, 1) k_fit_fwd(FitMixArgs a) {
   // layer 0: K = M1*16 features of D = T T<^T, formed from T as the B operand
   float4 Ta[NT];
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) Ta[nt] = ia[nt] >= 0 ? Ti[nt][g >> 1] : z4;
+  for (int nt = 0; nt < NT; ++nt) Ta[nt] = Ti[nt][g >> 1];
   dma_wait_all();
   int gc = 0;
   for (int c = 0; c < n0c; ++c, ++gc) {
@@ -267,7 +273,7 @@ __global__ void __launch_bounds__(64 * FIT_WAVES, 1) k_fit_fwd(FitMixArgs a) {
           }
           B[nt] = fsplit<P>(x, y);
           // next k-step's row a of T, in flight during this one's products
-          if (kk + 1 < KS0) Ta[nt] = ia[nt] >= 0 ? Ti[nt][2 * (kk + 1) + (g >> 1)] : z4;
+          if (kk + 1 < KS0) Ta[nt] = Ti[nt][2 * (kk + 1) + (g >> 1)];
         }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -454,8 +460,8 @@ __global__ void __launch_bounds__(64 * FIT_WAVES, 1) k_fit_bwd(FitMixArgs a) {
     Ti[nt] = (const float4 *)(a.T32 + (int64_t)(ia[nt] < 0 ? 0 : ia[nt]) * M1 * 4);
     dTi[nt] = (float4 *)(a.dT32 + (int64_t)(ia[nt] < 0 ? 0 : ia[nt]) * M1 * 4);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) Tq[nt][r] = (ia[nt] >= 0 && 4 * g + r < M1) ? Ti[nt][4 * g + r] : z4;
-    Ta[nt] = ia[nt] >= 0 ? Ti[nt][0] : z4;
+    for (int r = 0; r < 4; ++r) Tq[nt][r] = Ti[nt][4 * g + r];  // padding rows: results never stored
+    Ta[nt] = Ti[nt][0];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -485,7 +491,7 @@ __global__ void __launch_bounds__(64 * FIT_WAVES, 1) k_fit_bwd(FitMixArgs a) {
       for (int nt = 0; nt < NT; ++nt) {
         const v4f c = cc[nt];
         const float4 ta = Ta[nt];
-        if (aa + 1 < M1) Ta[nt] = ia[nt] >= 0 ? Ti[nt][aa + 1] : z4;
+        if (aa + 1 < M1) Ta[nt] = Ti[nt][aa + 1];
         float4 pc;
         pc.x = c[0] * Tq[nt][0].x + c[1] * Tq[nt][1].x + c[2] * Tq[nt][2].x + c[3] * Tq[nt][3].x;
         pc.y = c[0] * Tq[nt][0].y + c[1] * Tq[nt][1].y + c[2] * Tq[nt][2].y + c[3] * Tq[nt][3].y;
@@ -538,7 +544,7 @@ bool fit_mix_supported(const Dims &d, const char **why) {
     if (d.fw[l] != H) return *why = "mixed fitting net needs equal hidden widths", false;
   if (H != 16 * FIT_MT) return *why = "mixed fitting net is built for hidden width 240", false;
   if (d.M2 != 16) return *why = "mixed fitting net needs M2 = 16", false;
-  if (d.M1 % 2 != 0 || d.M1 > 2048) return *why = "mixed fitting net needs an even M1 <= 2048", false;
+  if (d.M1 % 2 != 0 || d.M1 < 16 || d.M1 > 2048) return *why = "mixed fitting net needs an even M1 in 16..2048", false;
   if (d.n_fit < 1 || d.n_fit > MAXF) return *why = "mixed fitting net needs 1..4 hidden layers", false;
   return true;
 }
