@@ -200,6 +200,49 @@ def accuracy(args, w, blob, m, m64, x, t, student, frame):
     return acc
 
 
+def rank_share(args, log_fn):
+    """One GPU's share of the spatial decomposition (Section V-D): brick
+    (0, 0, 0) of a 2 x 2 x 2 cut of the workload with its ghost shell of
+    rc + skin, evaluated with its own atoms as centres and the ghosts as
+    neighbours only (dp_compute_local), timed beside the whole-box
+    evaluation on the same GPU."""
+    import torch
+    from paper_2005_00223_amd import synth
+    from paper_2005_00223_amd.model import DPModel
+    w = synth.workload(args.workload)
+    spec = w["spec"]
+    n = len(w["types"])
+    m = DPModel(synth.pack_blob(spec), args.precision)
+    shell = spec.rcut + args.skin
+    sh = synth.brick_share(w["coords"], w["types"], w["box"], (2, 2, 2), (0, 0, 0), shell)
+    xb = torch.tensor(sh["coords"], dtype=torch.float64, device=m.device)
+    tb = torch.tensor(sh["types"], dtype=torch.int32, device=m.device)
+    xa = torch.tensor(w["coords"], dtype=torch.float64, device=m.device)
+    ta = torch.tensor(w["types"], dtype=torch.int32, device=m.device)
+
+    def timed(fn, k=5):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    t_brick = timed(lambda: m.compute_local(xb, tb, sh["box"], sh["n_local"]))
+    t_box = timed(lambda: m.compute(xa, ta, w["box"]))
+    nl = sh["n_local"]
+    log_fn(f"[rank-share] brick: {nl} owned + {len(tb) - nl} ghosts, {t_brick * 1e3:.2f} ms; whole box {n} atoms "
+           f"{t_box * 1e3:.2f} ms")
+    return {"metric": "rank-share evaluation time (E+F+virial of one brick of a 2x2x2 decomposition)",
+            "value": t_brick * 1e3, "unit": "ms", "higher_is_better": False, "n_gpus": 1, "dtype": args.precision,
+            "data": "synthetic",
+            "config": {"workload": args.workload, "atoms": n, "owned": nl, "ghosts": int(len(tb) - nl),
+                       "shell_A": shell},
+            "whole_box_ms": t_box * 1e3, "brick_over_eighth_of_box": t_brick / (t_box / 8.0),
+            "ghost_exchange_bytes_each_way": int((len(tb) - nl) * 24)}
+
+
 def sweep(args, log_fn):
     """Embedding-size study (Sec. VII-D, Fig. 7): the copper sweep workload
     (15^3 FCC cells, 13,500 atoms, rc 8 A, sel 512) with embedding nets
@@ -295,6 +338,8 @@ def main():
     ap.add_argument("--sweep-sizes", default="64x128,128x256,256x512,512x1024,1024x2048")
     ap.add_argument("--wide-storage", default="mix16,split",
                     help="activation storage of the GEMM path in the sweep: mix16, split or both")
+    ap.add_argument("--rank-share", action="store_true",
+                    help="time one brick of a 2x2x2 spatial decomposition (owned atoms + rc+skin ghost shell)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (traffic-counter calibration)")
     args = ap.parse_args()
@@ -315,6 +360,9 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy probe: 3 copies of {args.copy_probe_mb} MiB")
         del src, dst
+    if args.rank_share:
+        print(json.dumps(rank_share(args, log)), flush=True)
+        return
     if args.sweep:
         if args.precision == "fp64":
             print("bench.py: the embedding-size study runs in fp16 or bf16", file=sys.stderr)

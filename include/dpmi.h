@@ -122,6 +122,33 @@ int dp_set_precision(dp_ctx *c, int precision);
 int dp_compute(dp_ctx *c, int64_t natoms, const double *coords, const int32_t *types, const double *box,
                double *energy, double *forces, double *virial);
 
+/* Rank-share evaluation: the share of one GPU in the spatial domain
+ * decomposition of Section V-D ("Reducing MPI communication bottlenecks").
+ *   atoms [0, n_local)       the centres this rank owns (a brick of space)
+ *   atoms [n_local, natoms)  its ghosts: the atoms (or periodic images)
+ *                            within rc of the brick, neighbours only
+ * coords, types and box as for dp_compute; no atom may see a periodic image
+ * of another within rc unless that image is meant (pad the brick and its
+ * shell with rc of vacuum).  Outputs (device, may be NULL):
+ *   energy  sum of E_i over the centres
+ *   forces  [natoms][3]: -dE_local/dr for every atom, ghosts included; a
+ *           ghost's force belongs to the rank owning that atom, which adds
+ *           it to its own (dp_scatter_add_forces)
+ *   virial  -sum over centres i and their neighbours j of g_ij (x) r_ij, so
+ *           the bricks' energies, virials and reverse-added forces sum to
+ *           those of the whole system.
+ * Every pair force is added with FP64 atomics (no cell-ordered scatter).
+ * dp_get_nlist, dp_get_intermediates and dp_energy_backward do not refer to
+ * this evaluation.  Wide embedding nets return DP_E_MODEL. */
+int dp_compute_local(dp_ctx *c, int64_t n_local, int64_t natoms, const double *coords, const int32_t *types,
+                     const double *box, double *energy, double *forces, double *virial);
+
+/* f_out[index[k]][a] += f_in[k][a] for k < n, a < 3 (device arrays; index
+ * int32, entries < 0 skipped; FP64 atomics on the context's stream): the
+ * reverse communication of a spatial decomposition, adding ghost forces to
+ * their owners' (Section V-D). */
+int dp_scatter_add_forces(dp_ctx *c, int64_t n, const int32_t *index, const double *f_in, double *f_out);
+
 /* dp_compute without any device allocation, for callers that cannot
  * allocate (code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc).  Arguments, results and errors as for dp_compute;

@@ -15,7 +15,8 @@ DP_OK, DP_E_ARG, DP_E_NOMODEL, DP_E_MODEL, DP_E_BOX, DP_E_TYPE, DP_E_OOM, DP_E_H
 DP_FP64, DP_MIX_FP16, DP_MIX_BF16 = 0, 2, 3
 PRECISION = {"fp64": DP_FP64, "fp16": DP_MIX_FP16, "bf16": DP_MIX_BF16}
 
-EXPORTS = ("dp_create", "dp_set_model", "dp_set_precision", "dp_compute", "dp_compute_noalloc", "dp_energy", "dp_energy_backward",
+EXPORTS = ("dp_create", "dp_set_model", "dp_set_precision", "dp_compute", "dp_compute_noalloc", "dp_compute_local",
+           "dp_scatter_add_forces", "dp_energy", "dp_energy_backward",
            "dp_get_nlist", "dp_keep_intermediates",
            "dp_get_intermediates", "dp_get_stats", "dp_set_force_scatter", "dp_set_wide_storage", "dp_student_table", "dp_md_run", "dp_enable_timing", "dp_get_timing",
            "dp_student_default_cfg", "dp_student_train", "dp_student_get_params", "dp_student_set_params",
@@ -64,6 +65,8 @@ def lib():
         "dp_set_precision": (I32, [P, I32]),
         "dp_compute": (I32, [P, I64, P, P, P, P, P, P]),
         "dp_compute_noalloc": (I32, [P, I64, P, P, P, P, P, P]),
+        "dp_compute_local": (I32, [P, I64, I64, P, P, P, P, P, P]),
+        "dp_scatter_add_forces": (I32, [P, I64, P, P, P]),
         "dp_energy": (I32, [P, I64, P, P, P, P]),
         "dp_energy_backward": (I32, [P, D, P, P]),
         "dp_get_nlist": (I32, [P, P, P]),
@@ -129,6 +132,16 @@ def dp_compute(ctx, natoms, coords_ptr, types_ptr, box9, e_ptr, f_ptr, v_ptr):
 def dp_compute_noalloc(ctx, natoms, coords_ptr, types_ptr, box9, e_ptr, f_ptr, v_ptr):
     box = (C.c_double * 9)(*[float(b) for b in box9])
     return check(ctx, lib().dp_compute_noalloc(ctx, int(natoms), coords_ptr, types_ptr, box, e_ptr, f_ptr, v_ptr))
+
+
+def dp_compute_local(ctx, n_local, natoms, coords_ptr, types_ptr, box9, e_ptr, f_ptr, v_ptr):
+    box = (C.c_double * 9)(*[float(b) for b in box9])
+    return check(ctx, lib().dp_compute_local(ctx, int(n_local), int(natoms), coords_ptr, types_ptr, box, e_ptr, f_ptr,
+                                             v_ptr))
+
+
+def dp_scatter_add_forces(ctx, n, index_ptr, f_in_ptr, f_out_ptr):
+    return check(ctx, lib().dp_scatter_add_forces(ctx, int(n), index_ptr, f_in_ptr, f_out_ptr))
 
 
 def dp_energy(ctx, natoms, coords_ptr, types_ptr, box9, e_ptr):

@@ -276,6 +276,9 @@ struct dp_ctx {
   // no-allocation entry point: the device address of this GPU's static
   // scratch array (NULL if its lookup failed, scratch_rc says why), the
   // workspace laid out on it, and whether an evaluation runs on it now
+  // local (brick + ghost shell) evaluation: atoms the forces cover, when
+  // more than the centres (0: the centres are all atoms)
+  int64_t n_force = 0;
   void *scratch = nullptr;
   hipError_t scratch_rc = hipSuccess;
   Workspace ws_na;
@@ -999,7 +1002,7 @@ void eval_forward(dp_ctx *c, int64_t n, const double L[3]) {
 // the kernel arguments.
 bool cell_scatter_args(dp_ctx *c, int64_t n, const MixArgs &ma, CellArgs &ca, int &threads, size_t &lds) {
   Workspace &w = c->ws;
-  if (c->scatter != 0 || c->ov_atom_of_pos || !c->cgrid_ok || !w.cell_part || n <= 0) return false;
+  if (c->scatter != 0 || c->ov_atom_of_pos || c->n_force > 0 || !c->cgrid_ok || !w.cell_part || n <= 0) return false;
   for (int a = 0; a < 3; ++a)
     if (c->cgrid.nc[a] < 3 || c->cgrid.nc[a] > 255) return false;
   // atoms per cell kept in the LDS accumulator: twice the mean occupancy
@@ -1030,7 +1033,7 @@ void eval_backward(dp_ctx *c, int64_t n, double *F, double *V) {
   if (c->precision == DP_FP64) {
     launch_fit_f64(s, fit_args(c, rows), 2);
     tmark(c, 5);
-    launch_zero(s, F, 3 * n);
+    launch_zero(s, F, 3 * (c->n_force > 0 ? c->n_force : n));
     const int grid = embed_bwd_grid(rows);
     tmark(c, 6);
     launch_embed_bwd_f64(s, embed_args(c, n, rows, F), grid);
@@ -1039,7 +1042,7 @@ void eval_backward(dp_ctx *c, int64_t n, double *F, double *V) {
   } else {
     launch_fit_mix(s, fitmix_args(c, rows), 2);
     tmark(c, 5);
-    launch_zero(s, F, 3 * n);
+    launch_zero(s, F, 3 * (c->n_force > 0 ? c->n_force : n));
     tmark(c, 6);
     if (c->en[c->active].wide) {
       if (c->wb.ok) {
@@ -1664,9 +1667,110 @@ __global__ void k_scale(double *x, int64_t n, double a) {
   if (i < n) x[i] *= a;
 }
 
+// out[idx[k]] += in[k] (three components), FP64 atomics
+__global__ void k_scatter_add3(int64_t n, const int32_t *idx, const double *in, double *out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 3 * n) return;
+  const int32_t j = idx[k / 3];
+  if (j >= 0) atomicAdd(out + 3 * (int64_t)j + k % 3, in[k]);
+}
+
+// Evaluation of the atoms [0, n_local) of a spatial brick as centres, with
+// the ghost atoms [n_local, n) as neighbours only (a rank's share of the
+// spatial decomposition of Section V-D).
+static int compute_local_impl(dp_ctx *c, int64_t n_local, int64_t n, const double *coords, const int32_t *types,
+                              const double *box, double *energy, double *forces, double *virial) {
+  if (!c) return DP_E_ARG;
+  if (!c->has_model) return fail(c, DP_E_NOMODEL, "evaluation before dp_set_model");
+  if (n < 0 || n >= (1 << 26) || n_local < 0 || n_local > n) return fail(c, DP_E_ARG, "need 0 <= n_local <= natoms < 2^26");
+  if (n > 0 && (!coords || !types)) return fail(c, DP_E_ARG, "NULL coords or types");
+  if (c->en[c->active].wide) return fail(c, DP_E_MODEL, "local evaluation does not cover wide embedding nets");
+  HIPCHK(c, hipSetDevice(c->device));
+  const Dims &d = c->dims;
+  double L[3];
+  const double rlist = d.rcut;
+  int rc = check_box(c, box, rlist, L);
+  if (rc) return rc;
+  hipStream_t s = c->stream;
+  CellGrid g = make_grid(L, rlist);
+  const int64_t ncell = (int64_t)g.nc[0] * g.nc[1] * g.nc[2];
+  int cap = cand_capacity(n, L, rlist);
+  c->fwd_ready = false;
+  c->last_n = 0;  // the lists below cover the centres only
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    rc = ensure_ws(c, std::max<int64_t>(n, 1), ncell, cap);
+    if (rc) return rc;
+    Workspace &w = c->ws;
+    double *F = forces ? forces : w.force_tmp;
+    tmark(c, 0);
+    hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, w.status, 0u);
+    if (n_local > 0) {
+      launch_wrap(s, n, coords, types, d.ntypes, L, w.xw, &w.status->flags);
+      // rows (the fitting net's and the embedding kernels') for the centres only
+      launch_type_sort(s, n_local, w.xw, d.ntypes, w.blk_counts, w.type_count, w.type_start, w.pos_of_atom,
+                       w.atom_of_pos, w.rows_cap);
+      // the cell list holds every atom, candidate lists the centres
+      launch_cells(s, n, w.xw, g, w.cell_of, w.cell_start, w.cell_fill, w.cell_atoms, w.cell_code, w.scan_tmp,
+                   nullptr);
+      c->cgrid = g;
+      c->cgrid_ok = true;
+      launch_candidates(s, n_local, w.xw, g, w.cell_start, w.cell_atoms, rlist, w.cand_cap, w.cand, w.cand_n,
+                        &w.status->flags, nullptr);
+      c->n_force = n;
+      eval_forward(c, n_local, L);
+      eval_backward(c, n_local, F, w.virial);
+      c->n_force = 0;
+    } else {
+      if (n > 0 && forces) launch_zero(s, F, 3 * n);
+      launch_zero(s, w.energy, 1);
+      launch_zero(s, w.virial, 9);
+      for (int k = 1; k < NMARK; ++k) tmark(c, k);
+      tnext(c);
+    }
+    if (energy) HIPCHK(c, hipMemcpyAsync(energy, w.energy, sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (virial) HIPCHK(c, hipMemcpyAsync(virial, w.virial, 9 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipGetLastError());
+    rc = read_status(c);
+    if (rc) return rc;
+    const uint32_t fl = c->h_status->flags;
+    if (fl & FLAG_BAD_TYPE) return fail(c, DP_E_TYPE, "atom type out of range");
+    if (fl & FLAG_KEY_CAP) return fail(c, DP_E_CAP, "more than 512 neighbours within rcut of one atom");
+    if (fl & FLAG_CAND_CAP) {
+      cap *= 2;
+      if (c->timing && c->nev > 0) --c->nev;
+      continue;
+    }
+    c->stats.natoms = n;
+    c->stats.evaluations += 1;
+    c->stats.cand_cap = c->ws.cand_cap;
+    c->cgrid_ok = false;
+    return DP_OK;
+  }
+  c->n_force = 0;
+  return fail(c, DP_E_CAP, "candidate list capacity could not be sized");
+}
+
 int dp_compute(dp_ctx *c, int64_t n, const double *coords, const int32_t *types, const double *box, double *energy,
                double *forces, double *virial) {
   return compute_impl(c, n, coords, types, box, energy, forces, virial, true);
+}
+
+int dp_compute_local(dp_ctx *c, int64_t n_local, int64_t natoms, const double *coords, const int32_t *types,
+                     const double *box, double *energy, double *forces, double *virial) {
+  const int rc = compute_local_impl(c, n_local, natoms, coords, types, box, energy, forces, virial);
+  if (c) c->n_force = 0;
+  return rc;
+}
+
+int dp_scatter_add_forces(dp_ctx *c, int64_t n, const int32_t *index, const double *f_in, double *f_out) {
+  if (!c) return DP_E_ARG;
+  if (n < 0 || (n > 0 && (!index || !f_in || !f_out))) return fail(c, DP_E_ARG, "bad scatter arguments");
+  HIPCHK(c, hipSetDevice(c->device));
+  if (n > 0)
+    hipLaunchKernelGGL(k_scatter_add3, dim3((unsigned)((3 * n + 255) / 256)), dim3(256), 0, c->stream, n, index, f_in,
+                       f_out);
+  HIPCHK(c, hipGetLastError());
+  return DP_OK;
 }
 
 int dp_compute_noalloc(dp_ctx *c, int64_t n, const double *coords, const int32_t *types, const double *box,

@@ -65,6 +65,26 @@ class DPModel:
         self._n = n
         return e[0], f, v.view(3, 3)
 
+    def compute_local(self, coords, types, box, n_local):
+        """Rank-share evaluation: atoms [0, n_local) are centres, the rest
+        ghosts (neighbours only).  Energy (0-d), forces [N,3] on every atom
+        (ghosts included), virial [3,3]."""
+        x = self._dev(coords, torch.float64)
+        t = self._dev(types, torch.int32)
+        n = x.shape[0]
+        e = torch.empty(1, dtype=torch.float64, device=self.device)
+        f = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        v = torch.empty(9, dtype=torch.float64, device=self.device)
+        self.eval_id += 1
+        L.dp_compute_local(self.ctx, n_local, n, _ptr(x), _ptr(t), _box9(box), _ptr(e), _ptr(f), _ptr(v))
+        return e[0], f, v.view(3, 3)
+
+    def scatter_add_forces(self, index, f_in, f_out):
+        """f_out[index[k]] += f_in[k] on the device (reverse communication)."""
+        idx = self._dev(index, torch.int32)
+        assert f_in.dtype == torch.float64 and f_out.dtype == torch.float64 and f_in.is_contiguous()
+        L.dp_scatter_add_forces(self.ctx, idx.shape[0], _ptr(idx), _ptr(f_in), _ptr(f_out))
+
     def energy(self, coords, types, box):
         """Forward half only (0-d energy tensor); keeps the state for
         energy_backward."""

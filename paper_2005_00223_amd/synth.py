@@ -17,6 +17,7 @@ available, so weights are random and seeded):
 """
 from __future__ import annotations
 
+import itertools
 import struct
 from dataclasses import dataclass, field
 
@@ -326,3 +327,44 @@ def workload(name):
         return dict(name=name, coords=x, types=t, box=box, masses=np.array([MASS["Cu"]]),
                     spec=copper_model(1), dt_fs=1.0, temp=300.0, vseed=106)
     raise KeyError(name)
+
+
+def brick_share(coords, types, box, grid, brick, rc, pad=1.0):
+    """One rank's share of a spatial decomposition of a periodic orthorhombic
+    box into grid[0] x grid[1] x grid[2] bricks (Section V-D): the atoms whose
+    wrapped position lies in brick `brick` (owned, first), then every atom or
+    periodic image within rc of the brick (ghosts), translated into a box of
+    the brick's size plus 2 rc + pad per axis, so that no periodic image of
+    the local box comes within rc.  Pure geometry: no model arithmetic.
+
+    Returns dict(coords [n,3], types [n], box [3], n_local, index [n] int32 =
+    the atom each local atom is (ghosts: the atom they image))."""
+    x = np.asarray(coords, dtype=np.float64)
+    L = np.asarray(box, dtype=np.float64).reshape(-1)
+    L = L if L.size == 3 else np.diag(L.reshape(3, 3))
+    grid = np.asarray(grid, dtype=np.int64)
+    b = np.asarray(brick, dtype=np.int64)
+    side = L / grid
+    if np.any(side <= 2.0 * rc):
+        raise ValueError("bricks must be wider than 2 rc")
+    xw = x - L * np.floor(x / L)
+    lo, hi = b * side, (b + 1) * side
+    cell = np.minimum(np.floor(xw / side).astype(np.int64), grid - 1)
+    own = np.all(cell == b, axis=1)
+    owned = np.nonzero(own)[0]
+    gx, gi = [], []
+    for s in itertools.product((-1, 0, 1), repeat=3):
+        y = xw + np.asarray(s) * L
+        inside = np.all((y >= lo - rc) & (y < hi + rc), axis=1)
+        if s == (0, 0, 0):
+            inside &= ~own
+        sel = np.nonzero(inside)[0]
+        gx.append(y[sel])
+        gi.append(sel)
+    gx = np.concatenate(gx)
+    gi = np.concatenate(gi)
+    shift = rc + 0.5 * pad - lo
+    loc = np.concatenate([xw[owned], gx]) + shift
+    return dict(coords=loc, types=np.concatenate([types[owned], types[gi]]).astype(np.int32),
+                box=side + 2.0 * rc + pad, n_local=int(owned.size),
+                index=np.concatenate([owned, gi]).astype(np.int32))
