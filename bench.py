@@ -47,7 +47,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic(spec, n_atoms, n_pairs, emb=None, affine=False, mixed=True, table=False):
+def algorithmic(spec, n_atoms, n_pairs, emb=None, affine=False, mixed=True, table=False, n_cand=0.0):
     """Algorithmic work per evaluation, by kernel (no recompute, no padding):
     flops for the network kernels, bytes for the list/env kernels.  `emb`
     overrides the embedding widths (the student's 16-32-100); `affine`: the
@@ -80,50 +80,64 @@ def algorithmic(spec, n_atoms, n_pairs, emb=None, affine=False, mixed=True, tabl
         # bytes: per real slot nlist 4 B + neighbour position 32 B in, R (FP32 in
         # mixed precision: 16 B, and no (d, r); else 32 B and (d, r) 32 B) out
         "env": n_pairs * (4 + 32 + (16.0 if mixed else 64.0)) + n_atoms * (32 + 4 * spec.ntypes),
+        # bytes: per candidate (neighbours within rc + skin, n_cand per atom)
+        # its index 4 B + position 32 B in; per real slot 4 B out; own
+        # position and counts per atom
+        "format": n_cand * (4 + 32) + n_pairs * 4 + n_atoms * (32 + 4 * spec.ntypes),
     }
 
 
-# kernel name in the profiles and the sources whose hash the PMC summary records
+# kernel of each timed kernel-level phase (as named in the profiles) and the
+# source group whose hash the PMC summary records
 PHASE_KERNEL = {
-    ("embed_bwd", "fp16", True): (("k_embed_bwd_cells<16, 32, 100, 0>", "k_cell_gather"), "k_embed_mix"),
-    ("embed_fwd", "fp16", True): (("k_embed_fwd_lin<16, 32, 100, 0>",), "k_embed_mix"),
-    ("embed_bwd", "fp16", False): (("k_embed_bwd_mix<25, 50, 100, 0, 0>",), "k_embed_mix"),
-    ("embed_fwd", "fp16", False): (("k_embed_fwd_mix<25, 50, 100, 0, 0>",), "k_embed_mix"),
-    ("fit", "fp16", True): (("k_fit_fwd<0, 15>", "k_fit_bwd<0, 15>"), "k_fit_mix"),
-    ("fit", "fp16", False): (("k_fit_fwd<0, 15>", "k_fit_bwd<0, 15>"), "k_fit_mix"),
-    ("format", "fp16", True): (("k_format",), "k_nlist"),
-    ("env", "fp16", True): (("k_env<HIP_vector_type<float, 4u> >",), "k_env"),
+    ("embed_bwd_main", True): ("k_embed_bwd_cells<16, 32, 100, 0>", "k_embed_mix"),
+    ("embed_fwd", True): ("k_embed_fwd_lin<16, 32, 100, 0>", "k_embed_mix"),
+    ("embed_bwd_main", False): ("k_embed_bwd_mix<25, 50, 100, 0, 0>", "k_embed_mix"),
+    ("embed_fwd", False): ("k_embed_fwd_mix<25, 50, 100, 0, 0>", "k_embed_mix"),
+    ("fit_fwd", True): ("k_fit_fwd<0, 15>", "k_fit_mix"),
+    ("fit_fwd", False): ("k_fit_fwd<0, 15>", "k_fit_mix"),
+    ("fit_bwd", True): ("k_fit_bwd<0, 15>", "k_fit_mix"),
+    ("fit_bwd", False): ("k_fit_bwd<0, 15>", "k_fit_mix"),
+    ("format", True): ("k_format", "k_nlist"),
+    ("format", False): ("k_format", "k_nlist"),
+    ("env", True): ("k_env<HIP_vector_type<float, 4u> >", "k_env"),
+    ("env", False): ("k_env<HIP_vector_type<float, 4u> >", "k_env"),
 }
 HASH_FILES = {"k_embed_mix": ("k_embed_mix.hip", "dp_mix.h", "dp_internal.h"),
               "k_fit_mix": ("k_fit_mix.hip", "dp_mix.h", "dp_internal.h"),
               "k_nlist": ("k_nlist.hip", "dp_internal.h"), "k_env": ("k_env.hip", "dp_internal.h")}
+PMC_FILE = os.path.join(HERE, "profiles", "cu500k_fp16_student_pmc.txt")
 
 
-def pmc_traffic(phase, precision, student):
-    """HBM bytes per evaluation of the phase's kernels from the committed
-    rocprofv3 PMC summary (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by
-    the copy calibration recorded there, summed over the phase's kernels),
-    or None when there is no summary or the sources changed after the
-    counters were taken."""
+def source_hash(group):
     import hashlib
-    key = PHASE_KERNEL.get((phase, precision, student))
-    path = os.path.join(HERE, "profiles", "cu500k_fp16_student_pmc.txt")
-    if key is None or not os.path.exists(path):
-        return None
-    names, src = key
-    text = open(path).read()
     h = hashlib.sha256()
-    for f in HASH_FILES[src]:
+    for f in HASH_FILES[group]:
         h.update(open(os.path.join(HERE, "paper_2005_00223_amd", "csrc", f), "rb").read())
-    if f"# source-hash {src}: {h.hexdigest()[:16]}" not in text:
+    return h.hexdigest()[:16]
+
+
+def pmc_row(phase, precision, student):
+    """The committed rocprofv3 PMC summary's row for the phase's kernel
+    (FP16 headline precision only): HBM bytes per dispatch (FETCH_SIZE and
+    WRITE_SIZE scaled by the copy calibration recorded there), MFMA busy and
+    VALU active fractions; None when there is no such row or the kernel's
+    sources changed after the counters were taken."""
+    key = PHASE_KERNEL.get((phase, student))
+    if precision != "fp16" or key is None or not os.path.exists(PMC_FILE):
         return None
-    total = 0.0
-    for name in names:
-        rows = [ln for ln in text.splitlines() if ln.startswith("dpk::" + name + " ")]
-        if not rows:
-            return None
-        total += float(rows[0].split()[-1]) * 1e9
-    return total
+    name, group = key
+    text = open(PMC_FILE).read()
+    if f"# source-hash {group}: {source_hash(group)}" not in text:
+        return None
+    lines = text.splitlines()
+    head = next((ln.split() for ln in lines if ln.startswith("kernel ")), None)
+    row = next((ln for ln in lines if ln.startswith("dpk::" + name + "  ")), None)
+    if head is None or row is None:
+        return None
+    vals = row[len("dpk::" + name):].split()
+    rec = dict(zip(head[1:], (float(v) for v in vals)))
+    return {"traffic": rec["hbm_GB"] * 1e9, "mfma_util": rec["mfma_busy"], "valu_active": rec["valu_active"]}
 
 
 def cpu_baseline(w, blob, seconds, log_fn):
@@ -198,6 +212,123 @@ def accuracy(args, w, blob, m, m64, x, t, student, frame):
         log(f"[bench] {frame}: {k} vs oracle ({what}): force RMSE {acc[k]['force_rmse']:.3e} eV/A, "
             f"max {acc[k]['force_max_abs_err']:.3e}")
     return acc
+
+
+def profile_summary(kind, root, command):
+    """Condense rocprofv3 CSV output under `root` into the text summaries
+    kept in profiles/.  kind "kernels": the --kernel-trace --stats table
+    (calls, mean and total ms, share per kernel).  kind "pmc": one --pmc run
+    per sub-directory (counter passes); per kernel the mean per dispatch of
+    the duration, MFMA busy (SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE x
+    1024 SIMDs, the GRBM count summed over the 8 XCDs), VALU and LDS active
+    (SQ_ACTIVE_INST_VALU / _LDS in 4-cycle units, same denominator), LDS bank
+    conflict cycles per LDS instruction, FETCH_SIZE and WRITE_SIZE (KiB) and
+    the HBM bytes they give after the copy calibration (a 1 GiB device copy,
+    bench.py --copy-probe-mb 1024, in the same runs)."""
+    import csv
+    import glob
+    from collections import defaultdict
+    out = [f"# rocprofv3 {'kernel' if kind == 'kernels' else 'PMC'} summary", f"# command: {command}"]
+    if kind == "kernels":
+        f = glob.glob(os.path.join(root, "**", "*kernel_stats.csv"), recursive=True)[0]
+        rows = list(csv.DictReader(open(f)))
+        out.append(f"# condensed from {os.path.basename(f)} by bench.py --profile-summary kernels")
+        out.append("%-62s %6s %10s %10s %6s" % ("kernel", "calls", "avg_ms", "total_ms", "pct"))
+        for r in rows:
+            out.append("%-62s %6s %10.4f %10.3f %6.2f" % (r["Name"].split("(")[0].replace("void ", "")[:62], r["Calls"],
+                                                         float(r["AverageNs"]) / 1e6, float(r["TotalDurationNs"]) / 1e6,
+                                                         float(r["Percentage"])))
+        return "\n".join(out) + "\n"
+    vals = defaultdict(lambda: defaultdict(lambda: defaultdict(float)))
+    dur = defaultdict(dict)
+    for f in glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            k = r["Kernel_Name"].split("(")[0].replace("void ", "")
+            d = (f, r["Dispatch_Id"])
+            vals[k][r["Counter_Name"]][d] += float(r["Counter_Value"])
+            dur[k][d] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+
+    def mean(k, c):
+        v = vals[k].get(c)
+        return sum(v.values()) / len(v) if v else float("nan")
+    # the calibration copies are the largest copy dispatches (1 GiB each);
+    # without them the factors measured that way on this GPU (2 and 1) apply
+    copy = vals.get("__amd_rocclr_copyBuffer", {})
+    cw = max(copy.get("WRITE_SIZE", {0: 0.0}).values())
+    if cw >= 1048576.0:
+        cf = max(copy.get("FETCH_SIZE", {0: 524288.0}).values())
+        ff, fw = 1048576.0 / cf, 1048576.0 / cw
+        out.append(f"# calibration: 1 GiB device copy reads FETCH_SIZE {cf:.0f} KiB, WRITE_SIZE {cw:.0f} KiB -> "
+                   f"factors fetch x{ff:.3f}, write x{fw:.3f}")
+    else:
+        ff, fw = 2.0, 1.0
+        out.append("# calibration: no copy probe in these runs; factors fetch x2, write x1 (a 1 GiB device copy "
+                   "reads FETCH_SIZE = 1/2 and WRITE_SIZE = 1 x its bytes on this GPU)")
+    out.append("# hbm_GB = (FETCH_SIZE * fetch factor + WRITE_SIZE * write factor) * 1024 / 1e9, per dispatch;"
+               " mfma_busy, valu_active, lds_active are fractions of the kernel's SIMD-cycles")
+    for g in HASH_FILES:
+        out.append(f"# source-hash {g}: {source_hash(g)}")
+    out.append("%-50s %5s %9s %9s %11s %10s %8s %11s %11s %8s" % (
+        "kernel", "disp", "ms", "mfma_busy", "valu_active", "lds_active", "bank/lds", "FETCH_KiB", "WRITE_KiB",
+        "hbm_GB"))
+    order = sorted(dur, key=lambda k: -sum(dur[k].values()) / len(dur[k]))
+    for k in order:
+        if not k.startswith("dpk::"):
+            continue
+        ms = sum(dur[k].values()) / len(dur[k])
+        cyc = mean(k, "GRBM_GUI_ACTIVE") / 8.0 * 1024.0
+        hbm = (mean(k, "FETCH_SIZE") * ff + mean(k, "WRITE_SIZE") * fw) * 1024 / 1e9
+        npass = len({f for f, _ in dur[k]})
+        out.append("%-50s %5d %9.4f %9.4f %11.4f %10.4f %8.3f %11.0f %11.0f %8.3f" % (
+            k[:50], len(dur[k]) // max(npass, 1), ms, mean(k, "SQ_VALU_MFMA_BUSY_CYCLES") / cyc,
+            mean(k, "SQ_ACTIVE_INST_VALU") * 4 / cyc, mean(k, "SQ_ACTIVE_INST_LDS") * 4 / cyc,
+            mean(k, "SQ_LDS_BANK_CONFLICT") / max(mean(k, "SQ_INSTS_LDS"), 1.0),
+            mean(k, "FETCH_SIZE"), mean(k, "WRITE_SIZE"), hbm))
+    return "\n".join(out) + "\n"
+
+
+def cpu_grid(args, log_fn):
+    """The FP64 CPU oracle timed on this host with all threads and with one
+    thread: one evaluation each of the 192- and 12,288-atom water boxes and
+    the 32,000-atom copper box, 100 velocity-Verlet steps of the 12,288-atom
+    water box (all threads), and the 500,000-atom copper box (all threads:
+    the whole frame; one thread: a sample of 2,048 random centre atoms and
+    their neighbour lists)."""
+    from oracle import oracle as O
+    from paper_2005_00223_amd import synth
+    rows = []
+    nthr = O.num_threads()
+
+    def one(name, threads, centres=None, steps=0):
+        log_fn(f"[cpu-grid] {name}: {threads} threads, {'%d steps' % steps if steps else 'one evaluation'} ...")
+        w = synth.workload(name)
+        o = O.Oracle(synth.pack_blob(w["spec"]))
+        n = len(w["types"])
+        t0 = time.perf_counter()
+        if steps:
+            v0 = synth.maxwell_boltzmann(w["masses"][w["types"]], w["temp"], w["vseed"])
+            o.verlet(w["coords"], v0, w["types"], w["box"], w["masses"], w["dt_fs"], steps, every=steps,
+                     nthreads=threads)
+        else:
+            o.eval(w["coords"], w["types"], w["box"], centres=centres, nthreads=threads)
+        dt = time.perf_counter() - t0
+        k = n if centres is None else len(centres)
+        r = {"workload": name, "atoms": n, "threads": threads,
+             "what": f"{steps} Verlet steps" if steps else (f"1 evaluation of {k} centre atoms"),
+             "seconds": dt, "s_per_atom_per_eval": dt / (k * max(steps, 1))}
+        log_fn(f"[cpu-grid] {r}")
+        rows.append(r)
+
+    # the oracle keeps the last thread count it was given: always pass one
+    for name in ("water192", "water12288", "cu32000"):
+        one(name, nthr)
+        one(name, 1)
+    one("water12288", nthr, steps=100)
+    one("cu500k", nthr)
+    rng = np.random.default_rng(5)
+    one("cu500k", 1, centres=np.sort(rng.choice(500000, size=2048, replace=False)))
+    return {"metric": "FP64 CPU oracle time per atom per evaluation", "unit": "s/atom", "host_threads": nthr,
+            "rows": rows}
 
 
 def rank_share(args, log_fn):
@@ -338,11 +469,18 @@ def main():
     ap.add_argument("--sweep-sizes", default="64x128,128x256,256x512,512x1024,1024x2048")
     ap.add_argument("--wide-storage", default="mix16,split",
                     help="activation storage of the GEMM path in the sweep: mix16, split or both")
+    ap.add_argument("--profile-summary", nargs=3, metavar=("KIND", "DIR", "COMMAND"),
+                    help="condense rocprofv3 CSV output (KIND kernels or pmc) under DIR into a profiles/ text summary")
+    ap.add_argument("--cpu-grid", action="store_true", help="time the CPU oracle on several workloads, all and one thread")
     ap.add_argument("--rank-share", action="store_true",
                     help="time one brick of a 2x2x2 spatial decomposition (owned atoms + rc+skin ghost shell)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run a plain device copy of this many MiB (traffic-counter calibration)")
     args = ap.parse_args()
+    if args.profile_summary:
+        kind, root, command = args.profile_summary
+        sys.stdout.write(profile_summary(kind, root, command))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "spatial decomposition is a design, not code", file=sys.stderr)
@@ -360,6 +498,9 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy probe: 3 copies of {args.copy_probe_mb} MiB")
         del src, dst
+    if args.cpu_grid:
+        print(json.dumps(cpu_grid(args, log)), flush=True)
+        return
     if args.rank_share:
         print(json.dumps(rank_share(args, log)), flush=True)
         return
@@ -432,32 +573,42 @@ def main():
                    "+ FP64 least-squares output layer on 262144 samples, all inside the timed region"}
         log(f"[bench] student: train {t_train * 1e3:.1f} ms, G rel RMSE {fit:.2e}, judge RMSE "
             f"{st['last_judge_rmse']:.2e}, fallbacks {st['teacher_fallbacks']}")
-    phases = {k: m.timing(k) for k in ("lists", "format", "env", "embed_fwd", "fit", "embed_bwd", "total")}
+    phases = {k: m.timing(k) for k in ("lists", "format", "env", "embed_fwd", "fit", "embed_bwd", "total",
+                                       "fit_fwd", "fit_bwd", "embed_bwd_main")}
     _, nr = m.nlist(n, spec.nnei, spec.ntypes, with_list=False)
     n_pairs = float(nr.sum().item())
     used_student = student and st["teacher_fallbacks"] == 0
+    # candidates (neighbours within rc + skin) per atom: the real pairs scaled by the volume ratio
+    n_cand = n_pairs * ((spec.rcut + args.skin) / spec.rcut) ** 3
     alg = algorithmic(spec, n, n_pairs, emb=(16, 32, spec.M1) if used_student else None, affine=used_student,
-                      mixed=args.precision != "fp64", table=used_student and st["table_evals"] > 0)
-    kern = max(("format", "env", "embed_fwd", "fit", "embed_bwd"), key=lambda k: phases[k])
+                      mixed=args.precision != "fp64", table=used_student and st["table_evals"] > 0, n_cand=n_cand)
     thn = th.cpu().numpy()
     drift = float((thn[-1, 3] - thn[0, 3]) / n) if len(thn) > 1 else 0.0
+    # the longest single kernel of the step (kernel-level phases)
+    kern = max(("format", "env", "embed_fwd", "fit_fwd", "fit_bwd", "embed_bwd_main"), key=lambda k: phases[k])
+    work = {"format": alg["format"], "env": alg["env"], "embed_fwd": alg["embed_fwd"], "fit_fwd": alg["fit"] / 2,
+            "fit_bwd": alg["fit"] / 2, "embed_bwd_main": alg["embed_bwd"]}[kern]
     if kern in ("env", "format"):
-        ach = alg.get(kern, 0.0) / (phases[kern] * 1e-3) / 1e9
+        ach = work / (phases[kern] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": ach, "peak": PEAK["hbm"], "unit": "GB/s", "frac": ach / PEAK["hbm"]}
-    elif kern in ("embed_fwd", "embed_bwd") and used_student and args.precision != "fp64":
+    elif kern in ("embed_fwd", "embed_bwd_main") and used_student and args.precision != "fp64":
         # the student's embedding kernels spend their time in FP32 vector work
         # (table interpolation, operand splits) and the FP64 force pass, not in
         # the matrix cores: priced against the FP32 vector peak
-        ach = alg[kern] / (phases[kern] * 1e-3) / 1e12
+        ach = work / (phases[kern] * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": ach, "peak": PEAK["f32_valu"], "unit": "TFLOP/s",
                 "frac": ach / PEAK["f32_valu"]}
     else:
         pk = {"fp64": "f64_mfma", "fp32": "f32_valu", "fp16": "f16_mfma", "bf16": "bf16_mfma"}[args.precision]
-        ach = alg[kern] / (phases[kern] * 1e-3) / 1e12
+        ach = work / (phases[kern] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": ach, "peak": PEAK[pk], "unit": "TFLOP/s", "frac": ach / PEAK[pk]}
-    roof.update(kernel=kern, traffic=pmc_traffic(kern, args.precision, used_student))
-    if roof["traffic"] is not None:
-        roof["traffic_GBps_at_phase_time"] = roof["traffic"] / (phases[kern] * 1e-3) / 1e9
+    pm = pmc_row(kern, args.precision, used_student)
+    kname = PHASE_KERNEL.get((kern, used_student), (kern,))[0] if args.precision == "fp16" else kern
+    roof.update(kernel=kname, kernel_ms=phases[kern],
+                traffic=pm["traffic"] if pm else None)
+    if pm:
+        roof.update(traffic_GBps=pm["traffic"] / (phases[kern] * 1e-3) / 1e9, mfma_util=pm["mfma_util"],
+                    valu_active=pm["valu_active"], counters="profiles/cu500k_fp16_student_pmc.txt")
     if args.workload.startswith("cu"):
         wl = (f"{args.workload}: FCC Cu {n} atoms, rc 8 A, sel 512, emb 1-25-50-100, M2 16, fit 240x3, "
               f"NVE 1 fs, skin {args.skin} A")

@@ -257,8 +257,11 @@ int dp_md_run(dp_ctx *c, int64_t natoms, double *coords, double *vel, const int3
  * names: "lists" (wrap, type order, cells, candidate list), "format"
  * (formatted neighbour list kernel), "env" (environment-matrix kernel),
  * "embed_fwd" (fused embedding + descriptor kernel), "fit" (fitting-net
- * kernels), "embed_bwd" (embedding backward + force/virial kernel),
- * "total" (whole evaluation). */
+ * kernels and the energy sum), "fit_fwd" / "fit_bwd" (its forward kernel /
+ * the energy sum and its backward kernel), "embed_bwd" (embedding backward
+ * + force/virial kernel and, with the cell-ordered scatter, the gather
+ * pass), "embed_bwd_main" (the embedding backward kernel alone), "total"
+ * (whole evaluation). */
 int dp_enable_timing(dp_ctx *c, int on);
 int dp_get_timing(dp_ctx *c, const char *name, double *ms);
 

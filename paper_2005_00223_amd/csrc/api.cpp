@@ -704,7 +704,7 @@ int cand_capacity(int64_t n, const double L[3], double rlist) {
   return rup((int)cap, 64);
 }
 
-constexpr int NMARK = 8;
+constexpr int NMARK = 10;
 constexpr int EV_MAX = 2048;
 
 inline void tmark(dp_ctx *c, int k) {
@@ -971,6 +971,7 @@ void eval_nets_fwd(dp_ctx *c, int64_t n, double *E) {
     launch_embed_fwd_f64(s, embed_args(c, n, rows, nullptr));
     tmark(c, 4);
     launch_fit_f64(s, fit_args(c, rows), 1);
+    tmark(c, 8);
   } else {
     (void)ensure_table(c, n);  // a failed table build leaves tab_ok false: the layers are evaluated
     if (c->en[c->active].wide) {
@@ -984,6 +985,7 @@ void eval_nets_fwd(dp_ctx *c, int64_t n, double *E) {
     }
     tmark(c, 4);
     launch_fit_mix(s, fitmix_args(c, rows), 1);
+    tmark(c, 8);
   }
   launch_sum(s, w.eatom, n, w.partial, E, 1.0);
   if (c->active == 1) c->stats.student_evals += 1;
@@ -1037,6 +1039,7 @@ void eval_backward(dp_ctx *c, int64_t n, double *F, double *V) {
     const int grid = embed_bwd_grid(rows);
     tmark(c, 6);
     launch_embed_bwd_f64(s, embed_args(c, n, rows, F), grid);
+    tmark(c, 9);
     tmark(c, 7);
     launch_sum9(s, w.vir_part, grid, V);
   } else {
@@ -1049,9 +1052,11 @@ void eval_backward(dp_ctx *c, int64_t n, double *F, double *V) {
         WideArgs a = wide_args(c, n);
         a.force = F;
         launch_wide_bwd(s, a);
+        tmark(c, 9);
         tmark(c, 7);
         launch_sum9(s, w.vir_part, (int)std::min<int64_t>(n, WIDE_GRID), V);
       } else {
+        tmark(c, 9);
         tmark(c, 7);
         launch_zero(s, V, 9);
       }
@@ -1065,6 +1070,7 @@ void eval_backward(dp_ctx *c, int64_t n, double *F, double *V) {
     if (cell_scatter_args(c, n, ma, ca, threads, lds)) {
       const int grid = cells_grid(ca.ncell);
       launch_embed_cells(s, ma, ca, grid, threads, lds);
+      tmark(c, 9);
       launch_cell_gather(s, ca, F);
       tmark(c, 7);
       launch_sum9(s, w.vir_part, grid, V);
@@ -1072,6 +1078,7 @@ void eval_backward(dp_ctx *c, int64_t n, double *F, double *V) {
     } else {
       const int grid = mix_grid(rows);
       launch_embed_mix(s, ma, 2, grid);
+      tmark(c, 9);
       tmark(c, 7);
       launch_sum9(s, w.vir_part, grid, V);
     }
@@ -1577,13 +1584,16 @@ int dp_enable_timing(dp_ctx *c, int on) {
 
 int dp_get_timing(dp_ctx *c, const char *name, double *ms) {
   if (!c || !name || !ms) return DP_E_ARG;
-  // marks: 0 start, 1 lists built, 2 format, 3 env, 4 embed_fwd, 5 fitting
-  // net, 6 energy sum + force clear, 7 embed_bwd (with forces and virial)
-  static const char *names[] = {"lists", "format", "env", "embed_fwd", "fit", "embed_bwd", "total"};
-  static const int from[] = {0, 1, 2, 3, 4, 6, 0};
-  static const int to[] = {1, 2, 3, 4, 5, 7, 7};
+  // marks: 0 start, 1 lists built, 2 format, 3 env, 4 embed_fwd, 8 fitting
+  // net forward kernel, 5 fitting net (energy sum, backward kernel), 6 force
+  // clear, 9 embedding backward kernel, 7 embed_bwd done (gather of the
+  // cell-ordered scatter)
+  static const char *names[] = {"lists", "format", "env", "embed_fwd", "fit", "embed_bwd", "total",
+                                "fit_fwd", "fit_bwd", "embed_bwd_main"};
+  static const int from[] = {0, 1, 2, 3, 4, 6, 0, 4, 8, 6};
+  static const int to[] = {1, 2, 3, 4, 5, 7, 7, 8, 5, 9};
   if (c->nev == 0) return fail(c, DP_E_ARG, "no timed evaluation");
-  for (int k = 0; k < 7; ++k)
+  for (int k = 0; k < 10; ++k)
     if (std::strcmp(name, names[k]) == 0) {
       double sum = 0.0;
       for (int64_t e = 0; e < c->nev; ++e) {
@@ -1821,6 +1831,7 @@ int dp_energy_backward(dp_ctx *c, double grad_energy, double *forces, double *vi
     tmark(c, 2);
     tmark(c, 3);
     tmark(c, 4);
+    tmark(c, 8);
     eval_backward(c, n, F, w.virial);
     if (grad_energy != 1.0) {
       hipLaunchKernelGGL(k_scale, dim3((unsigned)((3 * n + 255) / 256)), dim3(256), 0, s, F, 3 * n, grad_energy);
