@@ -63,9 +63,45 @@ static EmbLds emb_lds_layout(const Dims &d, int pass) {
 }
 
 // One MFMA layer: acc[ct][mt] = (W^T H^T) for column tile ct, output tile mt.
+// Shapes known at compile time (KP = padded inputs, MP = padded outputs):
+// every weight load is unconditional and the next k-step's loads are in
+// flight during this k-step's products.
+template <int NCT, int KP, int MP>
+__device__ inline void mfma_layer_t(const double *__restrict__ W, const double *Hin, int cols, int lane,
+                                    v4d (&acc)[NCT][MAXMT]) {
+  constexpr int NMT = MP / 16;
+  static_assert(NMT <= MAXMT && KP % 4 == 0, "layer shape");
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int mt = 0; mt < MAXMT; ++mt) acc[ct][mt] = v4d{0.0, 0.0, 0.0, 0.0};
+  const double *wr = W + (size_t)(lane >> 4) * MP + (lane & 15);
+  double an[NMT];
+#pragma unroll
+  for (int mt = 0; mt < NMT; ++mt) an[mt] = wr[mt * 16];
+#pragma unroll
+  for (int kk = 0; kk < KP; kk += 4) {
+    double ac[NMT];
+#pragma unroll
+    for (int mt = 0; mt < NMT; ++mt) ac[mt] = an[mt];
+    if (kk + 4 < KP)
+#pragma unroll
+      for (int mt = 0; mt < NMT; ++mt) an[mt] = wr[(size_t)(kk + 4) * MP + mt * 16];
+    const int krow = kk + (lane >> 4);
+    double bv[NCT];
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) bv[ct] = Hin[krow * cols + ct * 16 + (lane & 15)];
+#pragma unroll
+    for (int mt = 0; mt < NMT; ++mt)
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) acc[ct][mt] = mfma64(ac[mt], bv[ct], acc[ct][mt]);
+  }
+}
+
+// Any shape (widths up to 128): the generic loop.
 template <int NCT>
-__device__ inline void mfma_layer(const double *__restrict__ W, int kp, int mp, const double *Hin, int cols, int lane,
-                                  v4d (&acc)[NCT][MAXMT]) {
+__device__ inline void mfma_layer_any(const double *__restrict__ W, int kp, int mp, const double *Hin, int cols,
+                                      int lane, v4d (&acc)[NCT][MAXMT]) {
   const int nmt = mp >> 4;
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct)
@@ -86,6 +122,18 @@ __device__ inline void mfma_layer(const double *__restrict__ W, int kp, int mp, 
       }
     }
   }
+}
+
+// The layer shapes of the 1-25-50-100 and 1-16-32-100 nets run the
+// compile-time loop, others the generic one (the branch is wave-uniform).
+template <int NCT>
+__device__ inline void mfma_layer(const double *__restrict__ W, int kp, int mp, const double *Hin, int cols, int lane,
+                                  v4d (&acc)[NCT][MAXMT]) {
+  if (kp == 28 && mp == 64) mfma_layer_t<NCT, 28, 64>(W, Hin, cols, lane, acc);
+  else if (kp == 52 && mp == 112) mfma_layer_t<NCT, 52, 112>(W, Hin, cols, lane, acc);
+  else if (kp == 16 && mp == 32) mfma_layer_t<NCT, 16, 32>(W, Hin, cols, lane, acc);
+  else if (kp == 32 && mp == 112) mfma_layer_t<NCT, 32, 112>(W, Hin, cols, lane, acc);
+  else mfma_layer_any<NCT>(W, kp, mp, Hin, cols, lane, acc);
 }
 
 __device__ inline int skip_src(int f, int in, int out) {

@@ -179,6 +179,14 @@ __device__ inline void copy_nets(unsigned char *dst, const unsigned char *src, i
   for (int o = threadIdx.x; o < bytes / 16; o += blockDim.x) d[o] = s[o];
 }
 
+// Environment row of slot q of a type block of cnt >= 1 real slots: the
+// load is unconditional (a slot past the block reads the last real row and
+// returns zeros), so it never waits behind a branch.
+__device__ inline float4 rt_row(const float4 *rt, int64_t base, int q, int cnt) {
+  const float4 v = rt[base + (q < cnt ? q : cnt - 1)];
+  return q < cnt ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 // ---------------------------------------------------------------------------
 // T += G R^T over the 16 neighbours of a tile, G transposed through LDS.
 // FP16: v_mfma_f32_16x16x16_f16 with G and R as hi + lo halves (three
@@ -376,7 +384,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 1>::B)) k_embed_fw
       const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
       const int64_t base = (int64_t)i * d.nnei + d.off[u];
       for (int n0 = 0; n0 < cnt; n0 += 16) {
-        const float4 r4 = n0 + n < cnt ? a.rt[base + n0 + n] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 r4 = rt_row(a.rt, base, n0 + n, cnt);
         const float s = r4.x;
         if (g == 0) *(float4 *)(Rs + 4 * n) = make_float4(r4.x, r4.y, r4.z, r4.w);
         float h1[2][4], hd_unused[2][4];
@@ -561,7 +569,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 2>::B)) k_embed_bw
       const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
       const int64_t base = (int64_t)i * d.nnei + d.off[u];
       for (int n0 = 0; n0 < cnt; n0 += 16) {
-        const float4 r4 = n0 + n < cnt ? a.rt[base + n0 + n] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 r4 = rt_row(a.rt, base, n0 + n, cnt);
         const float s = r4.x;
         if (g == 0) *(float4 *)(Rs + 4 * n) = make_float4(r4.x, r4.y, r4.z, r4.w);
         float h1[2][4], hd1[2][4];
@@ -768,11 +776,11 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_fwd_lin(MixArgs a) 
       const int64_t base = (int64_t)i * d.nnei + d.off[u];
       v4f Hacc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
       float sr0 = 0.f, sr1 = 0.f, sr2 = 0.f, sr3 = 0.f;  // this lane's neighbours: sum of R
-      float4 r4n = n < cnt ? a.rt[base + n] : make_float4(0.f, 0.f, 0.f, 0.f);
+      float4 r4n = rt_row(a.rt, base, n, cnt);
       for (int n0 = 0; n0 < cnt; n0 += 16) {
         // this tile's environment rows; the next tile's are loaded meanwhile
         const float4 r4 = r4n;
-        if (n0 + 16 < cnt) r4n = n0 + 16 + n < cnt ? a.rt[base + n0 + 16 + n] : make_float4(0.f, 0.f, 0.f, 0.f);
+        if (n0 + 16 < cnt) r4n = rt_row(a.rt, base, n0 + 16 + n, cnt);
         const float s = r4.x;
         if (g == 0) *(float4 *)(Rs + 4 * n) = make_float4(r4.x, r4.y, r4.z, r4.w);
         sr0 += r4.x;
@@ -948,15 +956,15 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
       my[r] = Macc[1][r];
     }
     const Split8<P> MA = split8<P>(mx, my);
-    float4 r4n = n < cnt ? a.rt[base + n] : make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 r4n = rt_row(a.rt, base, n, cnt);
     // force-pass operands of the current 64-neighbour chunk, loaded a chunk ahead
     double4 pjc = xi;  // neighbour positions of the chunk, gathered at its first tile
-    int jc = lane < cnt ? a.nlist[base + lane] : 0;
+    int jc = a.nlist[base + (lane < cnt ? lane : cnt - 1)];
     uint32_t codec = 0;
     for (int n0 = 0; n0 < cnt; n0 += 16) {
       // this tile's environment rows; the next tile's are loaded meanwhile
       const float4 r4 = r4n;
-      if (n0 + 16 < cnt) r4n = n0 + 16 + n < cnt ? a.rt[base + n0 + 16 + n] : make_float4(0.f, 0.f, 0.f, 0.f);
+      if (n0 + 16 < cnt) r4n = rt_row(a.rt, base, n0 + 16 + n, cnt);
       const float s = r4.x;
       float h2[S::MT2][4], hd2[S::MT2][4];
       if (tabs && __ballot(s > a.tab_shi) == 0ull) {
@@ -1036,9 +1044,7 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
             unsafeAtomicAdd(a.force + 3 * (int64_t)jc + 2, -gz);
           }
         }
-        if (qq + 64 < cnt) {
-          jc = a.nlist[base + qq + 64];
-        }
+        if (c0 + 64 < cnt) jc = a.nlist[base + (qq + 64 < cnt ? qq + 64 : cnt - 1)];
         wsync();
       }
     }

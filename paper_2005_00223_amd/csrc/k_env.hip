@@ -48,10 +48,13 @@ __global__ void __launch_bounds__(256) k_env(int64_t n, const double4 *__restric
 #pragma unroll
       for (int v = 0; v < ENV_BATCH; ++v) {
         const int q = q0 + 64 * v + lane;
-        jb[v] = q < cnt ? nlist[base + q] : -1;
+        jb[v] = nlist[base + (q < cnt ? q : cnt - 1)];  // unconditional; masked below
       }
 #pragma unroll
-      for (int v = 0; v < ENV_BATCH; ++v) pb[v] = jb[v] >= 0 ? xw[jb[v]] : p;
+      for (int v = 0; v < ENV_BATCH; ++v) pb[v] = xw[jb[v]];
+#pragma unroll
+      for (int v = 0; v < ENV_BATCH; ++v)
+        if (q0 + 64 * v + lane >= cnt) jb[v] = -1;
 #pragma unroll
       for (int v = 0; v < ENV_BATCH; ++v) {
         const int q = q0 + 64 * v + lane;

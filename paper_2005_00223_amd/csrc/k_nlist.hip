@@ -370,15 +370,23 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
   const int32_t *ci = cand + i * (int64_t)cap;
   for (int q0 = 0; q0 < nc; q0 += 64 * FMT_BATCH) {
     // issue the index loads, then the position gathers, of FMT_BATCH rounds
+    // unconditional loads (lanes past the list reread its last entry and
+    // are then masked), so none of them waits behind a branch
     int32_t jb[FMT_BATCH];
     double4 pb[FMT_BATCH];
 #pragma unroll
     for (int u = 0; u < FMT_BATCH; ++u) {
       const int q = q0 + 64 * u + lane;
-      jb[u] = q < nc ? ci[q] : -1;
+      jb[u] = ci[q < nc ? q : nc - 1];
     }
 #pragma unroll
-    for (int u = 0; u < FMT_BATCH; ++u) pb[u] = jb[u] >= 0 ? xw[jb[u]] : p;
+    for (int u = 0; u < FMT_BATCH; ++u) pb[u] = xw[jb[u]];
+#pragma unroll
+    for (int u = 0; u < FMT_BATCH; ++u)
+      if (q0 + 64 * u + lane >= nc) {
+        jb[u] = -1;
+        pb[u] = p;
+      }
 #pragma unroll
     for (int u = 0; u < FMT_BATCH; ++u) {
       const int32_t j = jb[u];
