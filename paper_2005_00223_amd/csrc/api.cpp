@@ -1007,13 +1007,16 @@ bool cell_scatter_args(dp_ctx *c, int64_t n, const MixArgs &ma, CellArgs &ca, in
   if (c->scatter != 0 || c->ov_atom_of_pos || c->n_force > 0 || !c->cgrid_ok || !w.cell_part || n <= 0) return false;
   for (int a = 0; a < 3; ++a)
     if (c->cgrid.nc[a] < 3 || c->cgrid.nc[a] > 255) return false;
-  // atoms per cell kept in the LDS accumulator: twice the mean occupancy
-  // plus slack (atoms beyond it add their forces with global atomics), at
-  // most CELL_CAP; a smaller accumulator leaves room for more nets
+  // atoms per cell kept in the LDS accumulator (atoms beyond it add their
+  // forces with global atomics): up to twice the mean occupancy plus slack,
+  // at most CELL_CAP, and at least the mean plus 16; within that range the
+  // kernel takes the most waves the LDS allows
   const int64_t ncell = (int64_t)c->cgrid.nc[0] * c->cgrid.nc[1] * c->cgrid.nc[2];
   const int64_t mean = (n + ncell - 1) / ncell;
-  const int cap = (int)std::max<int64_t>(32, std::min<int64_t>(CELL_CAP, (2 * mean + 16 + 15) / 16 * 16));
-  if (!embed_cells_config(ma, cap, &threads, &lds)) return false;
+  const int want = (int)std::max<int64_t>(32, std::min<int64_t>(CELL_CAP, (2 * mean + 16 + 15) / 16 * 16));
+  const int need = (int)std::min<int64_t>(want, std::max<int64_t>(16, mean + 16));
+  int cap = 0;
+  if (!embed_cells_config(ma, want, need, &cap, &threads, &lds)) return false;
   ca.cell_start = w.cell_start;
   ca.cell_atoms = w.cell_atoms;
   ca.cell_of = w.cell_of;

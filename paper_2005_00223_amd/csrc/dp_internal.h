@@ -128,6 +128,27 @@ __device__ inline double4 pair_disp(const double4 &pi, const double4 &pj, double
   else if (dz < -0.5 * L2) dz += L2;
   return make_double4(dx, dy, dz, sqrt(dx * dx + dy * dy + dz * dz));
 }
+// the same displacement with r^2 in place of r: (dx, dy, dz, r^2)
+__device__ inline double4 pair_disp_sq(const double4 &pi, const double4 &pj, double L0, double L1, double L2) {
+  double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+  if (dx > 0.5 * L0) dx -= L0;
+  else if (dx < -0.5 * L0) dx += L0;
+  if (dy > 0.5 * L1) dy -= L1;
+  else if (dy < -0.5 * L1) dy += L1;
+  if (dz > 0.5 * L2) dz -= L2;
+  else if (dz < -0.5 * L2) dz += L2;
+  return make_double4(dx, dy, dz, dx * dx + dy * dy + dz * dz);
+}
+// 1/sqrt(x) for normal x > 0: the hardware estimate (relative error below
+// 2^-22) and two Newton steps y += y (1 - x y^2) / 2, each squaring the
+// relative error, which leaves a few ulp of FP64
+__device__ inline double rsqrt64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-x * y, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-x * y, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
 // exactly one of rt (FP64 evaluation) and rt32 (mixed precision, the same
 // values rounded to FP32, which is all the mixed kernels read) is non-NULL;
 // dr (may be NULL: the mixed kernels recompute it from the positions)

@@ -45,35 +45,27 @@ __device__ inline float tanh_f(float x) {
   const float e = __builtin_amdgcn_exp2f(x * 2.8853900817779268f);
   return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
 }
-// C2 switching function of the smooth edition and its derivative d sw / dr
-__device__ inline void switch64(double r, double rcs, double rc, double inv_w, double &sw, double &dsw) {
-  if (r < rcs) {
-    sw = 1.0;
-    dsw = 0.0;
-  } else if (r < rc) {
-    const double x = (r - rcs) * inv_w;
-    sw = x * x * x * (-6.0 * x * x + 15.0 * x - 10.0) + 1.0;
-    dsw = x * x * (-30.0 * x * x + 60.0 * x - 30.0) * inv_w;
-  } else {
-    sw = 0.0;
-    dsw = 0.0;
-  }
-}
-
 // FP64 force of one pair from dE/dR (gr) and the neighbour's displacement
-// D4 = (dx, dy, dz, r): g = dE/dr_ij (F_i += g, F_j -= g), accumulated into
-// fi and the virial
+// D4 = (dx, dy, dz, r^2) (neighbours lie within the cut-off, r > 0):
+// g = dE/dr_ij (F_i += g, F_j -= g), accumulated into fi and the virial.
+// With R = (s, s d / r), s = sw(r) / r and t = s / r = sw / r^2:
+//   ds/dr = dsw / r - t,  dt/dr = (dsw / r - 2 t) / r,
+//   g = (g0 ds/dr + (g1:3 . d) dt/dr) d / r + t g1:3.
+// The switch takes the polynomial at x clamped to [0, 1], which gives
+// sw = 1, dsw = 0 inside rcs and sw = 0, dsw = 0 at and beyond rc.
 __device__ inline void pair_force(const double4 &D4, float4 gr, double rc, double rcs, double inv_w, double &gx,
                                   double &gy, double &gz, double &fi0, double &fi1, double &fi2, double (&vir)[9]) {
   const double g0 = gr.x, g1 = gr.y, g2 = gr.z, g3 = gr.w;
-  const double dx = D4.x, dy = D4.y, dz = D4.z, r = D4.w;
-  double sw, dsw;
-  switch64(r, rcs, rc, inv_w, sw, dsw);
-  const double ir = 1.0 / r;
-  const double sv = sw * ir;
-  const double ds = (dsw * r - sw) * ir * ir;
-  const double tt = sv * ir;
-  const double dtt = dsw * ir * ir - 2.0 * sw * ir * ir * ir;
+  const double dx = D4.x, dy = D4.y, dz = D4.z;
+  const double ir = rsqrt64(D4.w), r = D4.w * ir;
+  const double x = fmin(fmax((r - rcs) * inv_w, 0.0), 1.0);
+  const double sw = x * x * x * (-6.0 * x * x + 15.0 * x - 10.0) + 1.0;
+  const double dsw = x * x * (-30.0 * x * x + 60.0 * x - 30.0) * inv_w;
+  const double ir2 = ir * ir;
+  const double tt = sw * ir2;
+  const double A = dsw * ir;
+  const double ds = A - tt;
+  const double dtt = (A - 2.0 * tt) * ir;
   const double gd = g1 * dx + g2 * dy + g3 * dz;
   const double cc = (g0 * ds + dtt * gd) * ir;
   gx = cc * dx + tt * g1;
@@ -157,7 +149,7 @@ struct FitMixArgs {
 };
 
 // cell-ordered backward of the affine-last-layer nets (k_embed_bwd_cells)
-constexpr int CELL_WAVES = 12;   // waves per workgroup at most
+constexpr int CELL_WAVES = 16;   // waves per workgroup at most
 constexpr int CELL_CAP = 128;    // atoms per cell kept in LDS; the rest use global atomics
 struct CellArgs {
   const int32_t *cell_start;     // [ncell + 1]
@@ -169,9 +161,11 @@ struct CellArgs {
   int64_t ncell, n;
   double *part;                  // [27][n][3] per-cell parts of the forces, cell order
 };
-// workgroup size and LDS bytes of the cell kernel, or false when the net
-// shape or the LDS budget does not allow it
-bool embed_cells_config(const MixArgs &a, int cap, int *threads, size_t *lds);
+// accumulator capacity (atoms per cell, need <= cap <= want), workgroup size
+// and LDS bytes of the cell kernel: the most waves that leave room for at
+// least `need` atoms per cell; false when the net shape or the LDS budget
+// does not allow it
+bool embed_cells_config(const MixArgs &a, int want, int need, int *cap, int *threads, size_t *lds);
 int cells_grid(int64_t ncell);
 void launch_embed_cells(hipStream_t s, const MixArgs &a, const CellArgs &ca, int grid, int threads, size_t lds);
 void launch_cell_gather(hipStream_t s, const CellArgs &ca, double *F);

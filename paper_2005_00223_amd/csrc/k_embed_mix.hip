@@ -166,8 +166,9 @@ struct MixOcc {
 
 // rows handled by wave gw of nwaves: a contiguous chunk
 __device__ inline void wave_rows(int64_t rows, int64_t &p0, int64_t &p1) {
-  const int64_t nwaves = (int64_t)gridDim.x * MIX_WAVES;
-  const int64_t gw = (int64_t)blockIdx.x * MIX_WAVES + (threadIdx.x >> 6);
+  const int nw = blockDim.x >> 6;
+  const int64_t nwaves = (int64_t)gridDim.x * nw;
+  const int64_t gw = (int64_t)blockIdx.x * nw + (threadIdx.x >> 6);
   const int64_t chunk = (rows + nwaves - 1) / nwaves;
   p0 = gw * chunk;
   p1 = p0 + chunk < rows ? p0 + chunk : rows;
@@ -466,7 +467,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 1>::B)) k_embed_fw
 // pass 2
 // ---------------------------------------------------------------------------
 // pair_force with the neighbour's share scattered by global atomics;
-// D4 = dr[slot] and j = nlist[slot]
+// D4 = (d, r^2) of the pair and j = nlist[slot]
 __device__ inline void force_pair(const MixArgs &a, int64_t slot, const double4 &D4, int j, float4 gr, double rc,
                                   double rcs, double inv_w, double &fi0, double &fi1, double &fi2, double (&vir)[9]) {
   if (a.net_deriv) {
@@ -671,7 +672,7 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 2>::B)) k_embed_bw
           if (q < cnt) {
             const float4 gr = *(const float4 *)(gRs + 4 * lane);
             const int j = a.nlist[base + q];
-            force_pair(a, base + q, pair_disp(xi, a.xw[j], a.L[0], a.L[1], a.L[2]), j, gr, rc, rcs, inv_w, fi0,
+            force_pair(a, base + q, pair_disp_sq(xi, a.xw[j], a.L[0], a.L[1], a.L[2]), j, gr, rc, rcs, inv_w, fi0,
                        fi1, fi2, vir);
           }
           wsync();
@@ -696,15 +697,17 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, (MixOcc<W2, 2>::B)) k_embed_bw
 // ---------------------------------------------------------------------------
 // Tabulated second layer at s (0 <= s <= the table's range): lane group g
 // gets features f = 16 mt + 4 g + r, r = 0..3 (the MFMA output layout);
-// cubic Hermite interpolation between rows k and k + 1; D: also dh2/ds.
+// cubic Hermite interpolation between rows k and k + 1, written with the
+// node difference y1 - y0 (h00 = 1 - h01) so that value and slope share it;
+// D: also ds * dh2/ds (the caller applies the factor 1/ds once per neighbour).
 template <bool D>
 __device__ inline void tab_h2(const float *tab, float s, float inv_ds, int g, float (&h)[2][4], float (&dh)[2][4]) {
   const float x = s * inv_ds;
   int k = (int)x;
   k = k < TAB_K - 1 ? k : TAB_K - 1;
   const float t = x - (float)k, t2 = t * t, t3 = t2 * t;
-  const float h00 = 2.f * t3 - 3.f * t2 + 1.f, h10 = t3 - 2.f * t2 + t, h01 = 3.f * t2 - 2.f * t3, h11 = t3 - t2;
-  const float e00 = 6.f * (t2 - t), e10 = 3.f * t2 - 4.f * t + 1.f, e11 = 3.f * t2 - 2.f * t;
+  const float h10 = t3 - 2.f * t2 + t, h01 = 3.f * t2 - 2.f * t3, h11 = t3 - t2;
+  const float e01 = 6.f * (t - t2), e10 = 3.f * t2 - 4.f * t + 1.f, e11 = 3.f * t2 - 2.f * t;
   const float *r0 = tab + k * TAB_STRIDE, *r1 = r0 + TAB_STRIDE;
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt) {
@@ -715,8 +718,9 @@ __device__ inline void tab_h2(const float *tab, float s, float inv_ds, int g, fl
     const float y1[4] = {b0.x, b0.z, b1.x, b1.z}, m1[4] = {b0.y, b0.w, b1.y, b1.w};
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      h[mt][r] = h00 * y0[r] + h10 * m0[r] + h01 * y1[r] + h11 * m1[r];
-      if (D) dh[mt][r] = (e00 * (y0[r] - y1[r]) + e10 * m0[r] + e11 * m1[r]) * inv_ds;
+      const float dy = y1[r] - y0[r];
+      h[mt][r] = h01 * dy + h10 * m0[r] + h11 * m1[r] + y0[r];
+      if (D) dh[mt][r] = e01 * dy + e10 * m0[r] + e11 * m1[r];
     }
   }
 }
@@ -967,9 +971,11 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
       if (n0 + 16 < cnt) r4n = rt_row(a.rt, base, n0 + 16 + n, cnt);
       const float s = r4.x;
       float h2[S::MT2][4], hd2[S::MT2][4];
+      float dscale = 1.f;  // hd2 * dscale = dh2/ds
       if (tabs && __ballot(s > a.tab_shi) == 0ull) {
         // every neighbour of the tile inside the table's range
         tab_h2<true>(tabs + (t * d.ntypes + u) * (TAB_BYTES / 4), s, a.tab_inv_ds, g, h2, hd2);
+        dscale = a.tab_inv_ds;
       } else {
         float h1[2][4], hd1[2][4];
         layer1<W1, true>(w1, b1, s, g, h1, hd1);
@@ -1001,7 +1007,7 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
           }
       }
       const Split8<P> B3h = split8<P>(h2[0], h2[1]), B3d = split8<P>(hd2[0], hd2[1]);
-      // a = M^T h2 and b = M^T h2' (lane (g, n): component c = 4 g + r of neighbour n)
+      // a = M^T h2 and b = M^T hd2, h2' = dscale hd2 (lane (g, n): component c = 4 g + r of neighbour n)
       v4f ca = v4f{0.f, 0.f, 0.f, 0.f}, cb = v4f{0.f, 0.f, 0.f, 0.f};
       ca = mfma16<P>(MA.hi, B3h.hi, ca);
       ca = mfma16<P>(MA.hi, B3h.lo, ca);
@@ -1011,8 +1017,8 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
       cb = mfma16<P>(MA.lo, B3d.hi, cb);
       const int slot0 = n0 & 63;
       if (g == 0) {
-        // dE/dR = a + q + (R . b) e_0
-        const float bd = r4.x * cb[0] + r4.y * cb[1] + r4.z * cb[2] + r4.w * cb[3];
+        // dE/dR = a + q + dscale (R . b) e_0
+        const float bd = (r4.x * cb[0] + r4.y * cb[1] + r4.z * cb[2] + r4.w * cb[3]) * dscale;
         *(float4 *)(gRs + 4 * (slot0 + n)) = make_float4(ca[0] + q0 + bd, ca[1] + q1, ca[2] + q2, ca[3] + q3);
       }
       // positions and cell codes of this chunk's neighbours (jc arrived during the tile)
@@ -1028,7 +1034,7 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
         if (qq < cnt) {
           const float4 gr = *(const float4 *)(gRs + 4 * lane);
           double gx, gy, gz;
-          pair_force(pair_disp(xi, pjc, a.L[0], a.L[1], a.L[2]), gr, rc, rcs, inv_w, gx, gy, gz, fi0, fi1, fi2, vir);
+          pair_force(pair_disp_sq(xi, pjc, a.L[0], a.L[1], a.L[2]), gr, rc, rcs, inv_w, gx, gy, gz, fi0, fi1, fi2, vir);
           if (a.net_deriv) {
             double *nd = a.net_deriv + (base + qq) * 4;
             nd[0] = gr.x; nd[1] = gr.y; nd[2] = gr.z; nd[3] = gr.w;
@@ -1483,20 +1489,25 @@ void launch_smax(hipStream_t s, int64_t n, const Dims &d, const int32_t *nreal, 
 constexpr size_t CELL_LDS_MAX = 160 * 1024;  // LDS of one CU
 
 template <int W1, int W2, int W3, int LIN>
-static bool cells_config_t(int nnets, int cap, size_t tab, int *threads, size_t *lds) {
+static bool cells_config_t(int nnets, int want, int need, size_t tab, int *cap, int *threads, size_t *lds) {
   if constexpr (LIN == 0 || Shape<W1, W2, W3>::XL2) {
     return false;
   } else {
-    const size_t fixed =
-        (size_t)nnets * LinShape<W1, W2, W3>::NET_BYTES + tab + (size_t)27 * 3 * cap * sizeof(double);
+    // the most waves whose scratch leaves room for an accumulator of at
+    // least `need` atoms per cell; the accumulator then takes what is left,
+    // up to `want`
+    const size_t fixed = (size_t)nnets * LinShape<W1, W2, W3>::NET_BYTES + tab;
     const size_t budget = CELL_LDS_MAX - sizeof(double) * CELL_WAVES * 9;
+    const size_t per_atom = (size_t)27 * 3 * sizeof(double);
     for (int nw = CELL_WAVES; nw >= 4; nw -= 4) {
       const size_t b = fixed + (size_t)nw * CellShape<W1, W2, W3>::W_BYTES;
-      if (b <= budget) {
-        *threads = 64 * nw;
-        *lds = b;
-        return true;
-      }
+      if (b >= budget) continue;
+      const int fit = (int)std::min<size_t>((budget - b) / per_atom, 255);
+      if (fit < need) continue;
+      *cap = std::min(want, fit);
+      *threads = 64 * nw;
+      *lds = b + (size_t)*cap * per_atom;
+      return true;
     }
     return false;
   }
@@ -1511,13 +1522,13 @@ static void launch_cells_t(hipStream_t s, const MixArgs &a, const CellArgs &ca, 
   }
 }
 
-bool embed_cells_config(const MixArgs &a, int cap, int *threads, size_t *lds) {
-  if (cap < 1 || cap > 255) return false;
+bool embed_cells_config(const MixArgs &a, int want, int need, int *cap, int *threads, size_t *lds) {
+  if (need < 1 || want < need || want > 255) return false;
   const int nnets = a.d.ntypes * a.d.ntypes;
   int id = 0;
   const size_t tab = a.tab ? (size_t)nnets * TAB_BYTES : 0;
 #define X(a_, b_, c_, l_)                                                         \
-  if (a.shape == id) return cells_config_t<a_, b_, c_, l_>(nnets, cap, tab, threads, lds); \
+  if (a.shape == id) return cells_config_t<a_, b_, c_, l_>(nnets, want, need, tab, cap, threads, lds); \
   ++id;
   DPK_MIX_SHAPES(X)
 #undef X

@@ -536,7 +536,7 @@ __global__ void __launch_bounds__(256) k_wide_bwd(WideArgs a) {
           nd[3] = mine.w;
         }
         double gx, gy, gz;
-        pair_force(pair_disp(xi, a.xw[j], a.L[0], a.L[1], a.L[2]), mine, rc, rcs, inv_w, gx, gy, gz, fi0, fi1, fi2,
+        pair_force(pair_disp_sq(xi, a.xw[j], a.L[0], a.L[1], a.L[2]), mine, rc, rcs, inv_w, gx, gy, gz, fi0, fi1, fi2,
                    vir);
         unsafeAtomicAdd(a.force + 3 * (int64_t)j + 0, -gx);
         unsafeAtomicAdd(a.force + 3 * (int64_t)j + 1, -gy);
