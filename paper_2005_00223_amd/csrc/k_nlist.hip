@@ -10,6 +10,8 @@
 // before sorting.  Here the same lexicographic order is bit-packed:
 // type in bits 58..63, floor(r 1e8) in bits 26..57, j in bits 0..25, which
 // bounds rc < 42.9 A and n < 2^26 (checked by the host).
+#include <cmath>
+
 #include "dp_internal.h"
 
 namespace dpk {
@@ -327,29 +329,40 @@ constexpr int FMT_WAVES = 4;
 constexpr int FMT_CAP = KEY_CAP;
 constexpr int FMT_NB = 64;   // distance buckets per type
 
-// bucket of a key with type t and quantised distance qd < qlim; monotone
-// non-decreasing in (t, qd) (every step is), the same expression at insertion
-// and at ranking
-__device__ inline int fmt_bucket(int t, unsigned long long qd, unsigned long long qlim) {
-  const float x = (float)qd / (float)qlim;
+// bucket of a key with type t and quantised distance qd < qlim (inv_qlim =
+// 1 / qlim in FP32); monotone non-decreasing in (t, qd) (every step is), the
+// same expression at insertion and at ranking
+__device__ inline int fmt_bucket(int t, unsigned long long qd, float inv_qlim) {
+  const float x = (float)qd * inv_qlim;
   const int b = (int)(x * x * x * (float)FMT_NB);
   return t * FMT_NB + (b < FMT_NB - 1 ? b : FMT_NB - 1);
 }
 constexpr int FMT_BATCH = 4; // candidate gathers in flight per lane
 
+// per-wave LDS of the format kernel: keys (staged r^2 first) [FMT_CAP] u64,
+// neighbour and type [FMT_CAP] i32, bucket heads and starts [nb] i32 each,
+// list links [FMT_CAP] i16
+__host__ __device__ inline size_t fmt_wave_bytes(int nb) {
+  return (size_t)FMT_CAP * 8 + (size_t)FMT_CAP * 4 + (size_t)nb * 8 + (size_t)FMT_CAP * 2;
+}
+
 __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__restrict__ xw, Dims d, double L0,
-                                                double L1, double L2, const int32_t *__restrict__ cand,
+                                                double L1, double L2, double rc2max,
+                                                const int32_t *__restrict__ cand,
                                                 const int32_t *__restrict__ cand_n, int cap,
                                                 int32_t *__restrict__ nlist, int32_t *__restrict__ nreal,
                                                 unsigned long long *overflow, int32_t *max_real, uint32_t *flags) {
-  __shared__ unsigned long long keys[FMT_WAVES][FMT_CAP];
-  __shared__ int16_t next[FMT_WAVES][FMT_CAP];
-  __shared__ int32_t head[FMT_WAVES][MAXT * FMT_NB];
-  __shared__ int32_t bstart[FMT_WAVES][MAXT * FMT_NB];
+  extern __shared__ __align__(16) unsigned char fmt_lds[];
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int64_t i = (int64_t)blockIdx.x * FMT_WAVES + wv;
   if (i >= n) return;
   const int nb_tot = d.ntypes * FMT_NB;
+  unsigned char *wb = fmt_lds + (size_t)wv * fmt_wave_bytes(nb_tot);
+  unsigned long long *keys = (unsigned long long *)wb;
+  int32_t *jt = (int32_t *)(wb + (size_t)FMT_CAP * 8);
+  int32_t *head = jt + FMT_CAP;
+  int32_t *bstart = head + nb_tot;
+  int16_t *next = (int16_t *)(bstart + nb_tot);
   const unsigned long long below = (1ull << lane) - 1ull;
   // keys stored and neighbours within rc per type, wave-uniform: ballot
   // prefix counts instead of atomics on one LDS address
@@ -358,16 +371,17 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
 #pragma unroll
   for (int t = 0; t < MAXT; ++t) tc[t] = 0;
   for (int b = lane; b < nb_tot; b += 64) {
-    head[wv][b] = -1;
-    bstart[wv][b] = 0;
+    head[b] = -1;
+    bstart[b] = 0;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const unsigned long long qlim = (unsigned long long)floor(d.rcut * 1e8) + 1ull;
+  const float inv_qlim = 1.0f / (float)qlim;
   double4 p = xw[i];
   int nc = cand_n[i];
   const int32_t *ci = cand + i * (int64_t)cap;
+  // pass 1: distances of all candidates; those within rc (r^2 <= rc2max,
+  // the largest double whose square root is <= rc, so the same test as
+  // sqrt(r^2) <= rc) are staged compactly, r^2 in their key slot
   for (int q0 = 0; q0 < nc; q0 += 64 * FMT_BATCH) {
     // issue the index loads, then the position gathers, of FMT_BATCH rounds
     // unconditional loads (lanes past the list reread its last entry and
@@ -396,8 +410,7 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
       double dz = min_image(pj.z - p.z, L2);
       double r2 = dx * dx + dy * dy;
       r2 = r2 + dz * dz;
-      double r = sqrt(r2);
-      const bool keep = j >= 0 && r <= d.rcut;
+      const bool keep = j >= 0 && r2 <= rc2max;
       const unsigned long long m = __ballot(keep);
       if (m == 0ull) continue;
       const int tj = (int)pj.w;
@@ -407,12 +420,8 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
       for (int t = 0; t < MAXT; ++t)
         if (t < d.ntypes) tc[t] += __popcll(__ballot(keep && tj == t));
       if (keep && slot < FMT_CAP) {
-        unsigned long long qd = (unsigned long long)floor(r * 1e8);
-        unsigned long long key = ((unsigned long long)tj << 58) | (qd << 26) | (unsigned long long)j;
-        keys[wv][slot] = key;
-        const int b = fmt_bucket(tj, qd, qlim);
-        next[wv][slot] = (int16_t)atomicExch(&head[wv][b], slot);
-        atomicAdd(&bstart[wv][b], 1);
+        keys[slot] = (unsigned long long)__double_as_longlong(r2);
+        jt[slot] = j | (tj << 26);
       }
     }
   }
@@ -424,12 +433,27 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
     if (lane == 0) atomicOr(flags, FLAG_KEY_CAP);
     k = FMT_CAP;
   }
+  // pass 2, dense over the lanes: r, the key (type, floor(r 1e8), index)
+  // and its bucket's linked list
+  for (int q = lane; q < k; q += 64) {
+    const double r = sqrt(__longlong_as_double((long long)keys[q]));
+    const int32_t v = jt[q];
+    const unsigned long long tj = (unsigned long long)(v >> 26), j = (unsigned long long)(v & ((1 << 26) - 1));
+    const unsigned long long qd = (unsigned long long)floor(r * 1e8);
+    keys[q] = (tj << 58) | (qd << 26) | j;
+    const int b = fmt_bucket((int)tj, qd, inv_qlim);
+    next[q] = (int16_t)atomicExch(&head[b], q);
+    atomicAdd(&bstart[b], 1);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   // exclusive scan of the bucket histogram: lane takes a run of buckets
   {
     const int per = (nb_tot + 63) / 64;
     const int b0 = lane * per;
     int run = 0;
-    for (int b = b0; b < b0 + per && b < nb_tot; ++b) run += bstart[wv][b];
+    for (int b = b0; b < b0 + per && b < nb_tot; ++b) run += bstart[b];
     int incl = run;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -438,8 +462,8 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
     }
     int acc = incl - run;
     for (int b = b0; b < b0 + per && b < nb_tot; ++b) {
-      const int c = bstart[wv][b];
-      bstart[wv][b] = acc;
+      const int c = bstart[b];
+      bstart[b] = acc;
       acc += c;
     }
   }
@@ -460,11 +484,11 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
   int32_t *row = nlist + i * (int64_t)d.nnei;
   // exact rank of each key (keys are distinct)
   for (int q = lane; q < k; q += 64) {
-    const unsigned long long key = keys[wv][q];
+    const unsigned long long key = keys[q];
     const int t = (int)(key >> 58);
-    const int b = fmt_bucket(t, (key >> 26) & 0xffffffffull, qlim);
-    int rank = bstart[wv][b];
-    for (int m = head[wv][b]; m >= 0; m = next[wv][m]) rank += (keys[wv][m] < key) ? 1 : 0;
+    const int b = fmt_bucket(t, (key >> 26) & 0xffffffffull, inv_qlim);
+    int rank = bstart[b];
+    for (int m = head[b]; m >= 0; m = next[m]) rank += (keys[m] < key) ? 1 : 0;
     int ts = 0;
 #pragma unroll
     for (int u = 0; u < MAXT; ++u)
@@ -497,8 +521,14 @@ void launch_format(hipStream_t s, int64_t n, const double4 *xw, const Dims &d, c
                    const int32_t *cand_n, int cand_cap, int32_t *nlist, int32_t *nreal, unsigned long long *overflow,
                    int32_t *max_real, uint32_t *flags) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_format, dim3((unsigned)((n + FMT_WAVES - 1) / FMT_WAVES)), dim3(64 * FMT_WAVES), 0, s, n, xw, d,
-                     L[0], L[1], L[2], cand, cand_n, cand_cap, nlist, nreal, overflow, max_real, flags);
+  // the largest double x with sqrt(x) <= rc (sqrt is correctly rounded and
+  // monotone, so r^2 <= x exactly when sqrt(r^2) <= rc)
+  double x = d.rcut * d.rcut;
+  while (std::sqrt(x) > d.rcut) x = std::nextafter(x, 0.0);
+  while (std::sqrt(std::nextafter(x, HUGE_VAL)) <= d.rcut) x = std::nextafter(x, HUGE_VAL);
+  const size_t lds = FMT_WAVES * fmt_wave_bytes(d.ntypes * FMT_NB);
+  hipLaunchKernelGGL(k_format, dim3((unsigned)((n + FMT_WAVES - 1) / FMT_WAVES)), dim3(64 * FMT_WAVES), lds, s, n, xw,
+                     d, L[0], L[1], L[2], x, cand, cand_n, cand_cap, nlist, nreal, overflow, max_real, flags);
 }
 
 // -1 in every slot past a type's real count
