@@ -139,6 +139,47 @@ __device__ inline double4 pair_disp_sq(const double4 &pi, const double4 &pj, dou
   else if (dz < -0.5 * L2) dz += L2;
   return make_double4(dx, dy, dz, dx * dx + dy * dy + dz * dz);
 }
+// tanh in FP64 to a few ulp, about a fifth of the instructions of the
+// library routine (which carries double-double intermediates):
+//   tanh|x| = -m / (2 + m),  m = expm1(-2|x|) in (-1, 0],
+// expm1 by Cody and Waite's argument reduction z = k ln2 + r (|r| <= ln2/2,
+// ln2 as a double plus its remainder) and the Taylor series of expm1(r) to
+// r^13 (remainder below 2^-56 relative), expm1(z) = 2^k expm1(r) + (2^k - 1);
+// the quotient by a Newton-refined hardware reciprocal with one residual
+// correction.  |x| is capped at 20, where tanh rounds to 1; NaN stays NaN.
+__device__ inline double tanh64(double x) {
+  double a = fabs(x);
+  a = a > 20.0 ? 20.0 : a;
+  const double z = -2.0 * a;
+  const double kd = rint(z * 1.4426950408889634);  // z / ln2
+  double r = fma(-kd, 0.6931471805599453, z);
+  r = fma(-kd, 2.3190468138462996e-17, r);
+  double q = 1.0 / 6227020800.0;  // 1/13!
+  q = fma(q, r, 1.0 / 479001600.0);
+  q = fma(q, r, 1.0 / 39916800.0);
+  q = fma(q, r, 1.0 / 3628800.0);
+  q = fma(q, r, 1.0 / 362880.0);
+  q = fma(q, r, 1.0 / 40320.0);
+  q = fma(q, r, 1.0 / 5040.0);
+  q = fma(q, r, 1.0 / 720.0);
+  q = fma(q, r, 1.0 / 120.0);
+  q = fma(q, r, 1.0 / 24.0);
+  q = fma(q, r, 1.0 / 6.0);
+  q = fma(q, r, 0.5);
+  q = fma(q, r, 1.0);
+  const double p = q * r;  // expm1(r)
+  const double sk = ldexp(1.0, (int)kd);
+  const double m = fma(sk, p, sk - 1.0);
+  const double den = 2.0 + m, num = -m;
+  double y = __builtin_amdgcn_rcp(den);
+  double e = fma(-den, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-den, y, 1.0);
+  y = fma(y, e, y);
+  double t = num * y;
+  t = fma(fma(-den, t, num), y, t);
+  return copysign(t, x);
+}
 // 1/sqrt(x) for normal x > 0: the hardware estimate (relative error below
 // 2^-22) and two Newton steps y += y (1 - x y^2) / 2, each squaring the
 // relative error, which leaves a few ulp of FP64

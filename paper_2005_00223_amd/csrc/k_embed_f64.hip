@@ -197,7 +197,7 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
             const double s = Rl[n * 4];
             double h = 0.0;
             if (f < out1) {
-              h = tanh(s * W0[f] + b0[f]);
+              h = tanh64(s * W0[f] + b0[f]);
               if (out1 == 1 || out1 == 2) h += s;
             }
             H[f * 16 + n] = h;
@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
                   double h = 0.0;
                   if (f < out) {
                     const double z = acc[0][mt][r] + bias[f];
-                    h = (d.emb_lin && l == d.n_emb - 1) ? z : tanh(z);
+                    h = (d.emb_lin && l == d.n_emb - 1) ? z : tanh64(z);
                     const int sf = skip_src(f, in, out);
                     if (sf >= 0) h += Hin[sf * 16 + n];
                   }
@@ -378,7 +378,7 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_bwd_f64(EmbedArgs a, E
             const double s = Rl[n * 4];
             double h = 0.0, hd = 0.0;
             if (f < out1) {
-              const double th = tanh(s * W0[f] + b0[f]);
+              const double th = tanh64(s * W0[f] + b0[f]);
               h = th;
               hd = (1.0 - th * th) * W0[f];
               if (out1 == 1 || out1 == 2) {
@@ -413,7 +413,7 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_bwd_f64(EmbedArgs a, E
                 if (f < out) {
                   const double z = acc[0][mt][r] + bias[f];
                   const bool lin = d.emb_lin && last;
-                  const double th = lin ? z : tanh(z);
+                  const double th = lin ? z : tanh64(z);
                   h = th;
                   hd = lin ? acc[1][mt][r] : (1.0 - th * th) * acc[1][mt][r];
                   const int sf = skip_src(f, in, out);

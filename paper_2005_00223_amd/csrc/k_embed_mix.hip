@@ -1437,7 +1437,7 @@ __global__ void k_student_table(Dims d, EmbOffsets eo, const double *__restrict_
   double z = (double)(float)bl[f], dz = 0.0, hs = 0.0, dhs = 0.0;
   for (int i = 0; i < W1; ++i) {
     const double w = (double)(float)W0[i], b = (double)(float)b0[i];
-    const double h = tanh(sv * w + b), dh = (1.0 - h * h) * w;
+    const double h = tanh64(sv * w + b), dh = (1.0 - h * h) * w;
     const double wq = round16_dev(Wl[(size_t)i * mp + f], prec);
     z += wq * h;
     dz += wq * dh;
@@ -1446,7 +1446,7 @@ __global__ void k_student_table(Dims d, EmbOffsets eo, const double *__restrict_
       dhs = dh;
     }
   }
-  const double th = tanh(z);
+  const double th = tanh64(z);
   double y = th, dy = (1.0 - th * th) * dz;
   if (W2 == W1 || W2 == 2 * W1) {  // identity / doubling skip
     y += hs;

@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(256) k_fit_gemm(GemmArgs g) {
         if (col >= g.N) continue;
         const double c = acc[mi][ni][r];
         if (MODE == FIT_FWD) {
-          const double th = tanh(c + bias[col]);
+          const double th = tanh64(c + bias[col]);
           double y = th;
           if (g.out == g.in) y += g.X[row * g.in + col];
           else if (g.out == 2 * g.in) y += g.X[row * g.in + (col >= g.in ? col - g.in : col)];

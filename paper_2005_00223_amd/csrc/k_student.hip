@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(256) k_st_teacher(StTeacherArgs a) {
     const bool lin = d.emb_lin && d.n_emb == 1;
     for (int o = j; o < out; o += 16) {
       const double z = s * W0[o] + b0[o];
-      double h = lin ? z : tanh(z);
+      double h = lin ? z : tanh64(z);
       if (out <= 2) h += s;  // identity / doubling skip of the scalar input
       hA[o] = h;
     }
@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(256) k_st_teacher(StTeacherArgs a) {
     for (int o = j; o < out; o += 16) {
       double z = b[o];
       for (int i = 0; i < in; ++i) z += hA[i] * W[(size_t)i * mp + o];
-      double h = lin ? z : tanh(z);
+      double h = lin ? z : tanh64(z);
       if (out == in) h += hA[o];
       else if (out == 2 * in) h += hA[o % in];
       hB[o] = h;
@@ -329,13 +329,13 @@ __device__ inline void st_hidden_f64(const float *P, const StudentLayout &L, int
                                      double (&h2)[SH2]) {
   double t1[SH1];
 #pragma unroll
-  for (int i = 0; i < SH1; ++i) t1[i] = tanh(s * (double)P[L.o_w1 + i] + (double)P[L.o_b1 + i]);
+  for (int i = 0; i < SH1; ++i) t1[i] = tanh64(s * (double)P[L.o_w1 + i] + (double)P[L.o_b1 + i]);
 #pragma unroll
   for (int j = 0; j < SH2; ++j) {
     double z = (double)P[L.o_b2 + j];
 #pragma unroll
     for (int i = 0; i < SH1; ++i) z += t1[i] * st_round16(P[L.o_w2 + i * SH2 + j], quant);
-    h2[j] = t1[j % SH1] + tanh(z);
+    h2[j] = t1[j % SH1] + tanh64(z);
   }
 }
 
