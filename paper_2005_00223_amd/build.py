@@ -36,7 +36,7 @@ def hipcc():
 def _flags(src):
     f = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fno-gpu-rdc",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+         "-munsafe-fp-atomics", "-mllvm", "-amdgpu-mfma-vgpr-form", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
          "-I", INCLUDE, "-I", CSRC]
     if src in EXACT_FP:
         f.append("-ffp-contract=off")

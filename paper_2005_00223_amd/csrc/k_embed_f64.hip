@@ -29,7 +29,7 @@ namespace dpk {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int EMB_WAVES = 2;
-constexpr int MAXMT = 8;  // output features per layer <= 128
+constexpr int EMB_G = 4;  // output tiles per MFMA group
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -44,96 +44,100 @@ __device__ inline v4d mfma64(double a, double b, v4d c) {
 struct EmbLds {
   int rows[2];  // rows of the two ping-pong activation buffers
   int cols;     // 16 (forward) or 32 (tangent pass)
-  int off_buf[2], off_rt, off_t, per_wave;  // offsets in doubles
+  int off_buf[2], off_rt, off_t, off_g, per_wave;  // offsets in doubles
 };
 
+// per-wave LDS (doubles): the ping-pong activation buffers [feature][cols]
+// of the hidden layers (the last layer's output is not stored: the forward
+// stages one 16 x 16 tile of G at a time for T += G R), the tile's R rows
+// [16][4], T (forward: the unscaled sum; backward: dT) [M1 padded][4], and
+// the G tile [16][16] (forward)
 static EmbLds emb_lds_layout(const Dims &d, int pass) {
   EmbLds L{};
   L.cols = pass == 1 ? 16 : 32;
-  for (int l = 0; l < d.n_emb; ++l) {
-    int r = (l == d.n_emb - 1) ? (pass == 1 ? d.emp[d.n_emb] : 0) : d.ekp[l + 1];
+  for (int l = 0; l < d.n_emb - 1; ++l) {
+    const int r = d.ekp[l + 1];
     if (r > L.rows[l & 1]) L.rows[l & 1] = r;
   }
   L.off_buf[0] = 0;
   L.off_buf[1] = L.rows[0] * L.cols;
   L.off_rt = L.off_buf[1] + L.rows[1] * L.cols;
   L.off_t = L.off_rt + 64;
-  L.per_wave = L.off_t + d.emp[d.n_emb] * 4;
+  L.off_g = L.off_t + d.emp[d.n_emb] * 4;
+  L.per_wave = L.off_g + (pass == 1 ? 256 : 0);
   return L;
 }
 
-// One MFMA layer: acc[ct][mt] = (W^T H^T) for column tile ct, output tile mt.
-// Shapes known at compile time (KP = padded inputs, MP = padded outputs):
-// every weight load is unconditional and the next k-step's loads are in
-// flight during this k-step's products.
+// Output tiles mt0 .. mt0 + EMB_G - 1 of one layer, acc[ct][g] = (W^T H^T)
+// for column tile ct and output tile mt0 + g (a tile past the layer's last
+// reads the last tile's weights; the caller discards it).  The B operand
+// (activations, LDS) of a k-step feeds EMB_G tiles; every weight load is
+// unconditional.  Weights stream from L2 in their padded [K][M] layout.
+// KP > 0: the layer's shape is known at compile time, the k-loop is
+// unrolled and each k-step's weights are loaded one k-step ahead.
 template <int NCT, int KP, int MP>
-__device__ inline void mfma_layer_t(const double *__restrict__ W, const double *Hin, int cols, int lane,
-                                    v4d (&acc)[NCT][MAXMT]) {
-  constexpr int NMT = MP / 16;
-  static_assert(NMT <= MAXMT && KP % 4 == 0, "layer shape");
-#pragma unroll
-  for (int ct = 0; ct < NCT; ++ct)
-#pragma unroll
-    for (int mt = 0; mt < MAXMT; ++mt) acc[ct][mt] = v4d{0.0, 0.0, 0.0, 0.0};
-  const double *wr = W + (size_t)(lane >> 4) * MP + (lane & 15);
-  double an[NMT];
-#pragma unroll
-  for (int mt = 0; mt < NMT; ++mt) an[mt] = wr[mt * 16];
-#pragma unroll
-  for (int kk = 0; kk < KP; kk += 4) {
-    double ac[NMT];
-#pragma unroll
-    for (int mt = 0; mt < NMT; ++mt) ac[mt] = an[mt];
-    if (kk + 4 < KP)
-#pragma unroll
-      for (int mt = 0; mt < NMT; ++mt) an[mt] = wr[(size_t)(kk + 4) * MP + mt * 16];
-    const int krow = kk + (lane >> 4);
-    double bv[NCT];
-#pragma unroll
-    for (int ct = 0; ct < NCT; ++ct) bv[ct] = Hin[krow * cols + ct * 16 + (lane & 15)];
-#pragma unroll
-    for (int mt = 0; mt < NMT; ++mt)
-#pragma unroll
-      for (int ct = 0; ct < NCT; ++ct) acc[ct][mt] = mfma64(ac[mt], bv[ct], acc[ct][mt]);
+__device__ inline void mfma_group_t(const double *__restrict__ W, int kp, int mp, const double *Hin, int cols,
+                                    int lane, int mt0, v4d (&acc)[NCT][EMB_G]) {
+  if constexpr (KP > 0) {
+    kp = KP;
+    mp = MP;
   }
-}
-
-// Any shape (widths up to 128): the generic loop.
-template <int NCT>
-__device__ inline void mfma_layer_any(const double *__restrict__ W, int kp, int mp, const double *Hin, int cols,
-                                      int lane, v4d (&acc)[NCT][MAXMT]) {
   const int nmt = mp >> 4;
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
-    for (int mt = 0; mt < MAXMT; ++mt) acc[ct][mt] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int kk = 0; kk < kp; kk += 4) {
-    const int krow = kk + (lane >> 4);
-    double bv[NCT];
+    for (int g = 0; g < EMB_G; ++g) acc[ct][g] = v4d{0.0, 0.0, 0.0, 0.0};
+  const double *wr = W + (size_t)(lane >> 4) * mp + (lane & 15);
+  const double *hr = Hin + (lane >> 4) * cols + (lane & 15);
+  int col[EMB_G];
 #pragma unroll
-    for (int ct = 0; ct < NCT; ++ct) bv[ct] = Hin[krow * cols + ct * 16 + (lane & 15)];
-    const double *wr = W + (size_t)krow * mp + (lane & 15);
+  for (int g = 0; g < EMB_G; ++g) col[g] = 16 * (mt0 + g < nmt ? mt0 + g : nmt - 1);
+  if constexpr (KP > 0) {
+    double an[EMB_G];
 #pragma unroll
-    for (int mt = 0; mt < MAXMT; ++mt) {
-      if (mt < nmt) {
-        double a = wr[mt * 16];
+    for (int g = 0; g < EMB_G; ++g) an[g] = wr[col[g]];
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) acc[ct][mt] = mfma64(a, bv[ct], acc[ct][mt]);
-      }
+    for (int kk = 0; kk < KP; kk += 4) {
+      double ac[EMB_G];
+#pragma unroll
+      for (int g = 0; g < EMB_G; ++g) ac[g] = an[g];
+      if (kk + 4 < KP)
+#pragma unroll
+        for (int g = 0; g < EMB_G; ++g) an[g] = wr[(size_t)(kk + 4) * MP + col[g]];
+      double bv[NCT];
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) bv[ct] = hr[kk * cols + ct * 16];
+#pragma unroll
+      for (int g = 0; g < EMB_G; ++g)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) acc[ct][g] = mfma64(ac[g], bv[ct], acc[ct][g]);
+    }
+  } else {
+    for (int kk = 0; kk < kp; kk += 4) {
+      double ac[EMB_G];
+#pragma unroll
+      for (int g = 0; g < EMB_G; ++g) ac[g] = wr[(size_t)kk * mp + col[g]];
+      double bv[NCT];
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) bv[ct] = hr[kk * cols + ct * 16];
+#pragma unroll
+      for (int g = 0; g < EMB_G; ++g)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) acc[ct][g] = mfma64(ac[g], bv[ct], acc[ct][g]);
     }
   }
 }
 
-// The layer shapes of the 1-25-50-100 and 1-16-32-100 nets run the
+// The layer shapes of the 1-25-50-100 and 1-16-32-100 nets take the
 // compile-time loop, others the generic one (the branch is wave-uniform).
 template <int NCT>
-__device__ inline void mfma_layer(const double *__restrict__ W, int kp, int mp, const double *Hin, int cols, int lane,
-                                  v4d (&acc)[NCT][MAXMT]) {
-  if (kp == 28 && mp == 64) mfma_layer_t<NCT, 28, 64>(W, Hin, cols, lane, acc);
-  else if (kp == 52 && mp == 112) mfma_layer_t<NCT, 52, 112>(W, Hin, cols, lane, acc);
-  else if (kp == 16 && mp == 32) mfma_layer_t<NCT, 16, 32>(W, Hin, cols, lane, acc);
-  else if (kp == 32 && mp == 112) mfma_layer_t<NCT, 32, 112>(W, Hin, cols, lane, acc);
-  else mfma_layer_any<NCT>(W, kp, mp, Hin, cols, lane, acc);
+__device__ inline void mfma_group(const double *__restrict__ W, int kp, int mp, const double *Hin, int cols, int lane,
+                                  int mt0, v4d (&acc)[NCT][EMB_G]) {
+  if (kp == 28 && mp == 64) mfma_group_t<NCT, 28, 64>(W, kp, mp, Hin, cols, lane, mt0, acc);
+  else if (kp == 52 && mp == 112) mfma_group_t<NCT, 52, 112>(W, kp, mp, Hin, cols, lane, mt0, acc);
+  else if (kp == 16 && mp == 32) mfma_group_t<NCT, 16, 32>(W, kp, mp, Hin, cols, lane, mt0, acc);
+  else if (kp == 32 && mp == 112) mfma_group_t<NCT, 32, 112>(W, kp, mp, Hin, cols, lane, mt0, acc);
+  else mfma_group_t<NCT, 0, 0>(W, kp, mp, Hin, cols, lane, mt0, acc);
 }
 
 __device__ inline int skip_src(int f, int in, int out) {
@@ -154,11 +158,13 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
   double *lds = smem + wv * L.per_wave;
   double *Rl = lds + L.off_rt;
   double *Tl = lds + L.off_t;
+  double *Gt = lds + L.off_g;
   const int64_t nwaves = (int64_t)gridDim.x * EMB_WAVES;
   const int64_t gw = (int64_t)blockIdx.x * EMB_WAVES + wv;
   const int64_t chunk = (a.rows + nwaves - 1) / nwaves;
   const int64_t p_end = (gw + 1) * chunk < a.rows ? (gw + 1) * chunk : a.rows;
   const int nmtG = d.emp[d.n_emb] >> 4;
+  const int M1p = d.emp[d.n_emb];
   const int MM = d.M1 * d.M2;
 
   for (int64_t p = gw * chunk; p < p_end; ++p) {
@@ -169,9 +175,8 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
       continue;
     }
     const int t = (int)a.xw[i].w;
-    v4d Tacc[MAXMT];
-#pragma unroll
-    for (int mt = 0; mt < MAXMT; ++mt) Tacc[mt] = v4d{0.0, 0.0, 0.0, 0.0};
+    // T accumulates in LDS (unscaled): lane (g, c) owns T[f][c] for its rows f
+    for (int o = lane; o < M1p * 4; o += 64) Tl[o] = 0.0;
 
     for (int u = 0; u < d.ntypes; ++u) {
       const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
@@ -180,7 +185,9 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
       const double *b0 = a.ew + a.eo.b[t][u][0];
       for (int n0 = 0; n0 < cnt; n0 += 16) {
         if (lane < 16) {
-          double4 r4 = (n0 + lane < cnt) ? a.rt[base + n0 + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
+          // unconditional load: slots past the block reread its last row, then are zeroed
+          double4 r4 = a.rt[base + (n0 + lane < cnt ? n0 + lane : cnt - 1)];
+          if (n0 + lane >= cnt) r4 = make_double4(0.0, 0.0, 0.0, 0.0);
           Rl[lane * 4 + 0] = r4.x;
           Rl[lane * 4 + 1] = r4.y;
           Rl[lane * 4 + 2] = r4.z;
@@ -190,7 +197,7 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
         // layer 0: 1 -> ew[1] on VALU
         {
           const int out1 = d.ew[1];
-          const int rows = (d.n_emb == 1) ? d.emp[1] : d.ekp[1];
+          const int rows = d.ekp[1];
           double *H = lds + L.off_buf[0];
           for (int idx = lane; idx < rows * 16; idx += 64) {
             const int f = idx >> 4, n = idx & 15;
@@ -204,69 +211,71 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
           }
         }
         wave_sync();
-        // layers 1 .. n_emb-1 on MFMA
+        // layers 1 .. n_emb-1 on MFMA, EMB_G output tiles at a time; the last
+        // layer's tiles go one at a time through Gt into T += G R (K = the
+        // 16 neighbours of the tile)
         for (int l = 1; l < d.n_emb; ++l) {
           const int in = d.ew[l], out = d.ew[l + 1];
+          const bool last = l == d.n_emb - 1;
           const double *Hin = lds + L.off_buf[(l - 1) & 1];
           double *Hout = lds + L.off_buf[l & 1];
-          const int rows_out = (l == d.n_emb - 1) ? d.emp[l + 1] : d.ekp[l + 1];
+          const int rows_out = last ? 0 : d.ekp[l + 1];
           const double *W = a.ew + a.eo.w[t][u][l];
           const double *bias = a.ew + a.eo.b[t][u][l];
-          v4d acc[1][MAXMT];
-          mfma_layer<1>(W, d.ekp[l], d.emp[l + 1], Hin, 16, lane, acc);
           const int nmt = d.emp[l + 1] >> 4;
+          for (int mt0 = 0; mt0 < nmt; mt0 += EMB_G) {
+            v4d acc[1][EMB_G];
+            mfma_group<1>(W, d.ekp[l], d.emp[l + 1], Hin, 16, lane, mt0, acc);
 #pragma unroll
-          for (int mt = 0; mt < MAXMT; ++mt) {
-            if (mt < nmt) {
+            for (int g = 0; g < EMB_G; ++g) {
+              const int mt = mt0 + g;
+              if (mt < nmt) {
 #pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const int f = mt * 16 + 4 * r + (lane >> 4), n = lane & 15;
-                if (f < rows_out) {
+                for (int r = 0; r < 4; ++r) {
+                  const int f = mt * 16 + 4 * r + (lane >> 4), n = lane & 15;
                   double h = 0.0;
                   if (f < out) {
-                    const double z = acc[0][mt][r] + bias[f];
-                    h = (d.emb_lin && l == d.n_emb - 1) ? z : tanh64(z);
+                    const double z = acc[0][g][r] + bias[f];
+                    h = (d.emb_lin && last) ? z : tanh64(z);
                     const int sf = skip_src(f, in, out);
                     if (sf >= 0) h += Hin[sf * 16 + n];
                   }
-                  Hout[f * 16 + n] = h;
+                  if (last) Gt[(4 * r + (lane >> 4)) * 16 + n] = h;
+                  else if (f < rows_out) Hout[f * 16 + n] = h;
+                }
+                if (last) {
+                  wave_sync();
+                  // register r of lane (g, c) holds T[16 mt + 4 r + g][c]
+                  const int comp = lane & 15;
+                  double *Tr = Tl + (mt * 16 + (lane >> 4)) * 4 + comp;
+                  v4d tacc;
+#pragma unroll
+                  for (int r = 0; r < 4; ++r) tacc[r] = comp < 4 ? Tr[16 * r] : 0.0;
+#pragma unroll
+                  for (int kn = 0; kn < 4; ++kn) {
+                    const int nb = kn * 4 + (lane >> 4);
+                    const double bv = comp < 4 ? Rl[nb * 4 + comp] : 0.0;
+                    tacc = mfma64(Gt[(lane & 15) * 16 + nb], bv, tacc);
+                  }
+                  if (comp < 4)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Tr[16 * r] = tacc[r];
+                  wave_sync();
                 }
               }
             }
           }
           wave_sync();
         }
-        // T += G R (K = the 16 neighbours of the tile)
-        const double *G = lds + L.off_buf[(d.n_emb - 1) & 1];
-#pragma unroll
-        for (int kn = 0; kn < 4; ++kn) {
-          const int nb = kn * 4 + (lane >> 4);
-          const int comp = lane & 15;
-          const double bv = comp < 4 ? Rl[nb * 4 + comp] : 0.0;
-#pragma unroll
-          for (int mt = 0; mt < MAXMT; ++mt)
-            if (mt < nmtG) Tacc[mt] = mfma64(G[(mt * 16 + (lane & 15)) * 16 + nb], bv, Tacc[mt]);
-        }
-        wave_sync();
       }
     }
-    // T = Tacc / Nc -> global and LDS; lane holds T[mt*16 + 4r + l/16][l%16]
+    // T = sum / Nc -> global and LDS
     {
-      const int comp = lane & 15;
       double *Tg = a.T + (int64_t)i * d.M1 * 4;
-#pragma unroll
-      for (int mt = 0; mt < MAXMT; ++mt) {
-        if (mt < nmtG) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int f = mt * 16 + 4 * r + (lane >> 4);
-            const double v = Tacc[mt][r] * d.inv_nc;
-            if (comp < 4) {
-              Tl[f * 4 + comp] = v;
-              if (f < d.M1) Tg[f * 4 + comp] = v;
-            }
-          }
-        }
+      for (int o = lane; o < M1p * 4; o += 64) {
+        const double v = Tl[o] * d.inv_nc;
+        Tl[o] = v;
+        if ((o >> 2) < d.M1) Tg[o] = v;
       }
     }
     wave_sync();
@@ -274,15 +283,12 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
     {
       const int b = lane & 15;
       const double bv = b < d.M2 ? Tl[b * 4 + (lane >> 4)] : 0.0;
+      for (int mt = 0; mt < nmtG; ++mt) {
+        v4d z = mfma64(Tl[(mt * 16 + (lane & 15)) * 4 + (lane >> 4)], bv, v4d{0.0, 0.0, 0.0, 0.0});
 #pragma unroll
-      for (int mt = 0; mt < MAXMT; ++mt) {
-        if (mt < nmtG) {
-          v4d z = mfma64(Tl[(mt * 16 + (lane & 15)) * 4 + (lane >> 4)], bv, v4d{0.0, 0.0, 0.0, 0.0});
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int f = mt * 16 + 4 * r + (lane >> 4);
-            if (f < d.M1 && b < d.M2) Dp[f * d.M2 + b] = z[r];
-          }
+        for (int r = 0; r < 4; ++r) {
+          const int f = mt * 16 + 4 * r + (lane >> 4);
+          if (f < d.M1 && b < d.M2) Dp[f * d.M2 + b] = z[r];
         }
       }
     }
@@ -307,7 +313,7 @@ __device__ inline void switch_fn(double r, double rcs, double rc, double inv_w, 
   }
 }
 
-__global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_bwd_f64(EmbedArgs a, EmbLds L) {
+__global__ void __launch_bounds__(64 * EMB_WAVES) __attribute__((amdgpu_waves_per_eu(2))) k_embed_bwd_f64(EmbedArgs a, EmbLds L) {
   extern __shared__ double smem[];
   __shared__ double vred[EMB_WAVES][9];
   const Dims &d = a.d;
@@ -400,22 +406,24 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_bwd_f64(EmbedArgs a, E
           const int rows_out = last ? 0 : d.ekp[l + 1];
           const double *W = a.ew + a.eo.w[t][u][l];
           const double *bias = a.ew + a.eo.b[t][u][l];
-          v4d acc[2][MAXMT];
-          mfma_layer<2>(W, d.ekp[l], d.emp[l + 1], Hin, 32, lane, acc);
           const int nmt = d.emp[l + 1] >> 4;
+          for (int mt0 = 0; mt0 < nmt; mt0 += EMB_G) {
+            v4d acc[2][EMB_G];
+            mfma_group<2>(W, d.ekp[l], d.emp[l + 1], Hin, 32, lane, mt0, acc);
 #pragma unroll
-          for (int mt = 0; mt < MAXMT; ++mt) {
-            if (mt < nmt) {
+            for (int g = 0; g < EMB_G; ++g) {
+              const int mt = mt0 + g;
+              if (mt >= nmt) continue;
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 const int f = mt * 16 + 4 * r + (lane >> 4), n = lane & 15;
                 double h = 0.0, hd = 0.0;
                 if (f < out) {
-                  const double z = acc[0][mt][r] + bias[f];
+                  const double z = acc[0][g][r] + bias[f];
                   const bool lin = d.emb_lin && last;
                   const double th = lin ? z : tanh64(z);
                   h = th;
-                  hd = lin ? acc[1][mt][r] : (1.0 - th * th) * acc[1][mt][r];
+                  hd = lin ? acc[1][g][r] : (1.0 - th * th) * acc[1][g][r];
                   const int sf = skip_src(f, in, out);
                   if (sf >= 0) {
                     h += Hin[sf * 32 + n];
