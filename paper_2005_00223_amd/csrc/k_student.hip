@@ -145,11 +145,16 @@ __device__ inline void st_hidden_f32(const float *P, const StudentLayout &L, flo
 }
 
 // ---------------------------------------------------------------------------
-// 3a. squared error and its gradient: one block of 256 threads per 64
+// 3a. squared error and its gradient: GR_SPLIT blocks of eight waves per 64
 //     samples; wave w takes output features [w*oc, (w+1)*oc) of every sample,
-//     the four partial dE/dh2 meet in LDS
+//     the partial dE/dh2 meet in LDS, and block z sums parameters
+//     [z*per, (z+1)*per) over the 64 samples
 // ---------------------------------------------------------------------------
 constexpr int GR_WAVES = 8;
+constexpr int GR_OC = 16;  // output features per wave at most (M1 <= 128)
+// workgroups per 64 samples: each evaluates the samples and sums its share
+// of the parameters (a 4,096-sample batch of one net is 64 x 4 workgroups)
+constexpr int GR_SPLIT = 4;
 constexpr int GSP = 68;  // LDS row stride of the gradient kernel (samples): 16-byte rows for float4 sums
 
 __global__ void __launch_bounds__(64 * GR_WAVES) k_st_grad(StGradArgs a) {
@@ -180,17 +185,25 @@ __global__ void __launch_bounds__(64 * GR_WAVES) k_st_grad(StGradArgs a) {
   for (int k = 0; k < SH2; ++k) dh2[k] = 0.f;
   double lsum = 0.0;
   const double *Gt = a.G + q * M1;
-  const int oc = (M1 + GR_WAVES - 1) / GR_WAVES;
+  const int oc = (M1 + GR_WAVES - 1) / GR_WAVES;  // <= GR_OC (M1 <= 128)
   const int o0 = wv * oc, o1 = o0 + oc < M1 ? o0 + oc : M1;
-  for (int o = o0; o < o1; ++o) {
+  // this wave's teacher targets, all loads issued before the first use
+  // (unconditional: indices past the range reread the last output)
+  double gt[GR_OC];
+#pragma unroll
+  for (int k = 0; k < GR_OC; ++k) gt[k] = Gt[o0 + k < M1 ? o0 + k : M1 - 1];
+#pragma unroll
+  for (int k = 0; k < GR_OC; ++k) {
+    const int o = o0 + k;
+    if (o >= o1) break;
     float g = P[L.o_b3 + o];
 #pragma unroll
-    for (int k = 0; k < SH2; ++k) g += h2[k] * P[L.o_w3 + k * M1 + o];
-    const float r = w * (g - (float)Gt[o]);
+    for (int j = 0; j < SH2; ++j) g += h2[j] * P[L.o_w3 + j * M1 + o];
+    const float r = w * (g - (float)gt[k]);
     lsum += (double)r * r;
     rs[o * GSP + m] = r;
 #pragma unroll
-    for (int k = 0; k < SH2; ++k) dh2[k] += P[L.o_w3 + k * M1 + o] * r;
+    for (int j = 0; j < SH2; ++j) dh2[j] += P[L.o_w3 + j * M1 + o] * r;
   }
 #pragma unroll
   for (int k = 0; k < SH2; ++k) dhp[(wv * SH2 + k) * GSP + m] = dh2[k];
@@ -246,7 +259,10 @@ __global__ void __launch_bounds__(64 * GR_WAVES) k_st_grad(StGradArgs a) {
     }
     return acc;
   };
-  for (int e = tid; e < L.np; e += 64 * GR_WAVES) {
+  // this block's share of the parameters (blockIdx.z of GR_SPLIT)
+  const int per = (L.np + GR_SPLIT - 1) / GR_SPLIT;
+  const int e_end = (int)blockIdx.z * per + per < L.np ? (int)blockIdx.z * per + per : L.np;
+  for (int e = (int)blockIdx.z * per + tid; e < e_end; e += 64 * GR_WAVES) {
     float acc = 0.f;
     if (e < L.o_b1) {
       acc = dot64(ss, dz1s + e * GSP);
@@ -265,10 +281,23 @@ __global__ void __launch_bounds__(64 * GR_WAVES) k_st_grad(StGradArgs a) {
     }
     gp[e] = acc;
   }
-  if (tid < 2) {
-    double v = 0.0;
-    for (int k = 0; k < 64 * GR_WAVES; ++k) v += red[tid][k];
-    a.lpart[((int64_t)net * nblk + blk) * 2 + tid] = v;
+  if (blockIdx.z == 0 && wv == 0) {
+    // sums of the squared errors and of the weights: lane m takes every
+    // 64th entry, then a butterfly over the wave
+    double v0 = 0.0, v1 = 0.0;
+    for (int k = m; k < 64 * GR_WAVES; k += 64) {
+      v0 += red[0][k];
+      v1 += red[1][k];
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      v0 += __shfl_xor(v0, o);
+      v1 += __shfl_xor(v1, o);
+    }
+    if (m == 0) {
+      a.lpart[((int64_t)net * nblk + blk) * 2 + 0] = v0;
+      a.lpart[((int64_t)net * nblk + blk) * 2 + 1] = v1;
+    }
   }
 }
 
@@ -276,7 +305,7 @@ void launch_st_grad(hipStream_t st, const StGradArgs &a) {
   const StudentLayout L = student_layout(a.M1);
   const size_t shm =
       sizeof(float) * ((size_t)((L.np + 3) & ~3) + 64 + (size_t)(2 * SH1 + 2 * SH2 + a.M1 + GR_WAVES * SH2) * GSP);
-  hipLaunchKernelGGL(k_st_grad, dim3(a.batch / 64, a.nets), dim3(64 * GR_WAVES), shm, st, a);
+  hipLaunchKernelGGL(k_st_grad, dim3(a.batch / 64, a.nets, GR_SPLIT), dim3(64 * GR_WAVES), shm, st, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -289,11 +318,29 @@ __global__ void k_st_adam(StAdamArgs a) {
   const int net = (int)(e / L.np), p = (int)(e % L.np);
   double wsum = 0.0, lsum = 0.0;
   float g = 0.f;
-  for (int b = 0; b < a.nblk; ++b) {
-    const int64_t pb = (int64_t)net * a.nblk + b;
-    g += a.gpart[pb * L.np + p];
-    lsum += a.lpart[pb * 2 + 0];
-    wsum += a.lpart[pb * 2 + 1];
+  // the partials in block order, eight loads in flight before their adds
+  const int64_t pb0 = (int64_t)net * a.nblk;
+  int b = 0;
+  for (; b + 8 <= a.nblk; b += 8) {
+    float gv[8];
+    double lv[8], wv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      gv[u] = a.gpart[(pb0 + b + u) * L.np + p];
+      lv[u] = a.lpart[(pb0 + b + u) * 2 + 0];
+      wv[u] = a.lpart[(pb0 + b + u) * 2 + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      g += gv[u];
+      lsum += lv[u];
+      wsum += wv[u];
+    }
+  }
+  for (; b < a.nblk; ++b) {
+    g += a.gpart[(pb0 + b) * L.np + p];
+    lsum += a.lpart[(pb0 + b) * 2 + 0];
+    wsum += a.lpart[(pb0 + b) * 2 + 1];
   }
   const double denom = (double)a.M1 * (wsum > 0.0 ? wsum : 1.0);
   g *= (float)(2.0 / denom);
