@@ -19,6 +19,7 @@
 // Training work is small next to an MD run, so these kernels are plain
 // FP32/FP64 VALU code with LDS; they spread each sample over several threads
 // so that a batch of a few thousand samples still fills the chip.
+#include "dp_f64.h"
 #include "dp_student.h"
 
 namespace dpk {
@@ -63,66 +64,95 @@ void launch_st_sample(hipStream_t st, const StSampleArgs &a) {
 }
 
 // ---------------------------------------------------------------------------
-// 2. teacher G(s) in FP64: a block of 256 threads takes 16 samples, 16
-//    threads per sample; each thread computes every 16th output feature of
-//    a layer, the activations of the block's samples live in LDS
+// 2. teacher G(s) in FP64 on the matrix cores: a wave takes 16 samples (the
+//    MFMA N dimension); layer 0 on the VALU into a per-wave LDS tile
+//    [feature][sample], each later layer as W^T H^T four output tiles at a
+//    time (the embedding kernels' layer code), the last layer's outputs
+//    written straight to G
 // ---------------------------------------------------------------------------
-constexpr int TCH_SAMPLES = 16;
+constexpr int TCH_WAVES = 4;
 
-__global__ void __launch_bounds__(256) k_st_teacher(StTeacherArgs a) {
+// rows of the two per-wave activation buffers (outputs of the hidden layers
+// l < n_emb - 1, layer l into buffer l & 1)
+static void tch_rows(const Dims &d, int &r0, int &r1) {
+  r0 = r1 = 0;
+  for (int l = 0; l < d.n_emb - 1; ++l) {
+    int &r = (l & 1) ? r1 : r0;
+    r = d.ekp[l + 1] > r ? d.ekp[l + 1] : r;
+  }
+}
+
+__global__ void __launch_bounds__(64 * TCH_WAVES) k_st_teacher(StTeacherArgs a, int r0, int r1) {
   extern __shared__ double tsh[];
   const Dims &d = a.d;
   const int net = blockIdx.y;
   const int t = net / d.ntypes, u = net % d.ntypes;
-  const int j = threadIdx.x & 15, ql = threadIdx.x >> 4;
-  const int q = blockIdx.x * TCH_SAMPLES + ql;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, n = lane & 15;
+  const int q0 = (blockIdx.x * TCH_WAVES + wv) * 16;
+  if (q0 >= a.batch) return;  // the whole wave
   const int64_t row = ((int64_t)blockIdx.z * d.ntypes * d.ntypes + net) * a.batch;  // first sample of (batch, net)
-  int wmax = 1;
-  for (int l = 1; l <= d.n_emb; ++l) wmax = d.ew[l] > wmax ? d.ew[l] : wmax;
-  double *hA = tsh + ql * wmax, *hB = tsh + (TCH_SAMPLES + ql) * wmax;
-  const double s = q < a.batch ? a.s[row + q] : 0.0;
+  double *buf[2] = {tsh + (size_t)wv * (r0 + r1) * 16, tsh + (size_t)wv * (r0 + r1) * 16 + r0 * 16};
+  // unconditional load: samples past the batch reread its last one and are not written
+  const double s = a.s[row + (q0 + n < a.batch ? q0 + n : a.batch - 1)];
   {
     const double *W0 = a.ew + a.eo.w[t][u][0], *b0 = a.ew + a.eo.b[t][u][0];
     const int out = d.ew[1];
-    const bool lin = d.emb_lin && d.n_emb == 1;
-    for (int o = j; o < out; o += 16) {
-      const double z = s * W0[o] + b0[o];
-      double h = lin ? z : tanh64(z);
-      if (out <= 2) h += s;  // identity / doubling skip of the scalar input
-      hA[o] = h;
+    for (int idx = lane; idx < d.ekp[1] * 16; idx += 64) {
+      const int f = idx >> 4;  // sample idx & 15 == n
+      double h = 0.0;
+      if (f < out) {
+        h = tanh64(s * W0[f] + b0[f]);
+        if (out <= 2) h += s;  // identity / doubling skip of the scalar input
+      }
+      buf[0][f * 16 + n] = h;
     }
   }
-  __syncthreads();
+  wave_sync();
   for (int l = 1; l < d.n_emb; ++l) {
-    const int in = d.ew[l], out = d.ew[l + 1], mp = d.emp[l + 1];
-    const double *W = a.ew + a.eo.w[t][u][l], *b = a.ew + a.eo.b[t][u][l];
-    const bool lin = d.emb_lin && l == d.n_emb - 1;
-    for (int o = j; o < out; o += 16) {
-      double z = b[o];
-      for (int i = 0; i < in; ++i) z += hA[i] * W[(size_t)i * mp + o];
-      double h = lin ? z : tanh64(z);
-      if (out == in) h += hA[o];
-      else if (out == 2 * in) h += hA[o % in];
-      hB[o] = h;
+    const int in = d.ew[l], out = d.ew[l + 1];
+    const bool last = l == d.n_emb - 1;
+    const bool lin = d.emb_lin && last;
+    const double *Hin = buf[(l - 1) & 1];
+    double *Hout = buf[l & 1];
+    const int rows_out = last ? 0 : d.ekp[l + 1];
+    const double *W = a.ew + a.eo.w[t][u][l], *bias = a.ew + a.eo.b[t][u][l];
+    const int nmt = d.emp[l + 1] >> 4;
+    for (int mt0 = 0; mt0 < nmt; mt0 += EMB_G) {
+      v4d acc[1][EMB_G];
+      mfma_group<1>(W, d.ekp[l], d.emp[l + 1], Hin, 16, lane, mt0, acc);
+#pragma unroll
+      for (int g = 0; g < EMB_G; ++g) {
+        const int mt = mt0 + g;
+        if (mt >= nmt) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int f = mt * 16 + 4 * r + (lane >> 4);
+          double h = 0.0;
+          if (f < out) {
+            const double z = acc[0][g][r] + bias[f];
+            h = lin ? z : tanh64(z);
+            const int sf = skip_src(f, in, out);
+            if (sf >= 0) h += Hin[sf * 16 + n];
+          }
+          if (last) {
+            if (f < out && q0 + n < a.batch) a.G[(row + q0 + n) * d.M1 + f] = h;
+          } else if (f < rows_out) {
+            Hout[f * 16 + n] = h;
+          }
+        }
+      }
     }
-    __syncthreads();
-    double *tmp = hA;
-    hA = hB;
-    hB = tmp;
-  }
-  if (q < a.batch) {
-    double *G = a.G + (row + q) * d.M1;
-    for (int o = j; o < d.M1; o += 16) G[o] = hA[o];
+    wave_sync();
   }
 }
 
 void launch_st_teacher(hipStream_t st, const StTeacherArgs &a) {
-  int wmax = 1;
-  for (int l = 1; l <= a.d.n_emb; ++l) wmax = a.d.ew[l] > wmax ? a.d.ew[l] : wmax;
-  const size_t shm = (size_t)2 * TCH_SAMPLES * wmax * sizeof(double);
+  int r0, r1;
+  tch_rows(a.d, r0, r1);
+  const size_t shm = (size_t)TCH_WAVES * (r0 + r1) * 16 * sizeof(double);
   const int nets = a.d.ntypes * a.d.ntypes;
-  hipLaunchKernelGGL(k_st_teacher, dim3((a.batch + TCH_SAMPLES - 1) / TCH_SAMPLES, nets, a.nb), dim3(256), shm, st,
-                     a);
+  hipLaunchKernelGGL(k_st_teacher, dim3((a.batch + 16 * TCH_WAVES - 1) / (16 * TCH_WAVES), nets, a.nb),
+                     dim3(64 * TCH_WAVES), shm, st, a, r0, r1);
 }
 
 // ---------------------------------------------------------------------------
