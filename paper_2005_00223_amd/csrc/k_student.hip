@@ -208,8 +208,31 @@ __global__ void __launch_bounds__(64 * GR_WAVES) k_st_grad(StGradArgs a) {
   const int64_t q = (int64_t)net * a.batch + (int64_t)blk * 64 + m;
   const float s = (float)a.s[q];
   const float w = a.wt[q];
-  float t1[SH1], t2[SH2], h2[SH2];
-  st_hidden_f32(P, L, s, t1, t2, h2);
+  static_assert(SH1 == 2 * GR_WAVES && SH2 == 4 * GR_WAVES, "hidden features split evenly over the waves");
+  // forward, each hidden feature once per sample: wave wv takes the first
+  // layer's features 2 wv, 2 wv + 1 and the second layer's 4 wv .. 4 wv + 3
+  // (the same expressions as st_hidden_f32), shared through LDS
+  float t1o[2], t2o[4];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int i = 2 * wv + c;
+    t1o[c] = tanhf(s * P[L.o_w1 + i] + P[L.o_b1 + i]);
+    h1s[i * GSP + m] = t1o[c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int j = 4 * wv + c;
+    float z = P[L.o_b2 + j];
+#pragma unroll
+    for (int i = 0; i < SH1; ++i) z += h1s[i * GSP + m] * P[L.o_w2 + i * SH2 + j];
+    t2o[c] = tanhf(z);
+    h2s[j * GSP + m] = h1s[(j % SH1) * GSP + m] + t2o[c];
+  }
+  __syncthreads();
+  float h2[SH2];
+#pragma unroll
+  for (int j = 0; j < SH2; ++j) h2[j] = h2s[j * GSP + m];
   float dh2[SH2];
 #pragma unroll
   for (int k = 0; k < SH2; ++k) dh2[k] = 0.f;
@@ -240,33 +263,29 @@ __global__ void __launch_bounds__(64 * GR_WAVES) k_st_grad(StGradArgs a) {
   red[0][tid] = lsum;
   red[1][tid] = wv == 0 ? (double)w : 0.0;
   __syncthreads();
-  if (wv == 0) {
+  // backward through the hidden layers, split over the waves as the forward:
+  // dE/dh2 summed over the waves' partials in wave order, then
+  // dz2 = dE/dh2 (1 - t2^2) (into the wave-0 slice of the partials, which
+  // only this wave reads), then dz1 from all of dz2
 #pragma unroll
-    for (int k = 0; k < SH2; ++k)
-    {
-      float v = 0.f;
+  for (int c = 0; c < 4; ++c) {
+    const int k = 4 * wv + c;
+    float v = 0.f;
 #pragma unroll
-      for (int w2 = 0; w2 < GR_WAVES; ++w2) v += dhp[(w2 * SH2 + k) * GSP + m];
-      dh2[k] = v;
-    }
-    float dz2[SH2];
-#pragma unroll
-    for (int j = 0; j < SH2; ++j) dz2[j] = dh2[j] * (1.f - t2[j] * t2[j]);
-#pragma unroll
-    for (int i = 0; i < SH1; ++i) {
-      float g = dh2[i] + dh2[i + SH1];
-#pragma unroll
-      for (int j = 0; j < SH2; ++j) g += P[L.o_w2 + i * SH2 + j] * dz2[j];
-      dz1s[i * GSP + m] = g * (1.f - t1[i] * t1[i]);
-      h1s[i * GSP + m] = t1[i];
-    }
-#pragma unroll
-    for (int j = 0; j < SH2; ++j) {
-      h2s[j * GSP + m] = h2[j];
-      dz2s[j * GSP + m] = dz2[j];
-    }
-    ss[m] = s;
+    for (int w2 = 0; w2 < GR_WAVES; ++w2) v += dhp[(w2 * SH2 + k) * GSP + m];
+    dhp[k * GSP + m] = v;  // dE/dh2
+    dz2s[k * GSP + m] = v * (1.f - t2o[c] * t2o[c]);
   }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int i = 2 * wv + c;
+    float g = dhp[i * GSP + m] + dhp[(i + SH1) * GSP + m];
+#pragma unroll
+    for (int j = 0; j < SH2; ++j) g += P[L.o_w2 + i * SH2 + j] * dz2s[j * GSP + m];
+    dz1s[i * GSP + m] = g * (1.f - t1o[c] * t1o[c]);
+  }
+  if (wv == 0) ss[m] = s;
   __syncthreads();
   // sums over the 64 samples of the block, parameter by parameter
   float *gp = a.gpart + ((int64_t)net * nblk + blk) * L.np;
@@ -502,39 +521,53 @@ __global__ void __launch_bounds__(256) k_st_solve(StSolveArgs a) {
   double *Lc = A + SNF * SNF;    // [SNF][SNF] Cholesky factor
   double *B = Lc + SNF * SNF;    // [SNF][M1]
   __shared__ int bad;
+  const double *pn = a.part + (int64_t)net * a.nblk * NE;
   for (int e = tid; e < NE; e += blockDim.x) {
+    // the partials in order, eight loads in flight before their adds
     double v = 0.0;
-    for (int b = 0; b < a.nblk; ++b) v += a.part[((int64_t)net * a.nblk + b) * NE + e];
+    int b = 0;
+    for (; b + 8 <= a.nblk; b += 8) {
+      double x[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) x[k] = pn[(int64_t)(b + k) * NE + e];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v += x[k];
+    }
+    for (; b < a.nblk; ++b) v += pn[(int64_t)b * NE + e];
     if (e < SNF * SNF) A[e] = v;
     else B[e - SNF * SNF] = v;
   }
   __syncthreads();
+  __shared__ double lam;
   if (tid == 0) {
-    bad = 0;
-    if (!(A[SNF * SNF - 1] > 0.0)) bad = 2;
+    bad = A[SNF * SNF - 1] > 0.0 ? 0 : 2;
     double tr = 0.0;
     for (int i = 0; i < SNF; ++i) tr += A[i * SNF + i];
-    const double lam = a.ridge * tr / SNF;
-    for (int i = 0; i < SNF * SNF; ++i) Lc[i] = A[i];
-    for (int i = 0; i < SNF; ++i) Lc[i * SNF + i] += lam;
-    for (int j = 0; j < SNF && !bad; ++j) {
-      double dgn = Lc[j * SNF + j];
-      for (int k = 0; k < j; ++k) dgn -= Lc[j * SNF + k] * Lc[j * SNF + k];
-      if (!(dgn > 0.0)) {
-        bad = 1;
-        break;
-      }
-      const double ljj = sqrt(dgn);
-      Lc[j * SNF + j] = ljj;
-      for (int i = j + 1; i < SNF; ++i) {
-        double v = Lc[i * SNF + j];
-        for (int k = 0; k < j; ++k) v -= Lc[i * SNF + k] * Lc[j * SNF + k];
-        Lc[i * SNF + j] = v / ljj;
-      }
-    }
-    a.status[net] = bad;
+    lam = a.ridge * tr / SNF;
   }
   __syncthreads();
+  for (int e = tid; e < SNF * SNF; e += blockDim.x) Lc[e] = A[e] + ((e % (SNF + 1)) == 0 ? lam : 0.0);
+  __syncthreads();
+  // Cholesky, column by column: the diagonal on one thread, the rows below
+  // it in parallel (each entry's arithmetic as in the sequential order)
+  for (int j = 0; j < SNF; ++j) {
+    if (tid == 0 && bad == 0) {
+      double dgn = Lc[j * SNF + j];
+      for (int k = 0; k < j; ++k) dgn -= Lc[j * SNF + k] * Lc[j * SNF + k];
+      if (dgn > 0.0) Lc[j * SNF + j] = sqrt(dgn);
+      else bad = 1;
+    }
+    __syncthreads();
+    if (bad) break;
+    const double ljj = Lc[j * SNF + j];
+    for (int i = j + 1 + tid; i < SNF; i += blockDim.x) {
+      double v = Lc[i * SNF + j];
+      for (int k = 0; k < j; ++k) v -= Lc[i * SNF + k] * Lc[j * SNF + k];
+      Lc[i * SNF + j] = v / ljj;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) a.status[net] = bad;
   if (bad) return;
   for (int o = tid; o < M1; o += blockDim.x) {
     double y[SNF];
