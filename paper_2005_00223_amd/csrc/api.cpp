@@ -820,11 +820,15 @@ void eval_lists(dp_ctx *c, int64_t n, const double L[3]) {
   for (int k = 0; k < 3; ++k) c->box_L[k] = L[k];
   const Dims &d = c->dims;
   hipStream_t s = c->stream;
+  // the mixed path's FP32 environment rows come out of the format kernel
+  // (it has each slot's neighbour and position at hand); the FP64 path's
+  // rows and displacements from the environment kernel
+  const bool fused = w.rt32 && !w.dr;
   tmark(c, 1);
   launch_format(s, n, w.xw, d, L, w.cand, w.cand_n, w.cand_cap, w.nlist, w.nreal, &w.status->overflow,
-                w.status->max_real, &w.status->flags);
+                w.status->max_real, &w.status->flags, fused ? w.rt32 : nullptr);
   tmark(c, 2);
-  launch_env(s, n, w.xw, d, L, w.nlist, w.nreal, w.rt, w.rt32, w.dr);
+  if (!fused) launch_env(s, n, w.xw, d, L, w.nlist, w.nreal, w.rt, w.rt32, w.dr);
   tmark(c, 3);
 }
 

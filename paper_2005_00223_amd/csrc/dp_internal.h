@@ -89,9 +89,11 @@ void launch_candidates(hipStream_t s, int64_t n, const double4 *xw, const CellGr
                        const int32_t *cell_atoms, double rlist, int cand_cap, int32_t *cand, int32_t *cand_n,
                        uint32_t *flags, const uint32_t *cond);
 void launch_fill_u32(hipStream_t s, uint32_t *p, int64_t n, uint32_t v);
+// rt32 (may be NULL): also write the mixed path's FP32 environment rows of
+// the real slots (then the environment kernel is not needed)
 void launch_format(hipStream_t s, int64_t n, const double4 *xw, const Dims &d, const double *L, const int32_t *cand,
                    const int32_t *cand_n, int cand_cap, int32_t *nlist, int32_t *nreal,
-                   unsigned long long *overflow, int32_t *max_real, uint32_t *flags);
+                   unsigned long long *overflow, int32_t *max_real, uint32_t *flags, float4 *rt32);
 // -1 padding of the formatted list past each type's real count (the
 // formatting kernel writes the real slots only)
 void launch_pad_nlist(hipStream_t s, int64_t n, const Dims &d, const int32_t *nreal, int32_t *nlist);

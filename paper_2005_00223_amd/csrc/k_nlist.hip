@@ -351,7 +351,8 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
                                                 const int32_t *__restrict__ cand,
                                                 const int32_t *__restrict__ cand_n, int cap,
                                                 int32_t *__restrict__ nlist, int32_t *__restrict__ nreal,
-                                                unsigned long long *overflow, int32_t *max_real, uint32_t *flags) {
+                                                unsigned long long *overflow, int32_t *max_real, uint32_t *flags,
+                                                float4 *__restrict__ rt32) {
   extern __shared__ __align__(16) unsigned char fmt_lds[];
   int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int64_t i = (int64_t)blockIdx.x * FMT_WAVES + wv;
@@ -495,7 +496,19 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
       if (u == t) ts = tstart[u];
     int pos = rank - ts;
     // pos < 0 can only happen when the key buffer overflowed (flagged above)
-    if (pos >= 0 && pos < d.sel[t]) row[d.off[t] + pos] = (int32_t)(key & ((1ull << 26) - 1ull));
+    if (pos >= 0 && pos < d.sel[t]) {
+      const int32_t j = (int32_t)(key & ((1ull << 26) - 1ull));
+      row[d.off[t] + pos] = j;
+      if (rt32) {
+        // the slot's environment row (the mixed path's FP32 copy of the
+        // FP64 values, as the environment kernel computes them)
+        const double4 D = pair_disp(p, xw[j], L0, L1, L2);
+        const double sv = env_s(D.w, d.rcut_smth, d.rcut, 1.0 / (d.rcut - d.rcut_smth));
+        const double tv = sv * (1.0 / D.w);
+        rt32[i * (int64_t)d.nnei + d.off[t] + pos] =
+            make_float4((float)sv, (float)(tv * D.x), (float)(tv * D.y), (float)(tv * D.z));
+      }
+    }
   }
   // only the real slots are written; k_pad_nlist fills the -1 padding when
   // the list is copied out (every device consumer stops at the real count)
@@ -519,7 +532,7 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
 
 void launch_format(hipStream_t s, int64_t n, const double4 *xw, const Dims &d, const double *L, const int32_t *cand,
                    const int32_t *cand_n, int cand_cap, int32_t *nlist, int32_t *nreal, unsigned long long *overflow,
-                   int32_t *max_real, uint32_t *flags) {
+                   int32_t *max_real, uint32_t *flags, float4 *rt32) {
   if (n <= 0) return;
   // the largest double x with sqrt(x) <= rc (sqrt is correctly rounded and
   // monotone, so r^2 <= x exactly when sqrt(r^2) <= rc)
@@ -528,7 +541,7 @@ void launch_format(hipStream_t s, int64_t n, const double4 *xw, const Dims &d, c
   while (std::sqrt(std::nextafter(x, HUGE_VAL)) <= d.rcut) x = std::nextafter(x, HUGE_VAL);
   const size_t lds = FMT_WAVES * fmt_wave_bytes(d.ntypes * FMT_NB);
   hipLaunchKernelGGL(k_format, dim3((unsigned)((n + FMT_WAVES - 1) / FMT_WAVES)), dim3(64 * FMT_WAVES), lds, s, n, xw,
-                     d, L[0], L[1], L[2], x, cand, cand_n, cand_cap, nlist, nreal, overflow, max_real, flags);
+                     d, L[0], L[1], L[2], x, cand, cand_n, cand_cap, nlist, nreal, overflow, max_real, flags, rt32);
 }
 
 // -1 in every slot past a type's real count
