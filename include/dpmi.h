@@ -51,18 +51,24 @@ enum {
                           per-atom sort buffer (512) holds                  */
 };
 
-/* Precision policies (after the paper's MIX-16 scheme, Section V-B
- * "Mixed-precision computation").
+/* Precision policies (after the paper's MIX-32 and MIX-16 schemes, Section
+ * V-B "Mixed-precision computation").
  * DP_FP64: everything in double.
+ * DP_MIX_FP32 (the paper's MIX-32): the embedding and fitting nets' weights
+ *   rounded to FP32, the environment matrix rounded to FP32, and every
+ *   operation of both nets (matrix-core products, tanh, the descriptor
+ *   contractions, the backward) in FP32; the per-atom energies and the
+ *   network gradient dE/dR are converted to double.  Same net widths as
+ *   DP_FP64 (up to 128).
  * DP_MIX_FP16 / DP_MIX_BF16: embedding layers after the first and the first
  *   two fitting layers as 16-bit matrix-core products with FP32
  *   accumulation and 16-bit weights; activations enter those products as
  *   hi + lo 16-bit pairs (about 22 bits); tanh, the descriptor contractions,
  *   the remaining fitting layers and the output layer in FP32.
- * Coordinates, wrapping, distances, the environment matrix, the force
- * Jacobian, energy / force / virial sums and the integrator stay double in
- * every mode.  (Value 1 is reserved.) */
-enum { DP_FP64 = 0, DP_MIX_FP16 = 2, DP_MIX_BF16 = 3 };
+ * Coordinates, wrapping, distances, the environment matrix (before its
+ * rounding), the force Jacobian, energy / force / virial sums and the
+ * integrator stay double in every mode. */
+enum { DP_FP64 = 0, DP_MIX_FP32 = 1, DP_MIX_FP16 = 2, DP_MIX_BF16 = 3 };
 
 typedef struct {
   int64_t natoms;            /* atoms in the last dp_compute                 */

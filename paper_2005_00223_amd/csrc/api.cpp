@@ -210,6 +210,7 @@ struct EmbNets {
   Dims d{};                         // model dims with this set's embedding widths
   EmbOffsets eo{};
   double *d_emb = nullptr;          // FP64 padded weights
+  float *d_emb32 = nullptr;         // the same rounded to FP32 (DP_MIX_FP32)
   unsigned char *d_mix = nullptr;   // mixed-precision LDS images
   int mix_shape = -1;
   float *d_tab = nullptr;           // tabulated second layer (student nets, mixed precision)
@@ -230,6 +231,7 @@ struct dp_ctx {
   Dims dims{};                      // teacher dims (geometry, fitting net)
   FitOffsets fo{};
   double *d_fit = nullptr;
+  float *d_fit32 = nullptr;         // fitting weights rounded to FP32 (DP_MIX_FP32)
   // mixed-precision fitting weights (16-bit MFMA operands + f32)
   unsigned char *d_fit_mix = nullptr;
   FitMixOffsets fmo{};
@@ -321,12 +323,20 @@ void free_student(dp_ctx *c) {
   c->st = nullptr;
 }
 
+// Precision policies: DP_FP64 and DP_MIX_FP32 run the FP64-structured
+// kernels (in double and in float), DP_MIX_FP16 / DP_MIX_BF16 the
+// register-resident 16-bit kernels.
+inline bool prec16(int p) { return p == DP_MIX_FP16 || p == DP_MIX_BF16; }
+inline bool prec_ok(int p) { return p == DP_FP64 || p == DP_MIX_FP32 || prec16(p); }
+
 // Lay every buffer of the workspace out in one block: returns the block's
 // size for nn atoms, nc cells and cc candidate slots per atom, and, when
 // base is not NULL, points the buffers of w into the block at base.
 size_t ws_carve(const dp_ctx *c, Workspace &w, int64_t nn, int64_t nc, int cc, bool nd, char *base) {
   const Dims &d = c->dims;
-  const bool mixed = c->precision != DP_FP64;
+  const bool mixed = prec16(c->precision);
+  const bool f32 = c->precision == DP_MIX_FP32;
+  const size_t rb = f32 ? sizeof(float) : sizeof(double);  // FP64-structured buffers
   const int64_t rows = (nn + ROW_TILE - 1) / ROW_TILE * ROW_TILE + (int64_t)ROW_TILE * d.ntypes;
   const int64_t nblk = (nn + 255) / 256 + 1;
   size_t off = 0;
@@ -352,17 +362,18 @@ size_t ws_carve(const dp_ctx *c, Workspace &w, int64_t nn, int64_t nc, int cc, b
   add((void **)&w.blk_counts, (size_t)4 * nblk * MAXT);
   add((void **)&w.type_count, 4 * MAXT);
   add((void **)&w.type_start, 4 * (MAXT + 1));
-  if (mixed) add((void **)&w.rt32, sizeof(float4) * nn * d.nnei);
+  if (mixed || f32) add((void **)&w.rt32, sizeof(float4) * nn * d.nnei);
   else add((void **)&w.rt, sizeof(double4) * nn * d.nnei);
   if (!mixed) add((void **)&w.dr, sizeof(double4) * nn * d.nnei);
   if (!mixed) {
-    add((void **)&w.T, sizeof(double) * nn * d.M1 * 4);
-    add((void **)&w.D, sizeof(double) * rows * d.M1 * d.M2);
-    add((void **)&w.dD, sizeof(double) * rows * d.M1 * d.M2);
+    // in float under DP_MIX_FP32 (the pointers are then read as float)
+    add((void **)&w.T, rb * nn * d.M1 * 4);
+    add((void **)&w.D, rb * rows * d.M1 * d.M2);
+    add((void **)&w.dD, rb * rows * d.M1 * d.M2);
     for (int l = 1; l <= d.n_fit; ++l) {
-      add((void **)&w.Y[l], sizeof(double) * rows * d.fw[l]);
-      add((void **)&w.Tt[l], sizeof(double) * rows * d.fw[l]);
-      if (l < d.n_fit) add((void **)&w.G[l], sizeof(double) * rows * d.fw[l]);
+      add((void **)&w.Y[l], rb * rows * d.fw[l]);
+      add((void **)&w.Tt[l], rb * rows * d.fw[l]);
+      if (l < d.n_fit) add((void **)&w.G[l], rb * rows * d.fw[l]);
     }
   } else {
     add((void **)&w.T32, sizeof(float) * nn * d.M1 * 4);
@@ -391,6 +402,7 @@ size_t ws_carve(const dp_ctx *c, Workspace &w, int64_t nn, int64_t nc, int cc, b
     if (!nd) w.net_deriv = nullptr;
     if (!mixed) w.cell_part = nullptr;
     if (mixed) w.rt = w.dr = nullptr;
+    else if (f32) w.rt = nullptr;
     else w.rt32 = nullptr;
     w.G[0] = w.dD;
     w.prec = c->precision;
@@ -509,9 +521,14 @@ int upload_emb(dp_ctx *c, const HostModel &m, EmbNets &en) {
         }
       }
   if (en.d_emb) (void)hipFree(en.d_emb);
+  if (en.d_emb32) (void)hipFree(en.d_emb32);
   en.d_emb = nullptr;
+  en.d_emb32 = nullptr;
   HIPCHK(c, hipMalloc(&en.d_emb, sizeof(double) * E.size()));
   HIPCHK(c, hipMemcpy(en.d_emb, E.data(), sizeof(double) * E.size(), hipMemcpyHostToDevice));
+  const std::vector<float> E32(E.begin(), E.end());
+  HIPCHK(c, hipMalloc(&en.d_emb32, sizeof(float) * E32.size()));
+  HIPCHK(c, hipMemcpy(en.d_emb32, E32.data(), sizeof(float) * E32.size(), hipMemcpyHostToDevice));
   return DP_OK;
 }
 
@@ -560,9 +577,14 @@ int upload_model(dp_ctx *c) {
       F.insert(F.end(), b.begin(), b.end());
     }
   if (c->d_fit) (void)hipFree(c->d_fit);
+  if (c->d_fit32) (void)hipFree(c->d_fit32);
   c->d_fit = nullptr;
+  c->d_fit32 = nullptr;
   HIPCHK(c, hipMalloc(&c->d_fit, sizeof(double) * F.size()));
   HIPCHK(c, hipMemcpy(c->d_fit, F.data(), sizeof(double) * F.size(), hipMemcpyHostToDevice));
+  const std::vector<float> F32(F.begin(), F.end());
+  HIPCHK(c, hipMalloc(&c->d_fit32, sizeof(float) * F32.size()));
+  HIPCHK(c, hipMemcpy(c->d_fit32, F32.data(), sizeof(float) * F32.size(), hipMemcpyHostToDevice));
   return DP_OK;
 }
 
@@ -742,6 +764,32 @@ EmbedArgs embed_args(dp_ctx *c, int64_t n, int64_t rows, double *F) {
   return ea;
 }
 
+// DP_MIX_FP32: the same buffers read as float, the FP32 weight copies
+EmbedArgs32 embed_args32(dp_ctx *c, int64_t n, int64_t rows, double *F) {
+  const EmbedArgs e = embed_args(c, n, rows, F);
+  EmbedArgs32 a{};
+  a.d = e.d;
+  a.eo = e.eo;
+  a.ew = c->en[c->active].d_emb32;
+  a.atom_of_pos = e.atom_of_pos;
+  a.pos_of_atom = e.pos_of_atom;
+  a.type_start = e.type_start;
+  a.rows = e.rows;
+  a.natoms = e.natoms;
+  a.xw = e.xw;
+  a.nlist = e.nlist;
+  a.nreal = e.nreal;
+  a.rt = c->ws.rt32;
+  a.dr = e.dr;
+  a.T = (float *)e.T;
+  a.D = (float *)e.D;
+  a.dD = (const float *)e.dD;
+  a.force = e.force;
+  a.vir_part = e.vir_part;
+  a.net_deriv = e.net_deriv;
+  return a;
+}
+
 FitArgs fit_args(dp_ctx *c, int64_t rows) {
   Workspace &w = c->ws;
   FitArgs fa{};
@@ -759,6 +807,25 @@ FitArgs fit_args(dp_ctx *c, int64_t rows) {
   }
   fa.eatom = w.eatom;
   return fa;
+}
+
+FitArgs32 fit_args32(dp_ctx *c, int64_t rows) {
+  const FitArgs f = fit_args(c, rows);
+  FitArgs32 a{};
+  a.d = f.d;
+  a.fo = f.fo;
+  a.fwt = c->d_fit32;
+  a.type_start = f.type_start;
+  a.atom_of_pos = f.atom_of_pos;
+  a.rows = f.rows;
+  a.X0 = (float *)f.X0;
+  for (int l = 0; l <= MAXF; ++l) {
+    a.Y[l] = (float *)f.Y[l];
+    a.Tt[l] = (float *)f.Tt[l];
+    a.G[l] = (float *)f.G[l];
+  }
+  a.eatom = f.eatom;
+  return a;
 }
 
 MixArgs mix_args(dp_ctx *c, int64_t rows, double *F) {
@@ -838,7 +905,7 @@ void eval_lists(dp_ctx *c, int64_t n, const double L[3]) {
 // layers instead.
 int ensure_table(dp_ctx *c, int64_t n) {
   EmbNets &en = c->en[c->active];
-  if (c->active != 1 || !c->use_tab || c->precision == DP_FP64 || en.tab_ok || n <= 0) return DP_OK;
+  if (c->active != 1 || !c->use_tab || !prec16(c->precision) || en.tab_ok || n <= 0) return DP_OK;
   if (!mix_tab_fits(en.mix_shape, c->dims.ntypes)) return DP_OK;
   Workspace &w = c->ws;
   hipStream_t s = c->stream;
@@ -976,6 +1043,11 @@ void eval_nets_fwd(dp_ctx *c, int64_t n, double *E) {
     tmark(c, 4);
     launch_fit_f64(s, fit_args(c, rows), 1);
     tmark(c, 8);
+  } else if (c->precision == DP_MIX_FP32) {
+    launch_embed_fwd_f32(s, embed_args32(c, n, rows, nullptr));
+    tmark(c, 4);
+    launch_fit_f32(s, fit_args32(c, rows), 1);
+    tmark(c, 8);
   } else {
     (void)ensure_table(c, n);  // a failed table build leaves tab_ok false: the layers are evaluated
     if (c->en[c->active].wide) {
@@ -1039,13 +1111,16 @@ void eval_backward(dp_ctx *c, int64_t n, double *F, double *V) {
   Workspace &w = c->ws;
   hipStream_t s = c->stream;
   const int64_t rows = eval_rows(c, n);
-  if (c->precision == DP_FP64) {
-    launch_fit_f64(s, fit_args(c, rows), 2);
+  if (!prec16(c->precision)) {
+    const bool f32 = c->precision == DP_MIX_FP32;
+    if (f32) launch_fit_f32(s, fit_args32(c, rows), 2);
+    else launch_fit_f64(s, fit_args(c, rows), 2);
     tmark(c, 5);
     launch_zero(s, F, 3 * (c->n_force > 0 ? c->n_force : n));
     const int grid = embed_bwd_grid(rows);
     tmark(c, 6);
-    launch_embed_bwd_f64(s, embed_args(c, n, rows, F), grid);
+    if (f32) launch_embed_bwd_f32(s, embed_args32(c, n, rows, F), grid);
+    else launch_embed_bwd_f64(s, embed_args(c, n, rows, F), grid);
     tmark(c, 9);
     tmark(c, 7);
     launch_sum9(s, w.vir_part, grid, V);
@@ -1388,7 +1463,7 @@ int install_student(dp_ctx *c, HostModel &&m) {
   c->shm = std::move(m);
   int rc = upload_emb(c, c->shm, c->en[1]);
   if (rc) return rc;
-  if (c->precision != DP_FP64) {
+  if (prec16(c->precision)) {
     rc = upload_emb_mix(c, c->shm, c->en[1]);
     if (rc) return rc;
   }
@@ -1503,6 +1578,7 @@ void dp_destroy(dp_ctx *c) {
   free_ws(c->ws);
   for (auto &en : c->en) {
     if (en.d_emb) (void)hipFree(en.d_emb);
+    if (en.d_emb32) (void)hipFree(en.d_emb32);
     if (en.d_mix) (void)hipFree(en.d_mix);
     if (en.d_tab) (void)hipFree(en.d_tab);
     if (en.d_wide) (void)hipFree(en.d_wide);
@@ -1510,6 +1586,7 @@ void dp_destroy(dp_ctx *c) {
   free_wide(c);
   free_student(c);
   if (c->d_fit) (void)hipFree(c->d_fit);
+  if (c->d_fit32) (void)hipFree(c->d_fit32);
   if (c->d_fit_mix) (void)hipFree(c->d_fit_mix);
   if (c->h_status) (void)hipHostFree(c->h_status);
   for (auto &e : c->ev)
@@ -1521,8 +1598,7 @@ const char *dp_last_error(const dp_ctx *c) { return c ? c->err.c_str() : "NULL c
 
 int dp_set_model(dp_ctx *c, const void *blob, size_t nbytes, int precision) {
   if (!c || !blob) return fail(c, DP_E_ARG, "NULL argument");
-  if (precision != DP_FP64 && precision != DP_MIX_FP16 && precision != DP_MIX_BF16)
-    return fail(c, DP_E_ARG, "unsupported precision policy");
+  if (!prec_ok(precision)) return fail(c, DP_E_ARG, "unsupported precision policy");
   HIPCHK(c, hipSetDevice(c->device));
   c->fwd_ready = false;  // the workspace a pending backward needs is freed below
   HostModel m;
@@ -1539,9 +1615,9 @@ int dp_set_model(dp_ctx *c, const void *blob, size_t nbytes, int precision) {
   int rc = upload_model(c);
   if (rc) return rc;
   const char *why = nullptr;
-  if (precision == DP_FP64 && !f64_emb_ok(c->dims, &why)) return fail(c, DP_E_MODEL, why);
+  if (!prec16(precision) && !f64_emb_ok(c->dims, &why)) return fail(c, DP_E_MODEL, why);
   c->precision = precision;
-  if (precision != DP_FP64) {
+  if (prec16(precision)) {
     rc = upload_mix(c);
     if (rc) return rc;
   }
@@ -1552,14 +1628,13 @@ int dp_set_model(dp_ctx *c, const void *blob, size_t nbytes, int precision) {
 int dp_set_precision(dp_ctx *c, int precision) {
   if (!c) return DP_E_ARG;
   if (!c->has_model) return fail(c, DP_E_NOMODEL, "no model");
-  if (precision != DP_FP64 && precision != DP_MIX_FP16 && precision != DP_MIX_BF16)
-    return fail(c, DP_E_ARG, "unsupported precision policy");
+  if (!prec_ok(precision)) return fail(c, DP_E_ARG, "unsupported precision policy");
   const char *why = nullptr;
-  if (precision == DP_FP64 && !f64_emb_ok(c->dims, &why)) return fail(c, DP_E_MODEL, why);
+  if (!prec16(precision) && !f64_emb_ok(c->dims, &why)) return fail(c, DP_E_MODEL, why);
   const int old = c->precision;
   c->fwd_ready = false;  // the forward's buffers belong to the old precision
   c->precision = precision;
-  if (precision != DP_FP64) {
+  if (prec16(precision)) {
     int rc = upload_mix(c);
     if (rc) {
       c->precision = old;
@@ -2090,8 +2165,8 @@ int dp_student_train(dp_ctx *c, const dp_student_cfg *cfg, double *fit_rmse) {
       (g.refit && (g.ls_samples < g.batch || g.ls_samples % g.batch != 0)))
     return fail(c, DP_E_ARG, "bad student configuration");
   if (c->dims.M1 > 128) return fail(c, DP_E_MODEL, "student nets need M1 <= 128");
-  if (c->precision != DP_FP64 && c->dims.M1 != 100)
-    return fail(c, DP_E_MODEL, "the mixed-precision student kernels exist for M1 = 100 only");
+  if (prec16(c->precision) && c->dims.M1 != 100)
+    return fail(c, DP_E_MODEL, "the 16-bit student kernels exist for M1 = 100 only");
   HIPCHK(c, hipSetDevice(c->device));
   int rc = ensure_student(c, g.batch);
   if (rc) return rc;

@@ -198,11 +198,14 @@ __device__ inline double rsqrt64(double x) {
 void launch_env(hipStream_t s, int64_t n, const double4 *xw, const Dims &d, const double *L, const int32_t *nlist,
                 const int32_t *nreal, double4 *rt, float4 *rt32, double4 *dr);
 
-// ---- FP64 embedding + descriptor (k_embed_f64.hip) ----
-struct EmbedArgs {
+// ---- FP64 / FP32 embedding + descriptor (k_embed_f64.hip) ----
+// Real = double (DP_FP64) or float (DP_MIX_FP32: weights, R, T, D and dE/dD
+// in FP32; displacements, the force Jacobian, forces and the virial in FP64)
+template <typename Real, typename Real4>
+struct EmbedArgsT {
   Dims d;
   EmbOffsets eo;
-  const double *ew;          // padded embedding weights
+  const Real *ew;            // padded embedding weights
   const int32_t *atom_of_pos;
   const int32_t *pos_of_atom;
   const int32_t *type_start; // [ntypes+1] padded row starts
@@ -210,34 +213,43 @@ struct EmbedArgs {
   int64_t natoms;
   const double4 *xw;
   const int32_t *nlist, *nreal;
-  const double4 *rt, *dr;
-  double *T;                 // [natoms][M1][4]
-  double *D;                 // [rows][M1*M2]
-  const double *dD;          // [rows][M1*M2]
+  const Real4 *rt;           // environment rows
+  const double4 *dr;         // displacements (dx, dy, dz, r)
+  Real *T;                   // [natoms][M1][4]
+  Real *D;                   // [rows][M1*M2]
+  const Real *dD;            // [rows][M1*M2]
   double *force;             // [natoms][3]
   double *vir_part;          // [grid][9]
   double *net_deriv;         // optional [natoms][nnei][4]
 };
+typedef EmbedArgsT<double, double4> EmbedArgs;
+typedef EmbedArgsT<float, float4> EmbedArgs32;
 void launch_embed_fwd_f64(hipStream_t s, const EmbedArgs &a);
 void launch_embed_bwd_f64(hipStream_t s, const EmbedArgs &a, int grid);
+void launch_embed_fwd_f32(hipStream_t s, const EmbedArgs32 &a);
+void launch_embed_bwd_f32(hipStream_t s, const EmbedArgs32 &a, int grid);
 int embed_bwd_grid(int64_t rows);
 
-// ---- FP64 fitting net (k_fit_f64.hip) ----
-struct FitArgs {
+// ---- FP64 / FP32 fitting net (k_fit_f64.hip) ----
+template <typename Real>
+struct FitArgsT {
   Dims d;
   FitOffsets fo;
-  const double *fwt;          // fitting weights
+  const Real *fwt;            // fitting weights
   const int32_t *type_start;  // [ntypes+1] padded row starts (device)
   const int32_t *atom_of_pos; // [rows]
   int64_t rows;
-  double *X0;                 // D [rows][fw0]
-  double *Y[MAXF + 1];        // Y[l] l=1..n_fit [rows][fw[l]]
-  double *Tt[MAXF + 1];       // tanh outputs per layer [rows][fw[l]]
-  double *G[MAXF + 1];        // gradient wrt Y[l] [rows][fw[l]]; G[0] = dD
+  Real *X0;                   // D [rows][fw0]
+  Real *Y[MAXF + 1];          // Y[l] l=1..n_fit [rows][fw[l]]
+  Real *Tt[MAXF + 1];         // tanh outputs per layer [rows][fw[l]]
+  Real *G[MAXF + 1];          // gradient wrt Y[l] [rows][fw[l]]; G[0] = dD
   double *eatom;              // [natoms] (original order)
 };
+typedef FitArgsT<double> FitArgs;
+typedef FitArgsT<float> FitArgs32;
 // pass 1: forward layers and E_i; pass 2: backward to dE/dD
 void launch_fit_f64(hipStream_t s, const FitArgs &a, int pass);
+void launch_fit_f32(hipStream_t s, const FitArgs32 &a, int pass);
 
 // ---- reductions and MD (k_md.hip) ----
 void launch_sum(hipStream_t s, const double *x, int64_t n, double *partial, double *out, double scale);

@@ -1,4 +1,6 @@
-// Double-precision embedding net + descriptor, fused per centre atom so the
+// Double-precision embedding net + descriptor (and the same kernels in
+// single precision for DP_MIX_FP32, the paper's MIX-32 scheme, Section V-B
+// "Mixed-precision computation"), fused per centre atom so the
 // embedding matrix G never reaches HBM (Section V-B, "Increasing
 // computational granularity": the type-sorted, padded list lets every tile
 // of neighbours use one net without branching).
@@ -60,15 +62,18 @@ static EmbLds emb_lds_layout(const Dims &d, int pass) {
 // ---------------------------------------------------------------------------
 // pass 1
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, EmbLds L) {
-  extern __shared__ double smem[];
+template <typename Real>
+__global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgsT<Real, typename MF<Real>::vec4> a,
+                                                                EmbLds L) {
+  extern __shared__ __align__(16) unsigned char emb_smem[];
+  Real *smem = (Real *)emb_smem;
   const Dims &d = a.d;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  double *lds = smem + wv * L.per_wave;
-  double *Rl = lds + L.off_rt;
-  double *Tl = lds + L.off_t;
-  double *Gt = lds + L.off_g;
+  Real *lds = smem + wv * L.per_wave;
+  Real *Rl = lds + L.off_rt;
+  Real *Tl = lds + L.off_t;
+  Real *Gt = lds + L.off_g;
   const int64_t nwaves = (int64_t)gridDim.x * EMB_WAVES;
   const int64_t gw = (int64_t)blockIdx.x * EMB_WAVES + wv;
   const int64_t chunk = (a.rows + nwaves - 1) / nwaves;
@@ -79,7 +84,7 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
 
   for (int64_t p = gw * chunk; p < p_end; ++p) {
     const int i = a.atom_of_pos[p];
-    double *Dp = a.D + p * (int64_t)MM;
+    Real *Dp = a.D + p * (int64_t)MM;
     if (i < 0) {
       for (int o = lane; o < MM; o += 64) Dp[o] = 0.0;
       continue;
@@ -91,13 +96,13 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
     for (int u = 0; u < d.ntypes; ++u) {
       const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
       const int64_t base = (int64_t)i * d.nnei + d.off[u];
-      const double *W0 = a.ew + a.eo.w[t][u][0];
-      const double *b0 = a.ew + a.eo.b[t][u][0];
+      const Real *W0 = a.ew + a.eo.w[t][u][0];
+      const Real *b0 = a.ew + a.eo.b[t][u][0];
       for (int n0 = 0; n0 < cnt; n0 += 16) {
         if (lane < 16) {
           // unconditional load: slots past the block reread its last row, then are zeroed
-          double4 r4 = a.rt[base + (n0 + lane < cnt ? n0 + lane : cnt - 1)];
-          if (n0 + lane >= cnt) r4 = make_double4(0.0, 0.0, 0.0, 0.0);
+          typename MF<Real>::vec4 r4 = a.rt[base + (n0 + lane < cnt ? n0 + lane : cnt - 1)];
+          if (n0 + lane >= cnt) r4 = MF<Real>::zero4();
           Rl[lane * 4 + 0] = r4.x;
           Rl[lane * 4 + 1] = r4.y;
           Rl[lane * 4 + 2] = r4.z;
@@ -108,13 +113,13 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
         {
           const int out1 = d.ew[1];
           const int rows = d.ekp[1];
-          double *H = lds + L.off_buf[0];
+          Real *H = lds + L.off_buf[0];
           for (int idx = lane; idx < rows * 16; idx += 64) {
             const int f = idx >> 4, n = idx & 15;
-            const double s = Rl[n * 4];
-            double h = 0.0;
+            const Real s = Rl[n * 4];
+            Real h = 0;
             if (f < out1) {
-              h = tanh64(s * W0[f] + b0[f]);
+              h = MF<Real>::tanh_(s * W0[f] + b0[f]);
               if (out1 == 1 || out1 == 2) h += s;
             }
             H[f * 16 + n] = h;
@@ -127,14 +132,14 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
         for (int l = 1; l < d.n_emb; ++l) {
           const int in = d.ew[l], out = d.ew[l + 1];
           const bool last = l == d.n_emb - 1;
-          const double *Hin = lds + L.off_buf[(l - 1) & 1];
-          double *Hout = lds + L.off_buf[l & 1];
+          const Real *Hin = lds + L.off_buf[(l - 1) & 1];
+          Real *Hout = lds + L.off_buf[l & 1];
           const int rows_out = last ? 0 : d.ekp[l + 1];
-          const double *W = a.ew + a.eo.w[t][u][l];
-          const double *bias = a.ew + a.eo.b[t][u][l];
+          const Real *W = a.ew + a.eo.w[t][u][l];
+          const Real *bias = a.ew + a.eo.b[t][u][l];
           const int nmt = d.emp[l + 1] >> 4;
           for (int mt0 = 0; mt0 < nmt; mt0 += EMB_G) {
-            v4d acc[1][EMB_G];
+            typename MF<Real>::acc acc[1][EMB_G];
             mfma_group<1>(W, d.ekp[l], d.emp[l + 1], Hin, 16, lane, mt0, acc);
 #pragma unroll
             for (int g = 0; g < EMB_G; ++g) {
@@ -142,34 +147,34 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
               if (mt < nmt) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                  const int f = mt * 16 + 4 * r + (lane >> 4), n = lane & 15;
-                  double h = 0.0;
+                  const int f = mt * 16 + MF<Real>::row(r, lane >> 4), n = lane & 15;
+                  Real h = 0;
                   if (f < out) {
-                    const double z = acc[0][g][r] + bias[f];
-                    h = (d.emb_lin && last) ? z : tanh64(z);
+                    const Real z = acc[0][g][r] + bias[f];
+                    h = (d.emb_lin && last) ? z : MF<Real>::tanh_(z);
                     const int sf = skip_src(f, in, out);
                     if (sf >= 0) h += Hin[sf * 16 + n];
                   }
-                  if (last) Gt[(4 * r + (lane >> 4)) * 16 + n] = h;
+                  if (last) Gt[MF<Real>::row(r, lane >> 4) * 16 + n] = h;
                   else if (f < rows_out) Hout[f * 16 + n] = h;
                 }
                 if (last) {
                   wave_sync();
-                  // register r of lane (g, c) holds T[16 mt + 4 r + g][c]
+                  // register r of lane (g, c) holds T[16 mt + row(r, g)][c]
                   const int comp = lane & 15;
-                  double *Tr = Tl + (mt * 16 + (lane >> 4)) * 4 + comp;
-                  v4d tacc;
+                  Real *Tr = Tl + mt * 64 + comp;
+                  typename MF<Real>::acc tacc;
 #pragma unroll
-                  for (int r = 0; r < 4; ++r) tacc[r] = comp < 4 ? Tr[16 * r] : 0.0;
+                  for (int r = 0; r < 4; ++r) tacc[r] = comp < 4 ? Tr[4 * MF<Real>::row(r, lane >> 4)] : Real(0);
 #pragma unroll
                   for (int kn = 0; kn < 4; ++kn) {
                     const int nb = kn * 4 + (lane >> 4);
-                    const double bv = comp < 4 ? Rl[nb * 4 + comp] : 0.0;
-                    tacc = mfma64(Gt[(lane & 15) * 16 + nb], bv, tacc);
+                    const Real bv = comp < 4 ? Rl[nb * 4 + comp] : Real(0);
+                    tacc = MF<Real>::mma(Gt[(lane & 15) * 16 + nb], bv, tacc);
                   }
                   if (comp < 4)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) Tr[16 * r] = tacc[r];
+                    for (int r = 0; r < 4; ++r) Tr[4 * MF<Real>::row(r, lane >> 4)] = tacc[r];
                   wave_sync();
                 }
               }
@@ -181,9 +186,9 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
     }
     // T = sum / Nc -> global and LDS
     {
-      double *Tg = a.T + (int64_t)i * d.M1 * 4;
+      Real *Tg = a.T + (int64_t)i * d.M1 * 4;
       for (int o = lane; o < M1p * 4; o += 64) {
-        const double v = Tl[o] * d.inv_nc;
+        const Real v = Tl[o] * (Real)d.inv_nc;
         Tl[o] = v;
         if ((o >> 2) < d.M1) Tg[o] = v;
       }
@@ -192,12 +197,13 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgs a, E
     // D = T T_<^T : one MFMA step of K = 4 per output tile
     {
       const int b = lane & 15;
-      const double bv = b < d.M2 ? Tl[b * 4 + (lane >> 4)] : 0.0;
+      const Real bv = b < d.M2 ? Tl[b * 4 + (lane >> 4)] : Real(0);
       for (int mt = 0; mt < nmtG; ++mt) {
-        v4d z = mfma64(Tl[(mt * 16 + (lane & 15)) * 4 + (lane >> 4)], bv, v4d{0.0, 0.0, 0.0, 0.0});
+        typename MF<Real>::acc z = MF<Real>::mma(Tl[(mt * 16 + (lane & 15)) * 4 + (lane >> 4)], bv,
+                                                 typename MF<Real>::acc{0, 0, 0, 0});
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int f = mt * 16 + 4 * r + (lane >> 4);
+          const int f = mt * 16 + MF<Real>::row(r, lane >> 4);
           if (f < d.M1 && b < d.M2) Dp[f * d.M2 + b] = z[r];
         }
       }
@@ -223,15 +229,18 @@ __device__ inline void switch_fn(double r, double rcs, double rc, double inv_w, 
   }
 }
 
-__global__ void __launch_bounds__(64 * EMB_WAVES) __attribute__((amdgpu_waves_per_eu(2))) k_embed_bwd_f64(EmbedArgs a, EmbLds L) {
-  extern __shared__ double smem[];
+template <typename Real>
+__global__ void __launch_bounds__(64 * EMB_WAVES) __attribute__((amdgpu_waves_per_eu(2)))
+k_embed_bwd_f64(EmbedArgsT<Real, typename MF<Real>::vec4> a, EmbLds L) {
+  extern __shared__ __align__(16) unsigned char emb_smem[];
+  Real *smem = (Real *)emb_smem;
   __shared__ double vred[EMB_WAVES][9];
   const Dims &d = a.d;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  double *lds = smem + wv * L.per_wave;
-  double *Rl = lds + L.off_rt;
-  double *dTl = lds + L.off_t;
+  Real *lds = smem + wv * L.per_wave;
+  Real *Rl = lds + L.off_rt;
+  Real *dTl = lds + L.off_t;
   const int64_t nwaves = (int64_t)gridDim.x * EMB_WAVES;
   const int64_t gw = (int64_t)blockIdx.x * EMB_WAVES + wv;
   const int64_t chunk = (a.rows + nwaves - 1) / nwaves;
@@ -249,17 +258,17 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) __attribute__((amdgpu_waves_pe
     const int t = (int)a.xw[i].w;
     // dT / Nc
     {
-      const double *Ti = a.T + (int64_t)i * d.M1 * 4;
-      const double *dDp = a.dD + p * (int64_t)MM;
+      const Real *Ti = a.T + (int64_t)i * d.M1 * 4;
+      const Real *dDp = a.dD + p * (int64_t)MM;
       for (int o = lane; o < M1p * 4; o += 64) {
         const int f = o >> 2, k = o & 3;
-        double v = 0.0;
+        Real v = 0;
         if (f < d.M1) {
           for (int b = 0; b < d.M2; ++b) v += dDp[f * d.M2 + b] * Ti[b * 4 + k];
           if (f < d.M2)
             for (int a2 = 0; a2 < d.M1; ++a2) v += dDp[a2 * d.M2 + f] * Ti[a2 * 4 + k];
         }
-        dTl[o] = v * d.inv_nc;
+        dTl[o] = v * (Real)d.inv_nc;
       }
     }
     wave_sync();
@@ -267,11 +276,12 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) __attribute__((amdgpu_waves_pe
     for (int u = 0; u < d.ntypes; ++u) {
       const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
       const int64_t base = (int64_t)i * d.nnei + d.off[u];
-      const double *W0 = a.ew + a.eo.w[t][u][0];
-      const double *b0 = a.ew + a.eo.b[t][u][0];
+      const Real *W0 = a.ew + a.eo.w[t][u][0];
+      const Real *b0 = a.ew + a.eo.b[t][u][0];
       for (int n0 = 0; n0 < cnt; n0 += 16) {
         const bool valid = lane < 16 && n0 + lane < cnt;
-        double4 R4 = make_double4(0.0, 0.0, 0.0, 0.0), D4 = make_double4(0.0, 0.0, 0.0, 1.0);
+        typename MF<Real>::vec4 R4 = MF<Real>::zero4();
+        double4 D4 = make_double4(0.0, 0.0, 0.0, 1.0);
         int j = -1;
         if (valid) {
           R4 = a.rt[base + n0 + lane];
@@ -288,18 +298,18 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) __attribute__((amdgpu_waves_pe
         // layer 0 with tangent: h and dh/ds side by side (columns 0..15, 16..31)
         {
           const int out1 = d.ew[1];
-          double *H = lds + L.off_buf[0];
+          Real *H = lds + L.off_buf[0];
           for (int idx = lane; idx < d.ekp[1] * 16; idx += 64) {
             const int f = idx >> 4, n = idx & 15;
-            const double s = Rl[n * 4];
-            double h = 0.0, hd = 0.0;
+            const Real s = Rl[n * 4];
+            Real h = 0, hd = 0;
             if (f < out1) {
-              const double th = tanh64(s * W0[f] + b0[f]);
+              const Real th = MF<Real>::tanh_(s * W0[f] + b0[f]);
               h = th;
-              hd = (1.0 - th * th) * W0[f];
+              hd = (Real(1) - th * th) * W0[f];
               if (out1 == 1 || out1 == 2) {
                 h += s;
-                hd += 1.0;
+                hd += Real(1);
               }
             }
             H[f * 32 + n] = h;
@@ -307,18 +317,18 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) __attribute__((amdgpu_waves_pe
           }
         }
         wave_sync();
-        double ga[4] = {0.0, 0.0, 0.0, 0.0}, gb[4] = {0.0, 0.0, 0.0, 0.0};
+        Real ga[4] = {0, 0, 0, 0}, gb[4] = {0, 0, 0, 0};
         for (int l = 1; l < d.n_emb; ++l) {
           const int in = d.ew[l], out = d.ew[l + 1];
           const bool last = (l == d.n_emb - 1);
-          const double *Hin = lds + L.off_buf[(l - 1) & 1];
-          double *Hout = lds + L.off_buf[l & 1];
+          const Real *Hin = lds + L.off_buf[(l - 1) & 1];
+          Real *Hout = lds + L.off_buf[l & 1];
           const int rows_out = last ? 0 : d.ekp[l + 1];
-          const double *W = a.ew + a.eo.w[t][u][l];
-          const double *bias = a.ew + a.eo.b[t][u][l];
+          const Real *W = a.ew + a.eo.w[t][u][l];
+          const Real *bias = a.ew + a.eo.b[t][u][l];
           const int nmt = d.emp[l + 1] >> 4;
           for (int mt0 = 0; mt0 < nmt; mt0 += EMB_G) {
-            v4d acc[2][EMB_G];
+            typename MF<Real>::acc acc[2][EMB_G];
             mfma_group<2>(W, d.ekp[l], d.emp[l + 1], Hin, 32, lane, mt0, acc);
 #pragma unroll
             for (int g = 0; g < EMB_G; ++g) {
@@ -326,14 +336,14 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) __attribute__((amdgpu_waves_pe
               if (mt >= nmt) continue;
 #pragma unroll
               for (int r = 0; r < 4; ++r) {
-                const int f = mt * 16 + 4 * r + (lane >> 4), n = lane & 15;
-                double h = 0.0, hd = 0.0;
+                const int f = mt * 16 + MF<Real>::row(r, lane >> 4), n = lane & 15;
+                Real h = 0, hd = 0;
                 if (f < out) {
-                  const double z = acc[0][g][r] + bias[f];
+                  const Real z = acc[0][g][r] + bias[f];
                   const bool lin = d.emb_lin && last;
-                  const double th = lin ? z : tanh64(z);
+                  const Real th = lin ? z : MF<Real>::tanh_(z);
                   h = th;
-                  hd = lin ? acc[1][g][r] : (1.0 - th * th) * acc[1][g][r];
+                  hd = lin ? acc[1][g][r] : (Real(1) - th * th) * acc[1][g][r];
                   const int sf = skip_src(f, in, out);
                   if (sf >= 0) {
                     h += Hin[sf * 32 + n];
@@ -342,7 +352,7 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) __attribute__((amdgpu_waves_pe
                 }
                 if (last) {
                   if (f < out) {
-                    const double *dt = dTl + f * 4;
+                    const Real *dt = dTl + f * 4;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                       ga[k] += h * dt[k];
@@ -367,9 +377,10 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) __attribute__((amdgpu_waves_pe
           gb[k] += __shfl_xor(gb[k], 32);
         }
         if (valid) {
-          // dE/dR_j (the 1/Nc is inside dT); the embedding path adds to the s component
-          const double g0 = ga[0] + (R4.x * gb[0] + R4.y * gb[1] + R4.z * gb[2] + R4.w * gb[3]);
-          const double g1 = ga[1], g2 = ga[2], g3 = ga[3];
+          // dE/dR_j (the 1/Nc is inside dT; in the network's precision); the
+          // embedding path adds to the s component; the Jacobian in FP64
+          const double g0 = (double)(ga[0] + (R4.x * gb[0] + R4.y * gb[1] + R4.z * gb[2] + R4.w * gb[3]));
+          const double g1 = (double)ga[1], g2 = (double)ga[2], g3 = (double)ga[3];
           if (a.net_deriv) {
             double *nd = a.net_deriv + (base + n0 + lane) * 4;
             nd[0] = g0;
@@ -437,18 +448,26 @@ static int emb_grid(int64_t rows) {
 
 int embed_bwd_grid(int64_t rows) { return emb_grid(rows); }
 
-void launch_embed_fwd_f64(hipStream_t s, const EmbedArgs &a) {
+template <typename Real>
+static void launch_fwd_t(hipStream_t s, const EmbedArgsT<Real, typename MF<Real>::vec4> &a) {
   EmbLds L = emb_lds_layout(a.d, 1);
-  size_t shm = sizeof(double) * (size_t)L.per_wave * EMB_WAVES;
-  hipLaunchKernelGGL(k_embed_fwd_f64, dim3(emb_grid(a.rows)), dim3(64 * EMB_WAVES), shm, s, a, L);
+  size_t shm = sizeof(Real) * (size_t)L.per_wave * EMB_WAVES;
+  hipLaunchKernelGGL(k_embed_fwd_f64<Real>, dim3(emb_grid(a.rows)), dim3(64 * EMB_WAVES), shm, s, a, L);
 }
 
-void launch_embed_bwd_f64(hipStream_t s, const EmbedArgs &a, int grid) {
+template <typename Real>
+static void launch_bwd_t(hipStream_t s, const EmbedArgsT<Real, typename MF<Real>::vec4> &a, int grid) {
   EmbLds L = emb_lds_layout(a.d, 2);
-  size_t shm = sizeof(double) * (size_t)L.per_wave * EMB_WAVES;
-  hipLaunchKernelGGL(k_embed_bwd_f64, dim3(grid), dim3(64 * EMB_WAVES), shm, s, a, L);
+  size_t shm = sizeof(Real) * (size_t)L.per_wave * EMB_WAVES;
+  hipLaunchKernelGGL(k_embed_bwd_f64<Real>, dim3(grid), dim3(64 * EMB_WAVES), shm, s, a, L);
 }
 
+void launch_embed_fwd_f64(hipStream_t s, const EmbedArgs &a) { launch_fwd_t<double>(s, a); }
+void launch_embed_bwd_f64(hipStream_t s, const EmbedArgs &a, int grid) { launch_bwd_t<double>(s, a, grid); }
+void launch_embed_fwd_f32(hipStream_t s, const EmbedArgs32 &a) { launch_fwd_t<float>(s, a); }
+void launch_embed_bwd_f32(hipStream_t s, const EmbedArgs32 &a, int grid) { launch_bwd_t<float>(s, a, grid); }
+
+// LDS bytes of the FP64 kernels (the FP32 ones take half)
 size_t embed_lds_bytes(const Dims &d, int pass) {
   EmbLds L = emb_lds_layout(d, pass);
   return sizeof(double) * (size_t)L.per_wave * EMB_WAVES;

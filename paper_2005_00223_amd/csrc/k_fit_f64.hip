@@ -12,30 +12,30 @@
 // loaded, gY_l = gZ W^T (+ the skip's pass-through), gY_0 = dE/dD.
 //
 // MFMA v_mfma_f64_16x16x4 (D register r of lane l is row 4r + l/16,
-// column l%16); block tile 64 x 64, four waves of 32 x 32, K staged through
-// LDS in steps of 16.
-#include "dp_internal.h"
+// column l%16), or v_mfma_f32_16x16x4_f32 for DP_MIX_FP32 (row 4(l/16) + r);
+// block tile 64 x 64, four waves of 32 x 32, K staged through LDS in steps
+// of 16.  The per-atom energies are written in double either way.
+#include "dp_f64.h"
 
 namespace dpk {
-
-typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 16, APAD = BK + 1;
 
 enum { FIT_FWD = 0, FIT_BWD = 1 };
 
+template <typename Real>
 struct GemmArgs {
   int mode, layer, K, N, in, out;  // in/out of the layer (fwd: K=in, N=out; bwd: K=out, N=in)
   int ntypes;
   const int32_t *type_start;
-  const double *fwt;
+  const Real *fwt;
   FitOffsets fo;
-  const double *X;    // fwd: layer input [rows][in]
-  double *Tt;         // fwd: tanh output [rows][out] (written); bwd: read
-  double *Y;          // fwd: layer output [rows][out]
-  const double *gY;   // bwd: gradient wrt the layer output [rows][out] (NULL = output weights)
-  const double *wout; // bwd: output-layer weights of each type when gY == NULL (offset by type)
-  double *gX;         // bwd: gradient wrt the layer input [rows][in]
+  const Real *X;    // fwd: layer input [rows][in]
+  Real *Tt;         // fwd: tanh output [rows][out] (written); bwd: read
+  Real *Y;          // fwd: layer output [rows][out]
+  const Real *gY;   // bwd: gradient wrt the layer output [rows][out] (NULL = output weights)
+  const Real *wout; // bwd: output-layer weights of each type when gY == NULL (offset by type)
+  Real *gX;         // bwd: gradient wrt the layer input [rows][in]
 };
 
 __device__ inline int row_type(const int32_t *ts, int ntypes, int64_t r0) {
@@ -45,24 +45,24 @@ __device__ inline int row_type(const int32_t *ts, int ntypes, int64_t r0) {
   return t;
 }
 
-template <int MODE>
-__global__ void __launch_bounds__(256) k_fit_gemm(GemmArgs g) {
-  __shared__ double As[BM][APAD];
-  __shared__ double Bs[BK][BN];
+template <int MODE, typename Real>
+__global__ void __launch_bounds__(256) k_fit_gemm(GemmArgs<Real> g) {
+  __shared__ Real As[BM][APAD];
+  __shared__ Real Bs[BK][BN];
   const int64_t r0 = (int64_t)blockIdx.x * BM;
   const int c0 = blockIdx.y * BN;
   if (r0 >= g.type_start[g.ntypes]) return;
   const int t = row_type(g.type_start, g.ntypes, r0);
-  const double *W = g.fwt + g.fo.w[t][g.layer];
-  const double *bias = g.fwt + g.fo.b[t][g.layer];
-  const double *wo = (MODE == FIT_BWD && g.gY == nullptr) ? g.fwt + g.fo.w[t][g.layer + 1] : nullptr;
+  const Real *W = g.fwt + g.fo.w[t][g.layer];
+  const Real *bias = g.fwt + g.fo.b[t][g.layer];
+  const Real *wo = (MODE == FIT_BWD && g.gY == nullptr) ? g.fwt + g.fo.w[t][g.layer + 1] : nullptr;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = wv >> 1, wn = wv & 1;
-  v4d acc[2][2];
+  typename MF<Real>::acc acc[2][2];
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = typename MF<Real>::acc{0, 0, 0, 0};
 
   for (int k0 = 0; k0 < g.K; k0 += BK) {
     // A tile [64 x 16]
@@ -71,15 +71,15 @@ __global__ void __launch_bounds__(256) k_fit_gemm(GemmArgs g) {
       const int e = tid + q * 256;
       const int rr = e >> 4, kk = e & 15;
       const int k = k0 + kk;
-      double v = 0.0;
+      Real v = 0;
       if (k < g.K) {
         const int64_t row = r0 + rr;
         if (MODE == FIT_FWD) {
           v = g.X[row * g.K + k];
         } else {
-          const double th = g.Tt[row * g.K + k];
-          const double gy = wo ? wo[k] : g.gY[row * g.K + k];
-          v = gy * (1.0 - th * th);
+          const Real th = g.Tt[row * g.K + k];
+          const Real gy = wo ? wo[k] : g.gY[row * g.K + k];
+          v = gy * (Real(1) - th * th);
         }
       }
       As[rr][kk] = v;
@@ -90,14 +90,14 @@ __global__ void __launch_bounds__(256) k_fit_gemm(GemmArgs g) {
       const int e = tid + q * 256;
       const int kk = e >> 6, cc = e & 63;
       const int k = k0 + kk, c = c0 + cc;
-      double v = 0.0;
+      Real v = 0;
       if (k < g.K && c < g.N) v = (MODE == FIT_FWD) ? W[(int64_t)k * g.N + c] : W[(int64_t)c * g.K + k];
       Bs[kk][cc] = v;
     }
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
-      double af[2], bf[2];
+      Real af[2], bf[2];
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi) af[mi] = As[wm * 32 + mi * 16 + (lane & 15)][ks + (lane >> 4)];
 #pragma unroll
@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256) k_fit_gemm(GemmArgs g) {
       for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 2; ++ni)
-          acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+          acc[mi][ni] = MF<Real>::mma(af[mi], bf[ni], acc[mi][ni]);
     }
     __syncthreads();
   }
@@ -117,19 +117,19 @@ __global__ void __launch_bounds__(256) k_fit_gemm(GemmArgs g) {
     for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + wm * 32 + mi * 16 + 4 * r + (lane >> 4);
+        const int64_t row = r0 + wm * 32 + mi * 16 + MF<Real>::row(r, lane >> 4);
         const int col = c0 + wn * 32 + ni * 16 + (lane & 15);
         if (col >= g.N) continue;
-        const double c = acc[mi][ni][r];
+        const Real c = acc[mi][ni][r];
         if (MODE == FIT_FWD) {
-          const double th = tanh64(c + bias[col]);
-          double y = th;
+          const Real th = MF<Real>::tanh_(c + bias[col]);
+          Real y = th;
           if (g.out == g.in) y += g.X[row * g.in + col];
           else if (g.out == 2 * g.in) y += g.X[row * g.in + (col >= g.in ? col - g.in : col)];
           g.Tt[row * g.out + col] = th;
           g.Y[row * g.out + col] = y;
         } else {
-          double v = c;
+          Real v = c;
           if (g.out == g.in || g.out == 2 * g.in) {
             v += wo ? wo[col] : g.gY[row * g.out + col];
             if (g.out == 2 * g.in) v += wo ? wo[col + g.in] : g.gY[row * g.out + col + g.in];
@@ -139,9 +139,10 @@ __global__ void __launch_bounds__(256) k_fit_gemm(GemmArgs g) {
       }
 }
 
-// E_i = Y_L . w_out + b_out, one wave per row
+// E_i = Y_L . w_out + b_out, one wave per row (in Real, stored as double)
+template <typename Real>
 __global__ void __launch_bounds__(256) k_fit_out(const int32_t *type_start, int ntypes, const int32_t *atom_of_pos,
-                                                 const double *fwt, FitOffsets fo, int L, int width, const double *Y,
+                                                 const Real *fwt, FitOffsets fo, int L, int width, const Real *Y,
                                                  int64_t rows_cap, double *eatom) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -149,20 +150,21 @@ __global__ void __launch_bounds__(256) k_fit_out(const int32_t *type_start, int 
   const int atom = atom_of_pos[row];
   if (atom < 0) return;
   const int t = row_type(type_start, ntypes, row);
-  const double *w = fwt + fo.w[t][L];
-  double s = 0.0;
+  const Real *w = fwt + fo.w[t][L];
+  Real s = 0;
   for (int o = lane; o < width; o += 64) s += Y[row * width + o] * w[o];
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-  if (lane == 0) eatom[atom] = s + fwt[fo.b[t][L]];
+  if (lane == 0) eatom[atom] = (double)(s + fwt[fo.b[t][L]]);
 }
 
-void launch_fit_f64(hipStream_t s, const FitArgs &a, int pass) {
+template <typename Real>
+static void launch_fit_t(hipStream_t s, const FitArgsT<Real> &a, int pass) {
   const Dims &d = a.d;
   const int L = d.n_fit;
   const unsigned gm = (unsigned)((a.rows + BM - 1) / BM);
   for (int l = 0; l < L && pass == 1; ++l) {
-    GemmArgs g{};
+    GemmArgs<Real> g{};
     g.mode = FIT_FWD;
     g.layer = l;
     g.in = d.fw[l];
@@ -176,13 +178,13 @@ void launch_fit_f64(hipStream_t s, const FitArgs &a, int pass) {
     g.X = (l == 0) ? a.X0 : a.Y[l];
     g.Tt = a.Tt[l + 1];
     g.Y = a.Y[l + 1];
-    hipLaunchKernelGGL(k_fit_gemm<FIT_FWD>, dim3(gm, (unsigned)((g.N + BN - 1) / BN)), dim3(256), 0, s, g);
+    hipLaunchKernelGGL((k_fit_gemm<FIT_FWD, Real>), dim3(gm, (unsigned)((g.N + BN - 1) / BN)), dim3(256), 0, s, g);
   }
   if (pass == 1)
-    hipLaunchKernelGGL(k_fit_out, dim3((unsigned)((a.rows + 3) / 4)), dim3(256), 0, s, a.type_start, d.ntypes,
+    hipLaunchKernelGGL(k_fit_out<Real>, dim3((unsigned)((a.rows + 3) / 4)), dim3(256), 0, s, a.type_start, d.ntypes,
                        a.atom_of_pos, a.fwt, a.fo, L, d.fw[L], a.Y[L], a.rows, a.eatom);
   for (int l = L - 1; l >= 0 && pass == 2; --l) {
-    GemmArgs g{};
+    GemmArgs<Real> g{};
     g.mode = FIT_BWD;
     g.layer = l;
     g.in = d.fw[l];
@@ -196,8 +198,11 @@ void launch_fit_f64(hipStream_t s, const FitArgs &a, int pass) {
     g.Tt = a.Tt[l + 1];
     g.gY = (l == L - 1) ? nullptr : a.G[l + 1];
     g.gX = a.G[l];
-    hipLaunchKernelGGL(k_fit_gemm<FIT_BWD>, dim3(gm, (unsigned)((g.N + BN - 1) / BN)), dim3(256), 0, s, g);
+    hipLaunchKernelGGL((k_fit_gemm<FIT_BWD, Real>), dim3(gm, (unsigned)((g.N + BN - 1) / BN)), dim3(256), 0, s, g);
   }
 }
+
+void launch_fit_f64(hipStream_t s, const FitArgs &a, int pass) { launch_fit_t<double>(s, a, pass); }
+void launch_fit_f32(hipStream_t s, const FitArgs32 &a, int pass) { launch_fit_t<float>(s, a, pass); }
 
 }  // namespace dpk

@@ -22,8 +22,8 @@ def _ptr(t):
 class DPModel:
     """A loaded Deep Potential model on one GPU.
 
-    blob: bytes in the DPMIBLOB layout.  precision: "fp64", "fp16" or
-    "bf16" (mixed-precision kernels)."""
+    blob: bytes in the DPMIBLOB layout.  precision: "fp64", "fp32" (the
+    paper's MIX-32), "fp16" or "bf16" (the 16-bit mixed-precision kernels)."""
 
     def __init__(self, blob: bytes, precision: str = "fp64", device: int | None = None):
         if not torch.cuda.is_available():
