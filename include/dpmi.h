@@ -68,7 +68,7 @@ enum {
  * Coordinates, wrapping, distances, the environment matrix (before its
  * rounding), the force Jacobian, energy / force / virial sums and the
  * integrator stay double in every mode. */
-enum { DP_FP64 = 0, DP_MIX_FP32 = 1, DP_MIX_FP16 = 2, DP_MIX_BF16 = 3 };
+enum { DP_FP64 = 0, DP_MIX_FP32 = 1, DP_MIX_BF16 = 2, DP_MIX_FP16 = 3 };
 
 typedef struct {
   int64_t natoms;            /* atoms in the last dp_compute                 */

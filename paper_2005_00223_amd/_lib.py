@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(_HERE, "libdpmi.so")
 
 DP_OK, DP_E_ARG, DP_E_NOMODEL, DP_E_MODEL, DP_E_BOX, DP_E_TYPE, DP_E_OOM, DP_E_HIP, DP_E_NONFINITE, DP_E_CAP = \
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9
-DP_FP64, DP_MIX_FP32, DP_MIX_FP16, DP_MIX_BF16 = 0, 1, 2, 3
+DP_FP64, DP_MIX_FP32, DP_MIX_BF16, DP_MIX_FP16 = 0, 1, 2, 3
 PRECISION = {"fp64": DP_FP64, "fp32": DP_MIX_FP32, "fp16": DP_MIX_FP16, "bf16": DP_MIX_BF16}
 
 EXPORTS = ("dp_create", "dp_set_model", "dp_set_precision", "dp_compute", "dp_compute_noalloc", "dp_compute_local",
