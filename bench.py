@@ -8,8 +8,8 @@ output layer), then runs the MD steps with the student, the full teacher
 nets judging its forces every 20 steps (fallback above 1e-3 eV/A) on the
 atoms of a 60 A cube placed anew each time (teacher evaluated on the cube
 and its rc margin; --judge-side 0 judges every atom).  The same
-precision without the student, and the FP64 path, are timed after it for
-comparison.
+precision without the student, the FP64 path and the MIX-32 (FP32) path are
+timed after it for comparison.
 
 One step = one velocity-Verlet MD step of the whole hot path: periodic wrap,
 device-side skin check (cell list + candidate list rebuilt when an atom has
@@ -81,9 +81,10 @@ def algorithmic(spec, n_atoms, n_pairs, emb=None, affine=False, mixed=True, tabl
         # mixed precision: 16 B, and no (d, r); else 32 B and (d, r) 32 B) out
         "env": n_pairs * (4 + 32 + (16.0 if mixed else 64.0)) + n_atoms * (32 + 4 * spec.ntypes),
         # bytes: per candidate (neighbours within rc + skin, n_cand per atom)
-        # its index 4 B + position 32 B in; per real slot 4 B out; own
-        # position and counts per atom
-        "format": n_cand * (4 + 32) + n_pairs * 4 + n_atoms * (32 + 4 * spec.ntypes),
+        # its index 4 B + position 32 B in; per real slot 4 B out (and in
+        # 16-bit mixed precision, where the format kernel also writes the
+        # environment rows, R in FP32 16 B); own position and counts per atom
+        "format": n_cand * (4 + 32) + n_pairs * (4 + (16.0 if mixed else 0.0)) + n_atoms * (32 + 4 * spec.ntypes),
     }
 
 
@@ -457,6 +458,8 @@ def main():
     ap.add_argument("--teacher-steps", type=int, default=5,
                     help="steps of the same precision without the student, timed for comparison (0 = skip)")
     ap.add_argument("--fp64-steps", type=int, default=3, help="FP64 steps timed for the comparison (0 = skip)")
+    ap.add_argument("--fp32-steps", type=int, default=3,
+                    help="MIX-32 steps timed after the FP64 comparison (0 = skip)")
     ap.add_argument("--rmse", default="full",
                     help="force accuracy at the final frame vs the oracle: 'full' (every atom, one oracle "
                          "evaluation of the whole frame), N (N sampled atoms, local oracle evaluations) or 0")
@@ -676,6 +679,14 @@ def main():
         out["fp64_s_per_step_atom"] = s64 / n
         out["speedup_vs_fp64"] = s64 / s_step
         log(f"[bench] fp64 {s64 * 1e3:.1f} ms/step")
+        if args.fp32_steps > 0 and args.precision != "fp32":
+            # the paper's third policy (MIX-32) on the same configuration
+            del m64
+            m32 = DPModel(blob, "fp32")
+            s32 = step_time(m32, x.clone(), v.clone(), f64, args.fp32_steps)
+            out["fp32_s_per_step_atom"] = s32 / n
+            log(f"[bench] fp32 (MIX-32) {s32 * 1e3:.1f} ms/step")
+            del m32
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, blob, args.cpu_seconds, log)
         out["cpu_baseline"]["gpu_over_cpu"] = out["cpu_baseline"]["value"] / out["value"]
