@@ -98,10 +98,14 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgsT<Rea
       const int64_t base = (int64_t)i * d.nnei + d.off[u];
       const Real *W0 = a.ew + a.eo.w[t][u][0];
       const Real *b0 = a.ew + a.eo.b[t][u][0];
+      if (cnt == 0) continue;
+      // environment rows one tile ahead (unconditional loads: slots past the
+      // block reread its last row and are zeroed when used)
+      typename MF<Real>::vec4 r4n = a.rt[base + (lane < cnt ? lane : cnt - 1)];
       for (int n0 = 0; n0 < cnt; n0 += 16) {
+        typename MF<Real>::vec4 r4 = r4n;
+        r4n = a.rt[base + (n0 + 16 + lane < cnt ? n0 + 16 + lane : cnt - 1)];
         if (lane < 16) {
-          // unconditional load: slots past the block reread its last row, then are zeroed
-          typename MF<Real>::vec4 r4 = a.rt[base + (n0 + lane < cnt ? n0 + lane : cnt - 1)];
           if (n0 + lane >= cnt) r4 = MF<Real>::zero4();
           Rl[lane * 4 + 0] = r4.x;
           Rl[lane * 4 + 1] = r4.y;
