@@ -114,3 +114,38 @@ def test_precision_switches_keep_fp32_results():
     # the force sums are FP64 atomics, whose order may differ between runs
     assert abs(e1.item() - e2.item()) <= 1e-12 * abs(e64.item())
     np.testing.assert_allclose(f2, f1, rtol=0, atol=1e-12 * rms)
+
+
+def test_fp32_md_and_adjoint_match_fp64():
+    """MIX-32 through the other entry points: 20 velocity-Verlet steps
+    (dp_md_run) against the FP64 run from the same start (positions within
+    1e-6 A, thermo columns within the bar) and the forward / adjoint pair
+    (dp_energy, dp_energy_backward) against dp_compute in FP32 (the same
+    kernels: energy and forces equal to 1e-12)."""
+    from paper_2005_00223_amd.model import DPModel
+    w = synth.workload("water192")
+    blob = synth.pack_blob(w["spec"])
+    t = w["types"]
+    v0 = synth.maxwell_boltzmann(w["masses"][t], 300.0, w["vseed"])
+    out = {}
+    for prec in ("fp64", "fp32"):
+        m = DPModel(blob, prec)
+        x = torch.tensor(w["coords"], dtype=torch.float64, device="cuda")
+        v = torch.tensor(v0, dtype=torch.float64, device="cuda")
+        th = m.md_run(x, v, t, w["box"], w["masses"], 0.5, 20, skin=0.2, thermo_every=5)
+        out[prec] = (x.cpu().numpy(), th.cpu().numpy(), m)
+    d = out["fp32"][0] - out["fp64"][0]
+    d -= w["box"] * np.round(d / w["box"])
+    th32, th64 = out["fp32"][1], out["fp64"][1]
+    scale = np.abs(th64[:, 1:4]).max()
+    say(f"[fp32] md: max |dx| {np.abs(d).max():.2e} A, thermo (KE, PE, E) {np.abs(th32[:, 1:4] - th64[:, 1:4]).max() / scale:.2e} "
+        f"of their largest")
+    assert np.abs(d).max() < 1e-6
+    assert np.abs(th32[:, 1:4] - th64[:, 1:4]).max() <= BAR * scale
+    m = out["fp32"][2]
+    e, f, _ = m.compute(w["coords"], t, w["box"])
+    ea = m.energy(w["coords"], t, w["box"])
+    fa, _ = m.energy_backward(1.0)
+    rms = float(np.sqrt((f.cpu().numpy() ** 2).sum(1).mean()))
+    assert abs(ea.item() - e.item()) <= 1e-12 * abs(e.item())
+    np.testing.assert_allclose(fa.cpu().numpy(), f.cpu().numpy(), rtol=0, atol=1e-12 * rms)
