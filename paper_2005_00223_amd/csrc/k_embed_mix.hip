@@ -739,8 +739,9 @@ struct LinShape {
   static constexpr int P1_R = P1_HT + 32 * S::GTS * 4;  // float [16][4]
   static constexpr int P1_BYTES = P1_R + 256;
   static constexpr int P2_H1 = 0;                       // float [2][16][S1] (h, dh; cross-lane skips only)
-  static constexpr int P2_DT = P2_H1 + XL * 2 * 16 * S::S1 * 4;  // float [S3][4]
-  static constexpr int P2_GR = P2_DT + S::S3 * 16;      // float [64][4]
+  static constexpr int DT_ROWS = KF * 32;              // rows of dT read by the K-steps of W3 dT (zero past M1)
+  static constexpr int P2_DT = P2_H1 + XL * 2 * 16 * S::S1 * 4;  // float [DT_ROWS][4]
+  static constexpr int P2_GR = P2_DT + DT_ROWS * 16;    // float [64][4]
   static constexpr int P2_BYTES = P2_GR + 1024;
 };
 
@@ -914,9 +915,11 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
   const int t = (int)xi.w;
   {
     const float *dTi = a.dT32 + (int64_t)i * d.M1 * 4;
-    for (int o = lane; o < S::S3 * 4; o += 64) dTs[o] = (o >> 2) < d.M1 ? dTi[o] : 0.f;
+    for (int o = lane; o < LS::DT_ROWS * 4; o += 64) dTs[o] = (o >> 2) < d.M1 ? dTi[o] : 0.f;
   }
   wsync();
+  // lanes n >= 4 take zeros: their loads read component n & 3 and are scaled by 0
+  const float nmask = n < 4 ? 1.f : 0.f;
   double fi0 = 0.0, fi1 = 0.0, fi2 = 0.0;
   for (int u = 0; u < d.ntypes; ++u) {
     const unsigned char *net = smem + (t * d.ntypes + u) * LS::NET_BYTES;
@@ -935,9 +938,10 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
       float x[4], y[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
+        // rows f >= M1 of dTs are zero
         const int f0 = 32 * kk + 8 * g + v, f1 = f0 + 4;
-        x[v] = (n < 4 && f0 < W3) ? dTs[4 * f0 + n] : 0.f;
-        y[v] = (n < 4 && f1 < W3) ? dTs[4 * f1 + n] : 0.f;
+        x[v] = dTs[4 * f0 + (n & 3)] * nmask;
+        y[v] = dTs[4 * f1 + (n & 3)] * nmask;
       }
       const Split8<P> dB = split8<P>(x, y);
 #pragma unroll
@@ -1119,8 +1123,8 @@ template <int W1, int W2, int W3>
 struct CellShape {
   typedef Shape<W1, W2, W3> S;
   static_assert(!S::XL2, "the cell kernel keeps no cross-lane skip scratch");
-  static constexpr int W_DT = 0;                        // float [S3][4]
-  static constexpr int W_GR = S::S3 * 16;               // float [64][4]
+  static constexpr int W_DT = 0;                        // float [DT_ROWS][4]
+  static constexpr int W_GR = LinShape<W1, W2, W3>::DT_ROWS * 16;  // float [64][4]
   static constexpr int W_BYTES = W_GR + 1024;
 };
 
@@ -1155,9 +1159,10 @@ __global__ void __launch_bounds__(64 * CELL_WAVES, 1) k_embed_bwd_cells(MixArgs 
     cc.nc1 = ca.nc[1];
     cc.nc2 = ca.nc[2];
     cc.cap = ca.cap;
-    cc.cz = (int)(c % cc.nc2);
-    cc.cy = (int)((c / cc.nc2) % cc.nc1);
-    cc.cx = (int)(c / ((int64_t)cc.nc1 * cc.nc2));
+    // uniform over the block: kept in scalar registers
+    cc.cz = __builtin_amdgcn_readfirstlane((int)(c % cc.nc2));
+    cc.cy = __builtin_amdgcn_readfirstlane((int)((c / cc.nc2) % cc.nc1));
+    cc.cx = __builtin_amdgcn_readfirstlane((int)(c / ((int64_t)cc.nc1 * cc.nc2)));
     const int b = ca.cell_start[c], e = ca.cell_start[c + 1];
     for (int k = b + wv; k < e; k += nw)
       lin_bwd_atom<W1, W2, W3, P, true>(a, ca.cell_atoms[k], smem, tabs, nullptr, nullptr, dTs, gRs, lane, vir, cc,
