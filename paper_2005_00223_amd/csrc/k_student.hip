@@ -367,20 +367,20 @@ __global__ void k_st_adam(StAdamArgs a) {
   const int net = (int)(e / L.np), p = (int)(e % L.np);
   double wsum = 0.0, lsum = 0.0;
   float g = 0.f;
-  // the partials in block order, eight loads in flight before their adds
+  // the partials in block order, sixteen loads in flight before their adds
   const int64_t pb0 = (int64_t)net * a.nblk;
   int b = 0;
-  for (; b + 8 <= a.nblk; b += 8) {
-    float gv[8];
-    double lv[8], wv[8];
+  for (; b + 16 <= a.nblk; b += 16) {
+    float gv[16];
+    double lv[16], wv[16];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       gv[u] = a.gpart[(pb0 + b + u) * L.np + p];
       lv[u] = a.lpart[(pb0 + b + u) * 2 + 0];
       wv[u] = a.lpart[(pb0 + b + u) * 2 + 1];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 16; ++u) {
       g += gv[u];
       lsum += lv[u];
       wsum += wv[u];
