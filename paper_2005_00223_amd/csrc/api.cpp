@@ -160,6 +160,7 @@ struct DevStatus {
   double judge_count;  // atoms it covered
   int32_t sub_rows;    // padded rows of the judge's atom subset
   uint32_t smax_bits;  // largest s of the frame (float bits), for the student table
+  uint32_t defer_count;  // nets the table backward left to the layers
   long long fault_step;  // MD: the step an error flag stopped the integrator at (-1: none)
 };
 
@@ -173,7 +174,7 @@ struct Workspace {
   double4 *xw = nullptr, *xref = nullptr, *rt = nullptr, *dr = nullptr;
   float4 *rt32 = nullptr;  // mixed precision: the environment matrix in FP32
   int32_t *cell_of, *cell_atoms, *cell_start, *cell_fill, *scan_tmp, *cand, *cand_n, *nlist, *nreal, *pos_of_atom,
-      *atom_of_pos, *blk_counts, *type_count, *type_start;
+      *atom_of_pos, *blk_counts, *type_count, *type_start, *defer;
   double *T, *D, *dD, *Y[MAXF + 1], *Tt[MAXF + 1], *G[MAXF + 1], *eatom, *partial, *vir_part, *force_tmp,
       *net_deriv, *energy, *virial, *ke;
   // student judge: teacher forces / energy / virial, RMSE partial sums,
@@ -379,6 +380,7 @@ size_t ws_carve(const dp_ctx *c, Workspace &w, int64_t nn, int64_t nc, int cc, b
     add((void **)&w.T32, sizeof(float) * nn * d.M1 * 4);
     add((void **)&w.dT32, sizeof(float) * nn * d.M1 * 4);
     add((void **)&w.tbuf, sizeof(float) * fit_mix_tbuf_floats(d, rows));
+    add((void **)&w.defer, (size_t)4 * nn * d.ntypes);
   }
   add((void **)&w.eatom, sizeof(double) * nn);
   add((void **)&w.partial, sizeof(double) * 1024);
@@ -400,7 +402,10 @@ size_t ws_carve(const dp_ctx *c, Workspace &w, int64_t nn, int64_t nc, int cc, b
   add((void **)&w.status, sizeof(DevStatus));
   if (base) {
     if (!nd) w.net_deriv = nullptr;
-    if (!mixed) w.cell_part = nullptr;
+    if (!mixed) {
+      w.cell_part = nullptr;
+      w.defer = nullptr;
+    }
     if (mixed) w.rt = w.dr = nullptr;
     else if (f32) w.rt = nullptr;
     else w.rt32 = nullptr;
@@ -853,6 +858,9 @@ MixArgs mix_args(dp_ctx *c, int64_t rows, double *F) {
     ma.tab = en.d_tab;
     ma.tab_inv_ds = (float)(TAB_K / en.tab_shi);
     ma.tab_shi = (float)en.tab_shi;
+    ma.pimg = (const unsigned char *)en.d_tab + (size_t)c->dims.ntypes * c->dims.ntypes * TAB_BYTES;
+    ma.defer = w.defer;
+    ma.defer_count = &w.status->defer_count;
   }
   return ma;
 }
@@ -919,9 +927,11 @@ int ensure_table(dp_ctx *c, int64_t n) {
   const double shi = smax > 0.f ? 1.25 * (double)smax : 1.0;
   if (!en.d_tab) {
     if (c->noalloc) return DP_OK;  // no table yet and no allocation allowed: the layers are evaluated
-    HIPCHK(c, hipMalloc(&en.d_tab, (size_t)c->dims.ntypes * c->dims.ntypes * TAB_BYTES));
+    HIPCHK(c, hipMalloc(&en.d_tab, (size_t)c->dims.ntypes * c->dims.ntypes * (TAB_BYTES + PIMG_BYTES)));
   }
-  launch_student_table(s, en.d, en.eo, en.d_emb, c->precision == DP_MIX_FP16 ? 0 : 1, shi, en.d_tab);
+  const int nets = c->dims.ntypes * c->dims.ntypes, prec = c->precision == DP_MIX_FP16 ? 0 : 1;
+  launch_student_table(s, en.d, en.eo, en.d_emb, prec, shi, en.d_tab);
+  launch_student_pimg(s, nets, en.d_tab, prec, (unsigned char *)en.d_tab + (size_t)nets * TAB_BYTES);
   HIPCHK(c, hipGetLastError());
   en.tab_shi = shi;
   en.tab_ok = true;
@@ -1149,20 +1159,33 @@ void eval_backward(dp_ctx *c, int64_t n, double *F, double *V) {
     CellArgs ca{};
     int threads = 0;
     size_t lds = 0;
+    // with the table, nets with a neighbour beyond its range are deferred to
+    // a layer pass after the main kernel; its virial partials follow the
+    // main kernel's
+    if (ma.tab) launch_fill_u32(s, ma.defer_count, 1, 0u);
+    auto deferred = [&](int grid) {
+      if (!ma.tab) return 0;
+      MixArgs md = ma;
+      md.vir_part = w.vir_part + (size_t)9 * grid;
+      launch_embed_defer(s, md);
+      return DEFER_GRID;
+    };
     if (cell_scatter_args(c, n, ma, ca, threads, lds)) {
       const int grid = cells_grid(ca.ncell);
       launch_embed_cells(s, ma, ca, grid, threads, lds);
       tmark(c, 9);
       launch_cell_gather(s, ca, F);
+      const int gd = deferred(grid);
       tmark(c, 7);
-      launch_sum9(s, w.vir_part, grid, V);
+      launch_sum9(s, w.vir_part, grid + gd, V);
       c->stats.cell_scatter += 1;
     } else {
       const int grid = mix_grid(rows);
       launch_embed_mix(s, ma, 2, grid);
       tmark(c, 9);
+      const int gd = deferred(grid);
       tmark(c, 7);
-      launch_sum9(s, w.vir_part, grid, V);
+      launch_sum9(s, w.vir_part, grid + gd, V);
     }
   }
   tnext(c);

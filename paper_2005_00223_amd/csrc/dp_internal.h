@@ -130,15 +130,16 @@ __device__ inline double4 pair_disp(const double4 &pi, const double4 &pj, double
   else if (dz < -0.5 * L2) dz += L2;
   return make_double4(dx, dy, dz, sqrt(dx * dx + dy * dy + dz * dz));
 }
+// nearest image of a coordinate difference d (|d| < 1.5 L) as selects: the
+// values of the branch form above, without branches around the pair's work
+__device__ inline double min_img_sel(double d, double L) {
+  const double h = 0.5 * L, up = d - L, dn = d + L;
+  return d > h ? up : (d < -h ? dn : d);
+}
 // the same displacement with r^2 in place of r: (dx, dy, dz, r^2)
 __device__ inline double4 pair_disp_sq(const double4 &pi, const double4 &pj, double L0, double L1, double L2) {
-  double dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-  if (dx > 0.5 * L0) dx -= L0;
-  else if (dx < -0.5 * L0) dx += L0;
-  if (dy > 0.5 * L1) dy -= L1;
-  else if (dy < -0.5 * L1) dy += L1;
-  if (dz > 0.5 * L2) dz -= L2;
-  else if (dz < -0.5 * L2) dz += L2;
+  const double dx = min_img_sel(pj.x - pi.x, L0), dy = min_img_sel(pj.y - pi.y, L1),
+               dz = min_img_sel(pj.z - pi.z, L2);
   return make_double4(dx, dy, dz, dx * dx + dy * dy + dz * dz);
 }
 // tanh in FP64 to a few ulp, about a fifth of the instructions of the

@@ -101,6 +101,12 @@ struct MixArgs {
   // layers themselves
   const float *tab;
   float tab_inv_ds, tab_shi;
+  // with tab: the backward's projected-table operands (launch_student_pimg),
+  // and the nets it leaves to the layers (a neighbour beyond the table's
+  // range): entries i * ntypes + u, their count zeroed before the backward
+  const unsigned char *pimg;
+  int32_t *defer;
+  uint32_t *defer_count;
 };
 
 constexpr int TAB_K = 80;                         // intervals of the student table
@@ -109,6 +115,15 @@ constexpr int TAB_BYTES = (TAB_K + 1) * TAB_STRIDE * 4;
 // second layer of each student net tabulated (cubic Hermite data) over [0, shi]
 void launch_student_table(hipStream_t s, const Dims &d, const EmbOffsets &eo, const double *ew, int prec, double shi,
                           float *tab);
+// The student backward contracts the table with M = W3 dT per (atom, net):
+// rows (y_k, y_{k+1} - y_k, m_k) of the TAB_K + 1 nodes, PT_TILES MFMA tiles
+// of 16 rows; per net an image of PT_TILES x (hi, lo) 1 KB operand blocks,
+// per wave PT_BYTES of LDS for the projected rows (float4 each)
+constexpr int PT_TILES = 16;
+constexpr int PIMG_BYTES = PT_TILES * 2 * 1024;
+constexpr int PT_BYTES = PT_TILES * 16 * 16;
+static_assert(3 * (TAB_K + 1) <= 16 * PT_TILES, "projected rows must fit the tiles");
+void launch_student_pimg(hipStream_t s, int nets, const float *tab, int prec, unsigned char *img);
 // largest s of the frame (nearest neighbour of every atom and type) into *smax (bits of a float)
 void launch_smax(hipStream_t s, int64_t n, const Dims &d, const int32_t *nreal, const float4 *rt, uint32_t *smax);
 
@@ -119,6 +134,10 @@ size_t mix_lds_bytes(int shape, int ntypes, int pass);
 void mix_pack_net(int shape, const double *const *W, const double *const *b, int prec, unsigned char *out);
 int mix_grid(int64_t rows);
 void launch_embed_mix(hipStream_t s, const MixArgs &a, int pass, int grid);
+// the deferred nets of a table backward, by the layers (grid DEFER_GRID;
+// virial partials in a.vir_part[0 .. DEFER_GRID))
+constexpr int DEFER_GRID = 64;
+void launch_embed_defer(hipStream_t s, const MixArgs &a);
 
 // fused fitting net: byte offsets of the per-type operand images
 struct FitMixOffsets {
@@ -150,6 +169,9 @@ struct FitMixArgs {
 
 // cell-ordered backward of the affine-last-layer nets (k_embed_bwd_cells)
 constexpr int CELL_WAVES = 16;   // waves per workgroup at most
+// with the table at most 12 (three per SIMD, up to 168 registers each): the
+// projection images take the LDS a fourth wave per SIMD would need
+__host__ __device__ constexpr int cell_waves(bool proj) { return proj ? 12 : CELL_WAVES; }
 constexpr int CELL_CAP = 128;    // atoms per cell kept in LDS; the rest use global atomics
 struct CellArgs {
   const int32_t *cell_start;     // [ncell + 1]

@@ -245,6 +245,23 @@ __device__ inline v4f tacc16(const float *grow, const RSplit &RB, const float *R
   return acc;
 }
 
+// The same row scaled by 0 past the block instead of selected: the load's
+// result is always used, so the compiler keeps it unconditional and in
+// flight.
+__device__ inline float4 rt_row_m(const float4 *rt, int64_t base, int q, int cnt) {
+  const float4 v = rt[base + (q < cnt ? q : cnt - 1)];
+  const float m = q < cnt ? 1.f : 0.f;
+  return make_float4(v.x * m, v.y * m, v.z * m, v.w * m);
+}
+
+// x, y, z of atom j; w (the type) is not loaded: a dead part of a load in
+// flight lets the compiler reuse its registers only after waiting for it
+__device__ inline double4 pos3(const double4 *xw, int j) {
+  const double2 xy = *(const double2 *)(xw + j);
+  const double z = ((const double *)(xw + j))[2];
+  return make_double4(xy.x, xy.y, z, 0.0);
+}
+
 // ---------------------------------------------------------------------------
 // layer 1 on VALU: lane (g, n) computes slots 16 mt + 4 g + r (mt < 2)
 // ---------------------------------------------------------------------------
@@ -742,7 +759,9 @@ struct LinShape {
   static constexpr int DT_ROWS = KF * 32;              // rows of dT read by the K-steps of W3 dT (zero past M1)
   static constexpr int P2_DT = P2_H1 + XL * 2 * 16 * S::S1 * 4;  // float [DT_ROWS][4]
   static constexpr int P2_GR = P2_DT + DT_ROWS * 16;    // float [64][4]
-  static constexpr int P2_BYTES = P2_GR + 1024;
+  // per wave: the above (layers), or the projected table (dT staged in it first)
+  static constexpr int P2_BYTES = P2_GR + 1024 > PT_BYTES ? P2_GR + 1024 : PT_BYTES;
+  static_assert(DT_ROWS * 16 <= PT_BYTES, "dT is staged in the projected table's scratch");
 };
 
 template <int W1, int W2, int W3, int P>
@@ -872,6 +891,14 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_fwd_lin(MixArgs a) 
   }
 }
 
+// FP64 add into the block's LDS accumulator, through an LDS-qualified
+// pointer: the compiler then never merges it with the global atomics of the
+// other branch into one atomic on a pointer of unknown kind
+typedef __attribute__((address_space(3))) double lds_f64;
+__device__ inline void lds_add(double *p, double v) {
+  __hip_atomic_fetch_add((lds_f64 *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // LDS force accumulation of the cell-ordered backward: the block owns one
 // cell of the list grid, facc[27][cap][3] holds the forces on the atoms of the
 // 27 cells around it (slot = offset (dx, dy, dz) in {-1, 0, 1}^3, then the
@@ -897,169 +924,188 @@ __device__ inline int cell_slot(const CellCtx &cc, uint32_t code) {
   return ((dx + 1) * 9 + (dy + 1) * 3 + (dz + 1)) * cc.cap + l;
 }
 
-// backward of one atom i with an affine-last-layer net set: dE/dR per
-// neighbour, the FP64 pair forces, F_i and the virial.  CELL: neighbour and
-// own forces go to the block's LDS accumulator (li = index of i in its
-// cell), else straight to global memory with atomics.
-template <int W1, int W2, int W3, int P, bool CELL>
-__device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char *smem, const float *tabs, float *h1s,
-                                    float *hd1s, float *dTs, float *gRs, int lane, double (&vir)[9], const CellCtx &cc,
-                                    int li) {
+// h2 and ds-derivative of the second layer by the layers themselves, for the
+// 16 neighbours of a tile (lane (g, n): features 16 mt + 4 g + r of
+// neighbour n at s); h1s / hd1s: the cross-lane skip scratch (XL2 shapes)
+template <int W1, int W2, int W3, int P>
+__device__ inline void layers_h2(const unsigned char *net, float s, int lane, float *h1s, float *hd1s,
+                                 float (&h2)[Shape<W1, W2, W3>::MT2][4], float (&hd2)[Shape<W1, W2, W3>::MT2][4]) {
   typedef Shape<W1, W2, W3> S;
+  const int g = lane >> 4, n = lane & 15;
+  const float *w1 = (const float *)(net + S::O_W1), *b1 = (const float *)(net + S::O_B1);
+  const float *b2 = (const float *)(net + S::O_B2);
+  float h1[2][4], hd1[2][4];
+  layer1<W1, true>(w1, b1, s, g, h1, hd1);
+  if constexpr (S::XL2)
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      *(float4 *)(h1s + n * S::S1 + 16 * mt + 4 * g) = make_float4(h1[mt][0], h1[mt][1], h1[mt][2], h1[mt][3]);
+      *(float4 *)(hd1s + n * S::S1 + 16 * mt + 4 * g) = make_float4(hd1[mt][0], hd1[mt][1], hd1[mt][2], hd1[mt][3]);
+    }
+  Split8<P> B2h[1] = {split8<P>(h1[0], h1[1])}, B2d[1] = {split8<P>(hd1[0], hd1[1])};
+  v4f acc2[S::MT2], acc2d[S::MT2];
+  layer_mfma<P, S::MT2, 1>(net + S::O_A2, b2, B2h, lane, g, acc2);
+  layer_mfma_tan<P, S::MT2, 1>(net + S::O_A2, B2d, lane, acc2d);
+  wsync();
+#pragma unroll
+  for (int mt = 0; mt < S::MT2; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int f = 16 * mt + 4 * g + r;
+      float hv = 0.f, dv = 0.f;
+      if (16 * mt < W2 && f < W2) {
+        const float th = tanh_f(acc2[mt][r]);
+        hv = th + skip_val<W1, W2, S::SK2, 2>(f, mt, r, h1, h1s, n, S::S1);
+        dv = (1.f - th * th) * acc2d[mt][r] + skip_val<W1, W2, S::SK2, 2>(f, mt, r, hd1, hd1s, n, S::S1);
+      }
+      h2[mt][r] = hv;
+      hd2[mt][r] = dv;
+    }
+}
+
+// M = W3 dT for one (atom, net) as split 16-bit halves MA (lane (g, n): row
+// c = n < 4 of M^T, the layer-3 inputs in the permuted K order; rows n >= 4
+// are zero) and q = b3^T dT (q[c] in every lane).  dT of atom i is staged in
+// the wave's scratch dTs first; on return every lane is done with it.
+template <int W1, int W2, int W3, int P>
+__device__ inline void lin_m_q(const MixArgs &a, int i, const unsigned char *a3b, const float *b3, float *dTs, int lane,
+                               Split8<P> &MA, float (&q)[4]) {
   typedef LinShape<W1, W2, W3> LS;
   typedef typename HT<P>::v8 V;
   const Dims &d = a.d;
   const int g = lane >> 4, n = lane & 15;
-  const double rc = d.rcut, rcs = d.rcut_smth, inv_w = 1.0 / (d.rcut - d.rcut_smth);
-  const double4 xi = a.xw[i];
-  const int t = (int)xi.w;
-  {
-    const float *dTi = a.dT32 + (int64_t)i * d.M1 * 4;
-    for (int o = lane; o < LS::DT_ROWS * 4; o += 64) dTs[o] = (o >> 2) < d.M1 ? dTi[o] : 0.f;
+  const float *dTi = a.dT32 + (int64_t)i * d.M1 * 4;
+  for (int o = lane; o < LS::DT_ROWS * 4; o += 64) dTs[o] = (o >> 2) < d.M1 ? dTi[o] : 0.f;
+  wsync();
+  // B operands of W3 dT (K = outputs f = 32 kk + 8 g + v, N = components
+  // c = n); lanes n >= 4 take zeros: their loads read component n & 3 and
+  // are scaled by 0
+  const float nmask = n < 4 ? 1.f : 0.f;
+  v4f Macc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+  for (int kk = 0; kk < LS::KF; ++kk) {
+    float x[4], y[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      // rows f >= M1 of dTs are zero
+      const int f0 = 32 * kk + 8 * g + v, f1 = f0 + 4;
+      x[v] = dTs[4 * f0 + (n & 3)] * nmask;
+      y[v] = dTs[4 * f1 + (n & 3)] * nmask;
+    }
+    const Split8<P> dB = split8<P>(x, y);
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      const V av = *(const V *)(a3b + ((mt * LS::KF + kk) * 64 + lane) * 16);
+      Macc[mt] = mfma16<P>(av, dB.hi, Macc[mt]);
+      Macc[mt] = mfma16<P>(av, dB.lo, Macc[mt]);
+    }
+  }
+  // q: lane takes the entries lane + 64 m of the [M1][4] block (component
+  // lane & 3), then the lanes of one component are summed
+  float qv = 0.f;
+  for (int o = lane; o < W3 * 4; o += 64) qv += b3[o >> 2] * dTs[o];
+  qv += __shfl_xor(qv, 4);
+  qv += __shfl_xor(qv, 8);
+  qv += __shfl_xor(qv, 16);
+  qv += __shfl_xor(qv, 32);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) q[c] = __shfl(qv, c);
+  float mx[4], my[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    mx[r] = Macc[0][r];
+    my[r] = Macc[1][r];
+  }
+  MA = split8<P>(mx, my);
+  wsync();
+}
+
+// Projected table of one (atom, net) into the wave's scratch pts:
+// P[row][c] = sum_f coef[row][f] M[f][c], plus q[c] on the rows of h2 itself,
+// as PT_TILES MFMA tiles of 16 rows (A = M^T split, B = the coefficient image
+// in its hi and lo halves, loaded a tile ahead).  Output lane (0, n) holds
+// row 16 tt + n for the four components.  The tile loop stays a loop (two
+// tiles per trip): unrolled, the product chains of all tiles were scheduled
+// side by side and their accumulators spilled.
+template <int P>
+__device__ inline void proj_build(const unsigned char *img, const Split8<P> &MA, const float (&q)[4], float *pts,
+                                  int lane) {
+  typedef typename HT<P>::v8 V;
+  const int g = lane >> 4, n = lane & 15;
+  V bh = *(const V *)(img + 16 * lane), bl = *(const V *)(img + 1024 + 16 * lane);
+#pragma unroll 2
+  for (int tt = 0; tt < PT_TILES; ++tt) {
+    const int tn = tt + 1 < PT_TILES ? tt + 1 : tt;
+    const V nh = *(const V *)(img + (2 * tn) * 1024 + 16 * lane);
+    const V nl = *(const V *)(img + (2 * tn + 1) * 1024 + 16 * lane);
+    const int row = 16 * tt + n;
+    const float qs = (row % 3 == 0) ? 1.f : 0.f;
+    v4f acc = v4f{q[0] * qs, q[1] * qs, q[2] * qs, q[3] * qs};
+    acc = mfma16<P>(MA.hi, bh, acc);
+    acc = mfma16<P>(MA.hi, bl, acc);
+    acc = mfma16<P>(MA.lo, bh, acc);
+    if (g == 0) *(float4 *)(pts + 4 * row) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    bh = nh;
+    bl = nl;
   }
   wsync();
-  // lanes n >= 4 take zeros: their loads read component n & 3 and are scaled by 0
-  const float nmask = n < 4 ? 1.f : 0.f;
-  double fi0 = 0.0, fi1 = 0.0, fi2 = 0.0;
-  for (int u = 0; u < d.ntypes; ++u) {
-    const unsigned char *net = smem + (t * d.ntypes + u) * LS::NET_BYTES;
-    const float *w1 = (const float *)(net + S::O_W1), *b1 = (const float *)(net + S::O_B1);
-    const float *b2 = (const float *)(net + S::O_B2), *b3 = (const float *)(net + S::O_B3);
-    const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
-    if (cnt == 0) continue;
-    const int64_t base = (int64_t)i * d.nnei + d.off[u];
-    // M = W3 dT (lane (g, n): M[16 mt + 4 g + r][c = n]) and q = b3^T dT; the
-    // B operands of W3 dT (K = outputs f = 32 kk + 8 g + v, N = components
-    // c = n) are rebuilt per net so that they hold no registers in the
-    // neighbour loop
-    v4f Macc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-    for (int kk = 0; kk < LS::KF; ++kk) {
-      float x[4], y[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        // rows f >= M1 of dTs are zero
-        const int f0 = 32 * kk + 8 * g + v, f1 = f0 + 4;
-        x[v] = dTs[4 * f0 + (n & 3)] * nmask;
-        y[v] = dTs[4 * f1 + (n & 3)] * nmask;
-      }
-      const Split8<P> dB = split8<P>(x, y);
-#pragma unroll
-      for (int mt = 0; mt < 2; ++mt) {
-        const V av = *(const V *)(net + LS::O_A3B + ((mt * LS::KF + kk) * 64 + lane) * 16);
-        Macc[mt] = mfma16<P>(av, dB.hi, Macc[mt]);
-        Macc[mt] = mfma16<P>(av, dB.lo, Macc[mt]);
-      }
-    }
-    float q = 0.f;
-    if (n < 4)
-      for (int f = g; f < W3; f += 4) q += b3[f] * dTs[4 * f + n];
-    q += __shfl_xor(q, 16);
-    q += __shfl_xor(q, 32);
-    const float q0 = __shfl(q, 0), q1 = __shfl(q, 1), q2 = __shfl(q, 2), q3 = __shfl(q, 3);
-    float mx[4], my[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      mx[r] = Macc[0][r];
-      my[r] = Macc[1][r];
-    }
-    const Split8<P> MA = split8<P>(mx, my);
-    float4 r4n = rt_row(a.rt, base, n, cnt);
-    // force-pass operands of the current 64-neighbour chunk, loaded a chunk ahead
-    double4 pjc = xi;  // neighbour positions of the chunk, gathered at its first tile
-    int jc = a.nlist[base + (lane < cnt ? lane : cnt - 1)];
-    uint32_t codec = 0;
-    for (int n0 = 0; n0 < cnt; n0 += 16) {
-      // this tile's environment rows; the next tile's are loaded meanwhile
-      const float4 r4 = r4n;
-      if (n0 + 16 < cnt) r4n = rt_row(a.rt, base, n0 + 16 + n, cnt);
-      const float s = r4.x;
-      float h2[S::MT2][4], hd2[S::MT2][4];
-      float dscale = 1.f;  // hd2 * dscale = dh2/ds
-      if (tabs && __ballot(s > a.tab_shi) == 0ull) {
-        // every neighbour of the tile inside the table's range
-        tab_h2<true>(tabs + (t * d.ntypes + u) * (TAB_BYTES / 4), s, a.tab_inv_ds, g, h2, hd2);
-        dscale = a.tab_inv_ds;
-      } else {
-        float h1[2][4], hd1[2][4];
-        layer1<W1, true>(w1, b1, s, g, h1, hd1);
-        if (S::XL2)
-#pragma unroll
-          for (int mt = 0; mt < 2; ++mt) {
-            *(float4 *)(h1s + n * S::S1 + 16 * mt + 4 * g) = make_float4(h1[mt][0], h1[mt][1], h1[mt][2], h1[mt][3]);
-            *(float4 *)(hd1s + n * S::S1 + 16 * mt + 4 * g) =
-                make_float4(hd1[mt][0], hd1[mt][1], hd1[mt][2], hd1[mt][3]);
-          }
-        Split8<P> B2h[1] = {split8<P>(h1[0], h1[1])}, B2d[1] = {split8<P>(hd1[0], hd1[1])};
-        v4f acc2[S::MT2], acc2d[S::MT2];
-        layer_mfma<P, S::MT2, 1>(net + S::O_A2, b2, B2h, lane, g, acc2);
-        layer_mfma_tan<P, S::MT2, 1>(net + S::O_A2, B2d, lane, acc2d);
-        wsync();
-#pragma unroll
-        for (int mt = 0; mt < S::MT2; ++mt)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int f = 16 * mt + 4 * g + r;
-            float hv = 0.f, dv = 0.f;
-            if (16 * mt < W2 && f < W2) {
-              const float th = tanh_f(acc2[mt][r]);
-              hv = th + skip_val<W1, W2, S::SK2, 2>(f, mt, r, h1, h1s, n, S::S1);
-              dv = (1.f - th * th) * acc2d[mt][r] + skip_val<W1, W2, S::SK2, 2>(f, mt, r, hd1, hd1s, n, S::S1);
-            }
-            h2[mt][r] = hv;
-            hd2[mt][r] = dv;
-          }
-      }
-      const Split8<P> B3h = split8<P>(h2[0], h2[1]), B3d = split8<P>(hd2[0], hd2[1]);
-      // a = M^T h2 and b = M^T hd2, h2' = dscale hd2 (lane (g, n): component c = 4 g + r of neighbour n)
-      v4f ca = v4f{0.f, 0.f, 0.f, 0.f}, cb = v4f{0.f, 0.f, 0.f, 0.f};
-      ca = mfma16<P>(MA.hi, B3h.hi, ca);
-      ca = mfma16<P>(MA.hi, B3h.lo, ca);
-      ca = mfma16<P>(MA.lo, B3h.hi, ca);
-      cb = mfma16<P>(MA.hi, B3d.hi, cb);
-      cb = mfma16<P>(MA.hi, B3d.lo, cb);
-      cb = mfma16<P>(MA.lo, B3d.hi, cb);
-      const int slot0 = n0 & 63;
-      if (g == 0) {
-        // dE/dR = a + q + dscale (R . b) e_0
-        const float bd = (r4.x * cb[0] + r4.y * cb[1] + r4.z * cb[2] + r4.w * cb[3]) * dscale;
-        *(float4 *)(gRs + 4 * (slot0 + n)) = make_float4(ca[0] + q0 + bd, ca[1] + q1, ca[2] + q2, ca[3] + q3);
-      }
-      // positions and cell codes of this chunk's neighbours (jc arrived during the tile)
-      if (slot0 == 0) {
-        pjc = a.xw[jc];
-        if (CELL) codec = cc.code[jc];
-      }
-      wsync();
-      // every 64 neighbours (or at the end of the type block): FP64 force pass
-      if (((n0 + 16) & 63) == 0 || n0 + 16 >= cnt) {
-        const int c0 = n0 & ~63;
-        const int qq = c0 + lane;
-        if (qq < cnt) {
-          const float4 gr = *(const float4 *)(gRs + 4 * lane);
-          double gx, gy, gz;
-          pair_force(pair_disp_sq(xi, pjc, a.L[0], a.L[1], a.L[2]), gr, rc, rcs, inv_w, gx, gy, gz, fi0, fi1, fi2, vir);
-          if (a.net_deriv) {
-            double *nd = a.net_deriv + (base + qq) * 4;
-            nd[0] = gr.x; nd[1] = gr.y; nd[2] = gr.z; nd[3] = gr.w;
-          }
-          const int slot = CELL ? cell_slot(cc, codec) : -1;
-          if (slot >= 0) {
-            atomicAdd(cc.facc + 3 * slot + 0, -gx);
-            atomicAdd(cc.facc + 3 * slot + 1, -gy);
-            atomicAdd(cc.facc + 3 * slot + 2, -gz);
-          } else {
-            unsafeAtomicAdd(a.force + 3 * (int64_t)jc + 0, -gx);
-            unsafeAtomicAdd(a.force + 3 * (int64_t)jc + 1, -gy);
-            unsafeAtomicAdd(a.force + 3 * (int64_t)jc + 2, -gz);
-          }
-        }
-        if (c0 + 64 < cnt) jc = a.nlist[base + (qq + 64 < cnt ? qq + 64 : cnt - 1)];
-        wsync();
-      }
-    }
+}
+
+// dE/dR of one neighbour from the projected table: cubic Hermite in the
+// interval k of s, a = M^T h2(s) + q, b = M^T dh2/ds(s), and
+// dE/dR = a + (R . b) e_0
+__device__ inline float4 proj_eval(const float *pts, float4 r4, float inv_ds) {
+  const float x = r4.x * inv_ds;
+  int k = (int)x;
+  k = k < TAB_K - 1 ? k : TAB_K - 1;
+  const float t = x - (float)k, t2 = t * t, t3 = t2 * t;
+  const float h10 = t3 - 2.f * t2 + t, h01 = 3.f * t2 - 2.f * t3, h11 = t3 - t2;
+  const float e01 = 6.f * (t - t2), e10 = 3.f * t2 - 4.f * t + 1.f, e11 = 3.f * t2 - 2.f * t;
+  const float4 *pk = (const float4 *)pts + 3 * k;
+  const float4 py = pk[0], pdy = pk[1], pm0 = pk[2], pm1 = pk[5];
+  const float a0 = h01 * pdy.x + h10 * pm0.x + h11 * pm1.x + py.x;
+  const float a1 = h01 * pdy.y + h10 * pm0.y + h11 * pm1.y + py.y;
+  const float a2 = h01 * pdy.z + h10 * pm0.z + h11 * pm1.z + py.z;
+  const float a3 = h01 * pdy.w + h10 * pm0.w + h11 * pm1.w + py.w;
+  const float b0 = e01 * pdy.x + e10 * pm0.x + e11 * pm1.x;
+  const float b1 = e01 * pdy.y + e10 * pm0.y + e11 * pm1.y;
+  const float b2 = e01 * pdy.z + e10 * pm0.z + e11 * pm1.z;
+  const float b3 = e01 * pdy.w + e10 * pm0.w + e11 * pm1.w;
+  const float bd = (r4.x * b0 + r4.y * b1 + r4.z * b2 + r4.w * b3) * inv_ds;
+  return make_float4(a0 + bd, a1, a2, a3);
+}
+
+// FP64 force of the pair (i, slot) from gr = dE/dR, with the neighbour's
+// share to the block's LDS accumulator (CELL, when its cell is held) or to
+// global memory
+// (D4 = displacement and r^2 of the pair, slot = the neighbour's LDS slot
+// or -1)
+template <bool CELL>
+__device__ inline void scatter_pair(const MixArgs &a, const CellCtx &cc, int64_t slot_idx, const double4 &D4, int j,
+                                    int slot, float4 gr, double rc, double rcs, double inv_w, double &fi0,
+                                    double &fi1, double &fi2, double (&vir)[9]) {
+  double gx, gy, gz;
+  pair_force(D4, gr, rc, rcs, inv_w, gx, gy, gz, fi0, fi1, fi2, vir);
+  if (a.net_deriv) {
+    double *nd = a.net_deriv + slot_idx * 4;
+    nd[0] = gr.x; nd[1] = gr.y; nd[2] = gr.z; nd[3] = gr.w;
   }
-  // F_i: wave sum, one add per component
+  if (slot >= 0) {
+    lds_add(cc.facc + 3 * slot + 0, -gx);
+    lds_add(cc.facc + 3 * slot + 1, -gy);
+    lds_add(cc.facc + 3 * slot + 2, -gz);
+  } else {
+    unsafeAtomicAdd(a.force + 3 * (int64_t)j + 0, -gx);
+    unsafeAtomicAdd(a.force + 3 * (int64_t)j + 1, -gy);
+    unsafeAtomicAdd(a.force + 3 * (int64_t)j + 2, -gz);
+  }
+}
+
+// F_i: wave sum, one add per component (to the LDS accumulator when the
+// atom's own slot is held)
+template <bool CELL>
+__device__ inline void store_fi(const MixArgs &a, const CellCtx &cc, int i, int li, int lane, double fi0, double fi1,
+                                double fi2) {
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     fi0 += __shfl_xor(fi0, o);
@@ -1069,9 +1115,9 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
   if (lane == 0) {
     if (CELL && li < cc.cap) {
       double *f = cc.facc + 3 * (13 * cc.cap + li);
-      atomicAdd(f + 0, fi0);
-      atomicAdd(f + 1, fi1);
-      atomicAdd(f + 2, fi2);
+      lds_add(f + 0, fi0);
+      lds_add(f + 1, fi1);
+      lds_add(f + 2, fi2);
     } else {
       unsafeAtomicAdd(a.force + 3 * (int64_t)i + 0, fi0);
       unsafeAtomicAdd(a.force + 3 * (int64_t)i + 1, fi1);
@@ -1080,19 +1126,168 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
   }
 }
 
-template <int W1, int W2, int W3, int P>
+// backward of one (atom i, neighbour type u) with an affine-last-layer net,
+// layers evaluated per neighbour: dE/dR per neighbour, the FP64 pair forces,
+// F_i (into fi) and the virial.  CELL: neighbour forces go to the block's
+// LDS accumulator when their cell is held, else straight to global memory
+// with atomics.
+template <int W1, int W2, int W3, int P, bool CELL>
+__device__ inline void lin_bwd_net(const MixArgs &a, int i, int u, const unsigned char *smem, float *h1s, float *hd1s,
+                                   float *dTs, float *gRs, int lane, double (&vir)[9], const CellCtx &cc,
+                                   double &fi0, double &fi1, double &fi2) {
+  typedef Shape<W1, W2, W3> S;
+  typedef LinShape<W1, W2, W3> LS;
+  const Dims &d = a.d;
+  const int g = lane >> 4, n = lane & 15;
+  const double rc = d.rcut, rcs = d.rcut_smth, inv_w = 1.0 / (d.rcut - d.rcut_smth);
+  const double4 xi = a.xw[i];
+  const int t = (int)xi.w;
+  const unsigned char *net = smem + (t * d.ntypes + u) * LS::NET_BYTES;
+  const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
+  if (cnt == 0) return;
+  const int64_t base = (int64_t)i * d.nnei + d.off[u];
+  // M and q are rebuilt per net so that they hold no registers across nets
+  Split8<P> MA;
+  float q[4];
+  lin_m_q<W1, W2, W3, P>(a, i, net + LS::O_A3B, (const float *)(net + S::O_B3), dTs, lane, MA, q);
+  float4 r4n = rt_row(a.rt, base, n, cnt);
+  // force-pass operands of the current 64-neighbour chunk, loaded a chunk ahead
+  double4 pjc = xi;  // neighbour positions of the chunk, gathered at its first tile
+  int jc = a.nlist[base + (lane < cnt ? lane : cnt - 1)];
+  uint32_t codec = 0;
+  for (int n0 = 0; n0 < cnt; n0 += 16) {
+    // this tile's environment rows; the next tile's are loaded meanwhile
+    const float4 r4 = r4n;
+    if (n0 + 16 < cnt) r4n = rt_row(a.rt, base, n0 + 16 + n, cnt);
+    float h2[S::MT2][4], hd2[S::MT2][4];
+    layers_h2<W1, W2, W3, P>(net, r4.x, lane, h1s, hd1s, h2, hd2);
+    const Split8<P> B3h = split8<P>(h2[0], h2[1]), B3d = split8<P>(hd2[0], hd2[1]);
+    // a = M^T h2 and b = M^T dh2/ds (lane (g, n): component c = 4 g + r of neighbour n)
+    v4f ca = v4f{0.f, 0.f, 0.f, 0.f}, cb = v4f{0.f, 0.f, 0.f, 0.f};
+    ca = mfma16<P>(MA.hi, B3h.hi, ca);
+    ca = mfma16<P>(MA.hi, B3h.lo, ca);
+    ca = mfma16<P>(MA.lo, B3h.hi, ca);
+    cb = mfma16<P>(MA.hi, B3d.hi, cb);
+    cb = mfma16<P>(MA.hi, B3d.lo, cb);
+    cb = mfma16<P>(MA.lo, B3d.hi, cb);
+    const int slot0 = n0 & 63;
+    if (g == 0) {
+      // dE/dR = a + q + (R . b) e_0
+      const float bd = r4.x * cb[0] + r4.y * cb[1] + r4.z * cb[2] + r4.w * cb[3];
+      *(float4 *)(gRs + 4 * (slot0 + n)) = make_float4(ca[0] + q[0] + bd, ca[1] + q[1], ca[2] + q[2], ca[3] + q[3]);
+    }
+    // positions and cell codes of this chunk's neighbours (jc arrived during the tile)
+    if (slot0 == 0) {
+      pjc = a.xw[jc];
+      if (CELL) codec = cc.code[jc];
+    }
+    wsync();
+    // every 64 neighbours (or at the end of the type block): FP64 force pass
+    if (((n0 + 16) & 63) == 0 || n0 + 16 >= cnt) {
+      const int c0 = n0 & ~63;
+      const int qq = c0 + lane;
+      if (qq < cnt) {
+        const float4 gr = *(const float4 *)(gRs + 4 * lane);
+        scatter_pair<CELL>(a, cc, base + qq, pair_disp_sq(xi, pjc, a.L[0], a.L[1], a.L[2]), jc,
+                           CELL ? cell_slot(cc, codec) : -1, gr, rc, rcs, inv_w, fi0, fi1, fi2, vir);
+      }
+      if (c0 + 64 < cnt) jc = a.nlist[base + (qq + 64 < cnt ? qq + 64 : cnt - 1)];
+      wsync();
+    }
+  }
+}
+
+// backward of one atom i, layers evaluated per neighbour (li = index of i in
+// its cell, CELL only)
+template <int W1, int W2, int W3, int P, bool CELL>
+__device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char *smem, float *h1s, float *hd1s,
+                                    float *dTs, float *gRs, int lane, double (&vir)[9], const CellCtx &cc, int li) {
+  double fi0 = 0.0, fi1 = 0.0, fi2 = 0.0;
+  for (int u = 0; u < a.d.ntypes; ++u)
+    lin_bwd_net<W1, W2, W3, P, CELL>(a, i, u, smem, h1s, hd1s, dTs, gRs, lane, vir, cc, fi0, fi1, fi2);
+  store_fi<CELL>(a, cc, i, li, lane, fi0, fi1, fi2);
+}
+
+// The same with the student table, by projection: per (atom, net) the table
+// is contracted with M = W3 dT once (proj_build), then every neighbour takes
+// one lane and interpolates 3 x 4 projected values (proj_eval).  The list is
+// sorted by distance, so the nearest neighbour (slot 0) has the largest s of
+// the net's block up to ties of the quantised distance (1e-8 A); a net whose
+// slot 0 comes within 1e-6 (relative) of the table's end is appended to the
+// deferred list instead, for k_embed_bwd_defer to evaluate with the layers.
+// nb: the per-net LDS images (stride nb_bytes; W3 dT operands at o_a3b, b3
+// at o_b3), img: the projection images (stride PIMG_BYTES, LDS or global),
+// pts: the wave's PT_BYTES of scratch.
+template <int W1, int W2, int W3, int P, bool CELL>
+__device__ inline void lin_bwd_atom_proj(const MixArgs &a, int i, const unsigned char *nb, int nb_bytes, int o_a3b,
+                                         int o_b3, const unsigned char *img, float *pts, int lane, double (&vir)[9],
+                                         const CellCtx &cc, int li) {
+  const Dims &d = a.d;
+  const double rc = d.rcut, rcs = d.rcut_smth, inv_w = 1.0 / (d.rcut - d.rcut_smth);
+  const double4 xi = a.xw[i];
+  const int t = (int)xi.w;
+  double fi0 = 0.0, fi1 = 0.0, fi2 = 0.0;
+  for (int u = 0; u < d.ntypes; ++u) {
+    const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
+    if (cnt == 0) continue;
+    const int64_t base = (int64_t)i * d.nnei + d.off[u];
+    // slot data of the first chunk and the neighbours of the second, in
+    // flight during the table build
+    float4 r4 = rt_row_m(a.rt, base, lane, cnt);
+    int jc = a.nlist[base + (lane < cnt ? lane : cnt - 1)];
+    int jn = a.nlist[base + (lane + 64 < cnt ? lane + 64 : cnt - 1)];
+    if (__shfl(r4.x, 0) * 1.000001f > a.tab_shi) {
+      if (lane == 0) a.defer[atomicAdd(a.defer_count, 1u)] = i * d.ntypes + u;
+      continue;
+    }
+    const int net_id = t * d.ntypes + u;
+    const unsigned char *net = nb + (size_t)net_id * nb_bytes;
+    Split8<P> MA;
+    float q[4];
+    lin_m_q<W1, W2, W3, P>(a, i, net + o_a3b, (const float *)(net + o_b3), pts, lane, MA, q);
+    proj_build<P>(img + (size_t)net_id * PIMG_BYTES, MA, q, pts, lane);
+    uint32_t codec = CELL ? cc.code[jc] : 0u;
+    double4 pjc = pos3(a.xw, jc);
+    for (int c0 = 0; c0 < cnt; c0 += 64) {
+      const int qq = c0 + lane;
+      // everything that reads this chunk's loads (issued during the chunk
+      // before) comes first: a read after the next loads would make the
+      // compiler wait for those too, as it cannot count the force pass's
+      // conditional stores in between
+      const double4 D4 = pair_disp_sq(xi, pjc, a.L[0], a.L[1], a.L[2]);
+      const int slot = CELL ? cell_slot(cc, codec) : -1;
+      const float4 gr = proj_eval(pts, r4, a.tab_inv_ds);
+      __builtin_amdgcn_sched_barrier(0);
+      // loads for the next chunks (unconditional: past the block the last
+      // real slot is reread): the neighbours of the one after next, this
+      // one's successor's cell codes and positions (its neighbours arrived
+      // during the chunk before) and rows
+      const int jnn = a.nlist[base + (qq + 128 < cnt ? qq + 128 : cnt - 1)];
+      const uint32_t coden = CELL ? cc.code[jn] : 0u;
+      const double4 pjn = pos3(a.xw, jn);
+      const float4 r4n = rt_row_m(a.rt, base, qq + 64, cnt);
+      if (qq < cnt) scatter_pair<CELL>(a, cc, base + qq, D4, jc, slot, gr, rc, rcs, inv_w, fi0, fi1, fi2, vir);
+      r4 = r4n;
+      jc = jn;
+      jn = jnn;
+      pjc = pjn;
+      codec = coden;
+    }
+    wsync();  // every lane is done with the table before the next net overwrites it
+  }
+  store_fi<CELL>(a, cc, i, li, lane, fi0, fi1, fi2);
+}
+
+template <int W1, int W2, int W3, int P, bool PROJ>
 __global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_bwd_lin(MixArgs a) {
   typedef LinShape<W1, W2, W3> LS;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double vred[MIX_WAVES][9];
   const int nnets = a.d.ntypes * a.d.ntypes;
   copy_nets(smem, a.nets, nnets * LS::NET_BYTES);
-  const int tab_bytes = a.tab ? nnets * TAB_BYTES : 0;  // student table after the nets
-  if (a.tab) copy_nets(smem + nnets * LS::NET_BYTES, (const unsigned char *)a.tab, tab_bytes);
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const float *tabs = a.tab ? (const float *)(smem + nnets * LS::NET_BYTES) : nullptr;
-  unsigned char *ws = smem + nnets * LS::NET_BYTES + tab_bytes + wv * LS::P2_BYTES;
+  unsigned char *ws = smem + nnets * LS::NET_BYTES + wv * LS::P2_BYTES;
   float *h1s = (float *)(ws + LS::P2_H1), *hd1s = h1s + 16 * Shape<W1, W2, W3>::S1;
   float *dTs = (float *)(ws + LS::P2_DT);
   float *gRs = (float *)(ws + LS::P2_GR);
@@ -1105,7 +1300,48 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_bwd_lin(MixArgs a) 
   for (int64_t p = p0; p < p1; ++p) {
     const int i = a.atom_of_pos[p];
     if (i < 0) continue;
-    lin_bwd_atom<W1, W2, W3, P, false>(a, i, smem, tabs, h1s, hd1s, dTs, gRs, lane, vir, cc, 0);
+    if constexpr (PROJ)
+      lin_bwd_atom_proj<W1, W2, W3, P, false>(a, i, smem, LS::NET_BYTES, LS::O_A3B, Shape<W1, W2, W3>::O_B3, a.pimg,
+                                              (float *)ws, lane, vir, cc, 0);
+    else lin_bwd_atom<W1, W2, W3, P, false>(a, i, smem, h1s, hd1s, dTs, gRs, lane, vir, cc, 0);
+  }
+  finish_block_virial(a, vir, vred, lane, wv);
+}
+
+// The nets the table kernels deferred (a neighbour beyond the table's
+// range), by the layers: wave w of the grid takes entries w, w + waves, ...
+// of the list (i ntypes + u), forces by global atomics, the block's virial
+// partial in vir_part[blockIdx] (the host offsets vir_part past the main
+// kernel's partials).  With an empty list the blocks write zero partials.
+template <int W1, int W2, int W3, int P>
+__global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_bwd_defer(MixArgs a) {
+  typedef LinShape<W1, W2, W3> LS;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double vred[MIX_WAVES][9];
+  const uint32_t cnt = *a.defer_count;
+  if (cnt == 0) {  // uniform over the grid
+    if (threadIdx.x < 9) a.vir_part[(int64_t)blockIdx.x * 9 + threadIdx.x] = 0.0;
+    return;
+  }
+  const int nnets = a.d.ntypes * a.d.ntypes;
+  copy_nets(smem, a.nets, nnets * LS::NET_BYTES);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  unsigned char *ws = smem + nnets * LS::NET_BYTES + wv * LS::P2_BYTES;
+  float *h1s = (float *)(ws + LS::P2_H1), *hd1s = h1s + 16 * Shape<W1, W2, W3>::S1;
+  float *dTs = (float *)(ws + LS::P2_DT);
+  float *gRs = (float *)(ws + LS::P2_GR);
+  double vir[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) vir[k] = 0.0;
+  const CellCtx cc{};
+  const uint32_t nwaves = gridDim.x * MIX_WAVES;
+  for (uint32_t e = blockIdx.x * MIX_WAVES + wv; e < cnt; e += nwaves) {
+    const int code = a.defer[e];
+    const int i = code / a.d.ntypes, u = code % a.d.ntypes;
+    double fi0 = 0.0, fi1 = 0.0, fi2 = 0.0;
+    lin_bwd_net<W1, W2, W3, P, false>(a, i, u, smem, h1s, hd1s, dTs, gRs, lane, vir, cc, fi0, fi1, fi2);
+    store_fi<false>(a, cc, i, 0, lane, fi0, fi1, fi2);
   }
   finish_block_virial(a, vir, vred, lane, wv);
 }
@@ -1119,32 +1355,46 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_bwd_lin(MixArgs a) 
 // 26 - s = this cell seen from the destination).  Each part entry is written
 // by exactly one cell, so no global atomics are needed; k_cell_gather adds
 // the 27 parts of every atom.  Atoms past the capacity use global atomics.
+// With the table (PROJ) the block holds per net only b3 and the W3 dT
+// operands (the tail of the net image from O_B3 on) and, after them, the
+// nets' projection images, so the table build reads LDS, not L2.
 template <int W1, int W2, int W3>
 struct CellShape {
   typedef Shape<W1, W2, W3> S;
+  typedef LinShape<W1, W2, W3> LS;
   static_assert(!S::XL2, "the cell kernel keeps no cross-lane skip scratch");
   static constexpr int W_DT = 0;                        // float [DT_ROWS][4]
-  static constexpr int W_GR = LinShape<W1, W2, W3>::DT_ROWS * 16;  // float [64][4]
-  static constexpr int W_BYTES = W_GR + 1024;
+  static constexpr int W_GR = LS::DT_ROWS * 16;         // float [64][4]
+  // per wave: dT and gR (layers), or the projected table (dT staged in it first)
+  static constexpr int W_BYTES = W_GR + 1024 > PT_BYTES ? W_GR + 1024 : PT_BYTES;
+  static constexpr int NB = LS::NET_BYTES - S::O_B3;   // per-net bytes kept with the table
+  static_assert(S::O_B3 % 16 == 0 && NB % 16 == 0, "16-byte copies");
+  static constexpr size_t fixed(int nnets, bool proj) {
+    return proj ? (size_t)nnets * (NB + PIMG_BYTES) : (size_t)nnets * LS::NET_BYTES;
+  }
 };
 
-template <int W1, int W2, int W3, int P>
-__global__ void __launch_bounds__(64 * CELL_WAVES, 1) k_embed_bwd_cells(MixArgs a, CellArgs ca) {
+template <int W1, int W2, int W3, int P, bool PROJ>
+__global__ void __launch_bounds__(64 * cell_waves(PROJ), 1) k_embed_bwd_cells(MixArgs a, CellArgs ca) {
   typedef LinShape<W1, W2, W3> LS;
   typedef CellShape<W1, W2, W3> CS;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double vred[CELL_WAVES][9];
   const int nnets = a.d.ntypes * a.d.ntypes;
   const int nw = blockDim.x >> 6;
-  copy_nets(smem, a.nets, nnets * LS::NET_BYTES);
-  const int tab_bytes = a.tab ? nnets * TAB_BYTES : 0;  // student table after the nets
-  if (a.tab) copy_nets(smem + nnets * LS::NET_BYTES, (const unsigned char *)a.tab, tab_bytes);
+  if constexpr (PROJ) {
+    for (int k = 0; k < nnets; ++k)
+      copy_nets(smem + k * CS::NB, a.nets + (size_t)k * LS::NET_BYTES + Shape<W1, W2, W3>::O_B3, CS::NB);
+    copy_nets(smem + nnets * CS::NB, a.pimg, nnets * PIMG_BYTES);
+  } else {
+    copy_nets(smem, a.nets, nnets * LS::NET_BYTES);
+  }
+  const size_t fixed = CS::fixed(nnets, PROJ);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const float *tabs = a.tab ? (const float *)(smem + nnets * LS::NET_BYTES) : nullptr;
-  unsigned char *ws = smem + nnets * LS::NET_BYTES + tab_bytes + wv * CS::W_BYTES;
+  unsigned char *ws = smem + fixed + wv * CS::W_BYTES;
   float *dTs = (float *)(ws + CS::W_DT);
   float *gRs = (float *)(ws + CS::W_GR);
-  double *facc = (double *)(smem + nnets * LS::NET_BYTES + tab_bytes + nw * CS::W_BYTES);
+  double *facc = (double *)(smem + fixed + nw * CS::W_BYTES);
   const int nacc = 27 * 3 * ca.cap;
   double vir[9];
 #pragma unroll
@@ -1164,9 +1414,14 @@ __global__ void __launch_bounds__(64 * CELL_WAVES, 1) k_embed_bwd_cells(MixArgs 
     cc.cy = __builtin_amdgcn_readfirstlane((int)((c / cc.nc2) % cc.nc1));
     cc.cx = __builtin_amdgcn_readfirstlane((int)(c / ((int64_t)cc.nc1 * cc.nc2)));
     const int b = ca.cell_start[c], e = ca.cell_start[c + 1];
-    for (int k = b + wv; k < e; k += nw)
-      lin_bwd_atom<W1, W2, W3, P, true>(a, ca.cell_atoms[k], smem, tabs, nullptr, nullptr, dTs, gRs, lane, vir, cc,
-                                        k - b);
+    for (int k = b + wv; k < e; k += nw) {
+      if constexpr (PROJ)
+        lin_bwd_atom_proj<W1, W2, W3, P, true>(a, ca.cell_atoms[k], smem, CS::NB, LS::O_A3B - Shape<W1, W2, W3>::O_B3,
+                                               0, smem + nnets * CS::NB, (float *)ws, lane, vir, cc, k - b);
+      else
+        lin_bwd_atom<W1, W2, W3, P, true>(a, ca.cell_atoms[k], smem, nullptr, nullptr, dTs, gRs, lane, vir, cc,
+                                          k - b);
+    }
     __syncthreads();
     for (int s = 0; s < 27; ++s) {
       const int x = (cc.cx + s / 9 - 1 + cc.nc0) % cc.nc0, y = (cc.cy + (s / 3) % 3 - 1 + cc.nc1) % cc.nc1,
@@ -1296,8 +1551,10 @@ static void launch_t(hipStream_t s, const MixArgs &a, int pass, int grid) {
       const size_t shm = (size_t)nnets * LS::NET_BYTES + tab + (size_t)MIX_WAVES * LS::P1_BYTES;
       hipLaunchKernelGGL((k_embed_fwd_lin<W1, W2, W3, P>), dim3(grid), dim3(64 * MIX_WAVES), shm, s, a);
     } else {
-      const size_t shm = (size_t)nnets * LS::NET_BYTES + tab + (size_t)MIX_WAVES * LS::P2_BYTES;
-      hipLaunchKernelGGL((k_embed_bwd_lin<W1, W2, W3, P>), dim3(grid), dim3(64 * MIX_WAVES), shm, s, a);
+      // the backward takes the table through its projection image, not from LDS
+      const size_t shm = (size_t)nnets * LS::NET_BYTES + (size_t)MIX_WAVES * LS::P2_BYTES;
+      if (a.tab) hipLaunchKernelGGL((k_embed_bwd_lin<W1, W2, W3, P, true>), dim3(grid), dim3(64 * MIX_WAVES), shm, s, a);
+      else hipLaunchKernelGGL((k_embed_bwd_lin<W1, W2, W3, P, false>), dim3(grid), dim3(64 * MIX_WAVES), shm, s, a);
     }
     return;
   }
@@ -1328,8 +1585,10 @@ static bool tab_fits_t(int ntypes) {
     return false;
   } else {
     typedef LinShape<W1, W2, W3> LS;
-    const size_t base = (size_t)ntypes * ntypes * (LS::NET_BYTES + TAB_BYTES);
-    return base + (size_t)MIX_WAVES * LS::P1_BYTES <= 163840 && base + (size_t)MIX_WAVES * LS::P2_BYTES <= 163840;
+    // the forward holds the table in LDS, the backward only the nets
+    const size_t nets = (size_t)ntypes * ntypes;
+    return nets * (LS::NET_BYTES + TAB_BYTES) + (size_t)MIX_WAVES * LS::P1_BYTES <= 163840 &&
+           nets * LS::NET_BYTES + (size_t)MIX_WAVES * LS::P2_BYTES <= 163840;
   }
 }
 
@@ -1394,6 +1653,28 @@ int mix_grid(int64_t rows) {
   if (g > 2048) g = 2048;
   if (g < 1) g = 1;
   return (int)g;
+}
+
+template <int W1, int W2, int W3, int LIN, int P>
+static void launch_defer_t(hipStream_t s, const MixArgs &a) {
+  if constexpr (LIN != 0) {
+    typedef LinShape<W1, W2, W3> LS;
+    const size_t shm = (size_t)a.d.ntypes * a.d.ntypes * LS::NET_BYTES + (size_t)MIX_WAVES * LS::P2_BYTES;
+    hipLaunchKernelGGL((k_embed_bwd_defer<W1, W2, W3, P>), dim3(DEFER_GRID), dim3(64 * MIX_WAVES), shm, s, a);
+  }
+}
+
+void launch_embed_defer(hipStream_t s, const MixArgs &a) {
+  int id = 0;
+#define X(a_, b_, c_, l_)                                                      \
+  if (a.shape == id) {                                                         \
+    if (a.prec == 0) launch_defer_t<a_, b_, c_, l_, 0>(s, a);                  \
+    else launch_defer_t<a_, b_, c_, l_, 1>(s, a);                              \
+    return;                                                                    \
+  }                                                                            \
+  ++id;
+  DPK_MIX_SHAPES(X)
+#undef X
 }
 
 void launch_embed_mix(hipStream_t s, const MixArgs &a, int pass, int grid) {
@@ -1468,6 +1749,43 @@ void launch_student_table(hipStream_t s, const Dims &d, const EmbOffsets &eo, co
   hipLaunchKernelGGL(k_student_table, dim3((n + 127) / 128, nets), dim3(128), 0, s, d, eo, ew, prec, shi / TAB_K, tab);
 }
 
+// Operand image of the projected table (the backward's proj_build): per net
+// PT_TILES blocks of 16 rows, row 3k + j of node k = (y_k, y_{k+1} - y_k, m_k)
+// with y = h2(s_k) and m = ds dh2/ds(s_k) (the difference taken in FP32 from
+// the table's values, y_{81} - y_{80} = 0), rows past 3 (TAB_K + 1) zero;
+// B-operand lane (g, n) of tile tt holds row 16 tt + n at the layer-3 inputs
+// f = 16 (v / 4) + 4 g + v % 4 (v = 0..7, the permuted K order of M),
+// as hi = rn16(x) in one 1 KB block and lo = rn16(x - hi) in the next.
+__global__ void k_student_pimg(int nets, const float *__restrict__ tab, int prec, unsigned char *__restrict__ img) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nets * PT_TILES * 512) return;
+  const int v = idx & 7, lane = (idx >> 3) & 63, tt = (idx >> 9) % PT_TILES, net = idx / (PT_TILES * 512);
+  const int row = 16 * tt + (lane & 15), f = 16 * (v >> 2) + 4 * (lane >> 4) + (v & 3);
+  const int k = row / 3, j = row % 3;
+  float x = 0.f;
+  if (k <= TAB_K) {
+    const float *r0 = tab + ((int64_t)net * (TAB_K + 1) + k) * TAB_STRIDE;
+    if (j == 0) x = r0[2 * f];
+    else if (j == 1) x = k < TAB_K ? r0[TAB_STRIDE + 2 * f] - r0[2 * f] : 0.f;
+    else x = r0[2 * f + 1];
+  }
+  uint16_t *o = (uint16_t *)(img + (size_t)((net * PT_TILES + tt) * 2) * 1024) + lane * 8 + v;
+  if (prec == 0) {
+    const _Float16 h = (_Float16)x, l = (_Float16)(x - (float)h);
+    o[0] = __builtin_bit_cast(uint16_t, h);
+    o[512] = __builtin_bit_cast(uint16_t, l);
+  } else {
+    const __bf16 h = (__bf16)x, l = (__bf16)(x - (float)h);
+    o[0] = __builtin_bit_cast(uint16_t, h);
+    o[512] = __builtin_bit_cast(uint16_t, l);
+  }
+}
+
+void launch_student_pimg(hipStream_t s, int nets, const float *tab, int prec, unsigned char *img) {
+  const int n = nets * PT_TILES * 512;
+  hipLaunchKernelGGL(k_student_pimg, dim3((n + 255) / 256), dim3(256), 0, s, nets, tab, prec, img);
+}
+
 // per atom the first real slot of each type block is its nearest neighbour
 // of that type (the list is distance-sorted), so the largest s is the
 // largest s of those slots; s >= 0, so its float bits order as unsigned
@@ -1494,17 +1812,17 @@ void launch_smax(hipStream_t s, int64_t n, const Dims &d, const int32_t *nreal, 
 constexpr size_t CELL_LDS_MAX = 160 * 1024;  // LDS of one CU
 
 template <int W1, int W2, int W3, int LIN>
-static bool cells_config_t(int nnets, int want, int need, size_t tab, int *cap, int *threads, size_t *lds) {
+static bool cells_config_t(int nnets, bool proj, int want, int need, int *cap, int *threads, size_t *lds) {
   if constexpr (LIN == 0 || Shape<W1, W2, W3>::XL2) {
     return false;
   } else {
     // the most waves whose scratch leaves room for an accumulator of at
     // least `need` atoms per cell; the accumulator then takes what is left,
     // up to `want`
-    const size_t fixed = (size_t)nnets * LinShape<W1, W2, W3>::NET_BYTES + tab;
+    const size_t fixed = CellShape<W1, W2, W3>::fixed(nnets, proj);
     const size_t budget = CELL_LDS_MAX - sizeof(double) * CELL_WAVES * 9;
     const size_t per_atom = (size_t)27 * 3 * sizeof(double);
-    for (int nw = CELL_WAVES; nw >= 4; nw -= 4) {
+    for (int nw = cell_waves(proj); nw >= 4; nw -= 4) {
       const size_t b = fixed + (size_t)nw * CellShape<W1, W2, W3>::W_BYTES;
       if (b >= budget) continue;
       const int fit = (int)std::min<size_t>((budget - b) / per_atom, 255);
@@ -1521,9 +1839,15 @@ static bool cells_config_t(int nnets, int want, int need, size_t tab, int *cap, 
 template <int W1, int W2, int W3, int LIN, int P>
 static void launch_cells_t(hipStream_t s, const MixArgs &a, const CellArgs &ca, int grid, int threads, size_t lds) {
   if constexpr (LIN != 0 && !Shape<W1, W2, W3>::XL2) {
-    (void)hipFuncSetAttribute((const void *)k_embed_bwd_cells<W1, W2, W3, P>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_embed_bwd_cells<W1, W2, W3, P>), dim3(grid), dim3(threads), lds, s, a, ca);
+    if (a.tab) {
+      (void)hipFuncSetAttribute((const void *)k_embed_bwd_cells<W1, W2, W3, P, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL((k_embed_bwd_cells<W1, W2, W3, P, true>), dim3(grid), dim3(threads), lds, s, a, ca);
+    } else {
+      (void)hipFuncSetAttribute((const void *)k_embed_bwd_cells<W1, W2, W3, P, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL((k_embed_bwd_cells<W1, W2, W3, P, false>), dim3(grid), dim3(threads), lds, s, a, ca);
+    }
   }
 }
 
@@ -1531,9 +1855,8 @@ bool embed_cells_config(const MixArgs &a, int want, int need, int *cap, int *thr
   if (need < 1 || want < need || want > 255) return false;
   const int nnets = a.d.ntypes * a.d.ntypes;
   int id = 0;
-  const size_t tab = a.tab ? (size_t)nnets * TAB_BYTES : 0;
 #define X(a_, b_, c_, l_)                                                         \
-  if (a.shape == id) return cells_config_t<a_, b_, c_, l_>(nnets, want, need, tab, cap, threads, lds); \
+  if (a.shape == id) return cells_config_t<a_, b_, c_, l_>(nnets, a.tab != nullptr, want, need, cap, threads, lds); \
   ++id;
   DPK_MIX_SHAPES(X)
 #undef X

@@ -177,3 +177,62 @@ def test_student_table_matches_layers(name, prec, skin):
     # 16-bit split activations), the table does not add to that
     assert df <= (1e-4 if prec == "fp16" else 3e-4) * max(1.0, rms)
     assert abs(e1 - e0) <= 1e-6 * max(1.0, abs(e0))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_table_defers_nets_beyond_its_range(mode):
+    """The table is built over the s range of the first frame it meets; a
+    later frame with a neighbour closer than that range allows sends the
+    nets of the atoms concerned to the deferred layer pass of the backward
+    (both force scatters).  Frame B pushes atom 0 to 0.7 of the smallest
+    pair distance of frame A (s = 1/r there, 1.43 x the largest s of A,
+    beyond the table's 1.25 x); its forces must match the layers' to the
+    table test's bar, which a cubic extrapolated that far would miss."""
+    from paper_2005_00223_amd.model import DPModel
+    w = synth.workload("cu_cells7")
+    spec = w["spec"]
+    sblob = _student(spec)
+    xa = np.asarray(w["coords"], dtype=np.float64)
+    L = np.asarray(w["box"], dtype=np.float64)
+    L = L if L.size == 3 else L.reshape(3, 3).diagonal()
+    d = xa[None, :, :] - xa[:, None, :]
+    d -= L * np.round(d / L)
+    r = np.sqrt((d ** 2).sum(-1))
+    np.fill_diagonal(r, np.inf)
+    rmin = float(r.min())
+    j = int(np.argmin(r[0]))
+    xb = xa.copy()
+    u = d[0, j] / r[0, j]
+    xb[0] = xa[j] - u * 0.7 * rmin  # atom 0 at 0.7 rmin from its nearest neighbour, same direction
+    # s = 1/r at the new distance (inside the switch's start) against at most
+    # 1/rmin anywhere in frame A: 1/0.7 = 1.43 x the table's reference
+    assert 0.7 * rmin < spec.rcut_smth
+
+    def model(tab):
+        m = DPModel(synth.pack_blob(spec), "fp16")
+        m.student_set_model(sblob)
+        m.student_use(True)
+        m.student_judge(0, 1.0)  # no judge: the untrained student's forces themselves are compared
+        m.student_table(tab)
+        m.set_force_scatter(mode)
+        return m
+
+    say(f"[table] deferred nets, scatter mode {mode}, rmin {rmin:.3f} A")
+    mt = model(True)
+    mt.compute(xa, w["types"], w["box"])  # builds the table over frame A's range
+    e1, f1, v1 = mt.compute(xb, w["types"], w["box"])
+    assert mt.stats()["table_evals"] == 2
+    m0 = model(False)
+    e0, f0, v0 = m0.compute(xb, w["types"], w["box"])
+    f1, f0 = f1.cpu().numpy(), f0.cpu().numpy()
+    v1 = np.asarray(v1.cpu().numpy()).reshape(-1)
+    v0 = np.asarray(v0.cpu().numpy()).reshape(-1)
+    df = float(np.sqrt(((f1 - f0) ** 2).sum(1).mean()))
+    rms = float(np.sqrt((f0 ** 2).sum(1).mean()))
+    d0 = float(np.abs(f1[0] - f0[0]).max())
+    say(f"  force RMSE table vs layers {df:.3e} (RMS|F| {rms:.3f}), atom 0 max |dF| {d0:.3e}, |F_0| "
+        f"{np.abs(f0[0]).max():.3f}")
+    assert np.isfinite(f1).all()
+    assert df <= 1e-4 * max(1.0, rms)
+    assert d0 <= 1e-4 * max(1.0, float(np.abs(f0[0]).max()))
+    assert np.abs(v1 - v0).max() <= 1e-4 * max(1.0, float(np.abs(v0).max()))
