@@ -965,17 +965,32 @@ __device__ inline void layers_h2(const unsigned char *net, float s, int lane, fl
 
 // M = W3 dT for one (atom, net) as split 16-bit halves MA (lane (g, n): row
 // c = n < 4 of M^T, the layer-3 inputs in the permuted K order; rows n >= 4
-// are zero) and q = b3^T dT (q[c] in every lane).  dT of atom i is staged in
-// the wave's scratch dTs first; on return every lane is done with it.
+// are zero) and q = b3^T dT (q[c] in every lane).  dT (rows dtr, from
+// dt_rows) is staged in the wave's scratch dTs first; on return every lane
+// is done with it.
+// dT rows lane and lane + 64 of atom i (zero past M1), as lin_m_q stages
+// them; unconditional loads, masked after
+__device__ inline void dt_rows(const MixArgs &a, int i, int lane, float4 (&dtr)[2]) {
+  const int M1 = a.d.M1;
+  const float4 *dTi = (const float4 *)a.dT32 + (int64_t)i * M1;
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int r = lane + 64 * m;
+    const float4 v = dTi[r < M1 ? r : M1 - 1];
+    const float k = r < M1 ? 1.f : 0.f;
+    dtr[m] = make_float4(v.x * k, v.y * k, v.z * k, v.w * k);
+  }
+}
+
 template <int W1, int W2, int W3, int P>
-__device__ inline void lin_m_q(const MixArgs &a, int i, const unsigned char *a3b, const float *b3, float *dTs, int lane,
+__device__ inline void lin_m_q(const float4 (&dtr)[2], const unsigned char *a3b, const float *b3, float *dTs, int lane,
                                Split8<P> &MA, float (&q)[4]) {
   typedef LinShape<W1, W2, W3> LS;
   typedef typename HT<P>::v8 V;
-  const Dims &d = a.d;
+  static_assert(LS::DT_ROWS == 128, "dT is staged as two rows per lane");
   const int g = lane >> 4, n = lane & 15;
-  const float *dTi = a.dT32 + (int64_t)i * d.M1 * 4;
-  for (int o = lane; o < LS::DT_ROWS * 4; o += 64) dTs[o] = (o >> 2) < d.M1 ? dTi[o] : 0.f;
+  ((float4 *)dTs)[lane] = dtr[0];
+  ((float4 *)dTs)[lane + 64] = dtr[1];
   wsync();
   // B operands of W3 dT (K = outputs f = 32 kk + 8 g + v, N = components
   // c = n); lanes n >= 4 take zeros: their loads read component n & 3 and
@@ -1149,7 +1164,9 @@ __device__ inline void lin_bwd_net(const MixArgs &a, int i, int u, const unsigne
   // M and q are rebuilt per net so that they hold no registers across nets
   Split8<P> MA;
   float q[4];
-  lin_m_q<W1, W2, W3, P>(a, i, net + LS::O_A3B, (const float *)(net + S::O_B3), dTs, lane, MA, q);
+  float4 dtr[2];
+  dt_rows(a, i, lane, dtr);
+  lin_m_q<W1, W2, W3, P>(dtr, net + LS::O_A3B, (const float *)(net + S::O_B3), dTs, lane, MA, q);
   float4 r4n = rt_row(a.rt, base, n, cnt);
   // force-pass operands of the current 64-neighbour chunk, loaded a chunk ahead
   double4 pjc = xi;  // neighbour positions of the chunk, gathered at its first tile
@@ -1218,10 +1235,12 @@ __device__ inline void lin_bwd_atom(const MixArgs &a, int i, const unsigned char
 // nb: the per-net LDS images (stride nb_bytes; W3 dT operands at o_a3b, b3
 // at o_b3), img: the projection images (stride PIMG_BYTES, LDS or global),
 // pts: the wave's PT_BYTES of scratch.
+// dtr: atom i's dT rows (dt_rows) on entry, the rows of atom inext (>= 0)
+// on return, loaded while i is evaluated.
 template <int W1, int W2, int W3, int P, bool CELL>
-__device__ inline void lin_bwd_atom_proj(const MixArgs &a, int i, const unsigned char *nb, int nb_bytes, int o_a3b,
-                                         int o_b3, const unsigned char *img, float *pts, int lane, double (&vir)[9],
-                                         const CellCtx &cc, int li) {
+__device__ inline void lin_bwd_atom_proj(const MixArgs &a, int i, int inext, float4 (&dtr)[2], const unsigned char *nb,
+                                         int nb_bytes, int o_a3b, int o_b3, const unsigned char *img, float *pts,
+                                         int lane, double (&vir)[9], const CellCtx &cc, int li) {
   const Dims &d = a.d;
   const double rc = d.rcut, rcs = d.rcut_smth, inv_w = 1.0 / (d.rcut - d.rcut_smth);
   const double4 xi = a.xw[i];
@@ -1244,7 +1263,11 @@ __device__ inline void lin_bwd_atom_proj(const MixArgs &a, int i, const unsigned
     const unsigned char *net = nb + (size_t)net_id * nb_bytes;
     Split8<P> MA;
     float q[4];
-    lin_m_q<W1, W2, W3, P>(a, i, net + o_a3b, (const float *)(net + o_b3), pts, lane, MA, q);
+    lin_m_q<W1, W2, W3, P>(dtr, net + o_a3b, (const float *)(net + o_b3), pts, lane, MA, q);
+    if (u == d.ntypes - 1 && inext >= 0) {
+      dt_rows(a, inext, lane, dtr);
+      inext = -1;
+    }
     proj_build<P>(img + (size_t)net_id * PIMG_BYTES, MA, q, pts, lane);
     uint32_t codec = CELL ? cc.code[jc] : 0u;
     double4 pjc = pos3(a.xw, jc);
@@ -1275,6 +1298,7 @@ __device__ inline void lin_bwd_atom_proj(const MixArgs &a, int i, const unsigned
     }
     wsync();  // every lane is done with the table before the next net overwrites it
   }
+  if (inext >= 0) dt_rows(a, inext, lane, dtr);  // the last net had no neighbours or was deferred
   store_fi<CELL>(a, cc, i, li, lane, fi0, fi1, fi2);
 }
 
@@ -1300,9 +1324,12 @@ __global__ void __launch_bounds__(64 * MIX_WAVES, 3) k_embed_bwd_lin(MixArgs a) 
   for (int64_t p = p0; p < p1; ++p) {
     const int i = a.atom_of_pos[p];
     if (i < 0) continue;
-    if constexpr (PROJ)
-      lin_bwd_atom_proj<W1, W2, W3, P, false>(a, i, smem, LS::NET_BYTES, LS::O_A3B, Shape<W1, W2, W3>::O_B3, a.pimg,
-                                              (float *)ws, lane, vir, cc, 0);
+    if constexpr (PROJ) {
+      float4 dtr[2];
+      dt_rows(a, i, lane, dtr);
+      lin_bwd_atom_proj<W1, W2, W3, P, false>(a, i, -1, dtr, smem, LS::NET_BYTES, LS::O_A3B, Shape<W1, W2, W3>::O_B3,
+                                              a.pimg, (float *)ws, lane, vir, cc, 0);
+    }
     else lin_bwd_atom<W1, W2, W3, P, false>(a, i, smem, h1s, hd1s, dTs, gRs, lane, vir, cc, 0);
   }
   finish_block_virial(a, vir, vred, lane, wv);
@@ -1414,10 +1441,13 @@ __global__ void __launch_bounds__(64 * cell_waves(PROJ), 1) k_embed_bwd_cells(Mi
     cc.cy = __builtin_amdgcn_readfirstlane((int)((c / cc.nc2) % cc.nc1));
     cc.cx = __builtin_amdgcn_readfirstlane((int)(c / ((int64_t)cc.nc1 * cc.nc2)));
     const int b = ca.cell_start[c], e = ca.cell_start[c + 1];
+    float4 dtr[2];  // table path: dT of the wave's next atom, loaded during the one before
+    if (PROJ && b + wv < e) dt_rows(a, ca.cell_atoms[b + wv], lane, dtr);
     for (int k = b + wv; k < e; k += nw) {
       if constexpr (PROJ)
-        lin_bwd_atom_proj<W1, W2, W3, P, true>(a, ca.cell_atoms[k], smem, CS::NB, LS::O_A3B - Shape<W1, W2, W3>::O_B3,
-                                               0, smem + nnets * CS::NB, (float *)ws, lane, vir, cc, k - b);
+        lin_bwd_atom_proj<W1, W2, W3, P, true>(a, ca.cell_atoms[k], k + nw < e ? ca.cell_atoms[k + nw] : -1, dtr, smem,
+                                               CS::NB, LS::O_A3B - Shape<W1, W2, W3>::O_B3, 0,
+                                               smem + nnets * CS::NB, (float *)ws, lane, vir, cc, k - b);
       else
         lin_bwd_atom<W1, W2, W3, P, true>(a, ca.cell_atoms[k], smem, nullptr, nullptr, dTs, gRs, lane, vir, cc,
                                           k - b);
