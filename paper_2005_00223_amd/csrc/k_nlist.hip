@@ -23,9 +23,10 @@ __device__ inline double wrap1(double x, double L) {
 }
 
 __device__ inline double min_image(double v, double L) {
-  if (v > 0.5 * L) v -= L;
-  else if (v < -0.5 * L) v += L;
-  return v;
+  // selects, not branches: the same values without a divergent branch per
+  // axis and candidate
+  const double h = 0.5 * L, up = v - L, dn = v + L;
+  return v > h ? up : (v < -h ? dn : v);
 }
 
 __global__ void k_wrap(int64_t n, const double *__restrict__ x, const int32_t *__restrict__ types, int ntypes,
@@ -375,6 +376,7 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
     head[b] = -1;
     bstart[b] = 0;
   }
+  const double inv_w = 1.0 / (d.rcut - d.rcut_smth);
   const unsigned long long qlim = (unsigned long long)floor(d.rcut * 1e8) + 1ull;
   const float inv_qlim = 1.0f / (float)qlim;
   double4 p = xw[i];
@@ -500,11 +502,14 @@ __global__ void __launch_bounds__(256) k_format(int64_t n, const double4 *__rest
       const int32_t j = (int32_t)(key & ((1ull << 26) - 1ull));
       row[d.off[t] + pos] = j;
       if (rt32) {
-        // the slot's environment row (the mixed path's FP32 copy of the
-        // FP64 values, as the environment kernel computes them)
-        const double4 D = pair_disp(p, xw[j], L0, L1, L2);
-        const double sv = env_s(D.w, d.rcut_smth, d.rcut, 1.0 / (d.rcut - d.rcut_smth));
-        const double tv = sv * (1.0 / D.w);
+        // the slot's environment row (the mixed path's FP32 copy of FP64
+        // values: from 1/r = rsqrt(r^2) with two Newton steps instead of the
+        // environment kernel's square root and divisions, within an ulp or
+        // two of its values before the rounding to FP32)
+        const double4 D = pair_disp_sq(p, xw[j], L0, L1, L2);
+        const double ir = rsqrt64(D.w), r = D.w * ir;
+        const double x = fmin(fmax((r - d.rcut_smth) * inv_w, 0.0), 1.0);
+        const double sv = (x * x * x * (-6.0 * x * x + 15.0 * x - 10.0) + 1.0) * ir, tv = sv * ir;
         rt32[i * (int64_t)d.nnei + d.off[t] + pos] =
             make_float4((float)sv, (float)(tv * D.x), (float)(tv * D.y), (float)(tv * D.z));
       }
