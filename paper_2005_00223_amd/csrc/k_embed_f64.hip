@@ -49,6 +49,11 @@ static EmbLds emb_lds_layout(const Dims &d, int pass) {
     const int r = d.ekp[l + 1];
     if (r > L.rows[l & 1]) L.rows[l & 1] = r;
   }
+  if (pass == 2) {
+    // the backward stages an atom's dD row and T in the two buffers first
+    const int need = d.M1 * d.M2 + 4 * d.M1, have = (L.rows[0] + L.rows[1]) * L.cols;
+    if (need > have) L.rows[1] += (need - have + L.cols - 1) / L.cols;
+  }
   L.off_buf[0] = 0;
   L.off_buf[1] = L.rows[0] * L.cols;
   L.off_rt = L.off_buf[1] + L.rows[1] * L.cols;
@@ -260,17 +265,24 @@ k_embed_bwd_f64(EmbedArgsT<Real, typename MF<Real>::vec4> a, EmbLds L) {
     const int i = a.atom_of_pos[p];
     if (i < 0) continue;
     const int t = (int)a.xw[i].w;
-    // dT / Nc
+    // dT / Nc, from the atom's dD row and T staged in the activation buffers
+    // (free until the first tile): one coalesced pass of loads, all in
+    // flight together, then the sums from LDS in the same order as before
     {
+      Real *dDs = lds + L.off_buf[0];
+      Real *Ts = dDs + MM;
       const Real *Ti = a.T + (int64_t)i * d.M1 * 4;
       const Real *dDp = a.dD + p * (int64_t)MM;
+      for (int o = lane; o < MM; o += 64) dDs[o] = dDp[o];
+      for (int o = lane; o < d.M1 * 4; o += 64) Ts[o] = Ti[o];
+      wave_sync();
       for (int o = lane; o < M1p * 4; o += 64) {
         const int f = o >> 2, k = o & 3;
         Real v = 0;
         if (f < d.M1) {
-          for (int b = 0; b < d.M2; ++b) v += dDp[f * d.M2 + b] * Ti[b * 4 + k];
+          for (int b = 0; b < d.M2; ++b) v += dDs[f * d.M2 + b] * Ts[b * 4 + k];
           if (f < d.M2)
-            for (int a2 = 0; a2 < d.M1; ++a2) v += dDp[a2 * d.M2 + f] * Ti[a2 * 4 + k];
+            for (int a2 = 0; a2 < d.M1; ++a2) v += dDs[a2 * d.M2 + f] * Ts[a2 * 4 + k];
         }
         dTl[o] = v * (Real)d.inv_nc;
       }
