@@ -58,9 +58,11 @@ struct MF<float> {
 // unconditional.  Weights stream from L2 in their padded [K][M] layout.
 // KP > 0: the layer's shape is known at compile time, the k-loop is
 // unrolled and each k-step's weights are loaded one k-step ahead.
-template <int NCT, int KP, int MP, typename Real>
-__device__ inline void mfma_group_t(const Real *__restrict__ W, int kp, int mp, const Real *Hin, int cols,
-                                    int lane, int mt0, typename MF<Real>::acc (&acc)[NCT][EMB_G]) {
+// bop(kk, ct): the B operand of k-step kk and column tile ct for this lane
+// (row kk + lane / 16 of the layer input, column lane % 16 of tile ct).
+template <int NCT, int KP, int MP, typename Real, class BOp>
+__device__ inline void mfma_group_tb(const Real *__restrict__ W, int kp, int mp, BOp bop, int lane, int mt0,
+                                     typename MF<Real>::acc (&acc)[NCT][EMB_G]) {
   if constexpr (KP > 0) {
     kp = KP;
     mp = MP;
@@ -71,7 +73,6 @@ __device__ inline void mfma_group_t(const Real *__restrict__ W, int kp, int mp, 
 #pragma unroll
     for (int g = 0; g < EMB_G; ++g) acc[ct][g] = typename MF<Real>::acc{0, 0, 0, 0};
   const Real *wr = W + (size_t)(lane >> 4) * mp + (lane & 15);
-  const Real *hr = Hin + (lane >> 4) * cols + (lane & 15);
   int col[EMB_G];
 #pragma unroll
   for (int g = 0; g < EMB_G; ++g) col[g] = 16 * (mt0 + g < nmt ? mt0 + g : nmt - 1);
@@ -89,7 +90,7 @@ __device__ inline void mfma_group_t(const Real *__restrict__ W, int kp, int mp, 
         for (int g = 0; g < EMB_G; ++g) an[g] = wr[(size_t)(kk + 4) * MP + col[g]];
       Real bv[NCT];
 #pragma unroll
-      for (int ct = 0; ct < NCT; ++ct) bv[ct] = hr[kk * cols + ct * 16];
+      for (int ct = 0; ct < NCT; ++ct) bv[ct] = bop(kk, ct);
 #pragma unroll
       for (int g = 0; g < EMB_G; ++g)
 #pragma unroll
@@ -102,13 +103,23 @@ __device__ inline void mfma_group_t(const Real *__restrict__ W, int kp, int mp, 
       for (int g = 0; g < EMB_G; ++g) ac[g] = wr[(size_t)kk * mp + col[g]];
       Real bv[NCT];
 #pragma unroll
-      for (int ct = 0; ct < NCT; ++ct) bv[ct] = hr[kk * cols + ct * 16];
+      for (int ct = 0; ct < NCT; ++ct) bv[ct] = bop(kk, ct);
 #pragma unroll
       for (int g = 0; g < EMB_G; ++g)
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) acc[ct][g] = MF<Real>::mma(ac[g], bv[ct], acc[ct][g]);
     }
   }
+}
+
+// the same with the B operands from an LDS tile [row][cols] (column tile ct
+// at column 16 ct)
+template <int NCT, int KP, int MP, typename Real>
+__device__ inline void mfma_group_t(const Real *__restrict__ W, int kp, int mp, const Real *Hin, int cols,
+                                    int lane, int mt0, typename MF<Real>::acc (&acc)[NCT][EMB_G]) {
+  const Real *hr = Hin + (lane >> 4) * cols + (lane & 15);
+  mfma_group_tb<NCT, KP, MP, Real>(
+      W, kp, mp, [&](int kk, int ct) { return hr[kk * cols + ct * 16]; }, lane, mt0, acc);
 }
 
 // The layer shapes of the 1-25-50-100 and 1-16-32-100 nets take the
@@ -121,6 +132,17 @@ __device__ inline void mfma_group(const Real *__restrict__ W, int kp, int mp, co
   else if (kp == 16 && mp == 32) mfma_group_t<NCT, 16, 32, Real>(W, kp, mp, Hin, cols, lane, mt0, acc);
   else if (kp == 32 && mp == 112) mfma_group_t<NCT, 32, 112, Real>(W, kp, mp, Hin, cols, lane, mt0, acc);
   else mfma_group_t<NCT, 0, 0, Real>(W, kp, mp, Hin, cols, lane, mt0, acc);
+}
+
+// the same dispatch with a B-operand functor (see mfma_group_tb)
+template <int NCT, typename Real, class BOp>
+__device__ inline void mfma_group_b(const Real *__restrict__ W, int kp, int mp, BOp bop, int lane, int mt0,
+                                    typename MF<Real>::acc (&acc)[NCT][EMB_G]) {
+  if (kp == 28 && mp == 64) mfma_group_tb<NCT, 28, 64, Real>(W, kp, mp, bop, lane, mt0, acc);
+  else if (kp == 52 && mp == 112) mfma_group_tb<NCT, 52, 112, Real>(W, kp, mp, bop, lane, mt0, acc);
+  else if (kp == 16 && mp == 32) mfma_group_tb<NCT, 16, 32, Real>(W, kp, mp, bop, lane, mt0, acc);
+  else if (kp == 32 && mp == 112) mfma_group_tb<NCT, 32, 112, Real>(W, kp, mp, bop, lane, mt0, acc);
+  else mfma_group_tb<NCT, 0, 0, Real>(W, kp, mp, bop, lane, mt0, acc);
 }
 
 __device__ inline int skip_src(int f, int in, int out) {

@@ -34,6 +34,7 @@ constexpr int EMB_WAVES = 2;
 struct EmbLds {
   int rows[2];  // rows of the two ping-pong activation buffers
   int cols;     // 16 (forward) or 32 (tangent pass)
+  int v0;       // backward of a three-layer net: buffer 0 holds layer 0's values only (16 columns)
   int off_buf[2], off_rt, off_t, off_g, per_wave;  // offsets in doubles
 };
 
@@ -49,16 +50,23 @@ static EmbLds emb_lds_layout(const Dims &d, int pass) {
     const int r = d.ekp[l + 1];
     if (r > L.rows[l & 1]) L.rows[l & 1] = r;
   }
+  // backward of a three-layer net whose first layer has no skip: layer 0's
+  // tangents are recomputed from its values as layer 1 reads them, and the
+  // tile's s values come by lane shuffles, so buffer 0 holds 16 columns and
+  // there is no R tile -- with dT unpadded, the wave's area fits four
+  // two-wave workgroups per CU in FP64
+  L.v0 = (pass == 2 && d.n_emb == 3 && d.ew[1] > 2) ? 1 : 0;
+  const int c0 = L.v0 ? 16 : L.cols;
   if (pass == 2) {
     // the backward stages an atom's dD row and T in the two buffers first
-    const int need = d.M1 * d.M2 + 4 * d.M1, have = (L.rows[0] + L.rows[1]) * L.cols;
+    const int need = d.M1 * d.M2 + 4 * d.M1, have = L.rows[0] * c0 + L.rows[1] * L.cols;
     if (need > have) L.rows[1] += (need - have + L.cols - 1) / L.cols;
   }
   L.off_buf[0] = 0;
-  L.off_buf[1] = L.rows[0] * L.cols;
+  L.off_buf[1] = L.rows[0] * c0;
   L.off_rt = L.off_buf[1] + L.rows[1] * L.cols;
-  L.off_t = L.off_rt + 64;
-  L.off_g = L.off_t + d.emp[d.n_emb] * 4;
+  L.off_t = L.off_rt + (L.v0 ? 0 : 64);
+  L.off_g = L.off_t + (L.v0 ? d.M1 : d.emp[d.n_emb]) * 4;
   L.per_wave = L.off_g + (pass == 1 ? 256 : 0);
   return L;
 }
@@ -276,7 +284,7 @@ k_embed_bwd_f64(EmbedArgsT<Real, typename MF<Real>::vec4> a, EmbLds L) {
       for (int o = lane; o < MM; o += 64) dDs[o] = dDp[o];
       for (int o = lane; o < d.M1 * 4; o += 64) Ts[o] = Ti[o];
       wave_sync();
-      for (int o = lane; o < M1p * 4; o += 64) {
+      for (int o = lane; o < (L.v0 ? d.M1 : M1p) * 4; o += 64) {
         const int f = o >> 2, k = o & 3;
         Real v = 0;
         if (f < d.M1) {
@@ -304,20 +312,29 @@ k_embed_bwd_f64(EmbedArgsT<Real, typename MF<Real>::vec4> a, EmbLds L) {
           D4 = a.dr[base + n0 + lane];
           j = a.nlist[base + n0 + lane];
         }
-        if (lane < 16) {
-          Rl[lane * 4 + 0] = R4.x;
-          Rl[lane * 4 + 1] = R4.y;
-          Rl[lane * 4 + 2] = R4.z;
-          Rl[lane * 4 + 3] = R4.w;
+        // the tile's s values: neighbour n = lane % 16 of every lane (lanes
+        // n < 16 hold their rows); through LDS unless the layout has no R tile
+        Real s_n;
+        if (L.v0) {
+          s_n = __shfl(R4.x, lane & 15);
+        } else {
+          if (lane < 16) {
+            Rl[lane * 4 + 0] = R4.x;
+            Rl[lane * 4 + 1] = R4.y;
+            Rl[lane * 4 + 2] = R4.z;
+            Rl[lane * 4 + 3] = R4.w;
+          }
+          wave_sync();
+          s_n = Rl[(lane & 15) * 4];
         }
-        wave_sync();
-        // layer 0 with tangent: h and dh/ds side by side (columns 0..15, 16..31)
+        // layer 0 with tangent: h and dh/ds side by side (columns 0..15,
+        // 16..31), or h alone (v0)
+        const int out1 = d.ew[1];
         {
-          const int out1 = d.ew[1];
           Real *H = lds + L.off_buf[0];
           for (int idx = lane; idx < d.ekp[1] * 16; idx += 64) {
             const int f = idx >> 4, n = idx & 15;
-            const Real s = Rl[n * 4];
+            const Real s = s_n;
             Real h = 0, hd = 0;
             if (f < out1) {
               const Real th = MF<Real>::tanh_(s * W0[f] + b0[f]);
@@ -328,8 +345,12 @@ k_embed_bwd_f64(EmbedArgsT<Real, typename MF<Real>::vec4> a, EmbLds L) {
                 hd += Real(1);
               }
             }
-            H[f * 32 + n] = h;
-            H[f * 32 + 16 + n] = hd;
+            if (L.v0) {
+              H[f * 16 + n] = h;
+            } else {
+              H[f * 32 + n] = h;
+              H[f * 32 + 16 + n] = hd;
+            }
           }
         }
         wave_sync();
@@ -343,9 +364,27 @@ k_embed_bwd_f64(EmbedArgsT<Real, typename MF<Real>::vec4> a, EmbLds L) {
           const Real *W = a.ew + a.eo.w[t][u][l];
           const Real *bias = a.ew + a.eo.b[t][u][l];
           const int nmt = d.emp[l + 1] >> 4;
+          // layer 0's values only (v0): its tangent (1 - h^2) w0 is formed
+          // here, the same expression the layer-0 loop evaluates
+          const bool hv = L.v0 && l == 1;
+          const int cin = hv ? 16 : 32;
+          const Real *hr = Hin + (lane >> 4) * cin + (lane & 15);
           for (int mt0 = 0; mt0 < nmt; mt0 += EMB_G) {
             typename MF<Real>::acc acc[2][EMB_G];
-            mfma_group<2>(W, d.ekp[l], d.emp[l + 1], Hin, 32, lane, mt0, acc);
+            // one instantiation for both layouts: the tangent column reads
+            // the stored tangent or forms it (the other operand is selected
+            // away; the loads stay inside the buffers)
+            mfma_group_b<2>(
+                W, d.ekp[l], d.emp[l + 1],
+                [&](int kk, int ct) {
+                  const Real h = hr[kk * cin];
+                  if (ct == 0) return h;
+                  const int f = kk + (lane >> 4);
+                  const Real w0 = W0[f < out1 ? f : 0];
+                  const Real formed = f < out1 ? (Real(1) - h * h) * w0 : Real(0);
+                  return hv ? formed : hr[kk * cin + (hv ? 0 : 16)];
+                },
+                lane, mt0, acc);
 #pragma unroll
             for (int g = 0; g < EMB_G; ++g) {
               const int mt = mt0 + g;
@@ -362,8 +401,9 @@ k_embed_bwd_f64(EmbedArgsT<Real, typename MF<Real>::vec4> a, EmbLds L) {
                   hd = lin ? acc[1][g][r] : (Real(1) - th * th) * acc[1][g][r];
                   const int sf = skip_src(f, in, out);
                   if (sf >= 0) {
-                    h += Hin[sf * 32 + n];
-                    hd += Hin[sf * 32 + 16 + n];
+                    const Real hs = Hin[sf * cin + n];
+                    h += hs;
+                    hd += hv ? (sf < out1 ? (Real(1) - hs * hs) * W0[sf] : Real(0)) : Hin[sf * 32 + 16 + n];
                   }
                 }
                 if (last) {
