@@ -43,7 +43,7 @@ struct EmbLds {
 // stages one 16 x 16 tile of G at a time for T += G R), the tile's R rows
 // [16][4], T (forward: the unscaled sum; backward: dT) [M1 padded][4], and
 // the G tile [16][16] (forward)
-static EmbLds emb_lds_layout(const Dims &d, int pass) {
+static EmbLds emb_lds_layout(const Dims &d, int pass, bool values_only) {
   EmbLds L{};
   L.cols = pass == 1 ? 16 : 32;
   for (int l = 0; l < d.n_emb - 1; ++l) {
@@ -54,8 +54,9 @@ static EmbLds emb_lds_layout(const Dims &d, int pass) {
   // tangents are recomputed from its values as layer 1 reads them, and the
   // tile's s values come by lane shuffles, so buffer 0 holds 16 columns and
   // there is no R tile -- with dT unpadded, the wave's area fits four
-  // two-wave workgroups per CU in FP64
-  L.v0 = (pass == 2 && d.n_emb == 3 && d.ew[1] > 2) ? 1 : 0;
+  // two-wave workgroups per CU in FP64. The FP32 twin is bound by registers,
+  // not LDS, and keeps the stored tangents (the recompute only costs it).
+  L.v0 = (values_only && pass == 2 && d.n_emb == 3 && d.ew[1] > 2) ? 1 : 0;
   const int c0 = L.v0 ? 16 : L.cols;
   if (pass == 2) {
     // the backward stages an atom's dD row and T in the two buffers first
@@ -258,6 +259,9 @@ k_embed_bwd_f64(EmbedArgsT<Real, typename MF<Real>::vec4> a, EmbLds L) {
   Real *lds = smem + wv * L.per_wave;
   Real *Rl = lds + L.off_rt;
   Real *dTl = lds + L.off_t;
+  // the values-only layer-0 layout exists for FP64 only: the FP32 build folds
+  // it away and keeps the stored-tangent code as it was
+  const bool v0 = sizeof(Real) == sizeof(double) && L.v0;
   const int64_t nwaves = (int64_t)gridDim.x * EMB_WAVES;
   const int64_t gw = (int64_t)blockIdx.x * EMB_WAVES + wv;
   const int64_t chunk = (a.rows + nwaves - 1) / nwaves;
@@ -284,7 +288,7 @@ k_embed_bwd_f64(EmbedArgsT<Real, typename MF<Real>::vec4> a, EmbLds L) {
       for (int o = lane; o < MM; o += 64) dDs[o] = dDp[o];
       for (int o = lane; o < d.M1 * 4; o += 64) Ts[o] = Ti[o];
       wave_sync();
-      for (int o = lane; o < (L.v0 ? d.M1 : M1p) * 4; o += 64) {
+      for (int o = lane; o < (v0 ? d.M1 : M1p) * 4; o += 64) {
         const int f = o >> 2, k = o & 3;
         Real v = 0;
         if (f < d.M1) {
@@ -315,7 +319,7 @@ k_embed_bwd_f64(EmbedArgsT<Real, typename MF<Real>::vec4> a, EmbLds L) {
         // the tile's s values: neighbour n = lane % 16 of every lane (lanes
         // n < 16 hold their rows); through LDS unless the layout has no R tile
         Real s_n;
-        if (L.v0) {
+        if (v0) {
           s_n = __shfl(R4.x, lane & 15);
         } else {
           if (lane < 16) {
@@ -345,7 +349,7 @@ k_embed_bwd_f64(EmbedArgsT<Real, typename MF<Real>::vec4> a, EmbLds L) {
                 hd += Real(1);
               }
             }
-            if (L.v0) {
+            if (v0) {
               H[f * 16 + n] = h;
             } else {
               H[f * 32 + n] = h;
@@ -366,7 +370,7 @@ k_embed_bwd_f64(EmbedArgsT<Real, typename MF<Real>::vec4> a, EmbLds L) {
           const int nmt = d.emp[l + 1] >> 4;
           // layer 0's values only (v0): its tangent (1 - h^2) w0 is formed
           // here, the same expression the layer-0 loop evaluates
-          const bool hv = L.v0 && l == 1;
+          const bool hv = v0 && l == 1;
           const int cin = hv ? 16 : 32;
           const Real *hr = Hin + (lane >> 4) * cin + (lane & 15);
           for (int mt0 = 0; mt0 < nmt; mt0 += EMB_G) {
@@ -506,14 +510,14 @@ int embed_bwd_grid(int64_t rows) { return emb_grid(rows); }
 
 template <typename Real>
 static void launch_fwd_t(hipStream_t s, const EmbedArgsT<Real, typename MF<Real>::vec4> &a) {
-  EmbLds L = emb_lds_layout(a.d, 1);
+  EmbLds L = emb_lds_layout(a.d, 1, false);
   size_t shm = sizeof(Real) * (size_t)L.per_wave * EMB_WAVES;
   hipLaunchKernelGGL(k_embed_fwd_f64<Real>, dim3(emb_grid(a.rows)), dim3(64 * EMB_WAVES), shm, s, a, L);
 }
 
 template <typename Real>
 static void launch_bwd_t(hipStream_t s, const EmbedArgsT<Real, typename MF<Real>::vec4> &a, int grid) {
-  EmbLds L = emb_lds_layout(a.d, 2);
+  EmbLds L = emb_lds_layout(a.d, 2, sizeof(Real) == sizeof(double));
   size_t shm = sizeof(Real) * (size_t)L.per_wave * EMB_WAVES;
   hipLaunchKernelGGL(k_embed_bwd_f64<Real>, dim3(grid), dim3(64 * EMB_WAVES), shm, s, a, L);
 }
@@ -523,9 +527,10 @@ void launch_embed_bwd_f64(hipStream_t s, const EmbedArgs &a, int grid) { launch_
 void launch_embed_fwd_f32(hipStream_t s, const EmbedArgs32 &a) { launch_fwd_t<float>(s, a); }
 void launch_embed_bwd_f32(hipStream_t s, const EmbedArgs32 &a, int grid) { launch_bwd_t<float>(s, a, grid); }
 
-// LDS bytes of the FP64 kernels (the FP32 ones take half)
+// LDS bytes of the FP64 kernels' larger layout (the one with stored
+// tangents); the FP32 kernels take half of it, the FP64 backward at most it
 size_t embed_lds_bytes(const Dims &d, int pass) {
-  EmbLds L = emb_lds_layout(d, pass);
+  EmbLds L = emb_lds_layout(d, pass, false);
   return sizeof(double) * (size_t)L.per_wave * EMB_WAVES;
 }
 
