@@ -60,9 +60,16 @@ struct MF<float> {
 // unrolled and each k-step's weights are loaded one k-step ahead.
 // bop(kk, ct): the B operand of k-step kk and column tile ct for this lane
 // (row kk + lane / 16 of the layer input, column lane % 16 of tile ct).
-template <int NCT, int KP, int MP, typename Real, class BOp>
+// HA: the same loads with the operands swapped -- bop gives the A operand
+// H[n = lane % 16][kk + lane / 16] and the weights are B, so acc holds
+// Z = H W (neighbours as rows) instead of its transpose.
+template <int NCT, int KP, int MP, bool HA, typename Real, class BOp>
 __device__ inline void mfma_group_tb(const Real *__restrict__ W, int kp, int mp, BOp bop, int lane, int mt0,
                                      typename MF<Real>::acc (&acc)[NCT][EMB_G]) {
+  auto mma = [](Real w, Real h, typename MF<Real>::acc c) {
+    if constexpr (HA) return MF<Real>::mma(h, w, c);
+    else return MF<Real>::mma(w, h, c);
+  };
   if constexpr (KP > 0) {
     kp = KP;
     mp = MP;
@@ -94,7 +101,7 @@ __device__ inline void mfma_group_tb(const Real *__restrict__ W, int kp, int mp,
 #pragma unroll
       for (int g = 0; g < EMB_G; ++g)
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) acc[ct][g] = MF<Real>::mma(ac[g], bv[ct], acc[ct][g]);
+        for (int ct = 0; ct < NCT; ++ct) acc[ct][g] = mma(ac[g], bv[ct], acc[ct][g]);
     }
   } else {
     for (int kk = 0; kk < kp; kk += 4) {
@@ -107,7 +114,7 @@ __device__ inline void mfma_group_tb(const Real *__restrict__ W, int kp, int mp,
 #pragma unroll
       for (int g = 0; g < EMB_G; ++g)
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) acc[ct][g] = MF<Real>::mma(ac[g], bv[ct], acc[ct][g]);
+        for (int ct = 0; ct < NCT; ++ct) acc[ct][g] = mma(ac[g], bv[ct], acc[ct][g]);
     }
   }
 }
@@ -118,7 +125,7 @@ template <int NCT, int KP, int MP, typename Real>
 __device__ inline void mfma_group_t(const Real *__restrict__ W, int kp, int mp, const Real *Hin, int cols,
                                     int lane, int mt0, typename MF<Real>::acc (&acc)[NCT][EMB_G]) {
   const Real *hr = Hin + (lane >> 4) * cols + (lane & 15);
-  mfma_group_tb<NCT, KP, MP, Real>(
+  mfma_group_tb<NCT, KP, MP, false, Real>(
       W, kp, mp, [&](int kk, int ct) { return hr[kk * cols + ct * 16]; }, lane, mt0, acc);
 }
 
@@ -135,14 +142,14 @@ __device__ inline void mfma_group(const Real *__restrict__ W, int kp, int mp, co
 }
 
 // the same dispatch with a B-operand functor (see mfma_group_tb)
-template <int NCT, typename Real, class BOp>
+template <int NCT, bool HA = false, typename Real, class BOp>
 __device__ inline void mfma_group_b(const Real *__restrict__ W, int kp, int mp, BOp bop, int lane, int mt0,
                                     typename MF<Real>::acc (&acc)[NCT][EMB_G]) {
-  if (kp == 28 && mp == 64) mfma_group_tb<NCT, 28, 64, Real>(W, kp, mp, bop, lane, mt0, acc);
-  else if (kp == 52 && mp == 112) mfma_group_tb<NCT, 52, 112, Real>(W, kp, mp, bop, lane, mt0, acc);
-  else if (kp == 16 && mp == 32) mfma_group_tb<NCT, 16, 32, Real>(W, kp, mp, bop, lane, mt0, acc);
-  else if (kp == 32 && mp == 112) mfma_group_tb<NCT, 32, 112, Real>(W, kp, mp, bop, lane, mt0, acc);
-  else mfma_group_tb<NCT, 0, 0, Real>(W, kp, mp, bop, lane, mt0, acc);
+  if (kp == 28 && mp == 64) mfma_group_tb<NCT, 28, 64, HA, Real>(W, kp, mp, bop, lane, mt0, acc);
+  else if (kp == 52 && mp == 112) mfma_group_tb<NCT, 52, 112, HA, Real>(W, kp, mp, bop, lane, mt0, acc);
+  else if (kp == 16 && mp == 32) mfma_group_tb<NCT, 16, 32, HA, Real>(W, kp, mp, bop, lane, mt0, acc);
+  else if (kp == 32 && mp == 112) mfma_group_tb<NCT, 32, 112, HA, Real>(W, kp, mp, bop, lane, mt0, acc);
+  else mfma_group_tb<NCT, 0, 0, HA, Real>(W, kp, mp, bop, lane, mt0, acc);
 }
 
 __device__ inline int skip_src(int f, int in, int out) {

@@ -34,21 +34,35 @@ constexpr int EMB_WAVES = 2;
 struct EmbLds {
   int rows[2];  // rows of the two ping-pong activation buffers
   int cols;     // 16 (forward) or 32 (tangent pass)
+  int ld[2];    // forward: row stride of the [16 neighbours][features] buffers
   int v0;       // backward of a three-layer net: buffer 0 holds layer 0's values only (16 columns)
   int off_buf[2], off_rt, off_t, off_g, per_wave;  // offsets in doubles
 };
 
-// per-wave LDS (doubles): the ping-pong activation buffers [feature][cols]
-// of the hidden layers (the last layer's output is not stored: the forward
-// stages one 16 x 16 tile of G at a time for T += G R), the tile's R rows
-// [16][4], T (forward: the unscaled sum; backward: dT) [M1 padded][4], and
-// the G tile [16][16] (forward)
+// per-wave LDS (doubles): the ping-pong activation buffers of the hidden
+// layers (the last layer's output is not stored), the tile's R rows [16][4]
+// and T (forward: the unscaled sum; backward: dT) [M1 padded][4]. The
+// forward's buffers are [16 neighbours][ld] with an odd stride ld, so that
+// both a feature column (the MFMA A operand) and a neighbour row (the
+// epilogue's stores) spread over the banks; the backward's are
+// [feature][cols] (value and tangent side by side).
 static EmbLds emb_lds_layout(const Dims &d, int pass, bool values_only) {
   EmbLds L{};
   L.cols = pass == 1 ? 16 : 32;
   for (int l = 0; l < d.n_emb - 1; ++l) {
     const int r = d.ekp[l + 1];
     if (r > L.rows[l & 1]) L.rows[l & 1] = r;
+  }
+  if (pass == 1) {
+    L.ld[0] = L.rows[0] | 1;
+    L.ld[1] = L.rows[1] | 1;
+    L.off_buf[0] = 0;
+    L.off_buf[1] = 16 * L.ld[0];
+    L.off_rt = L.off_buf[1] + 16 * L.ld[1];
+    L.off_t = L.off_rt + 64;
+    L.off_g = L.off_t + d.emp[d.n_emb] * 4;
+    L.per_wave = L.off_g;
+    return L;
   }
   // backward of a three-layer net whose first layer has no skip: layer 0's
   // tangents are recomputed from its values as layer 1 reads them, and the
@@ -68,7 +82,7 @@ static EmbLds emb_lds_layout(const Dims &d, int pass, bool values_only) {
   L.off_rt = L.off_buf[1] + L.rows[1] * L.cols;
   L.off_t = L.off_rt + (L.v0 ? 0 : 64);
   L.off_g = L.off_t + (L.v0 ? d.M1 : d.emp[d.n_emb]) * 4;
-  L.per_wave = L.off_g + (pass == 1 ? 256 : 0);
+  L.per_wave = L.off_g;
   return L;
 }
 
@@ -87,7 +101,6 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgsT<Rea
   Real *lds = smem + wv * L.per_wave;
   Real *Rl = lds + L.off_rt;
   Real *Tl = lds + L.off_t;
-  Real *Gt = lds + L.off_g;
   const int64_t nwaves = (int64_t)gridDim.x * EMB_WAVES;
   const int64_t gw = (int64_t)blockIdx.x * EMB_WAVES + wv;
   const int64_t chunk = (a.rows + nwaves - 1) / nwaves;
@@ -140,60 +153,74 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgsT<Rea
               h = MF<Real>::tanh_(s * W0[f] + b0[f]);
               if (out1 == 1 || out1 == 2) h += s;
             }
-            H[f * 16 + n] = h;
+            H[n * L.ld[0] + f] = h;
           }
         }
         wave_sync();
-        // layers 1 .. n_emb-1 on MFMA, EMB_G output tiles at a time; the last
-        // layer's tiles go one at a time through Gt into T += G R (K = the
-        // 16 neighbours of the tile)
+        // layers 1 .. n_emb-1 on MFMA, EMB_G output tiles at a time, with
+        // the tile's neighbours as the M dimension: Z[n][f] = sum_k H[n][k]
+        // W[k][f], so register r of lane (g, c) holds neighbour row(r, g) of
+        // feature 16 mt + c. The last layer's registers are then directly the
+        // B operand of T^T[c'][f] += sum_n R[n][c'] G[n][f] (k-step r takes
+        // register r; A holds R at the same neighbours), and G never goes to
+        // LDS.
+        // A operands of that product for this tile: R[row(kn, g)][c'] for
+        // c' = lane % 16 < 4, zero for the 12 unused output rows
+        Real ra[4];
+#pragma unroll
+        for (int kn = 0; kn < 4; ++kn)
+          ra[kn] = (lane & 15) < 4 ? Rl[MF<Real>::row(kn, lane >> 4) * 4 + (lane & 15)] : Real(0);
         for (int l = 1; l < d.n_emb; ++l) {
           const int in = d.ew[l], out = d.ew[l + 1];
           const bool last = l == d.n_emb - 1;
           const Real *Hin = lds + L.off_buf[(l - 1) & 1];
           Real *Hout = lds + L.off_buf[l & 1];
+          const int ldi = L.ld[(l - 1) & 1], ldo = L.ld[l & 1];
           const int rows_out = last ? 0 : d.ekp[l + 1];
           const Real *W = a.ew + a.eo.w[t][u][l];
           const Real *bias = a.ew + a.eo.b[t][u][l];
           const int nmt = d.emp[l + 1] >> 4;
+          // A operand of k-step kk: H[n = lane % 16][kk + lane / 16]
+          const Real *hr = Hin + (lane & 15) * ldi + (lane >> 4);
           for (int mt0 = 0; mt0 < nmt; mt0 += EMB_G) {
             typename MF<Real>::acc acc[1][EMB_G];
-            mfma_group<1>(W, d.ekp[l], d.emp[l + 1], Hin, 16, lane, mt0, acc);
+            mfma_group_b<1, true>(
+                W, d.ekp[l], d.emp[l + 1], [&](int kk, int) { return hr[kk]; }, lane, mt0, acc);
 #pragma unroll
             for (int g = 0; g < EMB_G; ++g) {
               const int mt = mt0 + g;
               if (mt < nmt) {
+                const int f = mt * 16 + (lane & 15);
+                Real hreg[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                  const int f = mt * 16 + MF<Real>::row(r, lane >> 4), n = lane & 15;
+                  const int n = MF<Real>::row(r, lane >> 4);
                   Real h = 0;
                   if (f < out) {
                     const Real z = acc[0][g][r] + bias[f];
                     h = (d.emb_lin && last) ? z : MF<Real>::tanh_(z);
                     const int sf = skip_src(f, in, out);
-                    if (sf >= 0) h += Hin[sf * 16 + n];
+                    if (sf >= 0) h += Hin[n * ldi + sf];
                   }
-                  if (last) Gt[MF<Real>::row(r, lane >> 4) * 16 + n] = h;
-                  else if (f < rows_out) Hout[f * 16 + n] = h;
+                  hreg[r] = h;
+                  if (!last && f < rows_out) Hout[n * ldo + f] = h;
                 }
                 if (last) {
-                  wave_sync();
-                  // register r of lane (g, c) holds T[16 mt + row(r, g)][c]
-                  const int comp = lane & 15;
-                  Real *Tr = Tl + mt * 64 + comp;
+                  // register r of lane (g', c) holds T^T[row(r, g')][16 mt + c];
+                  // rows below 4 are T's components, each owned by one lane
                   typename MF<Real>::acc tacc;
 #pragma unroll
-                  for (int r = 0; r < 4; ++r) tacc[r] = comp < 4 ? Tr[4 * MF<Real>::row(r, lane >> 4)] : Real(0);
-#pragma unroll
-                  for (int kn = 0; kn < 4; ++kn) {
-                    const int nb = kn * 4 + (lane >> 4);
-                    const Real bv = comp < 4 ? Rl[nb * 4 + comp] : Real(0);
-                    tacc = MF<Real>::mma(Gt[(lane & 15) * 16 + nb], bv, tacc);
+                  for (int r = 0; r < 4; ++r) {
+                    const int c = MF<Real>::row(r, lane >> 4);
+                    tacc[r] = c < 4 ? Tl[f * 4 + c] : Real(0);
                   }
-                  if (comp < 4)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) Tr[4 * MF<Real>::row(r, lane >> 4)] = tacc[r];
-                  wave_sync();
+                  for (int kn = 0; kn < 4; ++kn) tacc = MF<Real>::mma(ra[kn], hreg[kn], tacc);
+#pragma unroll
+                  for (int r = 0; r < 4; ++r) {
+                    const int c = MF<Real>::row(r, lane >> 4);
+                    if (c < 4) Tl[f * 4 + c] = tacc[r];
+                  }
                 }
               }
             }
