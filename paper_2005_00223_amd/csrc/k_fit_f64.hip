@@ -15,6 +15,13 @@
 // column l%16), or v_mfma_f32_16x16x4_f32 for DP_MIX_FP32 (row 4(l/16) + r);
 // block tile 64 x 64, four waves of 32 x 32, K staged through LDS in steps
 // of 16.  The per-atom energies are written in double either way.
+//
+// Block order: the column blocks of one 64-row block run back to back on
+// one XCD (workgroups are dealt to the eight XCDs round-robin by linear id),
+// so the row block's A tiles -- D in the forward's first layer (1600
+// columns), the tanh outputs and incoming gradient in the backward's
+// (25 column blocks of the 1600 outputs) -- come from HBM once and from
+// that XCD's L2 for the other column blocks.
 #include "dp_f64.h"
 
 namespace dpk {
@@ -27,6 +34,7 @@ template <typename Real>
 struct GemmArgs {
   int mode, layer, K, N, in, out;  // in/out of the layer (fwd: K=in, N=out; bwd: K=out, N=in)
   int ntypes;
+  int64_t nrb;                      // 64-row blocks
   const int32_t *type_start;
   const Real *fwt;
   FitOffsets fo;
@@ -49,9 +57,12 @@ template <int MODE, typename Real>
 __global__ void __launch_bounds__(256) k_fit_gemm(GemmArgs<Real> g) {
   __shared__ Real As[BM][APAD];
   __shared__ Real Bs[BK][BN];
-  const int64_t r0 = (int64_t)blockIdx.x * BM;
-  const int c0 = blockIdx.y * BN;
-  if (r0 >= g.type_start[g.ntypes]) return;
+  const int gn = (g.N + BN - 1) / BN;
+  const unsigned q = blockIdx.x >> 3;
+  const int64_t rb = (int64_t)(q / gn) * 8 + (blockIdx.x & 7);
+  const int64_t r0 = rb * BM;
+  const int c0 = (int)(q % gn) * BN;
+  if (rb >= g.nrb || r0 >= g.type_start[g.ntypes]) return;
   const int t = row_type(g.type_start, g.ntypes, r0);
   const Real *W = g.fwt + g.fo.w[t][g.layer];
   const Real *bias = g.fwt + g.fo.b[t][g.layer];
@@ -158,6 +169,12 @@ __global__ void __launch_bounds__(256) k_fit_out(const int32_t *type_start, int 
   if (lane == 0) eatom[atom] = (double)(s + fwt[fo.b[t][L]]);
 }
 
+// blocks of the XCD-grouped order: row blocks rounded up to a multiple of
+// eight, times the column blocks
+static unsigned fit_blocks(unsigned gm, int n) {
+  return ((gm + 7u) / 8u) * 8u * (unsigned)((n + BN - 1) / BN);
+}
+
 template <typename Real>
 static void launch_fit_t(hipStream_t s, const FitArgsT<Real> &a, int pass) {
   const Dims &d = a.d;
@@ -178,7 +195,8 @@ static void launch_fit_t(hipStream_t s, const FitArgsT<Real> &a, int pass) {
     g.X = (l == 0) ? a.X0 : a.Y[l];
     g.Tt = a.Tt[l + 1];
     g.Y = a.Y[l + 1];
-    hipLaunchKernelGGL((k_fit_gemm<FIT_FWD, Real>), dim3(gm, (unsigned)((g.N + BN - 1) / BN)), dim3(256), 0, s, g);
+    g.nrb = gm;
+    hipLaunchKernelGGL((k_fit_gemm<FIT_FWD, Real>), dim3(fit_blocks(gm, g.N)), dim3(256), 0, s, g);
   }
   if (pass == 1)
     hipLaunchKernelGGL(k_fit_out<Real>, dim3((unsigned)((a.rows + 3) / 4)), dim3(256), 0, s, a.type_start, d.ntypes,
@@ -198,7 +216,8 @@ static void launch_fit_t(hipStream_t s, const FitArgsT<Real> &a, int pass) {
     g.Tt = a.Tt[l + 1];
     g.gY = (l == L - 1) ? nullptr : a.G[l + 1];
     g.gX = a.G[l];
-    hipLaunchKernelGGL((k_fit_gemm<FIT_BWD, Real>), dim3(gm, (unsigned)((g.N + BN - 1) / BN)), dim3(256), 0, s, g);
+    g.nrb = gm;
+    hipLaunchKernelGGL((k_fit_gemm<FIT_BWD, Real>), dim3(fit_blocks(gm, g.N)), dim3(256), 0, s, g);
   }
 }
 
