@@ -75,37 +75,46 @@ __global__ void __launch_bounds__(256) k_fit_gemm(GemmArgs<Real> g) {
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = typename MF<Real>::acc{0, 0, 0, 0};
 
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
-    // A tile [64 x 16]
+  // the next K-tile's global loads are issued before the current tile's
+  // products and stored to LDS after them (raw values: the backward forms
+  // gy (1 - t^2) at the store)
+  Real xa[4], xb[4], xw[4];
+  auto load_tile = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + q * 256;
-      const int rr = e >> 4, kk = e & 15;
-      const int k = k0 + kk;
-      Real v = 0;
+      const int rr = e >> 4, k = k0 + (e & 15);
+      const int64_t row = r0 + rr;
+      xa[q] = 0;
+      xb[q] = 0;
       if (k < g.K) {
-        const int64_t row = r0 + rr;
         if (MODE == FIT_FWD) {
-          v = g.X[row * g.K + k];
+          xa[q] = g.X[row * g.K + k];
         } else {
-          const Real th = g.Tt[row * g.K + k];
-          const Real gy = wo ? wo[k] : g.gY[row * g.K + k];
-          v = gy * (Real(1) - th * th);
+          xa[q] = g.Tt[row * g.K + k];
+          xb[q] = wo ? wo[k] : g.gY[row * g.K + k];
         }
       }
-      As[rr][kk] = v;
     }
-    // B tile [16 x 64]
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + q * 256;
-      const int kk = e >> 6, cc = e & 63;
-      const int k = k0 + kk, c = c0 + cc;
-      Real v = 0;
-      if (k < g.K && c < g.N) v = (MODE == FIT_FWD) ? W[(int64_t)k * g.N + c] : W[(int64_t)c * g.K + k];
-      Bs[kk][cc] = v;
+      const int k = k0 + (e >> 6), c = c0 + (e & 63);
+      xw[q] = 0;
+      if (k < g.K && c < g.N) xw[q] = (MODE == FIT_FWD) ? W[(int64_t)k * g.N + c] : W[(int64_t)c * g.K + k];
+    }
+  };
+  load_tile(0);
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+    // A tile [64 x 16], B tile [16 x 64]
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + q * 256;
+      As[e >> 4][e & 15] = MODE == FIT_FWD ? xa[q] : xb[q] * (Real(1) - xa[q] * xa[q]);
+      Bs[e >> 6][e & 63] = xw[q];
     }
     __syncthreads();
+    if (k0 + BK < g.K) load_tile(k0 + BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       Real af[2], bf[2];
