@@ -82,7 +82,9 @@ static EmbLds emb_lds_layout(const Dims &d, int pass, bool values_only) {
   L.off_rt = L.off_buf[1] + L.rows[1] * L.cols;
   L.off_t = L.off_rt + (L.v0 ? 0 : 64);
   L.off_g = L.off_t + (L.v0 ? d.M1 : d.emp[d.n_emb]) * 4;
-  L.per_wave = L.off_g;
+  // FP64 backward: layer 0's weights, zero past its width, at off_g (read
+  // by the values-only layer-1 operand loader)
+  L.per_wave = L.off_g + (values_only && pass == 2 ? d.ekp[1] : 0);
   return L;
 }
 
@@ -286,6 +288,7 @@ k_embed_bwd_f64(EmbedArgsT<Real, typename MF<Real>::vec4> a, EmbLds L) {
   Real *lds = smem + wv * L.per_wave;
   Real *Rl = lds + L.off_rt;
   Real *dTl = lds + L.off_t;
+  Real *W0l = lds + L.off_g;
   // the values-only layer-0 layout exists for FP64 only: the FP32 build folds
   // it away and keeps the stored-tangent code as it was
   const bool v0 = sizeof(Real) == sizeof(double) && L.v0;
@@ -333,6 +336,11 @@ k_embed_bwd_f64(EmbedArgsT<Real, typename MF<Real>::vec4> a, EmbLds L) {
       const int64_t base = (int64_t)i * d.nnei + d.off[u];
       const Real *W0 = a.ew + a.eo.w[t][u][0];
       const Real *b0 = a.ew + a.eo.b[t][u][0];
+      // layer 0's weights for the formed tangents, from LDS: a global load
+      // there sat in a branch that waited for every load in flight (read
+      // after the barrier that follows layer 0)
+      if (v0)
+        for (int o = lane; o < d.ekp[1]; o += 64) W0l[o] = o < d.ew[1] ? W0[o] : Real(0);
       for (int n0 = 0; n0 < cnt; n0 += 16) {
         const bool valid = lane < 16 && n0 + lane < cnt;
         typename MF<Real>::vec4 R4 = MF<Real>::zero4();
@@ -410,9 +418,7 @@ k_embed_bwd_f64(EmbedArgsT<Real, typename MF<Real>::vec4> a, EmbLds L) {
                 [&](int kk, int ct) {
                   const Real h = hr[kk * cin];
                   if (ct == 0) return h;
-                  const int f = kk + (lane >> 4);
-                  const Real w0 = W0[f < out1 ? f : 0];
-                  const Real formed = f < out1 ? (Real(1) - h * h) * w0 : Real(0);
+                  const Real formed = (Real(1) - h * h) * W0l[kk + (lane >> 4)];
                   return hv ? formed : hr[kk * cin + (hv ? 0 : 16)];
                 },
                 lane, mt0, acc);
@@ -434,7 +440,7 @@ k_embed_bwd_f64(EmbedArgsT<Real, typename MF<Real>::vec4> a, EmbLds L) {
                   if (sf >= 0) {
                     const Real hs = Hin[sf * cin + n];
                     h += hs;
-                    hd += hv ? (sf < out1 ? (Real(1) - hs * hs) * W0[sf] : Real(0)) : Hin[sf * 32 + 16 + n];
+                    hd += hv ? (Real(1) - hs * hs) * W0l[sf] : Hin[sf * 32 + 16 + n];
                   }
                 }
                 if (last) {
@@ -554,11 +560,11 @@ void launch_embed_bwd_f64(hipStream_t s, const EmbedArgs &a, int grid) { launch_
 void launch_embed_fwd_f32(hipStream_t s, const EmbedArgs32 &a) { launch_fwd_t<float>(s, a); }
 void launch_embed_bwd_f32(hipStream_t s, const EmbedArgs32 &a, int grid) { launch_bwd_t<float>(s, a, grid); }
 
-// LDS bytes of the FP64 kernels' larger layout (the one with stored
-// tangents); the FP32 kernels take half of it, the FP64 backward at most it
+// LDS bytes of the larger of the FP64 kernels' two layouts; the FP32
+// kernels take half of the stored-tangent one
 size_t embed_lds_bytes(const Dims &d, int pass) {
-  EmbLds L = emb_lds_layout(d, pass, false);
-  return sizeof(double) * (size_t)L.per_wave * EMB_WAVES;
+  EmbLds L = emb_lds_layout(d, pass, false), V = emb_lds_layout(d, pass, true);
+  return sizeof(double) * (size_t)(L.per_wave > V.per_wave ? L.per_wave : V.per_wave) * EMB_WAVES;
 }
 
 }  // namespace dpk
