@@ -61,7 +61,7 @@ static EmbLds emb_lds_layout(const Dims &d, int pass, bool values_only) {
     L.off_rt = L.off_buf[1] + 16 * L.ld[1];
     L.off_t = L.off_rt + 64;
     L.off_g = L.off_t + d.emp[d.n_emb] * 4;
-    L.per_wave = L.off_g;
+    L.per_wave = L.off_g + 2 * d.ekp[1];  // + layer 0's weights and biases
     return L;
   }
   // backward of a three-layer net whose first layer has no skip: layer 0's
@@ -103,6 +103,7 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgsT<Rea
   Real *lds = smem + wv * L.per_wave;
   Real *Rl = lds + L.off_rt;
   Real *Tl = lds + L.off_t;
+  Real *W0s = lds + L.off_g, *b0s = W0s + d.ekp[1];
   const int64_t nwaves = (int64_t)gridDim.x * EMB_WAVES;
   const int64_t gw = (int64_t)blockIdx.x * EMB_WAVES + wv;
   const int64_t chunk = (a.rows + nwaves - 1) / nwaves;
@@ -125,9 +126,18 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgsT<Rea
     for (int u = 0; u < d.ntypes; ++u) {
       const int cnt = a.nreal[(int64_t)i * d.ntypes + u];
       const int64_t base = (int64_t)i * d.nnei + d.off[u];
-      const Real *W0 = a.ew + a.eo.w[t][u][0];
-      const Real *b0 = a.ew + a.eo.b[t][u][0];
       if (cnt == 0) continue;
+      // layer 0's weights and biases in LDS, zero past its width, so that
+      // the layer-0 loop has no branch around global loads (read after the
+      // barrier that follows the R rows)
+      {
+        const Real *W0 = a.ew + a.eo.w[t][u][0];
+        const Real *b0 = a.ew + a.eo.b[t][u][0];
+        for (int o = lane; o < d.ekp[1]; o += 64) {
+          W0s[o] = o < d.ew[1] ? W0[o] : Real(0);
+          b0s[o] = o < d.ew[1] ? b0[o] : Real(0);
+        }
+      }
       // environment rows one tile ahead (unconditional loads: slots past the
       // block reread its last row and are zeroed when used)
       typename MF<Real>::vec4 r4n = a.rt[base + (lane < cnt ? lane : cnt - 1)];
@@ -150,11 +160,9 @@ __global__ void __launch_bounds__(64 * EMB_WAVES) k_embed_fwd_f64(EmbedArgsT<Rea
           for (int idx = lane; idx < rows * 16; idx += 64) {
             const int f = idx >> 4, n = idx & 15;
             const Real s = Rl[n * 4];
-            Real h = 0;
-            if (f < out1) {
-              h = MF<Real>::tanh_(s * W0[f] + b0[f]);
-              if (out1 == 1 || out1 == 2) h += s;
-            }
+            // padded features: tanh(0) = 0
+            Real h = MF<Real>::tanh_(s * W0s[f] + b0s[f]);
+            if (out1 == 1 || out1 == 2) h += f < out1 ? s : Real(0);
             H[n * L.ld[0] + f] = h;
           }
         }
