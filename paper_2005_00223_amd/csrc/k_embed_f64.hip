@@ -18,13 +18,17 @@
 // This fuses the paper's ProdForce and ProdVirial operators into the
 // embedding backward.
 //
-// Matrix layout: each layer is computed transposed, Z^T[out x 16] = W^T H^T,
-// with the 16 neighbours of a tile as the MFMA N dimension.  For
-// v_mfma_f64_16x16x4: A lane l holds A[l%16][l/16], B lane l holds
-// B[l/16][l%16], and D register r of lane l is D[4r + l/16][l%16] (the f64
-// variant interleaves rows by register, unlike the f32-output variants).
-// Weights stream from L2 in their padded [K][M] layout; activations pass
-// between layers through a per-wave LDS tile [feature][neighbour].
+// Matrix layout.  For v_mfma_f64_16x16x4: A lane l holds A[l%16][l/16],
+// B lane l holds B[l/16][l%16], and D register r of lane l is
+// D[4r + l/16][l%16] (the f64 variant interleaves rows by register, unlike
+// the f32-output variants).  The backward computes each layer transposed,
+// Z^T[out x 16] = W^T H^T, with the 16 neighbours of a tile as the N
+// dimension and activations in a per-wave LDS tile [feature][neighbour].
+// The forward swaps the operands of the same loads, Z[16 x out] = H W with
+// the neighbours as M, so that the last layer's output registers are
+// directly the B operand of T^T += R^T G; its LDS tiles are
+// [neighbour][feature] with an odd row stride.  Weights stream from L2 in
+// their padded [K][M] layout; layer 0's weights are copied to LDS per net.
 #include "dp_f64.h"
 
 namespace dpk {
