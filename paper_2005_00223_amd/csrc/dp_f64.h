@@ -2,8 +2,9 @@
 // and FP32) and the student's FP64 teacher (k_embed_f64.hip,
 // k_student.hip).  Not part of the public ABI.
 //
-// Matrix layout: each layer is computed transposed, Z^T[out x 16] = W^T H^T,
-// with 16 samples (neighbours of a tile) as the MFMA N dimension.  For
+// Matrix layout: a layer is computed transposed, Z^T[out x 16] = W^T H^T,
+// with 16 samples (neighbours of a tile) as the MFMA N dimension, or, with
+// the operands of the same loads swapped (HA), as Z[16 x out] = H W.  For
 // v_mfma_f64_16x16x4: A lane l holds A[l%16][l/16], B lane l holds
 // B[l/16][l%16], and D register r of lane l is D[4r + l/16][l%16] (the f64
 // variant interleaves rows by register, unlike the f32-output variants).
